@@ -1,0 +1,329 @@
+"""CPU FP64 oracle for the phaseless-AFQMC walker step (Cholesky form).
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import this module. The GPU library never
+calls it and shares no code with it.
+
+Everything here is plain numpy in complex128/float64, written to be checked by
+eye against the definitions:
+
+* Hamiltonian: H = sum_ij h_ij c+_i c_j + 1/2 sum_ijkl v_ijkl c+_i c+_j c_l c_k
+  + E_II (the paper's Eq. "hamil", Section "Auxiliary Field Quantum Monte
+  Carlo").
+* Modified-Cholesky factorisation v_ijkl = sum_n L^n_ik L^n*_lj (same section);
+  for the real symmetric L^n used here this is sum_n L^n_ik L^n_jl.
+* The phaseless random walk and the Hubbard-Stratonovich transformation are
+  only cited by the paper (its references to Zhang & Krakauer's phaseless
+  method and Motta & Zhang's review). The steps below are the standard ones,
+  derived from the two statements above with Wick's theorem and a Gaussian
+  integral:
+
+  - mixed Green's function G^s = W^s (T^sH W^s)^-1 T^sH with <c+_i c_k> = G_ki;
+  - local energy E_L = E_II + sum_s tr(h G^s)
+        + 1/2 sum_n [ (sum_s tr(L^n G^s))^2 - sum_s tr(L^n G^s L^n G^s) ];
+  - one-body correction from normal ordering: h' = h - 1/2 sum_n L^n L^n;
+  - HS: exp(-dt v^2/2) = E_x[exp(i sqrt(dt) x v)], shifted by the force bias
+    xbar_n = -i sqrt(dt) vbar_n, vbar_n = sum_s tr(L^n G^s);
+  - walker update W <- B1 T_K(A) B1 W with B1 = exp(-dt h'/2),
+    A = i sqrt(dt) sum_n (x_n - xbar_n) L^n and T_K the order-K Taylor series;
+  - importance function I = (O'/O) exp(sum_n x_n xbar_n - xbar_n^2/2) exp(dt E_shift),
+    phaseless weight w <- w |I| max(0, cos(arg(O'/O)));
+  - periodic thin QR with a positive diagonal R, O <- O / prod_s det R^s.
+
+Walkers are stored as W[w] with shape (M, n_up + n_dn): up columns first.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# Small helpers
+# ---------------------------------------------------------------------------
+def spin_blocks(n_up, n_dn):
+    return [slice(0, n_up), slice(n_up, n_up + n_dn)]
+
+
+def two_body_tensor(chol):
+    """v_ijkl = sum_n L^n_ik L^n_jl (real symmetric L^n)."""
+    return np.einsum("nik,njl->ijkl", chol, chol)
+
+
+def one_body_corrected(h1, chol):
+    """h' = h - 1/2 sum_n L^n L^n (normal-ordering correction of the two-body term)."""
+    return h1 - 0.5 * np.einsum("nij,njk->ik", chol, chol)
+
+
+def sym_expm(a):
+    """exp(a) for a real symmetric matrix through its eigendecomposition."""
+    lam, v = np.linalg.eigh(a)
+    return (v * np.exp(lam)) @ v.T
+
+
+def taylor_apply(A, V, order):
+    """sum_{j=0}^{order} A^j V / j!  (the order-K Taylor propagator applied to V)."""
+    term = V.copy()
+    out = V.copy()
+    for j in range(1, order + 1):
+        term = (A @ term) / j
+        out = out + term
+    return out
+
+
+def qr_positive(W):
+    """Thin QR with a positive real diagonal in R (unique for full column rank)."""
+    Q, R = np.linalg.qr(W)
+    d = np.diag(R)
+    ph = d / np.abs(d)
+    Q = Q * ph[None, :]
+    R = R / ph[:, None]
+    return Q, R
+
+
+# ---------------------------------------------------------------------------
+# Green's function, overlap, force bias, local energy (plain form)
+# ---------------------------------------------------------------------------
+def overlap(T, W, n_up, n_dn):
+    """O = prod_s det(T^sH W^s) and the per-spin S^s."""
+    S = [T[:, b].conj().T @ W[:, b] for b in spin_blocks(n_up, n_dn)]
+    return np.prod([np.linalg.det(s) for s in S]), S
+
+
+def greens_function(T, W, n_up, n_dn):
+    """Per-spin mixed Green's function G^s = W^s (T^sH W^s)^-1 T^sH (M x M)."""
+    out = []
+    for b in spin_blocks(n_up, n_dn):
+        Ts, Ws = T[:, b], W[:, b]
+        S = Ts.conj().T @ Ws
+        out.append(Ws @ np.linalg.solve(S, Ts.conj().T))
+    return out
+
+
+def force_bias_plain(chol, G):
+    """vbar_n = sum_s tr(L^n G^s)."""
+    return sum(np.einsum("nik,ki->n", chol, g) for g in G)
+
+
+def local_energy_plain(h1, chol, T, W, n_up, n_dn, e_core=0.0):
+    """E_L from the full Green's function. Returns (E, E1, EJ, EK), all complex."""
+    G = greens_function(T, W, n_up, n_dn)
+    e1 = sum(np.trace(h1 @ g) for g in G)
+    vbar = force_bias_plain(chol, G)
+    ej = 0.5 * np.sum(vbar * vbar)
+    ek = 0.0
+    for g in G:
+        LG = np.einsum("nik,kj->nij", chol, g)          # L^n G
+        ek = ek - 0.5 * np.einsum("nij,nji->", LG, LG)   # tr(L G L G)
+    return e_core + e1 + ej + ek, e1, ej, ek
+
+
+# ---------------------------------------------------------------------------
+# Half-rotated form: tr(L G) = tr(Lt Theta), tr(LGLG) = tr(Omega Omega)
+# ---------------------------------------------------------------------------
+def half_rotate(h1, chol, T, n_up, n_dn):
+    """ht^s = T^sH h (N x M), Lt^s[n] = T^sH L^n (N x M)."""
+    ht, Lt = [], []
+    for b in spin_blocks(n_up, n_dn):
+        Th = T[:, b].conj().T
+        ht.append(Th @ h1)
+        Lt.append(np.einsum("ai,nik->nak", Th, chol))
+    return ht, Lt
+
+
+def theta(T, W, n_up, n_dn):
+    """Theta^s = W^s (T^sH W^s)^-1 and log det S^s."""
+    th, logdet = [], 0.0 + 0.0j
+    for b in spin_blocks(n_up, n_dn):
+        S = T[:, b].conj().T @ W[:, b]
+        th.append(W[:, b] @ np.linalg.inv(S))
+        sign, ld = np.linalg.slogdet(S)
+        logdet += ld + np.log(sign)
+    return th, logdet
+
+
+def local_energy_half(ht, Lt, T, W, n_up, n_dn, e_core=0.0):
+    """Half-rotated E_L and vbar: Omega^{ns} = Lt^{ns} Theta^s (N x N)."""
+    th, _ = theta(T, W, n_up, n_dn)
+    e1 = sum(np.sum(ht[s] * th[s].T) for s in range(2))
+    vbar = 0.0
+    ek = 0.0
+    for s in range(2):
+        Om = np.einsum("nak,kb->nab", Lt[s], th[s])
+        vbar = vbar + np.einsum("naa->n", Om)
+        ek = ek - 0.5 * np.einsum("nab,nba->", Om, Om)
+    ej = 0.5 * np.sum(vbar * vbar)
+    return e_core + e1 + ej + ek, (e1, ej, ek), vbar
+
+
+# ---------------------------------------------------------------------------
+# One-body propagator pieces (Hubbard-Stratonovich with the force-bias shift)
+# ---------------------------------------------------------------------------
+def force_bias_shift(vbar, dt):
+    """xbar_n = -i sqrt(dt) vbar_n."""
+    return -1j * np.sqrt(dt) * vbar
+
+
+def hs_operator(chol, x, xbar, dt):
+    """A = i sqrt(dt) sum_n (x_n - xbar_n) L^n (M x M)."""
+    return np.einsum("n,nij->ij", 1j * np.sqrt(dt) * (x - xbar), chol)
+
+
+def importance_log_factor(x, xbar):
+    """log of p(x - xbar)/p(x) for the standard normal p: sum_n x_n xbar_n - xbar_n^2/2."""
+    return np.sum(x * xbar - 0.5 * xbar * xbar)
+
+
+# ---------------------------------------------------------------------------
+# The walk
+# ---------------------------------------------------------------------------
+def prepare(h1, chol, phi_t, n_up, n_dn, dt):
+    hp = one_body_corrected(h1, chol)
+    B1 = sym_expm(-0.5 * dt * hp)
+    ht, Lt = half_rotate(h1, chol, phi_t, n_up, n_dn)
+    return dict(hp=hp, B1=B1, ht=ht, Lt=Lt)
+
+
+def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
+        e_shift=0.0, order=6, e_core=0.0, energy="half", record_walkers=False):
+    """Run len(fields) steps. fields[k, w, n] are the standard-normal HS fields.
+
+    Per step k (energy and force bias both at the start-of-step walker W_k):
+      1. Theta, E_L (E1, EJ, EK) and vbar at W_k;
+         E_mix(k) = sum_w w_k Re E_L / sum_w w_k with the pre-update weights.
+      2. For live walkers: W' = B1 T_K(A) B1 W, r = O'/O, phaseless weight.
+         A walker whose weight becomes 0 (or non-finite) is frozen (W not updated).
+      3. QR of the live walkers when (k+1) % qr_every == 0.
+    """
+    M = h1.shape[0]
+    nw = W0.shape[0]
+    pre = prepare(h1, chol, phi_t, n_up, n_dn, dt)
+    B1, ht, Lt = pre["B1"], pre["ht"], pre["Lt"]
+    W = W0.astype(np.complex128).copy()
+    w = np.asarray(weights0, dtype=np.float64).copy()
+    logO = np.empty(nw, dtype=np.complex128)
+    for i in range(nw):
+        _, logO[i] = theta(phi_t, W[i], n_up, n_dn)
+    alive = w > 0
+    n_steps = fields.shape[0]
+    out = dict(emix=np.zeros(n_steps), eloc=np.zeros((n_steps, nw), np.complex128),
+               parts=np.zeros((n_steps, nw, 3), np.complex128),
+               weights=np.zeros((n_steps, nw)), ratio=np.zeros((n_steps, nw), np.complex128),
+               cosdt=np.ones((n_steps, nw)))
+    if record_walkers:
+        out["walkers"] = np.zeros((n_steps,) + W.shape, np.complex128)
+    for k in range(n_steps):
+        vb = np.zeros((nw, chol.shape[0]), np.complex128)
+        for i in range(nw):
+            if energy == "plain":
+                e, e1, ej, ek = local_energy_plain(h1, chol, phi_t, W[i], n_up, n_dn, e_core)
+                parts = (e1, ej, ek)
+                G = greens_function(phi_t, W[i], n_up, n_dn)
+                vb[i] = force_bias_plain(chol, G)
+            else:
+                e, parts, vb[i] = local_energy_half(ht, Lt, phi_t, W[i], n_up, n_dn, e_core)
+            out["eloc"][k, i] = e
+            out["parts"][k, i] = parts
+        sw = np.sum(w)
+        out["emix"][k] = np.sum(w * out["eloc"][k].real) / sw if sw > 0 else 0.0
+        for i in range(nw):
+            if not alive[i]:
+                continue
+            x = fields[k, i]
+            xbar = force_bias_shift(vb[i], dt)
+            A = hs_operator(chol, x, xbar, dt)
+            Wn = B1 @ taylor_apply(A, B1 @ W[i], order)
+            _, logOn = theta(phi_t, Wn, n_up, n_dn)
+            log_r = logOn - logO[i]
+            r = np.exp(log_r)
+            log_I = log_r + importance_log_factor(x, xbar) + dt * e_shift
+            cos_dth = np.cos(log_r.imag)
+            wn = w[i] * np.exp(log_I.real) * cos_dth if cos_dth > 0.0 else 0.0
+            out["ratio"][k, i] = r
+            out["cosdt"][k, i] = cos_dth
+            if not np.isfinite(wn) or wn <= 0.0:
+                w[i] = 0.0
+                alive[i] = False
+                continue
+            w[i] = wn
+            W[i] = Wn
+            logO[i] = logOn
+        if qr_every > 0 and (k + 1) % qr_every == 0:
+            for i in range(nw):
+                if not alive[i]:
+                    continue
+                for b in spin_blocks(n_up, n_dn):
+                    Q, R = qr_positive(W[i][:, b])
+                    W[i][:, b] = Q
+                    logO[i] -= np.sum(np.log(np.diag(R).real))
+        out["weights"][k] = w
+        if record_walkers:
+            out["walkers"][k] = W
+    out.update(W=W, w=w, logO=logO, alive=alive)
+    return out
+
+
+def energy(h1, chol, phi_t, n_up, n_dn, W, weights, e_core=0.0, form="half"):
+    """Per-walker E_L, parts (E1, EJ, EK) and the weighted mixed energy."""
+    nw = W.shape[0]
+    el = np.zeros(nw, np.complex128)
+    parts = np.zeros((nw, 3), np.complex128)
+    if form == "half":
+        ht, Lt = half_rotate(h1, chol, phi_t, n_up, n_dn)
+    for i in range(nw):
+        if form == "half":
+            el[i], p, _ = local_energy_half(ht, Lt, phi_t, W[i], n_up, n_dn, e_core)
+        else:
+            e, e1, ej, ek = local_energy_plain(h1, chol, phi_t, W[i], n_up, n_dn, e_core)
+            el[i], p = e, (e1, ej, ek)
+        parts[i] = p
+    w = np.asarray(weights, dtype=np.float64)
+    emix = np.sum(w * el.real) / np.sum(w)
+    return el, parts, emix
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of the weighted mixed energy  Ebar = sum_w w Re E_L / sum_w w
+# (weights and the trial held fixed; gradients w.r.t. every entry of h1, L^n
+# and, in torch's convention d/dRe + i d/dIm, the walker orbitals).
+# ---------------------------------------------------------------------------
+def energy_grad(h1, chol, phi_t, n_up, n_dn, W, weights):
+    nw = W.shape[0]
+    X, M, _ = chol.shape
+    w = np.asarray(weights, dtype=np.float64)
+    wh = w / np.sum(w)
+    d_h1 = np.zeros((M, M))
+    d_chol = np.zeros((X, M, M))
+    d_W = np.zeros_like(W, dtype=np.complex128)
+    ht, Lt = half_rotate(h1, chol, phi_t, n_up, n_dn)
+    for i in range(nw):
+        G = greens_function(phi_t, W[i], n_up, n_dn)
+        Gsum = G[0] + G[1]
+        vbar = force_bias_plain(chol, G)
+        # dE/dh_ij = G_ji ; dE/dL^n_ij = vbar_n G_ji - sum_s (G L^n G)_ji
+        d_h1 += wh[i] * Gsum.T.real
+        dl = vbar[:, None, None] * Gsum.T[None]
+        for g in G:
+            GLG = np.einsum("ik,nkl,lj->nij", g, chol, g)
+            dl = dl - np.transpose(GLG, (0, 2, 1))
+        d_chol += wh[i] * dl.real
+        # dE/dW^s = (I - G^s)^T Gamma^s S^-T, Gamma = dE/dTheta (holomorphic)
+        th, _ = theta(phi_t, W[i], n_up, n_dn)
+        for s, b in enumerate(spin_blocks(n_up, n_dn)):
+            Om = np.einsum("nak,kb->nab", Lt[s], th[s])
+            gam = ht[s].T + np.einsum("n,nak->ka", vbar, Lt[s]) \
+                - np.einsum("nab,nbk->ka", Om, Lt[s])
+            S = phi_t[:, b].conj().T @ W[i][:, b]
+            dEdW = (np.eye(M) - G[s]).T @ gam @ np.linalg.inv(S).T
+            d_W[i][:, b] = wh[i] * np.conj(dEdW)
+    return d_h1, d_chol, d_W
+
+
+def mixed_rdm1(phi_t, n_up, n_dn, W, weights):
+    """Weighted mixed one-body density matrix P_ij = sum_w wh_w sum_s <c+_i c_j>_w = G_ji."""
+    w = np.asarray(weights, dtype=np.float64)
+    wh = w / np.sum(w)
+    P = 0.0
+    for i in range(W.shape[0]):
+        G = greens_function(phi_t, W[i], n_up, n_dn)
+        P = P + wh[i] * (G[0] + G[1]).T
+    return P
