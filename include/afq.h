@@ -1,0 +1,200 @@
+/*
+ * afq.h -- C ABI of the MI355X (gfx950) phaseless-AFQMC walker-step library.
+ *
+ * The library implements the batched walker step of phaseless auxiliary-field
+ * quantum Monte Carlo with a Cholesky-factorised two-electron tensor, for the
+ * Hamiltonian of the paper's Eq. "hamil" (Section "Auxiliary Field Quantum
+ * Monte Carlo"):
+ *
+ *   H = sum_ij h_ij c+_i c_j + 1/2 sum_ijkl v_ijkl c+_i c+_j c_l c_k + E_II,
+ *   v_ijkl = sum_n L^n_ik L^n*_lj        (modified-Cholesky form, same section)
+ *
+ * Step equations (the paper cites them from the phaseless-AFQMC literature;
+ * they follow from the two lines above by Wick's theorem and the
+ * Hubbard-Stratonovich transformation):
+ *   S^s = T^sH W^s, Theta^s = W^s (S^s)^-1, G^s = Theta^s T^sH,
+ *   Omega^{ns} = Lt^{ns} Theta^s with Lt^{ns} = T^sH L^n (half rotation),
+ *   vbar_n = sum_s tr Omega^{ns},
+ *   E_L = E_II + sum_s tr(ht^s Theta^s) + 1/2 sum_n vbar_n^2
+ *         - 1/2 sum_{n,s} tr(Omega^{ns} Omega^{ns}),   ht^s = T^sH h,
+ *   xbar_n = -i sqrt(dt) vbar_n, A = i sqrt(dt) sum_n (x_n - xbar_n) L^n,
+ *   W <- B1 T_K(A) B1 W,  B1 = exp(-dt h'/2),  h' = h - 1/2 sum_n L^n L^n,
+ *   r = O'/O, I = r exp(sum_n x_n xbar_n - xbar_n^2/2) exp(dt E_shift),
+ *   w <- w |I| max(0, cos arg r),  periodic thin QR of W (positive diag R).
+ *
+ * Conventions shared by every call
+ *   - All array arguments of afq_step, afq_energy, afq_energy_backward,
+ *     afq_walkers_get/set, afq_fields_generate and afq_batch_step are DEVICE
+ *     pointers on the device that was current when the system was created
+ *     (for instance torch.Tensor.data_ptr() of a CUDA tensor). The pointers
+ *     of afq_system_create and afq_walkers_create are device pointers too.
+ *   - Complex arrays are interleaved (re, im) float64 pairs, row-major.
+ *   - Orbital matrices (trial, walkers) are M x (n_up + n_dn): up-spin
+ *     columns first, then down-spin columns.
+ *   - Work is enqueued on the HIP stream given to afq_system_create and is
+ *     asynchronous unless stated otherwise; outputs are valid once that
+ *     stream has been synchronised. The library never synchronises the
+ *     device except in the create calls and afq_walkers_stats.
+ *   - Every call returns an afq_status; on failure afq_last_error() gives a
+ *     thread-local message. No C++ exception crosses the ABI.
+ *   - Handles are not thread-safe: use one per thread.
+ */
+#ifndef AFQ_H
+#define AFQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct afq_system_s *afq_system;
+typedef struct afq_walkers_s *afq_walkers;
+typedef struct afq_batch_s *afq_batch;
+
+typedef enum {
+  AFQ_OK = 0,
+  AFQ_E_INVALID = -1,     /* bad shape, NULL pointer, bad argument value */
+  AFQ_E_NOMEM = -2,       /* device allocation failed */
+  AFQ_E_HIP = -3,         /* a HIP runtime call failed */
+  AFQ_E_SINGULAR = -4,    /* initial walker overlap T^H W is singular */
+  AFQ_E_STATE = -5,       /* handles that do not belong together */
+  AFQ_E_UNSUPPORTED = -6  /* valid input outside what the library implements */
+} afq_status;
+
+/* Arithmetic of the contraction bulk (the Omega = Lt Theta exchange GEMM, the
+ * A = sum_n c_n L^n build and the Taylor increments). The overlap inverse and
+ * determinant, the phaseless ratio, the weights, QR and the walker orbitals
+ * are FP64 in every mode. */
+typedef enum {
+  AFQ_FP64 = 0,   /* complex128 contractions on FP64 MFMA */
+  AFQ_CFP32 = 1,  /* complex64 contractions on FP32 MFMA, FP32 accumulation */
+  AFQ_BF16X3 = 2  /* split-BF16x3 (hi*hi + hi*lo + lo*hi) on BF16 MFMA for the
+                     exchange GEMM, FP32 accumulation; complex64 elsewhere */
+} afq_precision;
+
+/* ------------------------------------------------------------------------ */
+/* System: h1, L^n, the trial and E_II (Eq. "hamil" and the Cholesky form).   */
+/* ------------------------------------------------------------------------ */
+
+/* Creates a system and copies the inputs into library-owned device memory
+ * (the caller may free its buffers on return; this call synchronises).
+ *   M        number of spatial orbitals (1 <= M <= 4096)
+ *   n_up/dn  electrons per spin (1 <= n <= min(M, 128))
+ *   n_chol   number of Cholesky vectors X (>= 1)
+ *   h1       M*M float64, real symmetric one-body matrix h_ij
+ *   chol     n_chol*M*M float64, real symmetric L^n_ik (n-major)
+ *   phi_t    M*(n_up+n_dn) complex128 trial orbitals T (orthonormal columns
+ *            per spin are assumed by the QR convention, not checked)
+ *   e_core   E_II, added to every local energy
+ *   precision one of afq_precision
+ *   stream   hipStream_t (NULL = default stream) used by every later call
+ * Errors: AFQ_E_INVALID for bad sizes, NULL pointers or an h1/L^n that is not
+ * symmetric to 1e-12 (relative to its largest entry); AFQ_E_NOMEM. */
+int afq_system_create(afq_system *out, int M, int n_up, int n_dn, int n_chol,
+                      const double *h1, const double *chol, const double *phi_t,
+                      double e_core, int precision, void *stream);
+/* Switches the contraction precision (prepares the packed operand copies;
+ * synchronises). */
+int afq_system_set_precision(afq_system s, int precision);
+/* Frees device memory. NULL-safe. */
+int afq_system_destroy(afq_system s);
+
+/* ------------------------------------------------------------------------ */
+/* Walkers: Slater determinants W (M x (n_up+n_dn) complex128) and weights.   */
+/* ------------------------------------------------------------------------ */
+
+/* w0: n_walkers*M*(n_up+n_dn) complex128, or NULL to start every walker at
+ * the trial. weights0: n_walkers float64, or NULL for all ones. A walker with
+ * weight 0 is dead (frozen). Synchronises; AFQ_E_SINGULAR if any live
+ * walker's overlap with the trial is singular. */
+int afq_walkers_create(afq_walkers *out, afq_system s, int n_walkers,
+                       const double *w0, const double *weights0);
+int afq_walkers_destroy(afq_walkers w);
+
+/* Checkpoint/resume. W: n_walkers*M*Ntot complex128; weights: n_walkers;
+ * logovlp: n_walkers complex128 (log of prod_s det(T^sH W^s), get only, may be
+ * NULL); alive: n_walkers int32 (may be NULL); counter: the step counter that
+ * keys the Philox fields (host pointer, may be NULL). */
+int afq_walkers_get(afq_walkers w, double *W, double *weights, double *logovlp,
+                    int32_t *alive, uint64_t *counter);
+int afq_walkers_set(afq_walkers w, const double *W, const double *weights,
+                    const int32_t *alive, uint64_t counter);
+/* Host-side counts: walkers alive, and the number killed by the phaseless
+ * projection or a singular overlap since creation. Synchronises. */
+int afq_walkers_stats(afq_walkers w, int *n_alive, int64_t *n_killed);
+
+/* ------------------------------------------------------------------------ */
+/* Hot path.                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Advances the walkers n_steps steps of length dt.
+ *   fields   NULL: standard-normal fields from the device Philox4x32-10
+ *            generator keyed by (seed, step counter, walker, n); else
+ *            n_steps*n_walkers*n_chol float64 fields x[k][w][n].
+ *   qr_every re-orthonormalise after every qr_every-th step (0 = never); the
+ *            phase of this cadence follows the walkers' step counter.
+ *   e_shift  E_shift of the importance function.
+ *   taylor_order K >= 1 (6 in the reference workloads).
+ * Optional outputs (NULL to skip), per step k, energies at the start-of-step
+ * walkers with the pre-update weights:
+ *   emix_out    n_steps float64: sum_w w Re E_L / sum_w w (0 if all dead)
+ *   eloc_out    n_steps*n_walkers complex128 local energies
+ *   weights_out n_steps*n_walkers float64 weights after step k
+ *   ratio_out   n_steps*n_walkers complex128 overlap ratios O'/O (1 for dead)
+ * Dead walkers are not errors; they are counted by afq_walkers_stats. */
+int afq_step(afq_system s, afq_walkers w, int n_steps, double dt,
+             const double *fields, uint64_t seed, int qr_every, double e_shift,
+             int taylor_order, double *emix_out, double *eloc_out,
+             double *weights_out, double *ratio_out);
+
+/* Local energy at the current walkers.
+ *   eloc_out  n_walkers complex128 E_L (may be NULL)
+ *   parts_out n_walkers*3 complex128 (E1, EJ, EK) (may be NULL)
+ *   vbar_out  n_walkers*n_chol complex128 force bias vbar_n (may be NULL)
+ *   emix_out  1 float64 weighted mixed energy (may be NULL) */
+int afq_energy(afq_system s, afq_walkers w, double *eloc_out, double *parts_out,
+               double *vbar_out, double *emix_out);
+
+/* Adjoint of  f = scale * sum_w w Re E_L / sum_w w  at the current walkers,
+ * with the weights and the trial held fixed. Theta and Omega are recomputed; nothing
+ * is stored from the forward call. Outputs (each may be NULL to skip):
+ *   d_h1      M*M float64, df/dh_ij for every entry (not symmetrised)
+ *   d_chol    n_chol*M*M float64, df/dL^n_ij for every entry
+ *   d_walkers n_walkers*M*Ntot complex128, df/dRe W + i df/dIm W
+ * The outputs are overwritten, not accumulated. */
+int afq_energy_backward(afq_system s, afq_walkers w, double scale, double *d_h1,
+                        double *d_chol, double *d_walkers);
+
+/* Standard-normal fields x[k][w][n] for steps step0..step0+n_steps-1 from the
+ * device Philox4x32-10 generator (the same stream afq_step draws with
+ * fields == NULL): counter (n/2, w, step, sys_id), key (seed lo, seed hi),
+ * Box-Muller on two 53-bit uniforms. out: n_steps*n_walkers*n_chol float64. */
+int afq_fields_generate(uint64_t seed, uint32_t sys_id, uint64_t step0, int n_steps,
+                        int n_walkers, int n_chol, double *out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Many uneven systems in one captured launch sequence.                       */
+/* ------------------------------------------------------------------------ */
+
+/* Groups n (system, walkers) pairs that share one stream and precision.
+ * The handles must outlive the batch. */
+int afq_batch_create(afq_batch *out, int n, const afq_system *systems,
+                     const afq_walkers *walkers);
+/* Advances every system n_steps steps with Philox fields (system i uses
+ * sys_id = i). The first call captures one HIP graph of qr_every steps (or one
+ * step when qr_every is 0) and later calls replay it. e_shift: n float64
+ * (host). emix_out: n*n_steps float64 device array, system-major. */
+int afq_batch_step(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_every,
+                   const double *e_shift, int taylor_order, double *emix_out);
+int afq_batch_destroy(afq_batch b);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *afq_last_error(void);
+/* Library version, (major << 16) | minor. */
+int afq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AFQ_H */

@@ -1,0 +1,181 @@
+// The extern "C" boundary: argument validation, status codes and the
+// thread-local error message; everything else is delegated to the runtime.
+#include <cmath>
+#include "common.h"
+#include "step_kernels.h"
+
+static thread_local std::string g_last_error;
+void afq_set_error(const std::string& msg) { g_last_error = msg; }
+
+int system_create_impl(afq_system* out, int M, int n_up, int n_dn, int X, const double* h1, const double* chol,
+                       const double* phi_t, double e_core, int prec, void* stream);
+int walkers_create_impl(afq_walkers* out, afq_system s, int nw, const double* w0, const double* wt0);
+int energy_call(afq_system s, afq_walkers w, double* eloc_out, double* parts_out, double* vbar_out,
+                double* emix_out);
+int batch_create_impl(afq_batch* out, int n, const afq_system* systems, const afq_walkers* walkers);
+int batch_step_impl(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_every, const double* e_shift,
+                    int order, double* emix_out);
+int batch_destroy_impl(afq_batch b);
+
+#define AFQ_GUARD(...)                                      \
+  try {                                                     \
+    __VA_ARGS__                                             \
+  } catch (const std::exception& e) {                       \
+    afq_set_error(std::string("internal error: ") + e.what()); \
+    return AFQ_E_HIP;                                       \
+  } catch (...) {                                           \
+    afq_set_error("internal error");                        \
+    return AFQ_E_HIP;                                       \
+  }
+
+static int check_device(afq_system s) {
+  int dev = -1;
+  AFQ_TRY_HIP(hipGetDevice(&dev));
+  AFQ_CHECK(dev == s->device, AFQ_E_STATE, "the current HIP device differs from the system's device");
+  return AFQ_OK;
+}
+
+extern "C" {
+
+const char* afq_last_error(void) { return g_last_error.c_str(); }
+int afq_version(void) { return (1 << 16) | 0; }
+
+int afq_system_create(afq_system* out, int M, int n_up, int n_dn, int n_chol, const double* h1, const double* chol,
+                      const double* phi_t, double e_core, int precision, void* stream) {
+  AFQ_GUARD(return system_create_impl(out, M, n_up, n_dn, n_chol, h1, chol, phi_t, e_core, precision, stream);)
+}
+
+int afq_system_set_precision(afq_system s, int precision) {
+  AFQ_CHECK(s, AFQ_E_INVALID, "afq_system_set_precision: system is NULL");
+  AFQ_CHECK(precision >= AFQ_FP64 && precision <= AFQ_BF16X3, AFQ_E_INVALID, "unknown precision");
+  AFQ_GUARD(AFQ_RET(check_device(s)); return system_prepare_pack(s, precision);)
+}
+
+int afq_system_destroy(afq_system s) {
+  if (!s) return AFQ_OK;
+  AFQ_GUARD((void)hipStreamSynchronize(s->stream); delete s; return AFQ_OK;)
+}
+
+int afq_walkers_create(afq_walkers* out, afq_system s, int n_walkers, const double* w0, const double* weights0) {
+  AFQ_GUARD(if (s) AFQ_RET(check_device(s)); return walkers_create_impl(out, s, n_walkers, w0, weights0);)
+}
+
+int afq_walkers_destroy(afq_walkers w) {
+  if (!w) return AFQ_OK;
+  AFQ_GUARD((void)hipStreamSynchronize(w->sys->stream); delete w; return AFQ_OK;)
+}
+
+int afq_walkers_get(afq_walkers w, double* W, double* weights, double* logovlp, int32_t* alive, uint64_t* counter) {
+  AFQ_CHECK(w, AFQ_E_INVALID, "afq_walkers_get: walkers is NULL");
+  AFQ_GUARD({
+    afq_system s = w->sys;
+    AFQ_RET(check_device(s));
+    hipStream_t st = s->stream;
+    const size_t per = (size_t)s->M * s->ntot;
+    if (W) AFQ_TRY_HIP(hipMemcpyAsync(W, w->W.p, w->nw * per * 16, hipMemcpyDeviceToDevice, st));
+    if (weights) AFQ_TRY_HIP(hipMemcpyAsync(weights, w->weights.p, w->nw * 8, hipMemcpyDeviceToDevice, st));
+    if (alive) AFQ_TRY_HIP(hipMemcpyAsync(alive, w->alive.p, w->nw * 4, hipMemcpyDeviceToDevice, st));
+    if (logovlp) {
+      AFQ_RET(walkers_alloc_scratch(w));
+      AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), false, w->logdet.as<double2>()));
+      AFQ_RET(launch_logovlp(w->logdet.as<double2>(), w->nw, reinterpret_cast<double2*>(logovlp), st));
+    }
+    if (counter) *counter = w->counter;
+    return AFQ_OK;
+  })
+}
+
+int afq_walkers_set(afq_walkers w, const double* W, const double* weights, const int32_t* alive, uint64_t counter) {
+  AFQ_CHECK(w, AFQ_E_INVALID, "afq_walkers_set: walkers is NULL");
+  AFQ_GUARD({
+    afq_system s = w->sys;
+    AFQ_RET(check_device(s));
+    hipStream_t st = s->stream;
+    const size_t per = (size_t)s->M * s->ntot;
+    if (W) AFQ_TRY_HIP(hipMemcpyAsync(w->W.p, W, w->nw * per * 16, hipMemcpyDeviceToDevice, st));
+    if (weights) AFQ_TRY_HIP(hipMemcpyAsync(w->weights.p, weights, w->nw * 8, hipMemcpyDeviceToDevice, st));
+    if (alive) AFQ_TRY_HIP(hipMemcpyAsync(w->alive.p, alive, w->nw * 4, hipMemcpyDeviceToDevice, st));
+    w->counter = counter;
+    return AFQ_OK;
+  })
+}
+
+int afq_walkers_stats(afq_walkers w, int* n_alive, int64_t* n_killed) {
+  AFQ_CHECK(w, AFQ_E_INVALID, "afq_walkers_stats: walkers is NULL");
+  AFQ_GUARD({
+    afq_system s = w->sys;
+    AFQ_RET(check_device(s));
+    std::vector<int> al(w->nw);
+    int64_t k = 0;
+    AFQ_TRY_HIP(hipMemcpyAsync(al.data(), w->alive.p, w->nw * 4, hipMemcpyDeviceToHost, s->stream));
+    AFQ_TRY_HIP(hipMemcpyAsync(&k, w->killed.p, 8, hipMemcpyDeviceToHost, s->stream));
+    AFQ_TRY_HIP(hipStreamSynchronize(s->stream));
+    int c = 0;
+    for (int a : al) c += a != 0;
+    if (n_alive) *n_alive = c;
+    if (n_killed) *n_killed = k;
+    return AFQ_OK;
+  })
+}
+
+int afq_step(afq_system s, afq_walkers w, int n_steps, double dt, const double* fields, uint64_t seed, int qr_every,
+             double e_shift, int taylor_order, double* emix_out, double* eloc_out, double* weights_out,
+             double* ratio_out) {
+  AFQ_CHECK(s && w, AFQ_E_INVALID, "afq_step: NULL handle");
+  AFQ_CHECK(w->sys == s, AFQ_E_STATE, "afq_step: walkers belong to another system");
+  AFQ_CHECK(n_steps >= 0, AFQ_E_INVALID, "afq_step: n_steps < 0");
+  AFQ_CHECK(std::isfinite(dt) && dt >= 0.0, AFQ_E_INVALID, "afq_step: dt must be finite and >= 0");
+  AFQ_CHECK(qr_every >= 0, AFQ_E_INVALID, "afq_step: qr_every < 0");
+  AFQ_CHECK(taylor_order >= 1 && taylor_order <= 32, AFQ_E_INVALID, "afq_step: taylor_order must be in [1, 32]");
+  AFQ_CHECK(std::isfinite(e_shift), AFQ_E_INVALID, "afq_step: e_shift is not finite");
+  AFQ_GUARD({
+    AFQ_RET(check_device(s));
+    AFQ_RET(system_prepare_dt(s, dt));
+    AFQ_RET(system_prepare_pack(s, s->prec));
+    AFQ_RET(walkers_alloc_scratch(w));
+    const long nw = w->nw, X = s->X;
+    for (int k = 0; k < n_steps; ++k) {
+      const uint64_t idx = w->counter;
+      const bool do_qr = qr_every > 0 && (idx + 1) % (uint64_t)qr_every == 0;
+      AFQ_RET(step_once(s, w, dt, fields ? fields + (long)k * nw * X : nullptr, seed, 0, idx, do_qr, e_shift,
+                        taylor_order, emix_out ? emix_out + k : nullptr, eloc_out ? eloc_out + 2 * k * nw : nullptr,
+                        weights_out ? weights_out + k * nw : nullptr, ratio_out ? ratio_out + 2 * k * nw : nullptr));
+      w->counter++;
+    }
+    return AFQ_OK;
+  })
+}
+
+int afq_energy(afq_system s, afq_walkers w, double* eloc_out, double* parts_out, double* vbar_out, double* emix_out) {
+  AFQ_CHECK(s && w, AFQ_E_INVALID, "afq_energy: NULL handle");
+  AFQ_CHECK(w->sys == s, AFQ_E_STATE, "afq_energy: walkers belong to another system");
+  AFQ_GUARD(AFQ_RET(check_device(s)); return energy_call(s, w, eloc_out, parts_out, vbar_out, emix_out);)
+}
+
+int afq_energy_backward(afq_system s, afq_walkers w, double scale, double* d_h1, double* d_chol, double* d_walkers) {
+  AFQ_CHECK(s && w, AFQ_E_INVALID, "afq_energy_backward: NULL handle");
+  AFQ_CHECK(w->sys == s, AFQ_E_STATE, "afq_energy_backward: walkers belong to another system");
+  AFQ_CHECK(std::isfinite(scale), AFQ_E_INVALID, "afq_energy_backward: scale is not finite");
+  AFQ_GUARD(AFQ_RET(check_device(s)); return energy_backward(s, w, scale, d_h1, d_chol, d_walkers);)
+}
+
+int afq_fields_generate(uint64_t seed, uint32_t sys_id, uint64_t step0, int n_steps, int n_walkers, int n_chol,
+                        double* out, void* stream) {
+  AFQ_CHECK(n_steps >= 0 && n_walkers >= 0 && n_chol >= 0, AFQ_E_INVALID, "afq_fields_generate: negative size");
+  AFQ_CHECK(out || (long)n_steps * n_walkers * n_chol == 0, AFQ_E_INVALID, "afq_fields_generate: out is NULL");
+  AFQ_GUARD(return launch_fields(seed, sys_id, step0, n_walkers, n_chol, out, (long)n_walkers * n_chol, n_steps,
+                                 static_cast<hipStream_t>(stream));)
+}
+
+int afq_batch_create(afq_batch* out, int n, const afq_system* systems, const afq_walkers* walkers) {
+  AFQ_GUARD(return batch_create_impl(out, n, systems, walkers);)
+}
+
+int afq_batch_step(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_every, const double* e_shift,
+                   int taylor_order, double* emix_out) {
+  AFQ_GUARD(return batch_step_impl(b, n_steps, dt, seed, qr_every, e_shift, taylor_order, emix_out);)
+}
+
+int afq_batch_destroy(afq_batch b) { AFQ_GUARD(return batch_destroy_impl(b);) }
+
+}  // extern "C"

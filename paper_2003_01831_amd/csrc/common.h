@@ -1,0 +1,199 @@
+// Shared declarations of the gfx950 phaseless-AFQMC library: complex helpers,
+// error plumbing, the system/walker objects and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+#include "afq.h"
+
+// ---------------------------------------------------------------------------
+// error handling: internal functions return afq_status; the C ABI stores the
+// message in a thread-local string.
+// ---------------------------------------------------------------------------
+void afq_set_error(const std::string& msg);
+
+#define AFQ_TRY_HIP(expr)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      afq_set_error(std::string(#expr) + ": " + hipGetErrorString(e_));          \
+      return e_ == hipErrorOutOfMemory ? AFQ_E_NOMEM : AFQ_E_HIP;                \
+    }                                                                            \
+  } while (0)
+
+#define AFQ_CHECK(cond, code, msg)                                               \
+  do {                                                                           \
+    if (!(cond)) {                                                               \
+      afq_set_error(msg);                                                        \
+      return (code);                                                             \
+    }                                                                            \
+  } while (0)
+
+#define AFQ_RET(expr)                                                            \
+  do {                                                                           \
+    int r_ = (expr);                                                             \
+    if (r_ != AFQ_OK) return r_;                                                 \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// complex arithmetic on HIP vector types (double2 / float2 = re, im)
+// ---------------------------------------------------------------------------
+template <typename T> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+template <typename T> using cplx_t = typename cvec<T>::type;
+
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double2 cdiv(double2 a, double2 b) {
+  // Smith's algorithm keeps the intermediate quotient in range
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  } else {
+    double r = b.x / b.y, d = b.y + b.x * r;
+    return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+  }
+}
+__device__ inline double2 clog(double2 a) { return make_double2(0.5 * log(cabs2(a)), atan2(a.y, a.x)); }
+
+// ---------------------------------------------------------------------------
+// device buffer owned by the library
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int alloc(size_t n);
+  void free();
+  template <typename T> T* as() const { return reinterpret_cast<T*>(p); }
+  ~DevBuf() { free(); }
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+};
+
+// ---------------------------------------------------------------------------
+// packed operand layout of the exchange GEMM  C[(n,a)][(w,part,b)] = sum_k A B
+//   A rows (n, a): n * np + a, a < N (rows a >= N are zero), k < kp
+//   B rows (w, part, b): per walker 2*np rows, part 0 = Re, 1 = Im
+//   real trial: k runs over M orbitals;  complex trial: k over 2M
+//   (A = [Lt_re | Lt_im], B = [[Th_re, Th_im], [-Th_im, Th_re]])
+// ---------------------------------------------------------------------------
+struct PackShape {
+  int n = 0;    // electrons of this spin
+  int np = 0;   // n rounded up to 16
+  int ke = 0;   // contraction length (M or 2M)
+  int kp = 0;   // ke rounded up to the k-chunk
+};
+
+int exch_kchunk(int prec);
+
+struct afq_system_s {
+  int M = 0, n_up = 0, n_dn = 0, X = 0, ntot = 0;
+  double e_core = 0.0;
+  int prec = AFQ_FP64;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool real_trial = true;
+  DevBuf h1, chol, phi;        // f64 inputs (phi complex M x ntot)
+  DevBuf chol32;               // f32 copy of L (reduced modes)
+  DevBuf hp;                   // h' = h - 1/2 sum L L   (M x M f64)
+  DevBuf B1;                   // exp(-dt h'/2)          (M x M f64)
+  double B1_dt = -1.0;
+  DevBuf ht;                   // (T^H h)  ntot x M complex
+  DevBuf Lt;                   // (T^H L^n) X x ntot x M complex
+  DevBuf apack[2];             // packed A operand per spin (precision of prec)
+  DevBuf apack_lo[2];          // BF16x3 low parts
+  int apack_prec = -1;
+  PackShape ps[2];
+  int nspin_n(int s) const { return s == 0 ? n_up : n_dn; }
+  int spin_off(int s) const { return s == 0 ? 0 : n_up; }
+};
+
+struct afq_walkers_s {
+  afq_system sys = nullptr;
+  int nw = 0;
+  uint64_t counter = 0;
+  DevBuf W, Wn;                // walkers and the propagated copy (nw x M x ntot c128)
+  DevBuf weights;              // nw f64
+  DevBuf alive;                // nw int32
+  DevBuf killed;               // 1 x int64: walkers killed so far
+  // per-step scratch
+  DevBuf S, Sinv;              // per (w, spin): n x n complex (max n^2 stride)
+  DevBuf logdet, logdet_new;   // nw x 2 complex
+  DevBuf sing;                 // nw x 2 int
+  DevBuf theta;                // nw x M x ntot complex
+  DevBuf bpack, bpack_lo;      // packed B operand, both spins
+  DevBuf tro, troo;            // nw x 2 x X complex: tr Omega, tr Omega^2
+  DevBuf e1;                   // nw complex
+  DevBuf eloc, parts, vbar;    // nw complex, nw x 3 complex, nw x X complex
+  DevBuf coef;                 // nw x X complex (f64 or f32)
+  DevBuf lfac;                 // nw complex: sum_n x xbar - xbar^2/2
+  DevBuf amat;                 // nw x M x M complex (f64 or f32)
+  DevBuf t1, t2;               // Taylor terms (nw x M x ntot, f64 or f32)
+  DevBuf u;                    // Taylor sum (nw x M x ntot c128)
+  DevBuf fields;               // nw x X f64 (device Philox)
+  DevBuf gram, rinv;           // QR scratch (nw x 2 x n^2)
+  DevBuf emix_tmp;             // scalar scratch
+  size_t scratch_prec = (size_t)-1;
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (all on the given stream)
+// ---------------------------------------------------------------------------
+enum GemmOp { OP_N = 0, OP_T = 1, OP_C = 2 };
+
+template <typename T> struct GemmArgs {
+  int m, n, k, batch;
+  const T* A; long lda, sA; int opA; bool cA;   // cA: A is complex (interleaved)
+  const T* B; long ldb, sB; int opB; bool cB;
+  T* C; long ldc, sC; bool cC;                  // cC: C complex
+  double ar, ai, br, bi;                        // alpha, beta
+  double2* D; long ldd, sD;                     // optional D += result (complex f64)
+};
+// C = alpha op(A) op(B) + beta C   (D += alpha op(A) op(B) if D)
+template <typename T> int gemm(const GemmArgs<T>& g, hipStream_t st);
+template <typename T> GemmArgs<T> gemm_args();
+
+// batched in-place Gauss-Jordan inverse with partial pivoting of n x n complex
+// matrices (stride between matrices `stride` elements). Writes inv (may be
+// NULL: log det only), logdet (complex, per matrix), sing flag per matrix.
+int lu_inverse(const double2* S, long stride, int n, int batch, double2* inv,
+               double2* logdet, long ld_logdet, int* sing, long ld_sing, hipStream_t st);
+// Cholesky of Hermitian G = R^H R then R^-1 (upper); logdet gets log det R (real part).
+int chol_inverse(const double2* G, long stride, int n, int batch, double2* rinv,
+                 double2* logdet, long ld_logdet, int* sing, long ld_sing, hipStream_t st);
+
+int launch_fields(uint64_t seed, uint32_t sys_id, uint64_t step, int nw, int X, double* out,
+                  long ld_step, int n_steps, hipStream_t st);
+
+// system preparation
+int system_prepare_dt(afq_system s, double dt);
+int system_prepare_pack(afq_system s, int prec);
+
+// walker pieces
+int walkers_alloc_scratch(afq_walkers w);
+int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool want_theta,
+                          double2* logdet_out);
+int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed,
+              uint32_t sys_id, uint64_t step_index, bool do_qr, double e_shift, int order,
+              double* emix_out, double* eloc_out, double* weights_out, double* ratio_out);
+int energy_backward(afq_system s, afq_walkers w, double scale, double* d_h1, double* d_chol,
+                    double* d_walkers);
+
+// exchange contraction: tr Omega and tr Omega^2 per (w, spin, n)
+int exchange_launch(afq_system s, afq_walkers w, int spin, hipStream_t st);
+int pack_theta(afq_system s, afq_walkers w, hipStream_t st);
+
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+inline int round_up(int a, int b) { return (a + b - 1) / b * b; }

@@ -1,0 +1,263 @@
+// Batched small dense FP64 factorisations, one workgroup per matrix with the
+// matrix held in registers (element e = tid + NT*j of the row-major n x n
+// matrix lives in thread tid, slot j):
+//   * Gauss-Jordan inverse with partial pivoting and log-determinant (overlap
+//     matrices S = T^H W: Theta = W S^-1, log O = log det S);
+//   * Cholesky factor R of a Hermitian Gram matrix W^H W and its inverse, for
+//     CholeskyQR (Q = W R^-1, det R > 0).
+// Pivot rows are tracked implicitly (no physical swaps); the pivot row and
+// column are broadcast through LDS, three barriers per elimination step.
+#include "common.h"
+
+namespace {
+
+constexpr int NMAX = 128;
+
+template <int NT>
+struct GjShared {
+  double2 rowp[NMAX], colk[NMAX];
+  int used[NMAX], perm[NMAX], q[NMAX];
+  double red_v[NT / 64];
+  int red_i[NT / 64];
+  int p, sing;
+  double d;
+};
+
+// Gauss-Jordan elimination on the register-resident matrix. pivoting=false
+// takes pivot row k at step k (used for the triangular factor of QR).
+template <int NT, int EPT>
+__device__ void gauss_jordan(double2 (&a)[EPT], int n, bool pivoting, GjShared<NT>& sh,
+                             double2& logdet) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nn = n * n;
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    if (pivoting) {
+      double best = -1.0;
+      int bi = 1 << 30;
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int e = tid + NT * j;
+        if (e < nn) {
+          const int r = e / n, c = e - r * n;
+          if (c == k && !sh.used[r]) {
+            const double v = cabs2(a[j]);
+            if (v > best || (v == best && r < bi)) { best = v; bi = r; }
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if (lane == 0) { sh.red_v[wave] = best; sh.red_i[wave] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        double bv = sh.red_v[0];
+        int bx = sh.red_i[0];
+        for (int w = 1; w < NT / 64; ++w)
+          if (sh.red_v[w] > bv || (sh.red_v[w] == bv && sh.red_i[w] < bx)) { bv = sh.red_v[w]; bx = sh.red_i[w]; }
+        if (bx < 0 || bx >= n) {
+          // no usable pivot (non-finite column): take the first unused row, flag singular
+          bx = 0;
+          while (bx < n - 1 && sh.used[bx]) ++bx;
+          sh.sing = 1;
+        }
+        sh.p = bx;
+        sh.used[bx] = 1;
+        sh.perm[k] = bx;
+      }
+      __syncthreads();
+      p = sh.p;
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + NT * j;
+      if (e < nn) {
+        const int r = e / n, c = e - r * n;
+        if (r == p) sh.rowp[c] = a[j];
+        if (c == k) sh.colk[r] = a[j];
+      }
+    }
+    __syncthreads();
+    double2 piv = sh.rowp[k];
+    const double pm = cabs2(piv);
+    if (!(pm > 0.0) || !isfinite(pm)) {
+      if (tid == 0) sh.sing = 1;
+      piv = make_double2(1.0, 0.0);
+    }
+    const double2 ipiv = cdiv(make_double2(1.0, 0.0), piv);
+    logdet = cadd(logdet, clog(piv));
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + NT * j;
+      if (e < nn) {
+        const int r = e / n, c = e - r * n;
+        const double2 rp = c == k ? ipiv : cmul(sh.rowp[c], ipiv);
+        if (r == p) {
+          a[j] = rp;
+        } else {
+          const double2 base = c == k ? make_double2(0.0, 0.0) : a[j];
+          a[j] = csub(base, cmul(sh.colk[r], rp));
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int NT, int EPT>
+__global__ __launch_bounds__(NT) void gj_kernel(const double2* __restrict__ S, long stride, int n,
+                                                double2* __restrict__ inv, double2* __restrict__ logdet,
+                                                long ld_logdet, int* __restrict__ sing, long ld_sing) {
+  __shared__ GjShared<NT> sh;
+  const long b = blockIdx.x;
+  const int tid = threadIdx.x, nn = n * n;
+  double2 a[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = tid + NT * j;
+    a[j] = e < nn ? S[b * stride + e] : make_double2(0.0, 0.0);
+  }
+  if (tid < n) sh.used[tid] = 0;
+  if (tid == 0) sh.sing = 0;
+  __syncthreads();
+  double2 ld = make_double2(0.0, 0.0);
+  gauss_jordan<NT, EPT>(a, n, true, sh, ld);
+  if (tid == 0) {
+    // parity of the pivot permutation k -> perm[k]; inverse permutation q
+    int parity = 0;
+    for (int k = 0; k < n; ++k) { sh.q[sh.perm[k]] = k; sh.used[k] = 0; }
+    for (int s0 = 0; s0 < n; ++s0) {
+      if (sh.used[s0]) continue;
+      int len = 0, x = s0;
+      while (!sh.used[x]) { sh.used[x] = 1; x = sh.perm[x]; ++len; }
+      parity ^= (len - 1) & 1;
+    }
+    if (parity) ld.y += 3.14159265358979323846;
+    ld.y = remainder(ld.y, 2.0 * 3.14159265358979323846);
+    logdet[b * ld_logdet] = sh.sing ? make_double2(-INFINITY, 0.0) : ld;
+    sing[b * ld_sing] = sh.sing;
+  }
+  __syncthreads();
+  if (inv) {
+    // inverse element (a, b) = M[perm[a]][q[b]]: thread with M[r][c] writes (q[r], perm[c])
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + NT * j;
+      if (e < nn) {
+        const int r = e / n, c = e - r * n;
+        inv[b * stride + (long)sh.q[r] * n + sh.perm[c]] = a[j];
+      }
+    }
+  }
+}
+
+template <int NT, int EPT>
+__global__ __launch_bounds__(NT) void chol_inv_kernel(const double2* __restrict__ G, long stride, int n,
+                                                      double2* __restrict__ rinv, double2* __restrict__ logdet,
+                                                      long ld_logdet, int* __restrict__ sing, long ld_sing) {
+  __shared__ GjShared<NT> sh;
+  const long b = blockIdx.x;
+  const int tid = threadIdx.x, nn = n * n;
+  double2 a[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = tid + NT * j;
+    a[j] = e < nn ? G[b * stride + e] : make_double2(0.0, 0.0);
+  }
+  if (tid == 0) sh.sing = 0;
+  __syncthreads();
+  double ldr = 0.0;
+  // right-looking Cholesky G = R^H R on the upper triangle
+  for (int k = 0; k < n; ++k) {
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + NT * j;
+      if (e == k * n + k) {
+        double d = sqrt(a[j].x);
+        if (!(d > 0.0) || !isfinite(d)) { sh.sing = 1; d = 1.0; }
+        sh.d = d;
+      }
+    }
+    __syncthreads();
+    const double d = sh.d, id = 1.0 / d;
+    ldr += log(d);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + NT * j;
+      if (e < nn) {
+        const int r = e / n, c = e - r * n;
+        if (r == k && c >= k) {
+          a[j] = c == k ? make_double2(d, 0.0) : cscale(a[j], id);
+          sh.rowp[c] = a[j];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + NT * j;
+      if (e < nn) {
+        const int r = e / n, c = e - r * n;
+        if (r > k && c >= r) a[j] = csub(a[j], cmul(cconj(sh.rowp[r]), sh.rowp[c]));
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = tid + NT * j;
+    if (e < nn) {
+      const int r = e / n, c = e - r * n;
+      if (r > c) a[j] = make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  double2 ld = make_double2(0.0, 0.0);
+  gauss_jordan<NT, EPT>(a, n, false, sh, ld);
+  if (tid == 0) {
+    logdet[b * ld_logdet] = make_double2(ldr, 0.0);
+    sing[b * ld_sing] = sh.sing;
+  }
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = tid + NT * j;
+    if (e < nn) rinv[b * stride + e] = a[j];
+  }
+}
+
+}  // namespace
+
+#define AFQ_SMALL_DISPATCH(KERNEL, ...)                                                    \
+  do {                                                                                     \
+    if (n <= 32)                                                                           \
+      hipLaunchKernelGGL((KERNEL<256, 4>), dim3(batch), dim3(256), 0, st, __VA_ARGS__);    \
+    else if (n <= 64)                                                                      \
+      hipLaunchKernelGGL((KERNEL<256, 16>), dim3(batch), dim3(256), 0, st, __VA_ARGS__);   \
+    else if (n <= 101)                                                                     \
+      hipLaunchKernelGGL((KERNEL<512, 20>), dim3(batch), dim3(512), 0, st, __VA_ARGS__);   \
+    else                                                                                   \
+      hipLaunchKernelGGL((KERNEL<1024, 16>), dim3(batch), dim3(1024), 0, st, __VA_ARGS__); \
+  } while (0)
+
+int lu_inverse(const double2* S, long stride, int n, int batch, double2* inv, double2* logdet,
+               long ld_logdet, int* sing, long ld_sing, hipStream_t st) {
+  AFQ_CHECK(n >= 1 && n <= NMAX, AFQ_E_UNSUPPORTED, "lu_inverse: n must be in [1, 128]");
+  AFQ_CHECK(stride >= (long)n * n, AFQ_E_INVALID, "lu_inverse: stride < n*n");
+  if (batch <= 0) return AFQ_OK;
+  AFQ_SMALL_DISPATCH(gj_kernel, S, stride, n, inv, logdet, ld_logdet, sing, ld_sing);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+
+int chol_inverse(const double2* G, long stride, int n, int batch, double2* rinv, double2* logdet,
+                 long ld_logdet, int* sing, long ld_sing, hipStream_t st) {
+  AFQ_CHECK(n >= 1 && n <= NMAX, AFQ_E_UNSUPPORTED, "chol_inverse: n must be in [1, 128]");
+  AFQ_CHECK(stride >= (long)n * n, AFQ_E_INVALID, "chol_inverse: stride < n*n");
+  if (batch <= 0) return AFQ_OK;
+  AFQ_SMALL_DISPATCH(chol_inv_kernel, G, stride, n, rinv, logdet, ld_logdet, sing, ld_sing);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}

@@ -1,0 +1,56 @@
+// Launchers of the per-walker and elementwise kernels (step_kernels.hip).
+#pragma once
+#include "common.h"
+
+struct AssembleArgs {
+  int nw, ntot, M, X;
+  const double2* thetaT;   // nw x ntot x M
+  const double2* ht;       // ntot x M
+  const double2* tro;      // nw x 2 x X
+  const double2* troo;     // nw x 2 x X
+  double e_core, dt;
+  const double* fields;    // nw x X or NULL (Philox)
+  uint64_t seed, step;
+  uint32_t sys_id;
+  double2* eloc;           // nw (internal)
+  double2* eloc_out;       // nw (optional, caller)
+  double2* parts;          // nw x 3 (optional)
+  double2* vbar_out;       // nw x X (optional)
+  double2* lfac;           // nw (when coefficients are produced)
+};
+
+struct WeightArgs {
+  const double2* logdet_new;  // nw x 2
+  const double2* logdet_cur;  // nw x 2
+  const int* sing_new;        // nw x 2
+  const double2* lfac;        // nw
+  double* weights;            // nw
+  int* alive;                 // nw
+  int64_t* killed;            // 1
+  double dt, e_shift;
+  double2* ratio_out;         // nw (optional)
+  double* weights_out;        // nw (optional)
+  double2* W;                 // nw x per
+  const double2* Wn;          // nw x per
+  long per;
+};
+
+int pack_a(int prec, const double2* Lt, int X, int ntot, int M, int off, const PackShape& ps, bool real_trial,
+           void* hi, void* lo, hipStream_t st);
+int pack_b(int prec, const double2* thT, int nw, int ntot, int M, int off, const PackShape& ps, bool real_trial,
+           void* hi, void* lo, hipStream_t st);
+int convert_d2f(const double* x, float* y, long n, hipStream_t st);
+int copy_d(const double* x, double* y, long n, hipStream_t st);
+int fill_d(double* y, double v, long n, hipStream_t st);
+int fill_i(int* y, int v, long n, hipStream_t st);
+int fill_eye(double* y, int M, hipStream_t st);
+int broadcast_trial(const double2* phi, double2* W, long per, int nw, hipStream_t st);
+int masked_copy(const double2* src, double2* dst, long per, int nw, const int* alive, hipStream_t st);
+int launch_assemble(const AssembleArgs& a, void* coef, bool coef_f32, hipStream_t st);
+int launch_emix(const double2* eloc, const double* wt, int nw, double* out, hipStream_t st);
+int launch_weights(const WeightArgs& a, int nw, hipStream_t st);
+int launch_asym(const double* x, int M, long nmat, double* out2, hipStream_t st);
+int launch_maximag(const double2* z, long n, double* out, hipStream_t st);
+int launch_infnorm(const double* x, int M, double* out, hipStream_t st);
+int launch_logovlp(const double2* ld, int nw, double2* out, hipStream_t st);
+int launch_init_alive(const double* wt, const int* sing, int nw, int* alive, int* bad, hipStream_t st);

@@ -1,0 +1,308 @@
+// Walker objects and the sequence of one walker step:
+//   overlap S = T^H W, S^-1 and log det S (FP64)  ->  Theta^T = S^-T W^T
+//   -> packed Theta -> exchange/Coulomb traces -> E_L, force bias and the
+//   propagator coefficients -> A = sum_n c_n L^n -> W' = B1 T_K(A) B1 W
+//   -> new overlap and phaseless weight -> periodic CholeskyQR2.
+#include "common.h"
+#include "step_kernels.h"
+
+static size_t esz_of(int prec) { return prec == AFQ_FP64 ? 8 : prec == AFQ_CFP32 ? 4 : 2; }
+
+int walkers_alloc_scratch(afq_walkers w) {
+  afq_system s = w->sys;
+  if (w->scratch_prec == (size_t)s->prec) return AFQ_OK;
+  const int nw = w->nw, M = s->M, ntot = s->ntot, X = s->X;
+  const int nmax = std::max(s->n_up, s->n_dn);
+  const size_t per = (size_t)M * ntot;
+  const bool f64 = s->prec == AFQ_FP64;
+  const size_t cz = f64 ? 16 : 8;  // complex element of the reduced-precision buffers
+  if (!w->S.p) {
+    AFQ_RET(w->S.alloc((size_t)nw * 2 * nmax * nmax * 16));
+    AFQ_RET(w->Sinv.alloc((size_t)nw * 2 * nmax * nmax * 16));
+    AFQ_RET(w->logdet.alloc((size_t)nw * 2 * 16));
+    AFQ_RET(w->logdet_new.alloc((size_t)nw * 2 * 16));
+    AFQ_RET(w->sing.alloc((size_t)nw * 2 * sizeof(int)));
+    AFQ_RET(w->theta.alloc((size_t)nw * per * 16));
+    AFQ_RET(w->tro.alloc((size_t)nw * 2 * X * 16));
+    AFQ_RET(w->troo.alloc((size_t)nw * 2 * X * 16));
+    AFQ_RET(w->eloc.alloc((size_t)nw * 16));
+    AFQ_RET(w->lfac.alloc((size_t)nw * 16));
+    AFQ_RET(w->u.alloc((size_t)nw * per * 16));
+    AFQ_RET(w->gram.alloc((size_t)nw * 2 * nmax * nmax * 16));
+    AFQ_RET(w->rinv.alloc((size_t)nw * 2 * nmax * nmax * 16));
+    AFQ_RET(w->emix_tmp.alloc(64));
+  }
+  size_t bsz = 0;
+  for (int sp = 0; sp < 2; ++sp) bsz += (size_t)nw * 2 * s->ps[sp].np * s->ps[sp].kp;
+  AFQ_RET(w->bpack.alloc(bsz * esz_of(s->prec)));
+  if (s->prec == AFQ_BF16X3) AFQ_RET(w->bpack_lo.alloc(bsz * esz_of(s->prec)));
+  else w->bpack_lo.free();
+  AFQ_RET(w->coef.alloc((size_t)nw * X * cz));
+  AFQ_RET(w->amat.alloc((size_t)nw * M * M * cz));
+  AFQ_RET(w->t1.alloc((size_t)nw * per * cz));
+  AFQ_RET(w->t2.alloc((size_t)nw * per * cz));
+  w->scratch_prec = (size_t)s->prec;
+  return AFQ_OK;
+}
+
+// S^s = T^sH W^s for every walker; S^-1 (optional) and log det; Theta^T = S^-T W^T
+int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool want_theta, double2* logdet_out) {
+  hipStream_t st = s->stream;
+  const int M = s->M, ntot = s->ntot, nw = w->nw;
+  const int nmax = std::max(s->n_up, s->n_dn);
+  const long nm2 = (long)nmax * nmax;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = s->nspin_n(sp), off = s->spin_off(sp);
+    GemmArgs<double> g = gemm_args<double>();
+    g.m = n; g.n = n; g.k = M; g.batch = nw;
+    g.A = s->phi.as<double>() + 2 * off; g.lda = ntot; g.opA = OP_C; g.cA = true; g.sA = 0;
+    g.B = reinterpret_cast<const double*>(Wsrc) + 2 * off; g.ldb = ntot; g.cB = true; g.sB = (long)M * ntot;
+    g.C = w->S.as<double>() + 2 * sp * nm2; g.ldc = n; g.cC = true; g.sC = 2 * nm2;
+    AFQ_RET(gemm<double>(g, st));
+    AFQ_RET(lu_inverse(w->S.as<double2>() + sp * nm2, 2 * nm2, n, nw,
+                       want_theta ? w->Sinv.as<double2>() + sp * nm2 : nullptr, logdet_out + sp, 2,
+                       w->sing.as<int>() + sp, 2, st));
+    if (want_theta) {
+      // thetaT[w][off + b][k] = sum_j Sinv[j][b] W[k][off + j]
+      GemmArgs<double> t = gemm_args<double>();
+      t.m = n; t.n = M; t.k = n; t.batch = nw;
+      t.A = w->Sinv.as<double>() + 2 * sp * nm2; t.lda = n; t.opA = OP_T; t.cA = true; t.sA = 2 * nm2;
+      t.B = reinterpret_cast<const double*>(Wsrc) + 2 * off; t.ldb = ntot; t.opB = OP_T; t.cB = true;
+      t.sB = (long)M * ntot;
+      t.C = w->theta.as<double>() + 2 * (long)off * M; t.ldc = M; t.cC = true; t.sC = (long)ntot * M;
+      AFQ_RET(gemm<double>(t, st));
+    }
+  }
+  return AFQ_OK;
+}
+
+int pack_theta(afq_system s, afq_walkers w, hipStream_t st) {
+  const size_t esz = esz_of(s->prec);
+  size_t off_bytes = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const PackShape& ps = s->ps[sp];
+    void* hi = w->bpack.as<char>() + off_bytes;
+    void* lo = s->prec == AFQ_BF16X3 ? (void*)(w->bpack_lo.as<char>() + off_bytes) : nullptr;
+    AFQ_RET(pack_b(s->prec, w->theta.as<double2>(), w->nw, s->ntot, s->M, s->spin_off(sp), ps, s->real_trial, hi,
+                   lo, st));
+    off_bytes += (size_t)w->nw * 2 * ps.np * ps.kp * esz;
+  }
+  return AFQ_OK;
+}
+
+// Force bias / Coulomb traces in FP64: tro[w][s][n] = tr(Lt^{ns} Theta^s_w)
+//   = sum_{(a,k)} thetaT[w][off + a][k] Lt[n][off + a][k]
+// as one GEMM [nw x N M] x [N M x X] per spin. In split-BF16x3 mode this
+// replaces the exchange kernel's traces: vbar enters EJ squared and the
+// propagator, and its O(X N M) cost is 1/N of the exchange.
+static int coulomb_fp64(afq_system s, afq_walkers w, hipStream_t st) {
+  const int M = s->M, ntot = s->ntot, X = s->X;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = s->nspin_n(sp), off = s->spin_off(sp);
+    GemmArgs<double> g = gemm_args<double>();
+    g.m = w->nw; g.n = X; g.k = n * M;
+    g.A = w->theta.as<double>() + 2 * (long)off * M; g.lda = (long)ntot * M; g.cA = true;
+    g.B = s->Lt.as<double>() + 2 * (long)off * M; g.ldb = (long)ntot * M; g.opB = OP_T; g.cB = true;
+    g.C = w->tro.as<double>() + 2 * (long)sp * X; g.ldc = 2L * X; g.cC = true;
+    AFQ_RET(gemm<double>(g, st));
+  }
+  return AFQ_OK;
+}
+
+// Theta (already computed) -> exchange traces -> assembly (coef optional)
+static int energy_from_theta(afq_system s, afq_walkers w, AssembleArgs& a, bool want_coef) {
+  hipStream_t st = s->stream;
+  AFQ_RET(pack_theta(s, w, st));
+  AFQ_RET(exchange_launch(s, w, 0, st));
+  AFQ_RET(exchange_launch(s, w, 1, st));
+  if (s->prec == AFQ_BF16X3) AFQ_RET(coulomb_fp64(s, w, st));
+  a.nw = w->nw; a.ntot = s->ntot; a.M = s->M; a.X = s->X;
+  a.thetaT = w->theta.as<double2>();
+  a.ht = s->ht.as<double2>();
+  a.tro = w->tro.as<double2>();
+  a.troo = w->troo.as<double2>();
+  a.e_core = s->e_core;
+  a.eloc = w->eloc.as<double2>();
+  a.lfac = want_coef ? w->lfac.as<double2>() : nullptr;
+  return launch_assemble(a, want_coef ? w->coef.p : nullptr, s->prec != AFQ_FP64, st);
+}
+
+int energy_call(afq_system s, afq_walkers w, double* eloc_out, double* parts_out, double* vbar_out, double* emix_out) {
+  AFQ_RET(system_prepare_pack(s, s->prec));
+  AFQ_RET(walkers_alloc_scratch(w));
+  AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), true, w->logdet.as<double2>()));
+  AssembleArgs a{};
+  a.dt = 0.0;
+  a.eloc_out = reinterpret_cast<double2*>(eloc_out);
+  a.parts = reinterpret_cast<double2*>(parts_out);
+  a.vbar_out = reinterpret_cast<double2*>(vbar_out);
+  AFQ_RET(energy_from_theta(s, w, a, false));
+  if (emix_out) AFQ_RET(launch_emix(w->eloc.as<double2>(), w->weights.as<double>(), w->nw, emix_out, s->stream));
+  return AFQ_OK;
+}
+
+// W' = B1 T_K(A) B1 W for all walkers (complex A per walker, both spins at once)
+template <typename T>
+static int propagate(afq_system s, afq_walkers w, int order) {
+  hipStream_t st = s->stream;
+  const int M = s->M, ntot = s->ntot, nw = w->nw, X = s->X;
+  const long per = (long)M * ntot;
+  // A_w = sum_n c_wn L^n : [nw x X] (complex) x [X x M^2] (real)
+  {
+    GemmArgs<T> g = gemm_args<T>();
+    g.m = nw; g.n = M * M; g.k = X;
+    g.A = w->coef.as<T>(); g.lda = X; g.cA = true;
+    g.B = sizeof(T) == 8 ? reinterpret_cast<const T*>(s->chol.p) : reinterpret_cast<const T*>(s->chol32.p);
+    g.ldb = (long)M * M; g.cB = false;
+    g.C = w->amat.as<T>(); g.ldc = (long)M * M; g.cC = true;
+    AFQ_RET(gemm<T>(g, st));
+  }
+  // U = B1 W  (FP64)
+  {
+    GemmArgs<double> g = gemm_args<double>();
+    g.m = M; g.n = ntot; g.k = M; g.batch = nw;
+    g.A = s->B1.as<double>(); g.lda = M; g.cA = false; g.sA = 0;
+    g.B = w->W.as<double>(); g.ldb = ntot; g.cB = true; g.sB = per;
+    g.C = w->u.as<double>(); g.ldc = ntot; g.cC = true; g.sC = per;
+    AFQ_RET(gemm<double>(g, st));
+  }
+  // term_0 = U (in the contraction precision); term_j = A term_{j-1} / j; U += term_j
+  T* cur = w->t1.as<T>();
+  T* nxt = w->t2.as<T>();
+  if (sizeof(T) == 8) AFQ_RET(copy_d(w->u.as<double>(), reinterpret_cast<double*>(cur), 2 * per * nw, st));
+  else AFQ_RET(convert_d2f(w->u.as<double>(), reinterpret_cast<float*>(cur), 2 * per * nw, st));
+  for (int j = 1; j <= order; ++j) {
+    GemmArgs<T> g = gemm_args<T>();
+    g.m = M; g.n = ntot; g.k = M; g.batch = nw;
+    g.A = w->amat.as<T>(); g.lda = M; g.cA = true; g.sA = (long)M * M;
+    g.B = cur; g.ldb = ntot; g.cB = true; g.sB = per;
+    g.C = j < order ? nxt : nullptr; g.ldc = ntot; g.cC = true; g.sC = per;
+    g.ar = 1.0 / j;
+    g.D = w->u.as<double2>(); g.ldd = ntot; g.sD = per;
+    AFQ_RET(gemm<T>(g, st));
+    std::swap(cur, nxt);
+  }
+  // W' = B1 U
+  {
+    GemmArgs<double> g = gemm_args<double>();
+    g.m = M; g.n = ntot; g.k = M; g.batch = nw;
+    g.A = s->B1.as<double>(); g.lda = M; g.cA = false; g.sA = 0;
+    g.B = w->u.as<double>(); g.ldb = ntot; g.cB = true; g.sB = per;
+    g.C = w->Wn.as<double>(); g.ldc = ntot; g.cC = true; g.sC = per;
+    AFQ_RET(gemm<double>(g, st));
+  }
+  return AFQ_OK;
+}
+
+// CholeskyQR2 of every spin block: W^s <- W^s R^-1 twice, live walkers only.
+static int qr_walkers(afq_system s, afq_walkers w) {
+  hipStream_t st = s->stream;
+  const int M = s->M, ntot = s->ntot, nw = w->nw;
+  const long per = (long)M * ntot;
+  const int nmax = std::max(s->n_up, s->n_dn);
+  const long nm2 = (long)nmax * nmax;
+  double2* bufs[3] = {w->W.as<double2>(), w->Wn.as<double2>(), w->u.as<double2>()};
+  for (int pass = 0; pass < 2; ++pass) {
+    const double* src = reinterpret_cast<const double*>(bufs[pass]);
+    double* dst = reinterpret_cast<double*>(bufs[pass + 1]);
+    for (int sp = 0; sp < 2; ++sp) {
+      const int n = s->nspin_n(sp), off = s->spin_off(sp);
+      GemmArgs<double> g = gemm_args<double>();
+      g.m = n; g.n = n; g.k = M; g.batch = nw;
+      g.A = src + 2 * off; g.lda = ntot; g.opA = OP_C; g.cA = true; g.sA = per;
+      g.B = src + 2 * off; g.ldb = ntot; g.cB = true; g.sB = per;
+      g.C = w->gram.as<double>() + 2 * sp * nm2; g.ldc = n; g.cC = true; g.sC = 2 * nm2;
+      AFQ_RET(gemm<double>(g, st));
+      AFQ_RET(chol_inverse(w->gram.as<double2>() + sp * nm2, 2 * nm2, n, nw, w->rinv.as<double2>() + sp * nm2,
+                           w->logdet_new.as<double2>() + sp, 2, w->sing.as<int>() + sp, 2, st));
+      GemmArgs<double> q = gemm_args<double>();
+      q.m = M; q.n = n; q.k = n; q.batch = nw;
+      q.A = src + 2 * off; q.lda = ntot; q.cA = true; q.sA = per;
+      q.B = w->rinv.as<double>() + 2 * sp * nm2; q.ldb = n; q.cB = true; q.sB = 2 * nm2;
+      q.C = dst + 2 * off; q.ldc = ntot; q.cC = true; q.sC = per;
+      AFQ_RET(gemm<double>(q, st));
+    }
+  }
+  return masked_copy(bufs[2], bufs[0], per, nw, w->alive.as<int>(), st);
+}
+
+int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed, uint32_t sys_id,
+              uint64_t step_index, bool do_qr, double e_shift, int order, double* emix_out, double* eloc_out,
+              double* weights_out, double* ratio_out) {
+  hipStream_t st = s->stream;
+  const int nw = w->nw;
+  // overlap, Theta and the energy at the start-of-step walkers
+  AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), true, w->logdet.as<double2>()));
+  AssembleArgs a{};
+  a.dt = dt;
+  a.fields = fields;
+  a.seed = seed;
+  a.step = step_index;
+  a.sys_id = sys_id;
+  a.eloc_out = reinterpret_cast<double2*>(eloc_out);
+  AFQ_RET(energy_from_theta(s, w, a, true));
+  if (emix_out) AFQ_RET(launch_emix(w->eloc.as<double2>(), w->weights.as<double>(), nw, emix_out, st));
+  // propagate
+  if (s->prec == AFQ_FP64) AFQ_RET(propagate<double>(s, w, order));
+  else AFQ_RET(propagate<float>(s, w, order));
+  // new overlap (log det only) and the phaseless weight
+  AFQ_RET(compute_overlap_theta(s, w, w->Wn.as<double2>(), false, w->logdet_new.as<double2>()));
+  WeightArgs wa{};
+  wa.logdet_new = w->logdet_new.as<double2>();
+  wa.logdet_cur = w->logdet.as<double2>();
+  wa.sing_new = w->sing.as<int>();
+  wa.lfac = w->lfac.as<double2>();
+  wa.weights = w->weights.as<double>();
+  wa.alive = w->alive.as<int>();
+  wa.killed = w->killed.as<int64_t>();
+  wa.dt = dt;
+  wa.e_shift = e_shift;
+  wa.ratio_out = reinterpret_cast<double2*>(ratio_out);
+  wa.weights_out = weights_out;
+  wa.W = w->W.as<double2>();
+  wa.Wn = w->Wn.as<double2>();
+  wa.per = (long)s->M * s->ntot;
+  AFQ_RET(launch_weights(wa, nw, st));
+  if (do_qr) AFQ_RET(qr_walkers(s, w));
+  return AFQ_OK;
+}
+
+int walkers_create_impl(afq_walkers* out, afq_system s, int nw, const double* w0, const double* wt0) {
+  AFQ_CHECK(out, AFQ_E_INVALID, "afq_walkers_create: out is NULL");
+  *out = nullptr;
+  AFQ_CHECK(s, AFQ_E_INVALID, "afq_walkers_create: system is NULL");
+  AFQ_CHECK(nw >= 1 && nw <= 65535, AFQ_E_INVALID, "afq_walkers_create: n_walkers must be in [1, 65535]");
+  afq_walkers w = new afq_walkers_s();
+  int rc = [&]() -> int {
+    w->sys = s;
+    w->nw = nw;
+    hipStream_t st = s->stream;
+    const long per = (long)s->M * s->ntot;
+    AFQ_RET(w->W.alloc((size_t)nw * per * 16));
+    AFQ_RET(w->Wn.alloc((size_t)nw * per * 16));
+    AFQ_RET(w->weights.alloc((size_t)nw * 8));
+    AFQ_RET(w->alive.alloc((size_t)nw * 4));
+    AFQ_RET(w->killed.alloc(16));
+    AFQ_TRY_HIP(hipMemsetAsync(w->killed.p, 0, 16, st));
+    if (w0) AFQ_TRY_HIP(hipMemcpyAsync(w->W.p, w0, (size_t)nw * per * 16, hipMemcpyDeviceToDevice, st));
+    else AFQ_RET(broadcast_trial(s->phi.as<double2>(), w->W.as<double2>(), per, nw, st));
+    if (wt0) AFQ_TRY_HIP(hipMemcpyAsync(w->weights.p, wt0, (size_t)nw * 8, hipMemcpyDeviceToDevice, st));
+    else AFQ_RET(fill_d(w->weights.as<double>(), 1.0, nw, st));
+    AFQ_RET(walkers_alloc_scratch(w));
+    AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), false, w->logdet.as<double2>()));
+    int* bad = reinterpret_cast<int*>(w->emix_tmp.p);
+    AFQ_TRY_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+    AFQ_RET(launch_init_alive(w->weights.as<double>(), w->sing.as<int>(), nw, w->alive.as<int>(), bad, st));
+    int hbad = 0;
+    AFQ_TRY_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    AFQ_TRY_HIP(hipStreamSynchronize(st));
+    AFQ_CHECK(hbad == 0, AFQ_E_SINGULAR, "afq_walkers_create: a live walker has a singular overlap with the trial");
+    return AFQ_OK;
+  }();
+  if (rc != AFQ_OK) {
+    delete w;
+    return rc;
+  }
+  *out = w;
+  return AFQ_OK;
+}
