@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched phaseless-AFQMC walker step on one MI355X.
+
+Workload (default): M=400 orbitals, 100+100 electrons, 1600 Cholesky vectors,
+512 walkers at the trial, dt 0.005, QR every 5 steps, energy measured every
+step, fields from the device Philox stream; synthetic seeded inputs
+(paper_2003_01831_amd.synth, workload "m400").
+
+Prints ONE JSON line: walker-steps/s of the headline precision (split-BF16x3
+by default), the same rate for the plain FP64 path and complex FP32 on the same
+GPU, the algorithmic TFLOP/s, the roofline entry of the dominant kernel (the
+fused exchange contraction, timed with HIP events on the library stream), the
+error against the CPU FP64 oracle on a 4-walker subset, and the oracle's own
+rate on the host cores (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "cfp32": 157.3, "bf16x3": 2500.0}
+DTYPE = {"fp64": "f64", "cfp32": "f32", "bf16x3": "bf16x3"}
+
+
+def flops_per_walker_step(M, N, X, K=6, qr_every=5, real_trial=True):
+    """Algorithmic flop count of one walker step (both spins, energy every step).
+    The exchange and Coulomb terms use the real half-rotated Cholesky tensor of a
+    real trial (4 flop per real-by-complex multiply-add); the complex-model count
+    (8 flop per complex multiply-add everywhere) is returned alongside."""
+    cm = 8.0
+    ex_mac = 4.0 if real_trial else 8.0
+    parts = {
+        "overlap": cm * 2 * (N * N * M + N ** 3 + M * N * N),
+        "coulomb": ex_mac * 2 * X * N * M,
+        "exchange": ex_mac * 2 * X * N * N * M + cm * 2 * X * N * N,
+        "abuild": 4.0 * M * M * X,
+        "taylor": cm * K * M * M * 2 * N + 4.0 * 2 * M * M * 2 * N,
+        "weight": cm * 2 * (N * N * M + N ** 3 / 3),
+        "qr": cm * 2 * (2 * M * N * N - 2 * N ** 3 / 3) / max(qr_every, 1),
+    }
+    model = dict(parts)
+    model["coulomb"] = 8.0 * 2 * X * N * M
+    model["exchange"] = 8.0 * 2 * X * N * N * M + 8.0 * 2 * X * N * N
+    return sum(parts.values()), parts, sum(model.values())
+
+
+def rel_max(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="bf16x3", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--workload", default="m400")
+    ap.add_argument("--walkers", type=int, default=None, help="override the walker count")
+    ap.add_argument("--compare-steps", type=int, default=3, help="timed steps of the other precisions (0: skip)")
+    ap.add_argument("--check-steps", type=int, default=2, help="steps of the 4-walker oracle check (0: skip)")
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args(argv)
+
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the walker step shards by walkers and this build "
+              "measures one GPU's share (see DESIGN.md); use --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2003_01831_amd import synth, api, _lib
+
+    cfg = dict(synth.WORKLOADS[a.workload])
+    M, nu, nd, X = cfg["M"], cfg["n_up"], cfg["n_dn"], cfg["n_chol"]
+    nw = a.walkers or cfg["n_walkers"]
+    dt, qr = cfg["dt"], cfg["qr_every"]
+    t0 = time.perf_counter()
+    s = synth.make_system(M, nu, nd, X, seed=cfg["seed"])
+    print(f"[bench] system generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    lib = _lib.load()
+    sysg = api.System.from_synth(s, precision=a.precision)
+    # E_shift = variational energy of the trial (walkers at the trial)
+    probe = api.Walkers(sysg, 1)
+    e_var = float(probe.energy()[3][0])
+    probe.close()
+
+    def timed(prec, steps, warmup):
+        sysg.set_precision(prec)
+        wk = api.Walkers(sysg, nw)
+        if warmup:
+            wk.step(warmup, dt, seed=11, qr_every=qr, e_shift=e_var, outputs=("emix",))
+        torch.cuda.synchronize()
+        lib.afq_trace_reset()
+        lib.afq_trace_enable(1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = wk.step(steps, dt, seed=11, qr_every=qr, e_shift=e_var, outputs=("emix",))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        lib.afq_trace_enable(0)
+        import ctypes as C
+        phases = {}
+        for i, name in enumerate(_lib.PHASES):
+            ms, cnt = C.c_double(), C.c_int64()
+            _lib.check(lib.afq_trace_query(i, C.byref(ms), C.byref(cnt)))
+            phases[name] = (ms.value, cnt.value)
+        lib.afq_trace_reset()
+        emix = out["emix"].cpu().numpy()
+        wk.close()
+        return wall, phases, emix
+
+    print(f"[bench] timing {a.precision}: {a.warmup} warmup + {a.steps} steps, {nw} walkers", file=sys.stderr,
+          flush=True)
+    wall, phases, emix = timed(a.precision, a.steps, a.warmup)
+    value = nw * a.steps / wall
+    flop_ws, flop_parts, flop_model = flops_per_walker_step(M, nu, X, 6, qr)
+    alg_tflops = flop_ws * nw * a.steps / wall / 1e12
+
+    ex_ms, ex_cnt = phases["exchange"]
+    per_launch_flops = flop_parts["exchange"] / 2 * nw          # one spin per launch
+    ex_avg_s = ex_ms / 1e3 / max(ex_cnt, 1)
+    achieved = per_launch_flops / ex_avg_s / 1e12
+    peak = PEAK_TFLOPS[a.precision]
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "exchange_kernel (fused Omega = Lt Theta, tr Omega, tr Omega^2), one spin per launch",
+                "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt}
+    if a.precision == "bf16x3":
+        roofline["frac_of_bf16x3_effective_peak"] = round(achieved / (peak / 3), 4)
+
+    extra = {}
+    if a.compare_steps > 0:
+        for prec in ("fp64", "cfp32", "bf16x3"):
+            if prec == a.precision:
+                continue
+            print(f"[bench] timing {prec}: {a.compare_steps} steps", file=sys.stderr, flush=True)
+            w2, ph2, _ = timed(prec, a.compare_steps, 1)
+            extra[f"{prec}_walker_steps_per_s"] = round(nw * a.compare_steps / w2, 3)
+            exm, exc = ph2["exchange"]
+            extra[f"{prec}_exchange_tflops"] = round(per_launch_flops / (exm / 1e3 / max(exc, 1)) / 1e12, 3)
+        sysg.set_precision(a.precision)
+        if "fp64_walker_steps_per_s" in extra:
+            extra["speedup_vs_fp64_path"] = round(value / extra["fp64_walker_steps_per_s"], 3)
+
+    # error against the FP64 oracle and the oracle's own rate, on a 4-walker subset
+    err, cpu = None, None
+    if a.check_steps > 0:
+        from oracle import afqmc
+        nsub, ks = 4, a.check_steps
+        fields = synth.make_fields(ks, nsub, X, seed=cfg["field_seed"])
+        W0 = synth.trial_walkers(s, nsub)
+        wk = api.Walkers(sysg, nsub)
+        g = wk.step(ks, dt, fields=fields, qr_every=qr, e_shift=e_var)
+        el, parts, _, _ = wk.energy()
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in g.items()}
+        if not a.no_cpu:
+            try:
+                import threadpoolctl
+                threads = sum(p.get("num_threads", 0) for p in threadpoolctl.threadpool_info()) or os.cpu_count()
+            except Exception:
+                threads = os.cpu_count()
+            print(f"[bench] oracle: {nsub} walkers x {ks} steps on the host", file=sys.stderr, flush=True)
+            pre = afqmc.prepare(s.h1, s.chol, s.phi_t, nu, nd, dt)
+            t = time.perf_counter()
+            o = afqmc.run(s.h1, s.chol, s.phi_t, nu, nd, W0, np.ones(nsub), fields, dt, qr_every=qr,
+                          e_shift=e_var, pre=pre)
+            tc = time.perf_counter() - t
+            oel, oparts, _ = afqmc.energy(s.h1, s.chol, s.phi_t, nu, nd, o["W"], o["w"])
+            cpu = {"value": round(nsub * ks / tc, 4), "unit": "walker-steps/s", "cores": threads,
+                   "kind": "oracle",
+                   "sample": f"{nsub} walkers x {ks} steps of the same workload (numpy FP64, half-rotated "
+                             f"energy), {tc:.1f}s; walkers are independent so the rate scales linearly",
+                   "host_cpus": os.cpu_count()}
+            pg = parts.cpu().numpy()
+            err = {"precision": a.precision, "E_mix": rel_max(g["emix"], o["emix"]),
+                   "E_L": rel_max(g["eloc"], o["eloc"]), "weights": rel_max(g["weights"], o["weights"]),
+                   "ratio": rel_max(g["ratio"], o["ratio"]),
+                   "E1": rel_max(pg[:, 0], oparts[:, 0]), "EJ": rel_max(pg[:, 1], oparts[:, 1]),
+                   "EK": rel_max(pg[:, 2], oparts[:, 2])}
+            err = {k: (v if isinstance(v, str) else float(f"{v:.3e}")) for k, v in err.items()}
+        wk.close()
+
+    line = {
+        "metric": "walker-steps/s + MFMA TFLOP/s at M=400 vs plain FP64 path, err vs FP64 oracle",
+        "value": round(value, 3), "unit": "walker-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(wall / a.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[a.precision], "data": "synthetic",
+        "config": {"workload": f"{a.workload}: M={M}, N_up=N_dn={nu}, Nchol={X}, {nw} walkers, dt={dt}, "
+                               f"QR every {qr}, Taylor order 6, energy every step, Philox fields",
+                   "precision": a.precision, "walkers": nw, "parallelism": "single GPU"},
+        "alg_tflops": round(alg_tflops, 3),
+        "alg_tflops_complex_model": round(flop_model * nw * a.steps / wall / 1e12, 3),
+        "flop_per_walker_step": flop_ws,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "err_vs_fp64_oracle": err,
+        "phase_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in phases.items()},
+        "emix_last": float(emix[-1]),
+    }
+    line.update(extra)
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

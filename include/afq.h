@@ -189,6 +189,31 @@ int afq_batch_step(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_ev
                    const double *e_shift, int taylor_order, double *emix_out);
 int afq_batch_destroy(afq_batch b);
 
+/* ------------------------------------------------------------------------ */
+/* Phase timing (HIP events on the library stream; process-wide, not          */
+/* thread-safe). Phases, in step order:                                       */
+/* ------------------------------------------------------------------------ */
+enum {
+  AFQ_PH_OVERLAP = 0,   /* S = T^H W, Gauss-Jordan S^-1 and log det, Theta   */
+  AFQ_PH_PACK = 1,      /* Theta -> packed exchange operand                   */
+  AFQ_PH_EXCHANGE = 2,  /* fused Omega = Lt Theta, tr Omega, tr Omega^2 (one
+                           event pair per spin launch)                        */
+  AFQ_PH_COULOMB = 3,   /* FP64 force-bias traces (split-BF16x3 mode)         */
+  AFQ_PH_ASSEMBLE = 4,  /* E_L, force bias, propagator coefficients, E_mix    */
+  AFQ_PH_ABUILD = 5,    /* A = sum_n c_n L^n                                  */
+  AFQ_PH_TAYLOR = 6,    /* B1 T_K(A) B1 W                                     */
+  AFQ_PH_WEIGHT = 7,    /* new overlap, phaseless weight, walker commit       */
+  AFQ_PH_QR = 8,        /* CholeskyQR2                                         */
+  AFQ_TRACE_NPHASE = 9
+};
+/* on != 0 starts recording event pairs around every traced phase. */
+int afq_trace_enable(int on);
+/* Drops recorded events and zeroes the totals. */
+int afq_trace_reset(void);
+/* Synchronises on the recorded events and returns the summed milliseconds and
+ * the number of event pairs of a phase since the last reset. */
+int afq_trace_query(int phase, double *ms, int64_t *count);
+
 /* Thread-local message of the last failing call on this thread. */
 const char *afq_last_error(void);
 /* Library version, (major << 16) | minor. */

@@ -51,7 +51,7 @@ def two_body_tensor(chol):
 
 def one_body_corrected(h1, chol):
     """h' = h - 1/2 sum_n L^n L^n (normal-ordering correction of the two-body term)."""
-    return h1 - 0.5 * np.einsum("nij,njk->ik", chol, chol)
+    return h1 - 0.5 * np.tensordot(chol, chol, axes=([0, 2], [0, 1]))
 
 
 def sym_expm(a):
@@ -100,8 +100,8 @@ def greens_function(T, W, n_up, n_dn):
 
 
 def force_bias_plain(chol, G):
-    """vbar_n = sum_s tr(L^n G^s)."""
-    return sum(np.einsum("nik,ki->n", chol, g) for g in G)
+    """vbar_n = sum_s tr(L^n G^s) = sum_s sum_ik L^n_ik G^s_ki."""
+    return sum(np.tensordot(chol, g.T, axes=([1, 2], [0, 1])) for g in G)
 
 
 def local_energy_plain(h1, chol, T, W, n_up, n_dn, e_core=0.0):
@@ -112,8 +112,8 @@ def local_energy_plain(h1, chol, T, W, n_up, n_dn, e_core=0.0):
     ej = 0.5 * np.sum(vbar * vbar)
     ek = 0.0
     for g in G:
-        LG = np.einsum("nik,kj->nij", chol, g)          # L^n G
-        ek = ek - 0.5 * np.einsum("nij,nji->", LG, LG)   # tr(L G L G)
+        LG = np.matmul(chol, g)                          # L^n G
+        ek = ek - 0.5 * np.sum(LG * np.swapaxes(LG, 1, 2))   # tr(L G L G)
     return e_core + e1 + ej + ek, e1, ej, ek
 
 
@@ -126,7 +126,7 @@ def half_rotate(h1, chol, T, n_up, n_dn):
     for b in spin_blocks(n_up, n_dn):
         Th = T[:, b].conj().T
         ht.append(Th @ h1)
-        Lt.append(np.einsum("ai,nik->nak", Th, chol))
+        Lt.append(np.matmul(Th, chol))
     return ht, Lt
 
 
@@ -148,9 +148,9 @@ def local_energy_half(ht, Lt, T, W, n_up, n_dn, e_core=0.0):
     vbar = 0.0
     ek = 0.0
     for s in range(2):
-        Om = np.einsum("nak,kb->nab", Lt[s], th[s])
-        vbar = vbar + np.einsum("naa->n", Om)
-        ek = ek - 0.5 * np.einsum("nab,nba->", Om, Om)
+        Om = np.matmul(Lt[s], th[s])                     # Omega^{ns} = Lt^{ns} Theta^s
+        vbar = vbar + np.trace(Om, axis1=1, axis2=2)
+        ek = ek - 0.5 * np.sum(Om * np.swapaxes(Om, 1, 2))
     ej = 0.5 * np.sum(vbar * vbar)
     return e_core + e1 + ej + ek, (e1, ej, ek), vbar
 
@@ -165,7 +165,7 @@ def force_bias_shift(vbar, dt):
 
 def hs_operator(chol, x, xbar, dt):
     """A = i sqrt(dt) sum_n (x_n - xbar_n) L^n (M x M)."""
-    return np.einsum("n,nij->ij", 1j * np.sqrt(dt) * (x - xbar), chol)
+    return np.tensordot(1j * np.sqrt(dt) * (x - xbar), chol, axes=1)
 
 
 def importance_log_factor(x, xbar):
@@ -184,8 +184,9 @@ def prepare(h1, chol, phi_t, n_up, n_dn, dt):
 
 
 def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
-        e_shift=0.0, order=6, e_core=0.0, energy="half", record_walkers=False):
+        e_shift=0.0, order=6, e_core=0.0, energy="half", record_walkers=False, pre=None):
     """Run len(fields) steps. fields[k, w, n] are the standard-normal HS fields.
+    `pre` may hold prepare(h1, chol, phi_t, n_up, n_dn, dt) computed beforehand.
 
     Per step k (energy and force bias both at the start-of-step walker W_k):
       1. Theta, E_L (E1, EJ, EK) and vbar at W_k;
@@ -196,7 +197,8 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
     """
     M = h1.shape[0]
     nw = W0.shape[0]
-    pre = prepare(h1, chol, phi_t, n_up, n_dn, dt)
+    if pre is None:
+        pre = prepare(h1, chol, phi_t, n_up, n_dn, dt)
     B1, ht, Lt = pre["B1"], pre["ht"], pre["Lt"]
     W = W0.astype(np.complex128).copy()
     w = np.asarray(weights0, dtype=np.float64).copy()
@@ -303,15 +305,15 @@ def energy_grad(h1, chol, phi_t, n_up, n_dn, W, weights):
         d_h1 += wh[i] * Gsum.T.real
         dl = vbar[:, None, None] * Gsum.T[None]
         for g in G:
-            GLG = np.einsum("ik,nkl,lj->nij", g, chol, g)
+            GLG = np.matmul(np.matmul(g, chol), g)          # G L^n G
             dl = dl - np.transpose(GLG, (0, 2, 1))
         d_chol += wh[i] * dl.real
         # dE/dW^s = (I - G^s)^T Gamma^s S^-T, Gamma = dE/dTheta (holomorphic)
         th, _ = theta(phi_t, W[i], n_up, n_dn)
         for s, b in enumerate(spin_blocks(n_up, n_dn)):
-            Om = np.einsum("nak,kb->nab", Lt[s], th[s])
-            gam = ht[s].T + np.einsum("n,nak->ka", vbar, Lt[s]) \
-                - np.einsum("nab,nbk->ka", Om, Lt[s])
+            Om = np.matmul(Lt[s], th[s])
+            gam = ht[s].T + np.tensordot(vbar, Lt[s], axes=1).T \
+                - np.sum(np.matmul(Om, Lt[s]), axis=0).T
             S = phi_t[:, b].conj().T @ W[i][:, b]
             dEdW = (np.eye(M) - G[s]).T @ gam @ np.linalg.inv(S).T
             d_W[i][:, b] = wh[i] * np.conj(dEdW)

@@ -15,6 +15,7 @@ AFQ_OK = 0
 STATUS = {0: "AFQ_OK", -1: "AFQ_E_INVALID", -2: "AFQ_E_NOMEM", -3: "AFQ_E_HIP", -4: "AFQ_E_SINGULAR",
           -5: "AFQ_E_STATE", -6: "AFQ_E_UNSUPPORTED"}
 PRECISION = {"fp64": 0, "cfp32": 1, "bf16x3": 2}
+PHASES = ["overlap", "pack", "exchange", "coulomb", "assemble", "abuild", "taylor", "weight", "qr"]
 
 # every symbol declared in include/afq.h with its ctypes signature
 _vp, _i, _d, _u64, _u32 = C.c_void_p, C.c_int, C.c_double, C.c_uint64, C.c_uint32
@@ -34,6 +35,9 @@ SIGNATURES = {
     "afq_batch_create": (_i, [C.POINTER(_vp), _i, _vp, _vp]),
     "afq_batch_step": (_i, [_vp, _i, _d, _u64, _i, _vp, _i, _vp]),
     "afq_batch_destroy": (_i, [_vp]),
+    "afq_trace_enable": (_i, [_i]),
+    "afq_trace_reset": (_i, []),
+    "afq_trace_query": (_i, [_i, C.POINTER(_d), C.POINTER(C.c_int64)]),
     "afq_last_error": (C.c_char_p, []),
     "afq_version": (_i, []),
 }

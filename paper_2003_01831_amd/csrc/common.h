@@ -90,10 +90,13 @@ struct DevBuf {
 //   (A = [Lt_re | Lt_im], B = [[Th_re, Th_im], [-Th_im, Th_re]])
 // ---------------------------------------------------------------------------
 struct PackShape {
-  int n = 0;    // electrons of this spin
-  int np = 0;   // n rounded up to 16
-  int ke = 0;   // contraction length (M or 2M)
-  int kp = 0;   // ke rounded up to the k-chunk
+  int n = 0;      // electrons of this spin
+  int np = 0;     // rows per block: n rounded up to 16, or n (stacked layout)
+  int ke = 0;     // contraction length (M or 2M)
+  int kp = 0;     // ke rounded up to the k-chunk
+  bool big = false;  // stacked layout of the one-wave-per-SIMD kernel
+  int pad = 0;    // zero rows after the last block (A and B)
+  long rows_b(int nw) const { return (long)nw * 2 * np + pad; }
 };
 
 int exch_kchunk(int prec);

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <type_traits>
 #include "common.h"
+#include "exchange_big.h"
 
 namespace {
 
@@ -301,11 +302,22 @@ int exch_kchunk(int prec) {
 
 int exchange_launch(afq_system s, afq_walkers w, int spin, hipStream_t st) {
   const PackShape& ps = s->ps[spin];
+  const size_t esz = s->prec == AFQ_FP64 ? 8 : s->prec == AFQ_CFP32 ? 4 : 2;
+  const size_t boff = (size_t)spin * s->ps[0].rows_b(w->nw) * s->ps[0].kp * esz;
+  if (ps.big) {
+    ExchBigArgs b{};
+    b.a[0] = s->apack[spin].p;
+    b.a[1] = s->apack_lo[spin].p;
+    b.b[0] = w->bpack.as<char>() + boff;
+    b.b[1] = s->prec == AFQ_BF16X3 ? (const void*)(w->bpack_lo.as<char>() + boff) : nullptr;
+    b.n = ps.n; b.kp = ps.kp; b.X = s->X; b.nw = w->nw; b.spin = spin;
+    b.tro = w->tro.as<double2>();
+    b.troo = w->troo.as<double2>();
+    return exchange_big_launch(b, s->prec, st);
+  }
   ExchArgs g{};
   g.a_hi = s->apack[spin].p;
   g.a_lo = s->apack_lo[spin].p;
-  const size_t esz = s->prec == AFQ_FP64 ? 8 : s->prec == AFQ_CFP32 ? 4 : 2;
-  const size_t boff = (size_t)spin * w->nw * 2 * s->ps[0].np * s->ps[0].kp * esz;
   g.b_hi = w->bpack.as<char>() + boff;
   g.b_lo = s->prec == AFQ_BF16X3 ? (const void*)(w->bpack_lo.as<char>() + boff) : nullptr;
   g.n = ps.n; g.np = ps.np; g.kp = ps.kp; g.X = s->X; g.nw = w->nw; g.spin = spin;

@@ -89,15 +89,15 @@ template <> struct PackOut<AFQ_BF16X3> {
 // A rows (n, a) of one spin from Lt[n][off + a][k] (ntot x M complex per n)
 template <int PREC>
 __global__ void pack_a_kernel(const double2* __restrict__ Lt, int X, int ntot, int M, int off, int n, int np,
-                              int kp, bool real_trial, void* hi, void* lo) {
-  const long total = (long)X * np * kp;
+                              int kp, bool real_trial, void* hi, void* lo, int pad) {
+  const long total = ((long)X * np + pad) * kp;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     const int k = (int)(t % kp);
     const long row = t / kp;
     const int a = (int)(row % np);
     const long nn = row / np;
     double v = 0.0;
-    if (a < n) {
+    if (a < n && nn < X) {
       const double2* src = Lt + (nn * ntot + off + a) * (long)M;
       if (k < M) v = src[k].x;
       else if (!real_trial && k < 2 * M) v = src[k - M].y;
@@ -109,8 +109,8 @@ __global__ void pack_a_kernel(const double2* __restrict__ Lt, int X, int ntot, i
 // B rows (w, part, b) of one spin from thetaT[w][off + b][k]
 template <int PREC>
 __global__ void pack_b_kernel(const double2* __restrict__ thT, int nw, int ntot, int M, int off, int n, int np,
-                              int kp, bool real_trial, void* hi, void* lo) {
-  const long total = (long)nw * 2 * np * kp;
+                              int kp, bool real_trial, void* hi, void* lo, int pad) {
+  const long total = ((long)nw * 2 * np + pad) * kp;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     const int k = (int)(t % kp);
     const long row = t / kp;
@@ -118,7 +118,7 @@ __global__ void pack_b_kernel(const double2* __restrict__ thT, int nw, int ntot,
     const long w = row / (2 * np);
     const int part = c >= np, b = c - part * np;
     double v = 0.0;
-    if (b < n) {
+    if (b < n && w < nw) {
       const double2* src = thT + (w * ntot + off + b) * (long)M;
       if (k < M) {
         const double2 x = src[k];
@@ -136,8 +136,8 @@ static int grid_for(long total) { return (int)std::min<long>(std::max<long>(ceil
 
 int pack_a(int prec, const double2* Lt, int X, int ntot, int M, int off, const PackShape& ps, bool real_trial,
            void* hi, void* lo, hipStream_t st) {
-  const long total = (long)X * ps.np * ps.kp;
-#define AFQ_PACKA(P) hipLaunchKernelGGL(pack_a_kernel<P>, dim3(grid_for(total)), dim3(256), 0, st, Lt, X, ntot, M, off, ps.n, ps.np, ps.kp, real_trial, hi, lo)
+  const long total = ((long)X * ps.np + ps.pad) * ps.kp;
+#define AFQ_PACKA(P) hipLaunchKernelGGL(pack_a_kernel<P>, dim3(grid_for(total)), dim3(256), 0, st, Lt, X, ntot, M, off, ps.n, ps.np, ps.kp, real_trial, hi, lo, ps.pad)
   if (prec == AFQ_FP64) AFQ_PACKA(AFQ_FP64); else if (prec == AFQ_CFP32) AFQ_PACKA(AFQ_CFP32); else AFQ_PACKA(AFQ_BF16X3);
 #undef AFQ_PACKA
   AFQ_TRY_HIP(hipGetLastError());
@@ -146,8 +146,8 @@ int pack_a(int prec, const double2* Lt, int X, int ntot, int M, int off, const P
 
 int pack_b(int prec, const double2* thT, int nw, int ntot, int M, int off, const PackShape& ps, bool real_trial,
            void* hi, void* lo, hipStream_t st) {
-  const long total = (long)nw * 2 * ps.np * ps.kp;
-#define AFQ_PACKB(P) hipLaunchKernelGGL(pack_b_kernel<P>, dim3(grid_for(total)), dim3(256), 0, st, thT, nw, ntot, M, off, ps.n, ps.np, ps.kp, real_trial, hi, lo)
+  const long total = ps.rows_b(nw) * ps.kp;
+#define AFQ_PACKB(P) hipLaunchKernelGGL(pack_b_kernel<P>, dim3(grid_for(total)), dim3(256), 0, st, thT, nw, ntot, M, off, ps.n, ps.np, ps.kp, real_trial, hi, lo, ps.pad)
   if (prec == AFQ_FP64) AFQ_PACKB(AFQ_FP64); else if (prec == AFQ_CFP32) AFQ_PACKB(AFQ_CFP32); else AFQ_PACKB(AFQ_BF16X3);
 #undef AFQ_PACKB
   AFQ_TRY_HIP(hipGetLastError());

@@ -5,6 +5,7 @@
 #include <cmath>
 #include "common.h"
 #include "step_kernels.h"
+#include "exchange_big.h"
 
 int DevBuf::alloc(size_t n) {
   free();
@@ -43,10 +44,12 @@ int system_prepare_pack(afq_system s, int prec) {
   for (int sp = 0; sp < 2; ++sp) {
     PackShape& ps = s->ps[sp];
     ps.n = s->nspin_n(sp);
-    ps.np = round_up(ps.n, 16);
+    ps.big = exch_big_supported(prec, ps.n);
+    ps.np = ps.big ? ps.n : round_up(ps.n, 16);
+    ps.pad = ps.big ? exch_big_pad_rows() : 0;
     ps.ke = s->real_trial ? s->M : 2 * s->M;
-    ps.kp = round_up(ps.ke, kc);
-    const size_t elems = (size_t)s->X * ps.np * ps.kp;
+    ps.kp = round_up(ps.ke, ps.big ? exch_big_kchunk() : kc);
+    const size_t elems = ((size_t)s->X * ps.np + ps.pad) * ps.kp;
     AFQ_RET(s->apack[sp].alloc(elems * esz));
     if (prec == AFQ_BF16X3) AFQ_RET(s->apack_lo[sp].alloc(elems * esz));
     else s->apack_lo[sp].free();

@@ -5,6 +5,7 @@
 //   -> new overlap and phaseless weight -> periodic CholeskyQR2.
 #include "common.h"
 #include "step_kernels.h"
+#include "trace.h"
 
 static size_t esz_of(int prec) { return prec == AFQ_FP64 ? 8 : prec == AFQ_CFP32 ? 4 : 2; }
 
@@ -33,7 +34,7 @@ int walkers_alloc_scratch(afq_walkers w) {
     AFQ_RET(w->emix_tmp.alloc(64));
   }
   size_t bsz = 0;
-  for (int sp = 0; sp < 2; ++sp) bsz += (size_t)nw * 2 * s->ps[sp].np * s->ps[sp].kp;
+  for (int sp = 0; sp < 2; ++sp) bsz += (size_t)s->ps[sp].rows_b(nw) * s->ps[sp].kp;
   AFQ_RET(w->bpack.alloc(bsz * esz_of(s->prec)));
   if (s->prec == AFQ_BF16X3) AFQ_RET(w->bpack_lo.alloc(bsz * esz_of(s->prec)));
   else w->bpack_lo.free();
@@ -85,7 +86,7 @@ int pack_theta(afq_system s, afq_walkers w, hipStream_t st) {
     void* lo = s->prec == AFQ_BF16X3 ? (void*)(w->bpack_lo.as<char>() + off_bytes) : nullptr;
     AFQ_RET(pack_b(s->prec, w->theta.as<double2>(), w->nw, s->ntot, s->M, s->spin_off(sp), ps, s->real_trial, hi,
                    lo, st));
-    off_bytes += (size_t)w->nw * 2 * ps.np * ps.kp * esz;
+    off_bytes += (size_t)ps.rows_b(w->nw) * ps.kp * esz;
   }
   return AFQ_OK;
 }
@@ -112,10 +113,19 @@ static int coulomb_fp64(afq_system s, afq_walkers w, hipStream_t st) {
 // Theta (already computed) -> exchange traces -> assembly (coef optional)
 static int energy_from_theta(afq_system s, afq_walkers w, AssembleArgs& a, bool want_coef) {
   hipStream_t st = s->stream;
-  AFQ_RET(pack_theta(s, w, st));
-  AFQ_RET(exchange_launch(s, w, 0, st));
-  AFQ_RET(exchange_launch(s, w, 1, st));
-  if (s->prec == AFQ_BF16X3) AFQ_RET(coulomb_fp64(s, w, st));
+  {
+    TraceScope t(AFQ_PH_PACK, st);
+    AFQ_RET(pack_theta(s, w, st));
+  }
+  for (int sp = 0; sp < 2; ++sp) {
+    TraceScope t(AFQ_PH_EXCHANGE, st);
+    AFQ_RET(exchange_launch(s, w, sp, st));
+  }
+  if (s->prec == AFQ_BF16X3) {
+    TraceScope t(AFQ_PH_COULOMB, st);
+    AFQ_RET(coulomb_fp64(s, w, st));
+  }
+  TraceScope t(AFQ_PH_ASSEMBLE, st);
   a.nw = w->nw; a.ntot = s->ntot; a.M = s->M; a.X = s->X;
   a.thetaT = w->theta.as<double2>();
   a.ht = s->ht.as<double2>();
@@ -149,6 +159,7 @@ static int propagate(afq_system s, afq_walkers w, int order) {
   const long per = (long)M * ntot;
   // A_w = sum_n c_wn L^n : [nw x X] (complex) x [X x M^2] (real)
   {
+    TraceScope tr(AFQ_PH_ABUILD, st);
     GemmArgs<T> g = gemm_args<T>();
     g.m = nw; g.n = M * M; g.k = X;
     g.A = w->coef.as<T>(); g.lda = X; g.cA = true;
@@ -157,6 +168,7 @@ static int propagate(afq_system s, afq_walkers w, int order) {
     g.C = w->amat.as<T>(); g.ldc = (long)M * M; g.cC = true;
     AFQ_RET(gemm<T>(g, st));
   }
+  TraceScope tr(AFQ_PH_TAYLOR, st);
   // U = B1 W  (FP64)
   {
     GemmArgs<double> g = gemm_args<double>();
@@ -197,6 +209,7 @@ static int propagate(afq_system s, afq_walkers w, int order) {
 // CholeskyQR2 of every spin block: W^s <- W^s R^-1 twice, live walkers only.
 static int qr_walkers(afq_system s, afq_walkers w) {
   hipStream_t st = s->stream;
+  TraceScope tr(AFQ_PH_QR, st);
   const int M = s->M, ntot = s->ntot, nw = w->nw;
   const long per = (long)M * ntot;
   const int nmax = std::max(s->n_up, s->n_dn);
@@ -232,7 +245,10 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
   hipStream_t st = s->stream;
   const int nw = w->nw;
   // overlap, Theta and the energy at the start-of-step walkers
-  AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), true, w->logdet.as<double2>()));
+  {
+    TraceScope t(AFQ_PH_OVERLAP, st);
+    AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), true, w->logdet.as<double2>()));
+  }
   AssembleArgs a{};
   a.dt = dt;
   a.fields = fields;
@@ -241,28 +257,34 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
   a.sys_id = sys_id;
   a.eloc_out = reinterpret_cast<double2*>(eloc_out);
   AFQ_RET(energy_from_theta(s, w, a, true));
-  if (emix_out) AFQ_RET(launch_emix(w->eloc.as<double2>(), w->weights.as<double>(), nw, emix_out, st));
+  if (emix_out) {
+    TraceScope t(AFQ_PH_ASSEMBLE, st);
+    AFQ_RET(launch_emix(w->eloc.as<double2>(), w->weights.as<double>(), nw, emix_out, st));
+  }
   // propagate
   if (s->prec == AFQ_FP64) AFQ_RET(propagate<double>(s, w, order));
   else AFQ_RET(propagate<float>(s, w, order));
   // new overlap (log det only) and the phaseless weight
-  AFQ_RET(compute_overlap_theta(s, w, w->Wn.as<double2>(), false, w->logdet_new.as<double2>()));
-  WeightArgs wa{};
-  wa.logdet_new = w->logdet_new.as<double2>();
-  wa.logdet_cur = w->logdet.as<double2>();
-  wa.sing_new = w->sing.as<int>();
-  wa.lfac = w->lfac.as<double2>();
-  wa.weights = w->weights.as<double>();
-  wa.alive = w->alive.as<int>();
-  wa.killed = w->killed.as<int64_t>();
-  wa.dt = dt;
-  wa.e_shift = e_shift;
-  wa.ratio_out = reinterpret_cast<double2*>(ratio_out);
-  wa.weights_out = weights_out;
-  wa.W = w->W.as<double2>();
-  wa.Wn = w->Wn.as<double2>();
-  wa.per = (long)s->M * s->ntot;
-  AFQ_RET(launch_weights(wa, nw, st));
+  {
+    TraceScope tw(AFQ_PH_WEIGHT, st);
+    AFQ_RET(compute_overlap_theta(s, w, w->Wn.as<double2>(), false, w->logdet_new.as<double2>()));
+    WeightArgs wa{};
+    wa.logdet_new = w->logdet_new.as<double2>();
+    wa.logdet_cur = w->logdet.as<double2>();
+    wa.sing_new = w->sing.as<int>();
+    wa.lfac = w->lfac.as<double2>();
+    wa.weights = w->weights.as<double>();
+    wa.alive = w->alive.as<int>();
+    wa.killed = w->killed.as<int64_t>();
+    wa.dt = dt;
+    wa.e_shift = e_shift;
+    wa.ratio_out = reinterpret_cast<double2*>(ratio_out);
+    wa.weights_out = weights_out;
+    wa.W = w->W.as<double2>();
+    wa.Wn = w->Wn.as<double2>();
+    wa.per = (long)s->M * s->ntot;
+    AFQ_RET(launch_weights(wa, nw, st));
+  }
   if (do_qr) AFQ_RET(qr_walkers(s, w));
   return AFQ_OK;
 }

@@ -1,0 +1,49 @@
+"""Parity at the full benchmark size (M=400, 100+100 electrons, 1600 Cholesky
+vectors, 512 walkers, dt 0.005) in the launch configuration the benchmark
+times. The oracle cannot afford 512 walkers, so 4 sampled walkers are checked
+one by one (walkers are independent given their fields) and the mixed energy
+is checked as the weighted mean of the GPU's own per-walker outputs."""
+import numpy as np
+import pytest
+
+from oracle import afqmc
+from paper_2003_01831_amd import synth
+from gpu_util import rel_vec, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def full():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cfg = synth.WORKLOADS["m400"]
+    s = synth.make_system(cfg["M"], cfg["n_up"], cfg["n_dn"], cfg["n_chol"], seed=cfg["seed"])
+    pre = afqmc.prepare(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, cfg["dt"])
+    return cfg, s, pre
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-5), ("fp64", 1e-10)])
+def test_full_size_sampled_walkers(full, prec, tol):
+    from paper_2003_01831_amd import api
+    cfg, s, pre = full
+    nw, steps, dt = cfg["n_walkers"], 2, cfg["dt"]
+    fields = synth.make_fields(steps, nw, cfg["n_chol"], seed=cfg["field_seed"])
+    sysg = api.System.from_synth(s, precision=prec)
+    wk = api.Walkers(sysg, nw)
+    e_var = float(wk.energy()[3][0])
+    out = wk.step(steps, dt, fields=fields, qr_every=cfg["qr_every"], e_shift=e_var)
+    torch.cuda.synchronize()
+    g = {k: to_np(v) for k, v in out.items()}
+    sample = np.array([0, 137, 300, 511])
+    o = afqmc.run(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, synth.trial_walkers(s, 4), np.ones(4),
+                  fields[:, sample], dt, qr_every=cfg["qr_every"], e_shift=e_var, pre=pre)
+    for k in ("eloc", "weights", "ratio"):
+        err = rel_vec(g[k][:, sample], o[k])
+        print(prec, k, f"{err:.2e}")
+        assert err < tol, k
+    # E_mix is the weighted mean of the per-walker energies with the pre-step weights
+    wprev = np.vstack([np.ones(nw), g["weights"][:-1]])
+    ref = np.sum(wprev * g["eloc"].real, axis=1) / np.sum(wprev, axis=1)
+    assert rel_vec(g["emix"], ref) < 1e-12

@@ -74,7 +74,8 @@ def test_energy_complex_trial(api):
 
 
 @pytest.mark.parametrize("prec", ["cfp32", "bf16x3"])
-@pytest.mark.parametrize("shape", [(64, 16, 16, 256), (128, 32, 32, 512)])
+@pytest.mark.parametrize("shape", [(64, 16, 16, 256), (128, 32, 32, 512), (160, 80, 70, 96), (224, 100, 100, 128),
+                                   (240, 100, 97, 40)])
 def test_energy_reduced_precision(api, prec, shape):
     M, nu, nd, X = shape
     s = synth.make_system(M, nu, nd, X, seed=M + X)
