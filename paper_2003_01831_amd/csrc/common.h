@@ -115,6 +115,7 @@ struct afq_system_s {
   double B1_dt = -1.0;
   DevBuf ht;                   // (T^H h)  ntot x M complex
   DevBuf Lt;                   // (T^H L^n) X x ntot x M complex
+  DevBuf LtRe;                 // real part of Lt (real trial, split-BF16x3 force bias)
   DevBuf apack[2];             // packed A operand per spin (precision of prec)
   DevBuf apack_lo[2];          // BF16x3 low parts
   int apack_prec = -1;

@@ -1,13 +1,38 @@
-// Generic batched complex GEMM for the small and medium contractions of the
-// walker step (overlaps T^H W, Theta = W S^-1, B1 W, the Taylor products A V,
-// the Gram matrices of QR, the A = sum_n c_n L^n build and the system set-up).
-// 64 x 64 output tile per 256-thread workgroup, 4 x 4 complex outputs per
-// thread, k staged through LDS in chunks of 16 as separate Re/Im planes.
+// Batched complex/real GEMM on MFMA for the medium contractions of the walker
+// step (overlaps T^H W, Theta = W S^-1, B1 W, the Taylor products A V, the Gram
+// matrices of QR, the A = sum_n c_n L^n build, the FP64 force-bias traces and
+// the system set-up):
+//
+//   C = alpha op(A) op(B) + beta C,   optionally D += alpha op(A) op(B)
+//
+// 64 x 64 output tile per 256-thread workgroup; each wave owns a 32 x 32
+// quarter as 2 x 2 MFMA tiles (v_mfma_f64_16x16x4f64 or
+// v_mfma_f32_16x16x4f32). A complex product is four real MFMAs
+// (Re += ar br - ai bi, Im += ar bi + ai br); a real operand drops the terms
+// of its imaginary part at compile time. k is staged through LDS in chunks of
+// 16 as separate Re/Im planes, k-major so that fragment reads are contiguous.
+// Long contractions with few output tiles are split over k into a workspace
+// and reduced in a fixed order (deterministic).
 #include "common.h"
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 1;
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 4;
+
+typedef __attribute__((ext_vector_type(4))) float f4;
+typedef __attribute__((ext_vector_type(4))) double d4;
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using Acc = d4;
+  __device__ static void mma(Acc& c, double a, double b) { c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <> struct Mfma<float> {
+  using Acc = f4;
+  __device__ static void mma(Acc& c, float a, float b) { c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 template <typename T>
 __device__ inline void load_elem(const T* p, long idx, bool cplx, bool conj, T& re, T& im) {
@@ -20,103 +45,179 @@ __device__ inline void load_elem(const T* p, long idx, bool cplx, bool conj, T& 
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<T> g) {
-  __shared__ T As_r[BK][BM + PAD], As_i[BK][BM + PAD];
-  __shared__ T Bs_r[BK][BN + PAD], Bs_i[BK][BN + PAD];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const long b = blockIdx.z;
+// ksplit > 1: blockIdx.z = batch * ksplit + split; the partial products of a
+// split go to ws[(batch * ksplit + split)][m][n] (complex T) instead of C/D.
+template <typename T, bool CA, bool CB>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs<T> g, int ksplit, int kchunk, T* ws) {
+  using M = Mfma<T>;
+  using Acc = typename M::Acc;
+  constexpr bool CPLX = CA || CB;
+  __shared__ T As_r[BK][BM + PAD], Bs_r[BK][BN + PAD];
+  __shared__ T As_i[CA ? BK : 1][BM + PAD], Bs_i[CB ? BK : 1][BN + PAD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long b = blockIdx.z / ksplit;
+  const int split = blockIdx.z - (int)b * ksplit;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int es_a = g.cA ? 2 : 1, es_b = g.cB ? 2 : 1;
-  const T* A = g.A + b * g.sA * es_a;
-  const T* B = g.B + b * g.sB * es_b;
+  const T* A = g.A + b * g.sA * (CA ? 2 : 1);
+  const T* B = g.B + b * g.sB * (CB ? 2 : 1);
   const bool ca = g.opA == OP_C, cb = g.opB == OP_C;
+  const int kbeg = split * kchunk, kend = min(g.k, kbeg + kchunk);
 
-  T acc_r[4][4], acc_i[4][4];
+  Acc acc_r[2][2], acc_i[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc_r[i][j] = acc_i[i][j] = T(0);
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { acc_r[i][j][r] = 0; acc_i[i][j][r] = 0; }
 
-  for (int k0 = 0; k0 < g.k; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = tid + 256 * r;
+    for (int rr = 0; rr < 4; ++rr) {
+      const int e = tid + 256 * rr;
       int kk, mm;
       if (g.opA == OP_N) { kk = e & 15; mm = e >> 4; } else { kk = e >> 6; mm = e & 63; }
       const int gi = m0 + mm, gk = k0 + kk;
       T re = T(0), im = T(0);
-      if (gi < g.m && gk < g.k) {
+      if (gi < g.m && gk < kend) {
         const long idx = g.opA == OP_N ? (long)gi * g.lda + gk : (long)gk * g.lda + gi;
-        load_elem(A, idx, g.cA, ca, re, im);
+        load_elem(A, idx, CA, ca, re, im);
       }
       As_r[kk][mm] = re;
-      As_i[kk][mm] = im;
+      if constexpr (CA) As_i[kk][mm] = im;
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int e = tid + 256 * r;
+    for (int rr = 0; rr < 4; ++rr) {
+      const int e = tid + 256 * rr;
       int kk, nn;
       if (g.opB == OP_N) { kk = e >> 6; nn = e & 63; } else { kk = e & 15; nn = e >> 4; }
       const int gj = n0 + nn, gk = k0 + kk;
       T re = T(0), im = T(0);
-      if (gj < g.n && gk < g.k) {
+      if (gj < g.n && gk < kend) {
         const long idx = g.opB == OP_N ? (long)gk * g.ldb + gj : (long)gj * g.ldb + gk;
-        load_elem(B, idx, g.cB, cb, re, im);
+        load_elem(B, idx, CB, cb, re, im);
       }
       Bs_r[kk][nn] = re;
-      Bs_i[kk][nn] = im;
+      if constexpr (CB) Bs_i[kk][nn] = im;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < BK; ++kk) {
-      T ar[4], ai[4], br[4], bi[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) { ar[i] = As_r[kk][ty + 16 * i]; ai[i] = As_i[kk][ty + 16 * i]; }
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kr = ks + (lane >> 4), c16 = lane & 15;
+      T ar[2], ai[2], br[2], bi[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) { br[j] = Bs_r[kk][tx + 16 * j]; bi[j] = Bs_i[kk][tx + 16 * j]; }
+      for (int t = 0; t < 2; ++t) {
+        ar[t] = As_r[kr][wm * 32 + t * 16 + c16];
+        br[t] = Bs_r[kr][wn * 32 + t * 16 + c16];
+        if constexpr (CA) ai[t] = As_i[kr][wm * 32 + t * 16 + c16];
+        if constexpr (CB) bi[t] = Bs_i[kr][wn * 32 + t * 16 + c16];
+      }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc_r[i][j] += ar[i] * br[j] - ai[i] * bi[j];
-          acc_i[i][j] += ar[i] * bi[j] + ai[i] * br[j];
+        for (int j = 0; j < 2; ++j) {
+          M::mma(acc_r[i][j], ar[i], br[j]);
+          if constexpr (CA && CB) M::mma(acc_r[i][j], -ai[i], bi[j]);
+          if constexpr (CB) M::mma(acc_i[i][j], ar[i], bi[j]);
+          if constexpr (CA) M::mma(acc_i[i][j], ai[i], br[j]);
         }
     }
     __syncthreads();
   }
 
+  if (ksplit > 1) {
+    T* w = ws + ((long)blockIdx.z * g.m * g.n) * 2;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = m0 + wm * 32 + i * 16 + M::row(lane, r);
+          const int gj = n0 + wn * 32 + j * 16 + (lane & 15);
+          if (gi < g.m && gj < g.n) {
+            w[2 * ((long)gi * g.n + gj)] = acc_r[i][j][r];
+            w[2 * ((long)gi * g.n + gj) + 1] = CPLX ? acc_i[i][j][r] : T(0);
+          }
+        }
+    return;
+  }
   T* C = g.C ? g.C + b * g.sC * (g.cC ? 2 : 1) : nullptr;
   double2* D = g.D ? g.D + b * g.sD : nullptr;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gi = m0 + ty + 16 * i;
-    if (gi >= g.m) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gj = n0 + tx + 16 * j;
-      if (gj >= g.n) continue;
-      double vr = g.ar * (double)acc_r[i][j] - g.ai * (double)acc_i[i][j];
-      double vi = g.ar * (double)acc_i[i][j] + g.ai * (double)acc_r[i][j];
-      if (C) {
-        const long ci = (long)gi * g.ldc + gj;
-        if (g.br != 0.0 || g.bi != 0.0) {
-          double cr, cim;
-          if (g.cC) { cr = C[2 * ci]; cim = C[2 * ci + 1]; } else { cr = C[ci]; cim = 0.0; }
-          vr += g.br * cr - g.bi * cim;
-          vi += g.br * cim + g.bi * cr;
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = m0 + wm * 32 + i * 16 + M::row(lane, r);
+        const int gj = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (gi >= g.m || gj >= g.n) continue;
+        const double xr = (double)acc_r[i][j][r], xi = CPLX ? (double)acc_i[i][j][r] : 0.0;
+        double vr = g.ar * xr - g.ai * xi;
+        double vi = g.ar * xi + g.ai * xr;
+        if (C) {
+          const long ci = (long)gi * g.ldc + gj;
+          if (g.br != 0.0 || g.bi != 0.0) {
+            double cr, cim;
+            if (g.cC) { cr = C[2 * ci]; cim = C[2 * ci + 1]; } else { cr = C[ci]; cim = 0.0; }
+            vr += g.br * cr - g.bi * cim;
+            vi += g.br * cim + g.bi * cr;
+          }
+          if (g.cC) { C[2 * ci] = (T)vr; C[2 * ci + 1] = (T)vi; } else { C[ci] = (T)vr; }
         }
-        if (g.cC) { C[2 * ci] = (T)vr; C[2 * ci + 1] = (T)vi; } else { C[ci] = (T)vr; }
+        if (D) {
+          double2* d = D + (long)gi * g.ldd + gj;
+          d->x += vr;
+          d->y += vi;
+        }
       }
-      if (D) {
-        double2* d = D + (long)gi * g.ldd + gj;
-        d->x += vr;
-        d->y += vi;
+}
+
+// fixed-order sum of the k splits, then the same epilogue as the kernel above
+template <typename T>
+__global__ void gemm_splitk_reduce(GemmArgs<T> g, int ksplit, const T* ws) {
+  const long mn = (long)g.m * g.n;
+  const long total = mn * g.batch;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const long b = t / mn, e = t - b * mn;
+    const int gi = (int)(e / g.n), gj = (int)(e - (long)gi * g.n);
+    double xr = 0.0, xi = 0.0;
+    for (int s = 0; s < ksplit; ++s) {
+      const T* w = ws + ((b * ksplit + s) * mn + e) * 2;
+      xr += (double)w[0];
+      xi += (double)w[1];
+    }
+    double vr = g.ar * xr - g.ai * xi;
+    double vi = g.ar * xi + g.ai * xr;
+    if (g.C) {
+      T* C = g.C + b * g.sC * (g.cC ? 2 : 1);
+      const long ci = (long)gi * g.ldc + gj;
+      if (g.br != 0.0 || g.bi != 0.0) {
+        double cr, cim;
+        if (g.cC) { cr = C[2 * ci]; cim = C[2 * ci + 1]; } else { cr = C[ci]; cim = 0.0; }
+        vr += g.br * cr - g.bi * cim;
+        vi += g.br * cim + g.bi * cr;
       }
+      if (g.cC) { C[2 * ci] = (T)vr; C[2 * ci + 1] = (T)vi; } else { C[ci] = (T)vr; }
+    }
+    if (g.D) {
+      double2* d = g.D + b * g.sD + (long)gi * g.ldd + gj;
+      d->x += vr;
+      d->y += vi;
     }
   }
 }
+
+// split-k workspace, grown on demand and kept until the process ends (per
+// element type; never freed, so no device call runs during static destruction)
+template <typename T> struct Workspace {
+  static DevBuf& buf() {
+    static DevBuf* b = new DevBuf();
+    return *b;
+  }
+};
 
 }  // namespace
 
@@ -132,11 +233,36 @@ template <typename T> int gemm(const GemmArgs<T>& g, hipStream_t st) {
   AFQ_CHECK(g.m >= 0 && g.n >= 0 && g.k >= 0 && g.batch >= 0, AFQ_E_INVALID, "gemm: negative size");
   if (g.m == 0 || g.n == 0 || g.batch == 0) return AFQ_OK;
   AFQ_CHECK(g.A && g.B && (g.C || g.D), AFQ_E_INVALID, "gemm: null operand");
-  AFQ_CHECK(g.batch <= 65535, AFQ_E_INVALID, "gemm: batch too large");
-  dim3 grid(ceil_div(g.n, BN), ceil_div(g.m, BM), g.batch);
-  AFQ_CHECK(grid.y <= 65535, AFQ_E_INVALID, "gemm: m too large");
-  hipLaunchKernelGGL(gemm_kernel<T>, grid, dim3(256), 0, st, g);
+  const int tiles_m = ceil_div(g.m, BM), tiles_n = ceil_div(g.n, BN);
+  AFQ_CHECK(tiles_m <= 65535, AFQ_E_INVALID, "gemm: m too large");
+  // split k when few output tiles share a long contraction
+  int ksplit = 1;
+  const long tiles = (long)tiles_m * tiles_n * g.batch;
+  while (tiles * ksplit < 512 && g.k / (ksplit * 2) >= 1024 && ksplit < 64) ksplit *= 2;
+  const int kchunk = round_up(ceil_div(g.k, ksplit), BK);
+  AFQ_CHECK((long)g.batch * ksplit <= 65535, AFQ_E_INVALID, "gemm: batch too large");
+  T* ws = nullptr;
+  if (ksplit > 1) {
+    const size_t need = (size_t)g.batch * ksplit * g.m * g.n * 2 * sizeof(T);
+    DevBuf& w = Workspace<T>::buf();
+    if (w.bytes < need) {
+      AFQ_TRY_HIP(hipStreamSynchronize(st));   // the old workspace may still be in use
+      AFQ_RET(w.alloc(need));
+    }
+    ws = w.as<T>();
+  }
+  dim3 grid(tiles_n, tiles_m, g.batch * ksplit);
+  if (g.cA && g.cB) hipLaunchKernelGGL((gemm_mfma_kernel<T, true, true>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
+  else if (g.cA) hipLaunchKernelGGL((gemm_mfma_kernel<T, true, false>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
+  else if (g.cB) hipLaunchKernelGGL((gemm_mfma_kernel<T, false, true>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
+  else hipLaunchKernelGGL((gemm_mfma_kernel<T, false, false>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
   AFQ_TRY_HIP(hipGetLastError());
+  if (ksplit > 1) {
+    const long total = (long)g.m * g.n * g.batch;
+    const int blocks = (int)std::min<long>(ceil_div(total, 256), 65536);
+    hipLaunchKernelGGL(gemm_splitk_reduce<T>, dim3(blocks), dim3(256), 0, st, g, ksplit, ws);
+    AFQ_TRY_HIP(hipGetLastError());
+  }
   return AFQ_OK;
 }
 

@@ -41,6 +41,7 @@ int pack_b(int prec, const double2* thT, int nw, int ntot, int M, int off, const
            void* hi, void* lo, hipStream_t st);
 int convert_d2f(const double* x, float* y, long n, hipStream_t st);
 int copy_d(const double* x, double* y, long n, hipStream_t st);
+int real_part(const double2* z, double* y, long n, hipStream_t st);
 int fill_d(double* y, double v, long n, hipStream_t st);
 int fill_i(int* y, int v, long n, hipStream_t st);
 int fill_eye(double* y, int M, hipStream_t st);

@@ -166,6 +166,15 @@ int convert_d2f(const double* x, float* y, long n, hipStream_t st) {
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }
+__global__ void real_part_kernel(const double2* __restrict__ z, double* __restrict__ y, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = z[i].x;
+}
+int real_part(const double2* z, double* y, long n, hipStream_t st) {
+  if (n <= 0) return AFQ_OK;
+  hipLaunchKernelGGL(real_part_kernel, dim3(grid_for(n)), dim3(256), 0, st, z, y, n);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
 __global__ void copy_kernel(const double* __restrict__ x, double* __restrict__ y, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = x[i];
 }

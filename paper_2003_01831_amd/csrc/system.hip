@@ -56,6 +56,11 @@ int system_prepare_pack(afq_system s, int prec) {
     AFQ_RET(pack_a(prec, s->Lt.as<double2>(), s->X, s->ntot, s->M, s->spin_off(sp), ps, s->real_trial,
                    s->apack[sp].p, s->apack_lo[sp].p, s->stream));
   }
+  if (prec == AFQ_BF16X3 && s->real_trial && !s->LtRe.p) {
+    const long n = (long)s->X * s->ntot * s->M;
+    AFQ_RET(s->LtRe.alloc(n * sizeof(double)));
+    AFQ_RET(real_part(s->Lt.as<double2>(), s->LtRe.as<double>(), n, s->stream));
+  }
   if (prec != AFQ_FP64 && !s->chol32.p) {
     const long n = (long)s->X * s->M * s->M;
     AFQ_RET(s->chol32.alloc(n * sizeof(float)));

@@ -103,7 +103,11 @@ static int coulomb_fp64(afq_system s, afq_walkers w, hipStream_t st) {
     GemmArgs<double> g = gemm_args<double>();
     g.m = w->nw; g.n = X; g.k = n * M;
     g.A = w->theta.as<double>() + 2 * (long)off * M; g.lda = (long)ntot * M; g.cA = true;
-    g.B = s->Lt.as<double>() + 2 * (long)off * M; g.ldb = (long)ntot * M; g.opB = OP_T; g.cB = true;
+    if (s->real_trial) {   // real half-rotated Cholesky rows: two real MFMAs per element
+      g.B = s->LtRe.as<double>() + (long)off * M; g.ldb = (long)ntot * M; g.opB = OP_T; g.cB = false;
+    } else {
+      g.B = s->Lt.as<double>() + 2 * (long)off * M; g.ldb = (long)ntot * M; g.opB = OP_T; g.cB = true;
+    }
     g.C = w->tro.as<double>() + 2 * (long)sp * X; g.ldc = 2L * X; g.cC = true;
     AFQ_RET(gemm<double>(g, st));
   }
