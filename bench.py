@@ -52,6 +52,23 @@ def flops_per_walker_step(M, N, X, K=6, qr_every=5, real_trial=True):
     return sum(parts.values()), parts, sum(model.values())
 
 
+def profiled_traffic(kernel_src, profile_md):
+    """HBM bytes per launch of the exchange kernel measured with rocprofv3 PMC
+    counters (FETCH_SIZE/WRITE_SIZE, calibrated on a device copy) and recorded
+    in the profile summary, or None once the kernel source has changed since."""
+    import hashlib
+    import re
+    try:
+        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+        text = open(profile_md).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch=(\d+) exchange_big_sha256_16=([0-9a-f]+)", text)
+    if not m or m.group(2) != sha:
+        return None
+    return int(m.group(1))
+
+
 def rel_max(a, b):
     a, b = np.asarray(a), np.asarray(b)
     return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
@@ -68,6 +85,8 @@ def main(argv=None):
     ap.add_argument("--compare-steps", type=int, default=3, help="timed steps of the other precisions (0: skip)")
     ap.add_argument("--check-steps", type=int, default=2, help="steps of the 4-walker oracle check (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device copy of this many MiB (calibrates HBM byte counters) and exit")
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -77,6 +96,16 @@ def main(argv=None):
 
     import torch
     from paper_2003_01831_amd import synth, api, _lib
+
+    if a.copy_probe_mib:
+        n = a.copy_probe_mib * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}))
+        return 0
 
     cfg = dict(synth.WORKLOADS[a.workload])
     M, nu, nd, X = cfg["M"], cfg["n_up"], cfg["n_dn"], cfg["n_chol"]
@@ -130,8 +159,12 @@ def main(argv=None):
     ex_avg_s = ex_ms / 1e3 / max(ex_cnt, 1)
     achieved = per_launch_flops / ex_avg_s / 1e12
     peak = PEAK_TFLOPS[a.precision]
+    traffic = None
+    if a.precision == "bf16x3" and a.workload == "m400" and nw == 512:
+        traffic = profiled_traffic(os.path.join(ROOT, "paper_2003_01831_amd", "csrc", "exchange_big.hip"),
+                                   os.path.join(ROOT, "profiles", "exchange_bf16x3_m400.md"))
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "exchange_kernel (fused Omega = Lt Theta, tr Omega, tr Omega^2), one spin per launch",
                 "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt}
     if a.precision == "bf16x3":

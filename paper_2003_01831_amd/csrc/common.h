@@ -155,7 +155,7 @@ struct afq_walkers_s {
 // ---------------------------------------------------------------------------
 // kernel launchers (all on the given stream)
 // ---------------------------------------------------------------------------
-enum GemmOp { OP_N = 0, OP_T = 1, OP_C = 2 };
+enum GemmOp { OP_N = 0, OP_T = 1, OP_C = 2, OP_R = 3 };   // N, transpose, conj-transpose, conj
 
 template <typename T> struct GemmArgs {
   int m, n, k, batch;

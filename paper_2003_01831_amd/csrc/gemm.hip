@@ -61,7 +61,8 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs<T> g, int kspli
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const T* A = g.A + b * g.sA * (CA ? 2 : 1);
   const T* B = g.B + b * g.sB * (CB ? 2 : 1);
-  const bool ca = g.opA == OP_C, cb = g.opB == OP_C;
+  const bool ca = g.opA == OP_C || g.opA == OP_R, cb = g.opB == OP_C || g.opB == OP_R;
+  const bool na = g.opA == OP_N || g.opA == OP_R, nb = g.opB == OP_N || g.opB == OP_R;   // untransposed
   const int kbeg = split * kchunk, kend = min(g.k, kbeg + kchunk);
 
   Acc acc_r[2][2], acc_i[2][2];
@@ -77,11 +78,11 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs<T> g, int kspli
     for (int rr = 0; rr < 4; ++rr) {
       const int e = tid + 256 * rr;
       int kk, mm;
-      if (g.opA == OP_N) { kk = e & 15; mm = e >> 4; } else { kk = e >> 6; mm = e & 63; }
+      if (na) { kk = e & 15; mm = e >> 4; } else { kk = e >> 6; mm = e & 63; }
       const int gi = m0 + mm, gk = k0 + kk;
       T re = T(0), im = T(0);
       if (gi < g.m && gk < kend) {
-        const long idx = g.opA == OP_N ? (long)gi * g.lda + gk : (long)gk * g.lda + gi;
+        const long idx = na ? (long)gi * g.lda + gk : (long)gk * g.lda + gi;
         load_elem(A, idx, CA, ca, re, im);
       }
       As_r[kk][mm] = re;
@@ -91,11 +92,11 @@ __global__ __launch_bounds__(256) void gemm_mfma_kernel(GemmArgs<T> g, int kspli
     for (int rr = 0; rr < 4; ++rr) {
       const int e = tid + 256 * rr;
       int kk, nn;
-      if (g.opB == OP_N) { kk = e >> 6; nn = e & 63; } else { kk = e & 15; nn = e >> 4; }
+      if (nb) { kk = e >> 6; nn = e & 63; } else { kk = e & 15; nn = e >> 4; }
       const int gj = n0 + nn, gk = k0 + kk;
       T re = T(0), im = T(0);
       if (gj < g.n && gk < kend) {
-        const long idx = g.opB == OP_N ? (long)gk * g.ldb + gj : (long)gj * g.ldb + gk;
+        const long idx = nb ? (long)gk * g.ldb + gj : (long)gj * g.ldb + gk;
         load_elem(B, idx, CB, cb, re, im);
       }
       Bs_r[kk][nn] = re;
