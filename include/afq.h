@@ -141,7 +141,7 @@ int afq_walkers_stats(afq_walkers w, int *n_alive, int64_t *n_killed);
  *   emix_out    n_steps float64: sum_w w Re E_L / sum_w w (0 if all dead)
  *   eloc_out    n_steps*n_walkers complex128 local energies
  *   weights_out n_steps*n_walkers float64 weights after step k
- *   ratio_out   n_steps*n_walkers complex128 overlap ratios O'/O (1 for dead)
+ *   ratio_out   n_steps*n_walkers complex128 overlap ratios O'/O (0 for walkers already dead)
  * Dead walkers are not errors; they are counted by afq_walkers_stats. */
 int afq_step(afq_system s, afq_walkers w, int n_steps, double dt,
              const double *fields, uint64_t seed, int qr_every, double e_shift,

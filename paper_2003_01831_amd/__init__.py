@@ -15,7 +15,7 @@ __all__ = ["System", "Walkers", "Batch", "energy_backward", "fields_generate", "
 
 
 def __getattr__(name):
-    if name in ("System", "Walkers", "energy_backward", "fields_generate"):
+    if name in ("System", "Walkers", "Batch", "energy_backward", "fields_generate"):
         from . import api
         return getattr(api, name)
     if name == "LocalEnergy":

@@ -165,3 +165,39 @@ def fields_generate(seed, n_steps, n_walkers, n_chol, step0=0, sys_id=0):
     check(lib.afq_fields_generate(int(seed), int(sys_id), int(step0), int(n_steps), int(n_walkers), int(n_chol),
                                   _ptr(out), _stream_handle(None)))
     return out
+
+
+class Batch:
+    """Several (System, Walkers) pairs stepped together as branches of one
+    captured HIP graph (system i draws Philox fields with sys_id = i)."""
+
+    def __init__(self, pairs):
+        self.pairs = list(pairs)
+        if not self.pairs:
+            raise ValueError("Batch needs at least one (system, walkers) pair")
+        self.lib = self.pairs[0][0].lib
+        n = len(self.pairs)
+        self._sys = (C.c_void_p * n)(*[p[0].handle.value for p in self.pairs])
+        self._wk = (C.c_void_p * n)(*[p[1].handle.value for p in self.pairs])
+        h = C.c_void_p()
+        check(self.lib.afq_batch_create(C.byref(h), n, C.cast(self._sys, C.c_void_p), C.cast(self._wk, C.c_void_p)))
+        self.handle = h
+
+    def step(self, n_steps, dt, seed=0, qr_every=5, e_shift=0.0, taylor_order=6, emix=True):
+        n = len(self.pairs)
+        es = np.broadcast_to(np.asarray(e_shift, dtype=np.float64), (n,)).copy()
+        out = torch.zeros(n, n_steps, dtype=torch.float64, device=_dev()) if emix else None
+        check(self.lib.afq_batch_step(self.handle, int(n_steps), float(dt), int(seed), int(qr_every),
+                                      es.ctypes.data_as(C.c_void_p), int(taylor_order), _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.afq_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

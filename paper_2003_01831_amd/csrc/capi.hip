@@ -95,6 +95,7 @@ int afq_walkers_set(afq_walkers w, const double* W, const double* weights, const
     if (W) AFQ_TRY_HIP(hipMemcpyAsync(w->W.p, W, w->nw * per * 16, hipMemcpyDeviceToDevice, st));
     if (weights) AFQ_TRY_HIP(hipMemcpyAsync(w->weights.p, weights, w->nw * 8, hipMemcpyDeviceToDevice, st));
     if (alive) AFQ_TRY_HIP(hipMemcpyAsync(w->alive.p, alive, w->nw * 4, hipMemcpyDeviceToDevice, st));
+    AFQ_RET(counter_set(w->d_counter.as<uint64_t>(), counter, st));
     w->counter = counter;
     return AFQ_OK;
   })
@@ -135,13 +136,14 @@ int afq_step(afq_system s, afq_walkers w, int n_steps, double dt, const double* 
     AFQ_RET(walkers_alloc_scratch(w));
     const long nw = w->nw, X = s->X;
     for (int k = 0; k < n_steps; ++k) {
-      const uint64_t idx = w->counter;
+      const uint64_t idx = w->counter + k;
       const bool do_qr = qr_every > 0 && (idx + 1) % (uint64_t)qr_every == 0;
-      AFQ_RET(step_once(s, w, dt, fields ? fields + (long)k * nw * X : nullptr, seed, 0, idx, do_qr, e_shift,
+      AFQ_RET(step_once(s, w, dt, fields ? fields + (long)k * nw * X : nullptr, seed, 0, k, do_qr, e_shift,
                         taylor_order, emix_out ? emix_out + k : nullptr, eloc_out ? eloc_out + 2 * k * nw : nullptr,
                         weights_out ? weights_out + k * nw : nullptr, ratio_out ? ratio_out + 2 * k * nw : nullptr));
-      w->counter++;
     }
+    if (n_steps > 0) AFQ_RET(counter_add(w->d_counter.as<uint64_t>(), (uint64_t)n_steps, s->stream));
+    w->counter += n_steps;
     return AFQ_OK;
   })
 }

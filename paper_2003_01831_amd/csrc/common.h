@@ -132,6 +132,7 @@ struct afq_walkers_s {
   DevBuf weights;              // nw f64
   DevBuf alive;                // nw int32
   DevBuf killed;               // 1 x int64: walkers killed so far
+  DevBuf d_counter;            // 1 x uint64: step counter on the device (keys the Philox fields)
   // per-step scratch
   DevBuf S, Sinv;              // per (w, spin): n x n complex (max n^2 stride)
   DevBuf logdet, logdet_new;   // nw x 2 complex
@@ -168,6 +169,7 @@ template <typename T> struct GemmArgs {
 // C = alpha op(A) op(B) + beta C   (D += alpha op(A) op(B) if D)
 template <typename T> int gemm(const GemmArgs<T>& g, hipStream_t st);
 template <typename T> GemmArgs<T> gemm_args();
+void gemm_release_workspace(hipStream_t st);   // frees the split-k workspace of a stream
 
 // batched in-place Gauss-Jordan inverse with partial pivoting of n x n complex
 // matrices (stride between matrices `stride` elements). Writes inv (may be
@@ -189,9 +191,13 @@ int system_prepare_pack(afq_system s, int prec);
 int walkers_alloc_scratch(afq_walkers w);
 int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool want_theta,
                           double2* logdet_out);
+// one walker step; the Philox step index is *w->d_counter + step_off (the
+// counter itself is advanced by counter_add after the steps of a call)
 int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed,
-              uint32_t sys_id, uint64_t step_index, bool do_qr, double e_shift, int order,
+              uint32_t sys_id, uint64_t step_off, bool do_qr, double e_shift, int order,
               double* emix_out, double* eloc_out, double* weights_out, double* ratio_out);
+int counter_add(uint64_t* c, uint64_t v, hipStream_t st);
+int counter_set(uint64_t* c, uint64_t v, hipStream_t st);
 int energy_backward(afq_system s, afq_walkers w, double scale, double* d_h1, double* d_chol,
                     double* d_walkers);
 

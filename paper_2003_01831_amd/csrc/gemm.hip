@@ -13,6 +13,8 @@
 // 16 as separate Re/Im planes, k-major so that fragment reads are contiguous.
 // Long contractions with few output tiles are split over k into a workspace
 // and reduced in a fixed order (deterministic).
+#include <map>
+#include <mutex>
 #include "common.h"
 
 namespace {
@@ -211,14 +213,29 @@ __global__ void gemm_splitk_reduce(GemmArgs<T> g, int ksplit, const T* ws) {
   }
 }
 
-// split-k workspace, grown on demand and kept until the process ends (per
-// element type; never freed, so no device call runs during static destruction)
-template <typename T> struct Workspace {
-  static DevBuf& buf() {
-    static DevBuf* b = new DevBuf();
-    return *b;
-  }
+// split-k workspace, one per (stream, element type), grown on demand. Streams
+// that run concurrently (the branches of a batch) therefore never share one.
+// Entries live until gemm_release_workspace(stream) or the process ends (never
+// freed during static destruction, so no device call runs then).
+struct WsKey {
+  hipStream_t st;
+  int tsz;
+  bool operator<(const WsKey& o) const { return st != o.st ? st < o.st : tsz < o.tsz; }
 };
+std::mutex& ws_mutex() {
+  static std::mutex* m = new std::mutex();
+  return *m;
+}
+std::map<WsKey, DevBuf*>& ws_map() {
+  static auto* m = new std::map<WsKey, DevBuf*>();
+  return *m;
+}
+DevBuf& workspace(hipStream_t st, int tsz) {
+  std::lock_guard<std::mutex> lk(ws_mutex());
+  DevBuf*& b = ws_map()[WsKey{st, tsz}];
+  if (!b) b = new DevBuf();
+  return *b;
+}
 
 }  // namespace
 
@@ -245,8 +262,12 @@ template <typename T> int gemm(const GemmArgs<T>& g, hipStream_t st) {
   T* ws = nullptr;
   if (ksplit > 1) {
     const size_t need = (size_t)g.batch * ksplit * g.m * g.n * 2 * sizeof(T);
-    DevBuf& w = Workspace<T>::buf();
+    DevBuf& w = workspace(st, (int)sizeof(T));
     if (w.bytes < need) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      AFQ_TRY_HIP(hipStreamIsCapturing(st, &cs));
+      AFQ_CHECK(cs == hipStreamCaptureStatusNone, AFQ_E_STATE,
+                "gemm: split-k workspace must be sized by an eager call before graph capture");
       AFQ_TRY_HIP(hipStreamSynchronize(st));   // the old workspace may still be in use
       AFQ_RET(w.alloc(need));
     }
@@ -265,6 +286,17 @@ template <typename T> int gemm(const GemmArgs<T>& g, hipStream_t st) {
     AFQ_TRY_HIP(hipGetLastError());
   }
   return AFQ_OK;
+}
+
+void gemm_release_workspace(hipStream_t st) {
+  std::lock_guard<std::mutex> lk(ws_mutex());
+  for (int tsz : {4, 8}) {
+    auto it = ws_map().find(WsKey{st, tsz});
+    if (it == ws_map().end()) continue;
+    (void)hipStreamSynchronize(st);
+    delete it->second;
+    ws_map().erase(it);
+  }
 }
 
 template int gemm<double>(const GemmArgs<double>&, hipStream_t);

@@ -10,7 +10,9 @@ struct AssembleArgs {
   const double2* troo;     // nw x 2 x X
   double e_core, dt;
   const double* fields;    // nw x X or NULL (Philox)
-  uint64_t seed, step;
+  uint64_t seed;
+  const uint64_t* step_ptr;  // device step counter; Philox step = *step_ptr + step_off
+  uint64_t step_off;
   uint32_t sys_id;
   double2* eloc;           // nw (internal)
   double2* eloc_out;       // nw (optional, caller)

@@ -283,6 +283,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs a, CT* __res
   const double2* troo0 = a.troo + (long)w * 2 * a.X;
   const double2* troo1 = troo0 + a.X;
   const int npair = (a.X + 1) / 2;
+  const uint64_t step = a.step_ptr ? *a.step_ptr + a.step_off : a.step_off;
   for (int j = t; j < npair; j += 256) {
     double xs[2] = {0.0, 0.0};
     if (coef) {
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs a, CT* __res
         xs[0] = a.fields[(long)w * a.X + 2 * j];
         if (2 * j + 1 < a.X) xs[1] = a.fields[(long)w * a.X + 2 * j + 1];
       } else {
-        const double2 z = philox_normal_pair(a.seed, a.sys_id, a.step, w, j);
+        const double2 z = philox_normal_pair(a.seed, a.sys_id, step, w, j);
         xs[0] = z.x;
         xs[1] = z.y;
       }
@@ -498,6 +499,21 @@ __global__ void init_alive_kernel(const double* __restrict__ wt, const int* __re
 }
 int launch_init_alive(const double* wt, const int* sing, int nw, int* alive, int* bad, hipStream_t st) {
   hipLaunchKernelGGL(init_alive_kernel, dim3(ceil_div(nw, 256)), dim3(256), 0, st, wt, sing, nw, alive, bad);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+
+// step counter kept on the device, so captured launch sequences advance it
+__global__ void counter_kernel(uint64_t* c, uint64_t v, int add) {
+  if (threadIdx.x == 0) *c = add ? *c + v : v;
+}
+int counter_add(uint64_t* c, uint64_t v, hipStream_t st) {
+  hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, st, c, v, 1);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+int counter_set(uint64_t* c, uint64_t v, hipStream_t st) {
+  hipLaunchKernelGGL(counter_kernel, dim3(1), dim3(64), 0, st, c, v, 0);
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }

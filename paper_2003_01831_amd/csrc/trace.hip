@@ -35,6 +35,8 @@ int collect() {
 
 TraceScope::TraceScope(int phase, hipStream_t st) : slot_(-1), st_(st) {
   if (!g.on || phase < 0 || phase >= AFQ_TRACE_NPHASE) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;   // not inside graphs
   if (g.used == g.slots.size()) {
     if (g.used >= 65536 && collect() != AFQ_OK) return;
     if (g.used == g.slots.size()) {

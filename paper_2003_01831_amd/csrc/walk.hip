@@ -244,7 +244,7 @@ static int qr_walkers(afq_system s, afq_walkers w) {
 }
 
 int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed, uint32_t sys_id,
-              uint64_t step_index, bool do_qr, double e_shift, int order, double* emix_out, double* eloc_out,
+              uint64_t step_off, bool do_qr, double e_shift, int order, double* emix_out, double* eloc_out,
               double* weights_out, double* ratio_out) {
   hipStream_t st = s->stream;
   const int nw = w->nw;
@@ -257,7 +257,8 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
   a.dt = dt;
   a.fields = fields;
   a.seed = seed;
-  a.step = step_index;
+  a.step_ptr = w->d_counter.as<uint64_t>();
+  a.step_off = step_off;
   a.sys_id = sys_id;
   a.eloc_out = reinterpret_cast<double2*>(eloc_out);
   AFQ_RET(energy_from_theta(s, w, a, true));
@@ -310,6 +311,8 @@ int walkers_create_impl(afq_walkers* out, afq_system s, int nw, const double* w0
     AFQ_RET(w->alive.alloc((size_t)nw * 4));
     AFQ_RET(w->killed.alloc(16));
     AFQ_TRY_HIP(hipMemsetAsync(w->killed.p, 0, 16, st));
+    AFQ_RET(w->d_counter.alloc(sizeof(uint64_t)));
+    AFQ_RET(counter_set(w->d_counter.as<uint64_t>(), 0, st));
     if (w0) AFQ_TRY_HIP(hipMemcpyAsync(w->W.p, w0, (size_t)nw * per * 16, hipMemcpyDeviceToDevice, st));
     else AFQ_RET(broadcast_trial(s->phi.as<double2>(), w->W.as<double2>(), per, nw, st));
     if (wt0) AFQ_TRY_HIP(hipMemcpyAsync(w->weights.p, wt0, (size_t)nw * 8, hipMemcpyDeviceToDevice, st));

@@ -79,17 +79,21 @@ def test_autograd_function_and_finite_differences(case):
 
     eps = 1e-6
     with torch.no_grad():
+        # the library validates symmetry, so perturb (i, j) and (j, i) together
         for (i, j) in [(0, 0), (3, 17), (40, 2)]:
             hp, hm = h1.detach().clone(), h1.detach().clone()
             hp[i, j] += eps
             hm[i, j] -= eps
+            if i != j:
+                hp[j, i] += eps
+                hm[j, i] -= eps
             fd = (ebar(hp, chol.detach(), Wt.detach()) - ebar(hm, chol.detach(), Wt.detach())) / (2 * eps)
-            assert abs(fd - rh[i, j]) < 1e-6 * max(1.0, abs(fd))
+            ref = rh[i, j] + (rh[j, i] if i != j else 0.0)
+            assert abs(fd - ref) < 1e-6 * max(1.0, abs(fd))
         for (n, i, j) in [(0, 1, 2), (100, 10, 60)]:
             cp, cm = chol.detach().clone(), chol.detach().clone()
             cp[n, i, j] += eps
             cm[n, i, j] -= eps
-            # an unsymmetrised perturbation: the library validates symmetry, so perturb symmetrically
             cp[n, j, i] += eps
             cm[n, j, i] -= eps
             fd = (ebar(h1.detach(), cp, Wt.detach()) - ebar(h1.detach(), cm, Wt.detach())) / (2 * eps)
