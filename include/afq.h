@@ -173,6 +173,22 @@ int afq_energy_backward(afq_system s, afq_walkers w, double scale, double *d_h1,
 int afq_fields_generate(uint64_t seed, uint32_t sys_id, uint64_t step0, int n_steps,
                         int n_walkers, int n_chol, double *out, void *stream);
 
+/* Autotuner of the fused exchange contraction (the dominant kernel): times
+ * each launch variant (waves per workgroup, accumulator budget) of both spins
+ * on these walkers' own shapes with HIP events, `reps` launches each, and keeps
+ * the fastest for this walker set and for later walker sets of the same shape
+ * (a process-wide table). Recomputes Theta from the current walkers and writes
+ * only per-step scratch: W, weights and counters are unchanged. Synchronises
+ * the system stream. choice_out (host, 2 ints, may be NULL) receives the
+ * variant per spin, -1 where the shape has a single kernel (split-BF16x3 with
+ * 65..100 electrons per spin). */
+int afq_autotune(afq_system s, afq_walkers w, int reps, int *choice_out);
+/* Pins the exchange launch variant of one spin for this walker set (0..2, or
+ * -1 to return to the tuned/default choice), e.g. to replay a tuning table
+ * saved from an earlier process. A variant that does not fit the shape makes
+ * the next step or energy call fail with AFQ_E_UNSUPPORTED. */
+int afq_exchange_variant(afq_walkers w, int spin, int variant);
+
 /* ------------------------------------------------------------------------ */
 /* Many uneven systems in one captured launch sequence.                       */
 /* ------------------------------------------------------------------------ */
@@ -182,8 +198,11 @@ int afq_fields_generate(uint64_t seed, uint32_t sys_id, uint64_t step0, int n_st
 int afq_batch_create(afq_batch *out, int n, const afq_system *systems,
                      const afq_walkers *walkers);
 /* Advances every system n_steps steps with Philox fields (system i uses
- * sys_id = i). The first call captures one HIP graph of qr_every steps (or one
- * step when qr_every is 0) and later calls replay it. e_shift: n float64
+ * sys_id = i). The first call autotunes every system's exchange kernel
+ * (afq_autotune), runs eager steps up to a multiple of qr_every, then captures
+ * one HIP graph of qr_every steps (or one step when qr_every is 0) whose
+ * concurrent branches are the systems; later calls replay it (a change of dt,
+ * seed, qr_every, e_shift, order or precision captures a new graph). e_shift: n float64
  * (host). emix_out: n*n_steps float64 device array, system-major. */
 int afq_batch_step(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_every,
                    const double *e_shift, int taylor_order, double *emix_out);

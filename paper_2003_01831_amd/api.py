@@ -136,6 +136,15 @@ class Walkers:
         check(self.lib.afq_walkers_stats(self.handle, C.byref(na), C.byref(nk)))
         return int(na.value), int(nk.value)
 
+    def autotune(self, reps=3):
+        """Pick the fastest exchange-kernel variant for these walkers; returns the choice per spin."""
+        ch = (C.c_int * 2)()
+        check(self.lib.afq_autotune(self.sys.handle, self.handle, int(reps), C.cast(ch, C.c_void_p)))
+        return int(ch[0]), int(ch[1])
+
+    def set_exchange_variant(self, spin, variant):
+        check(self.lib.afq_exchange_variant(self.handle, int(spin), int(variant)))
+
     def close(self):
         if getattr(self, "handle", None):
             self.lib.afq_walkers_destroy(self.handle)

@@ -21,6 +21,7 @@ struct afq_batch_s {
   double dt = 0.0;
   uint64_t seed = 0;
   int qr_every = -1, order = 0, cycle = 0, prec = -1;
+  bool tuned = false;
   std::vector<double> e_shift;
   DevBuf emix_cycle;   // n x cycle, written by the graph
   ~afq_batch_s() {
@@ -157,6 +158,7 @@ int batch_step_impl(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_e
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+    if (b->prec != prec) b->tuned = false;
     b->prec = prec;
     b->dt = dt;
     b->seed = seed;
@@ -178,6 +180,11 @@ int batch_step_impl(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_e
     const int left = n_steps - done;
     if (warmed && c % b->cycle == 0 && left >= b->cycle) {
       if (!b->exec) {
+        if (!b->tuned) {   // exchange launch variants per system, before they are baked into the graph
+          int c[2];
+          for (int i = 0; i < n; ++i) AFQ_RET(exchange_autotune(b->sys[i], b->wk[i], 3, c));
+          b->tuned = true;
+        }
         AFQ_TRY_HIP(hipStreamSynchronize(b->origin));
         AFQ_RET(build_graph(b));
       }

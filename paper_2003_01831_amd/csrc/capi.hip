@@ -154,6 +154,22 @@ int afq_energy(afq_system s, afq_walkers w, double* eloc_out, double* parts_out,
   AFQ_GUARD(AFQ_RET(check_device(s)); return energy_call(s, w, eloc_out, parts_out, vbar_out, emix_out);)
 }
 
+int afq_autotune(afq_system s, afq_walkers w, int reps, int* choice_out) {
+  AFQ_CHECK(s && w, AFQ_E_INVALID, "afq_autotune: NULL handle");
+  AFQ_CHECK(w->sys == s, AFQ_E_STATE, "afq_autotune: walkers belong to another system");
+  AFQ_CHECK(reps >= 1 && reps <= 1000, AFQ_E_INVALID, "afq_autotune: reps must be in 1..1000");
+  AFQ_GUARD(AFQ_RET(check_device(s)); int c[2] = {-1, -1}; AFQ_RET(exchange_autotune(s, w, reps, c));
+            if (choice_out) { choice_out[0] = c[0]; choice_out[1] = c[1]; } return AFQ_OK;)
+}
+
+int afq_exchange_variant(afq_walkers w, int spin, int variant) {
+  AFQ_CHECK(w, AFQ_E_INVALID, "afq_exchange_variant: NULL handle");
+  AFQ_CHECK(spin == 0 || spin == 1, AFQ_E_INVALID, "afq_exchange_variant: spin must be 0 or 1");
+  AFQ_CHECK(variant >= -1 && variant < 3, AFQ_E_INVALID, "afq_exchange_variant: variant must be -1..2");
+  w->exch_var[spin] = variant;
+  return AFQ_OK;
+}
+
 int afq_energy_backward(afq_system s, afq_walkers w, double scale, double* d_h1, double* d_chol, double* d_walkers) {
   AFQ_CHECK(s && w, AFQ_E_INVALID, "afq_energy_backward: NULL handle");
   AFQ_CHECK(w->sys == s, AFQ_E_STATE, "afq_energy_backward: walkers belong to another system");

@@ -22,6 +22,12 @@ void afq_set_error(const std::string& msg);
     }                                                                            \
   } while (0)
 
+inline int hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return AFQ_OK;
+  afq_set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? AFQ_E_NOMEM : AFQ_E_HIP;
+}
+
 #define AFQ_CHECK(cond, code, msg)                                               \
   do {                                                                           \
     if (!(cond)) {                                                               \
@@ -133,6 +139,7 @@ struct afq_walkers_s {
   DevBuf alive;                // nw int32
   DevBuf killed;               // 1 x int64: walkers killed so far
   DevBuf d_counter;            // 1 x uint64: step counter on the device (keys the Philox fields)
+  int exch_var[2] = {-1, -1};  // exchange launch variant per spin chosen by the autotuner (-1: cached/default)
   // per-step scratch
   DevBuf S, Sinv;              // per (w, spin): n x n complex (max n^2 stride)
   DevBuf logdet, logdet_new;   // nw x 2 complex
@@ -203,6 +210,7 @@ int energy_backward(afq_system s, afq_walkers w, double scale, double* d_h1, dou
 
 // exchange contraction: tr Omega and tr Omega^2 per (w, spin, n)
 int exchange_launch(afq_system s, afq_walkers w, int spin, hipStream_t st);
+int exchange_autotune(afq_system s, afq_walkers w, int reps, int* choice);   // choice[2]
 int pack_theta(afq_system s, afq_walkers w, hipStream_t st);
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }

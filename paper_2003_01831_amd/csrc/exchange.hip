@@ -1,309 +1,77 @@
-// Fused half-rotated Coulomb/exchange contraction (the dominant cost of the
-// walker step; the dense 3-index "Energy" column of the paper's scaling table,
-// O(x_c N^2 M^2) per walker):
+// Dispatch of the fused exchange contraction (tr Omega, tr Omega^2 per
+// Cholesky vector, walker and spin) and its autotuner.
 //
-//   Omega^{ns}_w = Lt^{ns} Theta^s_w          (N x N, never stored)
-//   tro [w][s][n] = tr Omega^{ns}_w            (force bias / Coulomb)
-//   troo[w][s][n] = tr(Omega^{ns}_w Omega^{ns}_w)   (exchange)
-//
-// As one GEMM per spin: C[(n,a)][(w,part,b)] = sum_k A[(n,a)][k] B[(w,part,b)][k]
-// with A the packed half-rotated Cholesky rows and B the packed Theta^T rows
-// (part 0 = Re, 1 = Im; a complex trial doubles k, see PackShape). Every
-// workgroup owns PN whole n-blocks x PW whole walkers, so each N x N block and
-// its transpose live in one workgroup: the traces are taken in the epilogue
-// through LDS and Omega never reaches HBM.
-//
-// Arithmetic policies: FP64 MFMA (16x16x4 f64), FP32 MFMA (16x16x4 f32) and
-// split-BF16x3 on BF16 MFMA (16x16x32 bf16: hi*hi + hi*lo + lo*hi, FP32
-// accumulation). Each wave computes one n-block's rows (TM 16-row tiles) times
-// DC 16-column tiles of one walker's [Re | Im] columns.
-#include <algorithm>
-#include <type_traits>
+// Shapes with 65..100 electrons per spin in split-BF16x3 use the specialised
+// kernel of exchange_big.hip (fixed tiling). Every other shape uses the generic
+// kernel of exchange_generic.h, which has several launch variants (waves per
+// workgroup, accumulator budget). The autotuner times each variant on the
+// walker set's own shapes with HIP events and keeps the fastest, per walker set
+// and in a process-wide table keyed by the shape, so later walker sets of the
+// same shape start from the tuned choice.
+#include <map>
+#include <mutex>
+#include <tuple>
 #include "common.h"
 #include "exchange_big.h"
+#include "exchange_generic.h"
 
 namespace {
 
-typedef __attribute__((ext_vector_type(4))) float f4;
-typedef __attribute__((ext_vector_type(4))) double d4;
-typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
-
-struct PolF64 {
-  using E = double;          // stored element
-  using Acc = d4;
-  using Frag = double;
-  static constexpr int KSTEP = 4, KC = 16, PADE = 2, NPLANE = 1, ACC_REGS = 8;
-  static constexpr int MUL = 1;
-  // output row of (lane, r) inside a 16x16 tile
-  __device__ static int orow(int lane, int r) { return (lane >> 4) + 4 * r; }
-  __device__ static Frag frag(const E* base, int stride, int lane, int ks) {
-    return base[(lane & 15) * stride + ks * KSTEP + (lane >> 4)];
-  }
-  __device__ static void mma(Acc& c, Frag a, Frag b) { c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-};
-
-struct PolF32 {
-  using E = float;
-  using Acc = f4;
-  using Frag = float;
-  static constexpr int KSTEP = 4, KC = 32, PADE = 4, NPLANE = 1, ACC_REGS = 4;
-  __device__ static int orow(int lane, int r) { return 4 * (lane >> 4) + r; }
-  __device__ static Frag frag(const E* base, int stride, int lane, int ks) {
-    return base[(lane & 15) * stride + ks * KSTEP + (lane >> 4)];
-  }
-  __device__ static void mma(Acc& c, Frag a, Frag b) { c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-};
-
-struct PolBF16x3 {
-  using E = unsigned short;  // bf16 bits
-  using Acc = f4;
-  using Frag = bf16x8;
-  static constexpr int KSTEP = 32, KC = 32, PADE = 8, NPLANE = 2, ACC_REGS = 4;
-  __device__ static int orow(int lane, int r) { return 4 * (lane >> 4) + r; }
-  __device__ static Frag frag(const E* base, int stride, int lane, int ks) {
-    const uint4 v = *reinterpret_cast<const uint4*>(base + (lane & 15) * stride + ks * KSTEP + 8 * (lane >> 4));
-    return __builtin_bit_cast(Frag, v);
-  }
-  __device__ static void mma(Acc& c, Frag a, Frag b) { c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
-};
-
-template <class P> constexpr int dc_for(int tm, int budget) {
-  int best = 1;
-  for (int d = 1; d <= 2 * tm; ++d)
-    if ((2 * tm) % d == 0 && tm * d * P::ACC_REGS <= budget) best = d;
-  return best;
+using Key = std::tuple<int, int, int, int, int, int>;   // prec, n, np, kp, X, nw
+std::mutex& tune_mutex() {
+  static std::mutex* m = new std::mutex();
+  return *m;
+}
+std::map<Key, int>& tune_table() {
+  static auto* t = new std::map<Key, int>();
+  return *t;
+}
+Key key_of(afq_system s, afq_walkers w, int spin) {
+  const PackShape& ps = s->ps[spin];
+  return Key{s->prec, ps.n, ps.np, ps.kp, s->X, w->nw};
 }
 
-struct ExchArgs {
-  const void* a_hi; const void* a_lo;   // packed A for this spin
-  const void* b_hi; const void* b_lo;   // packed B for this spin
-  int n, np, kp, X, nw, PN, PW, spin;
-  int lds_kloop;                        // bytes of the k-loop staging
-  int rb;                               // blocks per epilogue round
-  double2* tro; double2* troo;          // [w][2][X]
-};
-
-// waves per workgroup for a policy/tile: G waves per block, about 8 in total
-template <int G> constexpr int waves_for() { return G >= 8 ? G : (8 / G) * G; }
-
-template <class P, int TM, int DC>
-__global__ __launch_bounds__(64 * waves_for<2 * TM / DC>()) void exchange_kernel(ExchArgs g) {
-  using E = typename P::E;
-  using Acc = typename P::Acc;
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double partial[16][5];
-
-  constexpr int G = 2 * TM / DC;        // waves per (n, w) block
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nthreads = blockDim.x;
-  const int np = g.np, kp = g.kp;
-  const int nblk_w = (g.nw + g.PW - 1) / g.PW;
-  const int bn = blockIdx.x / nblk_w, bw = blockIdx.x - bn * nblk_w;
-  const int n0 = bn * g.PN, w0 = bw * g.PW;
-  const int bl = wave / G, gi = wave - bl * G;       // block-local index, column group
-  const int nl = bl % g.PN, wl = bl / g.PN;
-
-  const int stride = P::KC + P::PADE;                // LDS row stride (elements)
-  const int rowsA = g.PN * np, rowsB = g.PW * 2 * np;
-  E* lA = reinterpret_cast<E*>(smem);
-  E* lB = lA + (size_t)rowsA * stride * P::NPLANE;
-
-  Acc acc[TM][DC];
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < DC; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
-
-  const long a_row0 = (long)n0 * np, a_rows_tot = (long)g.X * np;
-  const long b_row0 = (long)w0 * 2 * np, b_rows_tot = (long)g.nw * 2 * np;
-  constexpr int VPR = P::KC * (int)sizeof(E) / 16;   // 16-byte vectors per row chunk
-
-  for (int k0 = 0; k0 < kp; k0 += P::KC) {
-    __syncthreads();
-    // stage A and B chunks (all planes) into LDS
-    for (int pl = 0; pl < P::NPLANE; ++pl) {
-      const E* ga = reinterpret_cast<const E*>(pl == 0 ? g.a_hi : g.a_lo);
-      const E* gb = reinterpret_cast<const E*>(pl == 0 ? g.b_hi : g.b_lo);
-      E* la = lA + (size_t)pl * rowsA * stride;
-      E* lb = lB + (size_t)pl * rowsB * stride;
-      for (int v = tid; v < rowsA * VPR; v += nthreads) {
-        const int row = v / VPR, part = v - row * VPR;
-        const long gr = a_row0 + row;
-        uint4 val = make_uint4(0, 0, 0, 0);
-        if (gr < a_rows_tot)
-          val = *reinterpret_cast<const uint4*>(ga + gr * kp + k0 + part * (16 / sizeof(E)));
-        *reinterpret_cast<uint4*>(la + row * stride + part * (16 / sizeof(E))) = val;
-      }
-      for (int v = tid; v < rowsB * VPR; v += nthreads) {
-        const int row = v / VPR, part = v - row * VPR;
-        const long gr = b_row0 + row;
-        uint4 val = make_uint4(0, 0, 0, 0);
-        if (gr < b_rows_tot)
-          val = *reinterpret_cast<const uint4*>(gb + gr * kp + k0 + part * (16 / sizeof(E)));
-        *reinterpret_cast<uint4*>(lb + row * stride + part * (16 / sizeof(E))) = val;
-      }
-    }
-    __syncthreads();
-    const E* wa = lA + (size_t)(nl * np) * stride;
-    const E* wb = lB + (size_t)(wl * 2 * np + gi * DC * 16) * stride;
-#pragma unroll
-    for (int ks = 0; ks < P::KC / P::KSTEP; ++ks) {
-      typename P::Frag af[TM], af_lo[TM];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        af[i] = P::frag(wa + i * 16 * stride, stride, lane, ks);
-        if constexpr (P::NPLANE == 2) af_lo[i] = P::frag(wa + (size_t)rowsA * stride + i * 16 * stride, stride, lane, ks);
-      }
-#pragma unroll
-      for (int j = 0; j < DC; ++j) {
-        const typename P::Frag bf = P::frag(wb + j * 16 * stride, stride, lane, ks);
-        typename P::Frag bf_lo;
-        if constexpr (P::NPLANE == 2) bf_lo = P::frag(wb + (size_t)rowsB * stride + j * 16 * stride, stride, lane, ks);
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-          P::mma(acc[i][j], af[i], bf);
-          if constexpr (P::NPLANE == 2) {
-            P::mma(acc[i][j], af[i], bf_lo);
-            P::mma(acc[i][j], af_lo[i], bf);
-          }
-        }
-      }
-    }
-  }
-
-  // ---------------- epilogue: traces through LDS ----------------
-  // Each round stages rb whole blocks (Re and Im planes, n x n each) in LDS,
-  // then the workgroup reduces tr Omega and tr Omega^2 of one block at a time
-  // with a fixed-order reduction.
-  using V = typename std::conditional<sizeof(E) == 8, double, float>::type;
-  const int n = g.n, nn = n * n;
-  V* tbuf = reinterpret_cast<V*>(smem);
-  const int nblocks = g.PN * g.PW;
-  const int nwaves = nthreads >> 6;
-  for (int rb0 = 0; rb0 < nblocks; rb0 += g.rb) {
-    const int rcount = min(g.rb, nblocks - rb0);
-    __syncthreads();
-    if (bl >= rb0 && bl < rb0 + rcount) {
-      V* tb = tbuf + (size_t)(bl - rb0) * 2 * nn;
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < DC; ++j) {
-          const int cc = gi * DC * 16 + 16 * j + (lane & 15);
-          const int part = cc >= 16 * TM;
-          const int b = cc - part * 16 * TM;
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int a = 16 * i + P::orow(lane, r);
-            if (a < n && b < n) tb[part * nn + a * n + b] = (V)acc[i][j][r];
-          }
-        }
-    }
-    __syncthreads();
-    for (int q = 0; q < rcount; ++q) {
-      const V* tb = tbuf + (size_t)q * 2 * nn;
-      double tr_re = 0, tr_im = 0, s_rere = 0, s_imim = 0, s_reim = 0;
-      for (int e = tid; e < nn; e += nthreads) {
-        const int a = e / n, b = e - a * n;
-        const double rab = tb[e], iab = tb[nn + e];
-        const double rba = tb[b * n + a], iba = tb[nn + b * n + a];
-        s_rere += rab * rba;
-        s_imim += iab * iba;
-        s_reim += rab * iba;
-        if (a == b) { tr_re += rab; tr_im += iab; }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        tr_re += __shfl_xor(tr_re, off);
-        tr_im += __shfl_xor(tr_im, off);
-        s_rere += __shfl_xor(s_rere, off);
-        s_imim += __shfl_xor(s_imim, off);
-        s_reim += __shfl_xor(s_reim, off);
-      }
-      if (lane == 0) {
-        partial[wave][0] = tr_re; partial[wave][1] = tr_im;
-        partial[wave][2] = s_rere; partial[wave][3] = s_imim; partial[wave][4] = s_reim;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        double sum[5] = {0, 0, 0, 0, 0};
-        for (int v = 0; v < nwaves; ++v)
-          for (int t = 0; t < 5; ++t) sum[t] += partial[v][t];
-        const int blk = rb0 + q;
-        const int nidx = n0 + blk % g.PN, widx = w0 + blk / g.PN;
-        if (nidx < g.X && widx < g.nw) {
-          const long o = ((long)widx * 2 + g.spin) * g.X + nidx;
-          g.tro[o] = make_double2(sum[0], sum[1]);
-          g.troo[o] = make_double2(sum[2] - sum[3], 2.0 * sum[4]);
-        }
-      }
-      __syncthreads();
-    }
-  }
+exch::ExchArgs generic_args(afq_system s, afq_walkers w, int spin, size_t boff) {
+  const PackShape& ps = s->ps[spin];
+  exch::ExchArgs g{};
+  g.a_hi = s->apack[spin].p;
+  g.a_lo = s->apack_lo[spin].p;
+  g.b_hi = w->bpack.as<char>() + boff;
+  g.b_lo = s->prec == AFQ_BF16X3 ? (const void*)(w->bpack_lo.as<char>() + boff) : nullptr;
+  g.n = ps.n; g.np = ps.np; g.kp = ps.kp; g.X = s->X; g.nw = w->nw; g.spin = spin;
+  g.PN = 0; g.PW = 0;
+  g.tro = w->tro.as<double2>();
+  g.troo = w->troo.as<double2>();
+  return g;
 }
 
-template <class P, int TM, int DC>
-int launch_one(ExchArgs g, hipStream_t st) {
-  constexpr int G = 2 * TM / DC;
-  constexpr int WV = waves_for<G>();
-  static_assert(WV <= 16, "too many waves per workgroup");
-  // PN x PW blocks per workgroup with PN * PW = WV / G
-  const int bpw = WV / G;
-  int pn = 1, pw = 1;
-  while (pn * pw < bpw) { if (pn <= pw) pn *= 2; else pw *= 2; }
-  g.PN = pn; g.PW = pw;
-  const int waves = WV;
-  const int stride = P::KC + P::PADE;
-  const size_t kloop = (size_t)(pn * g.np + pw * 2 * g.np) * stride * sizeof(typename P::E) * P::NPLANE;
-  using V = typename std::conditional<sizeof(typename P::E) == 8, double, float>::type;
-  const size_t per_blk = 2 * (size_t)g.n * g.n * sizeof(V);   // Re and Im planes of one block
-  const size_t budget = 160 * 1024 - 1024;
-  AFQ_CHECK(per_blk <= budget, AFQ_E_UNSUPPORTED,
-            "exchange: at most 100 electrons per spin in FP64 mode (the Omega block must fit in LDS)");
-  int rb = (int)std::min<size_t>((size_t)pn * pw, std::max<size_t>(1, kloop / per_blk));
-  if (rb < 1) rb = 1;
-  size_t lds = std::max(kloop, rb * per_blk);
-  AFQ_CHECK(lds <= budget, AFQ_E_UNSUPPORTED, "exchange: LDS requirement exceeds 159 KiB");
-  g.rb = rb;
-  g.lds_kloop = (int)kloop;
-  const long nblk = (long)ceil_div(g.X, pn) * ceil_div(g.nw, pw);
-  AFQ_CHECK(nblk < (1l << 31), AFQ_E_INVALID, "exchange: grid too large");
-  hipLaunchKernelGGL((exchange_kernel<P, TM, DC>), dim3((unsigned)nblk), dim3(64 * waves), lds, st, g);
-  AFQ_TRY_HIP(hipGetLastError());
-  return AFQ_OK;
+size_t b_offset(afq_system s, afq_walkers w, int spin) {
+  const size_t esz = s->prec == AFQ_FP64 ? 8 : s->prec == AFQ_CFP32 ? 4 : 2;
+  return (size_t)spin * s->ps[0].rows_b(w->nw) * s->ps[0].kp * esz;
 }
 
-template <class P>
-int launch_policy(ExchArgs g, hipStream_t st) {
-  const int tm = g.np / 16;
-  constexpr int B = 128;
-  switch (tm) {
-    case 1: return launch_one<P, 1, dc_for<P>(1, B)>(g, st);
-    case 2: return launch_one<P, 2, dc_for<P>(2, B)>(g, st);
-    case 3: return launch_one<P, 3, dc_for<P>(3, B)>(g, st);
-    case 4: return launch_one<P, 4, dc_for<P>(4, B)>(g, st);
-    case 5: return launch_one<P, 5, dc_for<P>(5, B)>(g, st);
-    case 6: return launch_one<P, 6, dc_for<P>(6, B)>(g, st);
-    case 7: return launch_one<P, 7, dc_for<P>(7, B)>(g, st);
-    case 8: return launch_one<P, 8, dc_for<P>(8, B)>(g, st);
-    default: break;
-  }
-  afq_set_error("exchange: electrons per spin must be <= 128");
-  return AFQ_E_UNSUPPORTED;
+int launch_generic(afq_system s, const exch::ExchArgs& g, int variant, hipStream_t st) {
+  if (s->prec == AFQ_FP64) return exchange_generic_f64(g, variant, st);
+  if (s->prec == AFQ_CFP32) return exchange_generic_f32(g, variant, st);
+  return exchange_generic_bf16(g, variant, st);
+}
+
+int variant_for(afq_system s, afq_walkers w, int spin) {
+  if (w->exch_var[spin] >= 0) return w->exch_var[spin];
+  std::lock_guard<std::mutex> lk(tune_mutex());
+  auto it = tune_table().find(key_of(s, w, spin));
+  return it == tune_table().end() ? 0 : it->second;
 }
 
 }  // namespace
 
 int exch_kchunk(int prec) {
-  return prec == AFQ_FP64 ? PolF64::KC : prec == AFQ_CFP32 ? PolF32::KC : PolBF16x3::KC;
+  return prec == AFQ_FP64 ? exch::PolF64::KC : prec == AFQ_CFP32 ? exch::PolF32::KC : exch::PolBF16x3::KC;
 }
 
 int exchange_launch(afq_system s, afq_walkers w, int spin, hipStream_t st) {
   const PackShape& ps = s->ps[spin];
-  const size_t esz = s->prec == AFQ_FP64 ? 8 : s->prec == AFQ_CFP32 ? 4 : 2;
-  const size_t boff = (size_t)spin * s->ps[0].rows_b(w->nw) * s->ps[0].kp * esz;
+  const size_t boff = b_offset(s, w, spin);
   if (ps.big) {
     ExchBigArgs b{};
     b.a[0] = s->apack[spin].p;
@@ -315,16 +83,55 @@ int exchange_launch(afq_system s, afq_walkers w, int spin, hipStream_t st) {
     b.troo = w->troo.as<double2>();
     return exchange_big_launch(b, s->prec, st);
   }
-  ExchArgs g{};
-  g.a_hi = s->apack[spin].p;
-  g.a_lo = s->apack_lo[spin].p;
-  g.b_hi = w->bpack.as<char>() + boff;
-  g.b_lo = s->prec == AFQ_BF16X3 ? (const void*)(w->bpack_lo.as<char>() + boff) : nullptr;
-  g.n = ps.n; g.np = ps.np; g.kp = ps.kp; g.X = s->X; g.nw = w->nw; g.spin = spin;
-  g.PN = 0; g.PW = 0;
-  g.tro = w->tro.as<double2>();
-  g.troo = w->troo.as<double2>();
-  if (s->prec == AFQ_FP64) return launch_policy<PolF64>(g, st);
-  if (s->prec == AFQ_CFP32) return launch_policy<PolF32>(g, st);
-  return launch_policy<PolBF16x3>(g, st);
+  return launch_generic(s, generic_args(s, w, spin, boff), variant_for(s, w, spin), st);
+}
+
+// Times every launch variant of both spins on the current walkers (Theta is
+// recomputed and packed first; only per-step scratch is written) and keeps the
+// fastest. choice[spin] = the variant, or -1 where the shape has a single
+// kernel (the specialised split-BF16x3 kernel).
+int exchange_autotune(afq_system s, afq_walkers w, int reps, int* choice) {
+  hipStream_t st = s->stream;
+  AFQ_RET(system_prepare_pack(s, s->prec));
+  AFQ_RET(walkers_alloc_scratch(w));
+  AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), true, w->logdet.as<double2>()));
+  AFQ_RET(pack_theta(s, w, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  AFQ_TRY_HIP(hipEventCreate(&e0));
+  AFQ_TRY_HIP(hipEventCreate(&e1));
+  int rc = AFQ_OK;
+  for (int spin = 0; spin < 2 && rc == AFQ_OK; ++spin) {
+    choice[spin] = -1;
+    if (s->ps[spin].big) continue;
+    const exch::ExchArgs g = generic_args(s, w, spin, b_offset(s, w, spin));
+    float best = 0.f;
+    int best_v = -1;
+    for (int v = 0; v < exch::kNumExchVariants && rc == AFQ_OK; ++v) {
+      if (launch_generic(s, g, v, st) != AFQ_OK) continue;   // does not fit this shape (LDS)
+      if ((rc = hip_status(hipEventRecord(e0, st), "hipEventRecord")) != AFQ_OK) break;
+      for (int r = 0; r < reps && rc == AFQ_OK; ++r) rc = launch_generic(s, g, v, st);
+      if (rc != AFQ_OK) break;
+      if ((rc = hip_status(hipEventRecord(e1, st), "hipEventRecord")) != AFQ_OK) break;
+      if ((rc = hip_status(hipEventSynchronize(e1), "hipEventSynchronize")) != AFQ_OK) break;
+      float ms = 0.f;
+      if ((rc = hip_status(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) != AFQ_OK) break;
+      if (best_v < 0 || ms < best) {
+        best = ms;
+        best_v = v;
+      }
+    }
+    if (rc != AFQ_OK) break;
+    if (best_v < 0) {
+      afq_set_error("exchange autotune: no launch variant fits this shape");
+      rc = AFQ_E_UNSUPPORTED;
+      break;
+    }
+    choice[spin] = best_v;
+    w->exch_var[spin] = best_v;
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    tune_table()[key_of(s, w, spin)] = best_v;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }

@@ -12,6 +12,7 @@ static size_t esz_of(int prec) { return prec == AFQ_FP64 ? 8 : prec == AFQ_CFP32
 int walkers_alloc_scratch(afq_walkers w) {
   afq_system s = w->sys;
   if (w->scratch_prec == (size_t)s->prec) return AFQ_OK;
+  if (w->scratch_prec != (size_t)-1) w->exch_var[0] = w->exch_var[1] = -1;   // tuned for another precision
   const int nw = w->nw, M = s->M, ntot = s->ntot, X = s->X;
   const int nmax = std::max(s->n_up, s->n_dn);
   const size_t per = (size_t)M * ntot;
