@@ -90,7 +90,8 @@ struct DevBuf {
 
 // ---------------------------------------------------------------------------
 // packed operand layout of the exchange GEMM  C[(n,a)][(w,part,b)] = sum_k A B
-//   A rows (n, a): n * np + a, a < N (rows a >= N are zero), k < kp
+//   A rows (n, a): n * np + a, a < N (rows a >= N are zero), k < kp; stored
+//   row-major, or chunk-major (all rows of k-chunk 0, then of chunk 1, ...)
 //   B rows (w, part, b): per walker 2*np rows, part 0 = Re, 1 = Im
 //   real trial: k runs over M orbitals;  complex trial: k over 2M
 //   (A = [Lt_re | Lt_im], B = [[Th_re, Th_im], [-Th_im, Th_re]])
@@ -102,6 +103,7 @@ struct PackShape {
   int kp = 0;     // ke rounded up to the k-chunk
   bool big = false;  // stacked layout of the one-wave-per-SIMD kernel
   int pad = 0;    // zero rows after the last block (A and B)
+  int kcm = 0;    // 0: row-major (row * kp + k); else chunk-major ((k / kcm) * rows + row) * kcm + k % kcm
   long rows_b(int nw) const { return (long)nw * 2 * np + pad; }
 };
 

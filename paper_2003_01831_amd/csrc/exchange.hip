@@ -79,6 +79,8 @@ int exchange_launch(afq_system s, afq_walkers w, int spin, hipStream_t st) {
     b.b[0] = w->bpack.as<char>() + boff;
     b.b[1] = s->prec == AFQ_BF16X3 ? (const void*)(w->bpack_lo.as<char>() + boff) : nullptr;
     b.n = ps.n; b.kp = ps.kp; b.X = s->X; b.nw = w->nw; b.spin = spin;
+    b.rows_a = (long)s->X * ps.np + ps.pad;
+    b.rows_b = ps.rows_b(w->nw);
     b.tro = w->tro.as<double2>();
     b.troo = w->troo.as<double2>();
     return exchange_big_launch(b, s->prec, st);

@@ -7,17 +7,19 @@
 //     (TM = ceil(N / 16)); rows and columns are stacked without per-block
 //     padding in the packed operands;
 //   * the waves share the walker operand (B) and the Cholesky operand (A)
-//     through LDS; k advances in chunks of 32 that are double-buffered with
-//     direct global->LDS loads (no register staging), so the next chunk
-//     streams in while the current one feeds the MFMAs; the two buffers are
+//     through LDS. k advances in chunks of 32 through a three-stage ring of
+//     LDS buffers filled by direct global->LDS loads (no register staging):
+//     all loads of chunk c+2 are issued before the MFMAs of chunk c, so two
+//     chunks are in flight while one is consumed. The packed operands are
+//     chunk-major in HBM (all rows of k-chunk 0, then chunk 1, ...), so the
+//     rows of one chunk are one contiguous run. The three buffers are
 //     distinct LDS objects so the compiler can tell the one being read from
-//     the one being filled;
+//     the ones being filled;
 //   * fragments are read with 16-byte LDS loads from an XOR-swizzled layout;
-//   * epilogue: every wave stores the lower-triangle tiles of its plane in LDS
-//     (row stride N + 1, so the transposed reads are bank-conflict free) and
-//     reads the transposed partners of its upper-triangle tiles from its own
-//     and the other plane of the block, giving tr Omega and tr(Omega Omega)
-//     without any HBM traffic;
+//   * epilogue: every wave stores the lower triangle of its plane in LDS
+//     (packed triangular layout) and reads the transposed partners of its
+//     upper-triangle elements from its own and the other plane of the block,
+//     giving tr Omega and tr(Omega Omega) without any HBM traffic;
 //   * workgroups are ordered XCD by XCD in 2-D tiles of (n-pair, walker) so
 //     the operands of resident workgroups are shared in each XCD's L2.
 //
@@ -34,12 +36,12 @@ typedef __attribute__((ext_vector_type(4))) float f4;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((address_space(3))) unsigned char lds_t;
 
-constexpr int KC = 32;              // k per chunk (bf16 elements); chunks come in pairs
+constexpr int KC = 32;              // k per chunk (bf16 elements)
 constexpr int NWAVE = 4;
-constexpr int ROWB = KC * 2;        // bytes per LDS row per plane
-constexpr int CPR = ROWB / 16;      // 16-byte chunks per row
+constexpr int ROWB = KC * 2;        // bytes per LDS row per plane (one chunk of one row)
+constexpr int CPR = ROWB / 16;      // 16-byte pieces per row
 
-// XOR swizzle of the 16-byte chunks of a 64-byte row (an involution)
+// XOR swizzle of the 16-byte pieces of a 64-byte row (an involution)
 __device__ inline int swz(int row, int c) { return c ^ ((row >> 1) & 3); }
 
 __device__ inline uint4 lds16(const unsigned char* p) { return *reinterpret_cast<const uint4*>(p); }
@@ -48,14 +50,19 @@ __device__ inline bf16x8 frag(const unsigned char* plane, int row, int lq) {
   return __builtin_bit_cast(bf16x8, lds16(plane + row * ROWB + 16 * swz(row, lq)));
 }
 
-constexpr int NMAX = 100;           // largest N: both planes of two blocks fit in LDS at once
+constexpr int NMAX = 100;           // largest N
 
 template <int TM> struct Geo {
-  static constexpr int ROWS = 32 * TM;                 // rows per operand region (>= N + 16 TM)
-  static constexpr int BUF = 2 * ROWS * ROWB * 2;      // A and B, hi and lo
+  // rows staged per operand region: both blocks (2N rows) rounded to 16; the
+  // tile of the second block overhangs by at most 8 rows into the next region
+  // or the stage's slack (those rows only feed discarded outputs)
+  static constexpr int RR = 32 * TM < 208 ? 32 * TM : 208;
+  static constexpr int RI = RR / 16;                   // 1 KB load instructions per region
+  static constexpr int REG = RR * ROWB;                // bytes per region
+  static constexpr int STAGE = 4 * REG + 512;          // A hi, A lo, B hi, B lo + slack
   static constexpr int NE = 16 * TM < NMAX ? 16 * TM : NMAX;
-  static constexpr int EPI = 2 * NE * (NE + 1) * 4;    // Re and Im planes of one block, row stride N + 1
-  static constexpr int SIZE = BUF > EPI ? BUF : EPI;   // bytes of each of the two LDS objects
+  static constexpr int TRI = NE * (NE + 1) / 2;        // packed lower triangle of one plane
+  static_assert(2 * TRI * 4 <= STAGE, "epilogue planes must fit one stage");
 };
 
 // workgroups resident on one XCD form TB n-pairs x TW walkers tiles
@@ -66,18 +73,18 @@ constexpr int NXCD = 8, TB = 4, TW = 8;
 template <int TM>
 __device__ inline void mma_chunk(f4 (&acc)[TM][TM], const unsigned char* la, const unsigned char* lb, int arow,
                                  int brow, int lane) {
-  constexpr int R = Geo<TM>::ROWS;
+  constexpr int RB = Geo<TM>::REG;
   const int lr = lane & 15, lq = lane >> 4;
   bf16x8 a[TM];
 #pragma unroll
   for (int i = 0; i < TM; ++i) a[i] = frag(la, arow + 16 * i + lr, lq);
-  bf16x8 bh = frag(lb, brow + lr, lq), bl = frag(lb + R * ROWB, brow + lr, lq);
+  bf16x8 bh = frag(lb, brow + lr, lq), bl = frag(lb + RB, brow + lr, lq);
 #pragma unroll
   for (int j = 0; j < TM; ++j) {
     bf16x8 nh = bh, nl = bl;
     if (j + 1 < TM) {
       nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
-      nl = frag(lb + R * ROWB, brow + 16 * (j + 1) + lr, lq);
+      nl = frag(lb + RB, brow + 16 * (j + 1) + lr, lq);
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
@@ -88,7 +95,7 @@ __device__ inline void mma_chunk(f4 (&acc)[TM][TM], const unsigned char* la, con
     bl = nl;
   }
 #pragma unroll
-  for (int i = 0; i < TM; ++i) a[i] = frag(la + R * ROWB, arow + 16 * i + lr, lq);
+  for (int i = 0; i < TM; ++i) a[i] = frag(la + RB, arow + 16 * i + lr, lq);
   bh = frag(lb, brow + lr, lq);
 #pragma unroll
   for (int j = 0; j < TM; ++j) {
@@ -100,24 +107,45 @@ __device__ inline void mma_chunk(f4 (&acc)[TM][TM], const unsigned char* la, con
   }
 }
 
-// Direct global->LDS loads of one chunk of a region of `rows` rows of one
-// plane: slot s of wave-instruction j holds row s/CPR, swizzled chunk s%CPR.
-__device__ inline void dma_region(const unsigned char* g, long row0, long kp_bytes, long k0_bytes, lds_t* l,
-                                  int rows, int wave, int lane) {
-  const int ninstr = rows * ROWB / 1024;
-  for (int j = wave; j < ninstr; j += NWAVE) {
-    const int s = j * 64 + lane;
-    const int row = s / CPR, c = swz(row, s % CPR);
-    __builtin_amdgcn_global_load_lds(g + (row0 + row) * kp_bytes + k0_bytes + 16 * c, l + j * 1024, 16, 0, 0);
-  }
+// s_waitcnt vmcnt(W) with expcnt and lgkmcnt left unconstrained. The builtin
+// (not inline asm) lets the compiler's wait-count pass see the wait, so it
+// does not add a conservative vmcnt(0) of its own before the LDS reads.
+// Direct global->LDS loads and their waits, written as inline asm so that the
+// compiler's wait-count pass does not track them: it cannot tell the three
+// ring buffers apart across the loop and would add a conservative vmcnt(0)
+// before the LDS reads of some steps. The kernel therefore waits for its own
+// loads explicitly (every LDS read of a buffer follows a vmcnt wait covering
+// that buffer's loads and a barrier). Lane l of a load writes LDS bytes
+// [m0 + BYTES l, m0 + BYTES (l + 1)). No VGPR is written by these loads.
+// M0 is reserved by the compiler, but this kernel uses it nowhere else (it
+// needs no indirect register indexing, message or GWS instruction), so
+// clobbering it here is safe; the warning about it is silenced for these two.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ inline void dma16(const unsigned char* src, lds_t* dst) {
+  const unsigned m = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)dst);
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(m) : "memory", "m0");
+}
+__device__ inline void dma4(const unsigned char* src, lds_t* dst) {
+  const unsigned m = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)dst);
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(src), "s"(m) : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// s_waitcnt vmcnt(W) followed by s_barrier, one opaque statement: it is also a
+// compiler-level memory barrier, so no LDS access moves across it
+template <int W> __device__ inline void wait_vm_barrier() {
+  static_assert(W >= 0 && W < 64, "vmcnt is 6 bits");
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(W) : "memory");
 }
 
 template <int TM>
 __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
   using G = Geo<TM>;
-  constexpr int R = G::ROWS;
-  __shared__ __align__(16) unsigned char lds0[G::SIZE];
-  __shared__ __align__(16) unsigned char lds1[G::SIZE];
+  constexpr int RI = G::RI, REG = G::REG;
+  __shared__ __align__(16) unsigned char L0[G::STAGE];
+  __shared__ __align__(16) unsigned char L1[G::STAGE];
+  __shared__ __align__(16) unsigned char L2[G::STAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = g.n;
   const int nb = wave >> 1, part = wave & 1;      // n-block within the pair, plane
@@ -141,8 +169,38 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
   const int n0 = 2 * bn;                          // first n-block of the workgroup
   const long arow0 = (long)n0 * N;
   const long brow0 = (long)w0 * 2 * N;
-  const long kpb = (long)g.kp * 2;
-  const int rows = g.rows;                        // rows loaded per region and plane (<= R)
+
+  // Load q of this wave (q < RI) moves 1 KB: instruction t = 4 q + wave of the
+  // chunk, region t / RI (A hi, A lo, B hi, B lo), rows 16 (t % RI) ... + 15.
+  // Lane l writes LDS bytes base + 16 l: row (l / 4), swizzled piece.
+  const unsigned char* src[RI];
+  long cstride[RI];                               // bytes from one k-chunk to the next
+#pragma unroll
+  for (int q = 0; q < RI; ++q) {
+    const int t = q * NWAVE + wave, reg = t / RI, j = t - reg * RI;
+    const int sidx = j * 64 + lane, row = sidx / CPR, c = swz(row, sidx % CPR);
+    const unsigned char* base = static_cast<const unsigned char*>(reg == 0 ? g.a[0] : reg == 1 ? g.a[1]
+                                                                   : reg == 2 ? g.b[0] : g.b[1]);
+    src[q] = base + ((reg < 2 ? arow0 : brow0) + row) * ROWB + 16 * c;
+    cstride[q] = (reg < 2 ? g.rows_a : g.rows_b) * (long)ROWB;
+  }
+  auto issue = [&](int chunk, unsigned char* buf) {
+    lds_t* l = (lds_t*)buf;
+#pragma unroll
+    for (int q = 0; q < RI; ++q) {
+      const int t = q * NWAVE + wave, reg = t / RI, j = t - reg * RI;
+      dma16(src[q] + chunk * cstride[q], l + reg * REG + j * 1024);
+    }
+  };
+  // The last two steps have no chunk to prefetch: they issue RI tiny loads
+  // (4 bytes per lane, into this wave's slice of the epilogue trash area) so
+  // that every step keeps the same wait count and the same code shape.
+  __shared__ float trash[NWAVE * 64];
+  auto issue_dummy = [&]() {
+    lds_t* l = (lds_t*)(trash + wave * 64);
+#pragma unroll
+    for (int q = 0; q < RI; ++q) dma4(src[q], l);
+  };
 
   f4 acc[TM][TM];
 #pragma unroll
@@ -150,42 +208,49 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
 #pragma unroll
     for (int j = 0; j < TM; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  auto issue = [&](int chunk, unsigned char* buf) {
-    const long k0b = (long)chunk * KC * 2;
-    lds_t* l = (lds_t*)buf;
-    dma_region(static_cast<const unsigned char*>(g.a[0]), arow0, kpb, k0b, l, rows, wave, lane);
-    dma_region(static_cast<const unsigned char*>(g.a[1]), arow0, kpb, k0b, l + R * ROWB, rows, wave, lane);
-    dma_region(static_cast<const unsigned char*>(g.b[0]), brow0, kpb, k0b, l + 2 * R * ROWB, rows, wave, lane);
-    dma_region(static_cast<const unsigned char*>(g.b[1]), brow0, kpb, k0b, l + 3 * R * ROWB, rows, wave, lane);
-  };
-
-  const int nchunk = g.kp / KC;                   // even
+  const int nc = g.kp / KC;                       // >= 2
   const int arow = nb * N, brow = part * N;       // this wave's first rows in the A / B regions
-  issue(0, lds0);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  for (int c = 0; c < nchunk; c += 2) {
-    issue(c + 1, lds1);
-    mma_chunk<TM>(acc, lds0, lds0 + 2 * R * ROWB, arow, brow, lane);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    if (c + 2 < nchunk) issue(c + 2, lds0);
-    mma_chunk<TM>(acc, lds1, lds1 + 2 * R * ROWB, arow, brow, lane);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+  issue(0, L0);
+  issue(1, L1);
+  // chunk 0 has landed (chunk 1 may be in flight). A plain s_barrier, not
+  // __syncthreads(): its release fence would wait for every load in flight
+  // (vmcnt(0)) and serialise the pipeline. Each wave has waited for its own
+  // loads of the chunk consumed next, and its LDS reads of the previous chunk
+  // have returned (their MFMAs consumed them), so the barrier alone orders the
+  // buffer hand-over.
+  wait_vm_barrier<RI>();
+  // step c: prefetch chunk c+2 into the buffer freed by chunk c-1, consume
+  // chunk c, then wait until chunk c+1 has landed (a macro rather than a
+  // lambda: the barrier and wait builtins must stay in device-only code)
+#define AFQ_EXB_STEP(c, cur, pf)                                     \
+  do {                                                               \
+    if ((c) + 2 < nc) issue((c) + 2, pf);                            \
+    else issue_dummy();                                              \
+    __builtin_amdgcn_sched_barrier(0);                               \
+    mma_chunk<TM>(acc, cur, cur + 2 * REG, arow, brow, lane);        \
+    __builtin_amdgcn_sched_barrier(0);                               \
+    wait_vm_barrier<RI>();                                           \
+  } while (0)
+  for (int c = 0; c < nc; c += 3) {
+    AFQ_EXB_STEP(c, L0, L2);
+    if (c + 1 < nc) AFQ_EXB_STEP(c + 1, L1, L0);
+    if (c + 2 < nc) AFQ_EXB_STEP(c + 2, L2, L1);
   }
+#undef AFQ_EXB_STEP
+  wait_vm_barrier<0>();                           // the tail's tiny loads
+  __syncthreads();
 
-  // ---- epilogue: both planes of each block in LDS (row stride N + 1) ----
+  // ---- epilogue: packed lower triangles of both planes of each block ----
   // tr(Omega Omega) = sum_a Omega_aa^2 + 2 sum_{a<b} Omega_ab Omega_ba: waves
-  // store their lower-triangle tiles (i >= j) and read the transposed partners
-  // of their upper-triangle tiles (i <= j). Branch-free: out-of-range lanes
-  // store to a private trash slot and read a clamped address with a zero
-  // weight. Products of the FP32 accumulators are formed in FP64 (exact).
-  __shared__ float trash[NWAVE * 64];
-  const int S = N + 1;
-  float* pl = reinterpret_cast<float*>(nb == 0 ? lds0 : lds1);
-  float* mine = pl + part * N * S;
-  const float* other = pl + (part ^ 1) * N * S;
+  // store the elements a >= b of their plane at tri(a) + b and read, for their
+  // elements a <= b, the partners (b, a) at tri(b) + a. Branch-free:
+  // out-of-range lanes store to a private trash slot and read a clamped
+  // address with a zero weight. Products of the FP32 accumulators are formed
+  // in FP64 (exact).
+  float* pl = reinterpret_cast<float*>(nb == 0 ? L0 : L1);
+  const int T = N * (N + 1) / 2;
+  float* mine = pl + part * T;
+  const float* other = pl + (part ^ 1) * T;
   float* my_trash = trash + wave * 64 + lane;
   const int lr = lane & 15, lq = lane >> 4;
 #pragma unroll
@@ -197,8 +262,8 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int a = 16 * i + 4 * lq + r;
         // tiles before the last row/column lie inside the block (16 (TM-1) < N)
-        const bool ok = (i < TM - 1 || a < N) && (j < TM - 1 || b < N);
-        float* dst = ok ? mine + a * S + b : my_trash;
+        const bool ok = (i < TM - 1 || a < N) && (i > j || a >= b);
+        float* dst = ok ? mine + (a * (a + 1) / 2 + b) : my_trash;
         *dst = acc[i][j][r];
       }
     }
@@ -206,29 +271,30 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
   double s[5] = {0, 0, 0, 0, 0};   // tr_re, tr_im, rere, imim, reim
   double d_diag = 0.0, d_same = 0.0, d_other = 0.0;
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int j = 0; j < TM; ++j) {
+    const int b = 16 * j + lr;
+    const int tb = b * (b + 1) / 2;
 #pragma unroll
-    for (int j = i; j < TM; ++j) {
-      const int b = 16 * j + lr;
+    for (int i = 0; i <= j; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = 16 * i + 4 * lq + r;
-        const bool ok = (i < TM - 1 || a < N) && (j < TM - 1 || b < N);
-        const int idx = ok ? b * S + a : 0;
+        const bool ok = (j < TM - 1 || b < N) && (i < j || a <= b);
+        const int idx = ok ? tb + a : 0;
         const double v = ok ? (double)acc[i][j][r] : 0.0;
         const double ps = mine[idx], po = other[idx];
         if (i < j) {                       // whole tile above the diagonal: a < b
           d_same += 2.0 * v * ps;
           d_other += v * po;
         } else {
-          const double ws = a < b ? 2.0 : (a == b ? 1.0 : 0.0);
-          const double wo = a < b ? 1.0 : ((a == b && part == 0) ? 1.0 : 0.0);
+          const double ws = a < b ? 2.0 : 1.0;
+          const double wo = (a < b || part == 0) ? 1.0 : 0.0;
           d_same += ws * v * ps;
           d_other += wo * v * po;
           d_diag += a == b ? v : 0.0;
         }
       }
-    }
+  }
   s[part] = d_diag;
   s[2 + part] = d_same;
   s[4] = d_other;
@@ -254,10 +320,13 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
 
 template <int TM>
 int launch_tm(ExchBigArgs g, hipStream_t st) {
-  constexpr int R = Geo<TM>::ROWS;
-  g.rows = round_up(g.n + 16 * TM, 16);
-  AFQ_CHECK(g.rows <= R && g.n <= 16 * TM, AFQ_E_INVALID, "exchange: tile does not cover the block");
-  AFQ_CHECK(g.kp % (2 * KC) == 0, AFQ_E_INVALID, "exchange: contraction length must be a multiple of 64");
+  AFQ_CHECK(g.n <= 16 * TM && g.n > 16 * (TM - 1), AFQ_E_INVALID, "exchange: tile does not cover the block");
+  AFQ_CHECK(2 * g.n <= Geo<TM>::RR, AFQ_E_INVALID, "exchange: staged rows do not cover two blocks");
+  AFQ_CHECK(g.kp % KC == 0 && g.kp >= 2 * KC, AFQ_E_INVALID, "exchange: contraction length must be a multiple of 32");
+  // the last workgroup stages RR rows from its first row: they must lie in the arrays
+  AFQ_CHECK((long)(g.X - 2 + g.X % 2) * g.n + Geo<TM>::RR <= g.rows_a &&
+                (long)(g.nw - 1) * 2 * g.n + Geo<TM>::RR <= g.rows_b,
+            AFQ_E_INVALID, "exchange: packed operands lack padding rows");
   const long nbn = ceil_div(g.X, 2);
   const long grid = nbn * g.nw;
   AFQ_CHECK(grid < (1l << 31), AFQ_E_INVALID, "exchange: grid too large");
@@ -281,3 +350,4 @@ int exchange_big_launch(const ExchBigArgs& g, int prec, hipStream_t st) {
 }
 
 int exch_big_kchunk() { return 2 * KC; }
+int exch_big_kchunk_major() { return KC; }

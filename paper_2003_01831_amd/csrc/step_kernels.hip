@@ -87,10 +87,17 @@ template <> struct PackOut<AFQ_BF16X3> {
 };
 
 // A rows (n, a) of one spin from Lt[n][off + a][k] (ntot x M complex per n)
+// element (row, k) of a packed operand with `rows` rows: row-major, or
+// chunk-major in k-chunks of kcm elements
+__device__ inline long pack_index(long row, int k, int kp, long rows, int kcm) {
+  return kcm ? ((long)(k / kcm) * rows + row) * kcm + k % kcm : row * kp + k;
+}
+
 template <int PREC>
 __global__ void pack_a_kernel(const double2* __restrict__ Lt, int X, int ntot, int M, int off, int n, int np,
-                              int kp, bool real_trial, void* hi, void* lo, int pad) {
-  const long total = ((long)X * np + pad) * kp;
+                              int kp, bool real_trial, void* hi, void* lo, int pad, int kcm) {
+  const long rows = (long)X * np + pad;
+  const long total = rows * kp;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     const int k = (int)(t % kp);
     const long row = t / kp;
@@ -102,15 +109,16 @@ __global__ void pack_a_kernel(const double2* __restrict__ Lt, int X, int ntot, i
       if (k < M) v = src[k].x;
       else if (!real_trial && k < 2 * M) v = src[k - M].y;
     }
-    PackOut<PREC>::put(hi, lo, t, v);
+    PackOut<PREC>::put(hi, lo, pack_index(row, k, kp, rows, kcm), v);
   }
 }
 
 // B rows (w, part, b) of one spin from thetaT[w][off + b][k]
 template <int PREC>
 __global__ void pack_b_kernel(const double2* __restrict__ thT, int nw, int ntot, int M, int off, int n, int np,
-                              int kp, bool real_trial, void* hi, void* lo, int pad) {
-  const long total = ((long)nw * 2 * np + pad) * kp;
+                              int kp, bool real_trial, void* hi, void* lo, int pad, int kcm) {
+  const long rows = (long)nw * 2 * np + pad;
+  const long total = rows * kp;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     const int k = (int)(t % kp);
     const long row = t / kp;
@@ -128,7 +136,7 @@ __global__ void pack_b_kernel(const double2* __restrict__ thT, int nw, int ntot,
         v = part ? x.x : -x.y;
       }
     }
-    PackOut<PREC>::put(hi, lo, t, v);
+    PackOut<PREC>::put(hi, lo, pack_index(row, k, kp, rows, kcm), v);
   }
 }
 
@@ -137,7 +145,7 @@ static int grid_for(long total) { return (int)std::min<long>(std::max<long>(ceil
 int pack_a(int prec, const double2* Lt, int X, int ntot, int M, int off, const PackShape& ps, bool real_trial,
            void* hi, void* lo, hipStream_t st) {
   const long total = ((long)X * ps.np + ps.pad) * ps.kp;
-#define AFQ_PACKA(P) hipLaunchKernelGGL(pack_a_kernel<P>, dim3(grid_for(total)), dim3(256), 0, st, Lt, X, ntot, M, off, ps.n, ps.np, ps.kp, real_trial, hi, lo, ps.pad)
+#define AFQ_PACKA(P) hipLaunchKernelGGL(pack_a_kernel<P>, dim3(grid_for(total)), dim3(256), 0, st, Lt, X, ntot, M, off, ps.n, ps.np, ps.kp, real_trial, hi, lo, ps.pad, ps.kcm)
   if (prec == AFQ_FP64) AFQ_PACKA(AFQ_FP64); else if (prec == AFQ_CFP32) AFQ_PACKA(AFQ_CFP32); else AFQ_PACKA(AFQ_BF16X3);
 #undef AFQ_PACKA
   AFQ_TRY_HIP(hipGetLastError());
@@ -147,7 +155,7 @@ int pack_a(int prec, const double2* Lt, int X, int ntot, int M, int off, const P
 int pack_b(int prec, const double2* thT, int nw, int ntot, int M, int off, const PackShape& ps, bool real_trial,
            void* hi, void* lo, hipStream_t st) {
   const long total = ps.rows_b(nw) * ps.kp;
-#define AFQ_PACKB(P) hipLaunchKernelGGL(pack_b_kernel<P>, dim3(grid_for(total)), dim3(256), 0, st, thT, nw, ntot, M, off, ps.n, ps.np, ps.kp, real_trial, hi, lo, ps.pad)
+#define AFQ_PACKB(P) hipLaunchKernelGGL(pack_b_kernel<P>, dim3(grid_for(total)), dim3(256), 0, st, thT, nw, ntot, M, off, ps.n, ps.np, ps.kp, real_trial, hi, lo, ps.pad, ps.kcm)
   if (prec == AFQ_FP64) AFQ_PACKB(AFQ_FP64); else if (prec == AFQ_CFP32) AFQ_PACKB(AFQ_CFP32); else AFQ_PACKB(AFQ_BF16X3);
 #undef AFQ_PACKB
   AFQ_TRY_HIP(hipGetLastError());

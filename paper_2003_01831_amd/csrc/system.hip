@@ -47,6 +47,7 @@ int system_prepare_pack(afq_system s, int prec) {
     ps.big = exch_big_supported(prec, ps.n);
     ps.np = ps.big ? ps.n : round_up(ps.n, 16);
     ps.pad = ps.big ? exch_big_pad_rows() : 0;
+    ps.kcm = ps.big ? exch_big_kchunk_major() : 0;
     ps.ke = s->real_trial ? s->M : 2 * s->M;
     ps.kp = round_up(ps.ke, ps.big ? exch_big_kchunk() : kc);
     const size_t elems = ((size_t)s->X * ps.np + ps.pad) * ps.kp;
