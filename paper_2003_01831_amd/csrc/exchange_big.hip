@@ -52,6 +52,10 @@ __device__ inline bf16x8 frag(const unsigned char* plane, int row, int lq) {
 
 constexpr int NMAX = 100;           // largest N
 
+// start of row x in the row-padded lower-triangle layout: row y holds
+// round4(y + 1) floats, so every row starts 16-byte aligned
+__host__ __device__ constexpr int tri4(int x) { return 4 * (x / 4 + 1) * (2 * (x / 4) + x % 4); }
+
 template <int TM> struct Geo {
   // rows staged per operand region: both blocks (2N rows) rounded to 16; the
   // tile of the second block overhangs by at most 8 rows into the next region
@@ -61,8 +65,7 @@ template <int TM> struct Geo {
   static constexpr int REG = RR * ROWB;                // bytes per region
   static constexpr int STAGE = 4 * REG + 512;          // A hi, A lo, B hi, B lo + slack
   static constexpr int NE = 16 * TM < NMAX ? 16 * TM : NMAX;
-  static constexpr int TRI = NE * (NE + 1) / 2;        // packed lower triangle of one plane
-  static_assert(2 * TRI * 4 <= STAGE, "epilogue planes must fit one stage");
+  static_assert(2 * tri4(NE) * 4 <= STAGE, "epilogue planes must fit one stage");
 };
 
 // workgroups resident on one XCD form TB n-pairs x TW walkers tiles
@@ -86,11 +89,12 @@ __device__ inline void mma_chunk(f4 (&acc)[TM][TM], const unsigned char* la, con
       nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
       nl = frag(lb + RB, brow + 16 * (j + 1) + lr, lq);
     }
+    // hi*hi for every row tile, then hi*lo: consecutive MFMAs never depend on
+    // each other's result
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
-      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl, acc[i][j], 0, 0, 0);
-    }
+    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl, acc[i][j], 0, 0, 0);
     bh = nh;
     bl = nl;
   }
@@ -107,9 +111,6 @@ __device__ inline void mma_chunk(f4 (&acc)[TM][TM], const unsigned char* la, con
   }
 }
 
-// s_waitcnt vmcnt(W) with expcnt and lgkmcnt left unconstrained. The builtin
-// (not inline asm) lets the compiler's wait-count pass see the wait, so it
-// does not add a conservative vmcnt(0) of its own before the LDS reads.
 // Direct global->LDS loads and their waits, written as inline asm so that the
 // compiler's wait-count pass does not track them: it cannot tell the three
 // ring buffers apart across the loop and would add a conservative vmcnt(0)
@@ -240,17 +241,19 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
   wait_vm_barrier<0>();                           // the tail's tiny loads
   __syncthreads();
 
-  // ---- epilogue: packed lower triangles of both planes of each block ----
+  // ---- epilogue: lower triangles of both planes of each block in LDS ----
   // tr(Omega Omega) = sum_a Omega_aa^2 + 2 sum_{a<b} Omega_ab Omega_ba: waves
-  // store the elements a >= b of their plane at tri(a) + b and read, for their
-  // elements a <= b, the partners (b, a) at tri(b) + a. Branch-free:
+  // store the elements a >= b of their plane and read, for their elements
+  // a <= b, the partners (b, a). Rows are stored with their lengths rounded up
+  // to 4 (row x starts at tri4(x)), so the four partners (b, a..a+3) of a
+  // lane's four accumulator rows are one aligned 16-byte read. Branch-free:
   // out-of-range lanes store to a private trash slot and read a clamped
-  // address with a zero weight. Products of the FP32 accumulators are formed
-  // in FP64 (exact).
+  // address; masked terms are selected to zero (the padding may hold anything).
+  // Products of the FP32 accumulators are formed in FP64 (exact).
   float* pl = reinterpret_cast<float*>(nb == 0 ? L0 : L1);
-  const int T = N * (N + 1) / 2;
-  float* mine = pl + part * T;
-  const float* other = pl + (part ^ 1) * T;
+  const int T4 = tri4(N);
+  float* mine = pl + part * T4;
+  const float* other = pl + (part ^ 1) * T4;
   float* my_trash = trash + wave * 64 + lane;
   const int lr = lane & 15, lq = lane >> 4;
 #pragma unroll
@@ -263,7 +266,7 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
         const int a = 16 * i + 4 * lq + r;
         // tiles before the last row/column lie inside the block (16 (TM-1) < N)
         const bool ok = (i < TM - 1 || a < N) && (i > j || a >= b);
-        float* dst = ok ? mine + (a * (a + 1) / 2 + b) : my_trash;
+        float* dst = ok ? mine + (tri4(a) + b) : my_trash;
         *dst = acc[i][j][r];
       }
     }
@@ -273,27 +276,33 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
 #pragma unroll
   for (int j = 0; j < TM; ++j) {
     const int b = 16 * j + lr;
-    const int tb = b * (b + 1) / 2;
+    const bool okb = j < TM - 1 || b < N;
+    const int tb = tri4(b);
 #pragma unroll
-    for (int i = 0; i <= j; ++i)
+    for (int i = 0; i <= j; ++i) {
+      const int a0 = 16 * i + 4 * lq;
+      const int idx = okb ? tb + a0 : 0;
+      const float4 pm = *reinterpret_cast<const float4*>(mine + idx);
+      const float4 po = *reinterpret_cast<const float4*>(other + idx);
+      const float pmv[4] = {pm.x, pm.y, pm.z, pm.w}, pov[4] = {po.x, po.y, po.z, po.w};
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int a = 16 * i + 4 * lq + r;
-        const bool ok = (j < TM - 1 || b < N) && (i < j || a <= b);
-        const int idx = ok ? tb + a : 0;
+        const int a = a0 + r;
+        const bool ok = okb && (i < j || a <= b);
         const double v = ok ? (double)acc[i][j][r] : 0.0;
-        const double ps = mine[idx], po = other[idx];
+        const double ps = ok ? (double)pmv[r] : 0.0, po_ = ok ? (double)pov[r] : 0.0;
         if (i < j) {                       // whole tile above the diagonal: a < b
           d_same += 2.0 * v * ps;
-          d_other += v * po;
+          d_other += v * po_;
         } else {
           const double ws = a < b ? 2.0 : 1.0;
           const double wo = (a < b || part == 0) ? 1.0 : 0.0;
           d_same += ws * v * ps;
-          d_other += wo * v * po;
+          d_other += wo * v * po_;
           d_diag += a == b ? v : 0.0;
         }
       }
+    }
   }
   s[part] = d_diag;
   s[2 + part] = d_same;
