@@ -213,6 +213,231 @@ __global__ void gemm_splitk_reduce(GemmArgs<T> g, int ksplit, const T* ws) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tiled path for the large contractions (A row-major with k contiguous, B
+// either n-contiguous or k-contiguous): a (32 WM) x (32 WN) tile per 256-thread
+// workgroup, each wave a WM x WN grid of 16 x 16 MFMA tiles. k advances in
+// chunks of 16: the next chunk is fetched from HBM into registers with 16-byte
+// loads while the current one is multiplied out of LDS. LDS planes hold Re and
+// Im separately; rows of k-contiguous planes are padded so that both the
+// fragment reads and the 8-byte stores are bank-conflict free. A complex
+// product is issued as four sweeps over the tile grid (Re += ar br, Re -= ai bi,
+// Im += ar bi, Im += ai br), so consecutive MFMAs never depend on each other.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using V = float4; static constexpr int E = 4; };
+template <> struct Vec16<double> { using V = double2; static constexpr int E = 2; };
+
+template <typename T> __device__ inline typename Vec16<T>::V vmake(const T* t);
+template <> __device__ inline float4 vmake<float>(const float* t) { return make_float4(t[0], t[1], t[2], t[3]); }
+template <> __device__ inline double2 vmake<double>(const double* t) { return make_double2(t[0], t[1]); }
+
+template <typename T> __device__ inline T vget(const typename Vec16<T>::V& v, int e);
+template <> __device__ inline float vget<float>(const float4& v, int e) {
+  return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+}
+template <> __device__ inline double vget<double>(const double2& v, int e) { return e == 0 ? v.x : v.y; }
+
+template <typename T, bool CA, bool CB, bool BT, int WM, int WN>
+__global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs<T> g, int ksplit, int kchunk, T* ws) {
+  using M = Mfma<T>;
+  using Acc = typename M::Acc;
+  using V = typename Vec16<T>::V;
+  constexpr int E = Vec16<T>::E;
+  constexpr int BMt = 32 * WM, BNt = 32 * WN, BKt = 16;
+  constexpr bool CPLX = CA || CB;
+  constexpr int SK = BKt + (sizeof(T) == 4 ? 2 : 1);     // row stride of [row][k] planes
+  constexpr int SN = BNt + (sizeof(T) == 4 ? 16 : 8);    // row stride of [k][n] planes
+  constexpr int PA = CA ? 2 : 1, PB = CB ? 2 : 1;       // planes
+  constexpr int VA = BKt * PA / E;                      // 16-byte vectors per A row chunk
+  constexpr int NLA = BMt * VA / 256;                   // per thread
+  constexpr int VBr = BT ? BKt * PB / E : BNt * PB / E; // vectors per B row (n row if BT, k row else)
+  constexpr int NLB = (BT ? BNt : BKt) * VBr / 256;
+  static_assert(NLA >= 1 && NLB >= 1 && (BMt * VA) % 256 == 0, "tile too small for the loader");
+  __shared__ T As[PA][BMt * SK];
+  __shared__ T Bs[PB][BT ? BNt * SK : BKt * SN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const long b = blockIdx.z / ksplit;
+  const int split = blockIdx.z - (int)b * ksplit;
+  const int m0 = blockIdx.y * BMt, n0 = blockIdx.x * BNt;
+  const T* A = g.A + b * g.sA * PA;
+  const T* B = g.B + b * g.sB * PB;
+  const int kbeg = split * kchunk, kend = min(g.k, kbeg + kchunk);
+
+  V ra[NLA], rb[NLB];
+  // fetch one k-chunk into registers (zero outside the matrices)
+  auto fetch = [&](int kb) {
+#pragma unroll
+    for (int u = 0; u < NLA; ++u) {
+      const int flat = tid + 256 * u, row = flat / VA, v = flat - row * VA;
+      const int gi = m0 + row, gk = kb + v * E / PA;      // first k of the vector
+      const long base = ((long)gi * g.lda + gk) * PA;
+      if (gi < g.m && gk + E / PA <= kend) {
+        ra[u] = *reinterpret_cast<const V*>(A + base);
+      } else {
+        T t[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) t[e] = (gi < g.m && gk + e / PA < kend) ? A[base + e] : T(0);
+        ra[u] = vmake<T>(t);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NLB; ++u) {
+      const int flat = tid + 256 * u, r = flat / VBr, v = flat - r * VBr;
+      if constexpr (BT) {   // B stored n-major: row r = n, vector along k
+        const int gj = n0 + r, gk = kb + v * E / PB;
+        const long base = ((long)gj * g.ldb + gk) * PB;
+        if (gj < g.n && gk + E / PB <= kend) {
+          rb[u] = *reinterpret_cast<const V*>(B + base);
+        } else {
+          T t[E];
+#pragma unroll
+          for (int e = 0; e < E; ++e) t[e] = (gj < g.n && gk + e / PB < kend) ? B[base + e] : T(0);
+          rb[u] = vmake<T>(t);
+        }
+      } else {              // B stored k-major: row r = k, vector along n
+        const int gk = kb + r, gj = n0 + v * E / PB;
+        const long base = ((long)gk * g.ldb + gj) * PB;
+        if (gk < kend && gj + E / PB <= g.n) {
+          rb[u] = *reinterpret_cast<const V*>(B + base);
+        } else {
+          T t[E];
+#pragma unroll
+          for (int e = 0; e < E; ++e) t[e] = (gk < kend && gj + e / PB < g.n) ? B[base + e] : T(0);
+          rb[u] = vmake<T>(t);
+        }
+      }
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int u = 0; u < NLA; ++u) {
+      const int flat = tid + 256 * u, row = flat / VA, v = flat - row * VA;
+      const int k0 = v * E / PA;
+#pragma unroll
+      for (int e = 0; e < E; ++e) As[e % PA][row * SK + k0 + e / PA] = vget<T>(ra[u], e);
+    }
+#pragma unroll
+    for (int u = 0; u < NLB; ++u) {
+      const int flat = tid + 256 * u, r = flat / VBr, v = flat - r * VBr;
+      const int c0 = v * E / PB;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if constexpr (BT) Bs[e % PB][r * SK + c0 + e / PB] = vget<T>(rb[u], e);
+        else Bs[e % PB][r * SN + c0 + e / PB] = vget<T>(rb[u], e);
+      }
+    }
+  };
+
+  Acc acc_r[WM][WN], acc_i[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { acc_r[i][j][r] = 0; acc_i[i][j][r] = 0; }
+
+  const int c16 = lane & 15, kq = lane >> 4;
+  if (kbeg < kend) fetch(kbeg);
+  for (int kb = kbeg; kb < kend; kb += BKt) {
+    __syncthreads();                 // the previous chunk's fragments have been read
+    stash();
+    __syncthreads();
+    if (kb + BKt < kend) fetch(kb + BKt);   // in flight while this chunk is multiplied
+#pragma unroll
+    for (int ks = 0; ks < BKt; ks += 4) {
+      const int kk = ks + kq;
+      T ar[WM], ai[WM], br[WN], bi[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        const int row = wm * 16 * WM + i * 16 + c16;
+        ar[i] = As[0][row * SK + kk];
+        if constexpr (CA) ai[i] = As[1][row * SK + kk];
+      }
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int col = wn * 16 * WN + j * 16 + c16;
+        const int bi_ = BT ? col * SK + kk : kk * SN + col;
+        br[j] = Bs[0][bi_];
+        if constexpr (CB) bi[j] = Bs[1][bi_];
+      }
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) M::mma(acc_r[i][j], ar[i], br[j]);
+      if constexpr (CA && CB) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+          const T nai = -ai[i];
+#pragma unroll
+          for (int j = 0; j < WN; ++j) M::mma(acc_r[i][j], nai, bi[j]);
+        }
+      }
+      if constexpr (CB) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) M::mma(acc_i[i][j], ar[i], bi[j]);
+      }
+      if constexpr (CA) {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WN; ++j) M::mma(acc_i[i][j], ai[i], br[j]);
+      }
+    }
+  }
+
+  if (ksplit > 1) {
+    T* w = ws + ((long)blockIdx.z * g.m * g.n) * 2;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = m0 + wm * 16 * WM + i * 16 + M::row(lane, r);
+          const int gj = n0 + wn * 16 * WN + j * 16 + c16;
+          if (gi < g.m && gj < g.n) {
+            w[2 * ((long)gi * g.n + gj)] = acc_r[i][j][r];
+            w[2 * ((long)gi * g.n + gj) + 1] = CPLX ? acc_i[i][j][r] : T(0);
+          }
+        }
+    return;
+  }
+  T* C = g.C ? g.C + b * g.sC * (g.cC ? 2 : 1) : nullptr;
+  double2* D = g.D ? g.D + b * g.sD : nullptr;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = m0 + wm * 16 * WM + i * 16 + M::row(lane, r);
+        const int gj = n0 + wn * 16 * WN + j * 16 + c16;
+        if (gi >= g.m || gj >= g.n) continue;
+        const double xr = (double)acc_r[i][j][r], xi = CPLX ? (double)acc_i[i][j][r] : 0.0;
+        double vr = g.ar * xr - g.ai * xi;
+        double vi = g.ar * xi + g.ai * xr;
+        if (C) {
+          const long ci = (long)gi * g.ldc + gj;
+          if (g.br != 0.0 || g.bi != 0.0) {
+            double cr, cim;
+            if (g.cC) { cr = C[2 * ci]; cim = C[2 * ci + 1]; } else { cr = C[ci]; cim = 0.0; }
+            vr += g.br * cr - g.bi * cim;
+            vi += g.br * cim + g.bi * cr;
+          }
+          if (g.cC) { C[2 * ci] = (T)vr; C[2 * ci + 1] = (T)vi; } else { C[ci] = (T)vr; }
+        }
+        if (D) {
+          double2* d = D + (long)gi * g.ldd + gj;
+          d->x += vr;
+          d->y += vi;
+        }
+      }
+}
+
 // split-k workspace, one per (stream, element type), grown on demand. Streams
 // that run concurrently (the branches of a batch) therefore never share one.
 // Entries live until gemm_release_workspace(stream) or the process ends (never
@@ -247,11 +472,63 @@ template <typename T> GemmArgs<T> gemm_args() {
   return g;
 }
 
+// launch of the tiled kernel for one (WM, WN) configuration
+template <typename T, bool CA, bool CB, bool BT, int WM, int WN>
+void launch_tile(const GemmArgs<T>& g, dim3 grid, int ksplit, int kchunk, T* ws, hipStream_t st) {
+  hipLaunchKernelGGL((gemm_tile_kernel<T, CA, CB, BT, WM, WN>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
+}
+
+template <typename T, bool CA, bool CB, bool BT>
+void launch_tile_cfg(const GemmArgs<T>& g, int cfg, dim3 grid, int ksplit, int kchunk, T* ws, hipStream_t st) {
+  switch (cfg) {
+    case 0: launch_tile<T, CA, CB, BT, 2, 2>(g, grid, ksplit, kchunk, ws, st); break;
+    case 1: launch_tile<T, CA, CB, BT, 2, 4>(g, grid, ksplit, kchunk, ws, st); break;
+    case 2: launch_tile<T, CA, CB, BT, 4, 2>(g, grid, ksplit, kchunk, ws, st); break;
+    default:
+      if constexpr (sizeof(T) == 4) launch_tile<T, CA, CB, BT, 4, 4>(g, grid, ksplit, kchunk, ws, st);
+      break;   // not chosen for double (tile_config)
+  }
+}
+
+constexpr int kTileWM[4] = {2, 2, 4, 4}, kTileWN[4] = {2, 4, 2, 4};
+
+// the tiled kernel applies: A untransposed (k contiguous), B untransposed or
+// transposed, no conjugation, 16-byte aligned rows and bases
+template <typename T> bool tile_applies(const GemmArgs<T>& g) {
+  if (g.opA != OP_N || (g.opB != OP_N && g.opB != OP_T)) return false;
+  const long pa = g.cA ? 2 : 1, pb = g.cB ? 2 : 1, sz = sizeof(T);
+  const auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  if (!al(g.A) || !al(g.B)) return false;
+  if ((g.lda * pa * sz) % 16 || (g.ldb * pb * sz) % 16) return false;
+  if (g.batch > 1 && ((g.sA * pa * sz) % 16 || (g.sB * pb * sz) % 16)) return false;
+  return g.m >= 32 && g.n >= 32 && g.k >= 16;
+}
+
+// tile configuration with the least padded work; double precision stops at
+// 128 x 64 (its accumulators take twice the registers)
+template <typename T> int tile_config(const GemmArgs<T>& g) {
+  int best = -1;
+  long best_area = 0;
+  for (int c = 0; c < 4; ++c) {
+    if (sizeof(T) == 8 && c == 3) continue;
+    const long bm = 32 * kTileWM[c], bn = 32 * kTileWN[c];
+    const long area = ceil_div(g.m, (int)bm) * bm * ceil_div(g.n, (int)bn) * bn;
+    if (best < 0 || area < best_area || (area == best_area && bm * bn > 32L * kTileWM[best] * 32 * kTileWN[best])) {
+      best = c;
+      best_area = area;
+    }
+  }
+  return best;
+}
+
 template <typename T> int gemm(const GemmArgs<T>& g, hipStream_t st) {
   AFQ_CHECK(g.m >= 0 && g.n >= 0 && g.k >= 0 && g.batch >= 0, AFQ_E_INVALID, "gemm: negative size");
   if (g.m == 0 || g.n == 0 || g.batch == 0) return AFQ_OK;
   AFQ_CHECK(g.A && g.B && (g.C || g.D), AFQ_E_INVALID, "gemm: null operand");
-  const int tiles_m = ceil_div(g.m, BM), tiles_n = ceil_div(g.n, BN);
+  const bool tiled = tile_applies(g);
+  const int cfg = tiled ? tile_config(g) : -1;
+  const int bm = tiled ? 32 * kTileWM[cfg] : BM, bn = tiled ? 32 * kTileWN[cfg] : BN;
+  const int tiles_m = ceil_div(g.m, bm), tiles_n = ceil_div(g.n, bn);
   AFQ_CHECK(tiles_m <= 65535, AFQ_E_INVALID, "gemm: m too large");
   // split k when few output tiles share a long contraction
   int ksplit = 1;
@@ -274,10 +551,25 @@ template <typename T> int gemm(const GemmArgs<T>& g, hipStream_t st) {
     ws = w.as<T>();
   }
   dim3 grid(tiles_n, tiles_m, g.batch * ksplit);
-  if (g.cA && g.cB) hipLaunchKernelGGL((gemm_mfma_kernel<T, true, true>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
-  else if (g.cA) hipLaunchKernelGGL((gemm_mfma_kernel<T, true, false>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
-  else if (g.cB) hipLaunchKernelGGL((gemm_mfma_kernel<T, false, true>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
-  else hipLaunchKernelGGL((gemm_mfma_kernel<T, false, false>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
+  if (tiled) {
+    const bool bt = g.opB == OP_T;
+#define AFQ_TILE(CA_, CB_)                                                             \
+  (bt ? launch_tile_cfg<T, CA_, CB_, true>(g, cfg, grid, ksplit, kchunk, ws, st)       \
+      : launch_tile_cfg<T, CA_, CB_, false>(g, cfg, grid, ksplit, kchunk, ws, st))
+    if (g.cA && g.cB) AFQ_TILE(true, true);
+    else if (g.cA) AFQ_TILE(true, false);
+    else if (g.cB) AFQ_TILE(false, true);
+    else AFQ_TILE(false, false);
+#undef AFQ_TILE
+  } else if (g.cA && g.cB) {
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, true, true>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
+  } else if (g.cA) {
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, true, false>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
+  } else if (g.cB) {
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, false, true>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
+  } else {
+    hipLaunchKernelGGL((gemm_mfma_kernel<T, false, false>), grid, dim3(256), 0, st, g, ksplit, kchunk, ws);
+  }
   AFQ_TRY_HIP(hipGetLastError());
   if (ksplit > 1) {
     const long total = (long)g.m * g.n * g.batch;
