@@ -52,9 +52,18 @@ __device__ inline bf16x8 frag(const unsigned char* plane, int row, int lq) {
 
 constexpr int NMAX = 100;           // largest N
 
-// start of row x in the row-padded lower-triangle layout: row y holds
-// round4(y + 1) floats, so every row starts 16-byte aligned
-__host__ __device__ constexpr int tri4(int x) { return 4 * (x / 4 + 1) * (2 * (x / 4) + x % 4); }
+// Start (in floats) of row x of the padded lower-triangle layout used by the
+// epilogue. Row y holds L(y) = 4 + 32 ceil((y - 3) / 32) floats (4 for y <= 3),
+// at least y + 1, a multiple of 4 and congruent to 4 mod 32, so that
+//   * every row starts 16-byte aligned (one 16-byte read fetches a lane's four
+//     partners),
+//   * row x starts at 4x mod 32 words: the 8 lanes of a 16-byte read (8
+//     consecutive rows) hit 8 different 4-bank groups, and rows x and x + 4
+//     (the two 16-lane halves of a 4-byte store) start 16 banks apart.
+__host__ __device__ constexpr int trow(int x) {
+  return x < 4 ? 4 * x
+               : 4 * x + 32 * ((x - 4) + 16 * ((x - 4) >> 5) * (((x - 4) >> 5) - 1) + ((x - 4) >> 5) * ((x - 4) & 31));
+}
 
 template <int TM> struct Geo {
   // rows staged per operand region: both blocks (2N rows) rounded to 16; the
@@ -65,7 +74,7 @@ template <int TM> struct Geo {
   static constexpr int REG = RR * ROWB;                // bytes per region
   static constexpr int STAGE = 4 * REG + 512;          // A hi, A lo, B hi, B lo + slack
   static constexpr int NE = 16 * TM < NMAX ? 16 * TM : NMAX;
-  static_assert(2 * tri4(NE) * 4 <= STAGE, "epilogue planes must fit one stage");
+  static_assert(2 * trow(NE) * 4 <= STAGE, "epilogue planes must fit one stage");
 };
 
 // workgroups resident on one XCD form TB n-pairs x TW walkers tiles
@@ -244,14 +253,14 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
   // ---- epilogue: lower triangles of both planes of each block in LDS ----
   // tr(Omega Omega) = sum_a Omega_aa^2 + 2 sum_{a<b} Omega_ab Omega_ba: waves
   // store the elements a >= b of their plane and read, for their elements
-  // a <= b, the partners (b, a). Rows are stored with their lengths rounded up
-  // to 4 (row x starts at tri4(x)), so the four partners (b, a..a+3) of a
-  // lane's four accumulator rows are one aligned 16-byte read. Branch-free:
+  // a <= b, the partners (b, a). Rows are padded (row x starts at trow(x)), so
+  // the four partners (b, a..a+3) of a lane's four accumulator rows are one
+  // aligned 16-byte read and neither stores nor reads conflict on banks. Branch-free:
   // out-of-range lanes store to a private trash slot and read a clamped
   // address; masked terms are selected to zero (the padding may hold anything).
   // Products of the FP32 accumulators are formed in FP64 (exact).
   float* pl = reinterpret_cast<float*>(nb == 0 ? L0 : L1);
-  const int T4 = tri4(N);
+  const int T4 = trow(N);
   float* mine = pl + part * T4;
   const float* other = pl + (part ^ 1) * T4;
   float* my_trash = trash + wave * 64 + lane;
@@ -266,7 +275,7 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
         const int a = 16 * i + 4 * lq + r;
         // tiles before the last row/column lie inside the block (16 (TM-1) < N)
         const bool ok = (i < TM - 1 || a < N) && (i > j || a >= b);
-        float* dst = ok ? mine + (tri4(a) + b) : my_trash;
+        float* dst = ok ? mine + (trow(a) + b) : my_trash;
         *dst = acc[i][j][r];
       }
     }
@@ -277,7 +286,7 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
   for (int j = 0; j < TM; ++j) {
     const int b = 16 * j + lr;
     const bool okb = j < TM - 1 || b < N;
-    const int tb = tri4(b);
+    const int tb = trow(b);
 #pragma unroll
     for (int i = 0; i <= j; ++i) {
       const int a0 = 16 * i + 4 * lq;

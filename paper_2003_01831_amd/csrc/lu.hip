@@ -23,13 +23,31 @@ struct GjShared {
   double d;
 };
 
+// Row and column of register slot j (element e = tid + NT j) without an
+// integer division: r = mulhi(e, m) with m = ceil(2^32 / n) is exact for the
+// e < 2^16, n <= 128 used here. Rows of empty slots (e >= n^2) are >= n.
+struct SlotMap {
+  unsigned m;
+  int n;
+  __device__ explicit SlotMap(int n_) : m((unsigned)((0x100000000ull + (unsigned)n_ - 1) / (unsigned)n_)), n(n_) {}
+  __device__ int row(int e) const { return (int)__umulhi((unsigned)e, m); }
+  __device__ int col(int e, int r) const { return e - r * n; }
+};
+
 // Gauss-Jordan elimination on the register-resident matrix. pivoting=false
-// takes pivot row k at step k (used for the triangular factor of QR).
-template <int NT, int EPT>
-__device__ void gauss_jordan(double2 (&a)[EPT], int n, bool pivoting, GjShared<NT>& sh,
-                             double2& logdet) {
+// takes pivot row k at step k (used for the triangular factor of QR). With
+// FULL=false only the determinant is wanted: each step updates just the rows
+// not yet used as pivots, right of the pivot column (an LU factorisation in
+// place, a third of the work); the matrix left behind is not an inverse.
+// (FULL is a template parameter so that each kernel carries one update loop.)
+template <int NT, int EPT, bool FULL>
+__device__ void gauss_jordan(double2 (&a)[EPT], int n, bool pivoting, GjShared<NT>& sh, double2& logdet) {
+  static_assert(EPT <= 32, "slot mask");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nn = n * n;
+  const SlotMap sm(n);
+  unsigned live = 0;   // bit j: slot j's row has not been a pivot row yet
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) live |= (sm.row(tid + NT * j) < n ? 1u : 0u) << j;
   for (int k = 0; k < n; ++k) {
     int p = k;
     if (pivoting) {
@@ -37,13 +55,10 @@ __device__ void gauss_jordan(double2 (&a)[EPT], int n, bool pivoting, GjShared<N
       int bi = 1 << 30;
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
-        const int e = tid + NT * j;
-        if (e < nn) {
-          const int r = e / n, c = e - r * n;
-          if (c == k && !sh.used[r]) {
-            const double v = cabs2(a[j]);
-            if (v > best || (v == best && r < bi)) { best = v; bi = r; }
-          }
+        const int e = tid + NT * j, r = sm.row(e);
+        if (sm.col(e, r) == k && ((live >> j) & 1)) {
+          const double v = cabs2(a[j]);
+          if (v > best || (v == best && r < bi)) { best = v; bi = r; }
         }
       }
 #pragma unroll
@@ -74,9 +89,8 @@ __device__ void gauss_jordan(double2 (&a)[EPT], int n, bool pivoting, GjShared<N
     }
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-      const int e = tid + NT * j;
-      if (e < nn) {
-        const int r = e / n, c = e - r * n;
+      const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
+      if (r < n) {
         if (r == p) sh.rowp[c] = a[j];
         if (c == k) sh.colk[r] = a[j];
       }
@@ -90,26 +104,36 @@ __device__ void gauss_jordan(double2 (&a)[EPT], int n, bool pivoting, GjShared<N
     }
     const double2 ipiv = cdiv(make_double2(1.0, 0.0), piv);
     logdet = cadd(logdet, clog(piv));
+    if constexpr (FULL) {
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int e = tid + NT * j;
-      if (e < nn) {
-        const int r = e / n, c = e - r * n;
-        const double2 rp = c == k ? ipiv : cmul(sh.rowp[c], ipiv);
-        if (r == p) {
-          a[j] = rp;
-        } else {
-          const double2 base = c == k ? make_double2(0.0, 0.0) : a[j];
-          a[j] = csub(base, cmul(sh.colk[r], rp));
+      for (int j = 0; j < EPT; ++j) {
+        const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
+        if (r < n) {
+          const double2 rp = c == k ? ipiv : cmul(sh.rowp[c], ipiv);
+          if (r == p) {
+            a[j] = rp;
+          } else {
+            const double2 base = c == k ? make_double2(0.0, 0.0) : a[j];
+            a[j] = csub(base, cmul(sh.colk[r], rp));
+          }
         }
       }
+    } else {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
+        if (((live >> j) & 1) && r != p && c > k) a[j] = csub(a[j], cmul(sh.colk[r], cmul(sh.rowp[c], ipiv)));
+      }
     }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j)
+      if (sm.row(tid + NT * j) == p) live &= ~(1u << j);
     __syncthreads();
   }
 }
 
-template <int NT, int EPT>
-__global__ __launch_bounds__(NT) void gj_kernel(const double2* __restrict__ S, long stride, int n,
+template <int NT, int EPT, bool FULL>
+__device__ void gj_body(const double2* __restrict__ S, long stride, int n,
                                                 double2* __restrict__ inv, double2* __restrict__ logdet,
                                                 long ld_logdet, int* __restrict__ sing, long ld_sing) {
   __shared__ GjShared<NT> sh;
@@ -125,7 +149,7 @@ __global__ __launch_bounds__(NT) void gj_kernel(const double2* __restrict__ S, l
   if (tid == 0) sh.sing = 0;
   __syncthreads();
   double2 ld = make_double2(0.0, 0.0);
-  gauss_jordan<NT, EPT>(a, n, true, sh, ld);
+  gauss_jordan<NT, EPT, FULL>(a, n, true, sh, ld);
   if (tid == 0) {
     // parity of the pivot permutation k -> perm[k]; inverse permutation q
     int parity = 0;
@@ -142,7 +166,7 @@ __global__ __launch_bounds__(NT) void gj_kernel(const double2* __restrict__ S, l
     sing[b * ld_sing] = sh.sing;
   }
   __syncthreads();
-  if (inv) {
+  if (FULL) {
     // inverse element (a, b) = M[perm[a]][q[b]]: thread with M[r][c] writes (q[r], perm[c])
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
@@ -170,6 +194,7 @@ __global__ __launch_bounds__(NT) void chol_inv_kernel(const double2* __restrict_
   }
   if (tid == 0) sh.sing = 0;
   __syncthreads();
+  const SlotMap sm(n);
   double ldr = 0.0;
   // right-looking Cholesky G = R^H R on the upper triangle
   for (int k = 0; k < n; ++k) {
@@ -187,36 +212,27 @@ __global__ __launch_bounds__(NT) void chol_inv_kernel(const double2* __restrict_
     ldr += log(d);
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-      const int e = tid + NT * j;
-      if (e < nn) {
-        const int r = e / n, c = e - r * n;
-        if (r == k && c >= k) {
-          a[j] = c == k ? make_double2(d, 0.0) : cscale(a[j], id);
-          sh.rowp[c] = a[j];
-        }
+      const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
+      if (r == k && c >= k) {
+        a[j] = c == k ? make_double2(d, 0.0) : cscale(a[j], id);
+        sh.rowp[c] = a[j];
       }
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-      const int e = tid + NT * j;
-      if (e < nn) {
-        const int r = e / n, c = e - r * n;
-        if (r > k && c >= r) a[j] = csub(a[j], cmul(cconj(sh.rowp[r]), sh.rowp[c]));
-      }
+      const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
+      if (r > k && r < n && c >= r) a[j] = csub(a[j], cmul(cconj(sh.rowp[r]), sh.rowp[c]));
     }
   }
 #pragma unroll
   for (int j = 0; j < EPT; ++j) {
-    const int e = tid + NT * j;
-    if (e < nn) {
-      const int r = e / n, c = e - r * n;
-      if (r > c) a[j] = make_double2(0.0, 0.0);
-    }
+    const int e = tid + NT * j, r = sm.row(e);
+    if (r < n && r > sm.col(e, r)) a[j] = make_double2(0.0, 0.0);
   }
   __syncthreads();
   double2 ld = make_double2(0.0, 0.0);
-  gauss_jordan<NT, EPT>(a, n, false, sh, ld);
+  gauss_jordan<NT, EPT, true>(a, n, false, sh, ld);
   if (tid == 0) {
     logdet[b * ld_logdet] = make_double2(ldr, 0.0);
     sing[b * ld_sing] = sh.sing;
@@ -228,6 +244,17 @@ __global__ __launch_bounds__(NT) void chol_inv_kernel(const double2* __restrict_
   }
 }
 
+// Gauss-Jordan inverse + log det, and log det only (LU elimination)
+template <int NT, int EPT>
+__global__ __launch_bounds__(NT) void gj_kernel_full(const double2* S, long stride, int n, double2* inv,
+                                                     double2* logdet, long ld_logdet, int* sing, long ld_sing) {
+  gj_body<NT, EPT, true>(S, stride, n, inv, logdet, ld_logdet, sing, ld_sing);
+}
+template <int NT, int EPT>
+__global__ __launch_bounds__(NT) void gj_kernel_det(const double2* S, long stride, int n, double2* inv,
+                                                    double2* logdet, long ld_logdet, int* sing, long ld_sing) {
+  gj_body<NT, EPT, false>(S, stride, n, inv, logdet, ld_logdet, sing, ld_sing);
+}
 }  // namespace
 
 #define AFQ_SMALL_DISPATCH(KERNEL, ...)                                                    \
@@ -247,7 +274,8 @@ int lu_inverse(const double2* S, long stride, int n, int batch, double2* inv, do
   AFQ_CHECK(n >= 1 && n <= NMAX, AFQ_E_UNSUPPORTED, "lu_inverse: n must be in [1, 128]");
   AFQ_CHECK(stride >= (long)n * n, AFQ_E_INVALID, "lu_inverse: stride < n*n");
   if (batch <= 0) return AFQ_OK;
-  AFQ_SMALL_DISPATCH(gj_kernel, S, stride, n, inv, logdet, ld_logdet, sing, ld_sing);
+  if (inv) AFQ_SMALL_DISPATCH(gj_kernel_full, S, stride, n, inv, logdet, ld_logdet, sing, ld_sing);
+  else AFQ_SMALL_DISPATCH(gj_kernel_det, S, stride, n, inv, logdet, ld_logdet, sing, ld_sing);
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }
