@@ -249,10 +249,9 @@ __global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs<T> g, int kspli
   constexpr int SN = BNt + (sizeof(T) == 4 ? 16 : 8);    // row stride of [k][n] planes
   constexpr int PA = CA ? 2 : 1, PB = CB ? 2 : 1;       // planes
   constexpr int VA = BKt * PA / E;                      // 16-byte vectors per A row chunk
-  constexpr int NLA = BMt * VA / 256;                   // per thread
+  constexpr int TLA = BMt * VA, NLA = (TLA + 255) / 256;   // vectors per chunk, per thread
   constexpr int VBr = BT ? BKt * PB / E : BNt * PB / E; // vectors per B row (n row if BT, k row else)
-  constexpr int NLB = (BT ? BNt : BKt) * VBr / 256;
-  static_assert(NLA >= 1 && NLB >= 1 && (BMt * VA) % 256 == 0, "tile too small for the loader");
+  constexpr int TLB = (BT ? BNt : BKt) * VBr, NLB = (TLB + 255) / 256;
   __shared__ T As[PA][BMt * SK];
   __shared__ T Bs[PB][BT ? BNt * SK : BKt * SN];
 
@@ -271,6 +270,7 @@ __global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs<T> g, int kspli
 #pragma unroll
     for (int u = 0; u < NLA; ++u) {
       const int flat = tid + 256 * u, row = flat / VA, v = flat - row * VA;
+      if (TLA % 256 && flat >= TLA) break;
       const int gi = m0 + row, gk = kb + v * E / PA;      // first k of the vector
       const long base = ((long)gi * g.lda + gk) * PA;
       if (gi < g.m && gk + E / PA <= kend) {
@@ -285,6 +285,7 @@ __global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs<T> g, int kspli
 #pragma unroll
     for (int u = 0; u < NLB; ++u) {
       const int flat = tid + 256 * u, r = flat / VBr, v = flat - r * VBr;
+      if (TLB % 256 && flat >= TLB) break;
       if constexpr (BT) {   // B stored n-major: row r = n, vector along k
         const int gj = n0 + r, gk = kb + v * E / PB;
         const long base = ((long)gj * g.ldb + gk) * PB;
@@ -314,6 +315,7 @@ __global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs<T> g, int kspli
 #pragma unroll
     for (int u = 0; u < NLA; ++u) {
       const int flat = tid + 256 * u, row = flat / VA, v = flat - row * VA;
+      if (TLA % 256 && flat >= TLA) break;
       const int k0 = v * E / PA;
 #pragma unroll
       for (int e = 0; e < E; ++e) As[e % PA][row * SK + k0 + e / PA] = vget<T>(ra[u], e);
@@ -321,6 +323,7 @@ __global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs<T> g, int kspli
 #pragma unroll
     for (int u = 0; u < NLB; ++u) {
       const int flat = tid + 256 * u, r = flat / VBr, v = flat - r * VBr;
+      if (TLB % 256 && flat >= TLB) break;
       const int c0 = v * E / PB;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -490,6 +493,7 @@ void launch_tile_cfg(const GemmArgs<T>& g, int cfg, dim3 grid, int ksplit, int k
   }
 }
 
+// (WM, WN) of the tile configurations
 constexpr int kTileWM[4] = {2, 2, 4, 4}, kTileWN[4] = {2, 4, 2, 4};
 
 // the tiled kernel applies: A untransposed (k contiguous), B untransposed or
