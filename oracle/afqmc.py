@@ -158,9 +158,16 @@ def local_energy_half(ht, Lt, T, W, n_up, n_dn, e_core=0.0):
 # ---------------------------------------------------------------------------
 # One-body propagator pieces (Hubbard-Stratonovich with the force-bias shift)
 # ---------------------------------------------------------------------------
-def force_bias_shift(vbar, dt):
-    """xbar_n = -i sqrt(dt) vbar_n."""
-    return -1j * np.sqrt(dt) * vbar
+def force_bias_shift(vbar, dt, cap=0.0):
+    """xbar_n = -i sqrt(dt) vbar_n. With cap > 0 every xbar_n of modulus above
+    cap is scaled back to modulus cap, its phase kept (the usual force-bias cap
+    of production phaseless AFQMC; the paper does not discuss it)."""
+    xbar = -1j * np.sqrt(dt) * np.asarray(vbar)
+    if cap > 0.0:
+        mag = np.abs(xbar)
+        big = mag > cap
+        xbar = np.where(big, xbar * (cap / np.where(big, mag, 1.0)), xbar)
+    return xbar
 
 
 def hs_operator(chol, x, xbar, dt):
@@ -184,16 +191,22 @@ def prepare(h1, chol, phi_t, n_up, n_dn, dt):
 
 
 def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
-        e_shift=0.0, order=6, e_core=0.0, energy="half", record_walkers=False, pre=None):
+        e_shift=0.0, order=6, e_core=0.0, energy="half", record_walkers=False, pre=None,
+        fb_cap=0.0, w_cap=0.0, comb_every=0, comb_xi=None):
     """Run len(fields) steps. fields[k, w, n] are the standard-normal HS fields.
     `pre` may hold prepare(h1, chol, phi_t, n_up, n_dn, dt) computed beforehand.
 
     Per step k (energy and force bias both at the start-of-step walker W_k):
       1. Theta, E_L (E1, EJ, EK) and vbar at W_k;
          E_mix(k) = sum_w w_k Re E_L / sum_w w_k with the pre-update weights.
-      2. For live walkers: W' = B1 T_K(A) B1 W, r = O'/O, phaseless weight.
-         A walker whose weight becomes 0 (or non-finite) is frozen (W not updated).
+      2. For live walkers: W' = B1 T_K(A) B1 W, r = O'/O, phaseless weight
+         (the force bias capped at fb_cap and the new weight at w_cap when
+         these are positive). A walker whose weight becomes 0 (or non-finite)
+         is frozen (W not updated).
       3. QR of the live walkers when (k+1) % qr_every == 0.
+      4. Population control when comb_every > 0 and (k+1) % comb_every == 0:
+         comb() with the next uniform number of comb_xi. out["weights"][k]
+         holds the weights before this step's comb.
     """
     M = h1.shape[0]
     nw = W0.shape[0]
@@ -231,7 +244,7 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
             if not alive[i]:
                 continue
             x = fields[k, i]
-            xbar = force_bias_shift(vb[i], dt)
+            xbar = force_bias_shift(vb[i], dt, fb_cap)
             A = hs_operator(chol, x, xbar, dt)
             Wn = B1 @ taylor_apply(A, B1 @ W[i], order)
             _, logOn = theta(phi_t, Wn, n_up, n_dn)
@@ -246,6 +259,8 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
                 w[i] = 0.0
                 alive[i] = False
                 continue
+            if w_cap > 0.0:
+                wn = min(wn, w_cap)
             w[i] = wn
             W[i] = Wn
             logO[i] = logOn
@@ -258,10 +273,49 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
                     W[i][:, b] = Q
                     logO[i] -= np.sum(np.log(np.diag(R).real))
         out["weights"][k] = w
+        if comb_every > 0 and (k + 1) % comb_every == 0:
+            src, wnew, _ = comb(w, comb_xi[len(out.setdefault("comb_src", []))])
+            out["comb_src"].append(src)
+            W = W[src].copy()
+            logO = logO[src].copy()
+            w = np.full(nw, wnew)
+            alive = np.ones(nw, dtype=bool)
         if record_walkers:
             out["walkers"][k] = W
     out.update(W=W, w=w, logO=logO, alive=alive)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Population control (production bookkeeping around the walk; the paper only
+# cites the method, so these follow the standard phaseless-AFQMC practice)
+# ---------------------------------------------------------------------------
+def comb(weights, xi):
+    """Systematic resampling ("comb") of a weighted population of n walkers
+    into n walkers of equal weight W/n, W = sum of the weights.
+
+    The running sums C_i = w_0 + ... + w_i are formed left to right; tooth k of
+    the comb sits at u_k = (k + xi) W / n (0 <= xi < 1) and selects the walker
+    i with C_{i-1} <= u_k < C_i. A tooth that rounding puts at or beyond W
+    selects the last walker of positive weight. Returns (source index of every
+    new walker, the new common weight W/n, W)."""
+    w = np.asarray(weights, dtype=np.float64)
+    n = w.size
+    cum = np.cumsum(w)
+    total = cum[-1]
+    if not total > 0.0:
+        raise ValueError("comb: no walker has positive weight")
+    step = total / n
+    u = (np.arange(n, dtype=np.float64) + xi) * step
+    src = np.searchsorted(cum, u, side="right")
+    last = int(np.nonzero(w > 0.0)[0][-1])
+    return np.minimum(src, last), step, total
+
+
+def eshift_update(e_est, w_total, w_target, dt, gain_steps):
+    """Population-control energy shift: E_shift = E_est - ln(W / W_target) / (g dt)
+    with g = gain_steps, pulling the total weight W back toward W_target."""
+    return e_est - np.log(w_total / w_target) / (gain_steps * dt)
 
 
 def energy(h1, chol, phi_t, n_up, n_dn, W, weights, e_core=0.0, form="half"):
