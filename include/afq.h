@@ -125,6 +125,36 @@ int afq_walkers_set(afq_walkers w, const double *W, const double *weights,
 int afq_walkers_stats(afq_walkers w, int *n_alive, int64_t *n_killed);
 
 /* ------------------------------------------------------------------------ */
+/* Population control. The paper cites the phaseless method (Section          */
+/* "Auxiliary Field Quantum Monte Carlo") without its production controls;   */
+/* these are the standard ones of that method.                                */
+/* ------------------------------------------------------------------------ */
+
+/* Controls applied by later afq_step / afq_batch_step calls on this walker set
+ * (a batch re-captures its graph when they change): fb_cap > 0 scales every force-bias shift xbar_n whose modulus
+ * exceeds fb_cap back to modulus fb_cap, phase kept; w_cap > 0 caps every
+ * updated weight at w_cap. 0 switches a control off (the default). Negative or
+ * non-finite values give AFQ_E_INVALID. */
+int afq_walkers_set_controls(afq_walkers w, double fb_cap, double w_cap);
+
+/* Systematic resampling ("comb") of the n walkers into n walkers of equal
+ * weight W/n, W = sum of the weights: with running sums C_i = w_0 + ... + w_i
+ * formed in walker order, tooth k at u_k = (k + xi) W / n takes a copy of the
+ * first walker i with C_i > u_k (a tooth at or beyond W takes the last walker
+ * of positive weight); dead walkers get no copies and every new walker is
+ * alive. xi: uniform number in [0, 1). src_out (host, n ints, may be NULL)
+ * receives the source walker of every new walker, total_out (host, may be
+ * NULL) receives W. Synchronises the system stream. W <= 0 gives AFQ_E_STATE
+ * and leaves the walkers unchanged. */
+int afq_walkers_comb(afq_walkers w, double xi, int32_t *src_out, double *total_out);
+
+/* Energy-shift feedback of the population: *e_shift_out = e_est -
+ * ln(w_total / w_target) / (gain_steps dt). Host arithmetic only. Non-positive
+ * weights, dt or gain give AFQ_E_INVALID. */
+int afq_eshift_update(double e_est, double w_total, double w_target, double dt, double gain_steps,
+                      double *e_shift_out);
+
+/* ------------------------------------------------------------------------ */
 /* Hot path.                                                                  */
 /* ------------------------------------------------------------------------ */
 
@@ -202,7 +232,8 @@ int afq_batch_create(afq_batch *out, int n, const afq_system *systems,
  * (afq_autotune), runs eager steps up to a multiple of qr_every, then captures
  * one HIP graph of qr_every steps (or one step when qr_every is 0) whose
  * concurrent branches are the systems; later calls replay it (a change of dt,
- * seed, qr_every, e_shift, order or precision captures a new graph). e_shift: n float64
+ * seed, qr_every, e_shift, order, precision or walker controls captures a new
+ * graph). e_shift: n float64
  * (host). emix_out: n*n_steps float64 device array, system-major. */
 int afq_batch_step(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_every,
                    const double *e_shift, int taylor_order, double *emix_out);

@@ -142,6 +142,17 @@ class Walkers:
         check(self.lib.afq_autotune(self.sys.handle, self.handle, int(reps), C.cast(ch, C.c_void_p)))
         return int(ch[0]), int(ch[1])
 
+    def set_controls(self, fb_cap=0.0, w_cap=0.0):
+        """Force-bias and weight caps for later steps (0 = off)."""
+        check(self.lib.afq_walkers_set_controls(self.handle, float(fb_cap), float(w_cap)))
+
+    def comb(self, xi):
+        """Systematic resampling to equal weights; returns (source indices, total weight)."""
+        src = np.zeros(self.nw, dtype=np.int32)
+        tot = C.c_double()
+        check(self.lib.afq_walkers_comb(self.handle, float(xi), src.ctypes.data_as(C.c_void_p), C.byref(tot)))
+        return src, float(tot.value)
+
     def set_exchange_variant(self, spin, variant):
         check(self.lib.afq_exchange_variant(self.handle, int(spin), int(variant)))
 
@@ -166,6 +177,13 @@ def energy_backward(system: System, walkers: Walkers, scale=1.0, want=("h1", "ch
           if "walkers" in want else None)
     check(system.lib.afq_energy_backward(system.handle, walkers.handle, float(scale), _ptr(dh), _ptr(dl), _ptr(dw)))
     return dh, dl, dw
+
+
+def eshift_update(e_est, w_total, w_target, dt, gain_steps):
+    out = C.c_double()
+    check(_lib.load().afq_eshift_update(float(e_est), float(w_total), float(w_target), float(dt), float(gain_steps),
+                                        C.byref(out)))
+    return float(out.value)
 
 
 def fields_generate(seed, n_steps, n_walkers, n_chol, step0=0, sys_id=0):

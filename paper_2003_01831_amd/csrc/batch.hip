@@ -23,6 +23,7 @@ struct afq_batch_s {
   int qr_every = -1, order = 0, cycle = 0, prec = -1;
   bool tuned = false;
   std::vector<double> e_shift;
+  std::vector<double> caps;   // (fb_cap, w_cap) of every walker set, baked into the graph
   DevBuf emix_cycle;   // n x cycle, written by the graph
   ~afq_batch_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -150,10 +151,16 @@ int batch_step_impl(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_e
     AFQ_CHECK(b->wk[i]->counter == b->wk[0]->counter, AFQ_E_STATE,
               "afq_batch_step: the walker sets' step counters differ");
   std::vector<double> es(e_shift, e_shift + n);
+  std::vector<double> caps;
+  for (int i = 0; i < n; ++i) {
+    caps.push_back(b->wk[i]->fb_cap);
+    caps.push_back(b->wk[i]->w_cap);
+  }
   const int prec = b->sys[0]->prec;
   for (int i = 1; i < n; ++i)
     AFQ_CHECK(b->sys[i]->prec == prec, AFQ_E_STATE, "afq_batch_step: systems must share a precision");
-  if (!b->exec || b->prec != prec || b->dt != dt || b->seed != seed || b->qr_every != qr_every || b->order != order || b->e_shift != es) {
+  if (!b->exec || b->prec != prec || b->dt != dt || b->seed != seed || b->qr_every != qr_every || b->order != order || b->e_shift != es ||
+      b->caps != caps) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
@@ -165,6 +172,7 @@ int batch_step_impl(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_e
     b->qr_every = qr_every;
     b->order = order;
     b->e_shift = es;
+    b->caps = caps;
     b->cycle = qr_every > 0 ? qr_every : 1;
     AFQ_RET(b->emix_cycle.alloc((size_t)n * b->cycle * sizeof(double)));
   }

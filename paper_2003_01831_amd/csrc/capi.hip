@@ -101,6 +101,30 @@ int afq_walkers_set(afq_walkers w, const double* W, const double* weights, const
   })
 }
 
+int afq_walkers_set_controls(afq_walkers w, double fb_cap, double w_cap) {
+  AFQ_CHECK(w, AFQ_E_INVALID, "afq_walkers_set_controls: walkers is NULL");
+  AFQ_CHECK(std::isfinite(fb_cap) && fb_cap >= 0.0 && std::isfinite(w_cap) && w_cap >= 0.0, AFQ_E_INVALID,
+            "afq_walkers_set_controls: caps must be finite and >= 0");
+  w->fb_cap = fb_cap;
+  w->w_cap = w_cap;
+  return AFQ_OK;
+}
+
+int afq_walkers_comb(afq_walkers w, double xi, int32_t* src_out, double* total_out) {
+  AFQ_CHECK(w, AFQ_E_INVALID, "afq_walkers_comb: walkers is NULL");
+  AFQ_CHECK(xi >= 0.0 && xi < 1.0, AFQ_E_INVALID, "afq_walkers_comb: xi must be in [0, 1)");
+  AFQ_GUARD(AFQ_RET(check_device(w->sys)); return walkers_comb(w, xi, src_out, total_out);)
+}
+
+int afq_eshift_update(double e_est, double w_total, double w_target, double dt, double gain_steps,
+                      double* e_shift_out) {
+  AFQ_CHECK(e_shift_out, AFQ_E_INVALID, "afq_eshift_update: output is NULL");
+  AFQ_CHECK(w_total > 0.0 && w_target > 0.0 && dt > 0.0 && gain_steps > 0.0 && std::isfinite(e_est), AFQ_E_INVALID,
+            "afq_eshift_update: weights, dt and gain must be positive");
+  *e_shift_out = e_est - std::log(w_total / w_target) / (gain_steps * dt);
+  return AFQ_OK;
+}
+
 int afq_walkers_stats(afq_walkers w, int* n_alive, int64_t* n_killed) {
   AFQ_CHECK(w, AFQ_E_INVALID, "afq_walkers_stats: walkers is NULL");
   AFQ_GUARD({

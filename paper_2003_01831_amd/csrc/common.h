@@ -142,6 +142,10 @@ struct afq_walkers_s {
   DevBuf killed;               // 1 x int64: walkers killed so far
   DevBuf d_counter;            // 1 x uint64: step counter on the device (keys the Philox fields)
   int exch_var[2] = {-1, -1};  // exchange launch variant per spin chosen by the autotuner (-1: cached/default)
+  double fb_cap = 0.0;         // force-bias modulus cap (0: off)
+  double w_cap = 0.0;          // weight cap (0: off)
+  DevBuf comb_cum, comb_src;   // population control scratch: running weight sums, source indices
+  DevBuf comb_out;             // 2 doubles: total weight, new common weight
   // per-step scratch
   DevBuf S, Sinv;              // per (w, spin): n x n complex (max n^2 stride)
   DevBuf logdet, logdet_new;   // nw x 2 complex
@@ -213,6 +217,7 @@ int energy_backward(afq_system s, afq_walkers w, double scale, double* d_h1, dou
 // exchange contraction: tr Omega and tr Omega^2 per (w, spin, n)
 int exchange_launch(afq_system s, afq_walkers w, int spin, hipStream_t st);
 int exchange_autotune(afq_system s, afq_walkers w, int reps, int* choice);   // choice[2]
+int walkers_comb(afq_walkers w, double xi, int* src_out, double* total_out);
 int pack_theta(afq_system s, afq_walkers w, hipStream_t st);
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }

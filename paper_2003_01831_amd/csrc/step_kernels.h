@@ -9,6 +9,7 @@ struct AssembleArgs {
   const double2* tro;      // nw x 2 x X
   const double2* troo;     // nw x 2 x X
   double e_core, dt;
+  double fb_cap;           // force-bias modulus cap (0: off)
   const double* fields;    // nw x X or NULL (Philox)
   uint64_t seed;
   const uint64_t* step_ptr;  // device step counter; Philox step = *step_ptr + step_off
@@ -30,6 +31,7 @@ struct WeightArgs {
   int* alive;                 // nw
   int64_t* killed;            // 1
   double dt, e_shift;
+  double w_cap;               // weight cap (0: off)
   double2* ratio_out;         // nw (optional)
   double* weights_out;        // nw (optional)
   double2* W;                 // nw x per
@@ -52,6 +54,11 @@ int masked_copy(const double2* src, double2* dst, long per, int nw, const int* a
 int launch_assemble(const AssembleArgs& a, void* coef, bool coef_f32, hipStream_t st);
 int launch_emix(const double2* eloc, const double* wt, int nw, double* out, hipStream_t st);
 int launch_weights(const WeightArgs& a, int nw, hipStream_t st);
+// population control: comb indices (running sums in walker order, one thread),
+// then the gather of the chosen walkers into Wout and the equal new weights
+int launch_comb_index(const double* weights, int nw, double xi, double* cum, int* src, double* out2, hipStream_t st);
+int launch_comb_apply(const double2* W, double2* Wout, long per, int nw, const int* src, const double* out2,
+                      double* weights, int* alive, hipStream_t st);
 int launch_asym(const double* x, int M, long nmat, double* out2, hipStream_t st);
 int launch_maximag(const double2* z, long n, double* out, hipStream_t st);
 int launch_infnorm(const double* x, int M, double* out, hipStream_t st);

@@ -314,10 +314,14 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs a, CT* __res
       if (a.vbar_out) a.vbar_out[(long)w * a.X + n] = vb;
       if (coef) {
         const double x = xs[h];
-        const double2 xb = make_double2(sdt * vb.y, -sdt * vb.x);  // -i sqrt(dt) vbar
-        CT c;
-        c.x = -a.dt * vb.x;
-        c.y = sdt * x - a.dt * vb.y;
+        double2 xb = make_double2(sdt * vb.y, -sdt * vb.x);  // -i sqrt(dt) vbar
+        if (a.fb_cap > 0.0) {                               // cap |xbar|, keep its phase
+          const double m = sqrt(cabs2(xb));
+          if (m > a.fb_cap) xb = cscale(xb, a.fb_cap / m);
+        }
+        CT c;                                               // i sqrt(dt) (x - xbar)
+        c.x = sdt * xb.y;
+        c.y = sdt * (x - xb.x);
         coef[(long)w * a.X + n] = c;
         const double2 xb2 = cmul(xb, xb);
         v[3] = cadd(v[3], make_double2(x * xb.x - 0.5 * xb2.x, x * xb.y - 0.5 * xb2.y));
@@ -384,6 +388,7 @@ __global__ __launch_bounds__(256) void weight_kernel(WeightArgs a) {
       double wn = 0.0;
       if (cs > 0.0) wn = a.weights[w] * exp(lr.x + a.lfac[w].x + a.dt * a.e_shift) * cs;
       if (!sing && wn > 0.0 && isfinite(wn)) {
+        if (a.w_cap > 0.0) wn = fmin(wn, a.w_cap);
         a.weights[w] = wn;
         ok = 1;
       } else {
@@ -403,6 +408,75 @@ __global__ __launch_bounds__(256) void weight_kernel(WeightArgs a) {
 }
 int launch_weights(const WeightArgs& a, int nw, hipStream_t st) {
   hipLaunchKernelGGL(weight_kernel, dim3(nw), dim3(256), 0, st, a);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+
+// Population control by systematic resampling ("comb"). One workgroup: thread 0
+// forms the running sums C_i of the weights in walker order (the same
+// left-to-right FP64 additions as a sequential cumulative sum) and finds the
+// last walker of positive weight; then tooth k at u_k = (k + xi) W / n picks
+// the first walker i with C_i > u_k (a tooth at or beyond W picks that last
+// walker). out2 = {W, W / n}; W <= 0 leaves src untouched.
+__global__ __launch_bounds__(256) void comb_index_kernel(const double* __restrict__ wt, int nw, double xi,
+                                                         double* __restrict__ cum, int* __restrict__ src,
+                                                         double* __restrict__ out2) {
+  __shared__ double total_s;
+  __shared__ int last_s;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double acc = 0.0;
+    int last = -1;
+    for (int i = 0; i < nw; ++i) {
+      acc += wt[i];
+      cum[i] = acc;
+      if (wt[i] > 0.0) last = i;
+    }
+    total_s = acc;
+    last_s = last;
+    out2[0] = acc;
+    out2[1] = acc / nw;
+  }
+  __syncthreads();
+  const double total = total_s;
+  if (!(total > 0.0) || last_s < 0) return;
+  const double step = total / nw;
+  for (int k = t; k < nw; k += 256) {
+    const double u = ((double)k + xi) * step;
+    int lo = 0, hi = nw;                      // first i with cum[i] > u, or nw
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cum[mid] > u) hi = mid;
+      else lo = mid + 1;
+    }
+    src[k] = lo < last_s ? lo : last_s;
+  }
+}
+int launch_comb_index(const double* weights, int nw, double xi, double* cum, int* src, double* out2,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(comb_index_kernel, dim3(1), dim3(256), 0, st, weights, nw, xi, cum, src, out2);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+
+// Wout[k] = W[src[k]]; weights[k] = W / n; alive[k] = 1
+__global__ __launch_bounds__(256) void comb_apply_kernel(const double2* __restrict__ W, double2* __restrict__ Wout,
+                                                         long per, const int* __restrict__ src,
+                                                         const double* __restrict__ out2, double* weights,
+                                                         int* alive) {
+  const int k = blockIdx.y;
+  const double2* from = W + (long)src[k] * per;
+  double2* to = Wout + (long)k * per;
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < per; i += (long)gridDim.x * 256) to[i] = from[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    weights[k] = out2[1];
+    alive[k] = 1;
+  }
+}
+int launch_comb_apply(const double2* W, double2* Wout, long per, int nw, const int* src, const double* out2,
+                      double* weights, int* alive, hipStream_t st) {
+  const int bx = (int)std::min<long>(ceil_div(per, 256), 64);
+  hipLaunchKernelGGL(comb_apply_kernel, dim3(bx, nw), dim3(256), 0, st, W, Wout, per, src, out2, weights, alive);
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }

@@ -261,6 +261,7 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
   a.step_ptr = w->d_counter.as<uint64_t>();
   a.step_off = step_off;
   a.sys_id = sys_id;
+  a.fb_cap = w->fb_cap;
   a.eloc_out = reinterpret_cast<double2*>(eloc_out);
   AFQ_RET(energy_from_theta(s, w, a, true));
   if (emix_out) {
@@ -284,6 +285,7 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
     wa.killed = w->killed.as<int64_t>();
     wa.dt = dt;
     wa.e_shift = e_shift;
+    wa.w_cap = w->w_cap;
     wa.ratio_out = reinterpret_cast<double2*>(ratio_out);
     wa.weights_out = weights_out;
     wa.W = w->W.as<double2>();
@@ -334,5 +336,33 @@ int walkers_create_impl(afq_walkers* out, afq_system s, int nw, const double* w0
     return rc;
   }
   *out = w;
+  return AFQ_OK;
+}
+
+// Population control: comb the walkers to nw copies of equal weight (see
+// comb_index_kernel). Synchronises the stream to read the total weight back.
+int walkers_comb(afq_walkers w, double xi, int* src_out, double* total_out) {
+  afq_system s = w->sys;
+  hipStream_t st = s->stream;
+  const int nw = w->nw;
+  AFQ_RET(w->comb_cum.alloc((size_t)nw * sizeof(double)));
+  AFQ_RET(w->comb_src.alloc((size_t)nw * sizeof(int)));
+  AFQ_RET(w->comb_out.alloc(2 * sizeof(double)));
+  AFQ_RET(launch_comb_index(w->weights.as<double>(), nw, xi, w->comb_cum.as<double>(), w->comb_src.as<int>(),
+                            w->comb_out.as<double>(), st));
+  double out2[2];
+  AFQ_TRY_HIP(hipMemcpyAsync(out2, w->comb_out.p, sizeof(out2), hipMemcpyDeviceToHost, st));
+  AFQ_TRY_HIP(hipStreamSynchronize(st));
+  if (total_out) *total_out = out2[0];
+  AFQ_CHECK(out2[0] > 0.0 && std::isfinite(out2[0]), AFQ_E_STATE,
+            "afq_walkers_comb: the walkers carry no positive weight");
+  const long per = (long)s->M * s->ntot;
+  AFQ_RET(launch_comb_apply(w->W.as<double2>(), w->Wn.as<double2>(), per, nw, w->comb_src.as<int>(),
+                            w->comb_out.as<double>(), w->weights.as<double>(), w->alive.as<int>(), st));
+  AFQ_TRY_HIP(hipMemcpyAsync(w->W.p, w->Wn.p, (size_t)nw * per * 16, hipMemcpyDeviceToDevice, st));
+  if (src_out) {
+    AFQ_TRY_HIP(hipMemcpyAsync(src_out, w->comb_src.p, (size_t)nw * sizeof(int), hipMemcpyDeviceToHost, st));
+    AFQ_TRY_HIP(hipStreamSynchronize(st));
+  }
   return AFQ_OK;
 }
