@@ -260,6 +260,17 @@ def main(argv=None):
         roofline["real_lt_frac_of_bf16x3_effective_peak"] = round(roofline["achieved_real_lt"] / (peak / 3), 4)
 
     extra = {}
+    # population control at this size: one comb of all walkers (host-synchronising)
+    wk_pc = api.Walkers(sysg, nw)
+    wk_pc.set(weights=np.random.default_rng(3).uniform(0.5, 1.5, nw))
+    wk_pc.comb(0.5)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for r in range(5):
+        wk_pc.comb((r + 0.5) / 5)
+    torch.cuda.synchronize()
+    extra["comb_ms"] = round((time.perf_counter() - t) / 5 * 1e3, 3)
+    wk_pc.close()
     if a.compare_steps > 0:
         for prec in ("fp64", "cfp32", "bf16x3"):
             if prec == a.precision:
