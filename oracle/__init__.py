@@ -13,5 +13,11 @@ Parity status per function (pins in tests/test_oracle_*.py):
                                                            invariants, E_shift invariance)
   afqmc.energy_grad / mixed_rdm1                           pinned (central differences,
                                                            explicit 1-RDM from FCI)
+  afqmc.comb / eshift_update / caps in run                 pinned (hand example, floor/ceil
+                                                           counts, unbiasedness, limits)
+  afqmc.back_propagate / back_propagated_rdm1              pinned (many-body matrix element
+                                                           in the FCI space, L=0 ground-state
+                                                           density, invariances, walk
+                                                           bookkeeping incl. comb ancestry)
   philox.philox4x32_10                                     pinned (published KAT vectors)
 """

@@ -192,7 +192,7 @@ def prepare(h1, chol, phi_t, n_up, n_dn, dt):
 
 def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
         e_shift=0.0, order=6, e_core=0.0, energy="half", record_walkers=False, pre=None,
-        fb_cap=0.0, w_cap=0.0, comb_every=0, comb_xi=None):
+        fb_cap=0.0, w_cap=0.0, comb_every=0, comb_xi=None, bp_start=None, bp_len=0):
     """Run len(fields) steps. fields[k, w, n] are the standard-normal HS fields.
     `pre` may hold prepare(h1, chol, phi_t, n_up, n_dn, dt) computed beforehand.
 
@@ -207,6 +207,12 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
       4. Population control when comb_every > 0 and (k+1) % comb_every == 0:
          comb() with the next uniform number of comb_xi. out["weights"][k]
          holds the weights before this step's comb.
+    With bp_start set, a back-propagation window of bp_len steps opens at the
+    start of step bp_start: out["bp_W0"] holds the walkers then, out["bp_coefs"]
+    [j, w] the coefficients c_n = i sqrt(dt) (x_n - xbar_n) of A = sum_n c_n L^n
+    drawn by walker w in step bp_start + j (zero for frozen walkers), and
+    out["bp_weights"] the weights at the end of the window. A comb inside the
+    window hands every copy its source walker's history (ket and coefficients).
     """
     M = h1.shape[0]
     nw = W0.shape[0]
@@ -226,7 +232,16 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
                cosdt=np.ones((n_steps, nw)))
     if record_walkers:
         out["walkers"] = np.zeros((n_steps,) + W.shape, np.complex128)
+    def open_window():
+        out["bp_W0"] = W.copy()
+        out["bp_coefs"] = np.zeros((bp_len, nw, chol.shape[0]), np.complex128)
+        if bp_len == 0:
+            out["bp_weights"] = w.copy()
+
+    in_window = lambda k: bp_start is not None and bp_start <= k < bp_start + bp_len
     for k in range(n_steps):
+        if bp_start == k:
+            open_window()
         vb = np.zeros((nw, chol.shape[0]), np.complex128)
         for i in range(nw):
             if energy == "plain":
@@ -246,6 +261,8 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
             x = fields[k, i]
             xbar = force_bias_shift(vb[i], dt, fb_cap)
             A = hs_operator(chol, x, xbar, dt)
+            if in_window(k):
+                out["bp_coefs"][k - bp_start, i] = 1j * np.sqrt(dt) * (x - xbar)
             Wn = B1 @ taylor_apply(A, B1 @ W[i], order)
             _, logOn = theta(phi_t, Wn, n_up, n_dn)
             log_r = logOn - logO[i]
@@ -280,8 +297,15 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
             logO = logO[src].copy()
             w = np.full(nw, wnew)
             alive = np.ones(nw, dtype=bool)
+            if in_window(k):
+                out["bp_W0"] = out["bp_W0"][src].copy()
+                out["bp_coefs"] = out["bp_coefs"][:, src].copy()
+        if in_window(k) and k == bp_start + bp_len - 1:
+            out["bp_weights"] = w.copy()
         if record_walkers:
             out["walkers"][k] = W
+    if bp_start == n_steps:
+        open_window()
     out.update(W=W, w=w, logO=logO, alive=alive)
     return out
 
@@ -383,3 +407,58 @@ def mixed_rdm1(phi_t, n_up, n_dn, W, weights):
         G = greens_function(phi_t, W[i], n_up, n_dn)
         P = P + wh[i] * (G[0] + G[1]).T
     return P
+
+
+
+# ---------------------------------------------------------------------------
+# Back-propagated one-body density matrix (the back-propagation paragraph of
+# the AFQMC section; the method itself is only cited there). For an operator
+# that does not commute with H the mixed form <T|O|phi>/<T|phi> is biased; the
+# back-propagated form replaces the bra <T| by <T| B_{n-1} ... B_0, the trial
+# carried through the n steps that followed the ket phi (the walker at the
+# start of the window) with the fields those steps drew, and weighs each walker
+# by its weight at the end of the window. No path restoration of the phases is
+# applied.
+# ---------------------------------------------------------------------------
+def back_propagate(B1, chol, phi_t, n_up, n_dn, coefs, order, qr_every=0):
+    """Ket form of the back-propagated bra of one walker.
+
+    coefs[j, n] are the propagator coefficients of step j of the window,
+    A_j = sum_n coefs[j, n] L^n and B_j = B1 T_K(A_j) B1. The bra
+    <T| B_{n-1} ... B_0 is the ket B_0^H ... B_{n-1}^H |T>; with L^n and B1
+    real symmetric, B_j^H = B1 T_K(A_j^H) B1 with A_j^H = sum_n conj(c_jn) L^n
+    (the Taylor polynomial commutes with the adjoint). B_{n-1}^H acts first.
+    With qr_every > 0 each spin block is replaced by the Q of its
+    positive-diagonal QR after every qr_every of these steps; the estimator
+    depends on the bra only through the column space of each spin block, so
+    this changes nothing but rounding."""
+    psi = phi_t.astype(np.complex128).copy()
+    n = coefs.shape[0]
+    for t, j in enumerate(range(n - 1, -1, -1)):
+        AH = np.tensordot(np.conj(coefs[j]), chol, axes=1)
+        psi = B1 @ taylor_apply(AH, B1 @ psi, order)
+        if qr_every > 0 and (t + 1) % qr_every == 0:
+            for b in spin_blocks(n_up, n_dn):
+                psi[:, b], _ = qr_positive(psi[:, b])
+    return psi
+
+
+def back_propagated_rdm1(B1, chol, phi_t, n_up, n_dn, W0, coefs, weights, order, qr_every=0):
+    """Spin-resolved back-propagated 1-RDM
+        P[s, i, j] = sum_w w_w <psi_w| c+_is c_js |phi_w> / <psi_w|phi_w> / sum_w w_w
+    with phi_w = W0[w] (walkers at the start of the window), psi_w the
+    back-propagated bra of walker w (coefs[:, w, :]) and w_w the weights at the
+    end of the window. Per spin, <psi|c+_i c_j|phi>/<psi|phi> = G_ji with
+    G = phi (psi^H phi)^-1 psi^H (the same Wick form as the mixed estimate, bra
+    psi in place of T). Walkers of weight 0 are skipped."""
+    w = np.asarray(weights, dtype=np.float64)
+    M = phi_t.shape[0]
+    P = np.zeros((2, M, M), np.complex128)
+    for i in range(W0.shape[0]):
+        if w[i] == 0.0:
+            continue
+        psi = back_propagate(B1, chol, phi_t, n_up, n_dn, coefs[:, i], order, qr_every)
+        G = greens_function(psi, W0[i], n_up, n_dn)
+        for s in range(2):
+            P[s] += w[i] * G[s].T
+    return P / np.sum(w)

@@ -93,8 +93,9 @@ def hamiltonian(h1, v, n_up, n_dn, e_core=0.0):
     return H, dets
 
 
-def one_body_operator(A, n_up, n_dn):
-    """FCI matrix of sum_s sum_ik A_ik c+_is c_ks (A may be complex)."""
+def one_body_operator(A, n_up, n_dn, spin=None):
+    """FCI matrix of sum_s sum_ik A_ik c+_is c_ks (A may be complex); with
+    spin = 0 or 1 only that spin's term."""
     M = A.shape[0]
     nso = 2 * M
     dets = determinants(M, n_up, n_dn)
@@ -104,6 +105,8 @@ def one_body_operator(A, n_up, n_dn):
         for q in _occ(det, nso):
             d1, s1 = _annihilate(det, q)
             sq, k = divmod(q, M)
+            if spin is not None and sq != spin:
+                continue
             for i in range(M):
                 d2, s2 = _create(d1, sq * M + i)
                 if d2 is None:
