@@ -220,6 +220,40 @@ int afq_autotune(afq_system s, afq_walkers w, int reps, int *choice_out);
 int afq_exchange_variant(afq_walkers w, int spin, int variant);
 
 /* ------------------------------------------------------------------------ */
+/* Back-propagated one-body density matrix (back-propagation paragraph of    */
+/* Section "Auxiliary Field Quantum Monte Carlo"; the method is cited there). */
+/* ------------------------------------------------------------------------ */
+
+/* Opens a window of n_bp steps (0 <= n_bp <= 2^20) on the current walkers:
+ * they become the kets phi_w, and each of the next n_bp afq_step steps stores
+ * the conjugated propagator coefficients conj(c_wn) of every walker
+ * (A = sum_n c_wn L^n). dt, the Taylor order and the precision must stay fixed
+ * while the window records (AFQ_E_INVALID / AFQ_E_STATE otherwise);
+ * afq_batch_step refuses to step a walker set whose window records, and
+ * afq_walkers_set closes the window. An afq_walkers_comb inside the window
+ * hands every copy its source walker's ket and coefficients. Device memory:
+ * n_walkers*M*Ntot complex128 for the kets plus n_bp*n_walkers*n_chol complex
+ * (complex128, or complex64 in the reduced-precision modes). Reopening
+ * discards the previous window. */
+int afq_bp_begin(afq_walkers w, int n_bp);
+/* Once the window holds its n_bp steps and no further step was taken: carries
+ * the trial backwards, |psi_w> = B_0^H ... B_{n_bp-1}^H |T> with
+ * B_j^H = B1 T_K(A_j^H) B1 (the last step's first; QR of every spin block after
+ * every qr_every of these steps, 0 = never), and writes the spin-resolved
+ * back-propagated 1-RDM
+ *   rdm_out[s][i][j] = sum_w w_w <psi_w|c+_is c_js|phi_w>/<psi_w|phi_w> / sum_w w_w
+ * (device, 2*M*M complex128) with the weights w_w at the end of the window
+ * (walkers of weight 0 drop out; no phase restoration along the path).
+ * wsum_out (host, may be NULL) receives sum_w w_w. Synchronises the system
+ * stream. AFQ_E_STATE if the window is not full, steps followed it, the
+ * precision changed or no walker has positive weight; AFQ_E_SINGULAR if a
+ * walker of positive weight has a singular <psi_w|phi_w> in either spin (the
+ * output is then undefined). The window stays open: the call may be repeated. */
+int afq_bp_rdm1(afq_walkers w, int qr_every, double *rdm_out, double *wsum_out);
+/* Closes the window and frees its memory. */
+int afq_bp_end(afq_walkers w);
+
+/* ------------------------------------------------------------------------ */
 /* Many uneven systems in one captured launch sequence.                       */
 /* ------------------------------------------------------------------------ */
 

@@ -37,6 +37,9 @@ SIGNATURES = {
     "afq_fields_generate": (_i, [_u64, _u32, _u64, _i, _i, _i, _vp, _vp]),
     "afq_autotune": (_i, [_vp, _vp, _i, _vp]),
     "afq_exchange_variant": (_i, [_vp, _i, _i]),
+    "afq_bp_begin": (_i, [_vp, _i]),
+    "afq_bp_rdm1": (_i, [_vp, _i, _vp, C.POINTER(_d)]),
+    "afq_bp_end": (_i, [_vp]),
     "afq_batch_create": (_i, [C.POINTER(_vp), _i, _vp, _vp]),
     "afq_batch_step": (_i, [_vp, _i, _d, _u64, _i, _vp, _i, _vp]),
     "afq_batch_destroy": (_i, [_vp]),

@@ -153,6 +153,22 @@ class Walkers:
         check(self.lib.afq_walkers_comb(self.handle, float(xi), src.ctypes.data_as(C.c_void_p), C.byref(tot)))
         return src, float(tot.value)
 
+    def bp_begin(self, n_bp):
+        """Open a back-propagation window of n_bp steps on the current walkers."""
+        check(self.lib.afq_bp_begin(self.handle, int(n_bp)))
+
+    def bp_rdm1(self, qr_every=0):
+        """Back-propagated spin-resolved 1-RDM P[s, i, j] = <c+_is c_js> (2 x M x M
+        complex128 on the device) and the total weight at the end of the window."""
+        M = self.sys.M
+        out = torch.zeros(2, M, M, dtype=torch.complex128, device=_dev())
+        wsum = C.c_double()
+        check(self.lib.afq_bp_rdm1(self.handle, int(qr_every), _ptr(out), C.byref(wsum)))
+        return out, float(wsum.value)
+
+    def bp_end(self):
+        check(self.lib.afq_bp_end(self.handle))
+
     def set_exchange_variant(self, spin, variant):
         check(self.lib.afq_exchange_variant(self.handle, int(spin), int(variant)))
 

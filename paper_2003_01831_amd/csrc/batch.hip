@@ -150,6 +150,9 @@ int batch_step_impl(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_e
   for (int i = 1; i < n; ++i)
     AFQ_CHECK(b->wk[i]->counter == b->wk[0]->counter, AFQ_E_STATE,
               "afq_batch_step: the walker sets' step counters differ");
+  for (int i = 0; i < n; ++i)
+    AFQ_CHECK(n_steps == 0 || b->wk[i]->bp_n < 0 || b->wk[i]->bp_rec >= b->wk[i]->bp_n, AFQ_E_STATE,
+              "afq_batch_step: a walker set has a back-propagation window that still records (use afq_step)");
   std::vector<double> es(e_shift, e_shift + n);
   std::vector<double> caps;
   for (int i = 0; i < n; ++i) {

@@ -97,6 +97,7 @@ int afq_walkers_set(afq_walkers w, const double* W, const double* weights, const
     if (alive) AFQ_TRY_HIP(hipMemcpyAsync(w->alive.p, alive, w->nw * 4, hipMemcpyDeviceToDevice, st));
     AFQ_RET(counter_set(w->d_counter.as<uint64_t>(), counter, st));
     w->counter = counter;
+    w->bp_n = -1;   // the kets of an open back-propagation window no longer match
     return AFQ_OK;
   })
 }
@@ -158,18 +159,40 @@ int afq_step(afq_system s, afq_walkers w, int n_steps, double dt, const double* 
     AFQ_RET(system_prepare_dt(s, dt));
     AFQ_RET(system_prepare_pack(s, s->prec));
     AFQ_RET(walkers_alloc_scratch(w));
+    AFQ_RET(bp_check_step(w, n_steps, dt, taylor_order));
     const long nw = w->nw, X = s->X;
     for (int k = 0; k < n_steps; ++k) {
       const uint64_t idx = w->counter + k;
       const bool do_qr = qr_every > 0 && (idx + 1) % (uint64_t)qr_every == 0;
       AFQ_RET(step_once(s, w, dt, fields ? fields + (long)k * nw * X : nullptr, seed, 0, k, do_qr, e_shift,
                         taylor_order, emix_out ? emix_out + k : nullptr, eloc_out ? eloc_out + 2 * k * nw : nullptr,
-                        weights_out ? weights_out + k * nw : nullptr, ratio_out ? ratio_out + 2 * k * nw : nullptr));
+                        weights_out ? weights_out + k * nw : nullptr, ratio_out ? ratio_out + 2 * k * nw : nullptr,
+                        bp_record_slot(w)));
+      bp_advance(w, 1);
     }
     if (n_steps > 0) AFQ_RET(counter_add(w->d_counter.as<uint64_t>(), (uint64_t)n_steps, s->stream));
     w->counter += n_steps;
     return AFQ_OK;
   })
+}
+
+int afq_bp_begin(afq_walkers w, int n_bp) {
+  AFQ_CHECK(w, AFQ_E_INVALID, "afq_bp_begin: walkers is NULL");
+  AFQ_CHECK(n_bp >= 0 && n_bp <= (1 << 20), AFQ_E_INVALID, "afq_bp_begin: n_bp must be in [0, 2^20]");
+  AFQ_GUARD(AFQ_RET(check_device(w->sys)); return bp_begin(w, n_bp);)
+}
+
+int afq_bp_rdm1(afq_walkers w, int qr_every, double* rdm_out, double* wsum_out) {
+  AFQ_CHECK(w, AFQ_E_INVALID, "afq_bp_rdm1: walkers is NULL");
+  AFQ_CHECK(rdm_out, AFQ_E_INVALID, "afq_bp_rdm1: rdm_out is NULL");
+  AFQ_CHECK(qr_every >= 0, AFQ_E_INVALID, "afq_bp_rdm1: qr_every < 0");
+  AFQ_GUARD(AFQ_RET(check_device(w->sys)); return bp_rdm1(w, qr_every, rdm_out, wsum_out);)
+}
+
+int afq_bp_end(afq_walkers w) {
+  AFQ_CHECK(w, AFQ_E_INVALID, "afq_bp_end: walkers is NULL");
+  AFQ_GUARD(AFQ_RET(check_device(w->sys)); AFQ_TRY_HIP(hipStreamSynchronize(w->sys->stream)); bp_end(w);
+            return AFQ_OK;)
 }
 
 int afq_energy(afq_system s, afq_walkers w, double* eloc_out, double* parts_out, double* vbar_out, double* emix_out) {

@@ -146,6 +146,17 @@ struct afq_walkers_s {
   double w_cap = 0.0;          // weight cap (0: off)
   DevBuf comb_cum, comb_src;   // population control scratch: running weight sums, source indices
   DevBuf comb_out;             // 2 doubles: total weight, new common weight
+  // back-propagation window (bp_n < 0: none)
+  int bp_n = -1;               // window length in steps
+  int bp_rec = 0;              // steps recorded so far
+  uint64_t bp_start = 0;       // step counter when the window opened
+  double bp_dt = -1.0;         // time step of the recorded steps
+  int bp_order = 0;            // Taylor order of the recorded steps
+  int bp_prec = -1;            // precision of the recorded coefficients
+  DevBuf bp_W0;                // walkers when the window opened (nw x M x ntot c128)
+  DevBuf bp_coef, bp_tmp;      // bp_n x nw x X conj(c) (f64 or f32 complex); gather scratch
+  DevBuf bp_psi;               // back-propagated trial (nw x M x ntot c128)
+  DevBuf bp_stats;             // 2 doubles: sum of weights, singular count
   // per-step scratch
   DevBuf S, Sinv;              // per (w, spin): n x n complex (max n^2 stride)
   DevBuf logdet, logdet_new;   // nw x 2 complex
@@ -206,9 +217,23 @@ int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool
                           double2* logdet_out);
 // one walker step; the Philox step index is *w->d_counter + step_off (the
 // counter itself is advanced by counter_add after the steps of a call)
+// coef_record (optional): where conj of this step's propagator coefficients go
 int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed,
               uint32_t sys_id, uint64_t step_off, bool do_qr, double e_shift, int order,
-              double* emix_out, double* eloc_out, double* weights_out, double* ratio_out);
+              double* emix_out, double* eloc_out, double* weights_out, double* ratio_out,
+              void* coef_record = nullptr);
+// Wout = B1 T_K(A) B1 Win with A_w = sum_n coef[w][n] L^n (coef in the system's contraction precision)
+int propagate_walkers(afq_system s, afq_walkers w, int order, const void* coef, const double2* Win, double2* Wout);
+// CholeskyQR2 of every spin block: src -> mid -> dst
+int qr_orbitals(afq_system s, afq_walkers w, const double2* src, double2* mid, double2* dst);
+// back-propagation window (bp.hip)
+int bp_begin(afq_walkers w, int n_bp);
+void bp_end(afq_walkers w);
+void* bp_record_slot(afq_walkers w);   // NULL when the step is not recorded
+int bp_check_step(afq_walkers w, int n_steps, double dt, int order);
+void bp_advance(afq_walkers w, int n_steps);
+int bp_comb_gather(afq_walkers w, const int* src);
+int bp_rdm1(afq_walkers w, int qr_every, double* rdm_out, double* wsum_out);
 int counter_add(uint64_t* c, uint64_t v, hipStream_t st);
 int counter_set(uint64_t* c, uint64_t v, hipStream_t st);
 int energy_backward(afq_system s, afq_walkers w, double scale, double* d_h1, double* d_chol,

@@ -64,3 +64,11 @@ int launch_maximag(const double2* z, long n, double* out, hipStream_t st);
 int launch_infnorm(const double* x, int M, double* out, hipStream_t st);
 int launch_logovlp(const double2* ld, int nw, double2* out, hipStream_t st);
 int launch_init_alive(const double* wt, const int* sing, int nw, int* alive, int* bad, hipStream_t st);
+// back-propagation window: conjugated coefficient copy, row gather (comb
+// ancestry), weight sum + singular count, and the operands of the 1-RDM GEMM
+int launch_conj_copy(const void* src, void* dst, long n, bool f32, hipStream_t st);
+int launch_gather_rows(const void* src, void* dst, long row_bytes, int nrows, int nslabs, const int* idx,
+                       hipStream_t st);
+int launch_bp_stats(const double* wt, const int* sing, int nw, double* stats, hipStream_t st);
+int launch_bp_pack(double2* Y, double2* Q, const double2* psi, long per, int ntot, int off, int n, int nw, int M,
+                   const double* wt, const double* stats, hipStream_t st);

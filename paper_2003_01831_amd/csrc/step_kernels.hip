@@ -599,3 +599,101 @@ int counter_set(uint64_t* c, uint64_t v, hipStream_t st) {
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }
+
+// ---------------------------------------------------------------------------
+// back-propagation window
+// ---------------------------------------------------------------------------
+// dst = conj(src), n complex elements (the coefficients of B^H = B1 T_K(A^H) B1)
+template <typename C>
+__global__ void conj_copy_kernel(const C* __restrict__ src, C* __restrict__ dst, long n) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    C v = src[i];
+    v.y = -v.y;
+    dst[i] = v;
+  }
+}
+int launch_conj_copy(const void* src, void* dst, long n, bool f32, hipStream_t st) {
+  if (n <= 0) return AFQ_OK;
+  if (f32)
+    hipLaunchKernelGGL(conj_copy_kernel<float2>, dim3(grid_for(n)), dim3(256), 0, st,
+                       static_cast<const float2*>(src), static_cast<float2*>(dst), n);
+  else
+    hipLaunchKernelGGL(conj_copy_kernel<double2>, dim3(grid_for(n)), dim3(256), 0, st,
+                       static_cast<const double2*>(src), static_cast<double2*>(dst), n);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+
+// dst[slab][k] = src[slab][idx[k]] for rows of rw 8-byte words, nrows rows a slab
+__global__ void gather_rows_kernel(const uint2* __restrict__ src, uint2* __restrict__ dst, long rw, int nrows,
+                                   const int* __restrict__ idx, long total) {
+  for (long t = blockIdx.x * 256L + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+    const long row = t / rw, e = t - row * rw;
+    const long slab = row / nrows;
+    const int k = (int)(row - slab * nrows);
+    dst[t] = src[(slab * nrows + idx[k]) * rw + e];
+  }
+}
+int launch_gather_rows(const void* src, void* dst, long row_bytes, int nrows, int nslabs, const int* idx,
+                       hipStream_t st) {
+  AFQ_CHECK(row_bytes % 8 == 0, AFQ_E_INVALID, "gather_rows: row size is not a multiple of 8 bytes");
+  const long rw = row_bytes / 8, total = rw * nrows * (long)nslabs;
+  if (total == 0) return AFQ_OK;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for(total)), dim3(256), 0, st, static_cast<const uint2*>(src),
+                     static_cast<uint2*>(dst), rw, nrows, idx, total);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+
+// stats[0] = sum of the positive weights (fixed order), stats[1] = number of
+// walkers of positive weight whose bra-ket overlap is singular in either spin
+__global__ __launch_bounds__(256) void bp_stats_kernel(const double* __restrict__ wt, const int* __restrict__ sing,
+                                                       int nw, double* __restrict__ stats) {
+  const int t = threadIdx.x;
+  double2 v[1] = {make_double2(0, 0)};
+  for (int w = t; w < nw; w += 256) {
+    const double ww = wt[w];
+    if (ww > 0.0) {
+      v[0].x += ww;
+      v[0].y += (sing[2 * w] || sing[2 * w + 1]) ? 1.0 : 0.0;
+    }
+  }
+  block_sum<1>(v);
+  if (t == 0) { stats[0] = v[0].x; stats[1] = v[0].y; }
+}
+int launch_bp_stats(const double* wt, const int* sing, int nw, double* stats, hipStream_t st) {
+  hipLaunchKernelGGL(bp_stats_kernel, dim3(1), dim3(256), 0, st, wt, sing, nw, stats);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+
+// Operands of P^s = Q Y^T over the walker-stacked index r = w n + a:
+//   Y[i][r] <- f_w Y[i][r],  Q[i][r] = conj(psi_w[i][off + a])   (f_w = w_w / sum w)
+// and both zero for walkers of weight <= 0 (whatever their Y or psi hold).
+__global__ void bp_pack_kernel(double2* __restrict__ Y, double2* __restrict__ Q, const double2* __restrict__ psi,
+                               long per, int ntot, int off, int n, int nw, const double* __restrict__ wt,
+                               const double* __restrict__ stats, long total) {
+  const long K = (long)nw * n;
+  const double inv = stats[0] > 0.0 ? 1.0 / stats[0] : 0.0;
+  for (long t = blockIdx.x * 256L + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+    const long i = t / K, r = t - i * K;
+    const int w = (int)(r / n), a = (int)(r - (long)w * n);
+    const double ww = wt[w];
+    if (ww > 0.0) {
+      Y[t] = cscale(Y[t], ww * inv);
+      Q[t] = cconj(psi[w * per + i * ntot + off + a]);
+    } else {
+      Y[t] = make_double2(0.0, 0.0);
+      Q[t] = make_double2(0.0, 0.0);
+    }
+  }
+}
+int launch_bp_pack(double2* Y, double2* Q, const double2* psi, long per, int ntot, int off, int n, int nw, int M,
+                   const double* wt, const double* stats, hipStream_t st) {
+  const long total = (long)M * nw * n;
+  if (total == 0) return AFQ_OK;
+  hipLaunchKernelGGL(bp_pack_kernel, dim3(grid_for(total)), dim3(256), 0, st, Y, Q, psi, per, ntot, off, n, nw, wt,
+                     stats, total);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}

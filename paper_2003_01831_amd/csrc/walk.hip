@@ -156,9 +156,10 @@ int energy_call(afq_system s, afq_walkers w, double* eloc_out, double* parts_out
   return AFQ_OK;
 }
 
-// W' = B1 T_K(A) B1 W for all walkers (complex A per walker, both spins at once)
+// Wout = B1 T_K(A) B1 Win for all walkers (complex A per walker, both spins at
+// once), A_w = sum_n coef[w][n] L^n with coef in the contraction precision T.
 template <typename T>
-static int propagate(afq_system s, afq_walkers w, int order) {
+static int propagate(afq_system s, afq_walkers w, int order, const T* coef, const double2* Win, double2* Wout) {
   hipStream_t st = s->stream;
   const int M = s->M, ntot = s->ntot, nw = w->nw, X = s->X;
   const long per = (long)M * ntot;
@@ -167,7 +168,7 @@ static int propagate(afq_system s, afq_walkers w, int order) {
     TraceScope tr(AFQ_PH_ABUILD, st);
     GemmArgs<T> g = gemm_args<T>();
     g.m = nw; g.n = M * M; g.k = X;
-    g.A = w->coef.as<T>(); g.lda = X; g.cA = true;
+    g.A = coef; g.lda = X; g.cA = true;
     g.B = sizeof(T) == 8 ? reinterpret_cast<const T*>(s->chol.p) : reinterpret_cast<const T*>(s->chol32.p);
     g.ldb = (long)M * M; g.cB = false;
     g.C = w->amat.as<T>(); g.ldc = (long)M * M; g.cC = true;
@@ -179,7 +180,7 @@ static int propagate(afq_system s, afq_walkers w, int order) {
     GemmArgs<double> g = gemm_args<double>();
     g.m = M; g.n = ntot; g.k = M; g.batch = nw;
     g.A = s->B1.as<double>(); g.lda = M; g.cA = false; g.sA = 0;
-    g.B = w->W.as<double>(); g.ldb = ntot; g.cB = true; g.sB = per;
+    g.B = reinterpret_cast<const double*>(Win); g.ldb = ntot; g.cB = true; g.sB = per;
     g.C = w->u.as<double>(); g.ldc = ntot; g.cC = true; g.sC = per;
     AFQ_RET(gemm<double>(g, st));
   }
@@ -205,24 +206,30 @@ static int propagate(afq_system s, afq_walkers w, int order) {
     g.m = M; g.n = ntot; g.k = M; g.batch = nw;
     g.A = s->B1.as<double>(); g.lda = M; g.cA = false; g.sA = 0;
     g.B = w->u.as<double>(); g.ldb = ntot; g.cB = true; g.sB = per;
-    g.C = w->Wn.as<double>(); g.ldc = ntot; g.cC = true; g.sC = per;
+    g.C = reinterpret_cast<double*>(Wout); g.ldc = ntot; g.cC = true; g.sC = per;
     AFQ_RET(gemm<double>(g, st));
   }
   return AFQ_OK;
 }
 
-// CholeskyQR2 of every spin block: W^s <- W^s R^-1 twice, live walkers only.
-static int qr_walkers(afq_system s, afq_walkers w) {
+int propagate_walkers(afq_system s, afq_walkers w, int order, const void* coef, const double2* Win, double2* Wout) {
+  if (s->prec == AFQ_FP64) return propagate<double>(s, w, order, static_cast<const double*>(coef), Win, Wout);
+  return propagate<float>(s, w, order, static_cast<const float*>(coef), Win, Wout);
+}
+
+// CholeskyQR2 of every spin block of every walker: dst^s = (src^s R1^-1) R2^-1,
+// the first pass written to mid (all three nw x M x ntot complex).
+int qr_orbitals(afq_system s, afq_walkers w, const double2* src0, double2* mid, double2* dst0) {
   hipStream_t st = s->stream;
-  TraceScope tr(AFQ_PH_QR, st);
   const int M = s->M, ntot = s->ntot, nw = w->nw;
   const long per = (long)M * ntot;
   const int nmax = std::max(s->n_up, s->n_dn);
   const long nm2 = (long)nmax * nmax;
-  double2* bufs[3] = {w->W.as<double2>(), w->Wn.as<double2>(), w->u.as<double2>()};
+  const double2* in[2] = {src0, mid};
+  double2* out[2] = {mid, dst0};
   for (int pass = 0; pass < 2; ++pass) {
-    const double* src = reinterpret_cast<const double*>(bufs[pass]);
-    double* dst = reinterpret_cast<double*>(bufs[pass + 1]);
+    const double* src = reinterpret_cast<const double*>(in[pass]);
+    double* dst = reinterpret_cast<double*>(out[pass]);
     for (int sp = 0; sp < 2; ++sp) {
       const int n = s->nspin_n(sp), off = s->spin_off(sp);
       GemmArgs<double> g = gemm_args<double>();
@@ -241,12 +248,20 @@ static int qr_walkers(afq_system s, afq_walkers w) {
       AFQ_RET(gemm<double>(q, st));
     }
   }
-  return masked_copy(bufs[2], bufs[0], per, nw, w->alive.as<int>(), st);
+  return AFQ_OK;
+}
+
+// QR of the live walkers: W -> Wn -> u, then u back into W where alive
+static int qr_walkers(afq_system s, afq_walkers w) {
+  TraceScope tr(AFQ_PH_QR, s->stream);
+  AFQ_RET(qr_orbitals(s, w, w->W.as<double2>(), w->Wn.as<double2>(), w->u.as<double2>()));
+  return masked_copy(w->u.as<double2>(), w->W.as<double2>(), (long)s->M * s->ntot, w->nw, w->alive.as<int>(),
+                     s->stream);
 }
 
 int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed, uint32_t sys_id,
               uint64_t step_off, bool do_qr, double e_shift, int order, double* emix_out, double* eloc_out,
-              double* weights_out, double* ratio_out) {
+              double* weights_out, double* ratio_out, void* coef_record) {
   hipStream_t st = s->stream;
   const int nw = w->nw;
   // overlap, Theta and the energy at the start-of-step walkers
@@ -264,13 +279,13 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
   a.fb_cap = w->fb_cap;
   a.eloc_out = reinterpret_cast<double2*>(eloc_out);
   AFQ_RET(energy_from_theta(s, w, a, true));
+  if (coef_record)   // back-propagation window: conj(c) of this step, the coefficients of B^H
+    AFQ_RET(launch_conj_copy(w->coef.p, coef_record, (long)nw * s->X, s->prec != AFQ_FP64, st));
   if (emix_out) {
     TraceScope t(AFQ_PH_ASSEMBLE, st);
     AFQ_RET(launch_emix(w->eloc.as<double2>(), w->weights.as<double>(), nw, emix_out, st));
   }
-  // propagate
-  if (s->prec == AFQ_FP64) AFQ_RET(propagate<double>(s, w, order));
-  else AFQ_RET(propagate<float>(s, w, order));
+  AFQ_RET(propagate_walkers(s, w, order, w->coef.p, w->W.as<double2>(), w->Wn.as<double2>()));
   // new overlap (log det only) and the phaseless weight
   {
     TraceScope tw(AFQ_PH_WEIGHT, st);
@@ -360,6 +375,7 @@ int walkers_comb(afq_walkers w, double xi, int* src_out, double* total_out) {
   AFQ_RET(launch_comb_apply(w->W.as<double2>(), w->Wn.as<double2>(), per, nw, w->comb_src.as<int>(),
                             w->comb_out.as<double>(), w->weights.as<double>(), w->alive.as<int>(), st));
   AFQ_TRY_HIP(hipMemcpyAsync(w->W.p, w->Wn.p, (size_t)nw * per * 16, hipMemcpyDeviceToDevice, st));
+  AFQ_RET(bp_comb_gather(w, w->comb_src.as<int>()));
   if (src_out) {
     AFQ_TRY_HIP(hipMemcpyAsync(src_out, w->comb_src.p, (size_t)nw * sizeof(int), hipMemcpyDeviceToHost, st));
     AFQ_TRY_HIP(hipStreamSynchronize(st));

@@ -8,7 +8,7 @@ import pytest
 
 from oracle import afqmc
 from paper_2003_01831_amd import synth
-from gpu_util import rel_vec, to_np
+from gpu_util import rel_fro, rel_vec, to_np
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -47,3 +47,38 @@ def test_full_size_sampled_walkers(full, prec, tol):
     wprev = np.vstack([np.ones(nw), g["weights"][:-1]])
     ref = np.sum(wprev * g["eloc"].real, axis=1) / np.sum(wprev, axis=1)
     assert rel_vec(g["emix"], ref) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-5), ("fp64", 1e-10)])
+def test_full_size_back_propagation(full, prec, tol):
+    """Back-propagated 1-RDM over a 2-step window at the full size. With all 512
+    walkers alive the trace of every spin block must be its electron count; with
+    only the 4 sampled walkers alive (the others ride along frozen at weight 0,
+    same launches) the estimate must match the oracle's over those 4."""
+    from paper_2003_01831_amd import api
+    cfg, s, pre = full
+    nw, n_bp, dt = cfg["n_walkers"], 2, cfg["dt"]
+    fields = synth.make_fields(n_bp, nw, cfg["n_chol"], seed=cfg["field_seed"])
+    sysg = api.System.from_synth(s, precision=prec)
+    wk = api.Walkers(sysg, nw)
+    wk.bp_begin(n_bp)
+    wk.step(n_bp, dt, fields=fields, qr_every=cfg["qr_every"])
+    P, _ = wk.bp_rdm1(qr_every=cfg["qr_every"])
+    P = to_np(P)
+    for sp, n in enumerate((s.n_up, s.n_dn)):
+        assert abs(np.trace(P[sp]) - n) < 1e-9 * n
+    del wk
+    sample = np.array([0, 137, 300, 511])
+    w0 = np.zeros(nw)
+    w0[sample] = 1.0
+    wk = api.Walkers(sysg, nw, None, w0)
+    wk.bp_begin(n_bp)
+    wk.step(n_bp, dt, fields=fields, qr_every=cfg["qr_every"])
+    P, wsum = wk.bp_rdm1(qr_every=cfg["qr_every"])
+    o = afqmc.run(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, synth.trial_walkers(s, 4), np.ones(4),
+                  fields[:, sample], dt, qr_every=cfg["qr_every"], pre=pre, bp_start=0, bp_len=n_bp)
+    ref = afqmc.back_propagated_rdm1(pre["B1"], s.chol, s.phi_t, s.n_up, s.n_dn, o["bp_W0"], o["bp_coefs"],
+                                     o["bp_weights"], order=6, qr_every=cfg["qr_every"])
+    err = rel_fro(to_np(P), ref)
+    print(prec, f"full-size bp rdm1 rel err {err:.2e}")
+    assert err < tol
