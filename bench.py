@@ -271,6 +271,37 @@ def main(argv=None):
     torch.cuda.synchronize()
     extra["comb_ms"] = round((time.perf_counter() - t) / 5 * 1e3, 3)
     wk_pc.close()
+    # back-propagated 1-RDM at this size: a window of 2 QR periods recorded by
+    # ordinary steps, then the estimator (reversed walk of the trial + GEMMs)
+    n_bp = 2 * qr
+    wk_bp = api.Walkers(sysg, nw)
+    wk_bp.step(1, dt, seed=12, qr_every=qr, e_shift=e_var)
+    wk_bp.bp_begin(n_bp)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    wk_bp.step(n_bp, dt, seed=12, qr_every=qr, e_shift=e_var)
+    torch.cuda.synchronize()
+    rec_ms = (time.perf_counter() - t) / n_bp * 1e3
+    lib.afq_trace_reset()
+    lib.afq_trace_enable(1)
+    t = time.perf_counter()
+    P, _ = wk_bp.bp_rdm1(qr_every=qr)
+    torch.cuda.synchronize()
+    bp_ms = (time.perf_counter() - t) * 1e3
+    lib.afq_trace_enable(0)
+    bph = trace_phases(lib, _lib)
+    lib.afq_trace_reset()
+    Pn = P.cpu().numpy()
+    prop_ms = sum(bph[k][0] for k in ("abuild", "taylor") if k in bph)
+    est_flop = 2 * 8.0 * M * M * nw * nu      # P^s = Q Y^T over nw*n stacked columns, complex FP64
+    extra["back_propagation"] = {
+        "n_bp": n_bp, "recording_step_ms": round(rec_ms, 3), "rdm1_ms": round(bp_ms, 3),
+        "rdm1_ms_per_window_step": round(bp_ms / n_bp, 3),
+        "reverse_propagation_ms": round(prop_ms, 3), "qr_ms": round(bph.get("qr", (0.0, 0))[0], 3),
+        "estimator_gemm_gflop": round(est_flop / 1e9, 3),
+        "trace_err": float(max(abs(np.trace(Pn[0]).real - nu), abs(np.trace(Pn[1]).real - nd)))}
+    del P
+    wk_bp.close()
     if a.compare_steps > 0:
         for prec in ("fp64", "cfp32", "bf16x3"):
             if prec == a.precision:

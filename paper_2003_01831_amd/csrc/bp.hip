@@ -16,6 +16,7 @@
 #include <cmath>
 #include "common.h"
 #include "step_kernels.h"
+#include "trace.h"
 
 static size_t coef_elem(int prec) { return prec == AFQ_FP64 ? 16 : 8; }
 
@@ -122,6 +123,7 @@ int bp_rdm1(afq_walkers w, int qr_every, double* rdm_out, double* wsum_out) {
     AFQ_RET(propagate_walkers(s, w, w->bp_order, w->bp_coef.as<char>() + (size_t)j * slot, cur, oth));
     std::swap(cur, oth);
     if (qr_every > 0 && (t + 1) % qr_every == 0) {
+      TraceScope tr(AFQ_PH_QR, st);
       AFQ_RET(qr_orbitals(s, w, cur, w->theta.as<double2>(), oth));
       std::swap(cur, oth);
     }
