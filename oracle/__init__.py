@@ -19,5 +19,9 @@ Parity status per function (pins in tests/test_oracle_*.py):
                                                            in the FCI space, L=0 ground-state
                                                            density, invariances, walk
                                                            bookkeeping incl. comb ancestry)
+  msd.overlap / local_energy, run(msd=...)                 pinned (CI-vector matrix elements in
+                                                           the FCI space, orthonormality,
+                                                           zero variance of a complete
+                                                           expansion, one-determinant limit)
   philox.philox4x32_10                                     pinned (published KAT vectors)
 """

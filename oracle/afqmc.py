@@ -192,7 +192,7 @@ def prepare(h1, chol, phi_t, n_up, n_dn, dt):
 
 def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
         e_shift=0.0, order=6, e_core=0.0, energy="half", record_walkers=False, pre=None,
-        fb_cap=0.0, w_cap=0.0, comb_every=0, comb_xi=None, bp_start=None, bp_len=0):
+        fb_cap=0.0, w_cap=0.0, comb_every=0, comb_xi=None, bp_start=None, bp_len=0, msd=None):
     """Run len(fields) steps. fields[k, w, n] are the standard-normal HS fields.
     `pre` may hold prepare(h1, chol, phi_t, n_up, n_dn, dt) computed beforehand.
 
@@ -213,6 +213,10 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
     drawn by walker w in step bp_start + j (zero for frozen walkers), and
     out["bp_weights"] the weights at the end of the window. A comb inside the
     window hands every copy its source walker's history (ket and coefficients).
+    With msd = dict(dets=[...], coeffs=[...]) the trial is the orthogonal
+    multi-determinant expansion of oracle/msd.py (phi_t is then unused):
+    overlaps, E_L and the force bias come from its determinant sums, and the
+    recorded parts are (E1, E2, 0) with E2 the whole two-body term.
     """
     M = h1.shape[0]
     nw = W0.shape[0]
@@ -221,9 +225,17 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
     B1, ht, Lt = pre["B1"], pre["ht"], pre["Lt"]
     W = W0.astype(np.complex128).copy()
     w = np.asarray(weights0, dtype=np.float64).copy()
+    if msd is not None:
+        from . import msd as msd_mod
+
+        def log_ovlp(Wi):
+            return np.log(msd_mod.overlap(msd["dets"], msd["coeffs"], Wi, n_up, n_dn))
+    else:
+        def log_ovlp(Wi):
+            return theta(phi_t, Wi, n_up, n_dn)[1]
     logO = np.empty(nw, dtype=np.complex128)
     for i in range(nw):
-        _, logO[i] = theta(phi_t, W[i], n_up, n_dn)
+        logO[i] = log_ovlp(W[i])
     alive = w > 0
     n_steps = fields.shape[0]
     out = dict(emix=np.zeros(n_steps), eloc=np.zeros((n_steps, nw), np.complex128),
@@ -244,7 +256,11 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
             open_window()
         vb = np.zeros((nw, chol.shape[0]), np.complex128)
         for i in range(nw):
-            if energy == "plain":
+            if msd is not None:
+                e, e1, e2, vb[i] = msd_mod.local_energy(h1, chol, msd["dets"], msd["coeffs"], W[i], n_up, n_dn,
+                                                        e_core)
+                parts = (e1, e2, 0.0)
+            elif energy == "plain":
                 e, e1, ej, ek = local_energy_plain(h1, chol, phi_t, W[i], n_up, n_dn, e_core)
                 parts = (e1, ej, ek)
                 G = greens_function(phi_t, W[i], n_up, n_dn)
@@ -264,7 +280,7 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
             if in_window(k):
                 out["bp_coefs"][k - bp_start, i] = 1j * np.sqrt(dt) * (x - xbar)
             Wn = B1 @ taylor_apply(A, B1 @ W[i], order)
-            _, logOn = theta(phi_t, Wn, n_up, n_dn)
+            logOn = log_ovlp(Wn)
             log_r = logOn - logO[i]
             r = np.exp(log_r)
             log_I = log_r + importance_log_factor(x, xbar) + dt * e_shift

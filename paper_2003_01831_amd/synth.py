@@ -99,6 +99,44 @@ def random_weights(n_walkers: int, seed: int, lo: float = 0.5, hi: float = 1.5) 
     return rng.uniform(lo, hi, n_walkers)
 
 
+def make_msd(sys: System, n_det: int, n_occ_act: int, n_vir_act: int, k_max: int, seed: int,
+             decay: float = 0.3):
+    """Orthogonal multi-determinant trial for `sys`: the basis C holds every
+    eigenvector of h1 with the sign rule of the trial (its first n columns are
+    the trial's spin blocks); determinant 0 is the reference and the others
+    draw, per spin, k <= k_max holes among the n_occ_act highest occupied and
+    as many particles among the n_vir_act lowest virtual orbitals (holes and
+    particles each ascending, paired in that order), every (up, down) pair
+    distinct. Coefficients: 1 for the reference, complex normal times
+    decay^(k_up + k_dn) otherwise. Returns (C (M x M complex128), excitations,
+    coeffs (complex128)); excitations[I] = ((holes_up, parts_up), (holes_dn, parts_dn))."""
+    rng = np.random.default_rng(seed)
+    C = _lowest_eigvecs(sys.h1, sys.M).astype(np.complex128)
+    seen = {((), (), (), ())}
+    exc = [(((), ()), ((), ()))]
+    coeffs = [1.0 + 0.0j]
+    tries = 0
+    while len(exc) < n_det:
+        tries += 1
+        if tries > 100 * n_det:
+            raise ValueError("make_msd: the active space has too few distinct determinants")
+        per_spin = []
+        for n in (sys.n_up, sys.n_dn):
+            k = int(rng.integers(0, k_max + 1))
+            k = min(k, n_occ_act, n_vir_act, n)
+            holes = tuple(sorted(rng.choice(np.arange(n - min(n_occ_act, n), n), k, replace=False).tolist()))
+            parts = tuple(sorted(rng.choice(np.arange(n, min(n + n_vir_act, sys.M)), k, replace=False).tolist()))
+            per_spin.append((holes, parts))
+        key = per_spin[0] + per_spin[1]
+        if key in seen:
+            continue
+        seen.add(key)
+        exc.append(tuple(per_spin))
+        rank = len(per_spin[0][0]) + len(per_spin[1][0])
+        coeffs.append(decay ** rank * (rng.standard_normal() + 1j * rng.standard_normal()) / np.sqrt(2.0))
+    return C, exc, np.asarray(coeffs, dtype=np.complex128)
+
+
 # ---------------------------------------------------------------------------
 # Named workloads. Seeds: systems 1..5, fields 1001..1005, uneven systems 4000+s.
 # ---------------------------------------------------------------------------
