@@ -97,6 +97,29 @@ int afq_system_create(afq_system *out, int M, int n_up, int n_dn, int n_chol,
 /* Switches the contraction precision (prepares the packed operand copies;
  * synchronises). */
 int afq_system_set_precision(afq_system s, int precision);
+/* Orthogonal multi-determinant trial (the multi-determinant paragraph of
+ * Section "Auxiliary Field Quantum Monte Carlo"): psi_T = sum_I c_I |D_I>.
+ *   C       device, M*M complex128 orthonormal basis (|C^H C - I| <= 1e-10);
+ *           its first n_up (n_dn) columns must equal the up (down) block of
+ *           the system's trial to 1e-12, which is the reference determinant
+ *   n_det   number of determinants (0 detaches the expansion: back to phi_t)
+ *   coeffs  host, n_det complex128 c_I
+ *   exc     host, n_det*2*9 int32: per determinant and spin (up first) the
+ *           rank k <= 4, then 4 hole slots (reference columns, < n), then 4
+ *           particle orbitals (columns of C, >= n); entries past k ignored.
+ *           D_I puts particle q in the column of hole q of the reference.
+ * Every determinant needs its own occupation (the expansion is orthogonal).
+ * Later energies, force biases and overlap ratios use psi_T through
+ * Sherman-Morrison-Woodbury ratios and cofactor expansions of the rank-k
+ * changes (no determinant is inverted, so walkers orthogonal to some D_I are
+ * exact); a walker whose overlap with the reference determinant is singular
+ * counts as singular. FP64 mode only; back-propagation and the adjoint need a
+ * single determinant. Limits per spin: 64 electrons, 16 active holes, 32
+ * active virtual orbitals, 256 distinct excitations (AFQ_E_UNSUPPORTED
+ * beyond); AFQ_E_INVALID for a malformed or non-orthogonal expansion.
+ * Synchronises. */
+int afq_system_set_msd(afq_system s, const double *C, int n_det, const double *coeffs,
+                       const int32_t *exc);
 /* Frees device memory. NULL-safe. */
 int afq_system_destroy(afq_system s);
 

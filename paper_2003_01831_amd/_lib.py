@@ -22,6 +22,7 @@ _vp, _i, _d, _u64, _u32 = C.c_void_p, C.c_int, C.c_double, C.c_uint64, C.c_uint3
 SIGNATURES = {
     "afq_system_create": (_i, [C.POINTER(_vp), _i, _i, _i, _i, _vp, _vp, _vp, _d, _i, _vp]),
     "afq_system_set_precision": (_i, [_vp, _i]),
+    "afq_system_set_msd": (_i, [_vp, _vp, _i, _vp, _vp]),
     "afq_system_destroy": (_i, [_vp]),
     "afq_walkers_create": (_i, [C.POINTER(_vp), _vp, _i, _vp, _vp]),
     "afq_walkers_destroy": (_i, [_vp]),

@@ -64,6 +64,31 @@ class System:
         check(self.lib.afq_system_set_precision(self.handle, PRECISION[precision]))
         self.precision = precision
 
+    MSD_KMAX = 4
+
+    def set_msd(self, basis, excitations, coeffs):
+        """Orthogonal multi-determinant trial: basis (M x M orthonormal, its first
+        n columns equal to each spin block of phi_t); excitations[I] =
+        ((holes_up, parts_up), (holes_dn, parts_dn)) with particle p_q taking the
+        slot of hole h_q; coeffs[I] complex. Empty excitations detach it."""
+        n = len(excitations)
+        k = self.MSD_KMAX
+        table = np.zeros((max(n, 1), 2, 1 + 2 * k), dtype=np.int32)
+        for i, e in enumerate(excitations):
+            for sp in range(2):
+                holes, parts = e[sp]
+                if len(holes) != len(parts) or len(holes) > k:
+                    raise ValueError("each spin needs as many particles as holes, at most %d" % k)
+                table[i, sp, 0] = len(holes)
+                table[i, sp, 1:1 + len(holes)] = holes
+                table[i, sp, 1 + k:1 + k + len(parts)] = parts
+        c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.complex128).reshape(-1))
+        if c.size != n:
+            raise ValueError("one coefficient per determinant")
+        self._msd_basis = _as_dev(basis, torch.complex128)
+        check(self.lib.afq_system_set_msd(self.handle, _ptr(self._msd_basis), n, c.ctypes.data_as(C.c_void_p),
+                                          table.ctypes.data_as(C.c_void_p)))
+
     def close(self):
         if getattr(self, "handle", None):
             self.lib.afq_system_destroy(self.handle)

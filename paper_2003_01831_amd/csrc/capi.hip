@@ -48,7 +48,14 @@ int afq_system_create(afq_system* out, int M, int n_up, int n_dn, int n_chol, co
 int afq_system_set_precision(afq_system s, int precision) {
   AFQ_CHECK(s, AFQ_E_INVALID, "afq_system_set_precision: system is NULL");
   AFQ_CHECK(precision >= AFQ_FP64 && precision <= AFQ_BF16X3, AFQ_E_INVALID, "unknown precision");
+  AFQ_CHECK(s->msd_n == 0 || precision == AFQ_FP64, AFQ_E_UNSUPPORTED,
+            "afq_system_set_precision: a multi-determinant trial runs in FP64 mode");
   AFQ_GUARD(AFQ_RET(check_device(s)); return system_prepare_pack(s, precision);)
+}
+
+int afq_system_set_msd(afq_system s, const double* C, int n_det, const double* coeffs, const int32_t* exc) {
+  AFQ_CHECK(s, AFQ_E_INVALID, "afq_system_set_msd: system is NULL");
+  AFQ_GUARD(AFQ_RET(check_device(s)); return msd_set(s, C, n_det, coeffs, exc);)
 }
 
 int afq_system_destroy(afq_system s) {
@@ -77,7 +84,8 @@ int afq_walkers_get(afq_walkers w, double* W, double* weights, double* logovlp, 
     if (alive) AFQ_TRY_HIP(hipMemcpyAsync(alive, w->alive.p, w->nw * 4, hipMemcpyDeviceToDevice, st));
     if (logovlp) {
       AFQ_RET(walkers_alloc_scratch(w));
-      AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), false, w->logdet.as<double2>()));
+      AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), s->msd_n > 0, w->logdet.as<double2>()));
+      if (s->msd_n > 0) AFQ_RET(msd_overlap(s, w, w->logdet.as<double2>(), st));
       AFQ_RET(launch_logovlp(w->logdet.as<double2>(), w->nw, reinterpret_cast<double2*>(logovlp), st));
     }
     if (counter) *counter = w->counter;
@@ -179,6 +187,7 @@ int afq_step(afq_system s, afq_walkers w, int n_steps, double dt, const double* 
 int afq_bp_begin(afq_walkers w, int n_bp) {
   AFQ_CHECK(w, AFQ_E_INVALID, "afq_bp_begin: walkers is NULL");
   AFQ_CHECK(n_bp >= 0 && n_bp <= (1 << 20), AFQ_E_INVALID, "afq_bp_begin: n_bp must be in [0, 2^20]");
+  AFQ_CHECK(w->sys->msd_n == 0, AFQ_E_UNSUPPORTED, "afq_bp_begin: back-propagation needs a single-determinant trial");
   AFQ_GUARD(AFQ_RET(check_device(w->sys)); return bp_begin(w, n_bp);)
 }
 
@@ -221,6 +230,7 @@ int afq_energy_backward(afq_system s, afq_walkers w, double scale, double* d_h1,
   AFQ_CHECK(s && w, AFQ_E_INVALID, "afq_energy_backward: NULL handle");
   AFQ_CHECK(w->sys == s, AFQ_E_STATE, "afq_energy_backward: walkers belong to another system");
   AFQ_CHECK(std::isfinite(scale), AFQ_E_INVALID, "afq_energy_backward: scale is not finite");
+  AFQ_CHECK(s->msd_n == 0, AFQ_E_UNSUPPORTED, "afq_energy_backward: needs a single-determinant trial");
   AFQ_GUARD(AFQ_RET(check_device(s)); return energy_backward(s, w, scale, d_h1, d_chol, d_walkers);)
 }
 

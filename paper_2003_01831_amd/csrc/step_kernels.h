@@ -20,6 +20,8 @@ struct AssembleArgs {
   double2* parts;          // nw x 3 (optional)
   double2* vbar_out;       // nw x X (optional)
   double2* lfac;           // nw (when coefficients are produced)
+  const double2* parts_in; // nw x 3 (E1, EJ, EK) given instead of computed (multi-determinant trial)
+  const double2* vbar_in;  // nw x X force bias given with parts_in
 };
 
 struct WeightArgs {

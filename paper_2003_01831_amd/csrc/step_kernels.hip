@@ -284,7 +284,9 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs a, CT* __res
   const long per = (long)a.ntot * a.M;
   const double2* th = a.thetaT + w * per;
   double2 v[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
-  for (long e = t; e < per; e += 256) v[0] = cadd(v[0], cmul(a.ht[e], th[e]));
+  const bool given = a.parts_in != nullptr;
+  if (!given)
+    for (long e = t; e < per; e += 256) v[0] = cadd(v[0], cmul(a.ht[e], th[e]));
   const double sdt = sqrt(a.dt);
   const double2* tro0 = a.tro + (long)w * 2 * a.X;
   const double2* tro1 = tro0 + a.X;
@@ -308,9 +310,11 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs a, CT* __res
     for (int h = 0; h < 2; ++h) {
       const int n = 2 * j + h;
       if (n >= a.X) break;
-      const double2 vb = cadd(tro0[n], tro1[n]);
-      v[1] = cadd(v[1], cmul(vb, vb));
-      v[2] = cadd(v[2], cadd(troo0[n], troo1[n]));
+      const double2 vb = given ? a.vbar_in[(long)w * a.X + n] : cadd(tro0[n], tro1[n]);
+      if (!given) {
+        v[1] = cadd(v[1], cmul(vb, vb));
+        v[2] = cadd(v[2], cadd(troo0[n], troo1[n]));
+      }
       if (a.vbar_out) a.vbar_out[(long)w * a.X + n] = vb;
       if (coef) {
         const double x = xs[h];
@@ -330,7 +334,9 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs a, CT* __res
   }
   block_sum<4>(v);
   if (t == 0) {
-    const double2 e1 = v[0], ej = cscale(v[1], 0.5), ek = cscale(v[2], -0.5);
+    const double2 e1 = given ? a.parts_in[3 * w] : v[0];
+    const double2 ej = given ? a.parts_in[3 * w + 1] : cscale(v[1], 0.5);
+    const double2 ek = given ? a.parts_in[3 * w + 2] : cscale(v[2], -0.5);
     const double2 el = make_double2(a.e_core + e1.x + ej.x + ek.x, e1.y + ej.y + ek.y);
     a.eloc[w] = el;
     if (a.eloc_out) a.eloc_out[w] = el;

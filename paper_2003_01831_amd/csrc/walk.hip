@@ -115,20 +115,28 @@ static int coulomb_fp64(afq_system s, afq_walkers w, hipStream_t st) {
   return AFQ_OK;
 }
 
-// Theta (already computed) -> exchange traces -> assembly (coef optional)
-static int energy_from_theta(afq_system s, afq_walkers w, AssembleArgs& a, bool want_coef) {
+// Theta (already computed) -> exchange traces -> assembly (coef optional).
+// With a multi-determinant trial the determinant sums replace the traces and
+// log(sum_I conj(c_I) R_I) is added to logdet (the current walkers' log det).
+static int energy_from_theta(afq_system s, afq_walkers w, AssembleArgs& a, bool want_coef, double2* logdet) {
   hipStream_t st = s->stream;
-  {
-    TraceScope t(AFQ_PH_PACK, st);
-    AFQ_RET(pack_theta(s, w, st));
-  }
-  for (int sp = 0; sp < 2; ++sp) {
-    TraceScope t(AFQ_PH_EXCHANGE, st);
-    AFQ_RET(exchange_launch(s, w, sp, st));
-  }
-  if (s->prec == AFQ_BF16X3) {
-    TraceScope t(AFQ_PH_COULOMB, st);
-    AFQ_RET(coulomb_fp64(s, w, st));
+  if (s->msd_n > 0) {
+    AFQ_RET(msd_energy(s, w, logdet, st));
+    a.parts_in = w->msd_parts.as<double2>();
+    a.vbar_in = w->msd_vbar.as<double2>();
+  } else {
+    {
+      TraceScope t(AFQ_PH_PACK, st);
+      AFQ_RET(pack_theta(s, w, st));
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+      TraceScope t(AFQ_PH_EXCHANGE, st);
+      AFQ_RET(exchange_launch(s, w, sp, st));
+    }
+    if (s->prec == AFQ_BF16X3) {
+      TraceScope t(AFQ_PH_COULOMB, st);
+      AFQ_RET(coulomb_fp64(s, w, st));
+    }
   }
   TraceScope t(AFQ_PH_ASSEMBLE, st);
   a.nw = w->nw; a.ntot = s->ntot; a.M = s->M; a.X = s->X;
@@ -151,7 +159,7 @@ int energy_call(afq_system s, afq_walkers w, double* eloc_out, double* parts_out
   a.eloc_out = reinterpret_cast<double2*>(eloc_out);
   a.parts = reinterpret_cast<double2*>(parts_out);
   a.vbar_out = reinterpret_cast<double2*>(vbar_out);
-  AFQ_RET(energy_from_theta(s, w, a, false));
+  AFQ_RET(energy_from_theta(s, w, a, false, w->logdet.as<double2>()));
   if (emix_out) AFQ_RET(launch_emix(w->eloc.as<double2>(), w->weights.as<double>(), w->nw, emix_out, s->stream));
   return AFQ_OK;
 }
@@ -278,7 +286,7 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
   a.sys_id = sys_id;
   a.fb_cap = w->fb_cap;
   a.eloc_out = reinterpret_cast<double2*>(eloc_out);
-  AFQ_RET(energy_from_theta(s, w, a, true));
+  AFQ_RET(energy_from_theta(s, w, a, true, w->logdet.as<double2>()));
   if (coef_record)   // back-propagation window: conj(c) of this step, the coefficients of B^H
     AFQ_RET(launch_conj_copy(w->coef.p, coef_record, (long)nw * s->X, s->prec != AFQ_FP64, st));
   if (emix_out) {
@@ -289,7 +297,8 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
   // new overlap (log det only) and the phaseless weight
   {
     TraceScope tw(AFQ_PH_WEIGHT, st);
-    AFQ_RET(compute_overlap_theta(s, w, w->Wn.as<double2>(), false, w->logdet_new.as<double2>()));
+    AFQ_RET(compute_overlap_theta(s, w, w->Wn.as<double2>(), s->msd_n > 0, w->logdet_new.as<double2>()));
+    if (s->msd_n > 0) AFQ_RET(msd_overlap(s, w, w->logdet_new.as<double2>(), st));
     WeightArgs wa{};
     wa.logdet_new = w->logdet_new.as<double2>();
     wa.logdet_cur = w->logdet.as<double2>();
