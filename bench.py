@@ -158,6 +158,81 @@ def bench_uneven(a, torch, synth, api, _lib):
     return 0
 
 
+def bench_msd(a, torch, synth, api, _lib):
+    """Orthogonal multi-determinant trial (256 determinants, rank <= 4 per
+    spin) at M=128, 16+16 electrons, 512 Cholesky vectors, 256 walkers, FP64."""
+    cfg = dict(synth.WORKLOADS["msd_m128"])
+    M, nu, nd, X = cfg["M"], cfg["n_up"], cfg["n_dn"], cfg["n_chol"]
+    nw = a.walkers or cfg["n_walkers"]
+    dt, qr = cfg["dt"], cfg["qr_every"]
+    lib = _lib.load()
+    s = synth.make_system(M, nu, nd, X, seed=cfg["seed"])
+    C, exc, coeffs = synth.make_msd(s, cfg["n_det"], cfg["occ_act"], cfg["vir_act"], cfg["k_max"],
+                                    seed=cfg["msd_seed"])
+    sysg = api.System.from_synth(s, precision="fp64")
+    sysg.set_msd(C, exc, coeffs)
+    probe = api.Walkers(sysg, 1)
+    e_var = float(probe.energy()[3][0])
+    probe.close()
+    wk = api.Walkers(sysg, nw)
+    wk.step(a.warmup, dt, seed=11, qr_every=qr, e_shift=e_var, outputs=())
+    torch.cuda.synchronize()
+    lib.afq_trace_reset()
+    lib.afq_trace_enable(1)
+    t = time.perf_counter()
+    out = wk.step(a.steps, dt, seed=11, qr_every=qr, e_shift=e_var, outputs=("emix",))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    lib.afq_trace_enable(0)
+    ph = trace_phases(lib, _lib)
+    lib.afq_trace_reset()
+    value = nw * a.steps / wall
+    # the Omega GEMM: rows (X + 1) x (max(N_up, N_dn) + active virtuals of both spins), columns
+    # every walker's N_up + N_dn orbitals, contraction over M; 8 flop per complex multiply-add
+    nv = len({p for e in exc for sp in range(2) for p in e[sp][1]})
+    nr = max(nu, nd) + nv
+    om_ms, om_cnt = ph["msd_omega"]
+    om_avg_s = om_ms / 1e3 / max(om_cnt, 1)
+    chunks = max(om_cnt // max(a.steps, 1), 1)
+    per_launch = 8.0 * (X + 1) * nr * M * (nu + nd) * nw / chunks
+    achieved = per_launch / om_avg_s / 1e12
+    peak = PEAK_TFLOPS["fp64"]
+    cpu = None
+    if not a.no_cpu:
+        from oracle import msd as omsd
+        dets = omsd.determinants(C, nu, nd, exc)
+        W1 = synth.trial_walkers(s, 1)[0] + 0.05 * np.random.default_rng(5).standard_normal((M, nu + nd))
+        nsub = 16
+        tc = time.perf_counter()
+        omsd.local_energy(s.h1, s.chol, dets[:nsub], coeffs[:nsub], W1, nu, nd)
+        tc = time.perf_counter() - tc
+        per_ws = tc * cfg["n_det"] / nsub          # one walker's energy over all determinants
+        cpu = {"value": round(1.0 / per_ws, 6), "unit": "walker-steps/s", "cores": os.cpu_count(),
+               "kind": "oracle",
+               "sample": f"local energy of 1 walker over {nsub} of the {cfg['n_det']} determinants "
+                         f"({tc:.1f}s), scaled by {cfg['n_det']}/{nsub}; excludes the propagation"}
+    line = {
+        "metric": "walker-steps/s, orthogonal multi-determinant trial (FP64)",
+        "value": round(value, 3), "unit": "walker-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(wall / a.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"msd_m128: M={M}, N_up=N_dn={nu}, Nchol={X}, {nw} walkers, {cfg['n_det']} "
+                               f"determinants (rank <= {cfg['k_max']} per spin, active {cfg['occ_act']} occ + "
+                               f"{cfg['vir_act']} virt), dt={dt}, QR every {qr}",
+                   "precision": "fp64", "walkers": nw, "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "[C_ref^H; C_V^H] L^g Theta GEMM (FP64 complex x complex), both spins, one walker chunk per launch",
+                     "flop_per_launch": per_launch, "avg_launch_ms": round(om_avg_s * 1e3, 3),
+                     "launches": om_cnt},
+        "cpu_baseline": cpu,
+        "phase_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in ph.items()},
+        "emix_last": float(out["emix"][-1].item()),
+    }
+    print(json.dumps(line))
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +268,8 @@ def main(argv=None):
 
     if a.workload == "uneven24":
         return bench_uneven(a, torch, synth, api, _lib)
+    if a.workload == "msd_m128":
+        return bench_msd(a, torch, synth, api, _lib)
 
     cfg = dict(synth.WORKLOADS[a.workload])
     M, nu, nd, X = cfg["M"], cfg["n_up"], cfg["n_dn"], cfg["n_chol"]

@@ -311,7 +311,11 @@ enum {
   AFQ_PH_TAYLOR = 6,    /* B1 T_K(A) B1 W                                     */
   AFQ_PH_WEIGHT = 7,    /* new overlap, phaseless weight, walker commit       */
   AFQ_PH_QR = 8,        /* CholeskyQR2                                         */
-  AFQ_TRACE_NPHASE = 9
+  AFQ_PH_MSD_OMEGA = 9, /* multi-determinant trial: [T^H; C_V^H] L^g Theta GEMM
+                           (one event pair per spin and walker chunk)          */
+  AFQ_PH_MSD_SUMS = 10, /* multi-determinant trial: C_V^H Theta, cofactors,
+                           small products and the determinant sums             */
+  AFQ_TRACE_NPHASE = 11
 };
 /* on != 0 starts recording event pairs around every traced phase. */
 int afq_trace_enable(int on);

@@ -15,7 +15,8 @@ AFQ_OK = 0
 STATUS = {0: "AFQ_OK", -1: "AFQ_E_INVALID", -2: "AFQ_E_NOMEM", -3: "AFQ_E_HIP", -4: "AFQ_E_SINGULAR",
           -5: "AFQ_E_STATE", -6: "AFQ_E_UNSUPPORTED"}
 PRECISION = {"fp64": 0, "cfp32": 1, "bf16x3": 2}
-PHASES = ["overlap", "pack", "exchange", "coulomb", "assemble", "abuild", "taylor", "weight", "qr"]
+PHASES = ["overlap", "pack", "exchange", "coulomb", "assemble", "abuild", "taylor", "weight", "qr", "msd_omega",
+          "msd_sums"]
 
 # every symbol declared in include/afq.h with its ctypes signature
 _vp, _i, _d, _u64, _u32 = C.c_void_p, C.c_int, C.c_double, C.c_uint64, C.c_uint32

@@ -131,14 +131,16 @@ struct afq_system_s {
   // orthogonal multi-determinant trial (msd_n == 0: the single determinant phi)
   int msd_n = 0;               // determinants
   int msd_no[2] = {0, 0};      // active holes per spin
-  int msd_nv[2] = {0, 0};      // active virtual orbitals per spin
   int msd_nexc[2] = {0, 0};    // distinct excitations per spin
+  int msd_nv = 0;              // active virtual orbitals (both spins)
+  int msd_nr = 0;              // rows per operator: max(n_up, n_dn) reference + msd_nv virtual
+  size_t msd_lds = 0;          // dynamic LDS bytes of the determinant-sum kernel
   DevBuf msd_cconj;            // n_det complex: conj(c_I)
   DevBuf msd_pair;             // n_det x 2 int: excitation index of each spin
-  DevBuf msd_exc[2];           // n_exc x (1 + 2 MSD_KMAX) int: rank, hole slots (into hact), particle slots (into V)
+  DevBuf msd_exc[2];           // n_exc x MSD_EXC int: rank, hole slots, particle slots, hole columns
   DevBuf msd_hact[2];          // n_o int: reference column of every active hole
-  DevBuf msd_cvh[2];           // n_v x M complex: C_V^H (active virtual orbitals)
-  DevBuf msd_lact[2];          // (X + 1) x (n + n_v) x M complex: [T^H; C_V^H] L^g, g = X is h1
+  DevBuf msd_cvh;              // msd_nv x M complex: C_V^H (active virtual orbitals)
+  DevBuf msd_lact;             // (X + 1) x msd_nr x M complex: [C_ref^H; C_V^H] L^g, g = X is h1
   int nspin_n(int s) const { return s == 0 ? n_up : n_dn; }
   int spin_off(int s) const { return s == 0 ? 0 : n_up; }
 };
@@ -187,9 +189,9 @@ struct afq_walkers_s {
   DevBuf emix_tmp;             // scalar scratch
   size_t scratch_prec = (size_t)-1;
   // multi-determinant scratch
-  DevBuf msd_tv[2];            // nw x n_v x n complex: C_V^H Theta per spin
-  DevBuf msd_cof[2];           // nw x n_exc x MSD_NCOF complex: det A and its cofactors of orders 1, 2
-  DevBuf msd_omega[2];         // chunk x (X + 1) x (n + n_v) x n complex: [T^H; C_V^H] L^g Theta
+  DevBuf msd_tv;               // nw x msd_nv x ntot complex: C_V^H Theta
+  DevBuf msd_d0[2];            // nw x n_exc complex: det A per spin
+  DevBuf msd_omega;            // (X + 1) msd_nr x chunk ntot complex: [C_ref^H; C_V^H] L^g Theta
   DevBuf msd_num;              // nw x (2 X + 1) complex: numerators (force bias, two-body per g, one-body)
   DevBuf msd_den;              // nw complex: sum_I conj(c_I) det A_I(up) det A_I(down)
   DevBuf msd_parts, msd_vbar;  // nw x 3 and nw x X complex: E1, E2, 0 and the force bias
@@ -266,8 +268,7 @@ int pack_theta(afq_system s, afq_walkers w, hipStream_t st);
 
 // orthogonal multi-determinant trial (msd.hip)
 constexpr int MSD_KMAX = 4;                                   // excitation rank per spin
-constexpr int MSD_NCOF = 1 + MSD_KMAX * MSD_KMAX + 36;        // det, cofactors of order 1 and 2
-constexpr int MSD_EXC = 1 + 2 * MSD_KMAX;                     // ints per excitation record
+constexpr int MSD_EXC = 1 + 3 * MSD_KMAX;                     // ints per device excitation record
 int msd_set(afq_system s, const double* C, int n_det, const double* coeffs, const int32_t* exc);
 int msd_alloc_scratch(afq_system s, afq_walkers w);
 // energy pieces at the walkers whose Theta and log det are current: adds log(sum_I conj(c) R_I)

@@ -23,9 +23,14 @@
 //   vbar_g = sum_I conj(c_I) N1^g / sum_I conj(c_I) R_I,
 // with, per determinant and operator (spins u, d):
 //   N1 = N1_u R_d + R_u N1_d,   N2 = (P2_u R_d + R_u P2_d + 2 N1_u N1_d) / 2.
-// Work per step: one FP64 MFMA GEMM per spin over (X + 1) operators (L^g and
-// h1) and the reference plus active-virtual rows, then one workgroup per
-// (walker, operator) for the small products and the determinant sums.
+// The determinant of A + e Y1 + e^2 Y2 is taken in truncated polynomial
+// arithmetic (three coefficients per entry, Laplace expansion for k <= 4), which
+// yields det A, its first- and second-order changes at once.
+// Work per step: one FP64 MFMA GEMM per walker chunk over (X + 1) operators
+// (L^g and h1) and the reference plus active-virtual rows (shared by both
+// spins), then one workgroup per (walker, operator) that stages its blocks in
+// LDS for the small products, the per-excitation polynomials and the
+// determinant sums.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -35,110 +40,141 @@
 #include "step_kernels.h"
 #include "trace.h"
 
-constexpr int MSD_MAX_N = 64;     // electrons per spin
-constexpr int MSD_MAX_NO = 16;    // active holes per spin
-constexpr int MSD_MAX_NV = 32;    // active virtual orbitals per spin
-constexpr int MSD_MAX_EXC = 256;  // distinct excitations per spin
-constexpr size_t MSD_OMEGA_BUDGET = size_t(2) << 30;   // bytes of Omega per spin and walker chunk
+constexpr int MSD_MAX_N = 64;       // electrons per spin
+constexpr int MSD_MAX_NO = 16;      // active holes per spin
+constexpr int MSD_MAX_NV = 32;      // active virtual orbitals
+constexpr int MSD_MAX_EXC = 256;    // distinct excitations per spin
+constexpr size_t MSD_MAX_LDS = 160 * 1024;
+constexpr size_t MSD_OMEGA_BUDGET = size_t(4) << 30;   // bytes of Omega per walker chunk
 
 // ---------------------------------------------------------------------------
-// small determinants: rows/columns of the k x k block not in the skip masks
+// truncated polynomials a + b e + c e^2 and their k x k determinants (k <= 4)
 // ---------------------------------------------------------------------------
-__device__ inline double2 det2(double2 a, double2 b, double2 c, double2 d) { return csub(cmul(a, d), cmul(b, c)); }
+struct P3 {
+  double2 a, b, c;
+};
+__device__ inline P3 pmul(const P3& x, const P3& y) {
+  return {cmul(x.a, y.a), cadd(cmul(x.a, y.b), cmul(x.b, y.a)),
+          cadd(cadd(cmul(x.a, y.c), cmul(x.b, y.b)), cmul(x.c, y.a))};
+}
+__device__ inline P3 padd(const P3& x, const P3& y) { return {cadd(x.a, y.a), cadd(x.b, y.b), cadd(x.c, y.c)}; }
+__device__ inline P3 psub(const P3& x, const P3& y) { return {csub(x.a, y.a), csub(x.b, y.b), csub(x.c, y.c)}; }
+__device__ inline P3 pdet2(const P3& a, const P3& b, const P3& c, const P3& d) { return psub(pmul(a, d), pmul(b, c)); }
 
-__device__ double2 sub_det(const double2 (&A)[MSD_KMAX][MSD_KMAX], int k, unsigned rskip, unsigned cskip) {
-  int r[MSD_KMAX], c[MSD_KMAX], m = 0, mc = 0;
-  for (int i = 0; i < k; ++i) {
-    if (!((rskip >> i) & 1)) r[m++] = i;
-    if (!((cskip >> i) & 1)) c[mc++] = i;
+__device__ P3 pdet(const P3 (&m)[MSD_KMAX][MSD_KMAX], int k) {
+  const double2 z = make_double2(0.0, 0.0);
+  if (k == 0) return {make_double2(1.0, 0.0), z, z};
+  if (k == 1) return m[0][0];
+  if (k == 2) return pdet2(m[0][0], m[0][1], m[1][0], m[1][1]);
+  if (k == 3) {
+    const P3 c0 = pdet2(m[1][1], m[1][2], m[2][1], m[2][2]);
+    const P3 c1 = pdet2(m[1][0], m[1][2], m[2][0], m[2][2]);
+    const P3 c2 = pdet2(m[1][0], m[1][1], m[2][0], m[2][1]);
+    return padd(psub(pmul(m[0][0], c0), pmul(m[0][1], c1)), pmul(m[0][2], c2));
   }
-  if (m == 0) return make_double2(1.0, 0.0);
-  if (m == 1) return A[r[0]][c[0]];
-  if (m == 2) return det2(A[r[0]][c[0]], A[r[0]][c[1]], A[r[1]][c[0]], A[r[1]][c[1]]);
-  // m = 3 or 4: expansion along the first remaining row
-  double2 s = make_double2(0.0, 0.0);
-  for (int j = 0; j < m; ++j) {
-    double2 minor;
-    if (m == 3) {
-      int cc[2], q = 0;
-      for (int t = 0; t < 3; ++t)
-        if (t != j) cc[q++] = c[t];
-      minor = det2(A[r[1]][cc[0]], A[r[1]][cc[1]], A[r[2]][cc[0]], A[r[2]][cc[1]]);
-    } else {
-      int cc[3], q = 0;
-      for (int t = 0; t < 4; ++t)
-        if (t != j) cc[q++] = c[t];
-      const double2 m0 = det2(A[r[2]][cc[1]], A[r[2]][cc[2]], A[r[3]][cc[1]], A[r[3]][cc[2]]);
-      const double2 m1 = det2(A[r[2]][cc[0]], A[r[2]][cc[2]], A[r[3]][cc[0]], A[r[3]][cc[2]]);
-      const double2 m2 = det2(A[r[2]][cc[0]], A[r[2]][cc[1]], A[r[3]][cc[0]], A[r[3]][cc[1]]);
-      minor = cadd(csub(cmul(A[r[1]][cc[0]], m0), cmul(A[r[1]][cc[1]], m1)), cmul(A[r[1]][cc[2]], m2));
+  // k = 4: Laplace expansion along rows (0, 1) with the complementary minors of rows (2, 3)
+  P3 acc = {z, z, z};
+  const int cp[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  for (int t = 0; t < 6; ++t) {
+    const int a = cp[t][0], b = cp[t][1], c = cp[5 - t][0], d = cp[5 - t][1];
+    const P3 top = pdet2(m[0][a], m[0][b], m[1][a], m[1][b]);
+    const P3 bot = pdet2(m[2][c], m[2][d], m[3][c], m[3][d]);
+    const P3 term = pmul(top, bot);
+    // sign (-1)^(0 + 1 + a + b): pairs (0,2) and (1,3) are negative
+    acc = (t == 1 || t == 4) ? psub(acc, term) : padd(acc, term);
+  }
+  return acc;
+}
+
+// det(A + e Y1 + e^2 Y2) for one excitation of rank K, entries read from LDS:
+// A[q][r] = T[v_q][col_r], Y[q][r] = Y[v_q][hs_r] (v: particle slots, col:
+// hole columns, hs: hole slots)
+template <int K>
+__device__ P3 pdet_lds(const double2* T, const double2* Y1, const double2* Y2, int n, int no, const int* ex) {
+  int v[K > 0 ? K : 1], col[K > 0 ? K : 1], hs[K > 0 ? K : 1];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    v[q] = ex[1 + MSD_KMAX + q];
+    col[q] = ex[1 + 2 * MSD_KMAX + q];
+    hs[q] = ex[1 + q];
+  }
+  auto E = [&](int q, int r) -> P3 {
+    const int yi = v[q] * no + hs[r];
+    return {T[v[q] * n + col[r]], Y1[yi], Y2[yi]};
+  };
+  const double2 z = make_double2(0.0, 0.0);
+  if constexpr (K == 0) {
+    return {make_double2(1.0, 0.0), z, z};
+  } else if constexpr (K == 1) {
+    return E(0, 0);
+  } else if constexpr (K == 2) {
+    return pdet2(E(0, 0), E(0, 1), E(1, 0), E(1, 1));
+  } else if constexpr (K == 3) {
+    const P3 c0 = pdet2(E(1, 1), E(1, 2), E(2, 1), E(2, 2));
+    const P3 c1 = pdet2(E(1, 0), E(1, 2), E(2, 0), E(2, 2));
+    const P3 c2 = pdet2(E(1, 0), E(1, 1), E(2, 0), E(2, 1));
+    return padd(psub(pmul(E(0, 0), c0), pmul(E(0, 1), c1)), pmul(E(0, 2), c2));
+  } else {
+    // Laplace expansion along rows (0, 1) against the complementary minors of rows (2, 3)
+    const int cp[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    P3 acc = {z, z, z};
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const int a = cp[t][0], b = cp[t][1], c = cp[5 - t][0], d = cp[5 - t][1];
+      const P3 term = pmul(pdet2(E(0, a), E(0, b), E(1, a), E(1, b)), pdet2(E(2, c), E(2, d), E(3, c), E(3, d)));
+      acc = (t == 1 || t == 4) ? psub(acc, term) : padd(acc, term);   // sign (-1)^(1 + a + b)
     }
-    const double2 term = cmul(A[r[0]][c[j]], minor);
-    s = (j & 1) ? csub(s, term) : cadd(s, term);
+    return acc;
   }
-  return s;
 }
 
-// pair index of rows (q1 < q2) among k rows, in the order (0,1),(0,2),(0,3),(1,2),(1,3),(2,3)
-__device__ inline int pair_index(int q1, int q2) {
-  return q1 == 0 ? q2 - 1 : (q1 == 1 ? q2 + 1 : 5);
+// fixed-order sum of one complex value over a 256-thread workgroup (wave
+// butterflies, then the four wave sums in order); every thread gets the total
+__device__ inline double2 wg_sum(double2 v, double2* scratch4) {
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off);
+    v.y += __shfl_xor(v.y, off);
+  }
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) scratch4[t >> 6] = v;
+  __syncthreads();
+  const double2 r = cadd(cadd(scratch4[0], scratch4[1]), cadd(scratch4[2], scratch4[3]));
+  __syncthreads();
+  return r;
 }
 
 // ---------------------------------------------------------------------------
-// per (walker, excitation): A = T_V[p][h], det A, first-order cofactors
-// cof1[q][r] = (-1)^(q+r) minor(q; r) and second-order cofactors
-// cof2[(q1,q2)][(r1,r2)] = (-1)^(q1+q2+r1+r2) minor({q1,q2}; {r1,r2})
+// per (walker, excitation): det A, A[q][r] = T_V[p_q][h_r]
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void msd_cof_kernel(const double2* __restrict__ tv, int n, int nv,
-                                                     const int* __restrict__ exc, const int* __restrict__ hact,
-                                                     int nexc, double2* __restrict__ cof, int det_only) {
+__global__ __launch_bounds__(64) void msd_ratio_kernel(const double2* __restrict__ tv, int nv, int ntot, int off,
+                                                       const int* __restrict__ exc, int nexc,
+                                                       double2* __restrict__ d0) {
   const int e = blockIdx.x * 64 + threadIdx.x, w = blockIdx.y;
   if (e >= nexc) return;
   const int* ex = exc + e * MSD_EXC;
   const int k = ex[0];
-  const double2* T = tv + (long)w * nv * n;
-  double2 A[MSD_KMAX][MSD_KMAX];
+  const double2* T = tv + (long)w * nv * ntot + off;
+  const double2 z = make_double2(0.0, 0.0);
+  P3 m[MSD_KMAX][MSD_KMAX];
   for (int q = 0; q < MSD_KMAX; ++q)
     for (int r = 0; r < MSD_KMAX; ++r)
-      A[q][r] = (q < k && r < k) ? T[ex[1 + MSD_KMAX + q] * n + hact[ex[1 + r]]] : make_double2(0.0, 0.0);
-  double2* out = cof + ((long)w * nexc + e) * MSD_NCOF;
-  out[0] = sub_det(A, k, 0u, 0u);
-  if (det_only) return;
-  for (int q = 0; q < MSD_KMAX; ++q)
-    for (int r = 0; r < MSD_KMAX; ++r) {
-      double2 v = make_double2(0.0, 0.0);
-      if (q < k && r < k) {
-        v = sub_det(A, k, 1u << q, 1u << r);
-        if ((q + r) & 1) v = make_double2(-v.x, -v.y);
-      }
-      out[1 + q * MSD_KMAX + r] = v;
-    }
-  for (int q1 = 0; q1 < MSD_KMAX; ++q1)
-    for (int q2 = q1 + 1; q2 < MSD_KMAX; ++q2)
-      for (int r1 = 0; r1 < MSD_KMAX; ++r1)
-        for (int r2 = r1 + 1; r2 < MSD_KMAX; ++r2) {
-          double2 v = make_double2(0.0, 0.0);
-          if (q2 < k && r2 < k) {
-            v = sub_det(A, k, (1u << q1) | (1u << q2), (1u << r1) | (1u << r2));
-            if ((q1 + q2 + r1 + r2) & 1) v = make_double2(-v.x, -v.y);
-          }
-          out[1 + MSD_KMAX * MSD_KMAX + pair_index(q1, q2) * 6 + pair_index(r1, r2)] = v;
-        }
+      m[q][r] = {(q < k && r < k) ? T[(long)ex[1 + MSD_KMAX + q] * ntot + ex[1 + 2 * MSD_KMAX + r]] : z, z, z};
+  d0[(long)w * nexc + e] = pdet(m, k).a;
 }
 
 // ---------------------------------------------------------------------------
 // per walker: den = sum_I conj(c_I) R_I(up) R_I(down); logdet[2w] += log den
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void msd_den_kernel(const double2* __restrict__ cconj, const int* __restrict__ pair,
-                                                      int ndet, const double2* __restrict__ cof0, int nexc0,
-                                                      const double2* __restrict__ cof1, int nexc1,
+                                                      int ndet, const double2* __restrict__ d0u, int nexc0,
+                                                      const double2* __restrict__ d0d, int nexc1,
                                                       double2* __restrict__ den, double2* __restrict__ logdet) {
   const int w = blockIdx.x, t = threadIdx.x;
   __shared__ double2 red[256];
   double2 acc = make_double2(0.0, 0.0);
   for (int I = t; I < ndet; I += 256) {
-    const double2 ru = cof0[((long)w * nexc0 + pair[2 * I]) * MSD_NCOF];
-    const double2 rd = cof1[((long)w * nexc1 + pair[2 * I + 1]) * MSD_NCOF];
+    const double2 ru = d0u[(long)w * nexc0 + pair[2 * I]];
+    const double2 rd = d0d[(long)w * nexc1 + pair[2 * I + 1]];
     acc = cadd(acc, cmul(cconj[I], cmul(ru, rd)));
   }
   red[t] = acc;
@@ -158,12 +194,13 @@ __global__ __launch_bounds__(256) void msd_den_kernel(const double2* __restrict_
 // small products, per-excitation polynomials, then the determinant sums
 // ---------------------------------------------------------------------------
 struct MsdPostArgs {
-  const double2* omega[2];   // chunk x (X+1) x (n + nv) x n
-  const double2* tv[2];      // nw x nv x n
-  const double2* cof[2];     // nw x nexc x NCOF
+  const double2* omega;      // (X + 1) nr rows x ldo columns (walker-major, ntot per walker)
+  long ldo;
+  const double2* tv;         // nw x nv x ntot
   const int* exc[2];
   const int* hact[2];
-  int n[2], nv[2], no[2], nexc[2];
+  int n[2], off[2], no[2], nexc[2];
+  int nmax, nv, nr, ntot, nexc_max;
   const int* pair;
   const double2* cconj;
   int ndet, X, w0;
@@ -171,125 +208,111 @@ struct MsdPostArgs {
 };
 
 __global__ __launch_bounds__(256) void msd_post_kernel(MsdPostArgs a) {
+  extern __shared__ double2 lds[];
   const int g = blockIdx.x, wl = blockIdx.y, w = a.w0 + wl, t = threadIdx.x;
-  __shared__ double2 P[MSD_MAX_N * MSD_MAX_NO];
-  __shared__ double2 Q[MSD_MAX_N * MSD_MAX_NO];
-  __shared__ double2 Y1[MSD_MAX_NV * MSD_MAX_NO];
-  __shared__ double2 Y2[MSD_MAX_NV * MSD_MAX_NO];
-  __shared__ double2 N1[2][MSD_MAX_EXC];
-  __shared__ double2 P2[2][MSD_MAX_EXC];
-  __shared__ double2 red[2][256];
+  const int nv = a.nv;
+  // persistent: N1, P2, D0 per spin and excitation; reduction scratch
+  double2* N1 = lds;
+  double2* P2 = N1 + 2 * a.nexc_max;
+  double2* D0 = P2 + 2 * a.nexc_max;
+  double2* red = D0 + 2 * a.nexc_max;          // 4 wave partials (x 2)
+  double2* work = red + 8;
   for (int sp = 0; sp < 2; ++sp) {
-    const int n = a.n[sp], nv = a.nv[sp], no = a.no[sp], nr = n + nv;
-    const double2* om = a.omega[sp] + ((long)wl * (a.X + 1) + g) * nr * n;
-    const double2* T = a.tv[sp] + (long)w * nv * n;
-    const int* hact = a.hact[sp];
-    // traces of the reference block: t0 = tr Omega0, q0 = tr Omega0^2
+    const int n = a.n[sp], no = a.no[sp], off = a.off[sp];
+    double2* Om = work;                         // (n + nv) x n: reference rows, then virtual rows
+    double2* T = Om + (n + nv) * n;             // nv x n
+    double2* P = T + nv * n;                    // n x no: Omega0[:, h]
+    double2* Q = P + n * no;                    // n x no: Omega0 P
+    double2* Y1 = Q + n * no;                   // nv x no
+    double2* Y2 = Y1 + nv * no;                 // nv x no
+    const double2* src = a.omega + (long)g * a.nr * a.ldo + (long)wl * a.ntot + off;
+    for (int e = t; e < (n + nv) * n; e += 256) {
+      const int r = e / n, j = e - r * n;
+      const int ru = r < n ? r : a.nmax + (r - n);
+      Om[e] = src[(long)ru * a.ldo + j];
+    }
+    const double2* tvw = a.tv + (long)w * nv * a.ntot + off;
+    for (int e = t; e < nv * n; e += 256) {
+      const int v = e / n, j = e - v * n;
+      T[e] = tvw[(long)v * a.ntot + j];
+    }
+    __syncthreads();
+    // traces of the reference block: t0 = tr Omega0, q0 = tr Omega0^2; P = Omega0[:, h]
     double2 t0 = make_double2(0.0, 0.0), q0 = make_double2(0.0, 0.0);
-    for (int i = t; i < n; i += 256) t0 = cadd(t0, om[i * n + i]);
+    for (int i = t; i < n; i += 256) t0 = cadd(t0, Om[i * n + i]);
     for (int e = t; e < n * n; e += 256) {
       const int i = e / n, j = e - i * n;
-      q0 = cadd(q0, cmul(om[i * n + j], om[j * n + i]));
+      q0 = cadd(q0, cmul(Om[i * n + j], Om[j * n + i]));
     }
-    red[0][t] = t0;
-    red[1][t] = q0;
-    // P[l][hh] = Omega0[l][h_hh]
+    const int* hact = a.hact[sp];
     for (int e = t; e < n * no; e += 256) {
       const int l = e / no, hh = e - l * no;
-      P[e] = om[l * n + hact[hh]];
+      P[e] = Om[l * n + hact[hh]];
     }
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (t < s) {
-        red[0][t] = cadd(red[0][t], red[0][t + s]);
-        red[1][t] = cadd(red[1][t], red[1][t + s]);
-      }
-      __syncthreads();
-    }
-    t0 = red[0][0];
-    q0 = red[1][0];
-    // Q = Omega0 P = (Omega0^2)[:, h]
+    t0 = wg_sum(t0, red);
+    q0 = wg_sum(q0, red + 4);
+    // Q = Omega0 P
     for (int e = t; e < n * no; e += 256) {
       const int l = e / no, hh = e - l * no;
-      double2 s = make_double2(0.0, 0.0);
-      for (int j = 0; j < n; ++j) s = cadd(s, cmul(om[l * n + j], P[j * no + hh]));
-      Q[e] = s;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int j = 0; j < n; ++j) acc = cadd(acc, cmul(Om[l * n + j], P[j * no + hh]));
+      Q[e] = acc;
     }
     __syncthreads();
-    // Y1 = Omega_V[:, h] - T_V P ;  Y2 = -Omega_V P + T_V Q
+    // Y1 = Omega_V[:, h] - T_V P ;  Y2 = T_V Q - Omega_V P
     for (int e = t; e < nv * no; e += 256) {
       const int v = e / no, hh = e - v * no;
-      const double2* ov = om + (long)(n + v) * n;
+      const double2* ov = Om + (n + v) * n;
+      const double2* tv = T + v * n;
       double2 y1 = ov[hact[hh]], y2 = make_double2(0.0, 0.0);
       for (int l = 0; l < n; ++l) {
-        const double2 tvl = T[v * n + l];
-        y1 = csub(y1, cmul(tvl, P[l * no + hh]));
-        y2 = cadd(y2, csub(cmul(tvl, Q[l * no + hh]), cmul(ov[l], P[l * no + hh])));
+        const double2 p = P[l * no + hh];
+        y1 = csub(y1, cmul(tv[l], p));
+        y2 = cadd(y2, csub(cmul(tv[l], Q[l * no + hh]), cmul(ov[l], p)));
       }
       Y1[e] = y1;
       Y2[e] = y2;
     }
     __syncthreads();
-    // per excitation: d1 = sum cof1 Y1, d2 = sum cof1 Y2 + sum cof2 (2 x 2 minors of Y1)
-    const double2* cof = a.cof[sp] + (long)w * a.nexc[sp] * MSD_NCOF;
+    // per excitation: det(A + e Y1 + e^2 Y2) = d0 + d1 e + d2 e^2 (excitations
+    // are sorted by rank, so a wave mostly runs one of the five paths)
     for (int e = t; e < a.nexc[sp]; e += 256) {
       const int* ex = a.exc[sp] + e * MSD_EXC;
-      const int k = ex[0];
-      const double2* cf = cof + (long)e * MSD_NCOF;
-      double2 y1[MSD_KMAX][MSD_KMAX];
-      double2 d1 = make_double2(0.0, 0.0), d2 = make_double2(0.0, 0.0);
-      for (int q = 0; q < k; ++q)
-        for (int r = 0; r < k; ++r) {
-          const int idx = ex[1 + MSD_KMAX + q] * no + ex[1 + r];
-          y1[q][r] = Y1[idx];
-          const double2 c1 = cf[1 + q * MSD_KMAX + r];
-          d1 = cadd(d1, cmul(c1, Y1[idx]));
-          d2 = cadd(d2, cmul(c1, Y2[idx]));
-        }
-      for (int q1 = 0; q1 < k; ++q1)
-        for (int q2 = q1 + 1; q2 < k; ++q2)
-          for (int r1 = 0; r1 < k; ++r1)
-            for (int r2 = r1 + 1; r2 < k; ++r2) {
-              const double2 m = det2(y1[q1][r1], y1[q1][r2], y1[q2][r1], y1[q2][r2]);
-              d2 = cadd(d2, cmul(m, cf[1 + MSD_KMAX * MSD_KMAX + pair_index(q1, q2) * 6 + pair_index(r1, r2)]));
-            }
-      const double2 d0 = cf[0];
-      N1[sp][e] = cadd(d1, cmul(t0, d0));
+      P3 d;
+      switch (ex[0]) {
+        case 0: d = pdet_lds<0>(T, Y1, Y2, n, no, ex); break;
+        case 1: d = pdet_lds<1>(T, Y1, Y2, n, no, ex); break;
+        case 2: d = pdet_lds<2>(T, Y1, Y2, n, no, ex); break;
+        case 3: d = pdet_lds<3>(T, Y1, Y2, n, no, ex); break;
+        default: d = pdet_lds<4>(T, Y1, Y2, n, no, ex); break;
+      }
+      D0[sp * a.nexc_max + e] = d.a;
+      N1[sp * a.nexc_max + e] = cadd(d.b, cmul(t0, d.a));
       // P2 = 2 d2 + 2 t0 d1 + (t0^2 - q0) d0
-      P2[sp][e] = cadd(cadd(cscale(d2, 2.0), cscale(cmul(t0, d1), 2.0)), cmul(csub(cmul(t0, t0), q0), d0));
+      P2[sp * a.nexc_max + e] =
+          cadd(cadd(cscale(d.c, 2.0), cscale(cmul(t0, d.b), 2.0)), cmul(csub(cmul(t0, t0), q0), d.a));
     }
     __syncthreads();
   }
   // determinant sums
   double2 av = make_double2(0.0, 0.0), ae = make_double2(0.0, 0.0);
-  const double2* cu = a.cof[0] + (long)w * a.nexc[0] * MSD_NCOF;
-  const double2* cd = a.cof[1] + (long)w * a.nexc[1] * MSD_NCOF;
   for (int I = t; I < a.ndet; I += 256) {
-    const int eu = a.pair[2 * I], ed = a.pair[2 * I + 1];
+    const int eu = a.pair[2 * I], ed = a.nexc_max + a.pair[2 * I + 1];
     const double2 c = a.cconj[I];
-    const double2 ru = cu[(long)eu * MSD_NCOF], rd = cd[(long)ed * MSD_NCOF];
-    const double2 n1u = N1[0][eu], n1d = N1[1][ed];
+    const double2 ru = D0[eu], rd = D0[ed], n1u = N1[eu], n1d = N1[ed];
     av = cadd(av, cmul(c, cadd(cmul(n1u, rd), cmul(ru, n1d))));
-    const double2 two = cadd(cadd(cmul(P2[0][eu], rd), cmul(ru, P2[1][ed])), cscale(cmul(n1u, n1d), 2.0));
+    const double2 two = cadd(cadd(cmul(P2[eu], rd), cmul(ru, P2[ed])), cscale(cmul(n1u, n1d), 2.0));
     ae = cadd(ae, cmul(c, cscale(two, 0.5)));
   }
-  red[0][t] = av;
-  red[1][t] = ae;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) {
-      red[0][t] = cadd(red[0][t], red[0][t + s]);
-      red[1][t] = cadd(red[1][t], red[1][t + s]);
-    }
-    __syncthreads();
-  }
+  av = wg_sum(av, red);
+  ae = wg_sum(ae, red + 4);
   if (t == 0) {
     double2* out = a.num + (long)w * (2 * a.X + 1);
     if (g < a.X) {
-      out[g] = red[0][0];
-      out[a.X + g] = red[1][0];
+      out[g] = av;
+      out[a.X + g] = ae;
     } else {
-      out[2 * a.X] = red[0][0];
+      out[2 * a.X] = av;
     }
   }
 }
@@ -323,6 +346,17 @@ __global__ __launch_bounds__(256) void msd_finish_kernel(const double2* __restri
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+static size_t msd_lds_bytes(afq_system s) {
+  size_t spin = 0;
+  const size_t nv = s->msd_nv;
+  for (int sp = 0; sp < 2; ++sp) {
+    const size_t n = s->nspin_n(sp), no = s->msd_no[sp];
+    spin = std::max(spin, (n + nv) * n + nv * n + 2 * n * no + 2 * nv * no);
+  }
+  const size_t nexc = std::max(s->msd_nexc[0], s->msd_nexc[1]);
+  return (6 * nexc + 8 + spin) * 16;
+}
+
 int msd_set(afq_system s, const double* C, int n_det, const double* coeffs, const int32_t* exc) {
   hipStream_t st = s->stream;
   const int M = s->M, X = s->X;
@@ -369,16 +403,18 @@ int msd_set(afq_system s, const double* C, int n_det, const double* coeffs, cons
       }
     AFQ_CHECK(dev <= 1e-10, AFQ_E_INVALID, "afq_system_set_msd: C is not orthonormal (|C^H C - I| > 1e-10)");
   }
-  // excitations: validate, collect active holes / virtuals and distinct excitations per spin
+  // excitations: validate; collect active holes per spin, active virtuals (both
+  // spins) and the distinct excitations of each spin
   std::set<std::vector<int>> seen;
   std::vector<int> hpair((size_t)2 * n_det);
-  std::vector<std::vector<int>> hact(2), vact(2);
+  std::vector<std::vector<int>> hact(2);
+  std::vector<int> vact;
   std::vector<std::map<std::vector<int>, int>> uniq(2);
   std::vector<std::vector<std::vector<int>>> ulist(2);
   for (int I = 0; I < n_det; ++I) {
-    std::vector<int> key;
+    std::vector<int> occ;
     for (int sp = 0; sp < 2; ++sp) {
-      const int32_t* r = exc + ((size_t)I * 2 + sp) * MSD_EXC;
+      const int32_t* r = exc + ((size_t)I * 2 + sp) * 9;
       const int k = r[0], n = s->nspin_n(sp);
       AFQ_CHECK(k >= 0 && k <= MSD_KMAX && k <= n, AFQ_E_UNSUPPORTED,
                 "afq_system_set_msd: excitation rank must be in [0, 4] and at most the electron count");
@@ -393,45 +429,62 @@ int msd_set(afq_system s, const double* C, int n_det, const double* coeffs, cons
                   "afq_system_set_msd: repeated hole or particle in one excitation");
         e[1 + q] = h;
         e[1 + k + q] = p;
+        if (std::find(hact[sp].begin(), hact[sp].end(), h) == hact[sp].end()) hact[sp].push_back(h);
+        if (std::find(vact.begin(), vact.end(), p) == vact.end()) vact.push_back(p);
       }
-      key.insert(key.end(), e.begin(), e.end());
-      // the occupation set decides orthogonality; the slot pairing only fixes the sign
       auto it = uniq[sp].find(e);
       if (it == uniq[sp].end()) {
         it = uniq[sp].emplace(e, (int)ulist[sp].size()).first;
         ulist[sp].push_back(e);
       }
       hpair[2 * I + sp] = it->second;
-      for (int q = 0; q < k; ++q) {
-        if (std::find(hact[sp].begin(), hact[sp].end(), e[1 + q]) == hact[sp].end()) hact[sp].push_back(e[1 + q]);
-        if (std::find(vact[sp].begin(), vact[sp].end(), e[1 + k + q]) == vact[sp].end())
-          vact[sp].push_back(e[1 + k + q]);
-      }
-    }
-    // distinct occupation sets: compare sorted holes and particles per spin
-    std::vector<int> occ;
-    for (int sp = 0; sp < 2; ++sp) {
-      const std::vector<int>& e = ulist[sp][hpair[2 * I + sp]];
-      const int k = e[0];
-      std::vector<int> h(e.begin() + 1, e.begin() + 1 + k), p(e.begin() + 1 + k, e.end());
-      std::sort(h.begin(), h.end());
-      std::sort(p.begin(), p.end());
+      // the occupation set decides orthogonality; the slot pairing only fixes the sign
       occ.push_back(-1 - sp);
-      occ.insert(occ.end(), h.begin(), h.end());
+      occ.insert(occ.end(), hs.begin(), hs.end());
       occ.push_back(-10 - sp);
-      occ.insert(occ.end(), p.begin(), p.end());
+      occ.insert(occ.end(), ps.begin(), ps.end());
     }
     AFQ_CHECK(seen.insert(occ).second, AFQ_E_INVALID,
               "afq_system_set_msd: two determinants have the same occupation (the expansion must be orthogonal)");
   }
+  // order each spin's excitations by rank (waves of the sums kernel then take one rank path)
   for (int sp = 0; sp < 2; ++sp) {
-    AFQ_CHECK((int)hact[sp].size() <= MSD_MAX_NO && (int)vact[sp].size() <= MSD_MAX_NV &&
-                  (int)ulist[sp].size() <= MSD_MAX_EXC,
-              AFQ_E_UNSUPPORTED,
-              "afq_system_set_msd: at most 16 active holes, 32 active virtuals and 256 distinct excitations per spin");
-    std::sort(hact[sp].begin(), hact[sp].end());
-    std::sort(vact[sp].begin(), vact[sp].end());
+    std::vector<int> order(ulist[sp].size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ulist[sp][x][0] < ulist[sp][y][0]; });
+    std::vector<int> where(order.size());
+    std::vector<std::vector<int>> sorted(order.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+      where[order[i]] = (int)i;
+      sorted[i] = ulist[sp][order[i]];
+    }
+    ulist[sp].swap(sorted);
+    for (int I = 0; I < n_det; ++I) hpair[2 * I + sp] = where[hpair[2 * I + sp]];
   }
+  for (int sp = 0; sp < 2; ++sp) {
+    AFQ_CHECK((int)hact[sp].size() <= MSD_MAX_NO && (int)ulist[sp].size() <= MSD_MAX_EXC, AFQ_E_UNSUPPORTED,
+              "afq_system_set_msd: at most 16 active holes and 256 distinct excitations per spin");
+    std::sort(hact[sp].begin(), hact[sp].end());
+  }
+  AFQ_CHECK((int)vact.size() <= MSD_MAX_NV, AFQ_E_UNSUPPORTED, "afq_system_set_msd: at most 32 active virtuals");
+  std::sort(vact.begin(), vact.end());
+  const int nv = (int)vact.size(), nmax = std::max(s->n_up, s->n_dn), nr = nmax + nv;
+  // tentative sizes for the LDS check
+  const int old_no[2] = {s->msd_no[0], s->msd_no[1]}, old_nexc[2] = {s->msd_nexc[0], s->msd_nexc[1]};
+  const int old_nv = s->msd_nv;
+  for (int sp = 0; sp < 2; ++sp) {
+    s->msd_no[sp] = (int)hact[sp].size();
+    s->msd_nexc[sp] = (int)ulist[sp].size();
+  }
+  s->msd_nv = nv;
+  const size_t lds = msd_lds_bytes(s);
+  if (lds > MSD_MAX_LDS) {
+    for (int sp = 0; sp < 2; ++sp) { s->msd_no[sp] = old_no[sp]; s->msd_nexc[sp] = old_nexc[sp]; }
+    s->msd_nv = old_nv;
+    afq_set_error("afq_system_set_msd: the expansion needs more than 160 KB of LDS per workgroup");
+    return AFQ_E_UNSUPPORTED;
+  }
+  s->msd_n = 0;   // detached until the tables below are complete
   // device tables
   std::vector<double2> cc(n_det);
   for (int I = 0; I < n_det; ++I) {
@@ -444,81 +497,78 @@ int msd_set(afq_system s, const double* C, int n_det, const double* coeffs, cons
   AFQ_TRY_HIP(hipMemcpyAsync(s->msd_cconj.p, cc.data(), cc.size() * 16, hipMemcpyHostToDevice, st));
   AFQ_TRY_HIP(hipMemcpyAsync(s->msd_pair.p, hpair.data(), hpair.size() * sizeof(int), hipMemcpyHostToDevice, st));
   std::vector<std::vector<int>> dexc(2);
-  std::vector<std::vector<double2>> cvh(2);
   for (int sp = 0; sp < 2; ++sp) {
-    const int n = s->nspin_n(sp), off = s->spin_off(sp);
-    const int nv = (int)vact[sp].size(), no = (int)hact[sp].size(), nexc = (int)ulist[sp].size();
+    const int no = (int)hact[sp].size(), nexc = (int)ulist[sp].size();
     dexc[sp].assign((size_t)nexc * MSD_EXC, 0);
     for (int e = 0; e < nexc; ++e) {
       const std::vector<int>& u = ulist[sp][e];
       const int k = u[0];
-      dexc[sp][(size_t)e * MSD_EXC] = k;
+      int* d = &dexc[sp][(size_t)e * MSD_EXC];
+      d[0] = k;
       for (int q = 0; q < k; ++q) {
-        dexc[sp][(size_t)e * MSD_EXC + 1 + q] =
-            (int)(std::find(hact[sp].begin(), hact[sp].end(), u[1 + q]) - hact[sp].begin());
-        dexc[sp][(size_t)e * MSD_EXC + 1 + MSD_KMAX + q] =
-            (int)(std::find(vact[sp].begin(), vact[sp].end(), u[1 + k + q]) - vact[sp].begin());
+        d[1 + q] = (int)(std::find(hact[sp].begin(), hact[sp].end(), u[1 + q]) - hact[sp].begin());
+        d[1 + MSD_KMAX + q] = (int)(std::find(vact.begin(), vact.end(), u[1 + k + q]) - vact.begin());
+        d[1 + 2 * MSD_KMAX + q] = u[1 + q];
       }
     }
-    cvh[sp].resize((size_t)std::max(nv, 1) * M);
-    for (int v = 0; v < nv; ++v)
-      for (int i = 0; i < M; ++i) {
-        const double2 c = hC[(size_t)i * M + vact[sp][v]];
-        cvh[sp][(size_t)v * M + i] = make_double2(c.x, -c.y);
-      }
     AFQ_RET(s->msd_exc[sp].alloc(dexc[sp].size() * sizeof(int)));
     AFQ_RET(s->msd_hact[sp].alloc((size_t)std::max(no, 1) * sizeof(int)));
-    AFQ_RET(s->msd_cvh[sp].alloc(cvh[sp].size() * 16));
     AFQ_TRY_HIP(hipMemcpyAsync(s->msd_exc[sp].p, dexc[sp].data(), dexc[sp].size() * sizeof(int),
                                hipMemcpyHostToDevice, st));
     if (no) AFQ_TRY_HIP(hipMemcpyAsync(s->msd_hact[sp].p, hact[sp].data(), no * sizeof(int), hipMemcpyHostToDevice, st));
-    AFQ_TRY_HIP(hipMemcpyAsync(s->msd_cvh[sp].p, cvh[sp].data(), cvh[sp].size() * 16, hipMemcpyHostToDevice, st));
-    // Lact[g] = [T^H L^g ; C_V^H L^g] (rows n + nv), g = X: h1
-    const int nr = n + nv;
-    AFQ_RET(s->msd_lact[sp].alloc((size_t)(X + 1) * nr * M * 16));
-    AFQ_TRY_HIP(hipMemcpy2DAsync(s->msd_lact[sp].p, (size_t)nr * M * 16, s->Lt.as<double2>() + (size_t)off * M,
-                                 (size_t)s->ntot * M * 16, (size_t)n * M * 16, X, hipMemcpyDeviceToDevice, st));
-    AFQ_TRY_HIP(hipMemcpyAsync(s->msd_lact[sp].as<double2>() + (size_t)X * nr * M, s->ht.as<double2>() + (size_t)off * M,
-                               (size_t)n * M * 16, hipMemcpyDeviceToDevice, st));
-    if (nv) {
-      GemmArgs<double> g = gemm_args<double>();
-      g.m = nv; g.n = M; g.k = M; g.batch = X;
-      g.A = s->msd_cvh[sp].as<double>(); g.lda = M; g.cA = true; g.sA = 0;
-      g.B = s->chol.as<double>(); g.ldb = M; g.cB = false; g.sB = (long)M * M;
-      g.C = s->msd_lact[sp].as<double>() + 2L * n * M; g.ldc = M; g.cC = true; g.sC = (long)nr * M;
-      AFQ_RET(gemm<double>(g, st));
-      GemmArgs<double> h = g;
-      h.batch = 1;
-      h.B = s->h1.as<double>();
-      h.C = s->msd_lact[sp].as<double>() + 2L * ((long)X * nr + n) * M;
-      AFQ_RET(gemm<double>(h, st));
+  }
+  // [C_ref; C_V]^H (nr x M) and Lact[g] = [C_ref; C_V]^H L^g, g = X: h1
+  std::vector<double2> cah((size_t)nr * M);
+  for (int r = 0; r < nr; ++r) {
+    const int col = r < nmax ? r : vact[r - nmax];
+    for (int i = 0; i < M; ++i) {
+      const double2 c = hC[(size_t)i * M + col];
+      cah[(size_t)r * M + i] = make_double2(c.x, -c.y);
     }
-    s->msd_no[sp] = no;
-    s->msd_nv[sp] = nv;
-    s->msd_nexc[sp] = nexc;
+  }
+  DevBuf cad;
+  AFQ_RET(cad.alloc(cah.size() * 16));
+  AFQ_TRY_HIP(hipMemcpyAsync(cad.p, cah.data(), cah.size() * 16, hipMemcpyHostToDevice, st));
+  AFQ_RET(s->msd_cvh.alloc((size_t)std::max(nv, 1) * M * 16));
+  if (nv)
+    AFQ_TRY_HIP(hipMemcpyAsync(s->msd_cvh.p, cad.as<double2>() + (size_t)nmax * M, (size_t)nv * M * 16,
+                               hipMemcpyDeviceToDevice, st));
+  AFQ_RET(s->msd_lact.alloc((size_t)(X + 1) * nr * M * 16));
+  {
+    GemmArgs<double> g = gemm_args<double>();
+    g.m = nr; g.n = M; g.k = M; g.batch = X;
+    g.A = cad.as<double>(); g.lda = M; g.cA = true; g.sA = 0;
+    g.B = s->chol.as<double>(); g.ldb = M; g.cB = false; g.sB = (long)M * M;
+    g.C = s->msd_lact.as<double>(); g.ldc = M; g.cC = true; g.sC = (long)nr * M;
+    AFQ_RET(gemm<double>(g, st));
+    GemmArgs<double> h = g;
+    h.batch = 1;
+    h.B = s->h1.as<double>();
+    h.C = s->msd_lact.as<double>() + 2L * X * nr * M;
+    AFQ_RET(gemm<double>(h, st));
   }
   AFQ_TRY_HIP(hipStreamSynchronize(st));
+  if (lds > 64 * 1024)
+    AFQ_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(msd_post_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  s->msd_nr = nr;
+  s->msd_lds = lds;
   s->msd_n = n_det;
   return AFQ_OK;
 }
 
 int msd_alloc_scratch(afq_system s, afq_walkers w) {
-  const int nw = w->nw, X = s->X;
-  size_t per_walker = 0;
-  for (int sp = 0; sp < 2; ++sp) {
-    const int n = s->nspin_n(sp), nv = s->msd_nv[sp];
-    per_walker = std::max(per_walker, (size_t)(X + 1) * (n + nv) * n * 16);
-  }
+  const int nw = w->nw, X = s->X, ntot = s->ntot, nv = s->msd_nv;
+  const size_t per_walker = (size_t)(X + 1) * s->msd_nr * ntot * 16;
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>(nw, MSD_OMEGA_BUDGET / per_walker));
+  const size_t tv = (size_t)nw * std::max(nv, 1) * ntot * 16;
+  if (w->msd_tv.bytes < tv) AFQ_RET(w->msd_tv.alloc(tv));
   for (int sp = 0; sp < 2; ++sp) {
-    const int n = s->nspin_n(sp), nv = s->msd_nv[sp];
-    const size_t tv = (size_t)nw * std::max(nv, 1) * n * 16;
-    const size_t cof = (size_t)nw * s->msd_nexc[sp] * MSD_NCOF * 16;
-    const size_t om = (size_t)chunk * (X + 1) * (n + nv) * n * 16;
-    if (w->msd_tv[sp].bytes < tv) AFQ_RET(w->msd_tv[sp].alloc(tv));
-    if (w->msd_cof[sp].bytes < cof) AFQ_RET(w->msd_cof[sp].alloc(cof));
-    if (w->msd_omega[sp].bytes < om) AFQ_RET(w->msd_omega[sp].alloc(om));
+    const size_t d0 = (size_t)nw * s->msd_nexc[sp] * 16;
+    if (w->msd_d0[sp].bytes < d0) AFQ_RET(w->msd_d0[sp].alloc(d0));
   }
+  const size_t om = (size_t)chunk * per_walker;
+  if (w->msd_omega.bytes < om) AFQ_RET(w->msd_omega.alloc(om));
   const size_t num = (size_t)nw * (2 * X + 1) * 16;
   if (w->msd_num.bytes < num) AFQ_RET(w->msd_num.alloc(num));
   if (w->msd_den.bytes < (size_t)nw * 16) AFQ_RET(w->msd_den.alloc((size_t)nw * 16));
@@ -528,26 +578,25 @@ int msd_alloc_scratch(afq_system s, afq_walkers w) {
   return AFQ_OK;
 }
 
-// T_V = C_V^H Theta for every walker and spin, then det A (and cofactors)
-static int msd_ratios(afq_system s, afq_walkers w, bool det_only, double2* logdet, hipStream_t st) {
-  const int M = s->M, ntot = s->ntot, nw = w->nw;
+// T_V = C_V^H Theta for every walker (all columns), then det A of every excitation
+static int msd_ratios(afq_system s, afq_walkers w, double2* logdet, hipStream_t st) {
+  const int M = s->M, ntot = s->ntot, nw = w->nw, nv = s->msd_nv;
+  if (nv) {
+    GemmArgs<double> g = gemm_args<double>();
+    g.m = nv; g.n = ntot; g.k = M; g.batch = nw;
+    g.A = s->msd_cvh.as<double>(); g.lda = M; g.cA = true; g.sA = 0;
+    g.B = w->theta.as<double>(); g.ldb = M; g.opB = OP_T; g.cB = true; g.sB = (long)ntot * M;
+    g.C = w->msd_tv.as<double>(); g.ldc = ntot; g.cC = true; g.sC = (long)nv * ntot;
+    AFQ_RET(gemm<double>(g, st));
+  }
   for (int sp = 0; sp < 2; ++sp) {
-    const int n = s->nspin_n(sp), off = s->spin_off(sp), nv = s->msd_nv[sp];
-    if (nv) {
-      GemmArgs<double> g = gemm_args<double>();
-      g.m = nv; g.n = n; g.k = M; g.batch = nw;
-      g.A = s->msd_cvh[sp].as<double>(); g.lda = M; g.cA = true; g.sA = 0;
-      g.B = w->theta.as<double>() + 2L * off * M; g.ldb = M; g.opB = OP_T; g.cB = true; g.sB = (long)ntot * M;
-      g.C = w->msd_tv[sp].as<double>(); g.ldc = n; g.cC = true; g.sC = (long)nv * n;
-      AFQ_RET(gemm<double>(g, st));
-    }
-    hipLaunchKernelGGL(msd_cof_kernel, dim3(ceil_div(s->msd_nexc[sp], 64), nw), dim3(64), 0, st,
-                       w->msd_tv[sp].as<double2>(), n, nv, s->msd_exc[sp].as<int>(), s->msd_hact[sp].as<int>(),
-                       s->msd_nexc[sp], w->msd_cof[sp].as<double2>(), det_only ? 1 : 0);
+    hipLaunchKernelGGL(msd_ratio_kernel, dim3(ceil_div(s->msd_nexc[sp], 64), nw), dim3(64), 0, st,
+                       w->msd_tv.as<double2>(), nv, ntot, s->spin_off(sp), s->msd_exc[sp].as<int>(),
+                       s->msd_nexc[sp], w->msd_d0[sp].as<double2>());
     AFQ_TRY_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(msd_den_kernel, dim3(nw), dim3(256), 0, st, s->msd_cconj.as<double2>(), s->msd_pair.as<int>(),
-                     s->msd_n, w->msd_cof[0].as<double2>(), s->msd_nexc[0], w->msd_cof[1].as<double2>(),
+                     s->msd_n, w->msd_d0[0].as<double2>(), s->msd_nexc[0], w->msd_d0[1].as<double2>(),
                      s->msd_nexc[1], w->msd_den.as<double2>(), logdet);
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
@@ -555,29 +604,32 @@ static int msd_ratios(afq_system s, afq_walkers w, bool det_only, double2* logde
 
 int msd_overlap(afq_system s, afq_walkers w, double2* logdet, hipStream_t st) {
   AFQ_RET(msd_alloc_scratch(s, w));
-  return msd_ratios(s, w, true, logdet, st);
+  return msd_ratios(s, w, logdet, st);
 }
 
 int msd_energy(afq_system s, afq_walkers w, double2* logdet, hipStream_t st) {
   AFQ_RET(msd_alloc_scratch(s, w));
-  const int M = s->M, ntot = s->ntot, nw = w->nw, X = s->X;
+  const int M = s->M, ntot = s->ntot, nw = w->nw, X = s->X, nr = s->msd_nr;
   {
-    TraceScope tr(AFQ_PH_PACK, st);
-    AFQ_RET(msd_ratios(s, w, false, logdet, st));
+    TraceScope tr(AFQ_PH_MSD_SUMS, st);
+    AFQ_RET(msd_ratios(s, w, logdet, st));
   }
-  TraceScope tr(AFQ_PH_EXCHANGE, st);
   MsdPostArgs pa{};
+  pa.omega = w->msd_omega.as<double2>();
+  pa.tv = w->msd_tv.as<double2>();
   for (int sp = 0; sp < 2; ++sp) {
-    pa.omega[sp] = w->msd_omega[sp].as<double2>();
-    pa.tv[sp] = w->msd_tv[sp].as<double2>();
-    pa.cof[sp] = w->msd_cof[sp].as<double2>();
     pa.exc[sp] = s->msd_exc[sp].as<int>();
     pa.hact[sp] = s->msd_hact[sp].as<int>();
     pa.n[sp] = s->nspin_n(sp);
-    pa.nv[sp] = s->msd_nv[sp];
+    pa.off[sp] = s->spin_off(sp);
     pa.no[sp] = s->msd_no[sp];
     pa.nexc[sp] = s->msd_nexc[sp];
   }
+  pa.nmax = std::max(s->n_up, s->n_dn);
+  pa.nv = s->msd_nv;
+  pa.nr = nr;
+  pa.ntot = ntot;
+  pa.nexc_max = std::max(s->msd_nexc[0], s->msd_nexc[1]);
   pa.pair = s->msd_pair.as<int>();
   pa.cconj = s->msd_cconj.as<double2>();
   pa.ndet = s->msd_n;
@@ -585,20 +637,22 @@ int msd_energy(afq_system s, afq_walkers w, double2* logdet, hipStream_t st) {
   pa.num = w->msd_num.as<double2>();
   for (int w0 = 0; w0 < nw; w0 += w->msd_chunk) {
     const int nc = std::min(w->msd_chunk, nw - w0);
-    for (int sp = 0; sp < 2; ++sp) {
-      const int n = s->nspin_n(sp), off = s->spin_off(sp), nr = n + s->msd_nv[sp];
+    {
+      TraceScope tr(AFQ_PH_MSD_OMEGA, st);
       GemmArgs<double> g = gemm_args<double>();
-      g.m = (X + 1) * nr; g.n = n; g.k = M; g.batch = nc;
-      g.A = s->msd_lact[sp].as<double>(); g.lda = M; g.cA = true; g.sA = 0;
-      g.B = w->theta.as<double>() + 2L * ((long)w0 * ntot + off) * M; g.ldb = M; g.opB = OP_T; g.cB = true;
-      g.sB = (long)ntot * M;
-      g.C = w->msd_omega[sp].as<double>(); g.ldc = n; g.cC = true; g.sC = (long)(X + 1) * nr * n;
+      g.m = (X + 1) * nr; g.n = nc * ntot; g.k = M;
+      g.A = s->msd_lact.as<double>(); g.lda = M; g.cA = true;
+      g.B = w->theta.as<double>() + 2L * w0 * ntot * M; g.ldb = M; g.opB = OP_T; g.cB = true;
+      g.C = w->msd_omega.as<double>(); g.ldc = (long)nc * ntot; g.cC = true;
       AFQ_RET(gemm<double>(g, st));
     }
     pa.w0 = w0;
-    hipLaunchKernelGGL(msd_post_kernel, dim3(X + 1, nc), dim3(256), 0, st, pa);
+    pa.ldo = (long)nc * ntot;
+    TraceScope tr(AFQ_PH_MSD_SUMS, st);
+    hipLaunchKernelGGL(msd_post_kernel, dim3(X + 1, nc), dim3(256), s->msd_lds, st, pa);
     AFQ_TRY_HIP(hipGetLastError());
   }
+  TraceScope tr(AFQ_PH_MSD_SUMS, st);
   hipLaunchKernelGGL(msd_finish_kernel, dim3(nw), dim3(256), 0, st, w->msd_num.as<double2>(),
                      w->msd_den.as<double2>(), X, w->msd_parts.as<double2>(), w->msd_vbar.as<double2>());
   AFQ_TRY_HIP(hipGetLastError());

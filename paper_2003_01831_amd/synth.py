@@ -149,6 +149,11 @@ WORKLOADS = {
                      n_steps=0, qr_every=5, seed=3, field_seed=1003, perturb=0.1),
     "m400": dict(M=400, n_up=100, n_dn=100, n_chol=1600, n_walkers=512, dt=0.005,
                  n_steps=100, qr_every=5, seed=5, field_seed=1005),
+    # orthogonal multi-determinant trial: 256 determinants drawn in an active
+    # space of 8 occupied and 16 virtual orbitals per spin, rank <= 4 per spin
+    "msd_m128": dict(M=128, n_up=16, n_dn=16, n_chol=512, n_walkers=256, dt=0.005,
+                     n_steps=100, qr_every=5, seed=6, field_seed=1006, n_det=256, occ_act=8,
+                     vir_act=16, k_max=4, msd_seed=2006),
 }
 
 
