@@ -139,6 +139,8 @@ struct afq_system_s {
   DevBuf msd_pair;             // n_det x 2 int: excitation index of each spin
   DevBuf msd_exc[2];           // n_exc x MSD_EXC int: rank, hole slots, particle slots, hole columns
   DevBuf msd_hact[2];          // n_o int: reference column of every active hole
+  DevBuf msd_csr_off[2];       // n_exc + 1 int: determinants of each excitation (offsets)
+  DevBuf msd_csr_det[2];       // n_det int: determinant indices grouped by excitation
   DevBuf msd_cvh;              // msd_nv x M complex: C_V^H (active virtual orbitals)
   DevBuf msd_lact;             // (X + 1) x msd_nr x M complex: [C_ref^H; C_V^H] L^g, g = X is h1
   int nspin_n(int s) const { return s == 0 ? n_up : n_dn; }
@@ -191,6 +193,7 @@ struct afq_walkers_s {
   // multi-determinant scratch
   DevBuf msd_tv;               // nw x msd_nv x ntot complex: C_V^H Theta
   DevBuf msd_d0[2];            // nw x n_exc complex: det A per spin
+  DevBuf msd_S[2];             // nw x n_exc complex: sum over the excitation's determinants of conj(c) R(other spin)
   DevBuf msd_omega;            // (X + 1) msd_nr x chunk ntot complex: [C_ref^H; C_V^H] L^g Theta
   DevBuf msd_num;              // nw x (2 X + 1) complex: numerators (force bias, two-body per g, one-body)
   DevBuf msd_den;              // nw complex: sum_I conj(c_I) det A_I(up) det A_I(down)

@@ -115,14 +115,18 @@ __device__ P3 pdet_lds(const double2* T, const double2* Y1, const double2* Y2, i
     const P3 c2 = pdet2(E(1, 0), E(1, 1), E(2, 0), E(2, 1));
     return padd(psub(pmul(E(0, 0), c0), pmul(E(0, 1), c1)), pmul(E(0, 2), c2));
   } else {
-    // Laplace expansion along rows (0, 1) against the complementary minors of rows (2, 3)
-    const int cp[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+    // expansion along row 0 into 3 x 3 minors of rows 1..3, one at a time
+    // (keeps the register footprint of the rank-3 path)
     P3 acc = {z, z, z};
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
-      const int a = cp[t][0], b = cp[t][1], c = cp[5 - t][0], d = cp[5 - t][1];
-      const P3 term = pmul(pdet2(E(0, a), E(0, b), E(1, a), E(1, b)), pdet2(E(2, c), E(2, d), E(3, c), E(3, d)));
-      acc = (t == 1 || t == 4) ? psub(acc, term) : padd(acc, term);   // sign (-1)^(1 + a + b)
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {
+      const int c0 = j == 0 ? 1 : 0, c1 = j <= 1 ? 2 : 1, c2 = j <= 2 ? 3 : 2;
+      const P3 m0 = pdet2(E(2, c1), E(2, c2), E(3, c1), E(3, c2));
+      const P3 m1 = pdet2(E(2, c0), E(2, c2), E(3, c0), E(3, c2));
+      const P3 m2 = pdet2(E(2, c0), E(2, c1), E(3, c0), E(3, c1));
+      const P3 minor = padd(psub(pmul(E(1, c0), m0), pmul(E(1, c1), m1)), pmul(E(1, c2), m2));
+      const P3 term = pmul(E(0, j), minor);
+      acc = (j & 1) ? psub(acc, term) : padd(acc, term);
     }
     return acc;
   }
@@ -190,6 +194,36 @@ __global__ __launch_bounds__(256) void msd_den_kernel(const double2* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// per (walker, excitation of one spin): the operator-independent coefficient
+// of that excitation in the determinant sums,
+//   S_u[e] = sum_{I: up(I) = e} conj(c_I) R_d(I),  S_d[e] = sum_{I: dn(I) = e} conj(c_I) R_u(I)
+// (determinants grouped per excitation on the host, summed in index order)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void msd_pairsum_kernel(const double2* __restrict__ cconj,
+                                                          const int* __restrict__ pair,
+                                                          const int* __restrict__ off0, const int* __restrict__ det0,
+                                                          const int* __restrict__ off1, const int* __restrict__ det1,
+                                                          const double2* __restrict__ d0u, int nexc0,
+                                                          const double2* __restrict__ d0d, int nexc1,
+                                                          double2* __restrict__ su, double2* __restrict__ sd) {
+  const int w = blockIdx.x, t = threadIdx.x;
+  for (int e = t; e < nexc0 + nexc1; e += 256) {
+    const bool up = e < nexc0;
+    const int x = up ? e : e - nexc0;
+    const int* off = up ? off0 : off1;
+    const int* det = up ? det0 : det1;
+    const double2* other = up ? d0d + (long)w * nexc1 : d0u + (long)w * nexc0;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int j = off[x]; j < off[x + 1]; ++j) {
+      const int I = det[j];
+      acc = cadd(acc, cmul(cconj[I], other[pair[2 * I + (up ? 1 : 0)]]));
+    }
+    if (up) su[(long)w * nexc0 + x] = acc;
+    else sd[(long)w * nexc1 + x] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // one workgroup per (walker of the chunk, operator g in [0, X]): both spins'
 // small products, per-excitation polynomials, then the determinant sums
 // ---------------------------------------------------------------------------
@@ -201,6 +235,7 @@ struct MsdPostArgs {
   const int* hact[2];
   int n[2], off[2], no[2], nexc[2];
   int nmax, nv, nr, ntot, nexc_max;
+  const double2* S[2];       // nw x nexc: operator-independent coefficients per excitation
   const int* pair;
   const double2* cconj;
   int ndet, X, w0;
@@ -211,12 +246,12 @@ __global__ __launch_bounds__(256) void msd_post_kernel(MsdPostArgs a) {
   extern __shared__ double2 lds[];
   const int g = blockIdx.x, wl = blockIdx.y, w = a.w0 + wl, t = threadIdx.x;
   const int nv = a.nv;
-  // persistent: N1, P2, D0 per spin and excitation; reduction scratch
+  // persistent: N1 per spin and excitation (for the cross-spin term); reduction scratch
   double2* N1 = lds;
-  double2* P2 = N1 + 2 * a.nexc_max;
-  double2* D0 = P2 + 2 * a.nexc_max;
-  double2* red = D0 + 2 * a.nexc_max;          // 4 wave partials (x 2)
+  double2* red = N1 + 2 * a.nexc_max;          // 4 wave partials (x 2)
   double2* work = red + 8;
+  // linear terms: sum_e N1[e] S[e] (force bias) and sum_e P2[e] S[e] / 2 (two-body)
+  double2 av = make_double2(0.0, 0.0), ae = make_double2(0.0, 0.0);
   for (int sp = 0; sp < 2; ++sp) {
     const int n = a.n[sp], no = a.no[sp], off = a.off[sp];
     double2* Om = work;                         // (n + nv) x n: reference rows, then virtual rows
@@ -276,6 +311,7 @@ __global__ __launch_bounds__(256) void msd_post_kernel(MsdPostArgs a) {
     __syncthreads();
     // per excitation: det(A + e Y1 + e^2 Y2) = d0 + d1 e + d2 e^2 (excitations
     // are sorted by rank, so a wave mostly runs one of the five paths)
+    const double2* Sw = a.S[sp] + (long)w * a.nexc[sp];
     for (int e = t; e < a.nexc[sp]; e += 256) {
       const int* ex = a.exc[sp] + e * MSD_EXC;
       P3 d;
@@ -286,23 +322,20 @@ __global__ __launch_bounds__(256) void msd_post_kernel(MsdPostArgs a) {
         case 3: d = pdet_lds<3>(T, Y1, Y2, n, no, ex); break;
         default: d = pdet_lds<4>(T, Y1, Y2, n, no, ex); break;
       }
-      D0[sp * a.nexc_max + e] = d.a;
-      N1[sp * a.nexc_max + e] = cadd(d.b, cmul(t0, d.a));
-      // P2 = 2 d2 + 2 t0 d1 + (t0^2 - q0) d0
-      P2[sp * a.nexc_max + e] =
-          cadd(cadd(cscale(d.c, 2.0), cscale(cmul(t0, d.b), 2.0)), cmul(csub(cmul(t0, t0), q0), d.a));
+      const double2 n1 = cadd(d.b, cmul(t0, d.a));
+      // P2 / 2 = d2 + t0 d1 + (t0^2 - q0) d0 / 2
+      const double2 p2h = cadd(cadd(d.c, cmul(t0, d.b)), cscale(cmul(csub(cmul(t0, t0), q0), d.a), 0.5));
+      N1[sp * a.nexc_max + e] = n1;
+      const double2 se = Sw[e];
+      av = cadd(av, cmul(n1, se));
+      ae = cadd(ae, cmul(p2h, se));
     }
     __syncthreads();
   }
-  // determinant sums
-  double2 av = make_double2(0.0, 0.0), ae = make_double2(0.0, 0.0);
+  // cross-spin term of the two-body sum: sum_I conj(c_I) N1_u N1_d
   for (int I = t; I < a.ndet; I += 256) {
-    const int eu = a.pair[2 * I], ed = a.nexc_max + a.pair[2 * I + 1];
-    const double2 c = a.cconj[I];
-    const double2 ru = D0[eu], rd = D0[ed], n1u = N1[eu], n1d = N1[ed];
-    av = cadd(av, cmul(c, cadd(cmul(n1u, rd), cmul(ru, n1d))));
-    const double2 two = cadd(cadd(cmul(P2[eu], rd), cmul(ru, P2[ed])), cscale(cmul(n1u, n1d), 2.0));
-    ae = cadd(ae, cmul(c, cscale(two, 0.5)));
+    const double2 n1u = N1[a.pair[2 * I]], n1d = N1[a.nexc_max + a.pair[2 * I + 1]];
+    ae = cadd(ae, cmul(a.cconj[I], cmul(n1u, n1d)));
   }
   av = wg_sum(av, red);
   ae = wg_sum(ae, red + 4);
@@ -354,7 +387,7 @@ static size_t msd_lds_bytes(afq_system s) {
     spin = std::max(spin, (n + nv) * n + nv * n + 2 * n * no + 2 * nv * no);
   }
   const size_t nexc = std::max(s->msd_nexc[0], s->msd_nexc[1]);
-  return (6 * nexc + 8 + spin) * 16;
+  return (2 * nexc + 8 + spin) * 16;
 }
 
 int msd_set(afq_system s, const double* C, int n_det, const double* coeffs, const int32_t* exc) {
@@ -511,6 +544,16 @@ int msd_set(afq_system s, const double* C, int n_det, const double* coeffs, cons
         d[1 + 2 * MSD_KMAX + q] = u[1 + q];
       }
     }
+    // determinants grouped by this spin's excitation, in index order
+    std::vector<int> off(nexc + 1, 0), det(n_det);
+    for (int I = 0; I < n_det; ++I) ++off[hpair[2 * I + sp] + 1];
+    for (int e = 0; e < nexc; ++e) off[e + 1] += off[e];
+    std::vector<int> fill(off.begin(), off.end() - 1);
+    for (int I = 0; I < n_det; ++I) det[fill[hpair[2 * I + sp]]++] = I;
+    AFQ_RET(s->msd_csr_off[sp].alloc(off.size() * sizeof(int)));
+    AFQ_RET(s->msd_csr_det[sp].alloc(det.size() * sizeof(int)));
+    AFQ_TRY_HIP(hipMemcpyAsync(s->msd_csr_off[sp].p, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    AFQ_TRY_HIP(hipMemcpyAsync(s->msd_csr_det[sp].p, det.data(), det.size() * sizeof(int), hipMemcpyHostToDevice, st));
     AFQ_RET(s->msd_exc[sp].alloc(dexc[sp].size() * sizeof(int)));
     AFQ_RET(s->msd_hact[sp].alloc((size_t)std::max(no, 1) * sizeof(int)));
     AFQ_TRY_HIP(hipMemcpyAsync(s->msd_exc[sp].p, dexc[sp].data(), dexc[sp].size() * sizeof(int),
@@ -566,6 +609,7 @@ int msd_alloc_scratch(afq_system s, afq_walkers w) {
   for (int sp = 0; sp < 2; ++sp) {
     const size_t d0 = (size_t)nw * s->msd_nexc[sp] * 16;
     if (w->msd_d0[sp].bytes < d0) AFQ_RET(w->msd_d0[sp].alloc(d0));
+    if (w->msd_S[sp].bytes < d0) AFQ_RET(w->msd_S[sp].alloc(d0));
   }
   const size_t om = (size_t)chunk * per_walker;
   if (w->msd_omega.bytes < om) AFQ_RET(w->msd_omega.alloc(om));
@@ -613,6 +657,12 @@ int msd_energy(afq_system s, afq_walkers w, double2* logdet, hipStream_t st) {
   {
     TraceScope tr(AFQ_PH_MSD_SUMS, st);
     AFQ_RET(msd_ratios(s, w, logdet, st));
+    hipLaunchKernelGGL(msd_pairsum_kernel, dim3(nw), dim3(256), 0, st, s->msd_cconj.as<double2>(),
+                       s->msd_pair.as<int>(), s->msd_csr_off[0].as<int>(), s->msd_csr_det[0].as<int>(),
+                       s->msd_csr_off[1].as<int>(), s->msd_csr_det[1].as<int>(), w->msd_d0[0].as<double2>(),
+                       s->msd_nexc[0], w->msd_d0[1].as<double2>(), s->msd_nexc[1], w->msd_S[0].as<double2>(),
+                       w->msd_S[1].as<double2>());
+    AFQ_TRY_HIP(hipGetLastError());
   }
   MsdPostArgs pa{};
   pa.omega = w->msd_omega.as<double2>();
@@ -624,6 +674,7 @@ int msd_energy(afq_system s, afq_walkers w, double2* logdet, hipStream_t st) {
     pa.off[sp] = s->spin_off(sp);
     pa.no[sp] = s->msd_no[sp];
     pa.nexc[sp] = s->msd_nexc[sp];
+    pa.S[sp] = w->msd_S[sp].as<double2>();
   }
   pa.nmax = std::max(s->n_up, s->n_dn);
   pa.nv = s->msd_nv;
