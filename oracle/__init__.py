@@ -23,5 +23,10 @@ Parity status per function (pins in tests/test_oracle_*.py):
                                                            the FCI space, orthonormality,
                                                            zero variance of a complete
                                                            expansion, one-determinant limit)
+  kpoint.* (general complex Cholesky walk, k-point blocks) pinned (determinant-space matrix
+                                                           elements, operator identity for h'
+                                                           and the two fields, short-time HS
+                                                           limit, force-bias cancellation,
+                                                           Bloch transform of a supercell)
   philox.philox4x32_10                                     pinned (published KAT vectors)
 """

@@ -137,6 +137,65 @@ def make_msd(sys: System, n_det: int, n_occ_act: int, n_vir_act: int, k_max: int
     return C, exc, np.asarray(coeffs, dtype=np.complex128)
 
 
+@dataclasses.dataclass
+class KpSystem:
+    """k-point-blocked system: nk k-points on a ring (k + Q = (k + Q) mod nk),
+    m orbitals per k-point, n_up/n_dn electrons per k-point and spin."""
+    nk: int
+    m: int
+    n_up: int
+    n_dn: int
+    xq: int
+    kq: np.ndarray        # (nk, nk) int: kq[Q][k] = index of k + Q
+    hk: np.ndarray        # (nk, m, m) complex128 Hermitian blocks
+    Lk: np.ndarray        # (nk, nk, xq, m, m) complex128: Lk[Q, k, n] couples (k + Q) <- k
+    phik: np.ndarray      # (nk, m, n_up + n_dn) complex128 trial blocks
+    e_core: float = 0.0
+
+
+def _fix_phase(v):
+    """Column phases: the entry of largest modulus made real positive."""
+    v = v.copy()
+    for j in range(v.shape[1]):
+        k = int(np.argmax(np.abs(v[:, j])))
+        v[:, j] *= np.abs(v[k, j]) / v[k, j]
+    return v
+
+
+def make_kpoint_system(nk: int, m: int, n_up: int, n_dn: int, xq: int, seed: int,
+                       decay: float = 8.0) -> KpSystem:
+    """Random Hermitian h^k (scale 1/M) and Cholesky blocks with the symmetry of
+    a periodic Hermitian interaction, L^{-Q, k+Q}_n = (L^{Q,k}_n)^+ (drawn for
+    one Q of each (Q, -Q) pair; Q = -Q blocks made consistent), scaled by
+    exp(-n / decay) / M. The trial takes the n lowest eigenvectors of each h^k."""
+    rng = np.random.default_rng(seed)
+    M = nk * m
+    kq = np.array([[(k + Q) % nk for k in range(nk)] for Q in range(nk)], dtype=np.int64)
+    a = rng.standard_normal((nk, m, m)) + 1j * rng.standard_normal((nk, m, m))
+    hk = (a + np.conj(np.swapaxes(a, 1, 2))) / (2.0 * M)
+    scales = np.exp(-np.arange(xq) / decay) / M
+    Lk = np.zeros((nk, nk, xq, m, m), np.complex128)
+    done = np.zeros((nk, nk), bool)
+    for Q in range(nk):
+        mQ = (-Q) % nk
+        for k in range(nk):
+            if done[Q, k]:
+                continue
+            z = (rng.standard_normal((xq, m, m)) + 1j * rng.standard_normal((xq, m, m))) * scales[:, None, None]
+            k2 = kq[Q][k]
+            if (mQ, k2) == (Q, k):              # Q = -Q and k + Q = k: the block must be Hermitian
+                z = 0.5 * (z + np.conj(np.swapaxes(z, 1, 2)))
+            Lk[Q, k] = z
+            Lk[mQ, k2] = np.conj(np.swapaxes(z, 1, 2))
+            done[Q, k] = done[mQ, k2] = True
+    phik = np.zeros((nk, m, n_up + n_dn), np.complex128)
+    for k in range(nk):
+        _, v = np.linalg.eigh(hk[k])
+        phik[k, :, :n_up] = _fix_phase(v[:, :n_up])
+        phik[k, :, n_up:] = _fix_phase(v[:, :n_dn])
+    return KpSystem(nk, m, n_up, n_dn, xq, kq, hk, Lk, phik)
+
+
 # ---------------------------------------------------------------------------
 # Named workloads. Seeds: systems 1..5, fields 1001..1005, uneven systems 4000+s.
 # ---------------------------------------------------------------------------
