@@ -97,6 +97,34 @@ int afq_system_create(afq_system *out, int M, int n_up, int n_dn, int n_chol,
 /* Switches the contraction precision (prepares the packed operand copies;
  * synchronises). */
 int afq_system_set_precision(afq_system s, int precision);
+/* k-point-blocked system (the explicitly k-point dependent Cholesky
+ * factorisation of Section "Auxiliary Field Quantum Monte Carlo" and its row
+ * of Table tab:afqmc_comp). Copies the inputs (this call synchronises).
+ *   nk      number of k-points, 1..64
+ *   kq      host, nk*nk int32 addition table: kq[Q*nk + k] = index of k + Q;
+ *           must be an abelian group law with identity 0 (symmetric,
+ *           associative, every row and column a permutation)
+ *   m       orbitals per k-point; n_up / n_dn electrons per k-point and spin
+ *   xq      Cholesky vectors per momentum transfer Q
+ *   hk      device, nk*m*m complex128 Hermitian one-body blocks h^k
+ *   Lk      device, nk*nk*xq*m*m complex128: Lk[Q][k][n] = L^{Q,k}_n, the
+ *           block of vector (Q, n) from orbitals of k-point k (columns) to
+ *           those of k + Q (rows); the two-electron tensor is
+ *           v_ijkl = sum_(Q,n) L_ik conj(L_lj) over these block vectors
+ *   phik    device, nk*m*(n_up+n_dn) complex128 trial orbitals per k-point,
+ *           up columns first
+ * The system works with the ordinary walker calls (afq_walkers_*, afq_step,
+ * afq_energy, afq_batch_*, afq_bp_*). Its dense orbital index is k*m + i and
+ * its trial columns are (k, a), k-major, per spin (up block first): walkers
+ * are M x N with M = nk*m and N = nk*(n_up + n_dn). It has 2*nk*xq auxiliary
+ * fields, x for (L + L^+)/2 of every vector (Q, n) in (Q, n) order, then y for
+ * (L - L^+)/(2i); explicit fields and vbar_out use that order. FP64 mode only
+ * (AFQ_E_UNSUPPORTED otherwise); no multi-determinant trial and no adjoint.
+ * Limits: nk*m <= 4096, nk*max(n_up, n_dn) <= 128, and the trace kernel's
+ * LDS (about 16 bytes x (2 nk m n + n m (nk + 1) + 12 xq)) within 160 KB. */
+int afq_kp_system_create(afq_system *out, int nk, const int32_t *kq, int m, int n_up, int n_dn, int xq,
+                         const double *hk, const double *Lk, const double *phik, double e_core,
+                         int precision, void *stream);
 /* Orthogonal multi-determinant trial (the multi-determinant paragraph of
  * Section "Auxiliary Field Quantum Monte Carlo"): psi_T = sum_I c_I |D_I>.
  *   C       device, M*M complex128 orthonormal basis (|C^H C - I| <= 1e-10);

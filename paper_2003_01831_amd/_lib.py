@@ -24,6 +24,7 @@ SIGNATURES = {
     "afq_system_create": (_i, [C.POINTER(_vp), _i, _i, _i, _i, _vp, _vp, _vp, _d, _i, _vp]),
     "afq_system_set_precision": (_i, [_vp, _i]),
     "afq_system_set_msd": (_i, [_vp, _vp, _i, _vp, _vp]),
+    "afq_kp_system_create": (_i, [C.POINTER(_vp), _i, _vp, _i, _i, _i, _i, _vp, _vp, _vp, _d, _i, _vp]),
     "afq_system_destroy": (_i, [_vp]),
     "afq_walkers_create": (_i, [C.POINTER(_vp), _vp, _i, _vp, _vp]),
     "afq_walkers_destroy": (_i, [_vp]),

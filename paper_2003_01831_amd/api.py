@@ -60,6 +60,30 @@ class System:
     def from_synth(cls, s, precision="fp64"):
         return cls(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, s.e_core, precision)
 
+    @classmethod
+    def from_kpoint(cls, ks, precision="fp64", stream=None):
+        """k-point-blocked system from a synth.KpSystem-like object (nk, m,
+        n_up / n_dn per k-point, xq, kq, hk, Lk, phik, e_core)."""
+        self = cls.__new__(cls)
+        self.lib = _lib.load()
+        self.hk = _as_dev(ks.hk, torch.complex128)
+        self.Lk = _as_dev(ks.Lk, torch.complex128)
+        self.phik = _as_dev(ks.phik, torch.complex128)
+        kq = np.ascontiguousarray(np.asarray(ks.kq, dtype=np.int32))
+        self.M = int(ks.nk * ks.m)
+        self.n_up, self.n_dn = int(ks.nk * ks.n_up), int(ks.nk * ks.n_dn)
+        self.n_chol = int(2 * ks.nk * ks.xq)          # auxiliary fields
+        self.e_core = float(ks.e_core)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.precision = precision
+        h = C.c_void_p()
+        check(self.lib.afq_kp_system_create(C.byref(h), int(ks.nk), kq.ctypes.data_as(C.c_void_p), int(ks.m),
+                                            int(ks.n_up), int(ks.n_dn), int(ks.xq), _ptr(self.hk), _ptr(self.Lk),
+                                            _ptr(self.phik), self.e_core, PRECISION[precision],
+                                            _stream_handle(self.stream)))
+        self.handle = h
+        return self
+
     def set_precision(self, precision):
         check(self.lib.afq_system_set_precision(self.handle, PRECISION[precision]))
         self.precision = precision

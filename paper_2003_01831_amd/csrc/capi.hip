@@ -53,8 +53,15 @@ int afq_system_set_precision(afq_system s, int precision) {
   AFQ_GUARD(AFQ_RET(check_device(s)); return system_prepare_pack(s, precision);)
 }
 
+int afq_kp_system_create(afq_system* out, int nk, const int32_t* kq, int m, int n_up, int n_dn, int xq,
+                         const double* hk, const double* Lk, const double* phik, double e_core, int precision,
+                         void* stream) {
+  AFQ_GUARD(return kp_system_create_impl(out, nk, kq, m, n_up, n_dn, xq, hk, Lk, phik, e_core, precision, stream);)
+}
+
 int afq_system_set_msd(afq_system s, const double* C, int n_det, const double* coeffs, const int32_t* exc) {
   AFQ_CHECK(s, AFQ_E_INVALID, "afq_system_set_msd: system is NULL");
+  AFQ_CHECK(s->kp_nk == 0, AFQ_E_UNSUPPORTED, "afq_system_set_msd: not available for k-point systems");
   AFQ_GUARD(AFQ_RET(check_device(s)); return msd_set(s, C, n_det, coeffs, exc);)
 }
 
@@ -231,6 +238,7 @@ int afq_energy_backward(afq_system s, afq_walkers w, double scale, double* d_h1,
   AFQ_CHECK(w->sys == s, AFQ_E_STATE, "afq_energy_backward: walkers belong to another system");
   AFQ_CHECK(std::isfinite(scale), AFQ_E_INVALID, "afq_energy_backward: scale is not finite");
   AFQ_CHECK(s->msd_n == 0, AFQ_E_UNSUPPORTED, "afq_energy_backward: needs a single-determinant trial");
+  AFQ_CHECK(s->kp_nk == 0, AFQ_E_UNSUPPORTED, "afq_energy_backward: real Cholesky vectors only");
   AFQ_GUARD(AFQ_RET(check_device(s)); return energy_backward(s, w, scale, d_h1, d_chol, d_walkers);)
 }
 

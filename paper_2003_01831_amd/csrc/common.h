@@ -143,6 +143,19 @@ struct afq_system_s {
   DevBuf msd_csr_det[2];       // n_det int: determinant indices grouped by excitation
   DevBuf msd_cvh;              // msd_nv x M complex: C_V^H (active virtual orbitals)
   DevBuf msd_lact;             // (X + 1) x msd_nr x M complex: [C_ref^H; C_V^H] L^g, g = X is h1
+  // k-point-blocked Cholesky (kp_nk > 0): orbital (k, i) -> k m + i; trial
+  // columns (k, a) k-major per spin; 2 nk xq fields (x for the Hermitian parts
+  // a = (L + L^+)/2, y for b = (L - L^+)/(2i) of every vector (Q, n))
+  int kp_nk = 0, kp_m = 0, kp_xq = 0, kp_nu = 0, kp_nd = 0;   // per k-point electrons
+  size_t kp_lds = 0;           // dynamic LDS bytes of the k-point trace kernel
+  DevBuf kp_kq;                // nk x nk int: kq[Q][k] = k + Q
+  DevBuf kp_kd;                // nk x nk int: kd[a][b] = the Q with b + Q = a
+  DevBuf kp_L;                 // [Q][n][k][i][l] complex: L^{Q,k}_n, block (k + Q, k)
+  DevBuf kp_Lt;                // [Q][k][n][a][l] complex: (T^{k+Q})^H L^{Q,k}_n (both spins' a)
+  DevBuf kp_Ltd;               // [Q][k][n][a][l] complex: (T^k)^H (L^{Q,k}_n)^+
+  DevBuf kp_h;                 // M x M complex h (block diagonal)
+  DevBuf B1c;                  // M x M complex B1 = exp(-dt h'/2) (block diagonal)
+  std::vector<double2> kp_hp;  // h' blocks on the host, nk x m x m
   int nspin_n(int s) const { return s == 0 ? n_up : n_dn; }
   int spin_off(int s) const { return s == 0 ? 0 : n_up; }
 };
@@ -199,6 +212,10 @@ struct afq_walkers_s {
   DevBuf msd_den;              // nw complex: sum_I conj(c_I) det A_I(up) det A_I(down)
   DevBuf msd_parts, msd_vbar;  // nw x 3 and nw x X complex: E1, E2, 0 and the force bias
   int msd_chunk = 0;           // walkers per Omega chunk
+  // k-point scratch
+  DevBuf kp_part;              // nw x 2 x nk x xq x nk x 3 complex: per-row-block traces
+  DevBuf kp_cd;                // 2 x nw x nk xq complex: c and conj(d) of A = sum c L + d L^+
+  DevBuf kp_tmp;               // 2 x nk x nw x nk m^2 complex: A-build GEMM outputs
 };
 
 // ---------------------------------------------------------------------------
@@ -268,6 +285,16 @@ int exchange_launch(afq_system s, afq_walkers w, int spin, hipStream_t st);
 int exchange_autotune(afq_system s, afq_walkers w, int reps, int* choice);   // choice[2]
 int walkers_comb(afq_walkers w, double xi, int* src_out, double* total_out);
 int pack_theta(afq_system s, afq_walkers w, hipStream_t st);
+
+// k-point-blocked Cholesky (kpoint.hip)
+int kp_system_create_impl(afq_system* out, int nk, const int32_t* kq, int m, int nu, int nd, int xq,
+                          const double* hk, const double* Lk, const double* phik, double e_core, int prec,
+                          void* stream);
+int kp_prepare_dt(afq_system s, double dt);
+// tr(L G^s), tr(L^+ G^s) and tr(Omega Omega') per (walker, spin, vector) -> tro / troo in the 2X-field layout
+int kp_energy_traces(afq_system s, afq_walkers w, hipStream_t st);
+// amat = sum_g (c_g L^g + d_g L^g+) from the 2X propagator coefficients coef (complex f64)
+int kp_abuild(afq_system s, afq_walkers w, const double2* coef, hipStream_t st);
 
 // orthogonal multi-determinant trial (msd.hip)
 constexpr int MSD_KMAX = 4;                                   // excitation rank per spin

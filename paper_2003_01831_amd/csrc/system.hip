@@ -39,6 +39,11 @@ static int real_gemm(int m, int n, int k, const double* A, long lda, int opA, co
 
 int system_prepare_pack(afq_system s, int prec) {
   if (s->apack_prec == prec) return AFQ_OK;
+  if (s->kp_nk > 0) {   // k-point systems have their own trace kernel and run in FP64
+    AFQ_CHECK(prec == AFQ_FP64, AFQ_E_UNSUPPORTED, "k-point systems run in FP64 mode");
+    s->apack_prec = s->prec = prec;
+    return AFQ_OK;
+  }
   const int kc = exch_kchunk(prec);
   const size_t esz = prec == AFQ_FP64 ? 8 : prec == AFQ_CFP32 ? 4 : 2;
   for (int sp = 0; sp < 2; ++sp) {
@@ -76,6 +81,7 @@ int system_prepare_pack(afq_system s, int prec) {
 // B1 = exp(Z), Z = -dt h'/2: Z' = Z / 2^q with ||Z'||_inf <= 1/2, Horner
 // evaluation of the order-18 Taylor polynomial, then q squarings.
 int system_prepare_dt(afq_system s, double dt) {
+  if (s->kp_nk > 0) return kp_prepare_dt(s, dt);
   if (s->B1.p && s->B1_dt == dt) return AFQ_OK;
   const int M = s->M;
   const size_t mm = (size_t)M * M;

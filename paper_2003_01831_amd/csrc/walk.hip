@@ -120,7 +120,10 @@ static int coulomb_fp64(afq_system s, afq_walkers w, hipStream_t st) {
 // log(sum_I conj(c_I) R_I) is added to logdet (the current walkers' log det).
 static int energy_from_theta(afq_system s, afq_walkers w, AssembleArgs& a, bool want_coef, double2* logdet) {
   hipStream_t st = s->stream;
-  if (s->msd_n > 0) {
+  if (s->kp_nk > 0) {
+    TraceScope t(AFQ_PH_EXCHANGE, st);
+    AFQ_RET(kp_energy_traces(s, w, st));
+  } else if (s->msd_n > 0) {
     AFQ_RET(msd_energy(s, w, logdet, st));
     a.parts_in = w->msd_parts.as<double2>();
     a.vbar_in = w->msd_vbar.as<double2>();
@@ -172,7 +175,10 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
   const int M = s->M, ntot = s->ntot, nw = w->nw, X = s->X;
   const long per = (long)M * ntot;
   // A_w = sum_n c_wn L^n : [nw x X] (complex) x [X x M^2] (real)
-  {
+  if (s->kp_nk > 0) {
+    TraceScope tr(AFQ_PH_ABUILD, st);
+    AFQ_RET(kp_abuild(s, w, reinterpret_cast<const double2*>(coef), st));
+  } else {
     TraceScope tr(AFQ_PH_ABUILD, st);
     GemmArgs<T> g = gemm_args<T>();
     g.m = nw; g.n = M * M; g.k = X;
@@ -187,7 +193,7 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
   {
     GemmArgs<double> g = gemm_args<double>();
     g.m = M; g.n = ntot; g.k = M; g.batch = nw;
-    g.A = s->B1.as<double>(); g.lda = M; g.cA = false; g.sA = 0;
+    g.A = s->kp_nk ? s->B1c.as<double>() : s->B1.as<double>(); g.lda = M; g.cA = s->kp_nk > 0; g.sA = 0;
     g.B = reinterpret_cast<const double*>(Win); g.ldb = ntot; g.cB = true; g.sB = per;
     g.C = w->u.as<double>(); g.ldc = ntot; g.cC = true; g.sC = per;
     AFQ_RET(gemm<double>(g, st));
@@ -212,7 +218,7 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
   {
     GemmArgs<double> g = gemm_args<double>();
     g.m = M; g.n = ntot; g.k = M; g.batch = nw;
-    g.A = s->B1.as<double>(); g.lda = M; g.cA = false; g.sA = 0;
+    g.A = s->kp_nk ? s->B1c.as<double>() : s->B1.as<double>(); g.lda = M; g.cA = s->kp_nk > 0; g.sA = 0;
     g.B = w->u.as<double>(); g.ldb = ntot; g.cB = true; g.sB = per;
     g.C = reinterpret_cast<double*>(Wout); g.ldc = ntot; g.cC = true; g.sC = per;
     AFQ_RET(gemm<double>(g, st));
