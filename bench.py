@@ -233,6 +233,77 @@ def bench_msd(a, torch, synth, api, _lib):
     return 0
 
 
+def bench_kp(a, torch, synth, api, _lib):
+    """k-point-blocked Cholesky (8 k-points, M=192, 6+6 electrons per k-point,
+    96 vectors per momentum transfer), 256 walkers, FP64."""
+    cfg = dict(synth.WORKLOADS["kp_m192"])
+    nk, m, nu, nd, xq = cfg["nk"], cfg["m"], cfg["n_up"], cfg["n_dn"], cfg["xq"]
+    nw = a.walkers or cfg["n_walkers"]
+    dt, qr = cfg["dt"], cfg["qr_every"]
+    M, Nu, Nd, XL = nk * m, nk * nu, nk * nd, nk * xq
+    lib = _lib.load()
+    ks = synth.make_kpoint_system(nk, m, nu, nd, xq, seed=cfg["seed"])
+    sysg = api.System.from_kpoint(ks)
+    probe = api.Walkers(sysg, 1)
+    e_var = float(probe.energy()[3][0])
+    probe.close()
+    wk = api.Walkers(sysg, nw)
+    wk.step(a.warmup, dt, seed=11, qr_every=qr, e_shift=e_var, outputs=())
+    torch.cuda.synchronize()
+    lib.afq_trace_reset()
+    lib.afq_trace_enable(1)
+    t = time.perf_counter()
+    out = wk.step(a.steps, dt, seed=11, qr_every=qr, e_shift=e_var, outputs=("emix",))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    lib.afq_trace_enable(0)
+    ph = trace_phases(lib, _lib)
+    lib.afq_trace_reset()
+    value = nw * a.steps / wall
+    # trace kernel: per walker, spin, vector (Q, n), row block k1 and pair (a, k', b):
+    # two length-m complex dot products (8 flop per multiply-add)
+    tr_flop = sum(8.0 * 2 * m * (n * nk * n) * nk * XL for n in (nu, nd)) * nw
+    ex_ms, ex_cnt = ph["exchange"]
+    ex_avg_s = ex_ms / 1e3 / max(ex_cnt, 1)
+    achieved = tr_flop / ex_avg_s / 1e12
+    dense_flop = sum(2 * 8.0 * XL * (nk * n) ** 2 * M for n in (nu, nd)) * nw
+    cpu = None
+    if not a.no_cpu:
+        from oracle import kpoint as okp
+        h = okp.dense_one_body(ks.hk)
+        L = okp.dense_factors(ks.Lk, ks.kq)
+        T = okp.dense_trial(ks.phik, nu, nd)
+        W1 = T + 0.05 * np.random.default_rng(5).standard_normal(T.shape)
+        tc = time.perf_counter()
+        okp.local_energy(h, L, T, W1, Nu, Nd)
+        okp.force_bias(L, T, W1, Nu, Nd)
+        tc = time.perf_counter() - tc
+        cpu = {"value": round(1.0 / tc, 6), "unit": "walker-steps/s", "cores": os.cpu_count(), "kind": "oracle",
+               "sample": f"local energy and force bias of 1 walker over the dense block vectors ({tc:.1f}s); "
+                         f"excludes the propagation"}
+    line = {
+        "metric": "walker-steps/s, k-point-blocked Cholesky (FP64)",
+        "value": round(value, 3), "unit": "walker-steps/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(wall / a.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"kp_m192: {nk} k-points, m={m}, {nu}+{nd} electrons per k-point (M={M}, "
+                               f"N={Nu}+{Nd}), {xq} vectors per Q ({XL} complex vectors, {2 * XL} fields), "
+                               f"{nw} walkers, dt={dt}, QR every {qr}",
+                   "precision": "fp64", "walkers": nw, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_TFLOPS["fp64"], 4), "traffic": None,
+                     "kernel": "k-point trace kernel (per row block and Q: Omega, Omega' blocks, FP64 VALU) "
+                               "+ its row-block reduction",
+                     "flop_per_launch": tr_flop, "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt,
+                     "dense_equivalent_flop": dense_flop},
+        "cpu_baseline": cpu,
+        "phase_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in ph.items()},
+        "emix_last": float(out["emix"][-1].item()),
+    }
+    print(json.dumps(line))
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +341,8 @@ def main(argv=None):
         return bench_uneven(a, torch, synth, api, _lib)
     if a.workload == "msd_m128":
         return bench_msd(a, torch, synth, api, _lib)
+    if a.workload == "kp_m192":
+        return bench_kp(a, torch, synth, api, _lib)
 
     cfg = dict(synth.WORKLOADS[a.workload])
     M, nu, nd, X = cfg["M"], cfg["n_up"], cfg["n_dn"], cfg["n_chol"]

@@ -29,6 +29,7 @@
 #include "trace.h"
 
 constexpr size_t KP_MAX_LDS = 160 * 1024;
+constexpr int KP_NS_MAX = 16;   // electrons per k-point and spin held in registers by the trace kernel
 
 // ---------------------------------------------------------------------------
 // host helpers (set-up only)
@@ -92,8 +93,8 @@ int kp_prepare_dt(afq_system s, double dt) {
 }
 
 static size_t kp_lds_bytes(int nk, int m, int nmax, int xq) {
-  const size_t N = (size_t)nk * nmax, M = (size_t)nk * m;
-  return ((size_t)m * N + M * nmax + (size_t)nmax * m + (size_t)nk * nmax * m + (size_t)xq * 12) * 16;
+  const size_t N = (size_t)nk * nmax, M = (size_t)nk * m, npar = 256 / std::max<size_t>(N, 1);
+  return ((size_t)m * N + M * nmax + npar * N * 3 + (size_t)xq * 3) * 16;
 }
 
 int kp_system_create_impl(afq_system* out, int nk, const int32_t* kq, int m, int nu, int nd, int xq,
@@ -107,6 +108,8 @@ int kp_system_create_impl(afq_system* out, int nk, const int32_t* kq, int m, int
             "afq_kp_system_create: need 1 <= n_up, n_dn <= m per k-point");
   AFQ_CHECK((long)nk * m <= 4096 && (long)nk * std::max(nu, nd) <= 128, AFQ_E_UNSUPPORTED,
             "afq_kp_system_create: at most 4096 orbitals and 128 electrons per spin");
+  AFQ_CHECK(std::max(nu, nd) <= KP_NS_MAX && nk * std::max(nu, nd) <= 256, AFQ_E_UNSUPPORTED,
+            "afq_kp_system_create: at most 16 electrons per k-point and spin");
   AFQ_CHECK(kq && hk && Lk && phik, AFQ_E_INVALID, "afq_kp_system_create: NULL input");
   AFQ_CHECK(prec == AFQ_FP64, AFQ_E_UNSUPPORTED, "afq_kp_system_create: k-point systems run in FP64 mode");
   AFQ_CHECK(std::isfinite(e_core), AFQ_E_INVALID, "afq_kp_system_create: e_core is not finite");
@@ -322,94 +325,103 @@ int kp_abuild(afq_system s, afq_walkers w, const double2* coef, hipStream_t st) 
 }
 
 // ---------------------------------------------------------------------------
-// traces: one workgroup per (row block k1, Q, walker x spin). For every n:
-//   Omega[(k1,a),(k',b)]  = sum_l Lt^{Q,k2}_n[a][l] Theta[(k2,l),(k',b)],   k2 + Q = k1
-//   Omega'[(k',b),(k1,a)] = sum_l Ltd^{Q,k'}_n[b][l] Theta[(k'+Q,l),(k1,a)]
-// and the row block's share of tr(Omega Omega'), tr(Omega), tr(Omega').
+// traces: one workgroup per (row block k1, Q, walker x spin). With k2 + Q = k1,
+// for every vector n and every column c = (k', b) of the spin's trial block:
+//   Omega[(k1,a), c]      = sum_l Lt^{Q,k2}_n[a][l]  Theta[(k2, l), c]
+//   Omega'[c, (k1,a)]     = sum_l Ltd^{Q,k'}_n[b][l] Theta[(k'+Q, l), (k1, a)]
+// One thread owns one (n, c) and all a: it keeps the 2 x ns accumulators, so
+// each Theta / Ltd element it loads feeds ns multiply-adds. The Theta block
+// rows (k2, .) and the columns (k1, .) are staged in LDS once per workgroup;
+// the row block's shares of tr(Omega Omega'), tr(Omega), tr(Omega') are summed
+// over the columns in a fixed order.
 // ---------------------------------------------------------------------------
 struct KpTraceArgs {
   const double2* thetaT;   // nw x ntot x M
   const double2* Lt;       // [Q][k][n][a][l], a over nkn = nu + nd
   const double2* Ltd;
   const int* kq;
-  const int* kd;
   int nk, m, xq, nu, nd, ntot, M;
   double2* part;           // [w][spin][Q][n][k1][3]
 };
 
-__device__ inline double2 wave_sum(double2 v) {
-  for (int off = 32; off > 0; off >>= 1) {
-    v.x += __shfl_xor(v.x, off);
-    v.y += __shfl_xor(v.y, off);
-  }
-  return v;
-}
-
-__global__ __launch_bounds__(256) void kp_trace_kernel(KpTraceArgs a) {
+template <int NS>
+__global__ __launch_bounds__(256) void kp_trace_kernel(KpTraceArgs a, int sp) {
   extern __shared__ double2 lds[];
-  const int k1 = blockIdx.x, Q = blockIdx.y, w = blockIdx.z >> 1, sp = blockIdx.z & 1, t = threadIdx.x;
+  const int k1 = blockIdx.x, Q = blockIdx.y, w = blockIdx.z, t = threadIdx.x;
   const int nk = a.nk, m = a.m, M = a.M;
-  const int ns = sp ? a.nd : a.nu, N = nk * ns, off = sp ? nk * a.nu : 0, aoff = sp ? a.nu : 0;
+  const int ns = NS, N = nk * ns, off = sp ? nk * a.nu : 0, aoff = sp ? a.nu : 0;
   const int nkn = a.nu + a.nd;
-  int ksrc = 0;                                        // k2 with k2 + Q = k1
+  int k2 = 0;                               // k2 + Q = k1
   for (int c = 0; c < nk; ++c)
-    if (a.kq[Q * nk + c] == k1) ksrc = c;
-  double2* thA = lds;                       // [l][c]: Theta[(ksrc, l), c], c < N
-  double2* thB = thA + (long)m * N;         // [r][aa]: Theta[r, (k1, aa)], r < M, aa < ns
-  double2* LtS = thB + (long)M * ns;        // [aa][l]: Lt^{Q,ksrc}_n
-  double2* LtdS = LtS + (long)ns * m;       // [k'][b][l]: Ltd^{Q,k'}_n
-  double2* wp = LtdS + (long)nk * ns * m;   // [n][wave][3]
+    if (a.kq[Q * nk + c] == k1) k2 = c;
+  const int npar = 256 / N;                 // vectors per pass
+  double2* thA = lds;                       // [l][c]: Theta[(k2, l), c]
+  double2* thB = thA + (long)m * N;         // [r][aa]: Theta[r, (k1, aa)]
+  double2* pp = thB + (long)M * ns;         // [npar][N][3]: per-thread shares of one pass
+  double2* wp = pp + (long)npar * N * 3;    // [xq][3]
   const double2* th = a.thetaT + (long)w * a.ntot * M;
   for (int e = t; e < N * m; e += 256) {
     const int c = e / m, l = e - c * m;
-    thA[l * N + c] = th[(long)(off + c) * M + ksrc * m + l];
+    thA[l * N + c] = th[(long)(off + c) * M + k2 * m + l];
   }
   for (int e = t; e < ns * M; e += 256) {
     const int aa = e / M, r = e - aa * M;
     thB[r * ns + aa] = th[(long)(off + k1 * ns + aa) * M + r];
   }
-  const int lane = t & 63, wave = t >> 6;
-  const int npair = ns * N;                 // (aa, k', b)
-  for (int n = 0; n < a.xq; ++n) {
-    __syncthreads();                        // previous n done with LtS / LtdS; Theta staged
-    const double2* lt = a.Lt + ((((long)Q * nk + ksrc) * a.xq + n) * nkn + aoff) * m;
-    for (int e = t; e < ns * m; e += 256) LtS[e] = lt[e];
-    for (int e = t; e < nk * ns * m; e += 256) {
-      const int kp = e / (ns * m), rest = e - kp * ns * m;
-      LtdS[e] = a.Ltd[((((long)Q * nk + kp) * a.xq + n) * nkn + aoff) * m + rest];
+  __syncthreads();
+  const int nl = t / N, c = t - nl * N;
+  const int kp = c / ns, b = c - kp * ns;
+  const int rb = a.kq[Q * nk + kp];         // row block k' + Q of Theta for Omega'
+  for (int n0 = 0; n0 < a.xq; n0 += npar) {
+    const int n = n0 + nl;
+    if (nl < npar && n < a.xq) {
+      const double2* lt = a.Lt + ((((long)Q * nk + k2) * a.xq + n) * nkn + aoff) * m;
+      const double2* ltd = a.Ltd + ((((long)Q * nk + kp) * a.xq + n) * nkn + aoff + b) * m;
+      double2 om[NS], omd[NS];
+#pragma unroll
+      for (int q = 0; q < NS; ++q) om[q] = omd[q] = make_double2(0.0, 0.0);
+      for (int l = 0; l < m; ++l) {
+        const double2 xa = thA[l * N + c];
+        const double2 xd = ltd[l];
+        const double2* tb = thB + (rb * m + l) * ns;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+          om[q] = cadd(om[q], cmul(lt[q * m + l], xa));
+          omd[q] = cadd(omd[q], cmul(xd, tb[q]));
+        }
+      }
+      double2 ek = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < NS; ++q) ek = cadd(ek, cmul(om[q], omd[q]));
+      double2 tl = make_double2(0.0, 0.0), tld = make_double2(0.0, 0.0);
+      if (kp == k1) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q)
+          if (q == b) {
+            tl = om[q];
+            tld = omd[q];
+          }
+      }
+      double2* o = pp + ((long)nl * N + c) * 3;
+      o[0] = ek;
+      o[1] = tl;
+      o[2] = tld;
     }
     __syncthreads();
-    double2 ek = make_double2(0.0, 0.0), tl = make_double2(0.0, 0.0), tld = make_double2(0.0, 0.0);
-    for (int p = t; p < npair; p += 256) {
-      const int aa = p / N, c = p - aa * N, kp = c / ns, b = c - kp * ns;
-      const int rb = a.kq[Q * nk + kp];     // row block k' + Q of Theta for Omega'
-      double2 om = make_double2(0.0, 0.0), omd = make_double2(0.0, 0.0);
-      for (int l = 0; l < m; ++l) {
-        om = cadd(om, cmul(LtS[aa * m + l], thA[l * N + c]));
-        omd = cadd(omd, cmul(LtdS[(kp * ns + b) * m + l], thB[(rb * m + l) * ns + aa]));
-      }
-      ek = cadd(ek, cmul(om, omd));
-      if (kp == k1 && aa == b) {
-        tl = cadd(tl, om);
-        tld = cadd(tld, omd);
+    if (t < npar * 3) {
+      const int q = t / 3, j = t - q * 3, nn = n0 + q;
+      if (nn < a.xq) {
+        double2 v = make_double2(0.0, 0.0);
+        for (int cc = 0; cc < N; ++cc) v = cadd(v, pp[((long)q * N + cc) * 3 + j]);
+        wp[nn * 3 + j] = v;
       }
     }
-    ek = wave_sum(ek);
-    tl = wave_sum(tl);
-    tld = wave_sum(tld);
-    if (lane == 0) {
-      wp[(n * 4 + wave) * 3] = ek;
-      wp[(n * 4 + wave) * 3 + 1] = tl;
-      wp[(n * 4 + wave) * 3 + 2] = tld;
-    }
+    __syncthreads();
   }
-  __syncthreads();
   double2* out = a.part + ((((long)w * 2 + sp) * nk + Q) * a.xq) * nk * 3;
   for (int e = t; e < a.xq * 3; e += 256) {
     const int n = e / 3, j = e - n * 3;
-    double2 v = wp[(n * 4) * 3 + j];
-    for (int q = 1; q < 4; ++q) v = cadd(v, wp[(n * 4 + q) * 3 + j]);
-    out[((long)n * nk + k1) * 3 + j] = v;
+    out[((long)n * nk + k1) * 3 + j] = wp[n * 3 + j];
   }
 }
 
@@ -440,22 +452,33 @@ int kp_energy_traces(afq_system s, afq_walkers w, hipStream_t st) {
   const int nk = s->kp_nk, xq = s->kp_xq, nw = w->nw;
   const size_t part = (size_t)nw * 2 * nk * xq * nk * 3 * 16;
   if (w->kp_part.bytes < part) AFQ_RET(w->kp_part.alloc(part));
-  static bool attr = false;
-  if (s->kp_lds > 64 * 1024 && !attr) {
-    AFQ_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kp_trace_kernel),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)KP_MAX_LDS));
-    attr = true;
-  }
+
   KpTraceArgs a{};
   a.thetaT = w->theta.as<double2>();
   a.Lt = s->kp_Lt.as<double2>();
   a.Ltd = s->kp_Ltd.as<double2>();
   a.kq = s->kp_kq.as<int>();
-  a.kd = s->kp_kd.as<int>();
   a.nk = nk; a.m = s->kp_m; a.xq = xq; a.nu = s->kp_nu; a.nd = s->kp_nd; a.ntot = s->ntot; a.M = s->M;
   a.part = w->kp_part.as<double2>();
-  hipLaunchKernelGGL(kp_trace_kernel, dim3(nk, nk, 2 * nw), dim3(256), s->kp_lds, st, a);
-  AFQ_TRY_HIP(hipGetLastError());
+  for (int sp = 0; sp < 2; ++sp) {
+    const int ns = sp ? s->kp_nd : s->kp_nu;
+    switch (ns) {
+#define AFQ_KP_NS(V)                                                                                   \
+  case V:                                                                                              \
+    if (s->kp_lds > 64 * 1024)                                                                         \
+      AFQ_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kp_trace_kernel<V>),              \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)s->kp_lds));   \
+    hipLaunchKernelGGL(kp_trace_kernel<V>, dim3(nk, nk, nw), dim3(256), s->kp_lds, st, a, sp);          \
+    break;
+      AFQ_KP_NS(1) AFQ_KP_NS(2) AFQ_KP_NS(3) AFQ_KP_NS(4) AFQ_KP_NS(5) AFQ_KP_NS(6) AFQ_KP_NS(7) AFQ_KP_NS(8)
+      AFQ_KP_NS(9) AFQ_KP_NS(10) AFQ_KP_NS(11) AFQ_KP_NS(12) AFQ_KP_NS(13) AFQ_KP_NS(14) AFQ_KP_NS(15)
+      AFQ_KP_NS(16)
+#undef AFQ_KP_NS
+      default:
+        AFQ_CHECK(false, AFQ_E_UNSUPPORTED, "k-point trace kernel: at most 16 electrons per k-point and spin");
+    }
+    AFQ_TRY_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(kp_reduce_kernel, dim3(ceil_div(nk * xq, 256), 2 * nw), dim3(256), 0, st, w->kp_part.as<double2>(),
                      nk, xq, w->tro.as<double2>(), w->troo.as<double2>());
   AFQ_TRY_HIP(hipGetLastError());

@@ -210,6 +210,11 @@ WORKLOADS = {
                  n_steps=100, qr_every=5, seed=5, field_seed=1005),
     # orthogonal multi-determinant trial: 256 determinants drawn in an active
     # space of 8 occupied and 16 virtual orbitals per spin, rank <= 4 per spin
+    # k-point-blocked Cholesky: 8 k-points on a ring, 24 orbitals and 6 + 6
+    # electrons per k-point, 96 vectors per momentum transfer (M = 192, N = 48
+    # per spin, 768 complex vectors, 1536 auxiliary fields)
+    "kp_m192": dict(nk=8, m=24, n_up=6, n_dn=6, xq=96, n_walkers=256, dt=0.005, n_steps=100, qr_every=5,
+                    seed=7, field_seed=1007),
     "msd_m128": dict(M=128, n_up=16, n_dn=16, n_chol=512, n_walkers=256, dt=0.005,
                      n_steps=100, qr_every=5, seed=6, field_seed=1006, n_det=256, occ_act=8,
                      vir_act=16, k_max=4, msd_seed=2006),
