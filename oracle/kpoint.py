@@ -117,11 +117,15 @@ def force_bias(L, T, W, n_up, n_dn):
     return np.concatenate([np.einsum("gik,ki->g", a, Gt), np.einsum("gik,ki->g", b, Gt)])
 
 
-def run(h, L, T, n_up, n_dn, W0, weights0, fields, dt, qr_every=5, e_shift=0.0, order=6, e_core=0.0):
+def run(h, L, T, n_up, n_dn, W0, weights0, fields, dt, qr_every=5, e_shift=0.0, order=6, e_core=0.0,
+        bp_start=None, bp_len=0):
     """The phaseless walk of oracle/afqmc.run for general complex Cholesky
     vectors: fields[k, w] has 2X entries (x for the a_g, then y for the b_g);
     B1 = exp(-dt h'/2) with h' Hermitian; energy and force bias at the
-    start-of-step walker; QR every qr_every steps."""
+    start-of-step walker; QR every qr_every steps. With bp_start set, the
+    back-propagation window of oracle/afqmc.run is recorded (coefficients
+    i sqrt(dt) (z - zbar) of the 2X Hermitian operators out["ops"]); out["B1"]
+    is the one-body factor."""
     nw = W0.shape[0]
     X = L.shape[0]
     hp = one_body_corrected(h, L)
@@ -136,7 +140,11 @@ def run(h, L, T, n_up, n_dn, W0, weights0, fields, dt, qr_every=5, e_shift=0.0, 
     n_steps = fields.shape[0]
     out = dict(emix=np.zeros(n_steps), eloc=np.zeros((n_steps, nw), np.complex128),
                weights=np.zeros((n_steps, nw)), ratio=np.zeros((n_steps, nw), np.complex128))
+    out.update(B1=B1, ops=ops)
     for k in range(n_steps):
+        if bp_start == k:
+            out["bp_W0"] = W.copy()
+            out["bp_coefs"] = np.zeros((bp_len, nw, 2 * X), np.complex128)
         vb = np.zeros((nw, 2 * X), np.complex128)
         for i in range(nw):
             out["eloc"][k, i] = local_energy(h, L, T, W[i], n_up, n_dn, e_core)[0]
@@ -149,6 +157,8 @@ def run(h, L, T, n_up, n_dn, W0, weights0, fields, dt, qr_every=5, e_shift=0.0, 
             x = fields[k, i]
             xbar = afqmc.force_bias_shift(vb[i], dt)
             A = np.tensordot(1j * np.sqrt(dt) * (x - xbar), ops, axes=1)
+            if bp_start is not None and bp_start <= k < bp_start + bp_len:
+                out["bp_coefs"][k - bp_start, i] = 1j * np.sqrt(dt) * (x - xbar)
             Wn = B1 @ afqmc.taylor_apply(A, B1 @ W[i], order)
             logOn = afqmc.theta(T, Wn, n_up, n_dn)[1]
             log_r = logOn - logO[i]
@@ -172,5 +182,7 @@ def run(h, L, T, n_up, n_dn, W0, weights0, fields, dt, qr_every=5, e_shift=0.0, 
                     W[i][:, bl] = Q
                     logO[i] -= np.sum(np.log(np.diag(R).real))
         out["weights"][k] = w
+        if bp_start is not None and k == bp_start + bp_len - 1:
+            out["bp_weights"] = w.copy()
     out.update(W=W, w=w, logO=logO, alive=alive)
     return out
