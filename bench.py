@@ -52,10 +52,11 @@ def flops_per_walker_step(M, N, X, K=6, qr_every=5, real_trial=True):
     return sum(parts.values()), parts, sum(model.values())
 
 
-def profiled_traffic(kernel_src, profile_md):
-    """HBM bytes per launch of the exchange kernel measured with rocprofv3 PMC
-    counters (FETCH_SIZE/WRITE_SIZE, calibrated on a device copy) and recorded
-    in the profile summary, or None once the kernel source has changed since."""
+def profiled_traffic(kernel_src, profile_md, tag):
+    """HBM bytes per launch of a kernel measured with rocprofv3 PMC counters
+    (FETCH_SIZE/WRITE_SIZE, calibrated on a device copy) and recorded in the
+    profile summary as `traffic_bytes_per_launch=B <tag>_sha256_16=H`, or None
+    once the kernel source has changed since."""
     import hashlib
     import re
     try:
@@ -63,7 +64,7 @@ def profiled_traffic(kernel_src, profile_md):
         text = open(profile_md).read()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch=(\d+) exchange_big_sha256_16=([0-9a-f]+)", text)
+    m = re.search(r"traffic_bytes_per_launch=(\d+) " + re.escape(tag) + r"_sha256_16=([0-9a-f]+)", text)
     if not m or m.group(2) != sha:
         return None
     return int(m.group(1))
@@ -315,6 +316,8 @@ def main(argv=None):
     ap.add_argument("--compare-steps", type=int, default=3, help="timed steps of the other precisions (0: skip)")
     ap.add_argument("--check-steps", type=int, default=2, help="steps of the 4-walker oracle check (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--exchange-form", default="auto", choices=["auto", "cholesky", "four_index"],
+                    help="exchange form of the split-BF16x3 mode (auto: four-index where it pays)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this many MiB (calibrates HBM byte counters) and exit")
     a = ap.parse_args(argv)
@@ -353,7 +356,11 @@ def main(argv=None):
     print(f"[bench] system generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
     lib = _lib.load()
-    sysg = api.System.from_synth(s, precision=a.precision)
+    t0 = time.perf_counter()
+    sysg = api.System.from_synth(s, precision=a.precision, exchange_form=a.exchange_form)
+    form, tensor_bytes = sysg.exchange_form()
+    print(f"[bench] system set up in {time.perf_counter() - t0:.1f}s, exchange form {form} "
+          f"({tensor_bytes / 1e9:.2f} GB tensor)", file=sys.stderr, flush=True)
     # E_shift = variational energy of the trial (walkers at the trial)
     probe = api.Walkers(sysg, 1)
     e_var = float(probe.energy()[3][0])
@@ -385,29 +392,57 @@ def main(argv=None):
     value = nw * a.steps / wall
     flop_ws, flop_parts, flop_model = flops_per_walker_step(M, nu, X, 6, qr)
     alg_tflops = flop_ws * nw * a.steps / wall / 1e12
+    flop_exec = flop_ws
+    if form == "four_index":
+        flop_exec = flop_ws - flop_parts["exchange"] + 2 * 2.0 * (nu * M) ** 2
 
     ex_ms, ex_cnt = phases["exchange"]
-    # roofline: the exchange term of the general (complex L~) flop model, one
-    # spin per launch; the real-L~ count the kernel actually needs is beside it
-    per_launch_flops = (8.0 * X * nu * nu * M + 8.0 * X * nu * nu) * nw
-    per_launch_real = flop_parts["exchange"] / 2 * nw
     ex_avg_s = ex_ms / 1e3 / max(ex_cnt, 1)
-    achieved = per_launch_flops / ex_avg_s / 1e12
     peak = PEAK_TFLOPS[a.precision]
-    traffic = None
-    if a.precision == "bf16x3" and a.workload == "m400" and nw == 512:
-        traffic = profiled_traffic(os.path.join(ROOT, "paper_2003_01831_amd", "csrc", "exchange_big.hip"),
-                                   os.path.join(ROOT, "profiles", "exchange_bf16x3_m400.md"))
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "exchange kernel (fused Omega = Lt Theta, tr Omega, tr Omega^2), one spin per launch",
-                "flop_per_launch": per_launch_flops,
-                "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt,
-                "achieved_real_lt": round(per_launch_real / ex_avg_s / 1e12, 3)}
-    if a.precision == "bf16x3":
-        # split-BF16x3 issues three BF16 products per FP32-class product; against
-        # that effective peak, count only the multiply-adds the real L~ needs
-        roofline["real_lt_frac_of_bf16x3_effective_peak"] = round(roofline["achieved_real_lt"] / (peak / 3), 4)
+    csrc = os.path.join(ROOT, "paper_2003_01831_amd", "csrc")
+    if form == "four_index":
+        # the quadratic form Theta^T W Theta over the upper block triangle of the
+        # symmetric half-rotated tensor: (N M)^2 / 2 real-by-complex multiply-adds
+        # (4 flop each) per walker and spin, one spin per launch
+        NM = nu * M
+        per_launch_flops = 2.0 * NM * NM * nw
+        traffic = None
+        if a.workload == "m400" and nw == 512:
+            traffic = profiled_traffic(os.path.join(csrc, "eri.hip"),
+                                       os.path.join(ROOT, "profiles", "eri_bf16x3_m400.md"), "eri")
+        roofline = {"bound": "mfma", "achieved": round(per_launch_flops / ex_avg_s / 1e12, 3), "peak": peak,
+                    "unit": "TFLOP/s", "traffic": traffic,
+                    "kernel": "four-index exchange kernel (W'' Theta-hat in split BF16x3, FP64 epilogue) "
+                              "plus its per-walker reduction, one spin per launch",
+                    "flop_per_launch": per_launch_flops,
+                    "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt}
+        roofline["frac"] = round(roofline["achieved"] / peak, 4)
+        # every algorithmic product is three BF16 products (hi*hi + hi*lo + lo*hi)
+        roofline["bf16_products_per_flop"] = 3
+        roofline["mfma_pipe_frac"] = round(3 * roofline["achieved"] / peak, 4)
+        # the same exchange term counted with the Cholesky-form model, for comparison
+        roofline["cholesky_model_equivalent_tflops"] = round(
+            (8.0 * X * nu * nu * M + 8.0 * X * nu * nu) * nw / ex_avg_s / 1e12, 3)
+    else:
+        # the exchange term of the general (complex L~) flop model, one spin per
+        # launch; the real-L~ count the kernel actually needs is beside it
+        per_launch_flops = (8.0 * X * nu * nu * M + 8.0 * X * nu * nu) * nw
+        per_launch_real = flop_parts["exchange"] / 2 * nw
+        achieved = per_launch_flops / ex_avg_s / 1e12
+        traffic = None
+        if a.precision == "bf16x3" and a.workload == "m400" and nw == 512:
+            traffic = profiled_traffic(os.path.join(csrc, "exchange_big.hip"),
+                                       os.path.join(ROOT, "profiles", "exchange_bf16x3_m400.md"), "exchange_big")
+        roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 4), "traffic": traffic,
+                    "kernel": "exchange kernel (fused Omega = Lt Theta, tr Omega, tr Omega^2), one spin per launch",
+                    "flop_per_launch": per_launch_flops,
+                    "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt,
+                    "achieved_real_lt": round(per_launch_real / ex_avg_s / 1e12, 3)}
+        if a.precision == "bf16x3":
+            # split-BF16x3 issues three BF16 products per FP32-class product; against
+            # that effective peak, count only the multiply-adds the real L~ needs
+            roofline["real_lt_frac_of_bf16x3_effective_peak"] = round(roofline["achieved_real_lt"] / (peak / 3), 4)
 
     extra = {}
     # population control at this size: one comb of all walkers (host-synchronising)
@@ -512,11 +547,16 @@ def main(argv=None):
         "vs_baseline": None, "dtype": DTYPE[a.precision], "data": "synthetic",
         "config": {"workload": f"{a.workload}: M={M}, N_up=N_dn={nu}, Nchol={X}, {nw} walkers, dt={dt}, "
                                f"QR every {qr}, Taylor order 6, energy every step, Philox fields",
-                   "precision": a.precision, "walkers": nw, "parallelism": "single GPU"},
+                   "precision": a.precision, "walkers": nw, "parallelism": "single GPU",
+                   "exchange_form": form, "four_index_tensor_gb": round(tensor_bytes / 1e9, 3)},
         "alg_tflops": round(flop_model * nw * a.steps / wall / 1e12, 3),
         "alg_tflops_real_lt": round(alg_tflops, 3),
         "flop_per_walker_step": flop_model,
         "flop_per_walker_step_real_lt": flop_ws,
+        # the algorithm actually run: with the four-index form the exchange term
+        # is 2 (N M)^2 flop per spin instead of the Cholesky form's count
+        "flop_per_walker_step_executed": flop_exec,
+        "alg_tflops_executed": round(flop_exec * nw * a.steps / wall / 1e12, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "err_vs_fp64_oracle": err,

@@ -97,6 +97,38 @@ int afq_system_create(afq_system *out, int M, int n_up, int n_dn, int n_chol,
 /* Switches the contraction precision (prepares the packed operand copies;
  * synchronises). */
 int afq_system_set_precision(afq_system s, int precision);
+
+/* Form of the exchange term sum_n tr(Omega_n Omega_n) of the local energy
+ * (Eq. "EL" with the half-rotated Cholesky vectors of the AFQMC section's
+ * computational-cost discussion). The Cholesky form contracts every vector
+ * (X N^2 M products per walker and spin); the four-index form uses
+ *   sum_n tr(Omega_n Omega_n) = Theta^T W Theta,
+ *   W[(b,k),(a,l)] = sum_n (T^H L^n)[a][k] (T^H L^n)[b][l],
+ * the half-rotated two-electron tensor, built once per system, which needs
+ * (N M)^2 / 2 products (its symmetric upper block triangle) and N^2 M^2 stored
+ * entries per distinct spin block (split into BF16 hi / lo planes). The
+ * four-index form exists in split-BF16x3 mode for a real trial on plain
+ * (single-determinant, not k-point-blocked) systems; elsewhere the Cholesky
+ * form is used whatever the setting. */
+typedef enum {
+  AFQ_EXCH_AUTO = 0,       /* four-index form when it needs fewer products (M < 2X),
+                              N M >= 4096, and its tensor takes at most a quarter
+                              of the free device memory; else Cholesky (default) */
+  AFQ_EXCH_CHOLESKY = 1,   /* always the Cholesky form */
+  AFQ_EXCH_FOUR_INDEX = 2  /* the four-index form where it exists */
+} afq_exchange_form;
+
+/* Sets the exchange form (AFQ_EXCH_*). Builds the four-index tensor at once
+ * when it will be used, or frees it when it will not (synchronises; may
+ * allocate N^2 M^2 * 4 bytes per distinct spin block plus an FP64 set-up
+ * transient of N^2 M^2 * 8 bytes). A batch holding the system captures its
+ * step again on its next call. AFQ_E_INVALID for an unknown form,
+ * AFQ_E_NOMEM when the tensor does not fit. */
+int afq_system_set_exchange_form(afq_system s, int form);
+/* The form the next step uses: *in_use = AFQ_EXCH_CHOLESKY or
+ * AFQ_EXCH_FOUR_INDEX; *tensor_bytes (optional) = device bytes the four-index
+ * tensor holds (0 when none). */
+int afq_system_exchange_form(afq_system s, int* in_use, uint64_t* tensor_bytes);
 /* k-point-blocked system (the explicitly k-point dependent Cholesky
  * factorisation of Section "Auxiliary Field Quantum Monte Carlo" and its row
  * of Table tab:afqmc_comp). Copies the inputs (this call synchronises).

@@ -15,6 +15,7 @@ AFQ_OK = 0
 STATUS = {0: "AFQ_OK", -1: "AFQ_E_INVALID", -2: "AFQ_E_NOMEM", -3: "AFQ_E_HIP", -4: "AFQ_E_SINGULAR",
           -5: "AFQ_E_STATE", -6: "AFQ_E_UNSUPPORTED"}
 PRECISION = {"fp64": 0, "cfp32": 1, "bf16x3": 2}
+EXCHANGE_FORM = {"auto": 0, "cholesky": 1, "four_index": 2}
 PHASES = ["overlap", "pack", "exchange", "coulomb", "assemble", "abuild", "taylor", "weight", "qr", "msd_omega",
           "msd_sums"]
 
@@ -24,6 +25,8 @@ SIGNATURES = {
     "afq_system_create": (_i, [C.POINTER(_vp), _i, _i, _i, _i, _vp, _vp, _vp, _d, _i, _vp]),
     "afq_system_set_precision": (_i, [_vp, _i]),
     "afq_system_set_msd": (_i, [_vp, _vp, _i, _vp, _vp]),
+    "afq_system_set_exchange_form": (_i, [_vp, _i]),
+    "afq_system_exchange_form": (_i, [_vp, C.POINTER(_i), C.POINTER(_u64)]),
     "afq_kp_system_create": (_i, [C.POINTER(_vp), _i, _vp, _i, _i, _i, _i, _vp, _vp, _vp, _d, _i, _vp]),
     "afq_system_destroy": (_i, [_vp]),
     "afq_walkers_create": (_i, [C.POINTER(_vp), _vp, _i, _vp, _vp]),

@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import PRECISION, check
+from ._lib import EXCHANGE_FORM, PRECISION, check
 
 
 def _dev():
@@ -39,7 +39,8 @@ def _stream_handle(stream):
 class System:
     """h1 (M x M), chol (X x M x M), trial phi_t (M x (n_up+n_dn)) and E_II."""
 
-    def __init__(self, h1, chol, phi_t, n_up, n_dn, e_core=0.0, precision="fp64", stream=None):
+    def __init__(self, h1, chol, phi_t, n_up, n_dn, e_core=0.0, precision="fp64", stream=None,
+                 exchange_form="auto"):
         self.lib = _lib.load()
         self.h1 = _as_dev(h1, torch.float64)
         self.chol = _as_dev(chol, torch.float64)
@@ -50,15 +51,21 @@ class System:
         self.e_core = float(e_core)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.precision = precision
+        # a non-default exchange form is set before the precision, so that the
+        # automatic choice never builds a tensor that is dropped at once
+        first = precision if exchange_form == "auto" else "fp64"
         h = C.c_void_p()
         check(self.lib.afq_system_create(C.byref(h), self.M, self.n_up, self.n_dn, self.n_chol, _ptr(self.h1),
-                                         _ptr(self.chol), _ptr(self.phi_t), self.e_core, PRECISION[precision],
+                                         _ptr(self.chol), _ptr(self.phi_t), self.e_core, PRECISION[first],
                                          _stream_handle(self.stream)))
         self.handle = h
+        if exchange_form != "auto":
+            self.set_exchange_form(exchange_form)
+            self.set_precision(precision)
 
     @classmethod
-    def from_synth(cls, s, precision="fp64"):
-        return cls(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, s.e_core, precision)
+    def from_synth(cls, s, precision="fp64", exchange_form="auto"):
+        return cls(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, s.e_core, precision, exchange_form=exchange_form)
 
     @classmethod
     def from_kpoint(cls, ks, precision="fp64", stream=None):
@@ -87,6 +94,18 @@ class System:
     def set_precision(self, precision):
         check(self.lib.afq_system_set_precision(self.handle, PRECISION[precision]))
         self.precision = precision
+
+    def set_exchange_form(self, form):
+        """"auto", "cholesky" or "four_index" (the half-rotated two-electron
+        tensor; split-BF16x3 mode with a real trial only)."""
+        check(self.lib.afq_system_set_exchange_form(self.handle, EXCHANGE_FORM[form]))
+
+    def exchange_form(self):
+        """(form the next step uses, device bytes of the four-index tensor)."""
+        f, b = C.c_int(), C.c_uint64()
+        check(self.lib.afq_system_exchange_form(self.handle, C.byref(f), C.byref(b)))
+        names = {v: k for k, v in EXCHANGE_FORM.items()}
+        return names[f.value], int(b.value)
 
     MSD_KMAX = 4
 

@@ -24,6 +24,7 @@ struct afq_batch_s {
   bool tuned = false;
   std::vector<double> e_shift;
   std::vector<double> caps;   // (fb_cap, w_cap) of every walker set, baked into the graph
+  std::vector<unsigned> versions;   // the systems' kernel-sequence versions at capture
   DevBuf emix_cycle;   // n x cycle, written by the graph
   ~afq_batch_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -162,13 +163,21 @@ int batch_step_impl(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_e
   const int prec = b->sys[0]->prec;
   for (int i = 1; i < n; ++i)
     AFQ_CHECK(b->sys[i]->prec == prec, AFQ_E_STATE, "afq_batch_step: systems must share a precision");
+  // settle every system's set-up first: it may change the kernel sequence
+  for (int i = 0; i < n; ++i) {
+    AFQ_RET(system_prepare_dt(b->sys[i], dt));
+    AFQ_RET(system_prepare_pack(b->sys[i], b->sys[i]->prec));
+    AFQ_RET(walkers_alloc_scratch(b->wk[i]));
+  }
+  std::vector<unsigned> versions;
+  for (int i = 0; i < n; ++i) versions.push_back(b->sys[i]->version);
   if (!b->exec || b->prec != prec || b->dt != dt || b->seed != seed || b->qr_every != qr_every || b->order != order || b->e_shift != es ||
-      b->caps != caps) {
+      b->caps != caps || b->versions != versions) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
-    if (b->prec != prec) b->tuned = false;
+    if (b->prec != prec || b->versions != versions) b->tuned = false;
     b->prec = prec;
     b->dt = dt;
     b->seed = seed;
@@ -176,13 +185,9 @@ int batch_step_impl(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_e
     b->order = order;
     b->e_shift = es;
     b->caps = caps;
+    b->versions = versions;
     b->cycle = qr_every > 0 ? qr_every : 1;
     AFQ_RET(b->emix_cycle.alloc((size_t)n * b->cycle * sizeof(double)));
-  }
-  for (int i = 0; i < n; ++i) {
-    AFQ_RET(system_prepare_dt(b->sys[i], dt));
-    AFQ_RET(system_prepare_pack(b->sys[i], b->sys[i]->prec));
-    AFQ_RET(walkers_alloc_scratch(b->wk[i]));
   }
   int done = 0;
   bool warmed = b->exec != nullptr;

@@ -1,0 +1,143 @@
+// Building blocks of the split-BF16x3 MFMA kernels that stream both operands
+// through a three-stage LDS ring filled by direct global->LDS loads:
+//
+//   * operands are packed chunk-major in HBM: 32 contraction elements (64
+//     bytes of BF16) per row and chunk, all rows of chunk 0, then chunk 1, ...,
+//     with separate hi and lo planes;
+//   * one LDS stage holds four regions (A hi, A lo, B hi, B lo) of REG bytes;
+//     rows are 64 bytes whose 16-byte pieces are XOR-swizzled, so fragment
+//     reads (16 bytes per lane) spread over the banks;
+//   * mma_rect multiplies one chunk of a wave's TA x TB block of 16 x 16
+//     tiles as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
+//     accumulators, in two passes (the A hi fragments resident, then the A lo).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ring {
+
+typedef __attribute__((ext_vector_type(4))) float f4;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((address_space(3))) unsigned char lds_t;
+
+constexpr int KC = 32;              // contraction elements per chunk (bf16)
+constexpr int ROWB = KC * 2;        // bytes per LDS row per plane (one chunk of one row)
+constexpr int CPR = ROWB / 16;      // 16-byte pieces per row
+
+// XOR swizzle of the 16-byte pieces of a 64-byte row (an involution)
+__device__ inline int swz(int row, int c) { return c ^ ((row >> 1) & 3); }
+
+__device__ inline uint4 lds16(const unsigned char* p) { return *reinterpret_cast<const uint4*>(p); }
+
+__device__ inline bf16x8 frag(const unsigned char* plane, int row, int lq) {
+  return __builtin_bit_cast(bf16x8, lds16(plane + row * ROWB + 16 * swz(row, lq)));
+}
+
+// One chunk (32 contraction elements) of this wave's TA x TB block of 16 x 16
+// tiles. A planes at la (hi, then lo PA bytes later), B planes at lb (lo PB
+// bytes after hi); the wave's rows start at arow (A) and brow (B).
+template <int TA, int TB, int PA, int PB>
+__device__ inline void mma_rect(f4 (&acc)[TA][TB], const unsigned char* la, const unsigned char* lb, int arow,
+                                int brow, int lane) {
+  const int lr = lane & 15, lq = lane >> 4;
+  bf16x8 a[TA];
+#pragma unroll
+  for (int i = 0; i < TA; ++i) a[i] = frag(la, arow + 16 * i + lr, lq);
+  bf16x8 bh = frag(lb, brow + lr, lq), bl = frag(lb + PB, brow + lr, lq);
+#pragma unroll
+  for (int j = 0; j < TB; ++j) {
+    bf16x8 nh = bh, nl = bl;
+    if (j + 1 < TB) {
+      nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
+      nl = frag(lb + PB, brow + 16 * (j + 1) + lr, lq);
+    }
+    // hi*hi for every row tile, then hi*lo: consecutive MFMAs never depend on
+    // each other's result
+#pragma unroll
+    for (int i = 0; i < TA; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < TA; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl, acc[i][j], 0, 0, 0);
+    bh = nh;
+    bl = nl;
+  }
+#pragma unroll
+  for (int i = 0; i < TA; ++i) a[i] = frag(la + PA, arow + 16 * i + lr, lq);
+  bh = frag(lb, brow + lr, lq);
+#pragma unroll
+  for (int j = 0; j < TB; ++j) {
+    bf16x8 nh = bh;
+    if (j + 1 < TB) nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
+#pragma unroll
+    for (int i = 0; i < TA; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
+    bh = nh;
+  }
+}
+
+// The square case with equal plane offsets, written out rather than through
+// mma_rect: the exchange kernel's schedule and register allocation were tuned
+// on this form.
+template <int TM, int RB>
+__device__ inline void mma_chunk(f4 (&acc)[TM][TM], const unsigned char* la, const unsigned char* lb, int arow,
+                                 int brow, int lane) {
+  const int lr = lane & 15, lq = lane >> 4;
+  bf16x8 a[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) a[i] = frag(la, arow + 16 * i + lr, lq);
+  bf16x8 bh = frag(lb, brow + lr, lq), bl = frag(lb + RB, brow + lr, lq);
+#pragma unroll
+  for (int j = 0; j < TM; ++j) {
+    bf16x8 nh = bh, nl = bl;
+    if (j + 1 < TM) {
+      nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
+      nl = frag(lb + RB, brow + 16 * (j + 1) + lr, lq);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl, acc[i][j], 0, 0, 0);
+    bh = nh;
+    bl = nl;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i) a[i] = frag(la + RB, arow + 16 * i + lr, lq);
+  bh = frag(lb, brow + lr, lq);
+#pragma unroll
+  for (int j = 0; j < TM; ++j) {
+    bf16x8 nh = bh;
+    if (j + 1 < TM) nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
+    bh = nh;
+  }
+}
+
+// Direct global->LDS loads and their waits, written as inline asm so that the
+// compiler's wait-count pass does not track them: it cannot tell the three
+// ring buffers apart across the loop and would add a conservative vmcnt(0)
+// before the LDS reads of some steps. A kernel using them therefore waits for
+// its own loads explicitly (every LDS read of a buffer follows a vmcnt wait
+// covering that buffer's loads and a barrier). Lane l of a load writes LDS
+// bytes [m0 + BYTES l, m0 + BYTES (l + 1)). No VGPR is written by these loads.
+// M0 is reserved by the compiler, but the kernels using these helpers use it
+// nowhere else (no indirect register indexing, message or GWS instruction),
+// so clobbering it here is safe; the warning about it is silenced for these two.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ inline void dma16(const unsigned char* src, lds_t* dst) {
+  const unsigned m = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)dst);
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(m) : "memory", "m0");
+}
+__device__ inline void dma4(const unsigned char* src, lds_t* dst) {
+  const unsigned m = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)dst);
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(src), "s"(m) : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// s_waitcnt vmcnt(W) followed by s_barrier, one opaque statement: it is also a
+// compiler-level memory barrier, so no LDS access moves across it
+template <int W> __device__ inline void wait_vm_barrier() {
+  static_assert(W >= 0 && W < 64, "vmcnt is 6 bits");
+  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(W) : "memory");
+}
+
+}  // namespace ring

@@ -53,6 +53,27 @@ int afq_system_set_precision(afq_system s, int precision) {
   AFQ_GUARD(AFQ_RET(check_device(s)); return system_prepare_pack(s, precision);)
 }
 
+int afq_system_set_exchange_form(afq_system s, int form) {
+  AFQ_CHECK(s, AFQ_E_INVALID, "afq_system_set_exchange_form: system is NULL");
+  AFQ_CHECK(form >= AFQ_EXCH_AUTO && form <= AFQ_EXCH_FOUR_INDEX, AFQ_E_INVALID,
+            "afq_system_set_exchange_form: unknown form");
+  AFQ_GUARD({
+    AFQ_RET(check_device(s));
+    if (form != s->eri_form) {
+      s->eri_form = form;
+      s->eri_declined = false;
+    }
+    return eri_sync(s);
+  })
+}
+
+int afq_system_exchange_form(afq_system s, int* in_use, uint64_t* tensor_bytes) {
+  AFQ_CHECK(s && in_use, AFQ_E_INVALID, "afq_system_exchange_form: NULL argument");
+  *in_use = s->eri_ready ? AFQ_EXCH_FOUR_INDEX : AFQ_EXCH_CHOLESKY;
+  if (tensor_bytes) *tensor_bytes = eri_tensor_bytes(s);
+  return AFQ_OK;
+}
+
 int afq_kp_system_create(afq_system* out, int nk, const int32_t* kq, int m, int n_up, int n_dn, int xq,
                          const double* hk, const double* Lk, const double* phik, double e_core, int precision,
                          void* stream) {

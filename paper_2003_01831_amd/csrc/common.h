@@ -156,6 +156,15 @@ struct afq_system_s {
   DevBuf kp_h;                 // M x M complex h (block diagonal)
   DevBuf B1c;                  // M x M complex B1 = exp(-dt h'/2) (block diagonal)
   std::vector<double2> kp_hp;  // h' blocks on the host, nk x m x m
+  // four-index exchange (split-BF16x3, real trial): W'' planes per distinct spin block
+  int eri_form = AFQ_EXCH_AUTO;
+  bool eri_ready = false;      // planes built for the current configuration
+  bool eri_share = false;      // both spins use block 0 (equal trial blocks)
+  bool eri_declined = false;   // the automatic choice said no for this configuration
+  DevBuf eri_w[2];             // hi and lo planes, chunk-major [chunk][rows][32] bf16
+  DevBuf eri_units[2];         // work units (row block, first chunk, chunks, 0)
+  int eri_nunit[2] = {0, 0};
+  unsigned version = 0;        // bumped when the step's kernel sequence changes (batches capture again)
   int nspin_n(int s) const { return s == 0 ? n_up : n_dn; }
   int spin_off(int s) const { return s == 0 ? 0 : n_up; }
 };
@@ -216,6 +225,9 @@ struct afq_walkers_s {
   DevBuf kp_part;              // nw x 2 x nk x xq x nk x 3 complex: per-row-block traces
   DevBuf kp_cd;                // 2 x nw x nk xq complex: c and conj(d) of A = sum c L + d L^+
   DevBuf kp_tmp;               // 2 x nk x nw x nk m^2 complex: A-build GEMM outputs
+  // four-index exchange scratch
+  DevBuf eri_theta;            // packed Theta-hat hi / lo planes of one spin
+  DevBuf eri_part;             // per (work unit, column) complex partial sums
 };
 
 // ---------------------------------------------------------------------------
@@ -295,6 +307,15 @@ int kp_prepare_dt(afq_system s, double dt);
 int kp_energy_traces(afq_system s, afq_walkers w, hipStream_t st);
 // amat = sum_g (c_g L^g + d_g L^g+) from the 2X propagator coefficients coef (complex f64)
 int kp_abuild(afq_system s, afq_walkers w, const double2* coef, hipStream_t st);
+
+// four-index exchange (eri.hip)
+// builds or frees the W'' planes to match the system's precision, trial and form
+int eri_sync(afq_system s);
+int eri_alloc_scratch(afq_system s, afq_walkers w);
+size_t eri_tensor_bytes(afq_system s);
+// Theta-hat planes of one spin; then troo[w][spin][0] = sum_n tr(Omega_n Omega_n), troo[w][spin][n > 0] = 0
+int eri_pack(afq_system s, afq_walkers w, int sp, hipStream_t st);
+int eri_exchange(afq_system s, afq_walkers w, int sp, hipStream_t st);
 
 // orthogonal multi-determinant trial (msd.hip)
 constexpr int MSD_KMAX = 4;                                   // excitation rank per spin

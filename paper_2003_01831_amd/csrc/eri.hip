@@ -1,0 +1,496 @@
+// Exchange through the half-rotated four-index tensor (split-BF16x3 mode,
+// real trial). With Theta-hat = vec(Theta^s), index (a, k) -> a M + k, the sum
+// over Cholesky vectors of tr(Omega_n Omega_n) is one quadratic form,
+//   sum_n tr(Omega_n Omega_n) = Theta-hat^T W' Theta-hat,
+//   W'[(b,k),(a,l)] = sum_n Lt_n[a][k] Lt_n[b][l]      (Lt_n = T^H L^n, N x M),
+// W' symmetric of order N M. Cut into blocks of RA rows, the form is
+//   sum_p theta_p^T W'_pp theta_p + 2 sum_{p<q} theta_p^T W'_pq theta_q,
+// so only the upper block triangle is contracted: W'' = W' on the diagonal
+// blocks, 2 W' above them (exact in BF16), and row block p runs over the
+// contraction columns from its own diagonal block on. Per walker and spin
+// that is (N M)^2 / 2 multiply-adds instead of the X N^2 M of the Cholesky
+// form (1/8 of it at M = 400, X = 1600), for N^2 M^2 stored entries (BF16 hi
+// and lo planes: 6.4 GB per distinct spin block at M = 400, N = 100).
+//
+// W' is formed once per system: Lt transposed to [(a,k)][n], an FP64 GEMM over
+// n, then the permutation and block weighting into chunk-major BF16 planes.
+// Per step: Theta-hat of every walker is packed into rows (w, Re|Im); the
+// kernel multiplies W'' (rows I) by Theta-hat (rows C) in split BF16x3 through
+// the three-stage direct global->LDS ring, one work unit being a row block and
+// a contiguous run of contraction chunks; its epilogue contracts the FP32 tile
+// with Theta-hat in FP64 (no output matrix is stored) and writes one complex
+// partial per (unit, column); a fixed-order reduction gives every walker's sum.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+#include "bf16x3_ring.h"
+#include "common.h"
+#include "step_kernels.h"
+
+namespace {
+
+using ring::bf16x8;
+using ring::dma16;
+using ring::dma4;
+using ring::f4;
+using ring::KC;
+using ring::lds_t;
+using ring::ROWB;
+using ring::swz;
+using ring::wait_vm_barrier;
+
+constexpr int NWAVE = 4;
+constexpr int TA = 8, TB = 4;               // 16 x 16 tiles per wave: W'' rows x Theta-hat rows
+constexpr int RA = 32 * TA, RBR = 32 * TB;  // workgroup tile: 256 x 128 (2 x 2 waves)
+constexpr int REGA = RA * ROWB, REGB = RBR * ROWB;
+constexpr int STAGE = 2 * REGA + 2 * REGB;  // A hi, A lo, B hi, B lo
+constexpr int NT = STAGE / 1024;            // 1 KB load instructions per stage
+constexpr int NQ = NT / NWAVE;              // per wave
+static_assert(NT % NWAVE == 0, "loads must split evenly over the waves");
+constexpr int NXCD = 8;
+
+struct EriArgs {
+  const unsigned char* a[2];   // W'' hi / lo planes: [chunk][rows_a][32] bf16
+  const unsigned char* b[2];   // Theta-hat hi / lo planes: [chunk][rows_b][32] bf16
+  long rows_a, rows_b;
+  const int4* units;           // (row block, first chunk, chunks, 0)
+  int nunit, nblk_b, grid;     // grid: units x column blocks (launched rounded up to a multiple of 8)
+  const double2* thetaT;       // nw x ntot x M
+  int ntot, M, off, NM, nw;
+  double2* part;               // [unit][rows_b]
+};
+
+__global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
+  __shared__ __align__(16) unsigned char L0[STAGE];
+  __shared__ __align__(16) unsigned char L1[STAGE];
+  __shared__ __align__(16) unsigned char L2[STAGE];
+  __shared__ float trash[NWAVE * 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rb = wave >> 1, cb = wave & 1;        // row half (W''), column half (Theta-hat)
+  // XCD-aware order: workgroup i runs on XCD i % 8; each XCD takes a
+  // contiguous range of (unit, column block) pairs, column block fastest, so
+  // the column blocks of one unit share its W'' chunks in that XCD's L2
+  const int per = (int)(gridDim.x / NXCD);
+  const int lid = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+  if (lid >= g.grid) return;
+  const int u = lid / g.nblk_b, bb = lid - u * g.nblk_b;
+  const int4 un = g.units[u];
+  const int c0 = un.y, nc = un.z;                 // nc >= 1
+  const long arow0 = (long)un.x * RA, brow0 = (long)bb * RBR;
+  // load q of this wave: instruction t = q * 4 + wave of the stage, 16 rows of
+  // one region; lane l writes LDS bytes 1024 t + 16 l (row l / 4, swizzled piece)
+  const unsigned char* src[NQ];
+  long cstride[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int t = q * NWAVE + wave;
+    const int reg = t < RA / 16 ? 0 : t < RA / 8 ? 1 : t < RA / 8 + RBR / 16 ? 2 : 3;
+    const int j = reg == 0 ? t : reg == 1 ? t - RA / 16 : reg == 2 ? t - RA / 8 : t - RA / 8 - RBR / 16;
+    const int row = 16 * j + (lane >> 2), c = swz(row, lane & 3);
+    const unsigned char* base = reg == 0 ? g.a[0] : reg == 1 ? g.a[1] : reg == 2 ? g.b[0] : g.b[1];
+    cstride[q] = (reg < 2 ? g.rows_a : g.rows_b) * (long)ROWB;
+    src[q] = base + ((reg < 2 ? arow0 : brow0) + row) * ROWB + 16 * c + (long)c0 * cstride[q];
+  }
+  auto issue = [&](int chunk, unsigned char* buf) {
+    lds_t* l = (lds_t*)buf;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) dma16(src[q] + chunk * cstride[q], l + (q * NWAVE + wave) * 1024);
+  };
+  // the last two steps have no chunk to prefetch: tiny loads into this wave's
+  // trash slice keep the wait count of every step the same
+  auto issue_dummy = [&]() {
+    lds_t* l = (lds_t*)(trash + wave * 64);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) dma4(src[q], l);
+  };
+  f4 acc[TA][TB];
+#pragma unroll
+  for (int i = 0; i < TA; ++i)
+#pragma unroll
+    for (int j = 0; j < TB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const int arow = rb * (RA / 2), brow = cb * (RBR / 2);
+  issue(0, L0);
+  if (nc > 1) issue(1, L1);
+  else issue_dummy();
+  wait_vm_barrier<NQ>();
+  // step c: prefetch chunk c+2 into the buffer chunk c-1 used, multiply
+  // chunk c, wait until chunk c+1 has landed. One step per chunk with the three
+  // buffers rotated (the unrolled form with a fixed buffer per step makes the
+  // register allocator copy the accumulators between register files at every step).
+  unsigned char* cur = L0;
+  unsigned char* nxt = L1;
+  unsigned char* pf = L2;
+  for (int c = 0; c < nc; ++c) {
+    if (c + 2 < nc) issue(c + 2, pf);
+    else issue_dummy();
+    __builtin_amdgcn_sched_barrier(0);
+    ring::mma_rect<TA, TB, REGA, REGB>(acc, cur, cur + 2 * REGA, arow, brow, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    wait_vm_barrier<NQ>();
+    unsigned char* t = cur;
+    cur = nxt;
+    nxt = pf;
+    pf = t;
+  }
+  wait_vm_barrier<0>();
+  __syncthreads();
+
+  // epilogue: column C = (w, part) holds Re (part 0) or Im (part 1) of
+  // (W'' Theta-hat_w) over this unit's chunks; its share of the complex form
+  // Theta-hat_w . (W'' Theta-hat_w) is theta Z (part 0) or i theta Z (part 1),
+  // with the products in FP64
+  const int lr = lane & 15, lq = lane >> 4;
+  double sre[TB], sim[TB];
+#pragma unroll
+  for (int j = 0; j < TB; ++j) {
+    sre[j] = sim[j] = 0.0;
+    const long C = brow0 + brow + 16 * j + lr;
+    const int wk = (int)(C >> 1), pt = (int)(C & 1);
+    const bool okc = wk < g.nw;
+    const double2* th = g.thetaT + ((long)(okc ? wk : 0) * g.ntot + g.off) * g.M;
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long I = arow0 + arow + 16 * i + 4 * lq + r;
+        const bool ok = okc && I < g.NM;
+        const double2 tv = th[ok ? I : 0];
+        const double z = ok ? (double)acc[i][j][r] : 0.0;
+        sre[j] += z * (pt ? -tv.y : tv.x);
+        sim[j] += z * (pt ? tv.x : tv.y);
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < TB; ++j)
+#pragma unroll
+    for (int o = 16; o < 64; o <<= 1) {
+      sre[j] += __shfl_xor(sre[j], o);
+      sim[j] += __shfl_xor(sim[j], o);
+    }
+  double* red = reinterpret_cast<double*>(L0);   // [cb][j][lr][2] from the rb = 1 waves
+  if (rb == 1 && lane < 16)
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+      red[((cb * TB + j) * 16 + lane) * 2] = sre[j];
+      red[((cb * TB + j) * 16 + lane) * 2 + 1] = sim[j];
+    }
+  __syncthreads();
+  if (rb == 0 && lane < 16) {
+    double2* out = g.part + (long)u * g.rows_b;
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+      const long C = brow0 + brow + 16 * j + lane;
+      out[C] = make_double2(sre[j] + red[((cb * TB + j) * 16 + lane) * 2],
+                            sim[j] + red[((cb * TB + j) * 16 + lane) * 2 + 1]);
+    }
+  }
+}
+
+// split BF16: x -> f = fp32(x); hi = bf16(f); lo = bf16(f - hi), both rounded to nearest even
+__device__ inline unsigned short bf16_rne(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// W''[I = (b,k)][J = (a,l)] = s W[(a,k)][(b,l)], s = 1 on the diagonal blocks
+// (I / RA = J / RA), 2 above, 0 below, into chunk-major hi / lo planes
+// (rows I >= NM and columns J >= NM are zero)
+__global__ void eri_pack_w_kernel(const double* __restrict__ W, int M, int NM, long rows_a, int nchunk,
+                                  unsigned short* __restrict__ hi, unsigned short* __restrict__ lo) {
+  const long total = (long)nchunk * rows_a * KC;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const long c = e / (rows_a * KC), rem = e - c * rows_a * KC;
+    const long I = rem / KC, J = c * KC + (rem - I * KC);
+    const long p = I / RA, q = J / RA;
+    float f = 0.f;
+    if (I < NM && J < NM && q >= p) {
+      const long b = I / M, k = I - b * M, a = J / M, l = J - a * M;
+      const double v = W[(a * M + k) * NM + b * M + l];
+      f = (float)(q == p ? v : 2.0 * v);
+    }
+    const unsigned short h = bf16_rne(f);
+    hi[e] = h;
+    lo[e] = bf16_rne(f - bf16_f(h));
+  }
+}
+
+// Theta-hat rows C = 2 w + part of one spin into chunk-major hi / lo planes:
+// one thread per (chunk, walker, element of the chunk), both parts
+__global__ void eri_pack_theta_kernel(const double2* __restrict__ thetaT, int ntot, int M, int off, int NM, int nw,
+                                      long rows_b, int nchunk, unsigned short* __restrict__ hi,
+                                      unsigned short* __restrict__ lo) {
+  const long hw = rows_b / 2;
+  const long total = (long)nchunk * hw * KC;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const long c = e / (hw * KC), rem = e - c * hw * KC;
+    const long wk = rem / KC, jj = rem - wk * KC, J = c * KC + jj;
+    double2 v = make_double2(0.0, 0.0);
+    if (wk < nw && J < NM) v = thetaT[(wk * ntot + off) * M + J];
+    const long o = (c * rows_b + 2 * wk) * KC + jj;
+    const float fr = (float)v.x, fi = (float)v.y;
+    const unsigned short hr = bf16_rne(fr), him = bf16_rne(fi);
+    hi[o] = hr;
+    hi[o + KC] = him;
+    lo[o] = bf16_rne(fr - bf16_f(hr));
+    lo[o + KC] = bf16_rne(fi - bf16_f(him));
+  }
+}
+
+// per walker: the sum over units (fixed order) and both parts -> troo[w][spin][0];
+// the other vectors' entries are zero (the assembly only sums them)
+__global__ void eri_reduce_kernel(const double2* __restrict__ part, int nunit, long rows_b, int nw, int spin, int X,
+                                  double2* __restrict__ troo) {
+  const int w = blockIdx.x;
+  double2* o = troo + ((long)w * 2 + spin) * X;
+  if (threadIdx.x == 0) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int u = 0; u < nunit; ++u) {
+      const double2* p = part + (long)u * rows_b + 2L * w;
+      s = cadd(s, cadd(p[0], p[1]));
+    }
+    o[0] = s;
+  }
+  for (int n = 1 + threadIdx.x; n < X; n += blockDim.x) o[n] = make_double2(0.0, 0.0);
+}
+
+// out[c][r] = in[r * ld_in + c]  (rows x cols -> cols x rows)
+__global__ void transpose_real_kernel(const double* __restrict__ in, long rows, long cols, long ld_in,
+                                      double* __restrict__ out) {
+  const long total = rows * cols;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const long c = e / rows, r = e - c * rows;
+    out[e] = in[r * ld_in + c];
+  }
+}
+
+int grid_of(long total) { return (int)std::min<long>(std::max<long>((total + 255) / 256, 1), 1 << 20); }
+
+struct Shape {
+  long NM, rows_a;
+  int nchunk, nblk_a;
+};
+Shape shape_of(afq_system s, int sp) {
+  Shape h;
+  h.NM = (long)s->nspin_n(sp) * s->M;
+  h.rows_a = (h.NM + RA - 1) / RA * RA;
+  h.nchunk = (int)((h.NM + KC - 1) / KC);
+  h.nblk_a = (int)(h.rows_a / RA);
+  return h;
+}
+size_t plane_bytes(long rows, int nchunk) { return (size_t)rows * nchunk * KC * 2; }
+long rows_b_of(int nw) { return (2L * nw + RBR - 1) / RBR * RBR; }
+
+// work units: row block p covers chunks [TA p, nchunk) in runs of kper chunks;
+// ordered run-major (run 0 of every row block, then run 1, ...), so row blocks
+// resident together on one XCD read nearby Theta-hat chunks
+std::vector<int> make_units(const Shape& h, int kper) {
+  std::vector<int> u;
+  for (int j = 0;; ++j) {
+    bool any = false;
+    for (int p = 0; p < h.nblk_a; ++p) {
+      const long c0 = (long)TA * p + (long)j * kper;
+      if (c0 >= h.nchunk) continue;
+      any = true;
+      u.push_back(p);
+      u.push_back((int)c0);
+      u.push_back((int)std::min<long>(kper, h.nchunk - c0));
+      u.push_back(0);
+    }
+    if (!any) break;
+  }
+  return u;
+}
+
+// chunks per unit: about 512 units (with the walker blocks, a few thousand
+// workgroups to fill the device several times over), runs of at least 16 chunks
+int choose_kper(const Shape& h) {
+  long total = 0;
+  for (int p = 0; p < h.nblk_a; ++p) total += h.nchunk - (long)TA * p;
+  const long target = 512;
+  return (int)std::max<long>(16, (total + target - 1) / target);
+}
+
+void eri_free(afq_system s) {
+  for (int sp = 0; sp < 2; ++sp) {
+    s->eri_w[sp].free();
+    s->eri_units[sp].free();
+    s->eri_nunit[sp] = 0;
+  }
+  s->eri_ready = false;
+}
+
+// the four-index form pays when it needs fewer products than the Cholesky form
+// ((N M)^2 / 2 against X N^2 M per walker and spin, i.e. M < 2 X), the system
+// is large enough for its set-up to matter, and its planes take at most a
+// quarter of the free device memory (the set-up transients half)
+bool eri_pays(afq_system s) {
+  if (2L * s->X <= s->M) return false;
+  size_t bytes = 0;
+  for (int sp = 0; sp < (s->n_up == s->n_dn ? 1 : 2); ++sp) {
+    const Shape h = shape_of(s, sp);
+    if (h.NM < 4096) return false;
+    bytes += 2 * plane_bytes(h.rows_a, h.nchunk);
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
+  const long nm = std::max(shape_of(s, 0).NM, shape_of(s, 1).NM);
+  const size_t transient = (size_t)nm * nm * 8 + (size_t)nm * s->X * 8;
+  return bytes <= free_b / 4 && bytes + transient <= free_b / 2;
+}
+
+// W'' planes and work units of both spins (one copy when the two trial blocks are equal)
+int eri_prepare(afq_system s) {
+  hipStream_t st = s->stream;
+  const int M = s->M, X = s->X, ntot = s->ntot;
+  AFQ_CHECK(s->LtRe.p, AFQ_E_STATE, "exchange (four-index): real half-rotated vectors missing");
+  bool same = s->n_up == s->n_dn;
+  if (same) {
+    std::vector<double2> ph((size_t)M * ntot);
+    AFQ_TRY_HIP(hipMemcpyAsync(ph.data(), s->phi.p, ph.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+    AFQ_TRY_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < M && same; ++i)
+      for (int a = 0; a < s->n_up && same; ++a) {
+        const double2 x = ph[(size_t)i * ntot + a], y = ph[(size_t)i * ntot + s->n_up + a];
+        same = x.x == y.x && x.y == y.y;
+      }
+  }
+  s->eri_share = same;
+  for (int sp = 0; sp < (same ? 1 : 2); ++sp) {
+    const int off = s->spin_off(sp);
+    const Shape h = shape_of(s, sp);
+    AFQ_CHECK(h.NM <= 65535L * 32, AFQ_E_UNSUPPORTED, "exchange (four-index): N M too large");
+    const std::vector<int> units = make_units(h, choose_kper(h));
+    DevBuf LT, W;
+    int rc = LT.alloc((size_t)h.NM * X * 8);
+    if (rc == AFQ_OK) rc = W.alloc((size_t)h.NM * h.NM * 8);
+    if (rc == AFQ_OK) rc = s->eri_w[sp].alloc(2 * plane_bytes(h.rows_a, h.nchunk));
+    if (rc == AFQ_OK) rc = s->eri_units[sp].alloc(units.size() * sizeof(int));
+    if (rc == AFQ_OK) {
+      // LT[(a,k)][n] = Lt_n[a][k]
+      hipLaunchKernelGGL(transpose_real_kernel, dim3(grid_of((long)X * h.NM)), dim3(256), 0, st,
+                         s->LtRe.as<double>() + (long)off * M, (long)X, h.NM, (long)ntot * M, LT.as<double>());
+      rc = hip_status(hipGetLastError(), "exchange (four-index): transpose");
+    }
+    if (rc == AFQ_OK) {
+      // W[(a,k)][(b,l)] = sum_n LT[(a,k)][n] LT[(b,l)][n]
+      GemmArgs<double> g = gemm_args<double>();
+      g.m = (int)h.NM; g.n = (int)h.NM; g.k = X;
+      g.A = LT.as<double>(); g.lda = X; g.cA = false;
+      g.B = LT.as<double>(); g.ldb = X; g.opB = OP_T; g.cB = false;
+      g.C = W.as<double>(); g.ldc = h.NM; g.cC = false;
+      rc = gemm<double>(g, st);
+    }
+    if (rc == AFQ_OK) {
+      unsigned short* hi = s->eri_w[sp].as<unsigned short>();
+      const size_t pe = plane_bytes(h.rows_a, h.nchunk) / 2;   // elements per plane
+      hipLaunchKernelGGL(eri_pack_w_kernel, dim3(grid_of((long)h.nchunk * h.rows_a * KC)), dim3(256), 0, st,
+                         W.as<double>(), M, (int)h.NM, h.rows_a, h.nchunk, hi, hi + pe);
+      rc = hip_status(hipGetLastError(), "exchange (four-index): pack");
+    }
+    if (rc == AFQ_OK)
+      rc = hip_status(hipMemcpyAsync(s->eri_units[sp].p, units.data(), units.size() * sizeof(int),
+                                     hipMemcpyHostToDevice, st),
+                      "exchange (four-index): units");
+    // W and LT are freed on return: wait for the kernels that read them
+    if (rc == AFQ_OK) rc = hip_status(hipStreamSynchronize(st), "exchange (four-index): set-up");
+    if (rc != AFQ_OK) {
+      (void)hipStreamSynchronize(st);
+      eri_free(s);
+      return rc;
+    }
+    s->eri_nunit[sp] = (int)(units.size() / 4);
+  }
+  s->eri_ready = true;
+  return AFQ_OK;
+}
+
+}  // namespace
+
+int eri_sync(afq_system s) {
+  const bool can = s->kp_nk == 0 && s->msd_n == 0 && s->prec == AFQ_BF16X3 && s->real_trial &&
+                   s->eri_form != AFQ_EXCH_CHOLESKY;
+  if (!can) {
+    if (s->eri_ready) {
+      eri_free(s);
+      ++s->version;
+    }
+    return AFQ_OK;
+  }
+  if (s->eri_ready) return AFQ_OK;
+  if (s->eri_form == AFQ_EXCH_AUTO) {
+    if (s->eri_declined) return AFQ_OK;
+    if (!eri_pays(s)) {
+      s->eri_declined = true;
+      return AFQ_OK;
+    }
+  }
+  AFQ_RET(eri_prepare(s));
+  ++s->version;
+  return AFQ_OK;
+}
+
+size_t eri_tensor_bytes(afq_system s) { return s->eri_w[0].bytes + s->eri_w[1].bytes; }
+
+int eri_alloc_scratch(afq_system s, afq_walkers w) {
+  if (!s->eri_ready) return AFQ_OK;
+  const long rows_b = rows_b_of(w->nw);
+  size_t tb = 0, pb = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const Shape h = shape_of(s, sp);
+    tb = std::max(tb, 2 * plane_bytes(rows_b, h.nchunk));
+    pb = std::max(pb, (size_t)s->eri_nunit[s->eri_share ? 0 : sp] * rows_b * sizeof(double2));
+  }
+  if (w->eri_theta.bytes < tb) AFQ_RET(w->eri_theta.alloc(tb));
+  if (w->eri_part.bytes < pb) AFQ_RET(w->eri_part.alloc(pb));
+  return AFQ_OK;
+}
+
+int eri_pack(afq_system s, afq_walkers w, int sp, hipStream_t st) {
+  const Shape h = shape_of(s, sp);
+  const long rows_b = rows_b_of(w->nw);
+  const size_t pb = plane_bytes(rows_b, h.nchunk);
+  AFQ_CHECK(s->eri_ready && w->eri_theta.bytes >= 2 * pb, AFQ_E_STATE,
+            "exchange (four-index): walker scratch not prepared");
+  unsigned short* th = w->eri_theta.as<unsigned short>();
+  hipLaunchKernelGGL(eri_pack_theta_kernel, dim3(grid_of((long)h.nchunk * (rows_b / 2) * KC)), dim3(256), 0, st,
+                     w->theta.as<double2>(), s->ntot, s->M, s->spin_off(sp), (int)h.NM, w->nw, rows_b, h.nchunk, th,
+                     th + pb / 2);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+
+int eri_exchange(afq_system s, afq_walkers w, int sp, hipStream_t st) {
+  const Shape h = shape_of(s, sp);
+  const int wsp = s->eri_share ? 0 : sp;
+  const long rows_b = rows_b_of(w->nw);
+  const size_t pa = plane_bytes(h.rows_a, h.nchunk), pb = plane_bytes(rows_b, h.nchunk);
+  const int nunit = s->eri_nunit[wsp];
+  AFQ_CHECK(s->eri_ready && nunit > 0 && s->eri_w[wsp].bytes >= 2 * pa, AFQ_E_STATE,
+            "exchange (four-index): tensor not prepared");
+  AFQ_CHECK(w->eri_theta.bytes >= 2 * pb && w->eri_part.bytes >= (size_t)nunit * rows_b * sizeof(double2),
+            AFQ_E_STATE, "exchange (four-index): walker scratch not prepared");
+  EriArgs g{};
+  g.a[0] = s->eri_w[wsp].as<unsigned char>();
+  g.a[1] = g.a[0] + pa;
+  g.b[0] = w->eri_theta.as<unsigned char>();
+  g.b[1] = g.b[0] + pb;
+  g.rows_a = h.rows_a;
+  g.rows_b = rows_b;
+  g.units = s->eri_units[wsp].as<int4>();
+  g.nunit = nunit;
+  g.nblk_b = (int)(rows_b / RBR);
+  const long grid = (long)nunit * g.nblk_b;
+  AFQ_CHECK(grid < (1L << 30), AFQ_E_INVALID, "exchange (four-index): grid too large");
+  g.grid = (int)grid;
+  g.thetaT = w->theta.as<double2>();
+  g.ntot = s->ntot; g.M = s->M; g.off = s->spin_off(sp); g.NM = (int)h.NM; g.nw = w->nw;
+  g.part = w->eri_part.as<double2>();
+  const long launch = (grid + NXCD - 1) / NXCD * NXCD;
+  hipLaunchKernelGGL(eri_kernel, dim3((unsigned)launch), dim3(256), 0, st, g);
+  AFQ_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(eri_reduce_kernel, dim3(w->nw), dim3(256), 0, st, w->eri_part.as<double2>(), nunit, rows_b,
+                     w->nw, sp, s->X, w->troo.as<double2>());
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}

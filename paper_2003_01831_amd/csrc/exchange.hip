@@ -94,11 +94,11 @@ int exchange_launch(afq_system s, afq_walkers w, int spin, hipStream_t st) {
 // kernel (the specialised split-BF16x3 kernel).
 int exchange_autotune(afq_system s, afq_walkers w, int reps, int* choice) {
   hipStream_t st = s->stream;
-  if (s->kp_nk > 0 || s->msd_n > 0) {   // these trials do not use the exchange kernel
+  AFQ_RET(system_prepare_pack(s, s->prec));
+  if (s->kp_nk > 0 || s->msd_n > 0 || s->eri_ready) {   // no Cholesky-form exchange kernel in use
     choice[0] = choice[1] = -1;
     return AFQ_OK;
   }
-  AFQ_RET(system_prepare_pack(s, s->prec));
   AFQ_RET(walkers_alloc_scratch(w));
   AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), true, w->logdet.as<double2>()));
   AFQ_RET(pack_theta(s, w, st));

@@ -28,27 +28,23 @@
 // fragments resident, then lo*hi with the A lo fragments resident).
 #include <algorithm>
 #include "common.h"
+#include "bf16x3_ring.h"
 #include "exchange_big.h"
 
 namespace {
 
-typedef __attribute__((ext_vector_type(4))) float f4;
-typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
-typedef __attribute__((address_space(3))) unsigned char lds_t;
+using ring::bf16x8;
+using ring::CPR;
+using ring::dma16;
+using ring::dma4;
+using ring::f4;
+using ring::KC;
+using ring::lds_t;
+using ring::ROWB;
+using ring::swz;
+using ring::wait_vm_barrier;
 
-constexpr int KC = 32;              // k per chunk (bf16 elements)
 constexpr int NWAVE = 4;
-constexpr int ROWB = KC * 2;        // bytes per LDS row per plane (one chunk of one row)
-constexpr int CPR = ROWB / 16;      // 16-byte pieces per row
-
-// XOR swizzle of the 16-byte pieces of a 64-byte row (an involution)
-__device__ inline int swz(int row, int c) { return c ^ ((row >> 1) & 3); }
-
-__device__ inline uint4 lds16(const unsigned char* p) { return *reinterpret_cast<const uint4*>(p); }
-
-__device__ inline bf16x8 frag(const unsigned char* plane, int row, int lq) {
-  return __builtin_bit_cast(bf16x8, lds16(plane + row * ROWB + 16 * swz(row, lq)));
-}
 
 constexpr int NMAX = 100;           // largest N
 
@@ -79,75 +75,6 @@ template <int TM> struct Geo {
 
 // workgroups resident on one XCD form TB n-pairs x TW walkers tiles
 constexpr int NXCD = 8, TB = 4, TW = 8;
-
-// One chunk (32 k) of this wave's TM x TM tile. A planes at la (hi, then lo
-// after ROWS rows), B planes at lb likewise.
-template <int TM>
-__device__ inline void mma_chunk(f4 (&acc)[TM][TM], const unsigned char* la, const unsigned char* lb, int arow,
-                                 int brow, int lane) {
-  constexpr int RB = Geo<TM>::REG;
-  const int lr = lane & 15, lq = lane >> 4;
-  bf16x8 a[TM];
-#pragma unroll
-  for (int i = 0; i < TM; ++i) a[i] = frag(la, arow + 16 * i + lr, lq);
-  bf16x8 bh = frag(lb, brow + lr, lq), bl = frag(lb + RB, brow + lr, lq);
-#pragma unroll
-  for (int j = 0; j < TM; ++j) {
-    bf16x8 nh = bh, nl = bl;
-    if (j + 1 < TM) {
-      nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
-      nl = frag(lb + RB, brow + 16 * (j + 1) + lr, lq);
-    }
-    // hi*hi for every row tile, then hi*lo: consecutive MFMAs never depend on
-    // each other's result
-#pragma unroll
-    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl, acc[i][j], 0, 0, 0);
-    bh = nh;
-    bl = nl;
-  }
-#pragma unroll
-  for (int i = 0; i < TM; ++i) a[i] = frag(la + RB, arow + 16 * i + lr, lq);
-  bh = frag(lb, brow + lr, lq);
-#pragma unroll
-  for (int j = 0; j < TM; ++j) {
-    bf16x8 nh = bh;
-    if (j + 1 < TM) nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
-#pragma unroll
-    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
-    bh = nh;
-  }
-}
-
-// Direct global->LDS loads and their waits, written as inline asm so that the
-// compiler's wait-count pass does not track them: it cannot tell the three
-// ring buffers apart across the loop and would add a conservative vmcnt(0)
-// before the LDS reads of some steps. The kernel therefore waits for its own
-// loads explicitly (every LDS read of a buffer follows a vmcnt wait covering
-// that buffer's loads and a barrier). Lane l of a load writes LDS bytes
-// [m0 + BYTES l, m0 + BYTES (l + 1)). No VGPR is written by these loads.
-// M0 is reserved by the compiler, but this kernel uses it nowhere else (it
-// needs no indirect register indexing, message or GWS instruction), so
-// clobbering it here is safe; the warning about it is silenced for these two.
-#pragma clang diagnostic push
-#pragma clang diagnostic ignored "-Winline-asm"
-__device__ inline void dma16(const unsigned char* src, lds_t* dst) {
-  const unsigned m = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)dst);
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(m) : "memory", "m0");
-}
-__device__ inline void dma4(const unsigned char* src, lds_t* dst) {
-  const unsigned m = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)dst);
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(src), "s"(m) : "memory", "m0");
-}
-#pragma clang diagnostic pop
-
-// s_waitcnt vmcnt(W) followed by s_barrier, one opaque statement: it is also a
-// compiler-level memory barrier, so no LDS access moves across it
-template <int W> __device__ inline void wait_vm_barrier() {
-  static_assert(W >= 0 && W < 64, "vmcnt is 6 bits");
-  asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(W) : "memory");
-}
 
 template <int TM>
 __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
@@ -237,7 +164,7 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
     if ((c) + 2 < nc) issue((c) + 2, pf);                            \
     else issue_dummy();                                              \
     __builtin_amdgcn_sched_barrier(0);                               \
-    mma_chunk<TM>(acc, cur, cur + 2 * REG, arow, brow, lane);        \
+    ring::mma_chunk<TM, REG>(acc, cur, cur + 2 * REG, arow, brow, lane);        \
     __builtin_amdgcn_sched_barrier(0);                               \
     wait_vm_barrier<RI>();                                           \
   } while (0)

@@ -394,8 +394,9 @@ int msd_set(afq_system s, const double* C, int n_det, const double* coeffs, cons
   hipStream_t st = s->stream;
   const int M = s->M, X = s->X;
   if (n_det == 0) {
+    if (s->msd_n) ++s->version;
     s->msd_n = 0;
-    return AFQ_OK;
+    return eri_sync(s);
   }
   AFQ_CHECK(n_det >= 1 && n_det <= 65536, AFQ_E_INVALID, "afq_system_set_msd: n_det must be in [0, 65536]");
   AFQ_CHECK(C && coeffs && exc, AFQ_E_INVALID, "afq_system_set_msd: NULL input");
@@ -597,7 +598,8 @@ int msd_set(afq_system s, const double* C, int n_det, const double* coeffs, cons
   s->msd_nr = nr;
   s->msd_lds = lds;
   s->msd_n = n_det;
-  return AFQ_OK;
+  ++s->version;
+  return eri_sync(s);   // a multi-determinant trial has no four-index exchange
 }
 
 int msd_alloc_scratch(afq_system s, afq_walkers w) {

@@ -38,12 +38,13 @@ static int real_gemm(int m, int n, int k, const double* A, long lda, int opA, co
 }
 
 int system_prepare_pack(afq_system s, int prec) {
-  if (s->apack_prec == prec) return AFQ_OK;
+  if (s->apack_prec == prec) return eri_sync(s);
   if (s->kp_nk > 0) {   // k-point systems have their own trace kernel and run in FP64
     AFQ_CHECK(prec == AFQ_FP64, AFQ_E_UNSUPPORTED, "k-point systems run in FP64 mode");
     s->apack_prec = s->prec = prec;
     return AFQ_OK;
   }
+  if (s->apack_prec >= 0) ++s->version;
   const int kc = exch_kchunk(prec);
   const size_t esz = prec == AFQ_FP64 ? 8 : prec == AFQ_CFP32 ? 4 : 2;
   for (int sp = 0; sp < 2; ++sp) {
@@ -75,7 +76,8 @@ int system_prepare_pack(afq_system s, int prec) {
   AFQ_TRY_HIP(hipStreamSynchronize(s->stream));
   s->apack_prec = prec;
   s->prec = prec;
-  return AFQ_OK;
+  s->eri_declined = false;
+  return eri_sync(s);
 }
 
 // B1 = exp(Z), Z = -dt h'/2: Z' = Z / 2^q with ||Z'||_inf <= 1/2, Horner

@@ -11,6 +11,7 @@ static size_t esz_of(int prec) { return prec == AFQ_FP64 ? 8 : prec == AFQ_CFP32
 
 int walkers_alloc_scratch(afq_walkers w) {
   afq_system s = w->sys;
+  AFQ_RET(eri_alloc_scratch(s, w));
   if (w->scratch_prec == (size_t)s->prec) return AFQ_OK;
   if (w->scratch_prec != (size_t)-1) w->exch_var[0] = w->exch_var[1] = -1;   // tuned for another precision
   const int nw = w->nw, M = s->M, ntot = s->ntot, X = s->X;
@@ -127,6 +128,17 @@ static int energy_from_theta(afq_system s, afq_walkers w, AssembleArgs& a, bool 
     AFQ_RET(msd_energy(s, w, logdet, st));
     a.parts_in = w->msd_parts.as<double2>();
     a.vbar_in = w->msd_vbar.as<double2>();
+  } else if (s->eri_ready) {   // four-index exchange; the Coulomb traces below
+    for (int sp = 0; sp < 2; ++sp) {
+      {
+        TraceScope t(AFQ_PH_PACK, st);
+        AFQ_RET(eri_pack(s, w, sp, st));
+      }
+      TraceScope t(AFQ_PH_EXCHANGE, st);
+      AFQ_RET(eri_exchange(s, w, sp, st));
+    }
+    TraceScope t(AFQ_PH_COULOMB, st);
+    AFQ_RET(coulomb_fp64(s, w, st));
   } else {
     {
       TraceScope t(AFQ_PH_PACK, st);

@@ -21,8 +21,8 @@ def api():
     return api
 
 
-def _energy_case(api, s, W, w, prec):
-    sysg = api.System.from_synth(s, precision=prec)
+def _energy_case(api, s, W, w, prec, form="auto"):
+    sysg = api.System.from_synth(s, precision=prec, exchange_form=form)
     wk = api.Walkers(sysg, W.shape[0], W, w)
     el, parts, vb, em = wk.energy(want_vbar=True)
     torch.cuda.synchronize()
@@ -73,20 +73,22 @@ def test_energy_complex_trial(api):
         assert rel_vec(el, rel) < tol, prec
 
 
-@pytest.mark.parametrize("prec", ["cfp32", "bf16x3"])
+@pytest.mark.parametrize("prec,form", [("cfp32", "auto"), ("bf16x3", "cholesky"), ("bf16x3", "four_index")])
 @pytest.mark.parametrize("shape", [(64, 16, 16, 256), (128, 32, 32, 512), (160, 80, 70, 96), (224, 100, 100, 128),
                                    (240, 100, 97, 40)])
-def test_energy_reduced_precision(api, prec, shape):
+def test_energy_reduced_precision(api, prec, form, shape):
+    """Split-BF16x3 in both exchange forms: the Cholesky form (the 65..100
+    electron shapes take the one-wave-per-SIMD kernel) and the four-index form."""
     M, nu, nd, X = shape
     s = synth.make_system(M, nu, nd, X, seed=M + X)
     W = synth.perturbed_walkers(s, 6, 0.1, seed=3)
     w = synth.random_weights(6, seed=4)
-    el, parts, vb, em = _energy_case(api, s, W, w, prec)
+    el, parts, vb, em = _energy_case(api, s, W, w, prec, form)
     rel, rparts, rvb, rem = _oracle_energy(s, W, w)
     errs = {"E_L": rel_vec(el, rel), "E1": rel_vec(parts[:, 0], rparts[:, 0]),
             "EJ": rel_vec(parts[:, 1], rparts[:, 1]), "EK": rel_vec(parts[:, 2], rparts[:, 2]),
             "vbar": rel_fro(vb, rvb), "E_mix": rel_scalar(em, rem)}
-    print(prec, shape, {k: f"{v:.2e}" for k, v in errs.items()})
+    print(prec, form, shape, {k: f"{v:.2e}" for k, v in errs.items()})
     for k, v in errs.items():
         assert v < 1e-5, (k, v)
 
