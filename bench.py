@@ -305,6 +305,52 @@ def bench_kp(a, torch, synth, api, _lib):
     return 0
 
 
+def measure_extras(a, extra, sysg, api, lib, _lib, torch, nw, dt, qr, e_var, M, nu, nd):
+    """Population control and back-propagation at the headline size (outside the timed steps)."""
+    # population control at this size: one comb of all walkers (host-synchronising)
+    wk_pc = api.Walkers(sysg, nw)
+    wk_pc.set(weights=np.random.default_rng(3).uniform(0.5, 1.5, nw))
+    wk_pc.comb(0.5)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for r in range(5):
+        wk_pc.comb((r + 0.5) / 5)
+    torch.cuda.synchronize()
+    extra["comb_ms"] = round((time.perf_counter() - t) / 5 * 1e3, 3)
+    wk_pc.close()
+    # back-propagated 1-RDM at this size: a window of 2 QR periods recorded by
+    # ordinary steps, then the estimator (reversed walk of the trial + GEMMs)
+    n_bp = 2 * qr
+    wk_bp = api.Walkers(sysg, nw)
+    wk_bp.step(1, dt, seed=12, qr_every=qr, e_shift=e_var)
+    wk_bp.bp_begin(n_bp)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    wk_bp.step(n_bp, dt, seed=12, qr_every=qr, e_shift=e_var)
+    torch.cuda.synchronize()
+    rec_ms = (time.perf_counter() - t) / n_bp * 1e3
+    lib.afq_trace_reset()
+    lib.afq_trace_enable(1)
+    t = time.perf_counter()
+    P, _ = wk_bp.bp_rdm1(qr_every=qr)
+    torch.cuda.synchronize()
+    bp_ms = (time.perf_counter() - t) * 1e3
+    lib.afq_trace_enable(0)
+    bph = trace_phases(lib, _lib)
+    lib.afq_trace_reset()
+    Pn = P.cpu().numpy()
+    prop_ms = sum(bph[k][0] for k in ("abuild", "taylor") if k in bph)
+    est_flop = 2 * 8.0 * M * M * nw * nu      # P^s = Q Y^T over nw*n stacked columns, complex FP64
+    extra["back_propagation"] = {
+        "n_bp": n_bp, "recording_step_ms": round(rec_ms, 3), "rdm1_ms": round(bp_ms, 3),
+        "rdm1_ms_per_window_step": round(bp_ms / n_bp, 3),
+        "reverse_propagation_ms": round(prop_ms, 3), "qr_ms": round(bph.get("qr", (0.0, 0))[0], 3),
+        "estimator_gemm_gflop": round(est_flop / 1e9, 3),
+        "trace_err": float(max(abs(np.trace(Pn[0]).real - nu), abs(np.trace(Pn[1]).real - nd)))}
+    del P
+    wk_bp.close()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,6 +362,8 @@ def main(argv=None):
     ap.add_argument("--compare-steps", type=int, default=3, help="timed steps of the other precisions (0: skip)")
     ap.add_argument("--check-steps", type=int, default=2, help="steps of the 4-walker oracle check (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary measurements (comb, back-propagation window) after the timed steps")
     ap.add_argument("--exchange-form", default="auto", choices=["auto", "cholesky", "four_index"],
                     help="exchange form of the split-BF16x3 mode (auto: four-index where it pays)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -445,48 +493,8 @@ def main(argv=None):
             roofline["real_lt_frac_of_bf16x3_effective_peak"] = round(roofline["achieved_real_lt"] / (peak / 3), 4)
 
     extra = {}
-    # population control at this size: one comb of all walkers (host-synchronising)
-    wk_pc = api.Walkers(sysg, nw)
-    wk_pc.set(weights=np.random.default_rng(3).uniform(0.5, 1.5, nw))
-    wk_pc.comb(0.5)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for r in range(5):
-        wk_pc.comb((r + 0.5) / 5)
-    torch.cuda.synchronize()
-    extra["comb_ms"] = round((time.perf_counter() - t) / 5 * 1e3, 3)
-    wk_pc.close()
-    # back-propagated 1-RDM at this size: a window of 2 QR periods recorded by
-    # ordinary steps, then the estimator (reversed walk of the trial + GEMMs)
-    n_bp = 2 * qr
-    wk_bp = api.Walkers(sysg, nw)
-    wk_bp.step(1, dt, seed=12, qr_every=qr, e_shift=e_var)
-    wk_bp.bp_begin(n_bp)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    wk_bp.step(n_bp, dt, seed=12, qr_every=qr, e_shift=e_var)
-    torch.cuda.synchronize()
-    rec_ms = (time.perf_counter() - t) / n_bp * 1e3
-    lib.afq_trace_reset()
-    lib.afq_trace_enable(1)
-    t = time.perf_counter()
-    P, _ = wk_bp.bp_rdm1(qr_every=qr)
-    torch.cuda.synchronize()
-    bp_ms = (time.perf_counter() - t) * 1e3
-    lib.afq_trace_enable(0)
-    bph = trace_phases(lib, _lib)
-    lib.afq_trace_reset()
-    Pn = P.cpu().numpy()
-    prop_ms = sum(bph[k][0] for k in ("abuild", "taylor") if k in bph)
-    est_flop = 2 * 8.0 * M * M * nw * nu      # P^s = Q Y^T over nw*n stacked columns, complex FP64
-    extra["back_propagation"] = {
-        "n_bp": n_bp, "recording_step_ms": round(rec_ms, 3), "rdm1_ms": round(bp_ms, 3),
-        "rdm1_ms_per_window_step": round(bp_ms / n_bp, 3),
-        "reverse_propagation_ms": round(prop_ms, 3), "qr_ms": round(bph.get("qr", (0.0, 0))[0], 3),
-        "estimator_gemm_gflop": round(est_flop / 1e9, 3),
-        "trace_err": float(max(abs(np.trace(Pn[0]).real - nu), abs(np.trace(Pn[1]).real - nd)))}
-    del P
-    wk_bp.close()
+    if not a.no_extras:
+        measure_extras(a, extra, sysg, api, lib, _lib, torch, nw, dt, qr, e_var, M, nu, nd)
     if a.compare_steps > 0:
         for prec in ("fp64", "cfp32", "bf16x3"):
             if prec == a.precision:
@@ -495,7 +503,9 @@ def main(argv=None):
             w2, ph2, _ = timed(prec, a.compare_steps, 1)
             extra[f"{prec}_walker_steps_per_s"] = round(nw * a.compare_steps / w2, 3)
             exm, exc = ph2["exchange"]
-            extra[f"{prec}_exchange_tflops"] = round(per_launch_flops / (exm / 1e3 / max(exc, 1)) / 1e12, 3)
+            # the other precisions run the Cholesky form: its complex-model count
+            chol_launch = (8.0 * X * nu * nu * M + 8.0 * X * nu * nu) * nw
+            extra[f"{prec}_exchange_tflops"] = round(chol_launch / (exm / 1e3 / max(exc, 1)) / 1e12, 3)
         sysg.set_precision(a.precision)
         if "fp64_walker_steps_per_s" in extra:
             extra["speedup_vs_fp64_path"] = round(value / extra["fp64_walker_steps_per_s"], 3)

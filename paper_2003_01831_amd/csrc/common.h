@@ -117,7 +117,8 @@ struct afq_system_s {
   int device = 0;
   bool real_trial = true;
   DevBuf h1, chol, phi;        // f64 inputs (phi complex M x ntot)
-  DevBuf chol32;               // f32 copy of L (reduced modes)
+  DevBuf chol32t;              // reduced modes: L as FP32 packed rows e of [n / 16][e][n % 16] (FP32 ring)
+  DevBuf lt32[2];              // split-BF16x3, real trial: Lt rows n of each spin, FP32 packed [J / 16][n][J % 16]
   DevBuf hp;                   // h' = h - 1/2 sum L L   (M x M f64)
   DevBuf B1;                   // exp(-dt h'/2)          (M x M f64)
   double B1_dt = -1.0;
@@ -225,6 +226,8 @@ struct afq_walkers_s {
   DevBuf kp_part;              // nw x 2 x nk x xq x nk x 3 complex: per-row-block traces
   DevBuf kp_cd;                // 2 x nw x nk xq complex: c and conj(d) of A = sum c L + d L^+
   DevBuf kp_tmp;               // 2 x nk x nw x nk m^2 complex: A-build GEMM outputs
+  // FP32 ring scratch: packed coefficient rows, packed Theta-hat rows, force-bias partial tiles
+  DevBuf r32_coef, r32_theta, r32_part;
   // four-index exchange scratch
   DevBuf eri_theta;            // packed Theta-hat hi / lo planes of one spin
   DevBuf eri_part;             // per (work unit, column) complex partial sums
@@ -307,6 +310,15 @@ int kp_prepare_dt(afq_system s, double dt);
 int kp_energy_traces(afq_system s, afq_walkers w, hipStream_t st);
 // amat = sum_g (c_g L^g + d_g L^g+) from the 2X propagator coefficients coef (complex f64)
 int kp_abuild(afq_system s, afq_walkers w, const double2* coef, hipStream_t st);
+
+// FP32 ring contractions (ring32.hip)
+int r32_prepare(afq_system s);                     // packed L (reduced modes) and Lt (split-BF16x3, real trial)
+int r32_alloc_scratch(afq_system s, afq_walkers w);
+bool r32_coulomb_used(afq_system s);
+// amat[w] = sum_n coef[w][n] L^n (complex FP32) for the walkers of w
+int r32_abuild(afq_system s, afq_walkers w, const float* coef, float2* amat, hipStream_t st);
+// tro[w][spin][n] = tr(Lt^{n,spin} Theta^spin) from the FP32 operands
+int r32_coulomb(afq_system s, afq_walkers w, hipStream_t st);
 
 // four-index exchange (eri.hip)
 // builds or frees the W'' planes to match the system's precision, trial and form

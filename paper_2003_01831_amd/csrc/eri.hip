@@ -23,7 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <vector>
-#include "bf16x3_ring.h"
+#include "mfma_ring.h"
 #include "common.h"
 #include "step_kernels.h"
 

@@ -28,7 +28,7 @@
 // fragments resident, then lo*hi with the A lo fragments resident).
 #include <algorithm>
 #include "common.h"
-#include "bf16x3_ring.h"
+#include "mfma_ring.h"
 #include "exchange_big.h"
 
 namespace {

@@ -1,9 +1,10 @@
-// Building blocks of the split-BF16x3 MFMA kernels that stream both operands
-// through a three-stage LDS ring filled by direct global->LDS loads:
+// Building blocks of the MFMA kernels that stream both operands through a
+// three-stage LDS ring filled by direct global->LDS loads (split-BF16x3 and
+// FP32 contractions):
 //
-//   * operands are packed chunk-major in HBM: 32 contraction elements (64
-//     bytes of BF16) per row and chunk, all rows of chunk 0, then chunk 1, ...,
-//     with separate hi and lo planes;
+//   * operands are packed chunk-major in HBM: 64 bytes per row and chunk (32
+//     BF16 or 16 FP32 contraction elements), all rows of chunk 0, then chunk 1,
+//     ..., split BF16 with separate hi and lo planes;
 //   * one LDS stage holds four regions (A hi, A lo, B hi, B lo) of REG bytes;
 //     rows are 64 bytes whose 16-byte pieces are XOR-swizzled, so fragment
 //     reads (16 bytes per lane) spread over the banks;
@@ -109,6 +110,29 @@ __device__ inline void mma_chunk(f4 (&acc)[TM][TM], const unsigned char* la, con
     for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
     bh = nh;
   }
+}
+
+// One chunk (16 FP32 contraction elements, 64-byte rows) of this wave's TA x TB
+// block of 16 x 16 tiles on v_mfma_f32_16x16x4f32. Lane (lr, lq) reads piece
+// lq of its row (elements 4 lq .. 4 lq + 3) from A (at la) and from B (at lb),
+// both k-contiguous; the MFMA of step e pairs element e of both, so the four
+// steps together contract all 16 elements (the order of the sum over a chunk
+// is a permutation of k, the same for A and B).
+template <int TA, int TB>
+__device__ inline void mma_f32(f4 (&acc)[TA][TB], const unsigned char* la, const unsigned char* lb, int arow,
+                               int brow, int lane) {
+  const int lr = lane & 15, lq = lane >> 4;
+  f4 a[TA], b[TB];
+#pragma unroll
+  for (int i = 0; i < TA; ++i) a[i] = __builtin_bit_cast(f4, lds16(la + (arow + 16 * i + lr) * ROWB + 16 * swz(arow + 16 * i + lr, lq)));
+#pragma unroll
+  for (int j = 0; j < TB; ++j) b[j] = __builtin_bit_cast(f4, lds16(lb + (brow + 16 * j + lr) * ROWB + 16 * swz(brow + 16 * j + lr, lq)));
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int j = 0; j < TB; ++j)
+#pragma unroll
+      for (int i = 0; i < TA; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][e], b[j][e], acc[i][j], 0, 0, 0);
 }
 
 // Direct global->LDS loads and their waits, written as inline asm so that the

@@ -68,14 +68,10 @@ int system_prepare_pack(afq_system s, int prec) {
     AFQ_RET(s->LtRe.alloc(n * sizeof(double)));
     AFQ_RET(real_part(s->Lt.as<double2>(), s->LtRe.as<double>(), n, s->stream));
   }
-  if (prec != AFQ_FP64 && !s->chol32.p) {
-    const long n = (long)s->X * s->M * s->M;
-    AFQ_RET(s->chol32.alloc(n * sizeof(float)));
-    AFQ_RET(convert_d2f(s->chol.as<double>(), s->chol32.as<float>(), n, s->stream));
-  }
+  s->prec = prec;
+  AFQ_RET(r32_prepare(s));
   AFQ_TRY_HIP(hipStreamSynchronize(s->stream));
   s->apack_prec = prec;
-  s->prec = prec;
   s->eri_declined = false;
   return eri_sync(s);
 }

@@ -12,6 +12,7 @@ static size_t esz_of(int prec) { return prec == AFQ_FP64 ? 8 : prec == AFQ_CFP32
 int walkers_alloc_scratch(afq_walkers w) {
   afq_system s = w->sys;
   AFQ_RET(eri_alloc_scratch(s, w));
+  AFQ_RET(r32_alloc_scratch(s, w));
   if (w->scratch_prec == (size_t)s->prec) return AFQ_OK;
   if (w->scratch_prec != (size_t)-1) w->exch_var[0] = w->exch_var[1] = -1;   // tuned for another precision
   const int nw = w->nw, M = s->M, ntot = s->ntot, X = s->X;
@@ -138,7 +139,7 @@ static int energy_from_theta(afq_system s, afq_walkers w, AssembleArgs& a, bool 
       AFQ_RET(eri_exchange(s, w, sp, st));
     }
     TraceScope t(AFQ_PH_COULOMB, st);
-    AFQ_RET(coulomb_fp64(s, w, st));
+    AFQ_RET(r32_coulomb_used(s) ? r32_coulomb(s, w, st) : coulomb_fp64(s, w, st));
   } else {
     {
       TraceScope t(AFQ_PH_PACK, st);
@@ -150,7 +151,7 @@ static int energy_from_theta(afq_system s, afq_walkers w, AssembleArgs& a, bool 
     }
     if (s->prec == AFQ_BF16X3) {
       TraceScope t(AFQ_PH_COULOMB, st);
-      AFQ_RET(coulomb_fp64(s, w, st));
+      AFQ_RET(r32_coulomb_used(s) ? r32_coulomb(s, w, st) : coulomb_fp64(s, w, st));
     }
   }
   TraceScope t(AFQ_PH_ASSEMBLE, st);
@@ -190,12 +191,15 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
   if (s->kp_nk > 0) {
     TraceScope tr(AFQ_PH_ABUILD, st);
     AFQ_RET(kp_abuild(s, w, reinterpret_cast<const double2*>(coef), st));
+  } else if constexpr (sizeof(T) == 4) {   // reduced modes: the FP32 ring contraction
+    TraceScope tr(AFQ_PH_ABUILD, st);
+    AFQ_RET(r32_abuild(s, w, reinterpret_cast<const float*>(coef), w->amat.as<float2>(), st));
   } else {
     TraceScope tr(AFQ_PH_ABUILD, st);
     GemmArgs<T> g = gemm_args<T>();
     g.m = nw; g.n = M * M; g.k = X;
     g.A = coef; g.lda = X; g.cA = true;
-    g.B = sizeof(T) == 8 ? reinterpret_cast<const T*>(s->chol.p) : reinterpret_cast<const T*>(s->chol32.p);
+    g.B = reinterpret_cast<const T*>(s->chol.p);
     g.ldb = (long)M * M; g.cB = false;
     g.C = w->amat.as<T>(); g.ldc = (long)M * M; g.cC = true;
     AFQ_RET(gemm<T>(g, st));
