@@ -125,6 +125,7 @@ struct afq_system_s {
   DevBuf ht;                   // (T^H h)  ntot x M complex
   DevBuf Lt;                   // (T^H L^n) X x ntot x M complex
   DevBuf LtRe;                 // real part of Lt (real trial, split-BF16x3 force bias)
+  DevBuf phitr;                // real trial: T^T (ntot x M f64), the overlap GEMM's k-contiguous operand
   DevBuf apack[2];             // packed A operand per spin (precision of prec)
   DevBuf apack_lo[2];          // BF16x3 low parts
   int apack_prec = -1;
@@ -196,7 +197,7 @@ struct afq_walkers_s {
   DevBuf bp_psi;               // back-propagated trial (nw x M x ntot c128)
   DevBuf bp_stats;             // 2 doubles: sum of weights, singular count
   // per-step scratch
-  DevBuf S, Sinv;              // per (w, spin): n x n complex (max n^2 stride)
+  DevBuf S, Sinv, SinvT;       // per (w, spin): n x n complex (max n^2 stride); SinvT = (S^-1)^T
   DevBuf logdet, logdet_new;   // nw x 2 complex
   DevBuf sing;                 // nw x 2 int
   DevBuf theta;                // nw x M x ntot complex

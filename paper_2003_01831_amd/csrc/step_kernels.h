@@ -48,6 +48,10 @@ int pack_b(int prec, const double2* thT, int nw, int ntot, int M, int off, const
 int convert_d2f(const double* x, float* y, long n, hipStream_t st);
 int copy_d(const double* x, double* y, long n, hipStream_t st);
 int real_part(const double2* z, double* y, long n, hipStream_t st);
+// out_b = in_b^T for batch n x n complex matrices at the same stride
+int transpose_batched(const double2* in, long stride, int n, int batch, double2* out, hipStream_t st);
+// y[c][i] = Re z[i][c] for a rows x cols complex matrix
+int real_transpose(const double2* z, long rows, long cols, double* y, hipStream_t st);
 int fill_d(double* y, double v, long n, hipStream_t st);
 int fill_i(int* y, int v, long n, hipStream_t st);
 int fill_eye(double* y, int M, hipStream_t st);

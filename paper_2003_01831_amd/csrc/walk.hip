@@ -23,6 +23,7 @@ int walkers_alloc_scratch(afq_walkers w) {
   if (!w->S.p) {
     AFQ_RET(w->S.alloc((size_t)nw * 2 * nmax * nmax * 16));
     AFQ_RET(w->Sinv.alloc((size_t)nw * 2 * nmax * nmax * 16));
+    AFQ_RET(w->SinvT.alloc((size_t)nw * 2 * nmax * nmax * 16));
     AFQ_RET(w->logdet.alloc((size_t)nw * 2 * 16));
     AFQ_RET(w->logdet_new.alloc((size_t)nw * 2 * 16));
     AFQ_RET(w->sing.alloc((size_t)nw * 2 * sizeof(int)));
@@ -59,7 +60,11 @@ int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool
     const int n = s->nspin_n(sp), off = s->spin_off(sp);
     GemmArgs<double> g = gemm_args<double>();
     g.m = n; g.n = n; g.k = M; g.batch = nw;
-    g.A = s->phi.as<double>() + 2 * off; g.lda = ntot; g.opA = OP_C; g.cA = true; g.sA = 0;
+    if (s->phitr.p) {   // real trial: T^T rows, k-contiguous (real x complex)
+      g.A = s->phitr.as<double>() + (long)off * M; g.lda = M; g.cA = false; g.sA = 0;
+    } else {
+      g.A = s->phi.as<double>() + 2 * off; g.lda = ntot; g.opA = OP_C; g.cA = true; g.sA = 0;
+    }
     g.B = reinterpret_cast<const double*>(Wsrc) + 2 * off; g.ldb = ntot; g.cB = true; g.sB = (long)M * ntot;
     g.C = w->S.as<double>() + 2 * sp * nm2; g.ldc = n; g.cC = true; g.sC = 2 * nm2;
     AFQ_RET(gemm<double>(g, st));
@@ -67,10 +72,12 @@ int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool
                        want_theta ? w->Sinv.as<double2>() + sp * nm2 : nullptr, logdet_out + sp, 2,
                        w->sing.as<int>() + sp, 2, st));
     if (want_theta) {
-      // thetaT[w][off + b][k] = sum_j Sinv[j][b] W[k][off + j]
+      // thetaT[w][off + b][k] = sum_j (S^-1)^T[b][j] W[k][off + j]  (both operands k-contiguous)
+      AFQ_RET(transpose_batched(w->Sinv.as<double2>() + sp * nm2, 2 * nm2, n, nw, w->SinvT.as<double2>() + sp * nm2,
+                                st));
       GemmArgs<double> t = gemm_args<double>();
       t.m = n; t.n = M; t.k = n; t.batch = nw;
-      t.A = w->Sinv.as<double>() + 2 * sp * nm2; t.lda = n; t.opA = OP_T; t.cA = true; t.sA = 2 * nm2;
+      t.A = w->SinvT.as<double>() + 2 * sp * nm2; t.lda = n; t.cA = true; t.sA = 2 * nm2;
       t.B = reinterpret_cast<const double*>(Wsrc) + 2 * off; t.ldb = ntot; t.opB = OP_T; t.cB = true;
       t.sB = (long)M * ntot;
       t.C = w->theta.as<double>() + 2 * (long)off * M; t.ldc = M; t.cC = true; t.sC = (long)ntot * M;
