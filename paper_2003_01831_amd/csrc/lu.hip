@@ -16,21 +16,26 @@ constexpr int NMAX = 128;
 template <int NT>
 struct GjShared {
   double2 rowp[NMAX], colk[NMAX];
+  double2 pivs[NMAX];
   int used[NMAX], perm[NMAX], q[NMAX];
   double red_v[NT / 64];
   int red_i[NT / 64];
+  double2 red_z[NT / 64];
+  double2 red_l[NT / 64];
   int p, sing;
   double d;
 };
 
 // Row and column of register slot j (element e = tid + NT j) without an
 // integer division: r = mulhi(e, m) with m = ceil(2^32 / n) is exact for the
-// e < 2^16, n <= 128 used here. Rows of empty slots (e >= n^2) are >= n.
+// e < 2^16, 2 <= n <= 128 used here; for n = 1 (m = 2^32 does not fit in 32
+// bits) r = e. Rows of empty slots (e >= n^2) are >= n.
 struct SlotMap {
   unsigned m;
   int n;
-  __device__ explicit SlotMap(int n_) : m((unsigned)((0x100000000ull + (unsigned)n_ - 1) / (unsigned)n_)), n(n_) {}
-  __device__ int row(int e) const { return (int)__umulhi((unsigned)e, m); }
+  __device__ explicit SlotMap(int n_)
+      : m(n_ > 1 ? (unsigned)((0x100000000ull + (unsigned)n_ - 1) / (unsigned)n_) : 0u), n(n_) {}
+  __device__ int row(int e) const { return n > 1 ? (int)__umulhi((unsigned)e, m) : e; }
   __device__ int col(int e, int r) const { return e - r * n; }
 };
 
@@ -132,6 +137,116 @@ __device__ void gauss_jordan(double2 (&a)[EPT], int n, bool pivoting, GjShared<N
   }
 }
 
+// Gauss-Jordan (FULL) or LU (determinant only) elimination with partial
+// pivoting, two barriers per step: each wave reduces its candidates of
+// column k (|a|^2, row, value) and every thread combines the per-wave
+// winners in the same order, so all threads take the same pivot row p and
+// 1 / pivot without another barrier; row p is broadcast already scaled by
+// 1 / pivot. The pivots go to sh.pivs (their logs are summed afterwards, in
+// parallel) and the pivot order to sh.perm. A column without a usable pivot
+// (zero or non-finite) flags the matrix singular and takes pivot 1 in the
+// first row not yet used. The update of step k only overwrites registers and
+// the broadcast arrays are written after the first barrier of the next step,
+// so no barrier closes a step.
+template <int NT, int EPT, bool FULL>
+__device__ void gj_pivoted(double2 (&a)[EPT], int n, GjShared<NT>& sh) {
+  static_assert(EPT <= 32, "slot mask");
+  constexpr int NWV = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const SlotMap sm(n);
+  unsigned live = 0;   // bit j: slot j's row has not been a pivot row yet
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) live |= (sm.row(tid + NT * j) < n ? 1u : 0u) << j;
+  unsigned long long used0 = 0, used1 = 0;   // rows already taken as pivots (n <= 128)
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = 1 << 30;
+    double2 bv = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + NT * j, r = sm.row(e);
+      if (sm.col(e, r) == k && ((live >> j) & 1)) {
+        const double v = cabs2(a[j]);
+        if (v > best || (v == best && r < bi)) { best = v; bi = r; bv = a[j]; }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      const double ox = __shfl_xor(bv.x, off), oy = __shfl_xor(bv.y, off);
+      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; bv = make_double2(ox, oy); }
+    }
+    if (lane == 0) { sh.red_v[wave] = best; sh.red_i[wave] = bi; sh.red_z[wave] = bv; }
+    __syncthreads();
+    best = sh.red_v[0];
+    bi = sh.red_i[0];
+    bv = sh.red_z[0];
+#pragma unroll
+    for (int w = 1; w < NWV; ++w)
+      if (sh.red_v[w] > best || (sh.red_v[w] == best && sh.red_i[w] < bi)) {
+        best = sh.red_v[w];
+        bi = sh.red_i[w];
+        bv = sh.red_z[w];
+      }
+    bool bad = false;
+    if (bi < 0 || bi >= n) {   // no usable candidate (a non-finite column): first unused row
+      bad = true;
+      bi = ~used0 ? __ffsll((long long)~used0) - 1 : 64 + __ffsll((long long)~used1) - 1;
+      if (bi >= n) bi = n - 1;
+    }
+    const int p = bi;
+    if (p < 64) used0 |= 1ull << p;
+    else used1 |= 1ull << (p - 64);
+    double2 piv = bv;
+    const double pm = cabs2(piv);
+    if (bad || !(pm > 0.0) || !isfinite(pm)) {
+      bad = true;
+      piv = make_double2(1.0, 0.0);
+    }
+    const double2 ipiv = cdiv(make_double2(1.0, 0.0), piv);
+    if (tid == 0) {
+      sh.pivs[k] = piv;
+      sh.perm[k] = p;
+      if (bad) sh.sing = 1;
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
+      if (r < n) {
+        if (r == p) sh.rowp[c] = c == k ? ipiv : cmul(a[j], ipiv);
+        if (c == k) sh.colk[r] = a[j];
+      }
+    }
+    __syncthreads();
+    if constexpr (FULL) {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
+        if (r < n) {
+          const double2 rp = sh.rowp[c];
+          if (r == p) {
+            a[j] = rp;
+          } else {
+            const double2 base = c == k ? make_double2(0.0, 0.0) : a[j];
+            a[j] = csub(base, cmul(sh.colk[r], rp));
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) {
+        const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
+        if (((live >> j) & 1) && r != p && c > k) a[j] = csub(a[j], cmul(sh.colk[r], sh.rowp[c]));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j)
+      if (sm.row(tid + NT * j) == p) live &= ~(1u << j);
+  }
+  __syncthreads();
+}
+
 template <int NT, int EPT, bool FULL>
 __device__ void gj_body(const double2* __restrict__ S, long stride, int n,
                                                 double2* __restrict__ inv, double2* __restrict__ logdet,
@@ -148,9 +263,20 @@ __device__ void gj_body(const double2* __restrict__ S, long stride, int n,
   if (tid < n) sh.used[tid] = 0;
   if (tid == 0) sh.sing = 0;
   __syncthreads();
-  double2 ld = make_double2(0.0, 0.0);
-  gauss_jordan<NT, EPT, FULL>(a, n, true, sh, ld);
+  gj_pivoted<NT, EPT, FULL>(a, n, sh);
+  // log det = sum_k log(pivot_k) (+ i pi for an odd permutation): threads k < n
+  // take one pivot each, waves reduce, the per-wave sums are added in order
+  double2 ld = tid < n ? clog(sh.pivs[tid]) : make_double2(0.0, 0.0);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    ld.x += __shfl_xor(ld.x, off);
+    ld.y += __shfl_xor(ld.y, off);
+  }
+  if ((tid & 63) == 0 && tid < NMAX) sh.red_l[tid >> 6] = ld;
+  __syncthreads();
   if (tid == 0) {
+    ld = sh.red_l[0];
+    if (n > 64) ld = cadd(ld, sh.red_l[1]);
     // parity of the pivot permutation k -> perm[k]; inverse permutation q
     int parity = 0;
     for (int k = 0; k < n; ++k) { sh.q[sh.perm[k]] = k; sh.used[k] = 0; }
