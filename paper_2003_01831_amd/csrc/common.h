@@ -229,6 +229,8 @@ struct afq_walkers_s {
   DevBuf kp_tmp;               // 2 x nk x nw x nk m^2 complex: A-build GEMM outputs
   // FP32 ring scratch: packed coefficient rows, packed Theta-hat rows, force-bias partial tiles
   DevBuf r32_coef, r32_theta, r32_part;
+  DevBuf r32_x;                // real form of A_w, packed for the Taylor products
+  DevBuf r32_y[3];             // packed Taylor terms: V, then two alternating Horner terms
   // four-index exchange scratch
   DevBuf eri_theta;            // packed Theta-hat hi / lo planes of one spin
   DevBuf eri_part;             // per (work unit, column) complex partial sums
@@ -316,8 +318,11 @@ int kp_abuild(afq_system s, afq_walkers w, const double2* coef, hipStream_t st);
 int r32_prepare(afq_system s);                     // packed L (reduced modes) and Lt (split-BF16x3, real trial)
 int r32_alloc_scratch(afq_system s, afq_walkers w);
 bool r32_coulomb_used(afq_system s);
-// amat[w] = sum_n coef[w][n] L^n (complex FP32) for the walkers of w
-int r32_abuild(afq_system s, afq_walkers w, const float* coef, float2* amat, hipStream_t st);
+bool r32_taylor_used(afq_system s);
+// A_w = sum_n coef[w][n] L^n, written in packed real form to w->r32_x
+int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st);
+// w->u <- sum_{j <= order} A_w^j u / j! (Horner form, A_w from r32_abuild)
+int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st);
 // tro[w][spin][n] = tr(Lt^{n,spin} Theta^spin) from the FP32 operands
 int r32_coulomb(afq_system s, afq_walkers w, hipStream_t st);
 

@@ -4,16 +4,27 @@
 //   * the propagator matrices A_w = sum_n c_wn L^n: coefficient rows
 //     (w, Re|Im) times the Cholesky vectors, which are packed once per system
 //     k-contiguous (entry e of L^n at [n / 16][e][n % 16]); the epilogue writes
-//     A_w as complex FP32;
+//     A_w in real form, rows (m, Re) = [Re A, -Im A] and (m, Im) = [Im A, Re A]
+//     interleaved over k, packed k-contiguous for the Taylor products;
+//   * the Taylor propagator in Horner form, U = V + A (V + A/2 (... (V + A V/K))),
+//     V = B1 W: every product is the real contraction of the walker columns
+//     (rows n of the packed term, Re/Im interleaved over k) with the real form
+//     of A, so row n of the output is [Re, Im] of (A h)[m][n] over columns
+//     2m + part; intermediate terms V + A h / j stay FP32 in the packed layout,
+//     the last one is added to V in FP64;
 //   * the force-bias traces tr(Lt^{ns} Theta^s) = sum_(a,k) Theta-hat[(a,k)] Lt_n[a][k]
 //     (split-BF16x3 mode, real trial): Theta-hat rows (w, Re|Im) times the
 //     real half-rotated vectors, packed once per system; the N M contraction is
 //     split into runs whose FP32 tiles are summed in FP64 in a fixed order.
 //
-// Both are C = A B^T with A and B packed chunk-major (64-byte rows of 16 FP32
-// contraction elements, all rows of a chunk contiguous), the same layout and
-// swizzle as the split-BF16x3 kernels. Workgroup tile 256 x 128 (2 x 2 waves
-// of 8 x 4 MFMA tiles), 72 KB of LDS, two workgroups per CU.
+// All are C = A B^T with A and B packed chunk-major (64-byte rows of 16 FP32
+// contraction elements, all rows of a chunk contiguous), the layout and
+// swizzle of the split-BF16x3 kernels, batched over walkers where the
+// operands are per walker. Two tile geometries: 256 x 128 (2 x 2 waves of
+// 8 x 4 MFMA tiles) for the propagator build and the force bias, 224 x 160
+// (7 x 5 tiles) for the Taylor products, whose n_tot walker columns and 2M
+// real-form rows it covers with little padding at the M = 400, N = 200 shape.
+// 72-74 KB of LDS, two workgroups per CU.
 #include <algorithm>
 #include "common.h"
 #include "mfma_ring.h"
@@ -27,34 +38,49 @@ using ring::swz;
 using ring::wait_vm_barrier;
 
 constexpr int NWAVE = 4, NXCD = 8;
-constexpr int RK = 16;                      // FP32 contraction elements per chunk row
-constexpr int TA = 8, TB = 4;
-constexpr int RA = 32 * TA, RBR = 32 * TB;  // 256 x 128
-constexpr int REGA = RA * ROWB, REGB = RBR * ROWB;
-constexpr int STAGE = REGA + REGB;
-constexpr int NT = STAGE / 1024, NQ = NT / NWAVE;
-static_assert(NT % NWAVE == 0, "loads must split evenly over the waves");
+constexpr int RK = 16;   // FP32 contraction elements per chunk row
 
-enum { EPI_AMAT = 0, EPI_PART = 1 };
+template <int TA_, int TB_> struct Geo {
+  static constexpr int TA = TA_, TB = TB_;
+  static constexpr int RA = 32 * TA, RB = 32 * TB;
+  static constexpr int REGA = RA * ROWB, REGB = RB * ROWB, STAGE = REGA + REGB;
+  static constexpr int NT = STAGE / 1024, NQ = NT / NWAVE;
+  static_assert(NT % NWAVE == 0, "loads must split evenly over the waves");
+};
+using GeoAB = Geo<8, 4>;   // propagator build, force bias
+using GeoTY = Geo<7, 5>;   // Taylor products
+
+enum { EPI_XFORM = 0, EPI_PART = 1, EPI_HORNER = 2 };
 
 struct R32Args {
-  const unsigned char* a;   // packed A: [chunk][rows_a][16] float
+  const unsigned char* a;   // packed A: [chunk][rows_a][16] float (per batch member at a_bstride bytes)
   const unsigned char* b;   // packed B: [chunk][rows_b][16] float
-  long rows_a, rows_b;
-  int nchunk, kper, nblk_a, nblk_b;
-  int nunit, grid;          // units = A row blocks x contraction runs; grid = units x B blocks
+  long rows_a, rows_b, a_bstride, b_bstride;
+  int nchunk, kper, nblk_a, nblk_b, nbatch;
+  int nunit, grid;          // units = A row blocks x contraction runs; grid = batch x units x B blocks
   int a_fast;               // 1: consecutive workgroups take consecutive A row blocks (sharing a B block)
-  float2* amat;             // EPI_AMAT: rows (w, Re|Im), columns e -> amat[w][e]
-  long ncol;
-  int nw;
-  float* part;              // EPI_PART: part[(run * rows_a + row) * rows_b + col]
+  // EPI_XFORM: A rows (w, Re|Im), B rows e = m M + k -> real form of A_w at x + w x_wstride
+  float* x;
+  long x_wstride, x_rows, ncol;
+  int M, nw;
+  // EPI_PART: part[(run * rows_a + row) * rows_b + col]
+  float* part;
+  // EPI_HORNER: A rows n (walker columns), B rows 2m + part; batch member = walker
+  const float* vy;          // V in the packed term layout
+  float* yout;              // V + scale (A h) in the packed term layout (intermediate terms)
+  double2* u;               // U[w][m][n] += scale (A h) (last term)
+  float scale;
+  int last;
+  long y_rows, y_wstride;
+  int ntot;
 };
 
-template <int EPI>
+template <class G, int EPI>
 __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
-  __shared__ __align__(16) unsigned char L0[STAGE];
-  __shared__ __align__(16) unsigned char L1[STAGE];
-  __shared__ __align__(16) unsigned char L2[STAGE];
+  constexpr int TA = G::TA, TB = G::TB, RA = G::RA, RB = G::RB, REGA = G::REGA, NQ = G::NQ;
+  __shared__ __align__(16) unsigned char L0[G::STAGE];
+  __shared__ __align__(16) unsigned char L1[G::STAGE];
+  __shared__ __align__(16) unsigned char L2[G::STAGE];
   __shared__ float trash[NWAVE * 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rb = wave >> 1, cb = wave & 1;
@@ -63,17 +89,23 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
   const int per = (int)(gridDim.x / NXCD);
   const int lid = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
   if (lid >= g.grid) return;
-  int u, bb;
+  int u, bb, batch;
   if (g.a_fast) {
     u = lid % g.nunit;
-    bb = lid / g.nunit;
+    const int rest = lid / g.nunit;
+    bb = rest % g.nblk_b;
+    batch = rest / g.nblk_b;
   } else {
-    u = lid / g.nblk_b;
-    bb = lid - u * g.nblk_b;
+    bb = lid % g.nblk_b;
+    const int rest = lid / g.nblk_b;
+    u = rest % g.nunit;
+    batch = rest / g.nunit;
   }
   const int p = u % g.nblk_a, run = u / g.nblk_a;
   const int c0 = run * g.kper, nc = min(g.kper, g.nchunk - c0);   // >= 1
-  const long arow0 = (long)p * RA, brow0 = (long)bb * RBR;
+  const long arow0 = (long)p * RA, brow0 = (long)bb * RB;
+  const unsigned char* abase = g.a + batch * g.a_bstride;
+  const unsigned char* bbase = g.b + batch * g.b_bstride;
   // load q of this wave: instruction t = q * 4 + wave of the stage, 16 rows of
   // A (t < RA / 16) or B; lane l writes LDS bytes 1024 t + 16 l (row l / 4, swizzled piece)
   const unsigned char* src[NQ];
@@ -85,7 +117,7 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
     const int j = isb ? t - RA / 16 : t;
     const int row = 16 * j + (lane >> 2), c = swz(row, lane & 3);
     cstride[q] = (isb ? g.rows_b : g.rows_a) * (long)ROWB;
-    src[q] = (isb ? g.b : g.a) + ((isb ? brow0 : arow0) + row) * ROWB + 16 * c + (long)c0 * cstride[q];
+    src[q] = (isb ? bbase : abase) + ((isb ? brow0 : arow0) + row) * ROWB + 16 * c + (long)c0 * cstride[q];
   }
   auto issue = [&](int chunk, unsigned char* buf) {
     lds_t* l = (lds_t*)buf;
@@ -104,7 +136,7 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
   for (int i = 0; i < TA; ++i)
 #pragma unroll
     for (int j = 0; j < TB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  const int arow = rb * (RA / 2), brow = cb * (RBR / 2);
+  const int arow = rb * (RA / 2), brow = cb * (RB / 2);
   issue(0, L0);
   if (nc > 1) issue(1, L1);
   else issue_dummy();
@@ -130,20 +162,28 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
 
   // lane (lr, lq) holds rows 4 lq .. 4 lq + 3 of column lr of every tile
   const int lr = lane & 15, lq = lane >> 4;
-  if constexpr (EPI == EPI_AMAT) {
+  if constexpr (EPI == EPI_XFORM) {
 #pragma unroll
     for (int i = 0; i < TA; ++i)
 #pragma unroll
       for (int j = 0; j < TB; ++j) {
         const long row0 = arow0 + arow + 16 * i + 4 * lq;    // rows (w0, Re), (w0, Im), (w0 + 1, Re), (w0 + 1, Im)
-        const long col = brow0 + brow + 16 * j + lr;
-        const int w0 = (int)(row0 >> 1);
-        if (col < g.ncol) {
-          if (w0 < g.nw) g.amat[(long)w0 * g.ncol + col] = make_float2(acc[i][j][0], acc[i][j][1]);
-          if (w0 + 1 < g.nw) g.amat[(long)(w0 + 1) * g.ncol + col] = make_float2(acc[i][j][2], acc[i][j][3]);
+        const long col = brow0 + brow + 16 * j + lr;          // e = m M + k
+        if (col >= g.ncol) continue;
+        const int m = (int)(col / g.M), k = (int)(col - (long)m * g.M);
+        const long o0 = ((long)(k >> 3) * g.x_rows + 2 * m) * RK + 2 * (k & 7);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int w = (int)(row0 >> 1) + h;
+          if (w < g.nw) {
+            const float ar = acc[i][j][2 * h], ai = acc[i][j][2 * h + 1];
+            float* X = g.x + (long)w * g.x_wstride;
+            *reinterpret_cast<float2*>(X + o0) = make_float2(ar, -ai);
+            *reinterpret_cast<float2*>(X + o0 + RK) = make_float2(ai, ar);
+          }
         }
       }
-  } else {
+  } else if constexpr (EPI == EPI_PART) {
     float* out = g.part + (long)run * g.rows_a * g.rows_b;
 #pragma unroll
     for (int i = 0; i < TA; ++i)
@@ -155,6 +195,37 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
           const long col = brow0 + brow + 16 * j + lr;
           out[row * g.rows_b + col] = acc[i][j][v];
         }
+  } else {
+    // column 2m + part of row n is part (Re, Im) of (A h)[m][n]: the partner
+    // lane lr ^ 1 holds the other part; even lanes finish rows 0, 1 of their
+    // four, odd lanes rows 2, 3
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        float o[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = __shfl_xor(acc[i][j][r], 1);
+        const long n0 = arow0 + arow + 16 * i + 4 * lq;
+        const int col = (int)(brow0 + brow + 16 * j + lr), m = col >> 1, part = col & 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int r = part ? 2 + h : h;
+          const long n = n0 + r;
+          const float re = part ? o[r] : acc[i][j][r], im = part ? acc[i][j][r] : o[r];
+          if (n < g.ntot && m < g.M) {
+            if (g.last) {
+              double2* up = g.u + ((long)batch * g.M + m) * g.ntot + n;
+              const double2 v = *up;
+              *up = make_double2(v.x + (double)(g.scale * re), v.y + (double)(g.scale * im));
+            } else {
+              const long idx = (long)batch * g.y_wstride + ((long)(m >> 3) * g.y_rows + n) * RK + 2 * (m & 7);
+              const float2 v = *reinterpret_cast<const float2*>(g.vy + idx);
+              *reinterpret_cast<float2*>(g.yout + idx) = make_float2(v.x + g.scale * re, v.y + g.scale * im);
+            }
+          }
+        }
+      }
   }
 }
 
@@ -197,6 +268,20 @@ __global__ void pack_cols_kernel(const double* __restrict__ src, long ncol, int 
   }
 }
 
+// V[w][m][n] (complex FP64) -> the packed term layout of walker w: element
+// (n, 2m + part) at ((m / 8) y_rows + n) 16 + 2 (m % 8) + part
+__global__ void pack_terms_kernel(const double2* __restrict__ V, int nw, int M, int ntot, long y_rows, long y_wstride,
+                                  float* __restrict__ out) {
+  const long total = (long)nw * M * ntot;
+  for (long t = blockIdx.x * 256L + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+    const long w = t / ((long)M * ntot), rem = t - w * M * ntot;
+    const int m = (int)(rem / ntot), n = (int)(rem - (long)m * ntot);
+    const double2 v = V[t];
+    *reinterpret_cast<float2*>(out + w * y_wstride + ((long)(m >> 3) * y_rows + n) * RK + 2 * (m & 7)) =
+        make_float2((float)v.x, (float)v.y);
+  }
+}
+
 // tro[w][spin][n] = sum over runs (fixed order) of (part[run][2w][n], part[run][2w + 1][n])
 __global__ void coulomb_reduce_kernel(const float* __restrict__ part, int nrun, long rows_a, long rows_b, int nw,
                                       int X, int spin, double2* __restrict__ tro) {
@@ -215,41 +300,57 @@ __global__ void coulomb_reduce_kernel(const float* __restrict__ part, int nrun, 
 int grid_of(long total) { return (int)std::min<long>(std::max<long>((total + 255) / 256, 1), 1 << 20); }
 long pad_to(long x, long m) { return (x + m - 1) / m * m; }
 
-template <int EPI>
+template <class G, int EPI>
 int launch(R32Args& g, hipStream_t st) {
-  g.nblk_a = (int)(g.rows_a / RA);
-  g.nblk_b = (int)(g.rows_b / RBR);
+  g.nblk_a = (int)(g.rows_a / G::RA);
+  g.nblk_b = (int)(g.rows_b / G::RB);
+  if (g.nbatch < 1) g.nbatch = 1;
   const int nrun = (g.nchunk + g.kper - 1) / g.kper;
-  const long nunit = (long)g.nblk_a * nrun, grid = nunit * g.nblk_b;
-  AFQ_CHECK(g.nchunk >= 1 && g.rows_a % RA == 0 && g.rows_b % RBR == 0 && grid < (1L << 30), AFQ_E_INVALID,
-            "FP32 ring contraction: bad shape");
+  const long nunit = (long)g.nblk_a * nrun, grid = nunit * g.nblk_b * g.nbatch;
+  AFQ_CHECK(g.nchunk >= 1 && g.kper >= 1 && g.rows_a % G::RA == 0 && g.rows_b % G::RB == 0 && grid < (1L << 30),
+            AFQ_E_INVALID, "FP32 ring contraction: bad shape");
   g.nunit = (int)nunit;
   g.grid = (int)grid;
   const long launch = (grid + NXCD - 1) / NXCD * NXCD;
-  hipLaunchKernelGGL(ring32_kernel<EPI>, dim3((unsigned)launch), dim3(256), 0, st, g);
+  hipLaunchKernelGGL((ring32_kernel<G, EPI>), dim3((unsigned)launch), dim3(256), 0, st, g);
   return hip_status(hipGetLastError(), "FP32 ring contraction");
 }
 
 // rows of the coefficient operand and of the Theta-hat operand for nw walkers
-long coef_rows(int nw) { return pad_to(2L * nw, RA); }
+long coef_rows(int nw) { return pad_to(2L * nw, GeoAB::RA); }
 
 // runs of the force-bias contraction: about 2048 workgroups, runs of at least 16 chunks
 int coulomb_kper(long nchunk, long rows_a, long rows_b) {
-  const long tiles = (rows_a / RA) * (rows_b / RBR);
+  const long tiles = (rows_a / GeoAB::RA) * (rows_b / GeoAB::RB);
   const long nrun = std::max<long>(1, std::min<long>(nchunk / 16, (2048 + tiles - 1) / tiles));
   return (int)((nchunk + nrun - 1) / nrun);
+}
+
+// packed real form of A_w (rows 2M, contraction 2M) and packed terms (rows n_tot)
+struct TaylorShape {
+  long x_rows, y_rows, kchunk, x_wstride, y_wstride;   // strides in floats
+};
+TaylorShape taylor_shape(afq_system s) {
+  TaylorShape t;
+  t.x_rows = pad_to(2L * s->M, GeoTY::RB);
+  t.y_rows = pad_to(s->ntot, GeoTY::RA);
+  t.kchunk = pad_to(2L * s->M, RK) / RK;
+  t.x_wstride = t.x_rows * t.kchunk * RK;
+  t.y_wstride = t.y_rows * t.kchunk * RK;
+  return t;
 }
 
 }  // namespace
 
 bool r32_coulomb_used(afq_system s) { return s->lt32[0].p != nullptr; }
+bool r32_taylor_used(afq_system s) { return s->chol32t.p != nullptr; }
 
 int r32_prepare(afq_system s) {
   hipStream_t st = s->stream;
   const bool reduced = s->prec != AFQ_FP64 && s->kp_nk == 0;
   if (reduced && !s->chol32t.p) {
     const long m2 = (long)s->M * s->M;
-    const long rows = pad_to(m2, RBR);
+    const long rows = pad_to(m2, GeoAB::RB);
     const int nchunk = (int)pad_to(s->X, RK) / RK;
     AFQ_RET(s->chol32t.alloc((size_t)nchunk * rows * RK * sizeof(float)));
     hipLaunchKernelGGL(pack_cols_kernel, dim3(grid_of((long)nchunk * rows * RK)), dim3(256), 0, st,
@@ -261,7 +362,7 @@ int r32_prepare(afq_system s) {
     AFQ_CHECK(s->LtRe.p, AFQ_E_STATE, "force bias (FP32 ring): real half-rotated vectors missing");
     for (int sp = 0; sp < 2; ++sp) {
       const long NM = (long)s->nspin_n(sp) * s->M;
-      const long rows = pad_to(s->X, RBR);
+      const long rows = pad_to(s->X, GeoAB::RB);
       const int nchunk = (int)(pad_to(NM, RK) / RK);
       AFQ_RET(s->lt32[sp].alloc((size_t)nchunk * rows * RK * sizeof(float)));
       hipLaunchKernelGGL(pack_real_rows_kernel, dim3(grid_of((long)nchunk * rows * RK)), dim3(256), 0, st,
@@ -277,16 +378,28 @@ int r32_prepare(afq_system s) {
   return AFQ_OK;
 }
 
+// The packed buffers are cleared when allocated: their padding rows and
+// contraction columns are never written afterwards and must stay zero (finite).
+static int alloc_cleared(DevBuf& b, size_t bytes, hipStream_t st) {
+  if (b.bytes >= bytes) return AFQ_OK;
+  AFQ_RET(b.alloc(bytes));
+  AFQ_TRY_HIP(hipMemsetAsync(b.p, 0, bytes, st));
+  return AFQ_OK;
+}
+
 int r32_alloc_scratch(afq_system s, afq_walkers w) {
   if (!s->chol32t.p) return AFQ_OK;
+  hipStream_t st = s->stream;
   const long rows = coef_rows(w->nw);
-  size_t cb = (size_t)(pad_to(s->X, RK)) * rows * sizeof(float);
-  if (w->r32_coef.bytes < cb) AFQ_RET(w->r32_coef.alloc(cb));
+  AFQ_RET(alloc_cleared(w->r32_coef, (size_t)(pad_to(s->X, RK)) * rows * sizeof(float), st));
+  const TaylorShape ts = taylor_shape(s);
+  AFQ_RET(alloc_cleared(w->r32_x, (size_t)w->nw * ts.x_wstride * sizeof(float), st));
+  for (int i = 0; i < 3; ++i) AFQ_RET(alloc_cleared(w->r32_y[i], (size_t)w->nw * ts.y_wstride * sizeof(float), st));
   if (!s->lt32[0].p) return AFQ_OK;
   size_t tb = 0, pb = 0;
   for (int sp = 0; sp < 2; ++sp) {
     const long NM = (long)s->nspin_n(sp) * s->M;
-    const long nchunk = pad_to(NM, RK) / RK, rows_b = pad_to(s->X, RBR);
+    const long nchunk = pad_to(NM, RK) / RK, rows_b = pad_to(s->X, GeoAB::RB);
     tb = std::max(tb, (size_t)nchunk * rows * RK * sizeof(float));
     const int kper = coulomb_kper(nchunk, rows, rows_b);
     const long nrun = (nchunk + kper - 1) / kper;
@@ -297,11 +410,13 @@ int r32_alloc_scratch(afq_system s, afq_walkers w) {
   return AFQ_OK;
 }
 
-int r32_abuild(afq_system s, afq_walkers w, const float* coef, float2* amat, hipStream_t st) {
+int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st) {
   const long rows = coef_rows(w->nw);
   const int nchunk = (int)(pad_to(s->X, RK) / RK);
-  AFQ_CHECK(s->chol32t.p && w->r32_coef.bytes >= (size_t)nchunk * rows * RK * sizeof(float), AFQ_E_STATE,
-            "propagator build (FP32 ring): operands not prepared");
+  const TaylorShape ts = taylor_shape(s);
+  AFQ_CHECK(s->chol32t.p && w->r32_coef.bytes >= (size_t)nchunk * rows * RK * sizeof(float) &&
+                w->r32_x.bytes >= (size_t)w->nw * ts.x_wstride * sizeof(float),
+            AFQ_E_STATE, "propagator build (FP32 ring): operands not prepared");
   hipLaunchKernelGGL(pack_cplx_rows_kernel<float>, dim3(grid_of((long)nchunk * rows * RK)), dim3(256), 0, st, coef,
                      (long)s->X, w->nw, (long)s->X, rows, nchunk, w->r32_coef.as<float>());
   AFQ_TRY_HIP(hipGetLastError());
@@ -309,19 +424,62 @@ int r32_abuild(afq_system s, afq_walkers w, const float* coef, float2* amat, hip
   g.a = w->r32_coef.as<unsigned char>();
   g.b = s->chol32t.as<unsigned char>();
   g.rows_a = rows;
-  g.rows_b = pad_to((long)s->M * s->M, RBR);
+  g.rows_b = pad_to((long)s->M * s->M, GeoAB::RB);
   g.nchunk = nchunk;
   g.kper = nchunk;
   g.a_fast = 1;
-  g.amat = amat;
+  g.x = w->r32_x.as<float>();
+  g.x_wstride = ts.x_wstride;
+  g.x_rows = ts.x_rows;
   g.ncol = (long)s->M * s->M;
+  g.M = s->M;
   g.nw = w->nw;
-  return launch<EPI_AMAT>(g, st);
+  return launch<GeoAB, EPI_XFORM>(g, st);
+}
+
+int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st) {
+  const TaylorShape ts = taylor_shape(s);
+  const size_t yb = (size_t)w->nw * ts.y_wstride * sizeof(float);
+  AFQ_CHECK(w->r32_x.bytes >= (size_t)w->nw * ts.x_wstride * sizeof(float) && w->r32_y[0].bytes >= yb &&
+                w->r32_y[1].bytes >= yb && w->r32_y[2].bytes >= yb,
+            AFQ_E_STATE, "Taylor propagator (FP32 ring): walker scratch not prepared");
+  if (order < 1) return AFQ_OK;
+  float* V = w->r32_y[0].as<float>();
+  hipLaunchKernelGGL(pack_terms_kernel, dim3(grid_of((long)w->nw * s->M * s->ntot)), dim3(256), 0, st,
+                     w->u.as<double2>(), w->nw, s->M, s->ntot, ts.y_rows, ts.y_wstride, V);
+  AFQ_TRY_HIP(hipGetLastError());
+  const float* in = V;
+  for (int j = order; j >= 1; --j) {
+    float* out = w->r32_y[1 + (order - j) % 2].as<float>();
+    R32Args g{};
+    g.a = reinterpret_cast<const unsigned char*>(in);
+    g.b = w->r32_x.as<unsigned char>();
+    g.rows_a = ts.y_rows;
+    g.rows_b = ts.x_rows;
+    g.a_bstride = ts.y_wstride * (long)sizeof(float);
+    g.b_bstride = ts.x_wstride * (long)sizeof(float);
+    g.nchunk = (int)ts.kchunk;
+    g.kper = (int)ts.kchunk;
+    g.nbatch = w->nw;
+    g.a_fast = 0;
+    g.vy = V;
+    g.yout = out;
+    g.u = w->u.as<double2>();
+    g.scale = 1.0f / (float)j;
+    g.last = j == 1;
+    g.y_rows = ts.y_rows;
+    g.y_wstride = ts.y_wstride;
+    g.ntot = s->ntot;
+    g.M = s->M;
+    AFQ_RET((launch<GeoTY, EPI_HORNER>(g, st)));
+    in = out;
+  }
+  return AFQ_OK;
 }
 
 int r32_coulomb(afq_system s, afq_walkers w, hipStream_t st) {
   AFQ_CHECK(s->lt32[0].p, AFQ_E_STATE, "force bias (FP32 ring): operands not prepared");
-  const long rows = coef_rows(w->nw), rows_b = pad_to(s->X, RBR);
+  const long rows = coef_rows(w->nw), rows_b = pad_to(s->X, GeoAB::RB);
   for (int sp = 0; sp < 2; ++sp) {
     const long NM = (long)s->nspin_n(sp) * s->M;
     const int nchunk = (int)(pad_to(NM, RK) / RK);
@@ -344,7 +502,7 @@ int r32_coulomb(afq_system s, afq_walkers w, hipStream_t st) {
     g.kper = kper;
     g.a_fast = 0;
     g.part = w->r32_part.as<float>();
-    AFQ_RET(launch<EPI_PART>(g, st));
+    AFQ_RET((launch<GeoAB, EPI_PART>(g, st)));
     hipLaunchKernelGGL(coulomb_reduce_kernel, dim3(grid_of((long)w->nw * s->X)), dim3(256), 0, st,
                        w->r32_part.as<float>(), nrun, rows, rows_b, w->nw, s->X, sp, w->tro.as<double2>());
     AFQ_TRY_HIP(hipGetLastError());

@@ -43,9 +43,15 @@ int walkers_alloc_scratch(afq_walkers w) {
   if (s->prec == AFQ_BF16X3) AFQ_RET(w->bpack_lo.alloc(bsz * esz_of(s->prec)));
   else w->bpack_lo.free();
   AFQ_RET(w->coef.alloc((size_t)nw * X * cz));
-  AFQ_RET(w->amat.alloc((size_t)nw * M * M * cz));
-  AFQ_RET(w->t1.alloc((size_t)nw * per * cz));
-  AFQ_RET(w->t2.alloc((size_t)nw * per * cz));
+  if (r32_taylor_used(s)) {   // the FP32 ring propagator keeps its own packed operands
+    w->amat.free();
+    w->t1.free();
+    w->t2.free();
+  } else {
+    AFQ_RET(w->amat.alloc((size_t)nw * M * M * cz));
+    AFQ_RET(w->t1.alloc((size_t)nw * per * cz));
+    AFQ_RET(w->t2.alloc((size_t)nw * per * cz));
+  }
   w->scratch_prec = (size_t)s->prec;
   return AFQ_OK;
 }
@@ -198,9 +204,9 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
   if (s->kp_nk > 0) {
     TraceScope tr(AFQ_PH_ABUILD, st);
     AFQ_RET(kp_abuild(s, w, reinterpret_cast<const double2*>(coef), st));
-  } else if constexpr (sizeof(T) == 4) {   // reduced modes: the FP32 ring contraction
+  } else if (sizeof(T) == 4 && r32_taylor_used(s)) {   // reduced modes: the FP32 ring contraction
     TraceScope tr(AFQ_PH_ABUILD, st);
-    AFQ_RET(r32_abuild(s, w, reinterpret_cast<const float*>(coef), w->amat.as<float2>(), st));
+    AFQ_RET(r32_abuild(s, w, reinterpret_cast<const float*>(coef), st));
   } else {
     TraceScope tr(AFQ_PH_ABUILD, st);
     GemmArgs<T> g = gemm_args<T>();
@@ -221,21 +227,26 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
     g.C = w->u.as<double>(); g.ldc = ntot; g.cC = true; g.sC = per;
     AFQ_RET(gemm<double>(g, st));
   }
-  // term_0 = U (in the contraction precision); term_j = A term_{j-1} / j; U += term_j
-  T* cur = w->t1.as<T>();
-  T* nxt = w->t2.as<T>();
-  if (sizeof(T) == 8) AFQ_RET(copy_d(w->u.as<double>(), reinterpret_cast<double*>(cur), 2 * per * nw, st));
-  else AFQ_RET(convert_d2f(w->u.as<double>(), reinterpret_cast<float*>(cur), 2 * per * nw, st));
-  for (int j = 1; j <= order; ++j) {
-    GemmArgs<T> g = gemm_args<T>();
-    g.m = M; g.n = ntot; g.k = M; g.batch = nw;
-    g.A = w->amat.as<T>(); g.lda = M; g.cA = true; g.sA = (long)M * M;
-    g.B = cur; g.ldb = ntot; g.cB = true; g.sB = per;
-    g.C = j < order ? nxt : nullptr; g.ldc = ntot; g.cC = true; g.sC = per;
-    g.ar = 1.0 / j;
-    g.D = w->u.as<double2>(); g.ldd = ntot; g.sD = per;
-    AFQ_RET(gemm<T>(g, st));
-    std::swap(cur, nxt);
+  if (sizeof(T) == 4 && s->kp_nk == 0 && r32_taylor_used(s)) {
+    // reduced modes: U <- T_K(A) U in Horner form on the FP32 ring kernel
+    AFQ_RET(r32_taylor(s, w, order, st));
+  } else {
+    // term_0 = U (in the contraction precision); term_j = A term_{j-1} / j; U += term_j
+    T* cur = w->t1.as<T>();
+    T* nxt = w->t2.as<T>();
+    if (sizeof(T) == 8) AFQ_RET(copy_d(w->u.as<double>(), reinterpret_cast<double*>(cur), 2 * per * nw, st));
+    else AFQ_RET(convert_d2f(w->u.as<double>(), reinterpret_cast<float*>(cur), 2 * per * nw, st));
+    for (int j = 1; j <= order; ++j) {
+      GemmArgs<T> g = gemm_args<T>();
+      g.m = M; g.n = ntot; g.k = M; g.batch = nw;
+      g.A = w->amat.as<T>(); g.lda = M; g.cA = true; g.sA = (long)M * M;
+      g.B = cur; g.ldb = ntot; g.cB = true; g.sB = per;
+      g.C = j < order ? nxt : nullptr; g.ldc = ntot; g.cC = true; g.sC = per;
+      g.ar = 1.0 / j;
+      g.D = w->u.as<double2>(); g.ldd = ntot; g.sD = per;
+      AFQ_RET(gemm<T>(g, st));
+      std::swap(cur, nxt);
+    }
   }
   // W' = B1 U
   {
