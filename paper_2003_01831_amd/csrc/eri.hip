@@ -237,21 +237,28 @@ __global__ void eri_pack_theta_kernel(const double2* __restrict__ thetaT, int nt
   }
 }
 
-// per walker: the sum over units (fixed order) and both parts -> troo[w][spin][0];
-// the other vectors' entries are zero (the assembly only sums them)
-__global__ void eri_reduce_kernel(const double2* __restrict__ part, int nunit, long rows_b, int nw, int spin, int X,
-                                  double2* __restrict__ troo) {
-  const int w = blockIdx.x;
-  double2* o = troo + ((long)w * 2 + spin) * X;
-  if (threadIdx.x == 0) {
-    double2 s = make_double2(0.0, 0.0);
-    for (int u = 0; u < nunit; ++u) {
-      const double2* p = part + (long)u * rows_b + 2L * w;
-      s = cadd(s, cadd(p[0], p[1]));
-    }
-    o[0] = s;
+// per walker (one 256-thread workgroup): the sum over units and both parts ->
+// troo[w][spin][0], thread t taking units t, t + 256, ... and a fixed-shape tree
+// combining the threads (the same order on every call); the other vectors'
+// entries are zero (the assembly only sums them)
+__global__ __launch_bounds__(256) void eri_reduce_kernel(const double2* __restrict__ part, int nunit, long rows_b,
+                                                         int nw, int spin, int X, double2* __restrict__ troo) {
+  __shared__ double2 red[256];
+  const int w = blockIdx.x, t = threadIdx.x;
+  double2 s = make_double2(0.0, 0.0);
+  for (int u = t; u < nunit; u += 256) {
+    const double2* p = part + (long)u * rows_b + 2L * w;
+    s = cadd(s, cadd(p[0], p[1]));
   }
-  for (int n = 1 + threadIdx.x; n < X; n += blockDim.x) o[n] = make_double2(0.0, 0.0);
+  red[t] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] = cadd(red[t], red[t + h]);
+    __syncthreads();
+  }
+  double2* o = troo + ((long)w * 2 + spin) * X;
+  if (t == 0) o[0] = red[0];
+  for (int n = 1 + t; n < X; n += 256) o[n] = make_double2(0.0, 0.0);
 }
 
 // out[c][r] = in[r * ld_in + c]  (rows x cols -> cols x rows)
