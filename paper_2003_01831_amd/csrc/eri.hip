@@ -121,10 +121,12 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
   unsigned char* nxt = L1;
   unsigned char* pf = L2;
   for (int c = 0; c < nc; ++c) {
-    if (c + 2 < nc) issue(c + 2, pf);
-    else issue_dummy();
-    __builtin_amdgcn_sched_barrier(0);
-    ring::mma_rect<TA, TB, REGA, REGB>(acc, cur, cur + 2 * REGA, arow, brow, lane);
+    // the prefetch is issued after the chunk's first fragment reads, which
+    // complete while the loads go out
+    ring::mma_rect_then<TA, TB, REGA, REGB>(acc, cur, cur + 2 * REGA, arow, brow, lane, [&]() {
+      if (c + 2 < nc) issue(c + 2, pf);
+      else issue_dummy();
+    });
     __builtin_amdgcn_sched_barrier(0);
     wait_vm_barrier<NQ>();
     unsigned char* t = cur;

@@ -8,7 +8,7 @@
 //   * one LDS stage holds four regions (A hi, A lo, B hi, B lo) of REG bytes;
 //     rows are 64 bytes whose 16-byte pieces are XOR-swizzled, so fragment
 //     reads (16 bytes per lane) spread over the banks;
-//   * mma_rect multiplies one chunk of a wave's TA x TB block of 16 x 16
+//   * mma_rect_then multiplies one chunk of a wave's TA x TB block of 16 x 16
 //     tiles as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
 //     accumulators, in two passes (the A hi fragments resident, then the A lo).
 #pragma once
@@ -36,15 +36,20 @@ __device__ inline bf16x8 frag(const unsigned char* plane, int row, int lq) {
 
 // One chunk (32 contraction elements) of this wave's TA x TB block of 16 x 16
 // tiles. A planes at la (hi, then lo PA bytes later), B planes at lb (lo PB
-// bytes after hi); the wave's rows start at arow (A) and brow (B).
-template <int TA, int TB, int PA, int PB>
-__device__ inline void mma_rect(f4 (&acc)[TA][TB], const unsigned char* la, const unsigned char* lb, int arow,
-                                int brow, int lane) {
+// bytes after hi); the wave's rows start at arow (A) and brow (B). The
+// callback runs right after the first fragment reads are issued and before
+// the first MFMA: work placed there (the next chunk's global->LDS loads)
+// overlaps the latency of those reads. hi*hi for every row tile, then hi*lo,
+// so consecutive MFMAs never depend on each other's result.
+template <int TA, int TB, int PA, int PB, class F>
+__device__ inline void mma_rect_then(f4 (&acc)[TA][TB], const unsigned char* la, const unsigned char* lb, int arow,
+                                     int brow, int lane, F&& between) {
   const int lr = lane & 15, lq = lane >> 4;
   bf16x8 a[TA];
+  bf16x8 bh = frag(lb, brow + lr, lq), bl = frag(lb + PB, brow + lr, lq);
 #pragma unroll
   for (int i = 0; i < TA; ++i) a[i] = frag(la, arow + 16 * i + lr, lq);
-  bf16x8 bh = frag(lb, brow + lr, lq), bl = frag(lb + PB, brow + lr, lq);
+  between();
 #pragma unroll
   for (int j = 0; j < TB; ++j) {
     bf16x8 nh = bh, nl = bl;
@@ -52,8 +57,6 @@ __device__ inline void mma_rect(f4 (&acc)[TA][TB], const unsigned char* la, cons
       nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
       nl = frag(lb + PB, brow + 16 * (j + 1) + lr, lq);
     }
-    // hi*hi for every row tile, then hi*lo: consecutive MFMAs never depend on
-    // each other's result
 #pragma unroll
     for (int i = 0; i < TA; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
 #pragma unroll
@@ -74,9 +77,8 @@ __device__ inline void mma_rect(f4 (&acc)[TA][TB], const unsigned char* la, cons
   }
 }
 
-// The square case with equal plane offsets, written out rather than through
-// mma_rect: the exchange kernel's schedule and register allocation were tuned
-// on this form.
+// The square case with equal plane offsets for the Cholesky-form exchange
+// kernel, whose schedule and register allocation were tuned on this form.
 template <int TM, int RB>
 __device__ inline void mma_chunk(f4 (&acc)[TM][TM], const unsigned char* la, const unsigned char* lb, int arow,
                                  int brow, int lane) {
