@@ -248,6 +248,9 @@ template <typename T> struct GemmArgs {
   T* C; long ldc, sC; bool cC;                  // cC: C complex
   double ar, ai, br, bi;                        // alpha, beta
   double2* D; long ldd, sD;                     // optional D += result (complex f64)
+  // vn > 0: the n columns are batch members of vn columns each (column j is
+  // column j % vn of member j / vn, at the member strides sB, sC, sD); batch = 1
+  int vn;
 };
 // C = alpha op(A) op(B) + beta C   (D += alpha op(A) op(B) if D)
 template <typename T> int gemm(const GemmArgs<T>& g, hipStream_t st);

@@ -299,13 +299,20 @@ __global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs<T> g, int kspli
         }
       } else {              // B stored k-major: row r = k, vector along n
         const int gk = kb + r, gj = n0 + v * E / PB;
-        const long base = ((long)gk * g.ldb + gj) * PB;
+        const T* Bm = B;
+        int jj = gj;
+        if (g.vn) {           // virtual columns: member gj / vn (a vector never straddles two)
+          const int mb = gj / g.vn;
+          jj = gj - mb * g.vn;
+          Bm = g.B + (long)mb * g.sB * PB;
+        }
+        const long base = ((long)gk * g.ldb + jj) * PB;
         if (gk < kend && gj + E / PB <= g.n) {
-          rb[u] = *reinterpret_cast<const V*>(B + base);
+          rb[u] = *reinterpret_cast<const V*>(Bm + base);
         } else {
           T t[E];
 #pragma unroll
-          for (int e = 0; e < E; ++e) t[e] = (gk < kend && gj + e / PB < g.n) ? B[base + e] : T(0);
+          for (int e = 0; e < E; ++e) t[e] = (gk < kend && gj + e / PB < g.n) ? Bm[base + e] : T(0);
           rb[u] = vmake<T>(t);
         }
       }
@@ -409,8 +416,8 @@ __global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs<T> g, int kspli
         }
     return;
   }
-  T* C = g.C ? g.C + b * g.sC * (g.cC ? 2 : 1) : nullptr;
-  double2* D = g.D ? g.D + b * g.sD : nullptr;
+  T* C0 = g.C ? g.C + b * g.sC * (g.cC ? 2 : 1) : nullptr;
+  double2* D0 = g.D ? g.D + b * g.sD : nullptr;
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -418,8 +425,16 @@ __global__ __launch_bounds__(256) void gemm_tile_kernel(GemmArgs<T> g, int kspli
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gi = m0 + wm * 16 * WM + i * 16 + M::row(lane, r);
-        const int gj = n0 + wn * 16 * WN + j * 16 + c16;
+        int gj = n0 + wn * 16 * WN + j * 16 + c16;
         if (gi >= g.m || gj >= g.n) continue;
+        T* C = C0;
+        double2* D = D0;
+        if (g.vn) {           // virtual columns: member gj / vn
+          const int mb = gj / g.vn;
+          gj -= mb * g.vn;
+          if (C) C += (long)mb * g.sC * (g.cC ? 2 : 1);
+          if (D) D += (long)mb * g.sD;
+        }
         const double xr = (double)acc_r[i][j][r], xi = CPLX ? (double)acc_i[i][j][r] : 0.0;
         double vr = g.ar * xr - g.ai * xi;
         double vi = g.ar * xi + g.ai * xr;
@@ -529,6 +544,22 @@ template <typename T> int gemm(const GemmArgs<T>& g, hipStream_t st) {
   AFQ_CHECK(g.m >= 0 && g.n >= 0 && g.k >= 0 && g.batch >= 0, AFQ_E_INVALID, "gemm: negative size");
   if (g.m == 0 || g.n == 0 || g.batch == 0) return AFQ_OK;
   AFQ_CHECK(g.A && g.B && (g.C || g.D), AFQ_E_INVALID, "gemm: null operand");
+  if (g.vn) {
+    // virtual columns need the tiled kernel with B k-major, whole vectors per
+    // member and no split of k; otherwise run the members as a batch
+    AFQ_CHECK(g.vn > 0 && g.batch == 1 && g.n % g.vn == 0, AFQ_E_INVALID, "gemm: bad virtual column count");
+    const int vec = (int)(16 / sizeof(T)) / (g.cB ? 2 : 1);
+    const long tiles = (long)ceil_div(g.m, 64) * ceil_div(g.n, 128);
+    const bool ok = g.opB == OP_N && g.vn % vec == 0 && tile_applies(g) &&
+                    !(tiles < 512 && g.k / 2 >= 1024) && (g.sB * (g.cB ? 2 : 1) * (long)sizeof(T)) % 16 == 0;
+    if (!ok) {
+      GemmArgs<T> b = g;
+      b.batch = g.n / g.vn;
+      b.n = g.vn;
+      b.vn = 0;
+      return gemm<T>(b, st);
+    }
+  }
   const bool tiled = tile_applies(g);
   const int cfg = tiled ? tile_config(g) : -1;
   const int bm = tiled ? 32 * kTileWM[cfg] : BM, bn = tiled ? 32 * kTileWN[cfg] : BN;
@@ -537,7 +568,7 @@ template <typename T> int gemm(const GemmArgs<T>& g, hipStream_t st) {
   // split k when few output tiles share a long contraction
   int ksplit = 1;
   const long tiles = (long)tiles_m * tiles_n * g.batch;
-  while (tiles * ksplit < 512 && g.k / (ksplit * 2) >= 1024 && ksplit < 64) ksplit *= 2;
+  while (!g.vn && tiles * ksplit < 512 && g.k / (ksplit * 2) >= 1024 && ksplit < 64) ksplit *= 2;
   const int kchunk = round_up(ceil_div(g.k, ksplit), BK);
   AFQ_CHECK((long)g.batch * ksplit <= 65535, AFQ_E_INVALID, "gemm: batch too large");
   T* ws = nullptr;

@@ -66,8 +66,9 @@ int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool
     const int n = s->nspin_n(sp), off = s->spin_off(sp);
     GemmArgs<double> g = gemm_args<double>();
     g.m = n; g.n = n; g.k = M; g.batch = nw;
-    if (s->phitr.p) {   // real trial: T^T rows, k-contiguous (real x complex)
+    if (s->phitr.p) {   // real trial: T^T rows, k-contiguous (real x complex), walkers side by side
       g.A = s->phitr.as<double>() + (long)off * M; g.lda = M; g.cA = false; g.sA = 0;
+      g.n = nw * n; g.batch = 1; g.vn = n;
     } else {
       g.A = s->phi.as<double>() + 2 * off; g.lda = ntot; g.opA = OP_C; g.cA = true; g.sA = 0;
     }
@@ -218,10 +219,10 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
     AFQ_RET(gemm<T>(g, st));
   }
   TraceScope tr(AFQ_PH_TAYLOR, st);
-  // U = B1 W  (FP64)
+  // U = B1 W  (FP64; the walkers' columns side by side as one n = nw ntot product)
   {
     GemmArgs<double> g = gemm_args<double>();
-    g.m = M; g.n = ntot; g.k = M; g.batch = nw;
+    g.m = M; g.n = nw * ntot; g.k = M; g.vn = ntot;
     g.A = s->kp_nk ? s->B1c.as<double>() : s->B1.as<double>(); g.lda = M; g.cA = s->kp_nk > 0; g.sA = 0;
     g.B = reinterpret_cast<const double*>(Win); g.ldb = ntot; g.cB = true; g.sB = per;
     g.C = w->u.as<double>(); g.ldc = ntot; g.cC = true; g.sC = per;
@@ -251,7 +252,7 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
   // W' = B1 U
   {
     GemmArgs<double> g = gemm_args<double>();
-    g.m = M; g.n = ntot; g.k = M; g.batch = nw;
+    g.m = M; g.n = nw * ntot; g.k = M; g.vn = ntot;
     g.A = s->kp_nk ? s->B1c.as<double>() : s->B1.as<double>(); g.lda = M; g.cA = s->kp_nk > 0; g.sA = 0;
     g.B = w->u.as<double>(); g.ldb = ntot; g.cB = true; g.sB = per;
     g.C = reinterpret_cast<double*>(Wout); g.ldc = ntot; g.cC = true; g.sC = per;
