@@ -6,7 +6,7 @@
 //   * Cholesky factor R of a Hermitian Gram matrix W^H W and its inverse, for
 //     CholeskyQR (Q = W R^-1, det R > 0).
 // Pivot rows are tracked implicitly (no physical swaps); the pivot row and
-// column are broadcast through LDS, three barriers per elimination step.
+// column are broadcast through LDS, two barriers per elimination step.
 #include "common.h"
 
 namespace {
@@ -39,64 +39,21 @@ struct SlotMap {
   __device__ int col(int e, int r) const { return e - r * n; }
 };
 
-// Gauss-Jordan elimination on the register-resident matrix. pivoting=false
-// takes pivot row k at step k (used for the triangular factor of QR). With
-// FULL=false only the determinant is wanted: each step updates just the rows
-// not yet used as pivots, right of the pivot column (an LU factorisation in
-// place, a third of the work); the matrix left behind is not an inverse.
-// (FULL is a template parameter so that each kernel carries one update loop.)
-template <int NT, int EPT, bool FULL>
-__device__ void gauss_jordan(double2 (&a)[EPT], int n, bool pivoting, GjShared<NT>& sh, double2& logdet) {
-  static_assert(EPT <= 32, "slot mask");
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// Gauss-Jordan inverse without pivoting (pivot row k at step k) on the
+// register-resident matrix, for the triangular factor of CholeskyQR (its
+// diagonal is positive; a zero or non-finite pivot flags the matrix singular
+// and is taken as 1). Two barriers per step: the pivot row and column are
+// broadcast through LDS, then every element is updated.
+template <int NT, int EPT>
+__device__ void gj_unpivoted(double2 (&a)[EPT], int n, GjShared<NT>& sh) {
+  const int tid = threadIdx.x;
   const SlotMap sm(n);
-  unsigned live = 0;   // bit j: slot j's row has not been a pivot row yet
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) live |= (sm.row(tid + NT * j) < n ? 1u : 0u) << j;
   for (int k = 0; k < n; ++k) {
-    int p = k;
-    if (pivoting) {
-      double best = -1.0;
-      int bi = 1 << 30;
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const int e = tid + NT * j, r = sm.row(e);
-        if (sm.col(e, r) == k && ((live >> j) & 1)) {
-          const double v = cabs2(a[j]);
-          if (v > best || (v == best && r < bi)) { best = v; bi = r; }
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-      }
-      if (lane == 0) { sh.red_v[wave] = best; sh.red_i[wave] = bi; }
-      __syncthreads();
-      if (tid == 0) {
-        double bv = sh.red_v[0];
-        int bx = sh.red_i[0];
-        for (int w = 1; w < NT / 64; ++w)
-          if (sh.red_v[w] > bv || (sh.red_v[w] == bv && sh.red_i[w] < bx)) { bv = sh.red_v[w]; bx = sh.red_i[w]; }
-        if (bx < 0 || bx >= n) {
-          // no usable pivot (non-finite column): take the first unused row, flag singular
-          bx = 0;
-          while (bx < n - 1 && sh.used[bx]) ++bx;
-          sh.sing = 1;
-        }
-        sh.p = bx;
-        sh.used[bx] = 1;
-        sh.perm[k] = bx;
-      }
-      __syncthreads();
-      p = sh.p;
-    }
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
       if (r < n) {
-        if (r == p) sh.rowp[c] = a[j];
+        if (r == k) sh.rowp[c] = a[j];
         if (c == k) sh.colk[r] = a[j];
       }
     }
@@ -108,31 +65,19 @@ __device__ void gauss_jordan(double2 (&a)[EPT], int n, bool pivoting, GjShared<N
       piv = make_double2(1.0, 0.0);
     }
     const double2 ipiv = cdiv(make_double2(1.0, 0.0), piv);
-    logdet = cadd(logdet, clog(piv));
-    if constexpr (FULL) {
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
-        if (r < n) {
-          const double2 rp = c == k ? ipiv : cmul(sh.rowp[c], ipiv);
-          if (r == p) {
-            a[j] = rp;
-          } else {
-            const double2 base = c == k ? make_double2(0.0, 0.0) : a[j];
-            a[j] = csub(base, cmul(sh.colk[r], rp));
-          }
+    for (int j = 0; j < EPT; ++j) {
+      const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
+      if (r < n) {
+        const double2 rp = c == k ? ipiv : cmul(sh.rowp[c], ipiv);
+        if (r == k) {
+          a[j] = rp;
+        } else {
+          const double2 base = c == k ? make_double2(0.0, 0.0) : a[j];
+          a[j] = csub(base, cmul(sh.colk[r], rp));
         }
       }
-    } else {
-#pragma unroll
-      for (int j = 0; j < EPT; ++j) {
-        const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
-        if (((live >> j) & 1) && r != p && c > k) a[j] = csub(a[j], cmul(sh.colk[r], cmul(sh.rowp[c], ipiv)));
-      }
     }
-#pragma unroll
-    for (int j = 0; j < EPT; ++j)
-      if (sm.row(tid + NT * j) == p) live &= ~(1u << j);
     __syncthreads();
   }
 }
@@ -335,7 +280,7 @@ __global__ __launch_bounds__(NT) void chol_inv_kernel(const double2* __restrict_
     }
     __syncthreads();
     const double d = sh.d, id = 1.0 / d;
-    ldr += log(d);
+    if (tid == 0) ldr += log(d);   // only thread 0 reports it
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
       const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
@@ -357,8 +302,7 @@ __global__ __launch_bounds__(NT) void chol_inv_kernel(const double2* __restrict_
     if (r < n && r > sm.col(e, r)) a[j] = make_double2(0.0, 0.0);
   }
   __syncthreads();
-  double2 ld = make_double2(0.0, 0.0);
-  gauss_jordan<NT, EPT, true>(a, n, false, sh, ld);
+  gj_unpivoted<NT, EPT>(a, n, sh);
   if (tid == 0) {
     logdet[b * ld_logdet] = make_double2(ldr, 0.0);
     sing[b * ld_sing] = sh.sing;

@@ -269,17 +269,27 @@ __global__ void pack_cols_kernel(const double* __restrict__ src, long ncol, int 
 }
 
 // V[w][m][n] (complex FP64) -> the packed term layout of walker w: element
-// (n, 2m + part) at ((m / 8) y_rows + n) 16 + 2 (m % 8) + part
-__global__ void pack_terms_kernel(const double2* __restrict__ V, int nw, int M, int ntot, long y_rows, long y_wstride,
-                                  float* __restrict__ out) {
-  const long total = (long)nw * M * ntot;
-  for (long t = blockIdx.x * 256L + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
-    const long w = t / ((long)M * ntot), rem = t - w * M * ntot;
-    const int m = (int)(rem / ntot), n = (int)(rem - (long)m * ntot);
-    const double2 v = V[t];
-    *reinterpret_cast<float2*>(out + w * y_wstride + ((long)(m >> 3) * y_rows + n) * RK + 2 * (m & 7)) =
-        make_float2((float)v.x, (float)v.y);
+// (n, 2m + part) at ((m / 8) y_rows + n) 16 + 2 (m % 8) + part. A workgroup
+// moves an 8 (m) x 32 (n) tile through LDS so that both the reads (along n)
+// and the writes (8 consecutive m of one packed row) are contiguous.
+__global__ __launch_bounds__(256) void pack_terms_kernel(const double2* __restrict__ V, int M, int ntot, long y_rows,
+                                                         long y_wstride, float* __restrict__ out) {
+  __shared__ float2 tile[8][33];
+  const int t = threadIdx.x, n0 = blockIdx.x * 32, m0 = blockIdx.y * 8, w = blockIdx.z;
+  {
+    const int m = m0 + (t >> 5), n = n0 + (t & 31);
+    float2 v = make_float2(0.f, 0.f);
+    if (m < M && n < ntot) {
+      const double2 d = V[((long)w * M + m) * ntot + n];
+      v = make_float2((float)d.x, (float)d.y);
+    }
+    tile[t >> 5][t & 31] = v;
   }
+  __syncthreads();
+  const int n = n0 + (t >> 3), e = t & 7, m = m0 + e;
+  if (m < M && n < ntot)
+    *reinterpret_cast<float2*>(out + (long)w * y_wstride + ((long)(m0 >> 3) * y_rows + n) * RK + 2 * e) =
+        tile[e][t >> 3];
 }
 
 // tro[w][spin][n] = sum over runs (fixed order) of (part[run][2w][n], part[run][2w + 1][n])
@@ -445,8 +455,8 @@ int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st) {
             AFQ_E_STATE, "Taylor propagator (FP32 ring): walker scratch not prepared");
   if (order < 1) return AFQ_OK;
   float* V = w->r32_y[0].as<float>();
-  hipLaunchKernelGGL(pack_terms_kernel, dim3(grid_of((long)w->nw * s->M * s->ntot)), dim3(256), 0, st,
-                     w->u.as<double2>(), w->nw, s->M, s->ntot, ts.y_rows, ts.y_wstride, V);
+  hipLaunchKernelGGL(pack_terms_kernel, dim3(ceil_div(s->ntot, 32), ceil_div(s->M, 8), w->nw), dim3(256), 0, st,
+                     w->u.as<double2>(), s->M, s->ntot, ts.y_rows, ts.y_wstride, V);
   AFQ_TRY_HIP(hipGetLastError());
   const float* in = V;
   for (int j = order; j >= 1; --j) {
