@@ -118,6 +118,8 @@ struct afq_system_s {
   bool real_trial = true;
   DevBuf h1, chol, phi;        // f64 inputs (phi complex M x ntot)
   DevBuf chol32t;              // reduced modes: L as FP32 packed rows e of [n / 16][e][n % 16] (FP32 ring)
+  DevBuf b1x;                  // reduced modes: (B1 - I) FP32 packed rows m, for W + (B1 - I) W
+  double b1x_dt = -1.0;
   DevBuf lt32[2];              // split-BF16x3, real trial: Lt rows n of each spin, FP32 packed [J / 16][n][J % 16]
   DevBuf hp;                   // h' = h - 1/2 sum L L   (M x M f64)
   DevBuf B1;                   // exp(-dt h'/2)          (M x M f64)
@@ -231,6 +233,7 @@ struct afq_walkers_s {
   DevBuf r32_coef, r32_theta, r32_part;
   DevBuf r32_x;                // real form of A_w, packed for the Taylor products
   DevBuf r32_y[3];             // packed Taylor terms: V, then two alternating Horner terms
+  DevBuf r32_b1w;              // walker rows (n, Re|Im) packed for the B1 products
   // four-index exchange scratch
   DevBuf eri_theta;            // packed Theta-hat hi / lo planes of one spin
   DevBuf eri_part;             // per (work unit, column) complex partial sums
@@ -326,6 +329,10 @@ bool r32_taylor_used(afq_system s);
 int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st);
 // w->u <- sum_{j <= order} A_w^j u / j! (Horner form, A_w from r32_abuild)
 int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st);
+// (B1 - I) packed for the current B1 (no-op when up to date)
+int r32_prepare_b1(afq_system s);
+// out = B1 in = in + (B1 - I) in for every walker (M x n_tot complex FP64 each)
+int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStream_t st);
 // tro[w][spin][n] = tr(Lt^{n,spin} Theta^spin) from the FP32 operands
 int r32_coulomb(afq_system s, afq_walkers w, hipStream_t st);
 

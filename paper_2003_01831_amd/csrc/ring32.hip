@@ -12,6 +12,10 @@
 //     of A, so row n of the output is [Re, Im] of (A h)[m][n] over columns
 //     2m + part; intermediate terms V + A h / j stay FP32 in the packed layout,
 //     the last one is added to V in FP64;
+//   * the products B1 W and B1 U of the propagator as W + (B1 - I) W: the
+//     correction (B1 - I = O(dt h')) in FP32, walker rows (n, Re|Im) against
+//     rows m of B1 - I, added to W in FP64, so the product keeps FP64-class
+//     accuracy;
 //   * the force-bias traces tr(Lt^{ns} Theta^s) = sum_(a,k) Theta-hat[(a,k)] Lt_n[a][k]
 //     (split-BF16x3 mode, real trial): Theta-hat rows (w, Re|Im) times the
 //     real half-rotated vectors, packed once per system; the N M contraction is
@@ -50,7 +54,7 @@ template <int TA_, int TB_> struct Geo {
 using GeoAB = Geo<8, 4>;   // propagator build, force bias
 using GeoTY = Geo<7, 5>;   // Taylor products
 
-enum { EPI_XFORM = 0, EPI_PART = 1, EPI_HORNER = 2 };
+enum { EPI_XFORM = 0, EPI_PART = 1, EPI_HORNER = 2, EPI_B1 = 3 };
 
 struct R32Args {
   const unsigned char* a;   // packed A: [chunk][rows_a][16] float (per batch member at a_bstride bytes)
@@ -73,6 +77,9 @@ struct R32Args {
   int last;
   long y_rows, y_wstride;
   int ntot;
+  // EPI_B1: A rows (n, Re|Im) of a walker, B rows m of (B1 - I):
+  // u[w][m][n] = ubase[w][m][n] + ((B1 - I) W)[m][n]
+  const double2* ubase;
 };
 
 template <class G, int EPI>
@@ -195,6 +202,24 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
           const long col = brow0 + brow + 16 * j + lr;
           out[row * g.rows_b + col] = acc[i][j][v];
         }
+  } else if constexpr (EPI == EPI_B1) {
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        const long n0 = (arow0 + arow + 16 * i + 4 * lq) >> 1;   // rows (n0, Re), (n0, Im), (n0 + 1, Re), (n0 + 1, Im)
+        const long m = brow0 + brow + 16 * j + lr;
+        if (m >= g.M) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const long n = n0 + h;
+          if (n < g.ntot) {
+            const long idx = ((long)batch * g.M + m) * g.ntot + n;
+            const double2 v = g.ubase[idx];
+            g.u[idx] = make_double2(v.x + (double)acc[i][j][2 * h], v.y + (double)acc[i][j][2 * h + 1]);
+          }
+        }
+      }
   } else {
     // column 2m + part of row n is part (Re, Im) of (A h)[m][n]: the partner
     // lane lr ^ 1 holds the other part; even lanes finish rows 0, 1 of their
@@ -292,6 +317,41 @@ __global__ __launch_bounds__(256) void pack_terms_kernel(const double2* __restri
         tile[e][t >> 3];
 }
 
+// W[w][k][n] (complex FP64) -> rows (n, Re|Im) of walker w, k-contiguous:
+// component part of W[k][n] at ((k / 16) rows + 2n + part) 16 + k % 16, zero for
+// k >= M. A workgroup moves a 16 (k) x 16 (n) tile through LDS.
+__global__ __launch_bounds__(256) void pack_walker_rows_kernel(const double2* __restrict__ W, int M, int ntot, long rows,
+                                                               long wstride, float* __restrict__ out) {
+  __shared__ float2 tile[16][17];
+  const int t = threadIdx.x, n0 = blockIdx.x * 16, k0 = blockIdx.y * 16, w = blockIdx.z;
+  {
+    const int k = k0 + (t >> 4), n = n0 + (t & 15);
+    float2 v = make_float2(0.f, 0.f);
+    if (k < M && n < ntot) {
+      const double2 d = W[((long)w * M + k) * ntot + n];
+      v = make_float2((float)d.x, (float)d.y);
+    }
+    tile[t >> 4][t & 15] = v;
+  }
+  __syncthreads();
+  const int r = t >> 3, kp = t & 7, j = r >> 1, part = r & 1, n = n0 + j;
+  if (n < ntot) {
+    const float2 a = tile[2 * kp][j], b = tile[2 * kp + 1][j];
+    *reinterpret_cast<float2*>(out + (long)w * wstride + (((long)(k0 >> 4) * rows + 2 * n + part) * RK) + 2 * kp) =
+        part ? make_float2(a.y, b.y) : make_float2(a.x, b.x);
+  }
+}
+
+// (B1 - I) as rows m, k-contiguous: out[((k / 16) rows + m) 16 + k % 16]
+__global__ void pack_b1_kernel(const double* __restrict__ B1, int M, long rows, int nchunk, float* __restrict__ out) {
+  const long total = (long)nchunk * rows * RK;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const long c = e / (rows * RK), rem = e - c * rows * RK;
+    const long m = rem / RK, k = c * RK + (rem - m * RK);
+    out[e] = (m < M && k < M) ? (float)(B1[m * M + k] - (m == k ? 1.0 : 0.0)) : 0.f;
+  }
+}
+
 // tro[w][spin][n] = sum over runs (fixed order) of (part[run][2w][n], part[run][2w + 1][n])
 __global__ void coulomb_reduce_kernel(const float* __restrict__ part, int nrun, long rows_a, long rows_b, int nw,
                                       int X, int spin, double2* __restrict__ tro) {
@@ -350,9 +410,58 @@ TaylorShape taylor_shape(afq_system s) {
   return t;
 }
 
+// walker rows (n, Re|Im) against rows m of B1 - I
+struct B1Shape {
+  long a_rows, b_rows, kchunk, a_wstride;
+};
+B1Shape b1_shape(afq_system s) {
+  B1Shape b;
+  b.a_rows = pad_to(2L * s->ntot, GeoTY::RA);
+  b.b_rows = pad_to(s->M, GeoTY::RB);
+  b.kchunk = pad_to(s->M, RK) / RK;
+  b.a_wstride = b.a_rows * b.kchunk * RK;
+  return b;
+}
+
 }  // namespace
 
 bool r32_coulomb_used(afq_system s) { return s->lt32[0].p != nullptr; }
+
+int r32_prepare_b1(afq_system s) {
+  if (!s->chol32t.p || !s->B1.p || s->b1x_dt == s->B1_dt) return AFQ_OK;
+  const B1Shape b = b1_shape(s);
+  AFQ_RET(s->b1x.alloc((size_t)b.kchunk * b.b_rows * RK * sizeof(float)));
+  hipLaunchKernelGGL(pack_b1_kernel, dim3(grid_of(b.kchunk * b.b_rows * RK)), dim3(256), 0, s->stream,
+                     s->B1.as<double>(), s->M, b.b_rows, (int)b.kchunk, s->b1x.as<float>());
+  AFQ_TRY_HIP(hipGetLastError());
+  s->b1x_dt = s->B1_dt;
+  return AFQ_OK;
+}
+
+int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStream_t st) {
+  const B1Shape b = b1_shape(s);
+  AFQ_CHECK(s->b1x.p && s->b1x_dt == s->B1_dt && w->r32_b1w.bytes >= (size_t)w->nw * b.a_wstride * sizeof(float),
+            AFQ_E_STATE, "B1 product (FP32 ring): operands not prepared");
+  hipLaunchKernelGGL(pack_walker_rows_kernel, dim3(ceil_div(s->ntot, 16), ceil_div(s->M, 16), w->nw), dim3(256), 0,
+                     st, in, s->M, s->ntot, b.a_rows, b.a_wstride, w->r32_b1w.as<float>());
+  AFQ_TRY_HIP(hipGetLastError());
+  R32Args g{};
+  g.a = w->r32_b1w.as<unsigned char>();
+  g.b = s->b1x.as<unsigned char>();
+  g.rows_a = b.a_rows;
+  g.rows_b = b.b_rows;
+  g.a_bstride = b.a_wstride * (long)sizeof(float);
+  g.b_bstride = 0;
+  g.nchunk = (int)b.kchunk;
+  g.kper = (int)b.kchunk;
+  g.nbatch = w->nw;
+  g.a_fast = 1;
+  g.u = out;
+  g.ubase = in;
+  g.M = s->M;
+  g.ntot = s->ntot;
+  return launch<GeoTY, EPI_B1>(g, st);
+}
 bool r32_taylor_used(afq_system s) { return s->chol32t.p != nullptr; }
 
 int r32_prepare(afq_system s) {
@@ -385,7 +494,11 @@ int r32_prepare(afq_system s) {
     s->lt32[1].free();
   }
   if (!reduced && s->chol32t.p) s->chol32t.free();
-  return AFQ_OK;
+  if (!reduced) {
+    s->b1x.free();
+    s->b1x_dt = -1.0;
+  }
+  return r32_prepare_b1(s);
 }
 
 // The packed buffers are cleared when allocated: their padding rows and
@@ -405,6 +518,7 @@ int r32_alloc_scratch(afq_system s, afq_walkers w) {
   const TaylorShape ts = taylor_shape(s);
   AFQ_RET(alloc_cleared(w->r32_x, (size_t)w->nw * ts.x_wstride * sizeof(float), st));
   for (int i = 0; i < 3; ++i) AFQ_RET(alloc_cleared(w->r32_y[i], (size_t)w->nw * ts.y_wstride * sizeof(float), st));
+  AFQ_RET(alloc_cleared(w->r32_b1w, (size_t)w->nw * b1_shape(s).a_wstride * sizeof(float), st));
   if (!s->lt32[0].p) return AFQ_OK;
   size_t tb = 0, pb = 0;
   for (int sp = 0; sp < 2; ++sp) {

@@ -115,8 +115,9 @@ int system_prepare_dt(afq_system s, double dt) {
     std::swap(cur, nxt);
   }
   AFQ_RET(copy_d(cur, s->B1.as<double>(), (long)mm, st));
-  AFQ_TRY_HIP(hipStreamSynchronize(st));
   s->B1_dt = dt;
+  AFQ_RET(r32_prepare_b1(s));
+  AFQ_TRY_HIP(hipStreamSynchronize(st));
   return AFQ_OK;
 }
 

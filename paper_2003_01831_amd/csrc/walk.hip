@@ -219,8 +219,11 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
     AFQ_RET(gemm<T>(g, st));
   }
   TraceScope tr(AFQ_PH_TAYLOR, st);
+  const bool ring = sizeof(T) == 4 && s->kp_nk == 0 && r32_taylor_used(s);
   // U = B1 W  (FP64; the walkers' columns side by side as one n = nw ntot product)
-  {
+  if (ring) {   // reduced modes: W + (B1 - I) W with the correction on the FP32 ring
+    AFQ_RET(r32_b1(s, w, Win, w->u.as<double2>(), st));
+  } else {
     GemmArgs<double> g = gemm_args<double>();
     g.m = M; g.n = nw * ntot; g.k = M; g.vn = ntot;
     g.A = s->kp_nk ? s->B1c.as<double>() : s->B1.as<double>(); g.lda = M; g.cA = s->kp_nk > 0; g.sA = 0;
@@ -228,7 +231,7 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
     g.C = w->u.as<double>(); g.ldc = ntot; g.cC = true; g.sC = per;
     AFQ_RET(gemm<double>(g, st));
   }
-  if (sizeof(T) == 4 && s->kp_nk == 0 && r32_taylor_used(s)) {
+  if (ring) {
     // reduced modes: U <- T_K(A) U in Horner form on the FP32 ring kernel
     AFQ_RET(r32_taylor(s, w, order, st));
   } else {
@@ -250,7 +253,9 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
     }
   }
   // W' = B1 U
-  {
+  if (ring) {
+    AFQ_RET(r32_b1(s, w, w->u.as<double2>(), Wout, st));
+  } else {
     GemmArgs<double> g = gemm_args<double>();
     g.m = M; g.n = nw * ntot; g.k = M; g.vn = ntot;
     g.A = s->kp_nk ? s->B1c.as<double>() : s->B1.as<double>(); g.lda = M; g.cA = s->kp_nk > 0; g.sA = 0;
