@@ -25,6 +25,7 @@ struct afq_batch_s {
   std::vector<double> e_shift;
   std::vector<double> caps;   // (fb_cap, w_cap) of every walker set, baked into the graph
   std::vector<unsigned> versions;   // the systems' kernel-sequence versions at capture
+  std::vector<char> carried_after;  // each walker set's carried-inverse flag after the captured cycle
   DevBuf emix_cycle;   // n x cycle, written by the graph
   ~afq_batch_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -91,8 +92,13 @@ int build_graph(afq_batch b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
+  // the captured cycle starts from a full overlap inverse, whatever the state
+  // of the walkers when it is replayed
+  for (auto w : b->wk) w->s_carried = false;
   AFQ_TRY_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
   const int rc = enqueue_steps(b, b->cap, b->cycle, true, nullptr, 0, 0);
+  b->carried_after.clear();
+  for (auto w : b->wk) b->carried_after.push_back(w->s_carried);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(b->cap, &g);
   AFQ_RET(rc);
@@ -205,6 +211,7 @@ int batch_step_impl(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_e
         AFQ_RET(build_graph(b));
       }
       AFQ_TRY_HIP(hipGraphLaunch(b->exec, b->origin));
+      for (size_t i = 0; i < b->wk.size(); ++i) b->wk[i]->s_carried = b->carried_after[i];
       if (emix_out) {
         const int tot = n * b->cycle;
         hipLaunchKernelGGL(scatter_emix, dim3(ceil_div(tot, 256)), dim3(256), 0, b->origin,

@@ -94,6 +94,7 @@ int bp_comb_gather(afq_walkers w, const int* src) {
 }
 
 int bp_rdm1(afq_walkers w, int qr_every, double* rdm_out, double* wsum_out) {
+  w->s_carried = false;   // S, S^-1 and the log dets are scratch here
   afq_system s = w->sys;
   AFQ_CHECK(w->bp_n >= 0, AFQ_E_STATE, "afq_bp_rdm1: no back-propagation window is open");
   AFQ_CHECK(w->bp_rec == w->bp_n, AFQ_E_STATE,

@@ -129,6 +129,7 @@ int afq_walkers_set(afq_walkers w, const double* W, const double* weights, const
     hipStream_t st = s->stream;
     const size_t per = (size_t)s->M * s->ntot;
     if (W) AFQ_TRY_HIP(hipMemcpyAsync(w->W.p, W, w->nw * per * 16, hipMemcpyDeviceToDevice, st));
+    w->s_carried = false;
     if (weights) AFQ_TRY_HIP(hipMemcpyAsync(w->weights.p, weights, w->nw * 8, hipMemcpyDeviceToDevice, st));
     if (alive) AFQ_TRY_HIP(hipMemcpyAsync(w->alive.p, alive, w->nw * 4, hipMemcpyDeviceToDevice, st));
     AFQ_RET(counter_set(w->d_counter.as<uint64_t>(), counter, st));

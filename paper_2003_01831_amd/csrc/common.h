@@ -200,6 +200,8 @@ struct afq_walkers_s {
   DevBuf bp_stats;             // 2 doubles: sum of weights, singular count
   // per-step scratch
   DevBuf S, Sinv, SinvT;       // per (w, spin): n x n complex (max n^2 stride); SinvT = (S^-1)^T
+  DevBuf Sinv_new;             // S^-1 of the propagated walkers (carried to the next step)
+  bool s_carried = false;      // Sinv and logdet are those of the current W (set by a step's weight phase)
   DevBuf logdet, logdet_new;   // nw x 2 complex
   DevBuf sing;                 // nw x 2 int
   DevBuf theta;                // nw x M x ntot complex

@@ -39,6 +39,12 @@ struct WeightArgs {
   double2* W;                 // nw x per
   const double2* Wn;          // nw x per
   long per;
+  // optional: with W also copy S^-1 (sinv_per elements per walker) and the log
+  // det of the propagated walkers (sinv_new, logdet_new -> sinv, logdet_keep)
+  double2* sinv;
+  const double2* sinv_new;
+  double2* logdet_keep;
+  long sinv_per;
 };
 
 int pack_a(int prec, const double2* Lt, int X, int ntot, int M, int off, const PackShape& ps, bool real_trial,

@@ -440,6 +440,10 @@ __global__ __launch_bounds__(256) void weight_kernel(WeightArgs a) {
   if (!commit) return;
   const long per = a.per;
   for (long i = t; i < per; i += 256) a.W[w * per + i] = a.Wn[w * per + i];
+  if (a.sinv) {
+    for (long i = t; i < a.sinv_per; i += 256) a.sinv[w * a.sinv_per + i] = a.sinv_new[w * a.sinv_per + i];
+    if (t < 2) a.logdet_keep[2 * w + t] = a.logdet_new[2 * w + t];
+  }
 }
 int launch_weights(const WeightArgs& a, int nw, hipStream_t st) {
   hipLaunchKernelGGL(weight_kernel, dim3(nw), dim3(256), 0, st, a);

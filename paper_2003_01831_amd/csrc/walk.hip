@@ -24,6 +24,7 @@ int walkers_alloc_scratch(afq_walkers w) {
     AFQ_RET(w->S.alloc((size_t)nw * 2 * nmax * nmax * 16));
     AFQ_RET(w->Sinv.alloc((size_t)nw * 2 * nmax * nmax * 16));
     AFQ_RET(w->SinvT.alloc((size_t)nw * 2 * nmax * nmax * 16));
+    AFQ_RET(w->Sinv_new.alloc((size_t)nw * 2 * nmax * nmax * 16));
     AFQ_RET(w->logdet.alloc((size_t)nw * 2 * 16));
     AFQ_RET(w->logdet_new.alloc((size_t)nw * 2 * 16));
     AFQ_RET(w->sing.alloc((size_t)nw * 2 * sizeof(int)));
@@ -56,8 +57,8 @@ int walkers_alloc_scratch(afq_walkers w) {
   return AFQ_OK;
 }
 
-// S^s = T^sH W^s for every walker; S^-1 (optional) and log det; Theta^T = S^-T W^T
-int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool want_theta, double2* logdet_out) {
+// S^s = T^sH W^s for every walker; S^-1 into inv (optional) and log det
+static int overlap_inverse(afq_system s, afq_walkers w, const double2* Wsrc, double2* inv, double2* logdet_out) {
   hipStream_t st = s->stream;
   const int M = s->M, ntot = s->ntot, nw = w->nw;
   const int nmax = std::max(s->n_up, s->n_dn);
@@ -75,22 +76,38 @@ int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool
     g.B = reinterpret_cast<const double*>(Wsrc) + 2 * off; g.ldb = ntot; g.cB = true; g.sB = (long)M * ntot;
     g.C = w->S.as<double>() + 2 * sp * nm2; g.ldc = n; g.cC = true; g.sC = 2 * nm2;
     AFQ_RET(gemm<double>(g, st));
-    AFQ_RET(lu_inverse(w->S.as<double2>() + sp * nm2, 2 * nm2, n, nw,
-                       want_theta ? w->Sinv.as<double2>() + sp * nm2 : nullptr, logdet_out + sp, 2,
-                       w->sing.as<int>() + sp, 2, st));
-    if (want_theta) {
-      // thetaT[w][off + b][k] = sum_j (S^-1)^T[b][j] W[k][off + j]  (both operands k-contiguous)
-      AFQ_RET(transpose_batched(w->Sinv.as<double2>() + sp * nm2, 2 * nm2, n, nw, w->SinvT.as<double2>() + sp * nm2,
-                                st));
-      GemmArgs<double> t = gemm_args<double>();
-      t.m = n; t.n = M; t.k = n; t.batch = nw;
-      t.A = w->SinvT.as<double>() + 2 * sp * nm2; t.lda = n; t.cA = true; t.sA = 2 * nm2;
-      t.B = reinterpret_cast<const double*>(Wsrc) + 2 * off; t.ldb = ntot; t.opB = OP_T; t.cB = true;
-      t.sB = (long)M * ntot;
-      t.C = w->theta.as<double>() + 2 * (long)off * M; t.ldc = M; t.cC = true; t.sC = (long)ntot * M;
-      AFQ_RET(gemm<double>(t, st));
-    }
+    AFQ_RET(lu_inverse(w->S.as<double2>() + sp * nm2, 2 * nm2, n, nw, inv ? inv + sp * nm2 : nullptr,
+                       logdet_out + sp, 2, w->sing.as<int>() + sp, 2, st));
   }
+  return AFQ_OK;
+}
+
+// Theta^T from w->Sinv: thetaT[w][off + b][k] = sum_j (S^-1)^T[b][j] W[k][off + j]
+// (both operands k-contiguous)
+static int theta_from_inverse(afq_system s, afq_walkers w, const double2* Wsrc) {
+  hipStream_t st = s->stream;
+  const int M = s->M, ntot = s->ntot, nw = w->nw;
+  const int nmax = std::max(s->n_up, s->n_dn);
+  const long nm2 = (long)nmax * nmax;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = s->nspin_n(sp), off = s->spin_off(sp);
+    AFQ_RET(transpose_batched(w->Sinv.as<double2>() + sp * nm2, 2 * nm2, n, nw, w->SinvT.as<double2>() + sp * nm2,
+                              st));
+    GemmArgs<double> t = gemm_args<double>();
+    t.m = n; t.n = M; t.k = n; t.batch = nw;
+    t.A = w->SinvT.as<double>() + 2 * sp * nm2; t.lda = n; t.cA = true; t.sA = 2 * nm2;
+    t.B = reinterpret_cast<const double*>(Wsrc) + 2 * off; t.ldb = ntot; t.opB = OP_T; t.cB = true;
+    t.sB = (long)M * ntot;
+    t.C = w->theta.as<double>() + 2 * (long)off * M; t.ldc = M; t.cC = true; t.sC = (long)ntot * M;
+    AFQ_RET(gemm<double>(t, st));
+  }
+  return AFQ_OK;
+}
+
+// S^s = T^sH W^s for every walker; S^-1 (optional) and log det; Theta^T = S^-T W^T
+int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool want_theta, double2* logdet_out) {
+  AFQ_RET(overlap_inverse(s, w, Wsrc, want_theta ? w->Sinv.as<double2>() : nullptr, logdet_out));
+  if (want_theta) AFQ_RET(theta_from_inverse(s, w, Wsrc));
   return AFQ_OK;
 }
 
@@ -307,6 +324,7 @@ int qr_orbitals(afq_system s, afq_walkers w, const double2* src0, double2* mid, 
 
 // QR of the live walkers: W -> Wn -> u, then u back into W where alive
 static int qr_walkers(afq_system s, afq_walkers w) {
+  w->s_carried = false;   // W changes
   TraceScope tr(AFQ_PH_QR, s->stream);
   AFQ_RET(qr_orbitals(s, w, w->W.as<double2>(), w->Wn.as<double2>(), w->u.as<double2>()));
   return masked_copy(w->u.as<double2>(), w->W.as<double2>(), (long)s->M * s->ntot, w->nw, w->alive.as<int>(),
@@ -318,10 +336,14 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
               double* weights_out, double* ratio_out, void* coef_record) {
   hipStream_t st = s->stream;
   const int nw = w->nw;
-  // overlap, Theta and the energy at the start-of-step walkers
+  // overlap, Theta and the energy at the start-of-step walkers; S^-1 and log det
+  // are still those the previous step's weight phase carried over with W
+  // unless something has changed W since
   {
     TraceScope t(AFQ_PH_OVERLAP, st);
-    AFQ_RET(compute_overlap_theta(s, w, w->W.as<double2>(), true, w->logdet.as<double2>()));
+    if (!w->s_carried || s->msd_n > 0)   // a multi-determinant trial leaves its own overlap in logdet
+      AFQ_RET(overlap_inverse(s, w, w->W.as<double2>(), w->Sinv.as<double2>(), w->logdet.as<double2>()));
+    AFQ_RET(theta_from_inverse(s, w, w->W.as<double2>()));
   }
   AssembleArgs a{};
   a.dt = dt;
@@ -340,10 +362,17 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
     AFQ_RET(launch_emix(w->eloc.as<double2>(), w->weights.as<double>(), nw, emix_out, st));
   }
   AFQ_RET(propagate_walkers(s, w, order, w->coef.p, w->W.as<double2>(), w->Wn.as<double2>()));
-  // new overlap (log det only) and the phaseless weight
+  // new overlap and the phaseless weight. Without a multi-determinant trial
+  // and QR at the end of the step the full inverse of the new overlap is
+  // formed (hardly dearer than its determinant) and carried to the next step
+  // with the walkers the weight kernel keeps.
+  const bool carry = s->msd_n == 0 && !do_qr;
   {
     TraceScope tw(AFQ_PH_WEIGHT, st);
-    AFQ_RET(compute_overlap_theta(s, w, w->Wn.as<double2>(), s->msd_n > 0, w->logdet_new.as<double2>()));
+    if (carry)
+      AFQ_RET(overlap_inverse(s, w, w->Wn.as<double2>(), w->Sinv_new.as<double2>(), w->logdet_new.as<double2>()));
+    else
+      AFQ_RET(compute_overlap_theta(s, w, w->Wn.as<double2>(), s->msd_n > 0, w->logdet_new.as<double2>()));
     if (s->msd_n > 0) AFQ_RET(msd_overlap(s, w, w->logdet_new.as<double2>(), st));
     WeightArgs wa{};
     wa.logdet_new = w->logdet_new.as<double2>();
@@ -361,8 +390,16 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
     wa.W = w->W.as<double2>();
     wa.Wn = w->Wn.as<double2>();
     wa.per = (long)s->M * s->ntot;
+    if (carry) {
+      const int nmax = std::max(s->n_up, s->n_dn);
+      wa.sinv = w->Sinv.as<double2>();
+      wa.sinv_new = w->Sinv_new.as<double2>();
+      wa.logdet_keep = w->logdet.as<double2>();
+      wa.sinv_per = 2L * nmax * nmax;
+    }
     AFQ_RET(launch_weights(wa, nw, st));
   }
+  w->s_carried = carry;
   if (do_qr) AFQ_RET(qr_walkers(s, w));
   return AFQ_OK;
 }
@@ -430,6 +467,7 @@ int walkers_comb(afq_walkers w, double xi, int* src_out, double* total_out) {
   AFQ_RET(launch_comb_apply(w->W.as<double2>(), w->Wn.as<double2>(), per, nw, w->comb_src.as<int>(),
                             w->comb_out.as<double>(), w->weights.as<double>(), w->alive.as<int>(), st));
   AFQ_TRY_HIP(hipMemcpyAsync(w->W.p, w->Wn.p, (size_t)nw * per * 16, hipMemcpyDeviceToDevice, st));
+  w->s_carried = false;
   AFQ_RET(bp_comb_gather(w, w->comb_src.as<int>()));
   if (src_out) {
     AFQ_TRY_HIP(hipMemcpyAsync(src_out, w->comb_src.p, (size_t)nw * sizeof(int), hipMemcpyDeviceToHost, st));
