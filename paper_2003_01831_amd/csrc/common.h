@@ -117,7 +117,8 @@ struct afq_system_s {
   int device = 0;
   bool real_trial = true;
   DevBuf h1, chol, phi;        // f64 inputs (phi complex M x ntot)
-  DevBuf chol32t;              // reduced modes: L as FP32 packed rows e of [n / 16][e][n % 16] (FP32 ring)
+  DevBuf chol32t;              // reduced modes: upper block triangle of L as FP32 packed rows e of [n / 16][e][n % 16]
+  DevBuf tri8;                 // its 8 x 8 block pairs (bm << 16 | bk, bm <= bk), 64 rows e each (FP32 ring)
   DevBuf b1x;                  // reduced modes: (B1 - I) FP32 packed rows m, for W + (B1 - I) W
   double b1x_dt = -1.0;
   DevBuf lt32[2];              // split-BF16x3, real trial: Lt rows n of each spin, FP32 packed [J / 16][n][J % 16]

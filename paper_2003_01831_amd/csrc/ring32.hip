@@ -2,10 +2,12 @@
 // streamed through the three-stage direct global->LDS ring:
 //
 //   * the propagator matrices A_w = sum_n c_wn L^n: coefficient rows
-//     (w, Re|Im) times the Cholesky vectors, which are packed once per system
-//     k-contiguous (entry e of L^n at [n / 16][e][n % 16]); the epilogue writes
-//     A_w in real form, rows (m, Re) = [Re A, -Im A] and (m, Im) = [Im A, Re A]
-//     interleaved over k, packed k-contiguous for the Taylor products;
+//     (w, Re|Im) times the upper block triangle of the symmetric Cholesky
+//     vectors (8 x 8 block pairs, half the M^2 columns), packed once per system
+//     k-contiguous (entry e at [n / 16][e][n % 16]); the epilogue writes each
+//     block of the complex symmetric A_w and its mirror in real form, rows
+//     (m, Re) = [Re A, -Im A] and (m, Im) = [Im A, Re A] interleaved over k,
+//     packed k-contiguous for the Taylor products;
 //   * the Taylor propagator in Horner form, U = V + A (V + A/2 (... (V + A V/K))),
 //     V = B1 W: every product is the real contraction of the walker columns
 //     (rows n of the packed term, Re/Im interleaved over k) with the real form
@@ -63,7 +65,10 @@ struct R32Args {
   int nchunk, kper, nblk_a, nblk_b, nbatch;
   int nunit, grid;          // units = A row blocks x contraction runs; grid = batch x units x B blocks
   int a_fast;               // 1: consecutive workgroups take consecutive A row blocks (sharing a B block)
-  // EPI_XFORM: A rows (w, Re|Im), B rows e = m M + k -> real form of A_w at x + w x_wstride
+  // EPI_XFORM: A rows (w, Re|Im), B rows e = 64 p + 8 mi + ki of block pair p = (bm, bk)
+  // (tri[p] = bm << 16 | bk): m = 8 bm + mi, k = 8 bk + ki -> real form of A_w at
+  // x + w x_wstride, at (m, k) and, off the diagonal blocks, at (k, m)
+  const int* tri;
   float* x;
   long x_wstride, x_rows, ncol;
   int M, nw;
@@ -175,10 +180,16 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
 #pragma unroll
       for (int j = 0; j < TB; ++j) {
         const long row0 = arow0 + arow + 16 * i + 4 * lq;    // rows (w0, Re), (w0, Im), (w0 + 1, Re), (w0 + 1, Im)
-        const long col = brow0 + brow + 16 * j + lr;          // e = m M + k
+        const long col = brow0 + brow + 16 * j + lr;
         if (col >= g.ncol) continue;
-        const int m = (int)(col / g.M), k = (int)(col - (long)m * g.M);
+        // a wave's 64 columns are one block pair: the direct stores of 8
+        // neighbouring lanes fill one 64-byte packed row, the mirrored ones
+        // fill theirs over the wave's four column tiles
+        const int code = g.tri[col >> 6], bm = code >> 16, bk = code & 0xffff;
+        const int m = 8 * bm + (int)((col >> 3) & 7), k = 8 * bk + (int)(col & 7);
+        if (m >= g.M || k >= g.M) continue;
         const long o0 = ((long)(k >> 3) * g.x_rows + 2 * m) * RK + 2 * (k & 7);
+        const long o1 = ((long)(m >> 3) * g.x_rows + 2 * k) * RK + 2 * (m & 7);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int w = (int)(row0 >> 1) + h;
@@ -187,6 +198,10 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
             float* X = g.x + (long)w * g.x_wstride;
             *reinterpret_cast<float2*>(X + o0) = make_float2(ar, -ai);
             *reinterpret_cast<float2*>(X + o0 + RK) = make_float2(ai, ar);
+            if (bm != bk) {
+              *reinterpret_cast<float2*>(X + o1) = make_float2(ar, -ai);
+              *reinterpret_cast<float2*>(X + o1 + RK) = make_float2(ai, ar);
+            }
           }
         }
       }
@@ -280,15 +295,34 @@ __global__ void pack_real_rows_kernel(const double* __restrict__ src, long ld, i
   }
 }
 
-// columns of a row-major matrix as rows of a packed operand (the Cholesky
-// vectors, k = vector index): out[(c rows + e) 16 + kk] = src[(16 c + kk) ncol + e]
-__global__ void pack_cols_kernel(const double* __restrict__ src, long ncol, int K, long rows, int nchunk,
-                                 float* __restrict__ out) {
+// The 8 x 8 block pairs (bm, bk), bm <= bk, of an M x M symmetric matrix in
+// row order: tri[p] = bm << 16 | bk
+__global__ void tri_table_kernel(int nb, int nbp, int* __restrict__ tri) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (p >= nbp) return;
+  int bm = 0, r = p;
+  while (r >= nb - bm) {
+    r -= nb - bm;
+    ++bm;
+  }
+  tri[p] = bm << 16 | (bm + r);
+}
+
+// the upper block triangle of the symmetric L^n as rows of a packed operand
+// (k = vector index): row e = 64 p + 8 mi + ki of block pair p = (bm, bk) holds
+// (L^k[m][kk] + L^k[kk][m]) / 2, m = 8 bm + mi, kk = 8 bk + ki, zero outside
+__global__ void pack_tri_cols_kernel(const double* __restrict__ src, int M, int K, const int* __restrict__ tri,
+                                     long ncol, long rows, int nchunk, float* __restrict__ out) {
   const long total = (long)nchunk * rows * RK;
+  const long m2 = (long)M * M;
   for (long t = blockIdx.x * 256L + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
-    // consecutive threads read consecutive e of one vector
     const long k = t / rows, e = t - k * rows;
-    const float v = (k < K && e < ncol) ? (float)src[k * ncol + e] : 0.f;
+    float v = 0.f;
+    if (k < K && e < ncol) {
+      const int code = tri[e >> 6];
+      const int m = 8 * (code >> 16) + (int)((e >> 3) & 7), kk = 8 * (code & 0xffff) + (int)(e & 7);
+      if (m < M && kk < M) v = (float)(0.5 * (src[k * m2 + (long)m * M + kk] + src[k * m2 + (long)kk * M + m]));
+    }
     out[((k / RK) * rows + e) * RK + (k % RK)] = v;
   }
 }
@@ -396,6 +430,20 @@ int coulomb_kper(long nchunk, long rows_a, long rows_b) {
   return (int)((nchunk + nrun - 1) / nrun);
 }
 
+// columns of the propagator build: 64 per 8 x 8 block pair of the upper block triangle
+struct TriCols {
+  int nb, nbp;
+  long ncol, rows;
+};
+TriCols tri_cols(afq_system s) {
+  TriCols t;
+  t.nb = ceil_div(s->M, 8);
+  t.nbp = t.nb * (t.nb + 1) / 2;
+  t.ncol = 64L * t.nbp;
+  t.rows = pad_to(t.ncol, GeoAB::RB);
+  return t;
+}
+
 // packed real form of A_w (rows 2M, contraction 2M) and packed terms (rows n_tot)
 struct TaylorShape {
   long x_rows, y_rows, kchunk, x_wstride, y_wstride;   // strides in floats
@@ -468,12 +516,16 @@ int r32_prepare(afq_system s) {
   hipStream_t st = s->stream;
   const bool reduced = s->prec != AFQ_FP64 && s->kp_nk == 0;
   if (reduced && !s->chol32t.p) {
-    const long m2 = (long)s->M * s->M;
-    const long rows = pad_to(m2, GeoAB::RB);
+    const TriCols tc = tri_cols(s);
     const int nchunk = (int)pad_to(s->X, RK) / RK;
-    AFQ_RET(s->chol32t.alloc((size_t)nchunk * rows * RK * sizeof(float)));
-    hipLaunchKernelGGL(pack_cols_kernel, dim3(grid_of((long)nchunk * rows * RK)), dim3(256), 0, st,
-                       s->chol.as<double>(), m2, s->X, rows, nchunk, s->chol32t.as<float>());
+    AFQ_RET(s->tri8.alloc((size_t)tc.nbp * sizeof(int)));
+    hipLaunchKernelGGL(tri_table_kernel, dim3(ceil_div(tc.nbp, 256)), dim3(256), 0, st, tc.nb, tc.nbp,
+                       s->tri8.as<int>());
+    AFQ_TRY_HIP(hipGetLastError());
+    AFQ_RET(s->chol32t.alloc((size_t)nchunk * tc.rows * RK * sizeof(float)));
+    hipLaunchKernelGGL(pack_tri_cols_kernel, dim3(grid_of((long)nchunk * tc.rows * RK)), dim3(256), 0, st,
+                       s->chol.as<double>(), s->M, s->X, s->tri8.as<int>(), tc.ncol, tc.rows, nchunk,
+                       s->chol32t.as<float>());
     AFQ_TRY_HIP(hipGetLastError());
   }
   const bool coul = s->prec == AFQ_BF16X3 && s->real_trial && s->kp_nk == 0 && s->msd_n == 0;
@@ -493,7 +545,10 @@ int r32_prepare(afq_system s) {
     s->lt32[0].free();
     s->lt32[1].free();
   }
-  if (!reduced && s->chol32t.p) s->chol32t.free();
+  if (!reduced && s->chol32t.p) {
+    s->chol32t.free();
+    s->tri8.free();
+  }
   if (!reduced) {
     s->b1x.free();
     s->b1x_dt = -1.0;
@@ -548,14 +603,16 @@ int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st) {
   g.a = w->r32_coef.as<unsigned char>();
   g.b = s->chol32t.as<unsigned char>();
   g.rows_a = rows;
-  g.rows_b = pad_to((long)s->M * s->M, GeoAB::RB);
+  const TriCols tc = tri_cols(s);
+  g.rows_b = tc.rows;
   g.nchunk = nchunk;
   g.kper = nchunk;
   g.a_fast = 1;
+  g.tri = s->tri8.as<int>();
   g.x = w->r32_x.as<float>();
   g.x_wstride = ts.x_wstride;
   g.x_rows = ts.x_rows;
-  g.ncol = (long)s->M * s->M;
+  g.ncol = tc.ncol;
   g.M = s->M;
   g.nw = w->nw;
   return launch<GeoAB, EPI_XFORM>(g, st);
