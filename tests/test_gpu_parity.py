@@ -42,7 +42,7 @@ def _oracle_energy(s, W, w):
 
 
 @pytest.mark.parametrize("shape", [(8, 2, 2, 24), (20, 5, 3, 37), (64, 16, 16, 256), (128, 32, 32, 512),
-                                   (100, 50, 47, 60)])
+                                   (100, 50, 47, 60), (120, 100, 65, 40)])
 def test_energy_fp64(api, shape):
     M, nu, nd, X = shape
     s = synth.make_system(M, nu, nd, X, seed=M + X)
