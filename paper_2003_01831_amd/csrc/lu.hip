@@ -1,6 +1,5 @@
 // Batched small dense FP64 factorisations, one workgroup per matrix with the
-// matrix held in registers (element e = tid + NT*j of the row-major n x n
-// matrix lives in thread tid, slot j):
+// matrix held in registers, thread t owning a fixed RB x CB block:
 //   * Gauss-Jordan inverse with partial pivoting and log-determinant (overlap
 //     matrices S = T^H W: Theta = W S^-1, log O = log det S);
 //   * Cholesky factor R of a Hermitian Gram matrix W^H W and its inverse, for
@@ -22,88 +21,16 @@ struct GjShared {
   int red_i[NT / 64];
   double2 red_z[NT / 64];
   double2 red_l[NT / 64];
-  int p, sing;
-  double d;
+  int sing;
 };
 
-// Row and column of register slot j (element e = tid + NT j) without an
-// integer division: r = mulhi(e, m) with m = ceil(2^32 / n) is exact for the
-// e < 2^16, 2 <= n <= 128 used here; for n = 1 (m = 2^32 does not fit in 32
-// bits) r = e. Rows of empty slots (e >= n^2) are >= n.
-struct SlotMap {
-  unsigned m;
-  int n;
-  __device__ explicit SlotMap(int n_)
-      : m(n_ > 1 ? (unsigned)((0x100000000ull + (unsigned)n_ - 1) / (unsigned)n_) : 0u), n(n_) {}
-  __device__ int row(int e) const { return n > 1 ? (int)__umulhi((unsigned)e, m) : e; }
-  __device__ int col(int e, int r) const { return e - r * n; }
-};
-
-// Gauss-Jordan inverse without pivoting (pivot row k at step k) on the
-// register-resident matrix, for the triangular factor of CholeskyQR (its
-// diagonal is positive; a zero or non-finite pivot flags the matrix singular
-// and is taken as 1). Two barriers per step: the pivot row and column are
-// broadcast through LDS, then every element is updated.
-template <int NT, int EPT>
-__device__ void gj_unpivoted(double2 (&a)[EPT], int n, GjShared<NT>& sh) {
-  const int tid = threadIdx.x;
-  const SlotMap sm(n);
-  for (int k = 0; k < n; ++k) {
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
-      if (r < n) {
-        if (r == k) sh.rowp[c] = a[j];
-        if (c == k) sh.colk[r] = a[j];
-      }
-    }
-    __syncthreads();
-    double2 piv = sh.rowp[k];
-    const double pm = cabs2(piv);
-    if (!(pm > 0.0) || !isfinite(pm)) {
-      if (tid == 0) sh.sing = 1;
-      piv = make_double2(1.0, 0.0);
-    }
-    const double2 ipiv = cdiv(make_double2(1.0, 0.0), piv);
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
-      if (r < n) {
-        const double2 rp = c == k ? ipiv : cmul(sh.rowp[c], ipiv);
-        if (r == k) {
-          a[j] = rp;
-        } else {
-          const double2 base = c == k ? make_double2(0.0, 0.0) : a[j];
-          a[j] = csub(base, cmul(sh.colk[r], rp));
-        }
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Gauss-Jordan elimination with partial pivoting on a block layout: thread
-// t holds the RB x CB block (rg, cg) of the matrix, t = cg * nrg + rg with
-// nrg = ceil(n / RB) row groups, so the candidates of a pivot column sit in
-// the nrg consecutive threads of its column group (one or two waves). Per
-// step k, two barriers:
-//   1. the lanes of column k take their best live row (largest |a|^2, then
-//      lowest row), their waves reduce it and the winning lane posts row and
-//      value;
-//   2. every thread takes pivot row p and 1 / pivot; the lanes of row p
-//      broadcast it scaled by 1 / pivot (column k: 1 / pivot), the lanes of
-//      column k broadcast that column and clear it;
-// then every element takes a[r][c] -= colk[r] rowp[c] with no branch, and the
-// lanes of row p overwrite it with the scaled pivot row. The result is the
-// in-place inverse up to the pivot permutation (no physical row swaps). The
-// pivots go to sh.pivs (their logs are summed afterwards, in parallel) and
-// the pivot order to sh.perm. A column without a usable pivot (zero or non-
-// finite) flags the matrix singular and takes pivot 1 in the first row not
-// yet used.
 // One elimination step, pivot column k = k0 + KC of column group k0 / CB: the
 // column's place KC in the register block is a compile-time constant (a
-// runtime one would make the block a memory-resident array)
-template <int NT, int RB, int CB, int KC>
+// runtime one would make the block a memory-resident array). Without PIV the
+// pivot row is k (the triangular factor of CholeskyQR, whose diagonal is
+// positive; a zero or non-finite pivot flags the matrix singular and is taken
+// as 1).
+template <int NT, int RB, int CB, int KC, bool PIV>
 __device__ __forceinline__ void gj_step(double2 (&a)[RB][CB], int k0, int n, int nrg, int rg, int cg, bool act,
                                         unsigned long long& used0, unsigned long long& used1, GjShared<NT>& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -111,7 +38,16 @@ __device__ __forceinline__ void gj_step(double2 (&a)[RB][CB], int k0, int n, int
   // 1. candidates of column k: waves overlapping threads [cgk nrg, (cgk + 1) nrg)
   const int t0 = cgk * nrg, t1 = t0 + nrg - 1;
   const int w0 = t0 >> 6, w1 = t1 >> 6;
-  if (wave >= w0 && wave <= w1) {
+  if constexpr (!PIV) {   // the holder of (k, k) posts it
+    const int ik = k - rg * RB;
+    unsigned kb = act && cg == cgk && ik >= 0 && ik < RB ? 1u << ik : 0u;
+    __asm__ volatile("" : "+v"(kb));
+    if (kb) {
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+        if ((kb >> i) & 1) sh.red_z[0] = a[i][KC];
+    }
+  } else if (wave >= w0 && wave <= w1) {
     double best = -1.0;
     int bi = 1 << 30;
     double2 bv = make_double2(0.0, 0.0);
@@ -139,22 +75,24 @@ __device__ __forceinline__ void gj_step(double2 (&a)[RB][CB], int k0, int n, int
   __syncthreads();
   // 2. pivot, broadcasts
   double best = sh.red_v[0];
-  int bi = sh.red_i[0];
+  int bi = PIV ? sh.red_i[0] : k;
   double2 bv = sh.red_z[0];
-  if (w1 > w0 && (sh.red_v[1] > best || (sh.red_v[1] == best && sh.red_i[1] < bi))) {
-    best = sh.red_v[1];
-    bi = sh.red_i[1];
-    bv = sh.red_z[1];
-  }
   bool bad = false;
-  if (bi < 0 || bi >= n) {   // no usable candidate (a non-finite column): first unused row
-    bad = true;
-    bi = ~used0 ? __ffsll((long long)~used0) - 1 : 64 + __ffsll((long long)~used1) - 1;
-    if (bi >= n) bi = n - 1;
+  if constexpr (PIV) {
+    if (w1 > w0 && (sh.red_v[1] > best || (sh.red_v[1] == best && sh.red_i[1] < bi))) {
+      best = sh.red_v[1];
+      bi = sh.red_i[1];
+      bv = sh.red_z[1];
+    }
+    if (bi < 0 || bi >= n) {   // no usable candidate (a non-finite column): first unused row
+      bad = true;
+      bi = ~used0 ? __ffsll((long long)~used0) - 1 : 64 + __ffsll((long long)~used1) - 1;
+      if (bi >= n) bi = n - 1;
+    }
+    if (bi < 64) used0 |= 1ull << bi;
+    else used1 |= 1ull << (bi - 64);
   }
   const int p = bi;
-  if (p < 64) used0 |= 1ull << p;
-  else used1 |= 1ull << (p - 64);
   double2 piv = bv;
   const double pm = cabs2(piv);
   if (bad || !(pm > 0.0) || !isfinite(pm)) {
@@ -163,8 +101,10 @@ __device__ __forceinline__ void gj_step(double2 (&a)[RB][CB], int k0, int n, int
   }
   const double2 ipiv = cdiv(make_double2(1.0, 0.0), piv);
   if (tid == 0) {
-    sh.pivs[k] = piv;
-    sh.perm[k] = p;
+    if constexpr (PIV) {
+      sh.pivs[k] = piv;
+      sh.perm[k] = p;
+    }
     if (bad) sh.sing = 1;
   }
   // the row of the block that holds p, as a bit (a mask the compiler cannot
@@ -209,13 +149,13 @@ __device__ __forceinline__ void gj_step(double2 (&a)[RB][CB], int k0, int n, int
   }
 }
 
-template <int NT, int RB, int CB, int KC = 0>
+template <int NT, int RB, int CB, bool PIV, int KC = 0>
 __device__ __forceinline__ void gj_group(double2 (&a)[RB][CB], int k0, int n, int nrg, int rg, int cg, bool act,
                                          unsigned long long& used0, unsigned long long& used1, GjShared<NT>& sh) {
   if constexpr (KC < CB) {
     if (k0 + KC < n) {
-      gj_step<NT, RB, CB, KC>(a, k0, n, nrg, rg, cg, act, used0, used1, sh);
-      gj_group<NT, RB, CB, KC + 1>(a, k0, n, nrg, rg, cg, act, used0, used1, sh);
+      gj_step<NT, RB, CB, KC, PIV>(a, k0, n, nrg, rg, cg, act, used0, used1, sh);
+      gj_group<NT, RB, CB, PIV, KC + 1>(a, k0, n, nrg, rg, cg, act, used0, used1, sh);
     }
   }
 }
@@ -238,10 +178,38 @@ __device__ __forceinline__ void gj_group(double2 (&a)[RB][CB], int k0, int n, in
 // the pivot order to sh.perm. A column without a usable pivot (zero or non-
 // finite) flags the matrix singular and takes pivot 1 in the first row not
 // yet used.
-template <int NT, int RB, int CB>
+template <int NT, int RB, int CB, bool PIV>
 __device__ void gj_blocked(double2 (&a)[RB][CB], int n, int nrg, int rg, int cg, bool act, GjShared<NT>& sh) {
   unsigned long long used0 = 0, used1 = 0;   // rows already taken as pivots (n <= 128)
-  for (int k0 = 0; k0 < n; k0 += CB) gj_group<NT, RB, CB>(a, k0, n, nrg, rg, cg, act, used0, used1, sh);
+  for (int k0 = 0; k0 < n; k0 += CB) gj_group<NT, RB, CB, PIV>(a, k0, n, nrg, rg, cg, act, used0, used1, sh);
+  __syncthreads();
+}
+
+// The blocks of thread tid: column group cg, row group rg, active if cg < ncg;
+// element (r, c) of the row-major n x n matrix at m + r n + c, zero outside.
+// The broadcast arrays start zero, so entries beyond n stay zero and the
+// padding of the blocks does too.
+template <int NT, int RB, int CB>
+__device__ void blocks_load(double2 (&a)[RB][CB], const double2* __restrict__ m, int n, int& nrg, int& rg,
+                            int& cg, bool& act, GjShared<NT>& sh) {
+  const int tid = threadIdx.x;
+  nrg = (n + RB - 1) / RB;
+  const int ncg = (n + CB - 1) / CB;
+  cg = tid / nrg;
+  rg = tid - cg * nrg;
+  act = cg < ncg;
+#pragma unroll
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int r = rg * RB + i, cc = cg * CB + c;
+      a[i][c] = act && r < n && cc < n ? m[(long)r * n + cc] : make_double2(0.0, 0.0);
+    }
+  for (int e = tid; e < NMAX; e += NT) {
+    sh.rowp[e] = make_double2(0.0, 0.0);
+    sh.colk[e] = make_double2(0.0, 0.0);
+  }
+  if (tid == 0) sh.sing = 0;
   __syncthreads();
 }
 
@@ -252,25 +220,11 @@ __device__ void gj_body(const double2* __restrict__ S, long stride, int n,
   __shared__ GjShared<NT> sh;
   const long b = blockIdx.x;
   const int tid = threadIdx.x;
-  const int nrg = (n + RB - 1) / RB, ncg = (n + CB - 1) / CB;
-  const int cg = tid / nrg, rg = tid - cg * nrg;
-  const bool act = cg < ncg;
   double2 a[RB][CB];
-#pragma unroll
-  for (int i = 0; i < RB; ++i)
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      const int r = rg * RB + i, cc = cg * CB + c;
-      a[i][c] = act && r < n && cc < n ? S[b * stride + (long)r * n + cc] : make_double2(0.0, 0.0);
-    }
-  // broadcast entries beyond n stay zero, so the padding of the blocks does too
-  for (int e = tid; e < NMAX; e += NT) {
-    sh.rowp[e] = make_double2(0.0, 0.0);
-    sh.colk[e] = make_double2(0.0, 0.0);
-  }
-  if (tid == 0) sh.sing = 0;
-  __syncthreads();
-  gj_blocked<NT, RB, CB>(a, n, nrg, rg, cg, act, sh);
+  int nrg, rg, cg;
+  bool act;
+  blocks_load<NT, RB, CB>(a, S + b * stride, n, nrg, rg, cg, act, sh);
+  gj_blocked<NT, RB, CB, true>(a, n, nrg, rg, cg, act, sh);
   // log det = sum_k log(pivot_k) (+ i pi for an odd permutation): threads k < n
   // take one pivot each, waves reduce, the per-wave sums are added in order
   double2 ld = tid < n ? clog(sh.pivs[tid]) : make_double2(0.0, 0.0);
@@ -311,67 +265,86 @@ __device__ void gj_body(const double2* __restrict__ S, long stride, int n,
   }
 }
 
-template <int NT, int EPT>
-__global__ __launch_bounds__(NT) void chol_inv_kernel(const double2* __restrict__ G, long stride, int n,
-                                                      double2* __restrict__ rinv, double2* __restrict__ logdet,
-                                                      long ld_logdet, int* __restrict__ sing, long ld_sing) {
+// Cholesky factor R (G = R^H R, upper triangular) of a Hermitian positive
+// definite Gram matrix and its inverse, on the register blocks of the
+// Gauss-Jordan kernels. Right-looking: step k broadcasts row k unscaled, d =
+// sqrt(G_kk), every element takes a[r][c] -= conj(row[r]) row[c] / d^2 with
+// no branch (rows above k meet zero broadcast entries, the lower triangle is
+// cleared afterwards) and the lanes of row k overwrite it with R[k][c] =
+// row[c] / d, R[k][k] = d. A non-positive or non-finite d flags the matrix
+// singular and is taken as 1. Then the unpivoted Gauss-Jordan inverse of R.
+template <int NT, int RB, int CB>
+__global__ __launch_bounds__(NT) void chol_inv_kernel(
+    const double2* __restrict__ G, long stride, int n, double2* __restrict__ rinv, double2* __restrict__ logdet,
+    long ld_logdet, int* __restrict__ sing, long ld_sing) {
   __shared__ GjShared<NT> sh;
   const long b = blockIdx.x;
-  const int tid = threadIdx.x, nn = n * n;
-  double2 a[EPT];
-#pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int e = tid + NT * j;
-    a[j] = e < nn ? G[b * stride + e] : make_double2(0.0, 0.0);
-  }
-  if (tid == 0) sh.sing = 0;
-  __syncthreads();
-  const SlotMap sm(n);
-  double ldr = 0.0;
-  // right-looking Cholesky G = R^H R on the upper triangle
+  const int tid = threadIdx.x;
+  double2 a[RB][CB];
+  int nrg, rg, cg;
+  bool act;
+  blocks_load<NT, RB, CB>(a, G + b * stride, n, nrg, rg, cg, act, sh);
+  double ldr = 0.0;   // thread 0 sums log d in step order
   for (int k = 0; k < n; ++k) {
+    const int ik = k - rg * RB;
+    unsigned kbit = act && ik >= 0 && ik < RB ? 1u << ik : 0u;
+    __asm__ volatile("" : "+v"(kbit));
+    if (kbit) {
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int e = tid + NT * j;
-      if (e == k * n + k) {
-        double d = sqrt(a[j].x);
-        if (!(d > 0.0) || !isfinite(d)) { sh.sing = 1; d = 1.0; }
-        sh.d = d;
+      for (int i = 0; i < RB; ++i)
+        if ((kbit >> i) & 1)
+#pragma unroll
+          for (int c = 0; c < CB; ++c) {
+            const int cc = cg * CB + c;
+            if (cc < n) sh.rowp[cc] = cc >= k ? a[i][c] : make_double2(0.0, 0.0);
+          }
+    }
+    __syncthreads();
+    double d = sqrt(sh.rowp[k].x);
+    if (!(d > 0.0) || !isfinite(d)) {
+      if (tid == 0) sh.sing = 1;
+      d = 1.0;
+    }
+    if (tid == 0) ldr += log(d);
+    const double id = 1.0 / d, id2 = id * id;
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const double2 ck = cscale(cconj(sh.rowp[rg * RB + i]), id2);
+#pragma unroll
+        for (int c = 0; c < CB; ++c) a[i][c] = csub(a[i][c], cmul(ck, sh.rowp[cg * CB + c]));
+      }
+      if (kbit) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+          if ((kbit >> i) & 1)
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+              const int cc = cg * CB + c;
+              a[i][c] = cc == k ? make_double2(d, 0.0) : cscale(sh.rowp[cc], id);
+            }
       }
     }
     __syncthreads();
-    const double d = sh.d, id = 1.0 / d;
-    if (tid == 0) ldr += log(d);   // only thread 0 reports it
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
-      if (r == k && c >= k) {
-        a[j] = c == k ? make_double2(d, 0.0) : cscale(a[j], id);
-        sh.rowp[c] = a[j];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-      const int e = tid + NT * j, r = sm.row(e), c = sm.col(e, r);
-      if (r > k && r < n && c >= r) a[j] = csub(a[j], cmul(cconj(sh.rowp[r]), sh.rowp[c]));
-    }
   }
 #pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int e = tid + NT * j, r = sm.row(e);
-    if (r < n && r > sm.col(e, r)) a[j] = make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  gj_unpivoted<NT, EPT>(a, n, sh);
+  for (int i = 0; i < RB; ++i)
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+      if (rg * RB + i > cg * CB + c) a[i][c] = make_double2(0.0, 0.0);
+  gj_blocked<NT, RB, CB, false>(a, n, nrg, rg, cg, act, sh);
   if (tid == 0) {
     logdet[b * ld_logdet] = make_double2(ldr, 0.0);
     sing[b * ld_sing] = sh.sing;
   }
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int e = tid + NT * j;
-    if (e < nn) rinv[b * stride + e] = a[j];
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int r = rg * RB + i, cc = cg * CB + c;
+        if (r < n && cc < n) rinv[b * stride + (long)r * n + cc] = a[i][c];
+      }
   }
 }
 
@@ -403,18 +376,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void gj
       hipLaunchKernelGGL((KERNEL<1024, 4, 4>), dim3(batch), dim3(1024), 0, st, __VA_ARGS__);  \
   } while (0)
 
-#define AFQ_SMALL_DISPATCH(KERNEL, ...)                                                    \
-  do {                                                                                     \
-    if (n <= 32)                                                                           \
-      hipLaunchKernelGGL((KERNEL<256, 4>), dim3(batch), dim3(256), 0, st, __VA_ARGS__);    \
-    else if (n <= 64)                                                                      \
-      hipLaunchKernelGGL((KERNEL<256, 16>), dim3(batch), dim3(256), 0, st, __VA_ARGS__);   \
-    else if (n <= 101)                                                                     \
-      hipLaunchKernelGGL((KERNEL<512, 20>), dim3(batch), dim3(512), 0, st, __VA_ARGS__);   \
-    else                                                                                   \
-      hipLaunchKernelGGL((KERNEL<1024, 16>), dim3(batch), dim3(1024), 0, st, __VA_ARGS__); \
-  } while (0)
-
 int lu_inverse(const double2* S, long stride, int n, int batch, double2* inv, double2* logdet,
                long ld_logdet, int* sing, long ld_sing, hipStream_t st) {
   AFQ_CHECK(n >= 1 && n <= NMAX, AFQ_E_UNSUPPORTED, "lu_inverse: n must be in [1, 128]");
@@ -431,7 +392,7 @@ int chol_inverse(const double2* G, long stride, int n, int batch, double2* rinv,
   AFQ_CHECK(n >= 1 && n <= NMAX, AFQ_E_UNSUPPORTED, "chol_inverse: n must be in [1, 128]");
   AFQ_CHECK(stride >= (long)n * n, AFQ_E_INVALID, "chol_inverse: stride < n*n");
   if (batch <= 0) return AFQ_OK;
-  AFQ_SMALL_DISPATCH(chol_inv_kernel, G, stride, n, rinv, logdet, ld_logdet, sing, ld_sing);
+  AFQ_GJ_DISPATCH(chol_inv_kernel, G, stride, n, rinv, logdet, ld_logdet, sing, ld_sing);
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }
