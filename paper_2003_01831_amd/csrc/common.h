@@ -234,8 +234,9 @@ struct afq_walkers_s {
   DevBuf kp_tmp;               // 2 x nk x nw x nk m^2 complex: A-build GEMM outputs
   // FP32 ring scratch: packed coefficient rows, packed Theta-hat rows, force-bias partial tiles
   DevBuf r32_coef, r32_theta, r32_part;
-  DevBuf r32_x;                // real form of A_w, packed for the Taylor products
-  DevBuf r32_y[3];             // packed Taylor terms: V, then two alternating Horner terms
+  DevBuf r32_x;                // real form of A_w, packed for the Taylor products (FP32, or BF16 hi / lo planes)
+  DevBuf r32_y[3];             // packed Taylor terms: V (FP32), then two alternating Horner terms
+  int r32_layout = 0;          // layout r32_x / r32_y[1..2] were last cleared for: 1 FP32, 2 split BF16
   DevBuf r32_b1w;              // walker rows (n, Re|Im) packed for the B1 products
   // four-index exchange scratch
   DevBuf eri_theta;            // packed Theta-hat hi / lo planes of one spin

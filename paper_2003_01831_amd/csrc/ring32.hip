@@ -31,6 +31,14 @@
 // (7 x 5 tiles) for the Taylor products, whose n_tot walker columns and 2M
 // real-form rows it covers with little padding at the M = 400, N = 200 shape.
 // 72-74 KB of LDS, two workgroups per CU.
+//
+// In split-BF16x3 mode the Horner products run on v_mfma_f32_16x16x32_bf16
+// instead (hi*hi + hi*lo + lo*hi, FP32 accumulation): the propagator build
+// writes A in the same real form as BF16 hi / lo planes, and each product's
+// epilogue adds V (FP32) and splits the next term into hi / lo planes. Every
+// term is multiplied by A again before it reaches U, and |A| is small
+// (O(sqrt(dt)) per Cholesky vector), so the BF16 products' rounding reaches U
+// damped by |A|; the last product is still added to V in FP64.
 #include <algorithm>
 #include "common.h"
 #include "mfma_ring.h"
@@ -56,7 +64,20 @@ template <int TA_, int TB_> struct Geo {
 using GeoAB = Geo<8, 4>;   // propagator build, force bias
 using GeoTY = Geo<7, 5>;   // Taylor products
 
-enum { EPI_XFORM = 0, EPI_PART = 1, EPI_HORNER = 2, EPI_B1 = 3 };
+enum { EPI_XFORM = 0, EPI_PART = 1, EPI_HORNER = 2, EPI_B1 = 3, EPI_XFORM_B3 = 4 };
+
+// split BF16 of an FP32 value: hi = bf16(f), lo = bf16(f - hi), both rounded
+// to nearest even; a pair (x, y) of them packed as two BF16 (x low) per plane
+__device__ inline unsigned bf16_bits(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ inline void split_pair(float x, float y, unsigned& hi, unsigned& lo) {
+  const unsigned xh = bf16_bits(x), yh = bf16_bits(y);
+  const unsigned xl = bf16_bits(x - __uint_as_float(xh << 16)), yl = bf16_bits(y - __uint_as_float(yh << 16));
+  hi = xh | (yh << 16);
+  lo = xl | (yl << 16);
+}
 
 struct R32Args {
   const unsigned char* a;   // packed A: [chunk][rows_a][16] float (per batch member at a_bstride bytes)
@@ -71,6 +92,9 @@ struct R32Args {
   const int* tri;
   float* x;
   long x_wstride, x_rows, ncol;
+  // EPI_XFORM_B3: the same as BF16 hi / lo planes of 32-element chunks,
+  // xb_plane bytes apart, walkers xb_wstride bytes apart
+  long xb_plane, xb_wstride;
   int M, nw;
   // EPI_PART: part[(run * rows_a + row) * rows_b + col]
   float* part;
@@ -174,7 +198,7 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
 
   // lane (lr, lq) holds rows 4 lq .. 4 lq + 3 of column lr of every tile
   const int lr = lane & 15, lq = lane >> 4;
-  if constexpr (EPI == EPI_XFORM) {
+  if constexpr (EPI == EPI_XFORM || EPI == EPI_XFORM_B3) {
 #pragma unroll
     for (int i = 0; i < TA; ++i)
 #pragma unroll
@@ -188,6 +212,34 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
         const int code = g.tri[col >> 6], bm = code >> 16, bk = code & 0xffff;
         const int m = 8 * bm + (int)((col >> 3) & 7), k = 8 * bk + (int)(col & 7);
         if (m >= g.M || k >= g.M) continue;
+        if constexpr (EPI == EPI_XFORM_B3) {
+          // rows (m, Re) = [.., ar, -ai, ..] and (m, Im) = [.., ai, ar, ..] at
+          // contraction elements 2k, 2k + 1: one 4-byte pair per plane and row
+          const long b0 = ((long)(k >> 4) * g.x_rows + 2 * m) * ROWB + 4 * (k & 15);
+          const long b1 = ((long)(m >> 4) * g.x_rows + 2 * k) * ROWB + 4 * (m & 15);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int w = (int)(row0 >> 1) + h;
+            if (w < g.nw) {
+              const float ar = acc[i][j][2 * h], ai = acc[i][j][2 * h + 1];
+              unsigned char* X = reinterpret_cast<unsigned char*>(g.x) + (long)w * g.xb_wstride;
+              unsigned rh, rl, ih, il;
+              split_pair(ar, -ai, rh, rl);
+              split_pair(ai, ar, ih, il);
+              *reinterpret_cast<unsigned*>(X + b0) = rh;
+              *reinterpret_cast<unsigned*>(X + b0 + ROWB) = ih;
+              *reinterpret_cast<unsigned*>(X + g.xb_plane + b0) = rl;
+              *reinterpret_cast<unsigned*>(X + g.xb_plane + b0 + ROWB) = il;
+              if (bm != bk) {
+                *reinterpret_cast<unsigned*>(X + b1) = rh;
+                *reinterpret_cast<unsigned*>(X + b1 + ROWB) = ih;
+                *reinterpret_cast<unsigned*>(X + g.xb_plane + b1) = rl;
+                *reinterpret_cast<unsigned*>(X + g.xb_plane + b1 + ROWB) = il;
+              }
+            }
+          }
+          continue;
+        } else {
         const long o0 = ((long)(k >> 3) * g.x_rows + 2 * m) * RK + 2 * (k & 7);
         const long o1 = ((long)(m >> 3) * g.x_rows + 2 * k) * RK + 2 * (m & 7);
 #pragma unroll
@@ -203,6 +255,7 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
               *reinterpret_cast<float2*>(X + o1 + RK) = make_float2(ai, ar);
             }
           }
+        }
         }
       }
   } else if constexpr (EPI == EPI_PART) {
@@ -266,6 +319,166 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
           }
         }
       }
+  }
+}
+
+// Horner products of split-BF16x3 mode: the same contraction as EPI_HORNER
+// (walker columns h, rows n, against the real form of A, rows 2m + part) with
+// both operands as BF16 hi / lo planes of 32-element chunks, [chunk][rows][32]
+// per plane, a walker's hi plane then its lo plane.
+struct HornerB3Args {
+  const unsigned char* a;   // terms h: rows n, contraction 2m + part
+  const unsigned char* b;   // real form of A: rows 2m + part, contraction 2k + part
+  long rows_a, rows_b, a_plane, b_plane, a_wstride, b_wstride;   // bytes (planes, walkers)
+  int nchunk, nblk_a, nblk_b, nw, grid;
+  const float* vy;          // V in the FP32 packed term layout (16-element chunks)
+  long vy_rows, vy_wstride; // its rows and walker stride (floats)
+  unsigned char* yout;      // V + scale (A h), laid out as a (intermediate terms)
+  double2* u;               // U[w][m][n] += scale (A h) (last term)
+  float scale;
+  int last, ntot, M;
+};
+
+template <int TA, int TB>
+__global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
+  constexpr int RA = 32 * TA, RB = 32 * TB, REGA = RA * ROWB, REGB = RB * ROWB;
+  constexpr int STAGE = 2 * REGA + 2 * REGB, NT = STAGE / 1024, NQ = NT / NWAVE;
+  static_assert(NT % NWAVE == 0, "loads must split evenly over the waves");
+  __shared__ __align__(16) unsigned char L0[STAGE];
+  __shared__ __align__(16) unsigned char L1[STAGE];
+  __shared__ __align__(16) unsigned char L2[STAGE];
+  __shared__ float trash[NWAVE * 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rb = wave >> 1, cb = wave & 1;
+  // XCD-aware order: workgroup i runs on XCD i % 8; each XCD takes a
+  // contiguous range of the logical order (B blocks fastest, so the blocks of
+  // one walker share its terms in that XCD's L2)
+  const int per = (int)(gridDim.x / NXCD);
+  const int lid = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
+  if (lid >= g.grid) return;
+  const int bb = lid % g.nblk_b, rest = lid / g.nblk_b;
+  const int p = rest % g.nblk_a, w = rest / g.nblk_a;
+  const long arow0 = (long)p * RA, brow0 = (long)bb * RB;
+  const unsigned char* abase = g.a + (long)w * g.a_wstride;
+  const unsigned char* bbase = g.b + (long)w * g.b_wstride;
+  // load q of this wave: instruction t = q * 4 + wave of the stage, 16 rows of
+  // one region (A hi, A lo, B hi, B lo); lane l writes LDS bytes 1024 t + 16 l
+  const unsigned char* src[NQ];
+  long cstride[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int t = q * NWAVE + wave;
+    const int reg = t < RA / 16 ? 0 : t < RA / 8 ? 1 : t < RA / 8 + RB / 16 ? 2 : 3;
+    const int j = reg == 0 ? t : reg == 1 ? t - RA / 16 : reg == 2 ? t - RA / 8 : t - RA / 8 - RB / 16;
+    const int row = 16 * j + (lane >> 2), c = swz(row, lane & 3);
+    const unsigned char* base = reg == 0 ? abase : reg == 1 ? abase + g.a_plane : reg == 2 ? bbase : bbase + g.b_plane;
+    cstride[q] = (reg < 2 ? g.rows_a : g.rows_b) * (long)ROWB;
+    src[q] = base + ((reg < 2 ? arow0 : brow0) + row) * ROWB + 16 * c;
+  }
+  auto issue = [&](int chunk, unsigned char* buf) {
+    lds_t* l = (lds_t*)buf;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) ring::dma16(src[q] + chunk * cstride[q], l + (q * NWAVE + wave) * 1024);
+  };
+  // the last two steps have no chunk to prefetch: tiny loads into this wave's
+  // trash slice keep the wait count of every step the same
+  auto issue_dummy = [&]() {
+    lds_t* l = (lds_t*)(trash + wave * 64);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) ring::dma4(src[q], l);
+  };
+  f4 acc[TA][TB];
+#pragma unroll
+  for (int i = 0; i < TA; ++i)
+#pragma unroll
+    for (int j = 0; j < TB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const int arow = rb * (RA / 2), brow = cb * (RB / 2);
+  const int nc = g.nchunk;
+  issue(0, L0);
+  if (nc > 1) issue(1, L1);
+  else issue_dummy();
+  wait_vm_barrier<NQ>();
+  unsigned char* cur = L0;
+  unsigned char* nxt = L1;
+  unsigned char* pf = L2;
+  for (int c = 0; c < nc; ++c) {
+    ring::mma_rect_then<TA, TB, REGA, REGB>(acc, cur, cur + 2 * REGA, arow, brow, lane, [&]() {
+      if (c + 2 < nc) issue(c + 2, pf);
+      else issue_dummy();
+    });
+    __builtin_amdgcn_sched_barrier(0);
+    wait_vm_barrier<NQ>();
+    unsigned char* t = cur;
+    cur = nxt;
+    nxt = pf;
+    pf = t;
+  }
+  wait_vm_barrier<0>();
+
+  // column 2m + part of row n is part (Re, Im) of (A h)[m][n]: the partner
+  // lane lr ^ 1 holds the other part; even lanes finish rows 0, 1 of their
+  // four, odd lanes rows 2, 3
+  const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < TA; ++i)
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+      float o[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[r] = __shfl_xor(acc[i][j][r], 1);
+      const long n0 = arow0 + arow + 16 * i + 4 * lq;
+      const int col = (int)(brow0 + brow + 16 * j + lr), m = col >> 1, part = col & 1;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = part ? 2 + h : h;
+        const long n = n0 + r;
+        const float re = part ? o[r] : acc[i][j][r], im = part ? acc[i][j][r] : o[r];
+        if (n < g.ntot && m < g.M) {
+          if (g.last) {
+            double2* up = g.u + ((long)w * g.M + m) * g.ntot + n;
+            const double2 v = *up;
+            *up = make_double2(v.x + (double)(g.scale * re), v.y + (double)(g.scale * im));
+          } else {
+            const float2 v = *reinterpret_cast<const float2*>(
+                g.vy + (long)w * g.vy_wstride + ((long)(m >> 3) * g.vy_rows + n) * RK + 2 * (m & 7));
+            unsigned hi, lo;
+            split_pair(v.x + g.scale * re, v.y + g.scale * im, hi, lo);
+            unsigned char* y = g.yout + (long)w * g.a_wstride + ((long)(m >> 4) * g.rows_a + n) * ROWB + 4 * (m & 15);
+            *reinterpret_cast<unsigned*>(y) = hi;
+            *reinterpret_cast<unsigned*>(y + g.a_plane) = lo;
+          }
+        }
+      }
+    }
+}
+
+// V[w][m][n] (complex FP64) -> the BF16 hi / lo term planes of walker w:
+// element (n, 2m + part) at ((m / 16) rows + n) 64 + 4 (m % 16) + 2 part bytes.
+// A workgroup moves a 16 (m) x 16 (n) tile through LDS so that the reads (along
+// n) and the writes (16 consecutive m of one row: 64 bytes per plane) are
+// contiguous.
+__global__ __launch_bounds__(256) void pack_terms_bf3_kernel(const double2* __restrict__ V, int M, int ntot, long rows,
+                                                             long plane, long wstride, unsigned char* __restrict__ out) {
+  __shared__ float2 tile[16][17];
+  const int t = threadIdx.x, n0 = blockIdx.x * 16, m0 = blockIdx.y * 16, w = blockIdx.z;
+  {
+    const int m = m0 + (t >> 4), n = n0 + (t & 15);
+    float2 v = make_float2(0.f, 0.f);
+    if (m < M && n < ntot) {
+      const double2 d = V[((long)w * M + m) * ntot + n];
+      v = make_float2((float)d.x, (float)d.y);
+    }
+    tile[t >> 4][t & 15] = v;
+  }
+  __syncthreads();
+  const int n = n0 + (t >> 4), e = t & 15, m = m0 + e;
+  if (m < M && n < ntot) {
+    const float2 v = tile[e][t >> 4];
+    unsigned hi, lo;
+    split_pair(v.x, v.y, hi, lo);
+    unsigned char* y = out + (long)w * wstride + ((long)(m0 >> 4) * rows + n) * ROWB + 4 * e;
+    *reinterpret_cast<unsigned*>(y) = hi;
+    *reinterpret_cast<unsigned*>(y + plane) = lo;
   }
 }
 
@@ -458,6 +671,24 @@ TaylorShape taylor_shape(afq_system s) {
   return t;
 }
 
+// the same operands as BF16 hi / lo planes of 32-element chunks (bytes)
+struct TaylorB3Shape {
+  long x_rows, y_rows, kchunk, x_plane, x_wstride, y_plane, y_wstride;
+};
+constexpr int B3_TA = 7, B3_TB = 5;   // 224 x 160 tiles, as the FP32 Taylor products
+TaylorB3Shape taylor_b3_shape(afq_system s) {
+  TaylorB3Shape t;
+  t.x_rows = pad_to(2L * s->M, 32 * B3_TB);
+  t.y_rows = pad_to(s->ntot, 32 * B3_TA);
+  t.kchunk = pad_to(2L * s->M, ring::KC) / ring::KC;
+  t.x_plane = t.kchunk * t.x_rows * ROWB;
+  t.y_plane = t.kchunk * t.y_rows * ROWB;
+  t.x_wstride = 2 * t.x_plane;
+  t.y_wstride = 2 * t.y_plane;
+  return t;
+}
+bool taylor_b3(afq_system s) { return s->prec == AFQ_BF16X3; }
+
 // walker rows (n, Re|Im) against rows m of B1 - I
 struct B1Shape {
   long a_rows, b_rows, kchunk, a_wstride;
@@ -571,8 +802,19 @@ int r32_alloc_scratch(afq_system s, afq_walkers w) {
   const long rows = coef_rows(w->nw);
   AFQ_RET(alloc_cleared(w->r32_coef, (size_t)(pad_to(s->X, RK)) * rows * sizeof(float), st));
   const TaylorShape ts = taylor_shape(s);
-  AFQ_RET(alloc_cleared(w->r32_x, (size_t)w->nw * ts.x_wstride * sizeof(float), st));
-  for (int i = 0; i < 3; ++i) AFQ_RET(alloc_cleared(w->r32_y[i], (size_t)w->nw * ts.y_wstride * sizeof(float), st));
+  const TaylorB3Shape t3 = taylor_b3_shape(s);
+  const size_t xbytes = std::max((size_t)ts.x_wstride * sizeof(float), (size_t)t3.x_wstride) * w->nw;
+  const size_t ybytes = std::max((size_t)ts.y_wstride * sizeof(float), (size_t)t3.y_wstride) * w->nw;
+  AFQ_RET(alloc_cleared(w->r32_x, xbytes, st));
+  for (int i = 0; i < 3; ++i) AFQ_RET(alloc_cleared(w->r32_y[i], ybytes, st));
+  // the FP32 and the BF16 layouts put their zero padding in different places:
+  // clear the buffers when the layout changes
+  const int layout = taylor_b3(s) ? 2 : 1;
+  if (w->r32_layout != layout) {
+    AFQ_TRY_HIP(hipMemsetAsync(w->r32_x.p, 0, w->r32_x.bytes, st));
+    for (int i = 1; i < 3; ++i) AFQ_TRY_HIP(hipMemsetAsync(w->r32_y[i].p, 0, w->r32_y[i].bytes, st));
+    w->r32_layout = layout;
+  }
   AFQ_RET(alloc_cleared(w->r32_b1w, (size_t)w->nw * b1_shape(s).a_wstride * sizeof(float), st));
   if (!s->lt32[0].p) return AFQ_OK;
   size_t tb = 0, pb = 0;
@@ -612,13 +854,78 @@ int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st) {
   g.x = w->r32_x.as<float>();
   g.x_wstride = ts.x_wstride;
   g.x_rows = ts.x_rows;
+  if (taylor_b3(s)) {
+    const TaylorB3Shape tb = taylor_b3_shape(s);
+    AFQ_CHECK(w->r32_layout == 2 && w->r32_x.bytes >= (size_t)w->nw * tb.x_wstride, AFQ_E_STATE,
+              "propagator build (split BF16): walker scratch not prepared");
+    g.x_rows = tb.x_rows;
+    g.xb_plane = tb.x_plane;
+    g.xb_wstride = tb.x_wstride;
+  }
   g.ncol = tc.ncol;
   g.M = s->M;
   g.nw = w->nw;
+  if (taylor_b3(s)) return launch<GeoAB, EPI_XFORM_B3>(g, st);
   return launch<GeoAB, EPI_XFORM>(g, st);
 }
 
+// U <- T_K(A) U in Horner form with split-BF16x3 products
+static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st) {
+  const TaylorShape ts = taylor_shape(s);
+  const TaylorB3Shape tb = taylor_b3_shape(s);
+  AFQ_CHECK(w->r32_layout == 2 && w->r32_x.bytes >= (size_t)w->nw * tb.x_wstride &&
+                w->r32_y[0].bytes >= (size_t)w->nw * ts.y_wstride * sizeof(float) &&
+                w->r32_y[1].bytes >= (size_t)w->nw * tb.y_wstride && w->r32_y[2].bytes >= (size_t)w->nw * tb.y_wstride,
+            AFQ_E_STATE, "Taylor propagator (split BF16): walker scratch not prepared");
+  AFQ_CHECK(ts.y_rows == tb.y_rows && tb.y_rows % (32 * B3_TA) == 0 && tb.x_rows % (32 * B3_TB) == 0, AFQ_E_INVALID,
+            "Taylor propagator (split BF16): bad shape");
+  if (order < 1) return AFQ_OK;
+  // V in FP32 (added by every epilogue) and as BF16 planes (the first input)
+  hipLaunchKernelGGL(pack_terms_kernel, dim3(ceil_div(s->ntot, 32), ceil_div(s->M, 8), w->nw), dim3(256), 0, st,
+                     w->u.as<double2>(), s->M, s->ntot, ts.y_rows, ts.y_wstride, w->r32_y[0].as<float>());
+  AFQ_TRY_HIP(hipGetLastError());
+  hipLaunchKernelGGL(pack_terms_bf3_kernel, dim3(ceil_div(s->ntot, 16), ceil_div(s->M, 16), w->nw), dim3(256), 0, st,
+                     w->u.as<double2>(), s->M, s->ntot, tb.y_rows, tb.y_plane, tb.y_wstride,
+                     w->r32_y[2].as<unsigned char>());
+  AFQ_TRY_HIP(hipGetLastError());
+  HornerB3Args g{};
+  g.b = w->r32_x.as<unsigned char>();
+  g.rows_a = tb.y_rows;
+  g.rows_b = tb.x_rows;
+  g.a_plane = tb.y_plane;
+  g.b_plane = tb.x_plane;
+  g.a_wstride = tb.y_wstride;
+  g.b_wstride = tb.x_wstride;
+  g.nchunk = (int)tb.kchunk;
+  g.nblk_a = (int)(tb.y_rows / (32 * B3_TA));
+  g.nblk_b = (int)(tb.x_rows / (32 * B3_TB));
+  g.nw = w->nw;
+  const long grid = (long)g.nblk_a * g.nblk_b * w->nw;
+  AFQ_CHECK(grid < (1L << 30), AFQ_E_INVALID, "Taylor propagator (split BF16): too many workgroups");
+  g.grid = (int)grid;
+  g.vy = w->r32_y[0].as<float>();
+  g.vy_rows = ts.y_rows;
+  g.vy_wstride = ts.y_wstride;
+  g.u = w->u.as<double2>();
+  g.ntot = s->ntot;
+  g.M = s->M;
+  const long launch = (grid + NXCD - 1) / NXCD * NXCD;
+  const unsigned char* in = w->r32_y[2].as<unsigned char>();
+  for (int j = order; j >= 1; --j) {
+    unsigned char* out = w->r32_y[1 + (order - j) % 2].as<unsigned char>();
+    g.a = in;
+    g.yout = out;
+    g.scale = 1.0f / (float)j;
+    g.last = j == 1;
+    hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB>), dim3((unsigned)launch), dim3(256), 0, st, g);
+    AFQ_RET(hip_status(hipGetLastError(), "Taylor propagator (split BF16)"));
+    in = out;
+  }
+  return AFQ_OK;
+}
+
 int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st) {
+  if (taylor_b3(s)) return r32_taylor_b3(s, w, order, st);
   const TaylorShape ts = taylor_shape(s);
   const size_t yb = (size_t)w->nw * ts.y_wstride * sizeof(float);
   AFQ_CHECK(w->r32_x.bytes >= (size_t)w->nw * ts.x_wstride * sizeof(float) && w->r32_y[0].bytes >= yb &&

@@ -206,6 +206,38 @@ def test_checkpoint_resume_is_bitwise(api):
     assert torch.equal(c.get()["W"], a.get()["W"])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_walkers_replaced_between_steps(api, prec):
+    """Without QR at the end of a step the next step reuses S^-1 and log det
+    from the weight phase. Walkers replaced by set() or resampled by the comb
+    must not: the continued run equals fresh walkers started from the same
+    state, bit for bit."""
+    s = synth.make_system(12, 3, 3, 20, seed=5)
+    nw = 6
+    sysg = api.System.from_synth(s, precision=prec)
+    a = api.Walkers(sysg, nw)
+    a.step(4, 0.01, seed=5, qr_every=5)              # step 4 has no QR: the inverse is carried
+    W2 = synth.perturbed_walkers(s, nw, 0.1, seed=8)
+    a.set(W2, np.ones(nw), np.ones(nw, dtype=np.int32), 4)
+    got = a.step(3, 0.01, seed=5, qr_every=5)
+    b = api.Walkers(sysg, nw)
+    b.set(W2, np.ones(nw), np.ones(nw, dtype=np.int32), 4)
+    ref = b.step(3, 0.01, seed=5, qr_every=5)
+    torch.cuda.synchronize()
+    for k in ("eloc", "weights", "ratio"):
+        assert torch.equal(got[k], ref[k]), k
+    # the comb copies walkers over others: their carried inverses would be stale
+    a.comb(0.37)
+    st = a.get()
+    c = api.Walkers(sysg, nw)
+    c.set(st["W"], st["weights"], st["alive"], st["counter"])
+    got = a.step(3, 0.01, seed=5, qr_every=5)
+    ref = c.step(3, 0.01, seed=5, qr_every=5)
+    torch.cuda.synchronize()
+    for k in ("eloc", "weights", "ratio"):
+        assert torch.equal(got[k], ref[k]), k
+
+
 def test_repeatable_bitwise(api):
     """Fixed-order reductions: two identical runs agree bit for bit."""
     s = synth.make_system(40, 10, 10, 80, seed=6)
