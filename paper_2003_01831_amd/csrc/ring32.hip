@@ -40,6 +40,7 @@
 // (O(sqrt(dt)) per Cholesky vector), so the BF16 products' rounding reaches U
 // damped by |A|; the last product is still added to V in FP64.
 #include <algorithm>
+#include <type_traits>
 #include "common.h"
 #include "mfma_ring.h"
 
@@ -64,7 +65,7 @@ template <int TA_, int TB_> struct Geo {
 using GeoAB = Geo<8, 4>;   // propagator build, force bias
 using GeoTY = Geo<7, 5>;   // Taylor products
 
-enum { EPI_XFORM = 0, EPI_PART = 1, EPI_HORNER = 2, EPI_B1 = 3, EPI_XFORM_B3 = 4 };
+enum { EPI_XFORM = 0, EPI_PART = 1, EPI_HORNER = 2, EPI_B1 = 3, EPI_XFORM_B3 = 4, EPI_HORNER_LAST = 5 };
 
 // split BF16 of an FP32 value: hi = bf16(f), lo = bf16(f - hi), both rounded
 // to nearest even; a pair (x, y) of them packed as two BF16 (x low) per plane
@@ -98,12 +99,11 @@ struct R32Args {
   int M, nw;
   // EPI_PART: part[(run * rows_a + row) * rows_b + col]
   float* part;
-  // EPI_HORNER: A rows n (walker columns), B rows 2m + part; batch member = walker
+  // EPI_HORNER(_LAST): A rows n (walker columns), B rows 2m + part; batch member = walker
   const float* vy;          // V in the packed term layout
   float* yout;              // V + scale (A h) in the packed term layout (intermediate terms)
   double2* u;               // U[w][m][n] += scale (A h) (last term)
   float scale;
-  int last;
   long y_rows, y_wstride;
   int ntot;
   // EPI_B1: A rows (n, Re|Im) of a walker, B rows m of (B1 - I):
@@ -271,54 +271,90 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
           out[row * g.rows_b + col] = acc[i][j][v];
         }
   } else if constexpr (EPI == EPI_B1) {
+    // per row tile: gather every U_base value, then add and store (the loads
+    // are not held back behind the stores, which the compiler cannot tell
+    // apart from them)
 #pragma unroll
-    for (int i = 0; i < TA; ++i)
+    for (int i = 0; i < TA; ++i) {
+      const long n0 = (arow0 + arow + 16 * i + 4 * lq) >> 1;   // rows (n0, Re), (n0, Im), (n0 + 1, Re), (n0 + 1, Im)
+      double2 v[TB][2];
+      long idx[TB][2];
+      bool ok[TB][2];
 #pragma unroll
       for (int j = 0; j < TB; ++j) {
-        const long n0 = (arow0 + arow + 16 * i + 4 * lq) >> 1;   // rows (n0, Re), (n0, Im), (n0 + 1, Re), (n0 + 1, Im)
         const long m = brow0 + brow + 16 * j + lr;
-        if (m >= g.M) continue;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const long n = n0 + h;
-          if (n < g.ntot) {
-            const long idx = ((long)batch * g.M + m) * g.ntot + n;
-            const double2 v = g.ubase[idx];
-            g.u[idx] = make_double2(v.x + (double)acc[i][j][2 * h], v.y + (double)acc[i][j][2 * h + 1]);
-          }
+          ok[j][h] = m < g.M && n < g.ntot;
+          idx[j][h] = ok[j][h] ? ((long)batch * g.M + m) * g.ntot + n : 0;
+          v[j][h] = g.ubase[idx[j][h]];
         }
       }
+#pragma unroll
+      for (int j = 0; j < TB; ++j)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (ok[j][h])
+            g.u[idx[j][h]] = make_double2(v[j][h].x + (double)acc[i][j][2 * h], v[j][h].y + (double)acc[i][j][2 * h + 1]);
+    }
   } else {
     // column 2m + part of row n is part (Re, Im) of (A h)[m][n]: the partner
     // lane lr ^ 1 holds the other part; even lanes finish rows 0, 1 of their
-    // four, odd lanes rows 2, 3
+    // four, odd lanes rows 2, 3. Per row tile every input is gathered before
+    // any output is stored.
+    const bool odd = lr & 1;
 #pragma unroll
-    for (int i = 0; i < TA; ++i)
+    for (int i = 0; i < TA; ++i) {
+      const long n0 = arow0 + arow + 16 * i + 4 * lq;
+      float re[TB][2], im[TB][2];
+      long idx[TB][2];
+      bool ok[TB][2];
 #pragma unroll
       for (int j = 0; j < TB; ++j) {
         float o[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) o[r] = __shfl_xor(acc[i][j][r], 1);
-        const long n0 = arow0 + arow + 16 * i + 4 * lq;
-        const int col = (int)(brow0 + brow + 16 * j + lr), m = col >> 1, part = col & 1;
+        const int col = (int)(brow0 + brow + 16 * j + lr), m = col >> 1;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int r = part ? 2 + h : h;
-          const long n = n0 + r;
-          const float re = part ? o[r] : acc[i][j][r], im = part ? acc[i][j][r] : o[r];
-          if (n < g.ntot && m < g.M) {
-            if (g.last) {
-              double2* up = g.u + ((long)batch * g.M + m) * g.ntot + n;
-              const double2 v = *up;
-              *up = make_double2(v.x + (double)(g.scale * re), v.y + (double)(g.scale * im));
-            } else {
-              const long idx = (long)batch * g.y_wstride + ((long)(m >> 3) * g.y_rows + n) * RK + 2 * (m & 7);
-              const float2 v = *reinterpret_cast<const float2*>(g.vy + idx);
-              *reinterpret_cast<float2*>(g.yout + idx) = make_float2(v.x + g.scale * re, v.y + g.scale * im);
-            }
-          }
+          const long n = n0 + (odd ? 2 + h : h);
+          re[j][h] = odd ? o[2 + h] : acc[i][j][h];
+          im[j][h] = odd ? acc[i][j][2 + h] : o[h];
+          ok[j][h] = n < g.ntot && m < g.M;
+          if constexpr (EPI == EPI_HORNER_LAST)
+            idx[j][h] = ok[j][h] ? ((long)batch * g.M + m) * g.ntot + n : 0;
+          else
+            idx[j][h] = ok[j][h] ? (long)batch * g.y_wstride + ((long)(m >> 3) * g.y_rows + n) * RK + 2 * (m & 7) : 0;
         }
       }
+      if constexpr (EPI == EPI_HORNER_LAST) {
+        double2 v[TB][2];
+#pragma unroll
+        for (int j = 0; j < TB; ++j)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) v[j][h] = g.u[idx[j][h]];
+#pragma unroll
+        for (int j = 0; j < TB; ++j)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            if (ok[j][h])
+              g.u[idx[j][h]] = make_double2(v[j][h].x + (double)(g.scale * re[j][h]), v[j][h].y + (double)(g.scale * im[j][h]));
+      } else {
+        float2 v[TB][2];
+#pragma unroll
+        for (int j = 0; j < TB; ++j)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) v[j][h] = *reinterpret_cast<const float2*>(g.vy + idx[j][h]);
+#pragma unroll
+        for (int j = 0; j < TB; ++j)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            if (ok[j][h])
+              *reinterpret_cast<float2*>(g.yout + idx[j][h]) =
+                  make_float2(v[j][h].x + g.scale * re[j][h], v[j][h].y + g.scale * im[j][h]);
+      }
+    }
   }
 }
 
@@ -336,10 +372,10 @@ struct HornerB3Args {
   unsigned char* yout;      // V + scale (A h), laid out as a (intermediate terms)
   double2* u;               // U[w][m][n] += scale (A h) (last term)
   float scale;
-  int last, ntot, M;
+  int ntot, M;
 };
 
-template <int TA, int TB>
+template <int TA, int TB, bool LAST>
 __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
   constexpr int RA = 32 * TA, RB = 32 * TB, REGA = RA * ROWB, REGB = RB * ROWB;
   constexpr int STAGE = 2 * REGA + 2 * REGB, NT = STAGE / 1024, NQ = NT / NWAVE;
@@ -417,39 +453,73 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
 
   // column 2m + part of row n is part (Re, Im) of (A h)[m][n]: the partner
   // lane lr ^ 1 holds the other part; even lanes finish rows 0, 1 of their
-  // four, odd lanes rows 2, 3
+  // four, odd lanes rows 2, 3. The inputs of row tile i + 1 (V, or U for the
+  // last term) are loaded before the outputs of row tile i are stored, so
+  // only the first tile waits a full memory round trip.
   const int lr = lane & 15, lq = lane >> 4;
+  const bool odd = lr & 1;
+  using In = typename std::conditional<LAST, double2, float2>::type;
+  auto at = [&](int i, int j, int h, bool& ok) -> long {
+    const long n = arow0 + arow + 16 * i + 4 * lq + (odd ? 2 + h : h);
+    const int m = (int)((brow0 + brow + 16 * j + lr) >> 1);
+    ok = n < g.ntot && m < g.M;
+    if (!ok) return 0;
+    if constexpr (LAST) return ((long)w * g.M + m) * g.ntot + n;
+    else return (long)w * g.vy_wstride + ((long)(m >> 3) * g.vy_rows + n) * RK + 2 * (m & 7);
+  };
+  auto load = [&](long idx) -> In {
+    if constexpr (LAST) return g.u[idx];
+    else return *reinterpret_cast<const float2*>(g.vy + idx);
+  };
+  In pre[TB][2];
 #pragma unroll
-  for (int i = 0; i < TA; ++i)
+  for (int j = 0; j < TB; ++j)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      bool ok;
+      pre[j][h] = load(at(0, j, h, ok));
+    }
+#pragma unroll
+  for (int i = 0; i < TA; ++i) {
+    In cur[TB][2];
+#pragma unroll
+    for (int j = 0; j < TB; ++j)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) cur[j][h] = pre[j][h];
+    if (i + 1 < TA) {
+#pragma unroll
+      for (int j = 0; j < TB; ++j)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          bool ok;
+          pre[j][h] = load(at(i + 1, j, h, ok));
+        }
+    }
 #pragma unroll
     for (int j = 0; j < TB; ++j) {
       float o[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) o[r] = __shfl_xor(acc[i][j][r], 1);
-      const long n0 = arow0 + arow + 16 * i + 4 * lq;
-      const int col = (int)(brow0 + brow + 16 * j + lr), m = col >> 1, part = col & 1;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int r = part ? 2 + h : h;
-        const long n = n0 + r;
-        const float re = part ? o[r] : acc[i][j][r], im = part ? acc[i][j][r] : o[r];
-        if (n < g.ntot && m < g.M) {
-          if (g.last) {
-            double2* up = g.u + ((long)w * g.M + m) * g.ntot + n;
-            const double2 v = *up;
-            *up = make_double2(v.x + (double)(g.scale * re), v.y + (double)(g.scale * im));
-          } else {
-            const float2 v = *reinterpret_cast<const float2*>(
-                g.vy + (long)w * g.vy_wstride + ((long)(m >> 3) * g.vy_rows + n) * RK + 2 * (m & 7));
-            unsigned hi, lo;
-            split_pair(v.x + g.scale * re, v.y + g.scale * im, hi, lo);
-            unsigned char* y = g.yout + (long)w * g.a_wstride + ((long)(m >> 4) * g.rows_a + n) * ROWB + 4 * (m & 15);
-            *reinterpret_cast<unsigned*>(y) = hi;
-            *reinterpret_cast<unsigned*>(y + g.a_plane) = lo;
-          }
+        const float re = odd ? o[2 + h] : acc[i][j][h], im = odd ? acc[i][j][2 + h] : o[h];
+        bool ok;
+        const long idx = at(i, j, h, ok);
+        if (!ok) continue;
+        if constexpr (LAST) {
+          g.u[idx] = make_double2(cur[j][h].x + (double)(g.scale * re), cur[j][h].y + (double)(g.scale * im));
+        } else {
+          const long n = arow0 + arow + 16 * i + 4 * lq + (odd ? 2 + h : h);
+          const int m = (int)((brow0 + brow + 16 * j + lr) >> 1);
+          unsigned hi, lo;
+          split_pair(cur[j][h].x + g.scale * re, cur[j][h].y + g.scale * im, hi, lo);
+          unsigned char* y = g.yout + (long)w * g.a_wstride + ((long)(m >> 4) * g.rows_a + n) * ROWB + 4 * (m & 15);
+          *reinterpret_cast<unsigned*>(y) = hi;
+          *reinterpret_cast<unsigned*>(y + g.a_plane) = lo;
         }
       }
     }
+  }
 }
 
 // V[w][m][n] (complex FP64) -> the BF16 hi / lo term planes of walker w:
@@ -916,8 +986,10 @@ static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st)
     g.a = in;
     g.yout = out;
     g.scale = 1.0f / (float)j;
-    g.last = j == 1;
-    hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB>), dim3((unsigned)launch), dim3(256), 0, st, g);
+    if (j == 1)
+      hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, true>), dim3((unsigned)launch), dim3(256), 0, st, g);
+    else
+      hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, false>), dim3((unsigned)launch), dim3(256), 0, st, g);
     AFQ_RET(hip_status(hipGetLastError(), "Taylor propagator (split BF16)"));
     in = out;
   }
@@ -954,12 +1026,12 @@ int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st) {
     g.yout = out;
     g.u = w->u.as<double2>();
     g.scale = 1.0f / (float)j;
-    g.last = j == 1;
     g.y_rows = ts.y_rows;
     g.y_wstride = ts.y_wstride;
     g.ntot = s->ntot;
     g.M = s->M;
-    AFQ_RET((launch<GeoTY, EPI_HORNER>(g, st)));
+    if (j == 1) AFQ_RET((launch<GeoTY, EPI_HORNER_LAST>(g, st)));
+    else AFQ_RET((launch<GeoTY, EPI_HORNER>(g, st)));
     in = out;
   }
   return AFQ_OK;
