@@ -121,6 +121,8 @@ struct afq_system_s {
   DevBuf tri8;                 // its 8 x 8 block pairs (bm << 16 | bk, bm <= bk), 64 rows e each (FP32 ring)
   DevBuf b1x;                  // reduced modes: (B1 - I) FP32 packed rows m, for W + (B1 - I) W
   double b1x_dt = -1.0;
+  DevBuf b1x3;                 // split-BF16x3 mode: the same as BF16 hi / lo planes
+  double b1x3_dt = -1.0;
   DevBuf lt32[2];              // split-BF16x3, real trial: Lt rows n of each spin, FP32 packed [J / 16][n][J % 16]
   DevBuf hp;                   // h' = h - 1/2 sum L L   (M x M f64)
   DevBuf B1;                   // exp(-dt h'/2)          (M x M f64)

@@ -358,10 +358,13 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
   }
 }
 
-// Horner products of split-BF16x3 mode: the same contraction as EPI_HORNER
-// (walker columns h, rows n, against the real form of A, rows 2m + part) with
-// both operands as BF16 hi / lo planes of 32-element chunks, [chunk][rows][32]
-// per plane, a walker's hi plane then its lo plane.
+// Products of split-BF16x3 mode on the BF16 ring, both operands as BF16
+// hi / lo planes of 32-element chunks, [chunk][rows][32] per plane, a walker's
+// hi plane then its lo plane:
+//   * B3_HORNER(_LAST): the contraction of EPI_HORNER (walker columns h, rows n,
+//     against the real form of A, rows 2m + part);
+//   * B3_B1: the contraction of EPI_B1 (walker rows (n, Re|Im) against the rows
+//     m of B1 - I, shared by all walkers: b_wstride 0), added to U_base in FP64.
 struct HornerB3Args {
   const unsigned char* a;   // terms h: rows n, contraction 2m + part
   const unsigned char* b;   // real form of A: rows 2m + part, contraction 2k + part
@@ -370,13 +373,17 @@ struct HornerB3Args {
   const float* vy;          // V in the FP32 packed term layout (16-element chunks)
   long vy_rows, vy_wstride; // its rows and walker stride (floats)
   unsigned char* yout;      // V + scale (A h), laid out as a (intermediate terms)
-  double2* u;               // U[w][m][n] += scale (A h) (last term)
+  double2* u;               // U[w][m][n] += scale (A h) (last term); B3_B1: U = U_base + (B1 - I) W
+  const double2* ubase;
   float scale;
   int ntot, M;
 };
 
-template <int TA, int TB, bool LAST>
+enum { B3_HORNER = 0, B3_HORNER_LAST = 1, B3_B1 = 2 };
+
+template <int TA, int TB, int MODE>
 __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
+  constexpr bool LAST = MODE != B3_HORNER;   // the input is U (or U_base): FP64
   constexpr int RA = 32 * TA, RB = 32 * TB, REGA = RA * ROWB, REGB = RB * ROWB;
   constexpr int STAGE = 2 * REGA + 2 * REGB, NT = STAGE / 1024, NQ = NT / NWAVE;
   static_assert(NT % NWAVE == 0, "loads must split evenly over the waves");
@@ -460,6 +467,12 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
   const bool odd = lr & 1;
   using In = typename std::conditional<LAST, double2, float2>::type;
   auto at = [&](int i, int j, int h, bool& ok) -> long {
+    if constexpr (MODE == B3_B1) {   // rows (n0, Re), (n0, Im), (n0 + 1, Re), (n0 + 1, Im); column m
+      const long n = ((arow0 + arow + 16 * i + 4 * lq) >> 1) + h;
+      const long m = brow0 + brow + 16 * j + lr;
+      ok = n < g.ntot && m < g.M;
+      return ok ? ((long)w * g.M + m) * g.ntot + n : 0;
+    }
     const long n = arow0 + arow + 16 * i + 4 * lq + (odd ? 2 + h : h);
     const int m = (int)((brow0 + brow + 16 * j + lr) >> 1);
     ok = n < g.ntot && m < g.M;
@@ -468,7 +481,8 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
     else return (long)w * g.vy_wstride + ((long)(m >> 3) * g.vy_rows + n) * RK + 2 * (m & 7);
   };
   auto load = [&](long idx) -> In {
-    if constexpr (LAST) return g.u[idx];
+    if constexpr (MODE == B3_B1) return g.ubase[idx];
+    else if constexpr (LAST) return g.u[idx];
     else return *reinterpret_cast<const float2*>(g.vy + idx);
   };
   In pre[TB][2];
@@ -497,6 +511,16 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
     }
 #pragma unroll
     for (int j = 0; j < TB; ++j) {
+      if constexpr (MODE == B3_B1) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          bool ok;
+          const long idx = at(i, j, h, ok);
+          if (ok)
+            g.u[idx] = make_double2(cur[j][h].x + (double)acc[i][j][2 * h], cur[j][h].y + (double)acc[i][j][2 * h + 1]);
+        }
+        continue;
+      }
       float o[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) o[r] = __shfl_xor(acc[i][j][r], 1);
@@ -519,6 +543,50 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
         }
       }
     }
+  }
+}
+
+// W[w][k][n] (complex FP64) -> BF16 hi / lo planes of walker rows (n, Re|Im):
+// component part of W[k][n] at ((k / 32) rows + 2n + part) 64 + 2 (k % 32)
+// bytes, zero for k >= M. A workgroup moves a 32 (k) x 8 (n) tile through LDS;
+// each of its 16 rows is written as 64 contiguous bytes per plane.
+__global__ __launch_bounds__(256) void pack_walker_rows_bf3_kernel(const double2* __restrict__ W, int M, int ntot,
+                                                                   long rows, long plane, long wstride,
+                                                                   unsigned char* __restrict__ out) {
+  __shared__ float2 tile[32][9];
+  const int t = threadIdx.x, n0 = blockIdx.x * 8, k0 = blockIdx.y * 32, w = blockIdx.z;
+  {
+    const int k = k0 + (t >> 3), n = n0 + (t & 7);
+    float2 v = make_float2(0.f, 0.f);
+    if (k < M && n < ntot) {
+      const double2 d = W[((long)w * M + k) * ntot + n];
+      v = make_float2((float)d.x, (float)d.y);
+    }
+    tile[t >> 3][t & 7] = v;
+  }
+  __syncthreads();
+  const int r = t >> 4, kp = t & 15, j = r >> 1, part = r & 1, n = n0 + j;
+  if (n < ntot) {
+    const float2 a = tile[2 * kp][j], b = tile[2 * kp + 1][j];
+    unsigned hi, lo;
+    split_pair(part ? a.y : a.x, part ? b.y : b.x, hi, lo);
+    unsigned char* y = out + (long)w * wstride + ((long)blockIdx.y * rows + 2 * n + part) * ROWB + 4 * kp;
+    *reinterpret_cast<unsigned*>(y) = hi;
+    *reinterpret_cast<unsigned*>(y + plane) = lo;
+  }
+}
+
+// (B1 - I) as BF16 hi / lo planes of rows m: element k at ((k / 32) rows + m) 64 + 2 (k % 32) bytes
+__global__ void pack_b1_bf3_kernel(const double* __restrict__ B1, int M, long rows, int nchunk, long plane,
+                                   unsigned short* __restrict__ out) {
+  const long total = (long)nchunk * rows * 32;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const long c = e / (rows * 32), rem = e - c * rows * 32;
+    const long m = rem / 32, k = c * 32 + (rem - m * 32);
+    const float f = (m < M && k < M) ? (float)(B1[m * M + k] - (m == k ? 1.0 : 0.0)) : 0.f;
+    const unsigned h = bf16_bits(f);
+    out[e] = (unsigned short)h;
+    out[plane / 2 + e] = (unsigned short)bf16_bits(f - __uint_as_float(h << 16));
   }
 }
 
@@ -759,6 +827,21 @@ TaylorB3Shape taylor_b3_shape(afq_system s) {
 }
 bool taylor_b3(afq_system s) { return s->prec == AFQ_BF16X3; }
 
+// the B1 products' operands as BF16 hi / lo planes (bytes)
+struct B1B3Shape {
+  long a_rows, b_rows, kchunk, a_plane, a_wstride, b_plane;
+};
+B1B3Shape b1_b3_shape(afq_system s) {
+  B1B3Shape b;
+  b.a_rows = pad_to(2L * s->ntot, 32 * B3_TA);
+  b.b_rows = pad_to(s->M, 32 * B3_TB);
+  b.kchunk = pad_to(s->M, ring::KC) / ring::KC;
+  b.a_plane = b.kchunk * b.a_rows * ROWB;
+  b.a_wstride = 2 * b.a_plane;
+  b.b_plane = b.kchunk * b.b_rows * ROWB;
+  return b;
+}
+
 // walker rows (n, Re|Im) against rows m of B1 - I
 struct B1Shape {
   long a_rows, b_rows, kchunk, a_wstride;
@@ -777,6 +860,15 @@ B1Shape b1_shape(afq_system s) {
 bool r32_coulomb_used(afq_system s) { return s->lt32[0].p != nullptr; }
 
 int r32_prepare_b1(afq_system s) {
+  if (s->chol32t.p && s->B1.p && taylor_b3(s) && s->b1x3_dt != s->B1_dt) {
+    const B1B3Shape b = b1_b3_shape(s);
+    AFQ_RET(s->b1x3.alloc((size_t)2 * b.b_plane));
+    hipLaunchKernelGGL(pack_b1_bf3_kernel, dim3(grid_of(b.kchunk * b.b_rows * 32)), dim3(256), 0, s->stream,
+                       s->B1.as<double>(), s->M, b.b_rows, (int)b.kchunk, b.b_plane,
+                       s->b1x3.as<unsigned short>());
+    AFQ_TRY_HIP(hipGetLastError());
+    s->b1x3_dt = s->B1_dt;
+  }
   if (!s->chol32t.p || !s->B1.p || s->b1x_dt == s->B1_dt) return AFQ_OK;
   const B1Shape b = b1_shape(s);
   AFQ_RET(s->b1x.alloc((size_t)b.kchunk * b.b_rows * RK * sizeof(float)));
@@ -788,6 +880,38 @@ int r32_prepare_b1(afq_system s) {
 }
 
 int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStream_t st) {
+  if (taylor_b3(s)) {
+    const B1B3Shape b = b1_b3_shape(s);
+    AFQ_CHECK(s->b1x3.p && s->b1x3_dt == s->B1_dt && w->r32_layout == 2 &&
+                  w->r32_b1w.bytes >= (size_t)w->nw * b.a_wstride,
+              AFQ_E_STATE, "B1 product (split BF16): operands not prepared");
+    hipLaunchKernelGGL(pack_walker_rows_bf3_kernel, dim3(ceil_div(s->ntot, 8), (unsigned)b.kchunk, w->nw), dim3(256),
+                       0, st, in, s->M, s->ntot, b.a_rows, b.a_plane, b.a_wstride, w->r32_b1w.as<unsigned char>());
+    AFQ_TRY_HIP(hipGetLastError());
+    HornerB3Args g{};
+    g.a = w->r32_b1w.as<unsigned char>();
+    g.b = s->b1x3.as<unsigned char>();
+    g.rows_a = b.a_rows;
+    g.rows_b = b.b_rows;
+    g.a_plane = b.a_plane;
+    g.b_plane = b.b_plane;
+    g.a_wstride = b.a_wstride;
+    g.b_wstride = 0;
+    g.nchunk = (int)b.kchunk;
+    g.nblk_a = (int)(b.a_rows / (32 * B3_TA));
+    g.nblk_b = (int)(b.b_rows / (32 * B3_TB));
+    g.nw = w->nw;
+    const long grid = (long)g.nblk_a * g.nblk_b * w->nw;
+    AFQ_CHECK(grid < (1L << 30), AFQ_E_INVALID, "B1 product (split BF16): too many workgroups");
+    g.grid = (int)grid;
+    g.u = out;
+    g.ubase = in;
+    g.ntot = s->ntot;
+    g.M = s->M;
+    const long launch = (grid + NXCD - 1) / NXCD * NXCD;
+    hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, B3_B1>), dim3((unsigned)launch), dim3(256), 0, st, g);
+    return hip_status(hipGetLastError(), "B1 product (split BF16)");
+  }
   const B1Shape b = b1_shape(s);
   AFQ_CHECK(s->b1x.p && s->b1x_dt == s->B1_dt && w->r32_b1w.bytes >= (size_t)w->nw * b.a_wstride * sizeof(float),
             AFQ_E_STATE, "B1 product (FP32 ring): operands not prepared");
@@ -854,6 +978,10 @@ int r32_prepare(afq_system s) {
     s->b1x.free();
     s->b1x_dt = -1.0;
   }
+  if (s->prec != AFQ_BF16X3) {
+    s->b1x3.free();
+    s->b1x3_dt = -1.0;
+  }
   return r32_prepare_b1(s);
 }
 
@@ -877,15 +1005,18 @@ int r32_alloc_scratch(afq_system s, afq_walkers w) {
   const size_t ybytes = std::max((size_t)ts.y_wstride * sizeof(float), (size_t)t3.y_wstride) * w->nw;
   AFQ_RET(alloc_cleared(w->r32_x, xbytes, st));
   for (int i = 0; i < 3; ++i) AFQ_RET(alloc_cleared(w->r32_y[i], ybytes, st));
+  AFQ_RET(alloc_cleared(w->r32_b1w, std::max((size_t)b1_shape(s).a_wstride * sizeof(float),
+                                             (size_t)b1_b3_shape(s).a_wstride) * w->nw, st));
   // the FP32 and the BF16 layouts put their zero padding in different places:
   // clear the buffers when the layout changes
   const int layout = taylor_b3(s) ? 2 : 1;
   if (w->r32_layout != layout) {
     AFQ_TRY_HIP(hipMemsetAsync(w->r32_x.p, 0, w->r32_x.bytes, st));
     for (int i = 1; i < 3; ++i) AFQ_TRY_HIP(hipMemsetAsync(w->r32_y[i].p, 0, w->r32_y[i].bytes, st));
+    AFQ_TRY_HIP(hipMemsetAsync(w->r32_b1w.p, 0, w->r32_b1w.bytes, st));
     w->r32_layout = layout;
   }
-  AFQ_RET(alloc_cleared(w->r32_b1w, (size_t)w->nw * b1_shape(s).a_wstride * sizeof(float), st));
+
   if (!s->lt32[0].p) return AFQ_OK;
   size_t tb = 0, pb = 0;
   for (int sp = 0; sp < 2; ++sp) {
@@ -987,9 +1118,9 @@ static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st)
     g.yout = out;
     g.scale = 1.0f / (float)j;
     if (j == 1)
-      hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, true>), dim3((unsigned)launch), dim3(256), 0, st, g);
+      hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, B3_HORNER_LAST>), dim3((unsigned)launch), dim3(256), 0, st, g);
     else
-      hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, false>), dim3((unsigned)launch), dim3(256), 0, st, g);
+      hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, B3_HORNER>), dim3((unsigned)launch), dim3(256), 0, st, g);
     AFQ_RET(hip_status(hipGetLastError(), "Taylor propagator (split BF16)"));
     in = out;
   }
