@@ -139,11 +139,15 @@ def test_step_moderate_subset(api):
 
 
 @pytest.mark.parametrize("prec", ["cfp32", "bf16x3"])
-def test_step_reduced_precision(api, prec):
-    """Reduced-precision contractions against the FP64 oracle over 10 steps."""
-    s = synth.make_system(64, 16, 16, 256, seed=3)
+@pytest.mark.parametrize("shape", [(64, 16, 16, 256), (37, 9, 6, 70)])
+def test_step_reduced_precision(api, prec, shape):
+    """Reduced-precision contractions against the FP64 oracle over 10 steps.
+    M = 37 leaves ragged tails in every packed chunk (2M = 74, M = 37 against
+    16- and 32-element chunks) and in the walker-column tiles (n_tot = 15)."""
+    M, nu, nd, X = shape
+    s = synth.make_system(M, nu, nd, X, seed=3)
     nw, steps = 6, 10
-    fields = synth.make_fields(steps, nw, 256, seed=1003)
+    fields = synth.make_fields(steps, nw, X, seed=1003)
     W0 = synth.perturbed_walkers(s, nw, 0.05, seed=9)
     g, o = _run_both(api, s, W0, np.ones(nw), fields, 0.005, 5, 0.0, prec=prec)
     errs = {k: rel_vec(g[k], o[k]) for k in ("emix", "eloc", "weights", "ratio")}
