@@ -119,6 +119,7 @@ struct afq_system_s {
   DevBuf h1, chol, phi;        // f64 inputs (phi complex M x ntot)
   DevBuf chol32t;              // reduced modes: upper block triangle of L as FP32 packed rows e of [n / 16][e][n % 16]
   DevBuf tri8;                 // its 8 x 8 block pairs (bm << 16 | bk, bm <= bk), 64 rows e each (FP32 ring)
+  DevBuf chol3;                // split-BF16x3 mode: the same rows e as BF16 hi / lo planes [n / 32][e][n % 32]
   DevBuf b1x;                  // reduced modes: (B1 - I) FP32 packed rows m, for W + (B1 - I) W
   double b1x_dt = -1.0;
   DevBuf b1x3;                 // split-BF16x3 mode: the same as BF16 hi / lo planes

@@ -364,7 +364,10 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
 //   * B3_HORNER(_LAST): the contraction of EPI_HORNER (walker columns h, rows n,
 //     against the real form of A, rows 2m + part);
 //   * B3_B1: the contraction of EPI_B1 (walker rows (n, Re|Im) against the rows
-//     m of B1 - I, shared by all walkers: b_wstride 0), added to U_base in FP64.
+//     m of B1 - I, shared by all walkers: b_wstride 0), added to U_base in FP64;
+//   * B3_XFORM: the propagator build of EPI_XFORM_B3 (coefficient rows against
+//     the upper block triangle of L, one batch; consecutive workgroups take
+//     consecutive coefficient row blocks, so they share an L block in L2).
 struct HornerB3Args {
   const unsigned char* a;   // terms h: rows n, contraction 2m + part
   const unsigned char* b;   // real form of A: rows 2m + part, contraction 2k + part
@@ -377,9 +380,15 @@ struct HornerB3Args {
   const double2* ubase;
   float scale;
   int ntot, M;
+  // B3_XFORM: coefficient rows (w, Re|Im) against the block-pair columns of L
+  // (tri, ncol); A_w in real form to BF16 planes x (x_rows rows, x_plane bytes
+  // apart, walkers x_wstride bytes apart)
+  const int* tri;
+  unsigned char* x;
+  long x_rows, x_plane, x_wstride, ncol;
 };
 
-enum { B3_HORNER = 0, B3_HORNER_LAST = 1, B3_B1 = 2 };
+enum { B3_HORNER = 0, B3_HORNER_LAST = 1, B3_B1 = 2, B3_XFORM = 3 };
 
 template <int TA, int TB, int MODE>
 __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
@@ -399,8 +408,17 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
   const int per = (int)(gridDim.x / NXCD);
   const int lid = (int)(blockIdx.x % NXCD) * per + (int)(blockIdx.x / NXCD);
   if (lid >= g.grid) return;
-  const int bb = lid % g.nblk_b, rest = lid / g.nblk_b;
-  const int p = rest % g.nblk_a, w = rest / g.nblk_a;
+  int bb, p, w;
+  if constexpr (MODE == B3_XFORM) {
+    p = lid % g.nblk_a;
+    bb = (lid / g.nblk_a) % g.nblk_b;
+    w = 0;
+  } else {
+    bb = lid % g.nblk_b;
+    const int rest = lid / g.nblk_b;
+    p = rest % g.nblk_a;
+    w = rest / g.nblk_a;
+  }
   const long arow0 = (long)p * RA, brow0 = (long)bb * RB;
   const unsigned char* abase = g.a + (long)w * g.a_wstride;
   const unsigned char* bbase = g.b + (long)w * g.b_wstride;
@@ -458,6 +476,48 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
   }
   wait_vm_barrier<0>();
 
+  if constexpr (MODE == B3_XFORM) {
+    // rows (w0, Re), (w0, Im), (w0 + 1, Re), (w0 + 1, Im); a wave's 64 columns
+    // are one block pair (m in block bm, k in block bk): A_w[m][k] and, off the
+    // diagonal blocks, its mirror A_w[k][m], each as rows (m, Re) = [.., ar,
+    // -ai, ..] and (m, Im) = [.., ai, ar, ..] at elements 2k, 2k + 1
+    const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        const long row0 = arow0 + arow + 16 * i + 4 * lq;
+        const long col = brow0 + brow + 16 * j + lr;
+        if (col >= g.ncol) continue;
+        const int code = g.tri[col >> 6], bm = code >> 16, bk = code & 0xffff;
+        const int m = 8 * bm + (int)((col >> 3) & 7), k = 8 * bk + (int)(col & 7);
+        if (m >= g.M || k >= g.M) continue;
+        const long b0 = ((long)(k >> 4) * g.x_rows + 2 * m) * ROWB + 4 * (k & 15);
+        const long b1 = ((long)(m >> 4) * g.x_rows + 2 * k) * ROWB + 4 * (m & 15);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int wk = (int)(row0 >> 1) + h;
+          if (wk < g.nw) {
+            const float ar = acc[i][j][2 * h], ai = acc[i][j][2 * h + 1];
+            unsigned char* X = g.x + (long)wk * g.x_wstride;
+            unsigned rh, rl, ih, il;
+            split_pair(ar, -ai, rh, rl);
+            split_pair(ai, ar, ih, il);
+            *reinterpret_cast<unsigned*>(X + b0) = rh;
+            *reinterpret_cast<unsigned*>(X + b0 + ROWB) = ih;
+            *reinterpret_cast<unsigned*>(X + g.x_plane + b0) = rl;
+            *reinterpret_cast<unsigned*>(X + g.x_plane + b0 + ROWB) = il;
+            if (bm != bk) {
+              *reinterpret_cast<unsigned*>(X + b1) = rh;
+              *reinterpret_cast<unsigned*>(X + b1 + ROWB) = ih;
+              *reinterpret_cast<unsigned*>(X + g.x_plane + b1) = rl;
+              *reinterpret_cast<unsigned*>(X + g.x_plane + b1 + ROWB) = il;
+            }
+          }
+        }
+      }
+    return;
+  }
   // column 2m + part of row n is part (Re, Im) of (A h)[m][n]: the partner
   // lane lr ^ 1 holds the other part; even lanes finish rows 0, 1 of their
   // four, odd lanes rows 2, 3. The inputs of row tile i + 1 (V, or U for the
@@ -587,6 +647,46 @@ __global__ void pack_b1_bf3_kernel(const double* __restrict__ B1, int M, long ro
     const unsigned h = bf16_bits(f);
     out[e] = (unsigned short)h;
     out[plane / 2 + e] = (unsigned short)bf16_bits(f - __uint_as_float(h << 16));
+  }
+}
+
+// complex FP32 rows -> BF16 hi / lo planes of real rows (2 r + part), zero
+// outside: element k of row 2r + part (component part of src[r ld + k]) at
+// short ((k / 32) rows + 2r + part) 32 + k % 32 of the hi plane (lo plane
+// plane_s shorts later)
+__global__ void pack_cplx_rows_bf3_kernel(const float* __restrict__ src, long ld, int nrow_c, long K, long rows,
+                                          int nchunk, long plane_s, unsigned short* __restrict__ out) {
+  const long total = (long)nchunk * rows * 32;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const long c = e / (rows * 32), rem = e - c * rows * 32;
+    const long r = rem / 32, k = c * 32 + (rem - r * 32);
+    const float f = ((r >> 1) < nrow_c && k < K) ? src[2 * ((r >> 1) * ld + k) + (r & 1)] : 0.f;
+    const unsigned h = bf16_bits(f);
+    out[e] = (unsigned short)h;
+    out[plane_s + e] = (unsigned short)bf16_bits(f - __uint_as_float(h << 16));
+  }
+}
+
+// the block-pair columns e of the symmetrised L^k (as pack_tri_cols_kernel)
+// as BF16 hi / lo planes: element k of row e at short ((k / 32) rows + e) 32 +
+// k % 32 (lo plane plane_s shorts later)
+__global__ void pack_tri_cols_bf3_kernel(const double* __restrict__ src, int M, int K, const int* __restrict__ tri,
+                                         long ncol, long rows, int nchunk, long plane_s,
+                                         unsigned short* __restrict__ out) {
+  const long total = (long)nchunk * rows * 32;
+  const long m2 = (long)M * M;
+  for (long t = blockIdx.x * 256L + threadIdx.x; t < total; t += (long)gridDim.x * 256) {
+    const long k = t / rows, e = t - k * rows;
+    float f = 0.f;
+    if (k < K && e < ncol) {
+      const int code = tri[e >> 6];
+      const int m = 8 * (code >> 16) + (int)((e >> 3) & 7), kk = 8 * (code & 0xffff) + (int)(e & 7);
+      if (m < M && kk < M) f = (float)(0.5 * (src[k * m2 + (long)m * M + kk] + src[k * m2 + (long)kk * M + m]));
+    }
+    const long o = ((k / 32) * rows + e) * 32 + (k % 32);
+    const unsigned h = bf16_bits(f);
+    out[o] = (unsigned short)h;
+    out[plane_s + o] = (unsigned short)bf16_bits(f - __uint_as_float(h << 16));
   }
 }
 
@@ -953,6 +1053,18 @@ int r32_prepare(afq_system s) {
                        s->chol32t.as<float>());
     AFQ_TRY_HIP(hipGetLastError());
   }
+  if (reduced && s->prec == AFQ_BF16X3 && !s->chol3.p) {
+    const TriCols tc = tri_cols(s);
+    const int nchunk = (int)(pad_to(s->X, ring::KC) / ring::KC);
+    const long plane = (long)nchunk * tc.rows * ROWB;
+    AFQ_RET(s->chol3.alloc((size_t)2 * plane));
+    hipLaunchKernelGGL(pack_tri_cols_bf3_kernel, dim3(grid_of((long)nchunk * tc.rows * 32)), dim3(256), 0, st,
+                       s->chol.as<double>(), s->M, s->X, s->tri8.as<int>(), tc.ncol, tc.rows, nchunk, plane / 2,
+                       s->chol3.as<unsigned short>());
+    AFQ_TRY_HIP(hipGetLastError());
+  } else if (s->prec != AFQ_BF16X3 && s->chol3.p) {
+    s->chol3.free();
+  }
   const bool coul = s->prec == AFQ_BF16X3 && s->real_trial && s->kp_nk == 0 && s->msd_n == 0;
   if (coul && !s->lt32[0].p) {
     AFQ_CHECK(s->LtRe.p, AFQ_E_STATE, "force bias (FP32 ring): real half-rotated vectors missing");
@@ -998,7 +1110,8 @@ int r32_alloc_scratch(afq_system s, afq_walkers w) {
   if (!s->chol32t.p) return AFQ_OK;
   hipStream_t st = s->stream;
   const long rows = coef_rows(w->nw);
-  AFQ_RET(alloc_cleared(w->r32_coef, (size_t)(pad_to(s->X, RK)) * rows * sizeof(float), st));
+  AFQ_RET(alloc_cleared(w->r32_coef, std::max((size_t)pad_to(s->X, RK) * sizeof(float),
+                                              (size_t)pad_to(s->X, ring::KC) * 4) * rows, st));
   const TaylorShape ts = taylor_shape(s);
   const TaylorB3Shape t3 = taylor_b3_shape(s);
   const size_t xbytes = std::max((size_t)ts.x_wstride * sizeof(float), (size_t)t3.x_wstride) * w->nw;
@@ -1014,6 +1127,7 @@ int r32_alloc_scratch(afq_system s, afq_walkers w) {
     AFQ_TRY_HIP(hipMemsetAsync(w->r32_x.p, 0, w->r32_x.bytes, st));
     for (int i = 1; i < 3; ++i) AFQ_TRY_HIP(hipMemsetAsync(w->r32_y[i].p, 0, w->r32_y[i].bytes, st));
     AFQ_TRY_HIP(hipMemsetAsync(w->r32_b1w.p, 0, w->r32_b1w.bytes, st));
+    AFQ_TRY_HIP(hipMemsetAsync(w->r32_coef.p, 0, w->r32_coef.bytes, st));
     w->r32_layout = layout;
   }
 
@@ -1034,6 +1148,44 @@ int r32_alloc_scratch(afq_system s, afq_walkers w) {
 
 int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st) {
   const long rows = coef_rows(w->nw);
+  if (taylor_b3(s)) {   // split BF16 inputs (coefficients and L), A in BF16 planes
+    const int nchunk = (int)(pad_to(s->X, ring::KC) / ring::KC);
+    const TriCols tc = tri_cols(s);
+    const TaylorB3Shape tb = taylor_b3_shape(s);
+    const long aplane = (long)nchunk * rows * ROWB, bplane = (long)nchunk * tc.rows * ROWB;
+    AFQ_CHECK(s->chol3.p && s->chol3.bytes >= (size_t)2 * bplane && w->r32_layout == 2 &&
+                  w->r32_coef.bytes >= (size_t)2 * aplane && w->r32_x.bytes >= (size_t)w->nw * tb.x_wstride,
+              AFQ_E_STATE, "propagator build (split BF16): operands not prepared");
+    hipLaunchKernelGGL(pack_cplx_rows_bf3_kernel, dim3(grid_of((long)nchunk * rows * 32)), dim3(256), 0, st, coef,
+                       (long)s->X, w->nw, (long)s->X, rows, nchunk, aplane / 2, w->r32_coef.as<unsigned short>());
+    AFQ_TRY_HIP(hipGetLastError());
+    HornerB3Args g{};
+    g.a = w->r32_coef.as<unsigned char>();
+    g.b = s->chol3.as<unsigned char>();
+    g.rows_a = rows;
+    g.rows_b = tc.rows;
+    g.a_plane = aplane;
+    g.b_plane = bplane;
+    g.nchunk = nchunk;
+    g.nblk_a = (int)(rows / GeoAB::RA);
+    g.nblk_b = (int)(tc.rows / GeoAB::RB);
+    g.nw = w->nw;
+    const long grid = (long)g.nblk_a * g.nblk_b;
+    AFQ_CHECK(rows % GeoAB::RA == 0 && tc.rows % GeoAB::RB == 0 && grid < (1L << 30), AFQ_E_INVALID,
+              "propagator build (split BF16): bad shape");
+    g.grid = (int)grid;
+    g.M = s->M;
+    g.tri = s->tri8.as<int>();
+    g.x = w->r32_x.as<unsigned char>();
+    g.x_rows = tb.x_rows;
+    g.x_plane = tb.x_plane;
+    g.x_wstride = tb.x_wstride;
+    g.ncol = tc.ncol;
+    const long launch = (grid + NXCD - 1) / NXCD * NXCD;
+    hipLaunchKernelGGL((horner_bf3_kernel<GeoAB::TA, GeoAB::TB, B3_XFORM>), dim3((unsigned)launch), dim3(256), 0, st,
+                       g);
+    return hip_status(hipGetLastError(), "propagator build (split BF16)");
+  }
   const int nchunk = (int)(pad_to(s->X, RK) / RK);
   const TaylorShape ts = taylor_shape(s);
   AFQ_CHECK(s->chol32t.p && w->r32_coef.bytes >= (size_t)nchunk * rows * RK * sizeof(float) &&
