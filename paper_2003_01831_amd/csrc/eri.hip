@@ -57,6 +57,7 @@ struct EriArgs {
   int nunit, nblk_b, grid;     // grid: units x column blocks (launched rounded up to a multiple of 8)
   const double2* thetaT;       // nw x ntot x M
   int ntot, M, off, NM, nw;
+  int off1, nsp;               // column walkers nsp * nw: walker w of spin 1 (offset off1) at nw + w
   double2* part;               // [unit][rows_b]
 };
 
@@ -147,9 +148,11 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
   for (int j = 0; j < TB; ++j) {
     sre[j] = sim[j] = 0.0;
     const long C = brow0 + brow + 16 * j + lr;
-    const int wk = (int)(C >> 1), pt = (int)(C & 1);
-    const bool okc = wk < g.nw;
-    const double2* th = g.thetaT + ((long)(okc ? wk : 0) * g.ntot + g.off) * g.M;
+    const int wc = (int)(C >> 1), pt = (int)(C & 1);
+    const bool okc = wc < g.nsp * g.nw;
+    const bool s1 = wc >= g.nw;
+    const int wk = okc ? wc - (s1 ? g.nw : 0) : 0;
+    const double2* th = g.thetaT + ((long)wk * g.ntot + (s1 ? g.off1 : g.off)) * g.M;
 #pragma unroll
     for (int i = 0; i < TA; ++i)
 #pragma unroll
@@ -219,8 +222,9 @@ __global__ void eri_pack_w_kernel(const double* __restrict__ W, int M, int NM, l
 
 // Theta-hat rows C = 2 w + part of one spin into chunk-major hi / lo planes:
 // one thread per (chunk, walker, element of the chunk), both parts
-__global__ void eri_pack_theta_kernel(const double2* __restrict__ thetaT, int ntot, int M, int off, int NM, int nw,
-                                      long rows_b, int nchunk, unsigned short* __restrict__ hi,
+// (nsp = 2: walker w of spin 1, at offset off1, is column walker nw + w)
+__global__ void eri_pack_theta_kernel(const double2* __restrict__ thetaT, int ntot, int M, int off, int off1, int nsp,
+                                      int NM, int nw, long rows_b, int nchunk, unsigned short* __restrict__ hi,
                                       unsigned short* __restrict__ lo) {
   const long hw = rows_b / 2;
   const long total = (long)nchunk * hw * KC;
@@ -228,7 +232,10 @@ __global__ void eri_pack_theta_kernel(const double2* __restrict__ thetaT, int nt
     const long c = e / (hw * KC), rem = e - c * hw * KC;
     const long wk = rem / KC, jj = rem - wk * KC, J = c * KC + jj;
     double2 v = make_double2(0.0, 0.0);
-    if (wk < nw && J < NM) v = thetaT[(wk * ntot + off) * M + J];
+    if (wk < (long)nsp * nw && J < NM) {
+      const bool s1 = wk >= nw;
+      v = thetaT[((wk - (s1 ? nw : 0)) * ntot + (s1 ? off1 : off)) * M + J];
+    }
     const long o = (c * rows_b + 2 * wk) * KC + jj;
     const float fr = (float)v.x, fi = (float)v.y;
     const unsigned short hr = bf16_rne(fr), him = bf16_rne(fi);
@@ -441,9 +448,13 @@ int eri_sync(afq_system s) {
 
 size_t eri_tensor_bytes(afq_system s) { return s->eri_w[0].bytes + s->eri_w[1].bytes; }
 
+// spins contracted per launch: both when they share the tensor (one pass over
+// W'' for twice the columns), else one
+static int eri_nsp(afq_system s) { return s->eri_share ? 2 : 1; }
+
 int eri_alloc_scratch(afq_system s, afq_walkers w) {
   if (!s->eri_ready) return AFQ_OK;
-  const long rows_b = rows_b_of(w->nw);
+  const long rows_b = rows_b_of(eri_nsp(s) * w->nw);
   size_t tb = 0, pb = 0;
   for (int sp = 0; sp < 2; ++sp) {
     const Shape h = shape_of(s, sp);
@@ -457,14 +468,16 @@ int eri_alloc_scratch(afq_system s, afq_walkers w) {
 
 int eri_pack(afq_system s, afq_walkers w, int sp, hipStream_t st) {
   const Shape h = shape_of(s, sp);
-  const long rows_b = rows_b_of(w->nw);
+  const int nsp = eri_nsp(s);
+  const long rows_b = rows_b_of(nsp * w->nw);
   const size_t pb = plane_bytes(rows_b, h.nchunk);
   AFQ_CHECK(s->eri_ready && w->eri_theta.bytes >= 2 * pb, AFQ_E_STATE,
             "exchange (four-index): walker scratch not prepared");
+  AFQ_CHECK(nsp == 1 || sp == 0, AFQ_E_INVALID, "exchange (four-index): shared tensor packs both spins at once");
   unsigned short* th = w->eri_theta.as<unsigned short>();
   hipLaunchKernelGGL(eri_pack_theta_kernel, dim3(grid_of((long)h.nchunk * (rows_b / 2) * KC)), dim3(256), 0, st,
-                     w->theta.as<double2>(), s->ntot, s->M, s->spin_off(sp), (int)h.NM, w->nw, rows_b, h.nchunk, th,
-                     th + pb / 2);
+                     w->theta.as<double2>(), s->ntot, s->M, s->spin_off(sp), s->spin_off(1), nsp, (int)h.NM, w->nw,
+                     rows_b, h.nchunk, th, th + pb / 2);
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }
@@ -472,7 +485,9 @@ int eri_pack(afq_system s, afq_walkers w, int sp, hipStream_t st) {
 int eri_exchange(afq_system s, afq_walkers w, int sp, hipStream_t st) {
   const Shape h = shape_of(s, sp);
   const int wsp = s->eri_share ? 0 : sp;
-  const long rows_b = rows_b_of(w->nw);
+  const int nsp = eri_nsp(s);
+  AFQ_CHECK(nsp == 1 || sp == 0, AFQ_E_INVALID, "exchange (four-index): shared tensor contracts both spins at once");
+  const long rows_b = rows_b_of(nsp * w->nw);
   const size_t pa = plane_bytes(h.rows_a, h.nchunk), pb = plane_bytes(rows_b, h.nchunk);
   const int nunit = s->eri_nunit[wsp];
   AFQ_CHECK(s->eri_ready && nunit > 0 && s->eri_w[wsp].bytes >= 2 * pa, AFQ_E_STATE,
@@ -494,12 +509,15 @@ int eri_exchange(afq_system s, afq_walkers w, int sp, hipStream_t st) {
   g.grid = (int)grid;
   g.thetaT = w->theta.as<double2>();
   g.ntot = s->ntot; g.M = s->M; g.off = s->spin_off(sp); g.NM = (int)h.NM; g.nw = w->nw;
+  g.off1 = s->spin_off(1); g.nsp = nsp;
   g.part = w->eri_part.as<double2>();
   const long launch = (grid + NXCD - 1) / NXCD * NXCD;
   hipLaunchKernelGGL(eri_kernel, dim3((unsigned)launch), dim3(256), 0, st, g);
   AFQ_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(eri_reduce_kernel, dim3(w->nw), dim3(256), 0, st, w->eri_part.as<double2>(), nunit, rows_b,
-                     w->nw, sp, s->X, w->troo.as<double2>());
-  AFQ_TRY_HIP(hipGetLastError());
+  for (int q = 0; q < nsp; ++q) {   // spin sp + q: columns 2 (q nw + w) + part
+    hipLaunchKernelGGL(eri_reduce_kernel, dim3(w->nw), dim3(256), 0, st, w->eri_part.as<double2>() + 2L * q * w->nw,
+                       nunit, rows_b, w->nw, sp + q, s->X, w->troo.as<double2>());
+    AFQ_TRY_HIP(hipGetLastError());
+  }
   return AFQ_OK;
 }

@@ -160,8 +160,8 @@ static int energy_from_theta(afq_system s, afq_walkers w, AssembleArgs& a, bool 
     AFQ_RET(msd_energy(s, w, logdet, st));
     a.parts_in = w->msd_parts.as<double2>();
     a.vbar_in = w->msd_vbar.as<double2>();
-  } else if (s->eri_ready) {   // four-index exchange; the Coulomb traces below
-    for (int sp = 0; sp < 2; ++sp) {
+  } else if (s->eri_ready) {   // four-index exchange (both spins in one launch when they share the tensor)
+    for (int sp = 0; sp < (s->eri_share ? 1 : 2); ++sp) {
       {
         TraceScope t(AFQ_PH_PACK, st);
         AFQ_RET(eri_pack(s, w, sp, st));
