@@ -451,9 +451,11 @@ def main(argv=None):
     if form == "four_index":
         # the quadratic form Theta^T W Theta over the upper block triangle of the
         # symmetric half-rotated tensor: (N M)^2 / 2 real-by-complex multiply-adds
-        # (4 flop each) per walker and spin, one spin per launch
+        # (4 flop each) per walker and spin; spins that share the tensor are
+        # contracted in one launch (one exchange phase per step), else one each
         NM = nu * M
-        per_launch_flops = 2.0 * NM * NM * nw
+        spins_per_launch = 2 if ex_cnt <= a.steps else 1
+        per_launch_flops = 2.0 * NM * NM * nw * spins_per_launch
         traffic = None
         if a.workload == "m400" and nw == 512:
             traffic = profiled_traffic(os.path.join(csrc, "eri.hip"),
@@ -461,7 +463,8 @@ def main(argv=None):
         roofline = {"bound": "mfma", "achieved": round(per_launch_flops / ex_avg_s / 1e12, 3), "peak": peak,
                     "unit": "TFLOP/s", "traffic": traffic,
                     "kernel": "four-index exchange kernel (W'' Theta-hat in split BF16x3, FP64 epilogue) "
-                              "plus its per-walker reduction, one spin per launch",
+                              "plus its per-walker reductions, %d spin%s per launch"
+                              % (spins_per_launch, "s" if spins_per_launch > 1 else ""),
                     "flop_per_launch": per_launch_flops,
                     "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt}
         roofline["frac"] = round(roofline["achieved"] / peak, 4)
@@ -470,7 +473,7 @@ def main(argv=None):
         roofline["mfma_pipe_frac"] = round(3 * roofline["achieved"] / peak, 4)
         # the same exchange term counted with the Cholesky-form model, for comparison
         roofline["cholesky_model_equivalent_tflops"] = round(
-            (8.0 * X * nu * nu * M + 8.0 * X * nu * nu) * nw / ex_avg_s / 1e12, 3)
+            (8.0 * X * nu * nu * M + 8.0 * X * nu * nu) * nw * spins_per_launch / ex_avg_s / 1e12, 3)
     else:
         # the exchange term of the general (complex L~) flop model, one spin per
         # launch; the real-L~ count the kernel actually needs is beside it
