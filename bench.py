@@ -371,8 +371,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the walker step shards by walkers and this build "
-              "measures one GPU's share (see DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the walker step shards by walkers (each GPU steps its own "
+              "walkers, only the weighted energy sums are combined), so one GPU's share is the measured "
+              "unit; use --gpus 1", file=sys.stderr)
         return 2
 
     import torch
