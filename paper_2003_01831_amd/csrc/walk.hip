@@ -288,17 +288,23 @@ int propagate_walkers(afq_system s, afq_walkers w, int order, const void* coef, 
   return propagate<float>(s, w, order, static_cast<const float*>(coef), Win, Wout);
 }
 
-// CholeskyQR2 of every spin block of every walker: dst^s = (src^s R1^-1) R2^-1,
-// the first pass written to mid (all three nw x M x ntot complex).
+// CholeskyQR of every spin block of every walker (positive diagonal R). FP64
+// mode runs two passes, dst^s = (src^s R1^-1) R2^-1 with the first written to
+// mid (all three nw x M x ntot complex), so that Q is orthonormal to FP64
+// rounding whatever the conditioning. The reduced modes run one pass: its
+// loss of orthogonality, about cond(W)^2 times the FP64 unit roundoff, is far
+// below their own rounding for walkers re-orthonormalised every few steps, and
+// the step depends on W only through its column span.
 int qr_orbitals(afq_system s, afq_walkers w, const double2* src0, double2* mid, double2* dst0) {
   hipStream_t st = s->stream;
   const int M = s->M, ntot = s->ntot, nw = w->nw;
   const long per = (long)M * ntot;
   const int nmax = std::max(s->n_up, s->n_dn);
   const long nm2 = (long)nmax * nmax;
+  const int npass = s->prec == AFQ_FP64 ? 2 : 1;
   const double2* in[2] = {src0, mid};
-  double2* out[2] = {mid, dst0};
-  for (int pass = 0; pass < 2; ++pass) {
+  double2* out[2] = {npass == 2 ? mid : dst0, dst0};
+  for (int pass = 0; pass < npass; ++pass) {
     const double* src = reinterpret_cast<const double*>(in[pass]);
     double* dst = reinterpret_cast<double*>(out[pass]);
     for (int sp = 0; sp < 2; ++sp) {
