@@ -125,6 +125,8 @@ struct afq_system_s {
   DevBuf b1x3;                 // split-BF16x3 mode: the same as BF16 hi / lo planes
   double b1x3_dt = -1.0;
   DevBuf lt32[2];              // split-BF16x3, real trial: Lt rows n of each spin, FP32 packed [J / 16][n][J % 16]
+  bool lt_share = false;       // the two trial blocks are equal: lt32[1] is not built, the force bias contracts
+                               // Theta_up + Theta_dn with lt32[0]
   DevBuf hp;                   // h' = h - 1/2 sum L L   (M x M f64)
   DevBuf B1;                   // exp(-dt h'/2)          (M x M f64)
   double B1_dt = -1.0;

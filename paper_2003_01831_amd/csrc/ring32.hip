@@ -40,6 +40,7 @@
 // (O(sqrt(dt)) per Cholesky vector), so the BF16 products' rounding reaches U
 // damped by |A|; the last product is still added to V in FP64.
 #include <algorithm>
+#include <vector>
 #include <type_traits>
 #include "common.h"
 #include "mfma_ring.h"
@@ -838,8 +839,9 @@ __global__ void pack_b1_kernel(const double* __restrict__ B1, int M, long rows, 
 }
 
 // tro[w][spin][n] = sum over runs (fixed order) of (part[run][2w][n], part[run][2w + 1][n])
+// (with both: the traces of the spin sum, written to spin 0, and zero to spin 1)
 __global__ void coulomb_reduce_kernel(const float* __restrict__ part, int nrun, long rows_a, long rows_b, int nw,
-                                      int X, int spin, double2* __restrict__ tro) {
+                                      int X, int spin, int both, double2* __restrict__ tro) {
   const long t = blockIdx.x * 256L + threadIdx.x;
   if (t >= (long)nw * X) return;
   const int w = (int)(t / X), n = (int)(t - (long)w * X);
@@ -850,6 +852,24 @@ __global__ void coulomb_reduce_kernel(const float* __restrict__ part, int nrun, 
     im += (double)p[(2L * w + 1) * rows_b + n];
   }
   tro[((long)w * 2 + spin) * X + n] = make_double2(re, im);
+  if (both) tro[((long)w * 2 + 1) * X + n] = make_double2(0.0, 0.0);
+}
+
+// Theta-hat of the spin sum as real rows (w, Re|Im), k-contiguous:
+// out[(c rows + r) 16 + kk] = component (r & 1) of src[(r >> 1) ld + k] + src[(r >> 1) ld + off1 + k]
+__global__ void pack_cplx_rows_sum_kernel(const double* __restrict__ src, long ld, long off1, int nrow_c, long K,
+                                          long rows, int nchunk, float* __restrict__ out) {
+  const long total = (long)nchunk * rows * RK;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const long c = e / (rows * RK), rem = e - c * rows * RK;
+    const long r = rem / RK, k = c * RK + (rem - r * RK);
+    float v = 0.f;
+    if ((r >> 1) < nrow_c && k < K) {
+      const long i = 2 * ((r >> 1) * ld + k) + (r & 1);
+      v = (float)(src[i] + src[i + 2 * off1]);
+    }
+    out[e] = v;
+  }
 }
 
 int grid_of(long total) { return (int)std::min<long>(std::max<long>((total + 255) / 256, 1), 1 << 20); }
@@ -1068,7 +1088,22 @@ int r32_prepare(afq_system s) {
   const bool coul = s->prec == AFQ_BF16X3 && s->real_trial && s->kp_nk == 0 && s->msd_n == 0;
   if (coul && !s->lt32[0].p) {
     AFQ_CHECK(s->LtRe.p, AFQ_E_STATE, "force bias (FP32 ring): real half-rotated vectors missing");
-    for (int sp = 0; sp < 2; ++sp) {
+    // equal trial blocks give equal half-rotated vectors: one contraction with
+    // the spin sum of Theta replaces the two (the assembly only needs the sum)
+    bool same = s->n_up == s->n_dn;
+    if (same) {
+      const int M = s->M, ntot = s->ntot;
+      std::vector<double2> ph((size_t)M * ntot);
+      AFQ_TRY_HIP(hipMemcpyAsync(ph.data(), s->phi.p, ph.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+      AFQ_TRY_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < M && same; ++i)
+        for (int a = 0; a < s->n_up && same; ++a) {
+          const double2 x = ph[(size_t)i * ntot + a], y = ph[(size_t)i * ntot + s->n_up + a];
+          same = x.x == y.x && x.y == y.y;
+        }
+    }
+    s->lt_share = same;
+    for (int sp = 0; sp < (same ? 1 : 2); ++sp) {
       const long NM = (long)s->nspin_n(sp) * s->M;
       const long rows = pad_to(s->X, GeoAB::RB);
       const int nchunk = (int)(pad_to(NM, RK) / RK);
@@ -1081,6 +1116,7 @@ int r32_prepare(afq_system s) {
   } else if (!coul && s->lt32[0].p) {
     s->lt32[0].free();
     s->lt32[1].free();
+    s->lt_share = false;
   }
   if (!reduced && s->chol32t.p) {
     s->chol32t.free();
@@ -1321,9 +1357,11 @@ int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st) {
 }
 
 int r32_coulomb(afq_system s, afq_walkers w, hipStream_t st) {
-  AFQ_CHECK(s->lt32[0].p, AFQ_E_STATE, "force bias (FP32 ring): operands not prepared");
+  AFQ_CHECK(s->lt32[0].p && (s->lt_share || s->lt32[1].p), AFQ_E_STATE,
+            "force bias (FP32 ring): operands not prepared");
   const long rows = coef_rows(w->nw), rows_b = pad_to(s->X, GeoAB::RB);
-  for (int sp = 0; sp < 2; ++sp) {
+  const bool both = s->lt_share;   // one contraction of the spin sum (equal trial blocks)
+  for (int sp = 0; sp < (both ? 1 : 2); ++sp) {
     const long NM = (long)s->nspin_n(sp) * s->M;
     const int nchunk = (int)(pad_to(NM, RK) / RK);
     const int kper = coulomb_kper(nchunk, rows, rows_b);
@@ -1332,9 +1370,15 @@ int r32_coulomb(afq_system s, afq_walkers w, hipStream_t st) {
                   w->r32_part.bytes >= (size_t)nrun * rows * rows_b * sizeof(float),
               AFQ_E_STATE, "force bias (FP32 ring): walker scratch not prepared");
     // Theta-hat rows (w, Re|Im): thetaT[w][off + a][k] at (a, k) -> a M + k
-    hipLaunchKernelGGL(pack_cplx_rows_kernel<double>, dim3(grid_of((long)nchunk * rows * RK)), dim3(256), 0, st,
-                       reinterpret_cast<const double*>(w->theta.as<double2>() + (long)s->spin_off(sp) * s->M),
-                       (long)s->ntot * s->M, w->nw, NM, rows, nchunk, w->r32_theta.as<float>());
+    // (with both: thetaT[w][a][k] + thetaT[w][n_up + a][k])
+    const double* th = reinterpret_cast<const double*>(w->theta.as<double2>() + (long)s->spin_off(sp) * s->M);
+    if (both)
+      hipLaunchKernelGGL(pack_cplx_rows_sum_kernel, dim3(grid_of((long)nchunk * rows * RK)), dim3(256), 0, st, th,
+                         (long)s->ntot * s->M, (long)s->spin_off(1) * s->M, w->nw, NM, rows, nchunk,
+                         w->r32_theta.as<float>());
+    else
+      hipLaunchKernelGGL(pack_cplx_rows_kernel<double>, dim3(grid_of((long)nchunk * rows * RK)), dim3(256), 0, st,
+                         th, (long)s->ntot * s->M, w->nw, NM, rows, nchunk, w->r32_theta.as<float>());
     AFQ_TRY_HIP(hipGetLastError());
     R32Args g{};
     g.a = w->r32_theta.as<unsigned char>();
@@ -1347,7 +1391,8 @@ int r32_coulomb(afq_system s, afq_walkers w, hipStream_t st) {
     g.part = w->r32_part.as<float>();
     AFQ_RET((launch<GeoAB, EPI_PART>(g, st)));
     hipLaunchKernelGGL(coulomb_reduce_kernel, dim3(grid_of((long)w->nw * s->X)), dim3(256), 0, st,
-                       w->r32_part.as<float>(), nrun, rows, rows_b, w->nw, s->X, sp, w->tro.as<double2>());
+                       w->r32_part.as<float>(), nrun, rows, rows_b, w->nw, s->X, sp, both ? 1 : 0,
+                       w->tro.as<double2>());
     AFQ_TRY_HIP(hipGetLastError());
   }
   return AFQ_OK;
