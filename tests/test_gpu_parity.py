@@ -242,6 +242,28 @@ def test_walkers_replaced_between_steps(api, prec):
         assert torch.equal(got[k], ref[k]), k
 
 
+def test_precision_switch_between_steps(api):
+    """The FP32 and the split-BF16 propagator kernels pack their operands in
+    different layouts with zero padding in different places: walkers continued
+    after a precision switch equal fresh walkers started from the same state."""
+    s = synth.make_system(37, 9, 6, 70, seed=8)
+    nw = 5
+    sysg = api.System.from_synth(s, precision="cfp32")
+    a = api.Walkers(sysg, nw)
+    a.step(3, 0.01, seed=2, qr_every=2)
+    for prec in ("bf16x3", "cfp32", "bf16x3"):
+        sysg.set_precision(prec)
+        st = a.get()
+        b = api.Walkers(sysg, nw)
+        b.set(st["W"], st["weights"], st["alive"], st["counter"])
+        got = a.step(3, 0.01, seed=2, qr_every=2)
+        ref = b.step(3, 0.01, seed=2, qr_every=2)
+        torch.cuda.synchronize()
+        for k in ("eloc", "weights", "ratio"):
+            assert torch.equal(got[k], ref[k]), (prec, k)
+        b.close()
+
+
 def test_repeatable_bitwise(api):
     """Fixed-order reductions: two identical runs agree bit for bit."""
     s = synth.make_system(40, 10, 10, 80, seed=6)
