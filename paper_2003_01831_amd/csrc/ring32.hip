@@ -387,6 +387,12 @@ struct HornerB3Args {
   const int* tri;
   unsigned char* x;
   long x_rows, x_plane, x_wstride, ncol;
+  // B3_B1, optional: the new U also as V of the Taylor products, in the FP32
+  // packed term layout (vp) and as BF16 term planes (vb, laid out as yout)
+  float* vp;
+  long vp_rows, vp_wstride;
+  unsigned char* vb;
+  long vb_rows, vb_plane, vb_wstride;
 };
 
 enum { B3_HORNER = 0, B3_HORNER_LAST = 1, B3_B1 = 2, B3_XFORM = 3 };
@@ -577,8 +583,20 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
         for (int h = 0; h < 2; ++h) {
           bool ok;
           const long idx = at(i, j, h, ok);
-          if (ok)
-            g.u[idx] = make_double2(cur[j][h].x + (double)acc[i][j][2 * h], cur[j][h].y + (double)acc[i][j][2 * h + 1]);
+          if (!ok) continue;
+          const double2 nv = make_double2(cur[j][h].x + (double)acc[i][j][2 * h], cur[j][h].y + (double)acc[i][j][2 * h + 1]);
+          g.u[idx] = nv;
+          if (g.vp) {
+            const long n = ((arow0 + arow + 16 * i + 4 * lq) >> 1) + h;
+            const long m = brow0 + brow + 16 * j + lr;
+            const float2 f = make_float2((float)nv.x, (float)nv.y);
+            *reinterpret_cast<float2*>(g.vp + (long)w * g.vp_wstride + ((m >> 3) * g.vp_rows + n) * RK + 2 * (m & 7)) = f;
+            unsigned hi, lo;
+            split_pair(f.x, f.y, hi, lo);
+            unsigned char* y = g.vb + (long)w * g.vb_wstride + ((m >> 4) * g.vb_rows + n) * ROWB + 4 * (m & 15);
+            *reinterpret_cast<unsigned*>(y) = hi;
+            *reinterpret_cast<unsigned*>(y + g.vb_plane) = lo;
+          }
         }
         continue;
       }
@@ -999,7 +1017,9 @@ int r32_prepare_b1(afq_system s) {
   return AFQ_OK;
 }
 
-int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStream_t st) {
+bool r32_b1_packs_terms(afq_system s) { return taylor_b3(s); }
+
+int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStream_t st, bool pack_terms) {
   if (taylor_b3(s)) {
     const B1B3Shape b = b1_b3_shape(s);
     AFQ_CHECK(s->b1x3.p && s->b1x3_dt == s->B1_dt && w->r32_layout == 2 &&
@@ -1028,6 +1048,20 @@ int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStre
     g.ubase = in;
     g.ntot = s->ntot;
     g.M = s->M;
+    if (pack_terms) {   // out is V of the Taylor products: write it in their packed layouts too
+      const TaylorShape ts = taylor_shape(s);
+      const TaylorB3Shape t3 = taylor_b3_shape(s);
+      AFQ_CHECK(w->r32_y[0].bytes >= (size_t)w->nw * ts.y_wstride * sizeof(float) &&
+                    w->r32_y[2].bytes >= (size_t)w->nw * t3.y_wstride,
+                AFQ_E_STATE, "B1 product (split BF16): term scratch not prepared");
+      g.vp = w->r32_y[0].as<float>();
+      g.vp_rows = ts.y_rows;
+      g.vp_wstride = ts.y_wstride;
+      g.vb = w->r32_y[2].as<unsigned char>();
+      g.vb_rows = t3.y_rows;
+      g.vb_plane = t3.y_plane;
+      g.vb_wstride = t3.y_wstride;
+    }
     const long launch = (grid + NXCD - 1) / NXCD * NXCD;
     hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, B3_B1>), dim3((unsigned)launch), dim3(256), 0, st, g);
     return hip_status(hipGetLastError(), "B1 product (split BF16)");
@@ -1259,7 +1293,7 @@ int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st) {
 }
 
 // U <- T_K(A) U in Horner form with split-BF16x3 products
-static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st) {
+static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st, bool terms_packed) {
   const TaylorShape ts = taylor_shape(s);
   const TaylorB3Shape tb = taylor_b3_shape(s);
   AFQ_CHECK(w->r32_layout == 2 && w->r32_x.bytes >= (size_t)w->nw * tb.x_wstride &&
@@ -1269,14 +1303,17 @@ static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st)
   AFQ_CHECK(ts.y_rows == tb.y_rows && tb.y_rows % (32 * B3_TA) == 0 && tb.x_rows % (32 * B3_TB) == 0, AFQ_E_INVALID,
             "Taylor propagator (split BF16): bad shape");
   if (order < 1) return AFQ_OK;
-  // V in FP32 (added by every epilogue) and as BF16 planes (the first input)
-  hipLaunchKernelGGL(pack_terms_kernel, dim3(ceil_div(s->ntot, 32), ceil_div(s->M, 8), w->nw), dim3(256), 0, st,
-                     w->u.as<double2>(), s->M, s->ntot, ts.y_rows, ts.y_wstride, w->r32_y[0].as<float>());
-  AFQ_TRY_HIP(hipGetLastError());
-  hipLaunchKernelGGL(pack_terms_bf3_kernel, dim3(ceil_div(s->ntot, 16), ceil_div(s->M, 16), w->nw), dim3(256), 0, st,
-                     w->u.as<double2>(), s->M, s->ntot, tb.y_rows, tb.y_plane, tb.y_wstride,
-                     w->r32_y[2].as<unsigned char>());
-  AFQ_TRY_HIP(hipGetLastError());
+  // V in FP32 (added by every epilogue) and as BF16 planes (the first input),
+  // unless the B1 product that formed V wrote them
+  if (!terms_packed) {
+    hipLaunchKernelGGL(pack_terms_kernel, dim3(ceil_div(s->ntot, 32), ceil_div(s->M, 8), w->nw), dim3(256), 0, st,
+                       w->u.as<double2>(), s->M, s->ntot, ts.y_rows, ts.y_wstride, w->r32_y[0].as<float>());
+    AFQ_TRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(pack_terms_bf3_kernel, dim3(ceil_div(s->ntot, 16), ceil_div(s->M, 16), w->nw), dim3(256), 0,
+                       st, w->u.as<double2>(), s->M, s->ntot, tb.y_rows, tb.y_plane, tb.y_wstride,
+                       w->r32_y[2].as<unsigned char>());
+    AFQ_TRY_HIP(hipGetLastError());
+  }
   HornerB3Args g{};
   g.b = w->r32_x.as<unsigned char>();
   g.rows_a = tb.y_rows;
@@ -1315,8 +1352,8 @@ static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st)
   return AFQ_OK;
 }
 
-int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st) {
-  if (taylor_b3(s)) return r32_taylor_b3(s, w, order, st);
+int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st, bool terms_packed) {
+  if (taylor_b3(s)) return r32_taylor_b3(s, w, order, st, terms_packed);
   const TaylorShape ts = taylor_shape(s);
   const size_t yb = (size_t)w->nw * ts.y_wstride * sizeof(float);
   AFQ_CHECK(w->r32_x.bytes >= (size_t)w->nw * ts.x_wstride * sizeof(float) && w->r32_y[0].bytes >= yb &&
