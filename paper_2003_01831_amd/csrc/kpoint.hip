@@ -92,9 +92,18 @@ int kp_prepare_dt(afq_system s, double dt) {
   return AFQ_OK;
 }
 
-static size_t kp_lds_bytes(int nk, int m, int nmax, int xq) {
-  const size_t N = (size_t)nk * nmax, M = (size_t)nk * m, npar = 256 / std::max<size_t>(N, 1);
-  return ((size_t)m * N + M * nmax + npar * N * 3 + (size_t)xq * 3) * 16;
+// dynamic LDS of the trace kernel: the larger of the two spins' layouts
+// (Theta rows m x N, columns M x ns, the per-thread shares npar x N x 3, the
+// per-vector sums xq x 3, one pass's Lt rows npar x ns x m; N = nk ns and
+// npar = 256 / N vectors per pass, so a spin with fewer electrons can need more)
+static size_t kp_lds_bytes(int nk, int m, int nu, int nd, int xq) {
+  size_t need = 0;
+  for (int ns : {nu, nd}) {
+    if (ns < 1) continue;
+    const size_t N = (size_t)nk * ns, M = (size_t)nk * m, npar = 256 / N;
+    need = std::max(need, ((size_t)m * N + M * ns + npar * N * 3 + (size_t)xq * 3 + npar * ns * m) * 16);
+  }
+  return need;
 }
 
 int kp_system_create_impl(afq_system* out, int nk, const int32_t* kq, int m, int nu, int nd, int xq,
@@ -132,7 +141,7 @@ int kp_system_create_impl(afq_system* out, int nk, const int32_t* kq, int m, int
         AFQ_CHECK(kq[a * nk + kq[b * nk + c]] == kq[kq[a * nk + b] * nk + c], AFQ_E_INVALID,
                   "afq_kp_system_create: k-point table is not associative");
   const int M = nk * m, Nu = nk * nu, Nd = nk * nd, ntot = Nu + Nd, nkn = nu + nd;
-  const size_t lds = kp_lds_bytes(nk, m, std::max(nu, nd), xq);
+  const size_t lds = kp_lds_bytes(nk, m, nu, nd, xq);
   AFQ_CHECK(lds <= KP_MAX_LDS, AFQ_E_UNSUPPORTED, "afq_kp_system_create: the trace kernel needs more than 160 KB of LDS");
   afq_system s = new afq_system_s();
   int rc = [&]() -> int {
@@ -331,7 +340,9 @@ int kp_abuild(afq_system s, afq_walkers w, const double2* coef, hipStream_t st) 
 //   Omega'[c, (k1,a)]     = sum_l Ltd^{Q,k'}_n[b][l] Theta[(k'+Q, l), (k1, a)]
 // One thread owns one (n, c) and all a: it keeps the 2 x ns accumulators, so
 // each Theta / Ltd element it loads feeds ns multiply-adds. The Theta block
-// rows (k2, .) and the columns (k1, .) are staged in LDS once per workgroup;
+// rows (k2, .) and the columns (k1, .) are staged in LDS once per workgroup,
+// the Lt rows of the pass's vectors (shared by the N threads of a vector) once
+// per pass;
 // the row block's shares of tr(Omega Omega'), tr(Omega), tr(Omega') are summed
 // over the columns in a fixed order.
 // ---------------------------------------------------------------------------
@@ -359,6 +370,7 @@ __global__ __launch_bounds__(256) void kp_trace_kernel(KpTraceArgs a, int sp) {
   double2* thB = thA + (long)m * N;         // [r][aa]: Theta[r, (k1, aa)]
   double2* pp = thB + (long)M * ns;         // [npar][N][3]: per-thread shares of one pass
   double2* wp = pp + (long)npar * N * 3;    // [xq][3]
+  double2* ltb = wp + (long)a.xq * 3;       // [npar][a][l]: Lt^{Q,k2}_n of the pass's vectors
   const double2* th = a.thetaT + (long)w * a.ntot * M;
   for (int e = t; e < N * m; e += 256) {
     const int c = e / m, l = e - c * m;
@@ -373,9 +385,15 @@ __global__ __launch_bounds__(256) void kp_trace_kernel(KpTraceArgs a, int sp) {
   const int kp = c / ns, b = c - kp * ns;
   const int rb = a.kq[Q * nk + kp];         // row block k' + Q of Theta for Omega'
   for (int n0 = 0; n0 < a.xq; n0 += npar) {
+    for (int e = t; e < npar * NS * m; e += 256) {
+      const int p = e / (NS * m), r = e - p * (NS * m);   // r = a m + l
+      const int nn = n0 + p;
+      ltb[e] = nn < a.xq ? a.Lt[((((long)Q * nk + k2) * a.xq + nn) * nkn + aoff) * m + r] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
     const int n = n0 + nl;
     if (nl < npar && n < a.xq) {
-      const double2* lt = a.Lt + ((((long)Q * nk + k2) * a.xq + n) * nkn + aoff) * m;
+      const double2* lt = ltb + (long)nl * NS * m;
       const double2* ltd = a.Ltd + ((((long)Q * nk + kp) * a.xq + n) * nkn + aoff + b) * m;
       double2 om[NS], omd[NS];
 #pragma unroll
