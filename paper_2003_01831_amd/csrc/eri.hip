@@ -318,12 +318,12 @@ std::vector<int> make_units(const Shape& h, int kper) {
   return u;
 }
 
-// chunks per unit: about 512 units (with the walker blocks, a few thousand
+// chunks per unit: about 1024 units (with the walker blocks, several thousand
 // workgroups to fill the device several times over), runs of at least 16 chunks
 int choose_kper(const Shape& h) {
   long total = 0;
   for (int p = 0; p < h.nblk_a; ++p) total += h.nchunk - (long)TA * p;
-  const long target = 512;
+  const long target = 1024;
   return (int)std::max<long>(16, (total + target - 1) / target);
 }
 
