@@ -213,6 +213,9 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
     drawn by walker w in step bp_start + j (zero for frozen walkers), and
     out["bp_weights"] the weights at the end of the window. A comb inside the
     window hands every copy its source walker's history (ket and coefficients).
+    out["log_I"][k, w] is the complex log of the importance factor I of
+    walker w in step k, before the phaseless projection (zero for frozen
+    walkers).
     With msd = dict(dets=[...], coeffs=[...]) the trial is the orthogonal
     multi-determinant expansion of oracle/msd.py (phi_t is then unused):
     overlaps, E_L and the force bias come from its determinant sums, and the
@@ -241,7 +244,7 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
     out = dict(emix=np.zeros(n_steps), eloc=np.zeros((n_steps, nw), np.complex128),
                parts=np.zeros((n_steps, nw, 3), np.complex128),
                weights=np.zeros((n_steps, nw)), ratio=np.zeros((n_steps, nw), np.complex128),
-               cosdt=np.ones((n_steps, nw)))
+               log_I=np.zeros((n_steps, nw), np.complex128), cosdt=np.ones((n_steps, nw)))
     if record_walkers:
         out["walkers"] = np.zeros((n_steps,) + W.shape, np.complex128)
     def open_window():
@@ -284,6 +287,7 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
             log_r = logOn - logO[i]
             r = np.exp(log_r)
             log_I = log_r + importance_log_factor(x, xbar) + dt * e_shift
+            out["log_I"][k, i] = log_I
             cos_dth = np.cos(log_r.imag)
             wn = w[i] * np.exp(log_I.real) * cos_dth if cos_dth > 0.0 else 0.0
             out["ratio"][k, i] = r

@@ -125,7 +125,8 @@ def run(h, L, T, n_up, n_dn, W0, weights0, fields, dt, qr_every=5, e_shift=0.0, 
     start-of-step walker; QR every qr_every steps. With bp_start set, the
     back-propagation window of oracle/afqmc.run is recorded (coefficients
     i sqrt(dt) (z - zbar) of the 2X Hermitian operators out["ops"]); out["B1"]
-    is the one-body factor."""
+    is the one-body factor and out["log_I"][k, w] the complex log of the
+    importance factor I before the phaseless projection."""
     nw = W0.shape[0]
     X = L.shape[0]
     hp = one_body_corrected(h, L)
@@ -139,7 +140,8 @@ def run(h, L, T, n_up, n_dn, W0, weights0, fields, dt, qr_every=5, e_shift=0.0, 
     alive = w > 0
     n_steps = fields.shape[0]
     out = dict(emix=np.zeros(n_steps), eloc=np.zeros((n_steps, nw), np.complex128),
-               weights=np.zeros((n_steps, nw)), ratio=np.zeros((n_steps, nw), np.complex128))
+               weights=np.zeros((n_steps, nw)), ratio=np.zeros((n_steps, nw), np.complex128),
+               log_I=np.zeros((n_steps, nw), np.complex128))
     out.update(B1=B1, ops=ops)
     for k in range(n_steps):
         if bp_start == k:
@@ -163,6 +165,7 @@ def run(h, L, T, n_up, n_dn, W0, weights0, fields, dt, qr_every=5, e_shift=0.0, 
             logOn = afqmc.theta(T, Wn, n_up, n_dn)[1]
             log_r = logOn - logO[i]
             log_I = log_r + afqmc.importance_log_factor(x, xbar) + dt * e_shift
+            out["log_I"][k, i] = log_I
             cos_dth = np.cos(log_r.imag)
             wn = w[i] * np.exp(log_I.real) * cos_dth if cos_dth > 0.0 else 0.0
             out["ratio"][k, i] = np.exp(log_r)
