@@ -3,11 +3,15 @@
  *
  * The library implements the batched walker step of phaseless auxiliary-field
  * quantum Monte Carlo with a Cholesky-factorised two-electron tensor, for the
- * Hamiltonian of the paper's Eq. "hamil" (Section "Auxiliary Field Quantum
- * Monte Carlo"):
+ * second-quantised Hamiltonian of Eq. eq:hamil in Section sec:afqmc
+ * ("Auxiliary Field Quantum Monte Carlo") of arXiv 2003.01831:
  *
  *   H = sum_ij h_ij c+_i c_j + 1/2 sum_ijkl v_ijkl c+_i c+_j c_l c_k + E_II,
- *   v_ijkl = sum_n L^n_ik L^n*_lj        (modified-Cholesky form, same section)
+ *   v_ijkl = sum_n L^n_ik L^n*_lj   (the modified-Cholesky factorisation, the
+ *                                    equation after eq:hamil in sec:afqmc)
+ *
+ * Cost model of the walk (Table tab:afqmc_comp, dense 3-index row):
+ * propagation O(N M^2), energy O(x_c N^2 M^2) with X = x_c M vectors.
  *
  * Step equations (the paper cites them from the phaseless-AFQMC literature;
  * they follow from the two lines above by Wick's theorem and the
@@ -27,7 +31,9 @@
  *     afq_walkers_get/set, afq_fields_generate and afq_batch_step are DEVICE
  *     pointers on the device that was current when the system was created
  *     (for instance torch.Tensor.data_ptr() of a CUDA tensor). The pointers
- *     of afq_system_create and afq_walkers_create are device pointers too.
+ *     of afq_walkers_create are device pointers too; those of
+ *     afq_system_create are device pointers, or host pointers with the
+ *     AFQ_HOST_PTRS flag.
  *   - Complex arrays are interleaved (re, im) float64 pairs, row-major.
  *   - Orbital matrices (trial, walkers) are M x (n_up + n_dn): up-spin
  *     columns first, then down-spin columns.
@@ -74,10 +80,18 @@ typedef enum {
 } afq_precision;
 
 /* ------------------------------------------------------------------------ */
-/* System: h1, L^n, the trial and E_II (Eq. "hamil" and the Cholesky form).   */
+/* System: h1, L^n, the trial and E_II (Eq. eq:hamil and the Cholesky form).  */
 /* ------------------------------------------------------------------------ */
 
-/* Creates a system and copies the inputs into library-owned device memory
+/* afq_system_create flag: h1, chol and phi_t are host pointers (pageable or
+ * pinned). Without it they are device pointers on the current device. */
+#define AFQ_HOST_PTRS 1u
+
+/* Creates a system from the one-body matrix h_ij and E_II of Eq. eq:hamil,
+ * the Cholesky vectors L^n of the modified-Cholesky factorisation that
+ * follows it (Section sec:afqmc; real symmetric L^n, so v_ijkl =
+ * sum_n L^n_ik L^n_jl) and the trial determinant of the phaseless walk the
+ * same section names. Copies the inputs into library-owned device memory
  * (the caller may free its buffers on return; this call synchronises).
  *   M        number of spatial orbitals (1 <= M <= 4096)
  *   n_up/dn  electrons per spin (1 <= n <= min(M, 128))
@@ -89,18 +103,23 @@ typedef enum {
  *   e_core   E_II, added to every local energy
  *   precision one of afq_precision
  *   stream   hipStream_t (NULL = default stream) used by every later call
- * Errors: AFQ_E_INVALID for bad sizes, NULL pointers or an h1/L^n that is not
- * symmetric to 1e-12 (relative to its largest entry); AFQ_E_NOMEM. */
+ *   flags    0: h1, chol, phi_t are device pointers (stream-ordered copy);
+ *            AFQ_HOST_PTRS: they are host pointers
+ * Errors: AFQ_E_INVALID for bad sizes, NULL pointers, unknown flags or an
+ * h1/L^n that is not symmetric to 1e-12 (relative to its largest entry);
+ * AFQ_E_NOMEM; AFQ_E_HIP when a copy fails (for instance a host pointer
+ * passed without AFQ_HOST_PTRS). */
 int afq_system_create(afq_system *out, int M, int n_up, int n_dn, int n_chol,
                       const double *h1, const double *chol, const double *phi_t,
-                      double e_core, int precision, void *stream);
+                      double e_core, int precision, void *stream, unsigned flags);
 /* Switches the contraction precision (prepares the packed operand copies;
  * synchronises). */
 int afq_system_set_precision(afq_system s, int precision);
 
 /* Form of the exchange term sum_n tr(Omega_n Omega_n) of the local energy
- * (Eq. "EL" with the half-rotated Cholesky vectors of the AFQMC section's
- * computational-cost discussion). The Cholesky form contracts every vector
+ * (the two-body part of Eq. eq:hamil evaluated with half-rotated Cholesky
+ * vectors; its cost is the energy column of Table tab:afqmc_comp, dense
+ * 3-index row, O(x_c N^2 M^2)). The Cholesky form contracts every vector
  * (X N^2 M products per walker and spin); the four-index form uses
  *   sum_n tr(Omega_n Omega_n) = Theta^T W Theta,
  *   W[(b,k),(a,l)] = sum_n (T^H L^n)[a][k] (T^H L^n)[b][l],
@@ -187,7 +206,11 @@ int afq_system_destroy(afq_system s);
 /* Walkers: Slater determinants W (M x (n_up+n_dn) complex128) and weights.   */
 /* ------------------------------------------------------------------------ */
 
-/* w0: n_walkers*M*(n_up+n_dn) complex128, or NULL to start every walker at
+/* Creates the walker population of the phaseless AFQMC random walk (the
+ * method Section sec:afqmc names in its first paragraph, in the orbital-space
+ * form of Eq. eq:hamil): each walker is a Slater determinant W with a weight
+ * and its overlap with the trial.
+ * w0 (device): n_walkers*M*(n_up+n_dn) complex128, or NULL to start every walker at
  * the trial. weights0: n_walkers float64, or NULL for all ones. A walker with
  * weight 0 is dead (frozen). Synchronises; AFQ_E_SINGULAR if any live
  * walker's overlap with the trial is singular. */
@@ -195,7 +218,8 @@ int afq_walkers_create(afq_walkers *out, afq_system s, int n_walkers,
                        const double *w0, const double *weights0);
 int afq_walkers_destroy(afq_walkers w);
 
-/* Checkpoint/resume. W: n_walkers*M*Ntot complex128; weights: n_walkers;
+/* Checkpoint/resume of the walker state of afq_walkers_create (device
+ * pointers). W: n_walkers*M*Ntot complex128; weights: n_walkers;
  * logovlp: n_walkers complex128 (log of prod_s det(T^sH W^s), get only, may be
  * NULL); alive: n_walkers int32 (may be NULL); counter: the step counter that
  * keys the Philox fields (host pointer, may be NULL). */
@@ -241,7 +265,13 @@ int afq_eshift_update(double e_est, double w_total, double w_target, double dt, 
 /* Hot path.                                                                  */
 /* ------------------------------------------------------------------------ */
 
-/* Advances the walkers n_steps steps of length dt.
+/* Advances the walkers n_steps steps of the phaseless AFQMC walk (Section
+ * sec:afqmc, first paragraph: the method, and the Hubbard-Stratonovich
+ * transformation that the Cholesky vectors make possible); each step is the
+ * short-time propagator exp(-dt (H - E_shift)) of Eq. eq:hamil sampled over
+ * the auxiliary fields (the equations at the top of this file). Its cost is
+ * the propagation column of Table tab:afqmc_comp (dense 3-index row) plus one
+ * local energy per step.
  *   fields   NULL: standard-normal fields from the device Philox4x32-10
  *            generator keyed by (seed, step counter, walker, n); else
  *            n_steps*n_walkers*n_chol float64 fields x[k][w][n].
@@ -261,7 +291,10 @@ int afq_step(afq_system s, afq_walkers w, int n_steps, double dt,
              int taylor_order, double *emix_out, double *eloc_out,
              double *weights_out, double *ratio_out);
 
-/* Local energy at the current walkers.
+/* Local energy of the walkers, E_L = <T|H|W>/<T|W> for the Hamiltonian of
+ * Eq. eq:hamil with the Cholesky form of v_ijkl (Section sec:afqmc), in the
+ * half-rotated form given at the top of this file; its cost is the energy
+ * column of Table tab:afqmc_comp (dense 3-index row).
  *   eloc_out  n_walkers complex128 E_L (may be NULL)
  *   parts_out n_walkers*3 complex128 (E1, EJ, EK) (may be NULL)
  *   vbar_out  n_walkers*n_chol complex128 force bias vbar_n (may be NULL)
@@ -269,7 +302,12 @@ int afq_step(afq_system s, afq_walkers w, int n_steps, double dt,
 int afq_energy(afq_system s, afq_walkers w, double *eloc_out, double *parts_out,
                double *vbar_out, double *emix_out);
 
-/* Adjoint of  f = scale * sum_w w Re E_L / sum_w w  at the current walkers,
+/* Derivatives of the weighted mean local energy of afq_energy with respect to
+ * the inputs of Eq. eq:hamil (h_ij and the Cholesky vectors L^n of the
+ * factorisation after it, Section sec:afqmc) and the walker orbitals; the
+ * paper states the energy, not its derivative: this is the exact adjoint of
+ * that expression.
+ * Adjoint of  f = scale * sum_w w Re E_L / sum_w w  at the current walkers,
  * with the weights and the trial held fixed. Theta and Omega are recomputed; nothing
  * is stored from the forward call. Outputs (each may be NULL to skip):
  *   d_h1      M*M float64, df/dh_ij for every entry (not symmetrised)
@@ -279,14 +317,17 @@ int afq_energy(afq_system s, afq_walkers w, double *eloc_out, double *parts_out,
 int afq_energy_backward(afq_system s, afq_walkers w, double scale, double *d_h1,
                         double *d_chol, double *d_walkers);
 
-/* Standard-normal fields x[k][w][n] for steps step0..step0+n_steps-1 from the
+/* The auxiliary fields of the Hubbard-Stratonovich transformation (Section
+ * sec:afqmc, first paragraph), one per Cholesky vector, walker and step:
+ * standard-normal fields x[k][w][n] for steps step0..step0+n_steps-1 from the
  * device Philox4x32-10 generator (the same stream afq_step draws with
  * fields == NULL): counter (n/2, w, step, sys_id), key (seed lo, seed hi),
  * Box-Muller on two 53-bit uniforms. out: n_steps*n_walkers*n_chol float64. */
 int afq_fields_generate(uint64_t seed, uint32_t sys_id, uint64_t step0, int n_steps,
                         int n_walkers, int n_chol, double *out, void *stream);
 
-/* Autotuner of the fused exchange contraction (the dominant kernel): times
+/* Autotuner of the fused exchange contraction, the energy term that
+ * dominates the cost (Table tab:afqmc_comp, dense 3-index row): times
  * each launch variant (waves per workgroup, accumulator budget) of both spins
  * on these walkers' own shapes with HIP events, `reps` launches each, and keeps
  * the fastest for this walker set and for later walker sets of the same shape
@@ -340,7 +381,10 @@ int afq_bp_end(afq_walkers w);
 /* Many uneven systems in one captured launch sequence.                       */
 /* ------------------------------------------------------------------------ */
 
-/* Groups n (system, walkers) pairs that share one stream and precision.
+/* Many systems stepped together on one GPU (each is the walk of afq_step on
+ * its own Hamiltonian of Eq. eq:hamil; the GPU column of Table
+ * tab:afqmc_comp marks the dense 3-index and k-point paths as GPU ones).
+ * Groups n (system, walkers) pairs that share one stream and precision.
  * The handles must outlive the batch. */
 int afq_batch_create(afq_batch *out, int n, const afq_system *systems,
                      const afq_walkers *walkers);

@@ -16,13 +16,14 @@ STATUS = {0: "AFQ_OK", -1: "AFQ_E_INVALID", -2: "AFQ_E_NOMEM", -3: "AFQ_E_HIP", 
           -5: "AFQ_E_STATE", -6: "AFQ_E_UNSUPPORTED"}
 PRECISION = {"fp64": 0, "cfp32": 1, "bf16x3": 2}
 EXCHANGE_FORM = {"auto": 0, "cholesky": 1, "four_index": 2}
+AFQ_HOST_PTRS = 1          # afq_system_create flag: h1, chol and phi_t are host pointers
 PHASES = ["overlap", "pack", "exchange", "coulomb", "assemble", "abuild", "taylor", "weight", "qr", "msd_omega",
           "msd_sums"]
 
 # every symbol declared in include/afq.h with its ctypes signature
 _vp, _i, _d, _u64, _u32 = C.c_void_p, C.c_int, C.c_double, C.c_uint64, C.c_uint32
 SIGNATURES = {
-    "afq_system_create": (_i, [C.POINTER(_vp), _i, _i, _i, _i, _vp, _vp, _vp, _d, _i, _vp]),
+    "afq_system_create": (_i, [C.POINTER(_vp), _i, _i, _i, _i, _vp, _vp, _vp, _d, _i, _vp, _u32]),
     "afq_system_set_precision": (_i, [_vp, _i]),
     "afq_system_set_msd": (_i, [_vp, _vp, _i, _vp, _vp]),
     "afq_system_set_exchange_form": (_i, [_vp, _i]),

@@ -37,17 +37,30 @@ def _stream_handle(stream):
 
 
 class System:
-    """h1 (M x M), chol (X x M x M), trial phi_t (M x (n_up+n_dn)) and E_II."""
+    """h1 (M x M), chol (X x M x M), trial phi_t (M x (n_up+n_dn)) and E_II.
+
+    numpy inputs are handed to the library as host pointers (AFQ_HOST_PTRS:
+    one host-to-device copy, no staging tensors); torch tensors are moved to
+    the current device and handed over as device pointers. The library keeps
+    its own copies either way."""
 
     def __init__(self, h1, chol, phi_t, n_up, n_dn, e_core=0.0, precision="fp64", stream=None,
                  exchange_form="auto"):
         self.lib = _lib.load()
-        self.h1 = _as_dev(h1, torch.float64)
-        self.chol = _as_dev(chol, torch.float64)
-        self.phi_t = _as_dev(phi_t, torch.complex128)
-        self.M = int(self.h1.shape[0])
+        _dev()
+        host = all(isinstance(a, np.ndarray) for a in (h1, chol, phi_t))
+        if host:
+            ins = [np.ascontiguousarray(h1, dtype=np.float64), np.ascontiguousarray(chol, dtype=np.float64),
+                   np.ascontiguousarray(phi_t, dtype=np.complex128)]
+            ptrs = [C.c_void_p(a.ctypes.data) for a in ins]
+            flags = _lib.AFQ_HOST_PTRS
+        else:
+            ins = [_as_dev(h1, torch.float64), _as_dev(chol, torch.float64), _as_dev(phi_t, torch.complex128)]
+            ptrs = [_ptr(a) for a in ins]
+            flags = 0
+        self.M = int(ins[0].shape[0])
         self.n_up, self.n_dn = int(n_up), int(n_dn)
-        self.n_chol = int(self.chol.shape[0])
+        self.n_chol = int(ins[1].shape[0])
         self.e_core = float(e_core)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.precision = precision
@@ -55,10 +68,10 @@ class System:
         # automatic choice never builds a tensor that is dropped at once
         first = precision if exchange_form == "auto" else "fp64"
         h = C.c_void_p()
-        check(self.lib.afq_system_create(C.byref(h), self.M, self.n_up, self.n_dn, self.n_chol, _ptr(self.h1),
-                                         _ptr(self.chol), _ptr(self.phi_t), self.e_core, PRECISION[first],
-                                         _stream_handle(self.stream)))
+        check(self.lib.afq_system_create(C.byref(h), self.M, self.n_up, self.n_dn, self.n_chol, *ptrs,
+                                         self.e_core, PRECISION[first], _stream_handle(self.stream), flags))
         self.handle = h
+        del ins, ptrs                 # the create call synchronised; the library owns copies
         if exchange_form != "auto":
             self.set_exchange_form(exchange_form)
             self.set_precision(precision)

@@ -8,18 +8,41 @@ dEbar/dchol (every entry, not symmetrised) and dEbar/dW in torch's complex
 convention (d/dRe + i d/dIm); the trial and the weights are held fixed. The
 library recomputes Theta and Omega in the backward call instead of keeping
 them from the forward call.
+
+The system (h', B1, the half-rotated and packed copies of h1 and L^n) is
+built once and reused while the same h1, chol and phi_t tensors are passed
+unmodified (same objects, same in-place version counters), so a loop that
+only changes the walkers does not rebuild it; any change of those tensors
+builds a new one.
 """
 from __future__ import annotations
+
+import weakref
 
 import torch
 
 from . import api
 
+_cached = {"refs": None, "key": None, "system": None}
+
+
+def _system_for(h1, chol, phi_t, n_up, n_dn, e_core, precision):
+    ts = (h1, chol, phi_t)
+    key = tuple((t._version, tuple(t.shape), t.dtype, t.device) for t in ts) + (n_up, n_dn, e_core, precision)
+    refs = _cached["refs"]
+    if refs is not None and _cached["key"] == key and all(r() is t for r, t in zip(refs, ts)):
+        return _cached["system"]
+    # the previous system is freed once no pending backward holds it
+    _cached.update(refs=None, key=None, system=None)
+    sysg = api.System(h1.detach(), chol.detach(), phi_t.detach(), n_up, n_dn, e_core, precision)
+    _cached.update(refs=tuple(weakref.ref(t) for t in ts), key=key, system=sysg)
+    return sysg
+
 
 class LocalEnergy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, h1, chol, W, weights, phi_t, n_up, n_dn, e_core=0.0, precision="fp64"):
-        sysg = api.System(h1.detach(), chol.detach(), phi_t.detach(), n_up, n_dn, e_core, precision)
+        sysg = _system_for(h1, chol, phi_t, int(n_up), int(n_dn), float(e_core), precision)
         wk = api.Walkers(sysg, W.shape[0], W.detach(), weights.detach())
         _, _, _, emix = wk.energy()
         ctx.sysg, ctx.wk = sysg, wk
@@ -30,5 +53,4 @@ class LocalEnergy(torch.autograd.Function):
         scale = float(grad_out)
         d_h1, d_chol, d_w = api.energy_backward(ctx.sysg, ctx.wk, scale)
         ctx.wk.close()
-        ctx.sysg.close()
         return d_h1, d_chol, d_w, None, None, None, None, None, None

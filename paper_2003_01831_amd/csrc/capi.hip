@@ -8,7 +8,7 @@ static thread_local std::string g_last_error;
 void afq_set_error(const std::string& msg) { g_last_error = msg; }
 
 int system_create_impl(afq_system* out, int M, int n_up, int n_dn, int X, const double* h1, const double* chol,
-                       const double* phi_t, double e_core, int prec, void* stream);
+                       const double* phi_t, double e_core, int prec, void* stream, unsigned flags);
 int walkers_create_impl(afq_walkers* out, afq_system s, int nw, const double* w0, const double* wt0);
 int energy_call(afq_system s, afq_walkers w, double* eloc_out, double* parts_out, double* vbar_out,
                 double* emix_out);
@@ -41,8 +41,9 @@ const char* afq_last_error(void) { return g_last_error.c_str(); }
 int afq_version(void) { return (1 << 16) | 0; }
 
 int afq_system_create(afq_system* out, int M, int n_up, int n_dn, int n_chol, const double* h1, const double* chol,
-                      const double* phi_t, double e_core, int precision, void* stream) {
-  AFQ_GUARD(return system_create_impl(out, M, n_up, n_dn, n_chol, h1, chol, phi_t, e_core, precision, stream);)
+                      const double* phi_t, double e_core, int precision, void* stream, unsigned flags) {
+  AFQ_GUARD(return system_create_impl(out, M, n_up, n_dn, n_chol, h1, chol, phi_t, e_core, precision, stream,
+                                      flags);)
 }
 
 int afq_system_set_precision(afq_system s, int precision) {

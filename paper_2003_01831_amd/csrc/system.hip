@@ -122,7 +122,7 @@ int system_prepare_dt(afq_system s, double dt) {
 }
 
 int system_create_impl(afq_system* out, int M, int n_up, int n_dn, int X, const double* h1, const double* chol,
-                       const double* phi_t, double e_core, int prec, void* stream) {
+                       const double* phi_t, double e_core, int prec, void* stream, unsigned flags) {
   AFQ_CHECK(out, AFQ_E_INVALID, "afq_system_create: out is NULL");
   *out = nullptr;
   AFQ_CHECK(M >= 1 && M <= 4096, AFQ_E_INVALID, "afq_system_create: M must be in [1, 4096]");
@@ -133,6 +133,8 @@ int system_create_impl(afq_system* out, int M, int n_up, int n_dn, int X, const 
   AFQ_CHECK(h1 && chol && phi_t, AFQ_E_INVALID, "afq_system_create: NULL input array");
   AFQ_CHECK(prec >= AFQ_FP64 && prec <= AFQ_BF16X3, AFQ_E_INVALID, "afq_system_create: unknown precision");
   AFQ_CHECK(std::isfinite(e_core), AFQ_E_INVALID, "afq_system_create: e_core is not finite");
+  AFQ_CHECK((flags & ~AFQ_HOST_PTRS) == 0, AFQ_E_INVALID, "afq_system_create: unknown flag");
+  const hipMemcpyKind in_kind = (flags & AFQ_HOST_PTRS) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
   afq_system s = new afq_system_s();
   int rc = [&]() -> int {
     s->M = M; s->n_up = n_up; s->n_dn = n_dn; s->X = X; s->ntot = n_up + n_dn;
@@ -144,9 +146,11 @@ int system_create_impl(afq_system* out, int M, int n_up, int n_dn, int X, const 
     AFQ_RET(s->h1.alloc(mm * 8));
     AFQ_RET(s->chol.alloc((size_t)X * mm * 8));
     AFQ_RET(s->phi.alloc((size_t)M * s->ntot * 16));
-    AFQ_TRY_HIP(hipMemcpyAsync(s->h1.p, h1, mm * 8, hipMemcpyDeviceToDevice, st));
-    AFQ_TRY_HIP(hipMemcpyAsync(s->chol.p, chol, (size_t)X * mm * 8, hipMemcpyDeviceToDevice, st));
-    AFQ_TRY_HIP(hipMemcpyAsync(s->phi.p, phi_t, (size_t)M * s->ntot * 16, hipMemcpyDeviceToDevice, st));
+    // host inputs are pageable memory: the copies are complete once the
+    // stream is synchronised below, before this call returns
+    AFQ_TRY_HIP(hipMemcpyAsync(s->h1.p, h1, mm * 8, in_kind, st));
+    AFQ_TRY_HIP(hipMemcpyAsync(s->chol.p, chol, (size_t)X * mm * 8, in_kind, st));
+    AFQ_TRY_HIP(hipMemcpyAsync(s->phi.p, phi_t, (size_t)M * s->ntot * 16, in_kind, st));
     // validation: symmetry of h1 and every L^n, finiteness, real/complex trial
     DevBuf chk;
     AFQ_RET(chk.alloc(5 * sizeof(double)));

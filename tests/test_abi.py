@@ -40,13 +40,13 @@ def test_version(lib):
 
 def test_null_arguments_are_rejected(lib):
     h = C.c_void_p()
-    assert lib.afq_system_create(None, 8, 2, 2, 4, None, None, None, 0.0, 0, None) == -1
+    assert lib.afq_system_create(None, 8, 2, 2, 4, None, None, None, 0.0, 0, None, 0) == -1
     assert b"out" in lib.afq_last_error()
-    assert lib.afq_system_create(C.byref(h), 0, 2, 2, 4, None, None, None, 0.0, 0, None) == -1
-    assert lib.afq_system_create(C.byref(h), 8, 0, 2, 4, None, None, None, 0.0, 0, None) == -1
-    assert lib.afq_system_create(C.byref(h), 8, 2, 2, 0, None, None, None, 0.0, 0, None) == -1
-    assert lib.afq_system_create(C.byref(h), 300, 200, 2, 4, None, None, None, 0.0, 0, None) == -6
-    assert lib.afq_system_create(C.byref(h), 8, 2, 2, 4, None, None, None, 0.0, 0, None) == -1
+    assert lib.afq_system_create(C.byref(h), 0, 2, 2, 4, None, None, None, 0.0, 0, None, 0) == -1
+    assert lib.afq_system_create(C.byref(h), 8, 0, 2, 4, None, None, None, 0.0, 0, None, 0) == -1
+    assert lib.afq_system_create(C.byref(h), 8, 2, 2, 0, None, None, None, 0.0, 0, None, 0) == -1
+    assert lib.afq_system_create(C.byref(h), 300, 200, 2, 4, None, None, None, 0.0, 0, None, 0) == -6
+    assert lib.afq_system_create(C.byref(h), 8, 2, 2, 4, None, None, None, 0.0, 0, None, 0) == -1
     assert lib.afq_walkers_create(C.byref(h), None, 4, None, None) == -1
     assert lib.afq_step(None, None, 1, 0.01, None, 0, 5, 0.0, 6, None, None, None, None) == -1
     assert lib.afq_energy(None, None, None, None, None, None) == -1

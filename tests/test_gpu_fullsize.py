@@ -1,8 +1,10 @@
 """Parity at the full benchmark size (M=400, 100+100 electrons, 1600 Cholesky
 vectors, 512 walkers, dt 0.005) in the launch configuration the benchmark
-times. The oracle cannot afford 512 walkers, so 4 sampled walkers are checked
+times. The oracle cannot afford 512 walkers, so sampled walkers are checked
 one by one (walkers are independent given their fields) and the mixed energy
-is checked as the weighted mean of the GPU's own per-walker outputs."""
+is checked as the weighted mean of the GPU's own per-walker outputs. The walk
+takes 6 steps with QR every 5, so the re-orthonormalisation at 100 electrons
+per spin runs and the sixth step starts from its output."""
 import numpy as np
 import pytest
 
@@ -34,7 +36,7 @@ def test_full_size_sampled_walkers(full, prec, form, tol):
     four-index form at this size), and FP64."""
     from paper_2003_01831_amd import api
     cfg, s, pre = full
-    nw, steps, dt = cfg["n_walkers"], 2, cfg["dt"]
+    nw, steps, dt = cfg["n_walkers"], 6, cfg["dt"]
     fields = synth.make_fields(steps, nw, cfg["n_chol"], seed=cfg["field_seed"])
     sysg = api.System.from_synth(s, precision=prec, exchange_form=form)
     if prec == "bf16x3":
@@ -44,18 +46,22 @@ def test_full_size_sampled_walkers(full, prec, form, tol):
         _oracle_cache["e_var"] = afqmc.local_energy_plain(s.h1, s.chol, s.phi_t, s.phi_t, s.n_up, s.n_dn)[0].real
     e_var = _oracle_cache["e_var"]
     out = wk.step(steps, dt, fields=fields, qr_every=cfg["qr_every"], e_shift=e_var)
+    Wg = to_np(wk.get()["W"])
     torch.cuda.synchronize()
     g = {k: to_np(v) for k, v in out.items()}
-    sample = np.array([0, 137, 300, 511])
+    sample = np.array([0, 300, 511])
     if "run" not in _oracle_cache:
-        _oracle_cache["run"] = afqmc.run(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, synth.trial_walkers(s, 4),
-                                         np.ones(4), fields[:, sample], dt, qr_every=cfg["qr_every"],
-                                         e_shift=e_var, pre=pre)
+        _oracle_cache["run"] = afqmc.run(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn,
+                                         synth.trial_walkers(s, len(sample)), np.ones(len(sample)),
+                                         fields[:, sample], dt, qr_every=cfg["qr_every"], e_shift=e_var, pre=pre)
     o = _oracle_cache["run"]
     for k in ("eloc", "weights", "ratio"):
         err = rel_vec(g[k][:, sample], o[k])
         print(prec, form, k, f"{err:.2e}")
         assert err < tol, k
+    err = rel_fro(Wg[sample], o["W"])
+    print(prec, form, "W", f"{err:.2e}")
+    assert err < tol
     # E_mix is the weighted mean of the per-walker energies with the pre-step weights
     wprev = np.vstack([np.ones(nw), g["weights"][:-1]])
     ref = np.sum(wprev * g["eloc"].real, axis=1) / np.sum(wprev, axis=1)

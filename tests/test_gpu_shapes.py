@@ -1,0 +1,231 @@
+"""GPU parity at the shapes the workloads run, against the CPU FP64 oracle.
+
+Each case reaches a code path that a smaller test does not:
+  * QR re-orthonormalisation for 33..64, 65..100 and 101..128 electrons per
+    spin (the three larger register-block layouts of the Cholesky-QR and
+    Gauss-Jordan kernels), over walks long enough that QR fires twice and the
+    steps after it depend on the re-orthonormalised walkers;
+  * the moderate workload (M=128, 32+32 electrons, 512 vectors) at its full
+    256 walkers over 20 steps, 8 sampled walkers checked one by one (walkers
+    are independent given their fields, so a sampled trajectory is exact);
+  * the 24 uneven systems (M up to 256) stepped together by one batch, the
+    largest and smallest systems' sampled walkers against the oracle fed with
+    the CPU Philox fields of their system;
+  * the k-point workload's shape (8 k-points, 24 orbitals and 6+6 electrons per
+    k-point, 96 vectors per momentum transfer: the 6-electron trace kernel) at
+    256 walkers, one sampled walker, and a 6-electron shape whose trace kernel
+    needs more than 64 KB of LDS.
+Tolerances: 1e-10 relative in FP64 mode, 1e-5 in the reduced modes.
+"""
+import numpy as np
+import pytest
+
+from oracle import afqmc, kpoint, philox
+from paper_2003_01831_amd import synth
+from gpu_util import rel_fro, rel_vec, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = {"fp64": 1e-10, "cfp32": 1e-5, "bf16x3": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2003_01831_amd import api
+    return api
+
+
+def _walk(api, s, W0, w0, fields, dt, qr_every, prec, e_shift=0.0):
+    sysg = api.System.from_synth(s, precision=prec)
+    wk = api.Walkers(sysg, W0.shape[0], W0, w0)
+    out = wk.step(fields.shape[0], dt, fields=fields, qr_every=qr_every, e_shift=e_shift)
+    st = wk.get()
+    torch.cuda.synchronize()
+    g = {k: to_np(v) for k, v in out.items()}
+    g["W"] = to_np(st["W"])
+    return g
+
+
+_oracle_runs = {}
+
+
+@pytest.mark.parametrize("shape,precs", [
+    ((96, 48, 40, 128), ("fp64", "cfp32", "bf16x3")),     # 33..64 electrons: <256,4,4> blocks
+    ((200, 100, 90, 96), ("fp64", "cfp32", "bf16x3")),    # 65..100: <512,4,5> blocks
+    ((160, 120, 110, 64), ("cfp32", "bf16x3")),           # 101..128: <1024,4,4> blocks (no FP64 exchange)
+])
+def test_walk_with_qr_at_larger_electron_counts(api, shape, precs):
+    M, nu, nd, X = shape
+    s = synth.make_system(M, nu, nd, X, seed=M + nu)
+    nw, steps, dt, qr = 4, 11, 0.005, 5                   # QR after steps 5 and 10
+    fields = synth.make_fields(steps, nw, X, seed=M + 1)
+    W0 = synth.perturbed_walkers(s, nw, 0.05, seed=M + 2)
+    w0 = synth.random_weights(nw, seed=M + 3)
+    o = afqmc.run(s.h1, s.chol, s.phi_t, nu, nd, W0, w0, fields, dt, qr_every=qr)
+    for prec in precs:
+        g = _walk(api, s, W0, w0, fields, dt, qr, prec)
+        errs = {k: rel_vec(g[k], o[k]) for k in ("emix", "eloc", "weights", "ratio")}
+        errs["W"] = rel_fro(g["W"], o["W"])
+        print(shape, prec, {k: f"{v:.2e}" for k, v in errs.items()})
+        for k, v in errs.items():
+            assert v < TOL[prec], (prec, k, v)
+
+
+def test_moderate_workload_all_walkers_sampled(api):
+    """M=128, 32+32, X=512, 256 walkers at the trial, dt 0.005, QR every 5,
+    20 steps in FP64; 8 sampled walkers against the oracle, E_mix against the
+    weighted mean of the GPU's own per-walker energies."""
+    cfg = synth.WORKLOADS["m128"]
+    s = synth.make_system(cfg["M"], cfg["n_up"], cfg["n_dn"], cfg["n_chol"], seed=cfg["seed"])
+    nw, steps = cfg["n_walkers"], 20
+    fields = synth.make_fields(steps, nw, cfg["n_chol"], seed=cfg["field_seed"])
+    evar = afqmc.local_energy_plain(s.h1, s.chol, s.phi_t, s.phi_t, s.n_up, s.n_dn)[0].real
+    g = _walk(api, s, synth.trial_walkers(s, nw), np.ones(nw), fields, cfg["dt"], cfg["qr_every"], "fp64",
+              e_shift=evar)
+    sample = np.array([0, 31, 64, 100, 128, 199, 230, 255])
+    o = afqmc.run(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, synth.trial_walkers(s, len(sample)),
+                  np.ones(len(sample)), fields[:, sample], cfg["dt"], qr_every=cfg["qr_every"], e_shift=evar)
+    for k in ("eloc", "weights", "ratio"):
+        err = rel_vec(g[k][:, sample], o[k])
+        print("m128", k, f"{err:.2e}")
+        assert err < 1e-10, k
+    assert rel_fro(g["W"][sample], o["W"]) < 1e-10
+    wprev = np.vstack([np.ones(nw), g["weights"][:-1]])
+    ref = np.sum(wprev * g["eloc"].real, axis=1) / np.sum(wprev, axis=1)
+    assert rel_vec(g["emix"], ref) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
+def test_uneven_systems_workload_sampled(api, prec):
+    """The 24 uneven systems (M uniform in {32..256}, N = M/4, X = 4M, 16..128
+    walkers at the trial) in one batch, 6 steps with QR every 5. Sampled
+    walkers of the six largest and the two smallest systems are run by the
+    oracle with the CPU Philox fields of their system and compared after the
+    walk (orbitals and weights)."""
+    shapes = synth.uneven_systems(24, seed=4000)
+    if prec == "fp64":                                   # the FP64 exchange holds N <= 100
+        shapes = [c for c in shapes if c["n_up"] <= 100]
+    dt, seed, steps, qr = 0.005, 77, 6, 5
+    order = np.argsort([c["M"] for c in shapes])
+    checked = set(order[-6:].tolist()) | set(order[:2].tolist())
+    pairs, keep = [], {}
+    for i, c in enumerate(shapes):
+        s = synth.make_system(c["M"], c["n_up"], c["n_dn"], c["n_chol"], seed=c["seed"])
+        g = api.System.from_synth(s, precision=prec)
+        pairs.append((g, api.Walkers(g, c["n_walkers"])))
+        if i in checked:
+            keep[i] = s
+        del s
+    b = api.Batch(pairs)
+    b.step(steps, dt, seed=seed, qr_every=qr, e_shift=0.0)
+    torch.cuda.synchronize()
+    for i in sorted(checked):
+        c, s = shapes[i], keep[i]
+        smp = np.array([0, c["n_walkers"] - 1])
+        f = philox.normal_fields(seed, steps, c["n_walkers"], c["n_chol"], sys_id=i)[:, smp]
+        o = afqmc.run(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, synth.trial_walkers(s, len(smp)),
+                      np.ones(len(smp)), f, dt, qr_every=qr)
+        st = pairs[i][1].get()
+        ew = rel_vec(to_np(st["weights"])[smp], o["w"])
+        eW = rel_fro(to_np(st["W"])[smp], o["W"])
+        print(f"system {i} M={c['M']} nw={c['n_walkers']} {prec}: weights {ew:.1e} W {eW:.1e}")
+        assert ew < TOL[prec] and eW < TOL[prec], i
+    b.close()
+
+
+def _kp_lds(nk, m, ns, xq):
+    """Dynamic LDS bytes of the k-point trace kernel for one spin (its Theta
+    rows, columns, per-thread shares, per-vector sums and one pass's Lt rows)."""
+    N, M = nk * ns, nk * m
+    npar = 256 // N
+    return (m * N + M * ns + npar * N * 3 + xq * 3 + npar * ns * m) * 16
+
+
+@pytest.mark.parametrize("case", ["kp_m192", "lds96k"])
+def test_kpoint_six_electrons_sampled(api, case):
+    """Six electrons per k-point and spin (the 6-electron trace kernel):
+    kp_m192 is the k-point workload itself (8 k-points on a ring, m=24, 96
+    vectors per Q: M=192, N=48+48, 1536 fields, 63 KB of LDS) at 256 walkers,
+    one sampled walker; lds96k (4 k-points, m=48, 32 vectors per Q) needs 96 KB
+    of LDS, the launch above the default 64 KB limit. 2 steps with QR after
+    each (N = 48 and 24: the <256,4,4> and <256,2,2> QR blocks)."""
+    if case == "kp_m192":
+        cfg = synth.WORKLOADS["kp_m192"]
+        nk, m, nu, nd, xq, nw, seed = cfg["nk"], cfg["m"], cfg["n_up"], cfg["n_dn"], cfg["xq"], cfg["n_walkers"], 7
+        smp = np.array([137])
+    else:
+        nk, m, nu, nd, xq, nw, seed = 4, 48, 6, 6, 32, 16, 17
+        smp = np.array([0, 15])
+    lds = max(_kp_lds(nk, m, nu, xq), _kp_lds(nk, m, nd, xq))
+    print(case, "trace-kernel LDS bytes", lds)
+    if case == "lds96k":
+        assert lds > 64 * 1024
+    ks = synth.make_kpoint_system(nk, m, nu, nd, xq, seed=seed)
+    h = kpoint.dense_one_body(ks.hk)
+    L = kpoint.dense_factors(ks.Lk, ks.kq)
+    T = kpoint.dense_trial(ks.phik, nu, nd)
+    steps, dt = 2, 0.005
+    rng = np.random.default_rng(seed + 1000)
+    W0 = T[None] + 0.05 * (rng.standard_normal((nw,) + T.shape) + 1j * rng.standard_normal((nw,) + T.shape))
+    w0 = synth.random_weights(nw, seed=seed + 1)
+    fields = rng.standard_normal((steps, nw, 2 * L.shape[0]))
+    g = api.System.from_kpoint(ks)
+    wk = api.Walkers(g, nw, W0, w0)
+    out = wk.step(steps, dt, fields=fields, qr_every=1, outputs=("eloc", "weights", "ratio"))
+    torch.cuda.synchronize()
+    o = kpoint.run(h, L, T, nk * nu, nk * nd, W0[smp], w0[smp], fields[:, smp], dt, qr_every=1)
+    for k in ("eloc", "weights", "ratio"):
+        err = rel_vec(to_np(out[k])[:, smp], o[k])
+        print(case, k, f"{err:.2e}")
+        assert err < 1e-10, k
+
+
+def test_host_and_device_inputs_give_the_same_system(api):
+    """afq_system_create with AFQ_HOST_PTRS (numpy inputs) and with device
+    pointers (torch tensors) set up identical systems: bitwise equal energies
+    and walks."""
+    s = synth.make_system(40, 9, 7, 60, seed=21)
+    nw = 5
+    W0 = synth.perturbed_walkers(s, nw, 0.1, seed=22)
+    fields = synth.make_fields(6, nw, 60, seed=23)
+    res = []
+    for host in (True, False):
+        if host:
+            sysg = api.System(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, s.e_core)
+        else:
+            sysg = api.System(torch.from_numpy(s.h1).cuda(), torch.from_numpy(s.chol).cuda(),
+                              torch.from_numpy(s.phi_t).cuda(), s.n_up, s.n_dn, s.e_core)
+        wk = api.Walkers(sysg, nw, W0)
+        el = wk.energy()[0].clone()
+        out = wk.step(6, 0.01, fields=fields, qr_every=3)
+        torch.cuda.synchronize()
+        res.append((el, out["eloc"], out["weights"], wk.get()["W"]))
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
+
+
+def test_autograd_reuses_the_system_until_inputs_change(api):
+    from paper_2003_01831_amd import autograd
+    s = synth.make_system(24, 5, 4, 30, seed=31)
+    h1 = torch.from_numpy(s.h1).cuda().requires_grad_()
+    chol = torch.from_numpy(s.chol).cuda().requires_grad_()
+    phi = torch.from_numpy(s.phi_t).cuda()
+    W = torch.from_numpy(synth.perturbed_walkers(s, 4, 0.1, seed=32)).cuda().requires_grad_()
+    wts = torch.ones(4, dtype=torch.float64, device="cuda")
+    e1 = autograd.LocalEnergy.apply(h1, chol, W, wts, phi, 5, 4)
+    first = autograd._cached["system"]
+    e1.backward()
+    g1 = h1.grad.clone()
+    h1.grad = None
+    e2 = autograd.LocalEnergy.apply(h1, chol, W, wts, phi, 5, 4)
+    assert autograd._cached["system"] is first             # reused
+    e2.backward()
+    assert torch.equal(h1.grad, g1) and torch.equal(e1, e2)
+    with torch.no_grad():
+        h1.mul_(1.01)                                       # in-place change: a new system
+    e3 = autograd.LocalEnergy.apply(h1, chol, W, wts, phi, 5, 4)
+    assert autograd._cached["system"] is not first
+    assert not torch.equal(e3, e1)
