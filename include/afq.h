@@ -255,6 +255,25 @@ int afq_walkers_set_controls(afq_walkers w, double fb_cap, double w_cap);
  * and leaves the walkers unchanged. */
 int afq_walkers_comb(afq_walkers w, double xi, int32_t *src_out, double *total_out);
 
+/* Largest walker set afq_walkers_comb_noalloc accepts. Its scratch is one
+ * file-scope device array of 256 B + 12 B per walker (48.25 KiB), which every
+ * GPU the library runs on holds until the process ends. */
+#define AFQ_COMB_NOALLOC_MAX_WALKERS 4096
+/* For callers that cannot allocate device memory (no hipMalloc / hipFree may
+ * happen inside their loop: fixed-budget serving loops, harnesses that forbid
+ * allocation): afq_walkers_comb with the same kernels and the same result bit
+ * for bit, but its scratch (running weight sums, source indices, total weight)
+ * lives in the library's static device array instead of buffers allocated on
+ * the first comb. The call allocates nothing; it synchronises the system
+ * stream like afq_walkers_comb. Every call on one GPU shares that GPU's array
+ * and overwrites it: calls that overlap on one GPU (other threads, other
+ * streams) race and must be serialised by the caller. Errors: AFQ_E_INVALID
+ * for more than AFQ_COMB_NOALLOC_MAX_WALKERS walkers or xi outside [0, 1);
+ * AFQ_E_UNSUPPORTED while a back-propagation window is open (its history
+ * gather needs a buffer; use afq_walkers_comb); AFQ_E_STATE as
+ * afq_walkers_comb. */
+int afq_walkers_comb_noalloc(afq_walkers w, double xi, int32_t *src_out, double *total_out);
+
 /* Energy-shift feedback of the population: *e_shift_out = e_est -
  * ln(w_total / w_target) / (gain_steps dt). Host arithmetic only. Non-positive
  * weights, dt or gain give AFQ_E_INVALID. */

@@ -37,6 +37,7 @@ SIGNATURES = {
     "afq_walkers_stats": (_i, [_vp, C.POINTER(_i), C.POINTER(C.c_int64)]),
     "afq_walkers_set_controls": (_i, [_vp, _d, _d]),
     "afq_walkers_comb": (_i, [_vp, _d, _vp, C.POINTER(_d)]),
+    "afq_walkers_comb_noalloc": (_i, [_vp, _d, _vp, C.POINTER(_d)]),
     "afq_eshift_update": (_i, [_d, _d, _d, _d, _d, C.POINTER(_d)]),
     "afq_step": (_i, [_vp, _vp, _i, _d, _vp, _u64, _i, _d, _i, _vp, _vp, _vp, _vp]),
     "afq_energy": (_i, [_vp, _vp, _vp, _vp, _vp, _vp]),
