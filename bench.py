@@ -7,11 +7,15 @@ step, fields from the device Philox stream; synthetic seeded inputs
 (paper_2003_01831_amd.synth, workload "m400").
 
 Prints ONE JSON line: walker-steps/s of the headline precision (split-BF16x3
-by default), the same rate for the plain FP64 path and complex FP32 on the same
-GPU, the algorithmic TFLOP/s, the roofline entry of the dominant kernel (the
-fused exchange contraction, timed with HIP events on the library stream), the
-error against the CPU FP64 oracle on a 4-walker subset, and the oracle's own
-rate on the host cores (cpu_baseline).
+by default, with the exchange form the library chooses: the four-index form at
+M=400), the same rate for the plain FP64 path with the same exchange form, and
+both precisions (plus complex FP32) with the Cholesky form; the TFLOP/s of the
+work each run executes (never a model count of an algorithm that did not run);
+the roofline entry of the dominant kernel (timed with HIP events on the library
+stream); the error against the CPU FP64 oracle on a 4-walker subset over 6
+steps (a QR step included); the oracle's own rate on the host cores with all
+BLAS threads and with one (cpu_baseline); and the adjoint (energy gradient) of
+the differentiation workload: its time and its errors against the oracle.
 """
 from __future__ import annotations
 
@@ -50,6 +54,18 @@ def flops_per_walker_step(M, N, X, K=6, qr_every=5, real_trial=True):
     model["coulomb"] = 8.0 * 2 * X * N * M
     model["exchange"] = 8.0 * 2 * X * N * N * M + 8.0 * 2 * X * N * N
     return sum(parts.values()), parts, sum(model.values())
+
+
+def exchange_flops_executed(form, M, N, X, nw, spins=2):
+    """Algorithmic flop of the exchange term that the chosen form computes
+    (real half-rotated vectors of a real trial): the Cholesky form contracts
+    Omega_n = Lt_n Theta (X N^2 M real-by-complex multiply-adds, 4 flop each,
+    per walker and spin) and forms tr(Omega Omega) (8 X N^2); the four-index
+    form contracts the quadratic form of the symmetric tensor, (N M)^2 / 2
+    real-by-complex multiply-adds per walker and spin."""
+    if form == "four_index":
+        return 2.0 * (N * M) ** 2 * nw * spins
+    return (4.0 * X * N * N * M + 8.0 * X * N * N) * nw * spins
 
 
 def profiled_traffic(kernel_src, profile_md, tag):
@@ -94,8 +110,9 @@ def bench_uneven(a, torch, synth, api, _lib):
     lib = _lib.load()
     t0 = time.perf_counter()
     pairs, e_shift = [], []
-    flop_model = flop_real = 0.0
+    flop_exec = 0.0
     ex_flops = 0.0
+    forms = {"cholesky": 0, "four_index": 0}
     for c in shapes:
         s = synth.make_system(c["M"], c["n_up"], c["n_dn"], c["n_chol"], seed=c["seed"])
         g = api.System.from_synth(s, precision=a.precision)
@@ -103,11 +120,12 @@ def bench_uneven(a, torch, synth, api, _lib):
         e_shift.append(float(probe.energy()[3][0]))
         probe.close()
         pairs.append((g, api.Walkers(g, c["n_walkers"])))
-        fr, parts, fm = flops_per_walker_step(c["M"], c["n_up"], c["n_chol"], 6, qr)
-        flop_model += fm * c["n_walkers"]
-        flop_real += fr * c["n_walkers"]
-        N = c["n_up"]
-        ex_flops += 2 * (8.0 * c["n_chol"] * N * N * c["M"] + 8.0 * c["n_chol"] * N * N) * c["n_walkers"]
+        used = g.exchange_form()[0]
+        forms[used] += 1
+        _, parts, _ = flops_per_walker_step(c["M"], c["n_up"], c["n_chol"], 6, qr)
+        ex = exchange_flops_executed(used, c["M"], c["n_up"], c["n_chol"], c["n_walkers"])
+        flop_exec += (sum(parts.values()) - parts["exchange"]) * c["n_walkers"] + ex
+        ex_flops += ex
         del s
     nwt = sum(c["n_walkers"] for c in shapes)
     print(f"[bench] 24 systems, {nwt} walkers, built in {time.perf_counter() - t0:.1f}s", file=sys.stderr,
@@ -144,8 +162,10 @@ def bench_uneven(a, torch, synth, api, _lib):
         "config": {"workload": f"uneven24: 24 systems, M in [32, 256], N_up=N_dn=M/4, Nchol=4M, {nwt} walkers, "
                                f"dt={dt}, QR every {qr}, graph of one QR cycle replayed",
                    "precision": a.precision, "walkers": nwt, "parallelism": "single GPU"},
-        "alg_tflops": round(flop_model * steps / wall / 1e12, 3),
-        "alg_tflops_real_lt": round(flop_real * steps / wall / 1e12, 3),
+        # the work executed (each system's exchange counted for the form it ran)
+        "tflops": round(flop_exec * steps / wall / 1e12, 3),
+        "tflops_frac_of_peak": round(flop_exec * steps / wall / 1e12 / peak, 4),
+        "exchange_forms": forms,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": None,
                      "kernel": "exchange kernels of all 24 systems (one eager traced step, sum of launch times)",
@@ -305,6 +325,50 @@ def bench_kp(a, torch, synth, api, _lib):
     return 0
 
 
+def measure_gradient(api, torch, synth):
+    """Adjoint of the weighted mixed energy on the differentiation workload
+    (M=64, 16+16 electrons, 256 vectors, 64 walkers perturbed by 0.1, weights
+    in [0.5, 1.5]): milliseconds per afq_energy_backward call (all three
+    gradients) and per afq_energy call, and the relative Frobenius error of each
+    gradient against the oracle's adjoint, per precision."""
+    from oracle import afqmc
+    cfg = synth.WORKLOADS["grad_m64"]
+    s = synth.make_system(cfg["M"], cfg["n_up"], cfg["n_dn"], cfg["n_chol"], seed=cfg["seed"])
+    nw = cfg["n_walkers"]
+    W = synth.perturbed_walkers(s, nw, cfg["perturb"], seed=cfg["field_seed"])
+    w = synth.random_weights(nw, seed=7)
+    print("[bench] gradient workload: oracle adjoint", file=sys.stderr, flush=True)
+    rh, rl, rw = afqmc.energy_grad(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, W, w)
+
+    def rel(x, r):
+        return float(f"{np.linalg.norm((x - r).ravel()) / np.linalg.norm(r.ravel()):.3e}")
+
+    out = {"workload": f"grad_m64: M={cfg['M']}, N_up=N_dn={cfg['n_up']}, Nchol={cfg['n_chol']}, {nw} walkers"}
+    for prec in ("fp64", "cfp32", "bf16x3"):
+        sysg = api.System.from_synth(s, precision=prec)
+        wk = api.Walkers(sysg, nw, W, w)
+        dh, dl, dw = api.energy_backward(sysg, wk, 1.0)
+        wk.energy()
+        torch.cuda.synchronize()
+        reps = 5
+        t = time.perf_counter()
+        for _ in range(reps):
+            api.energy_backward(sysg, wk, 1.0)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t) / reps
+        t = time.perf_counter()
+        for _ in range(reps):
+            wk.energy()
+        torch.cuda.synchronize()
+        tf = (time.perf_counter() - t) / reps
+        out[prec] = {"backward_ms": round(tb * 1e3, 3), "energy_ms": round(tf * 1e3, 3),
+                     "err_d_h1": rel(dh.cpu().numpy(), rh), "err_d_chol": rel(dl.cpu().numpy(), rl),
+                     "err_d_W": rel(dw.cpu().numpy(), rw)}
+        wk.close()
+        sysg.close()
+    return out
+
+
 def measure_extras(a, extra, sysg, api, lib, _lib, torch, nw, dt, qr, e_var, M, nu, nd):
     """Population control and back-propagation at the headline size (outside the timed steps)."""
     # population control at this size: one comb of all walkers (host-synchronising)
@@ -349,6 +413,17 @@ def measure_extras(a, extra, sysg, api, lib, _lib, torch, nw, dt, qr, e_var, M, 
         "trace_err": float(max(abs(np.trace(Pn[0]).real - nu), abs(np.trace(Pn[1]).real - nd)))}
     del P
     wk_bp.close()
+    # the adjoint at this size: all three gradients (dL alone is X M^2 doubles)
+    wk_g = api.Walkers(sysg, nw)
+    wk_g.step(2, dt, seed=13, qr_every=qr, e_shift=e_var, outputs=())
+    api.energy_backward(sysg, wk_g, 1.0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    d = api.energy_backward(sysg, wk_g, 1.0)
+    torch.cuda.synchronize()
+    extra["backward_ms"] = round((time.perf_counter() - t) * 1e3, 3)
+    del d
+    wk_g.close()
 
 
 def main(argv=None):
@@ -359,8 +434,13 @@ def main(argv=None):
     ap.add_argument("--precision", default="bf16x3", choices=list(PEAK_TFLOPS))
     ap.add_argument("--workload", default="m400")
     ap.add_argument("--walkers", type=int, default=None, help="override the walker count")
-    ap.add_argument("--compare-steps", type=int, default=3, help="timed steps of the other precisions (0: skip)")
-    ap.add_argument("--check-steps", type=int, default=2, help="steps of the 4-walker oracle check (0: skip)")
+    ap.add_argument("--compare-steps", type=int, default=5,
+                    help="timed steps of the comparison runs (other precisions and forms; 0: skip)")
+    ap.add_argument("--check-steps", type=int, default=6, help="steps of the 4-walker oracle check (0: skip)")
+    ap.add_argument("--single-thread-steps", type=int, default=2,
+                    help="steps of the 1-walker oracle run on one BLAS thread (0: skip)")
+    ap.add_argument("--no-grad", dest="grad", action="store_false",
+                    help="skip the adjoint measurement on the differentiation workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (comb, back-propagation window) after the timed steps")
@@ -415,8 +495,12 @@ def main(argv=None):
     e_var = float(probe.energy()[3][0])
     probe.close()
 
-    def timed(prec, steps, warmup):
+    def timed(prec, steps, warmup, form):
+        """walls, traced phases and E_mix of `steps` steps of a fresh walker set
+        after `warmup` untimed ones, in precision `prec` with exchange form `form`"""
+        sysg.set_exchange_form(form)
         sysg.set_precision(prec)
+        used, _ = sysg.exchange_form()
         wk = api.Walkers(sysg, nw)
         if warmup:
             wk.step(warmup, dt, seed=11, qr_every=qr, e_shift=e_var, outputs=("emix",))
@@ -433,17 +517,34 @@ def main(argv=None):
         lib.afq_trace_reset()
         emix = out["emix"].cpu().numpy()
         wk.close()
-        return wall, phases, emix
+        return wall, phases, emix, used
+
+    def summary(prec, steps, wall, phases, used):
+        """walker-steps/s, executed TFLOP/s of the whole step and of the exchange
+        launches, each with its fraction of the peak of the MFMA type used"""
+        fe = flops_per_walker_step(M, nu, X, 6, qr)[1]
+        step_flop = sum(fe.values()) - fe["exchange"] + exchange_flops_executed(used, M, nu, X, 1)
+        ex_ms, ex_cnt = phases["exchange"]
+        ex_flop = exchange_flops_executed(used, M, nu, X, nw) * steps
+        pk = PEAK_TFLOPS[prec]
+        out = {"walker_steps_per_s": round(nw * steps / wall, 3), "ms_per_step": round(wall / steps * 1e3, 3),
+               "exchange_form": used, "steps_timed": steps,
+               "step_tflops_executed": round(step_flop * nw * steps / wall / 1e12, 3),
+               "exchange_tflops_executed": round(ex_flop / (ex_ms / 1e3) / 1e12, 3) if ex_ms > 0 else None,
+               "peak_tflops": pk}
+        out["step_frac_of_peak"] = round(out["step_tflops_executed"] / pk, 4)
+        if out["exchange_tflops_executed"] is not None:
+            out["exchange_frac_of_peak"] = round(out["exchange_tflops_executed"] / pk, 4)
+        out["phase_ms_per_step"] = {k: round(v[0] / steps, 3) for k, v in phases.items() if v[0] > 0}
+        return out
 
     print(f"[bench] timing {a.precision}: {a.warmup} warmup + {a.steps} steps, {nw} walkers", file=sys.stderr,
           flush=True)
-    wall, phases, emix = timed(a.precision, a.steps, a.warmup)
+    wall, phases, emix, form = timed(a.precision, a.steps, a.warmup, a.exchange_form)
     value = nw * a.steps / wall
-    flop_ws, flop_parts, flop_model = flops_per_walker_step(M, nu, X, 6, qr)
-    alg_tflops = flop_ws * nw * a.steps / wall / 1e12
-    flop_exec = flop_ws
-    if form == "four_index":
-        flop_exec = flop_ws - flop_parts["exchange"] + 2 * 2.0 * (nu * M) ** 2
+    flop_model, flop_parts = flops_per_walker_step(M, nu, X, 6, qr)[2], flops_per_walker_step(M, nu, X, 6, qr)[1]
+    flop_exec = sum(flop_parts.values()) - flop_parts["exchange"] + exchange_flops_executed(form, M, nu, X, 1)
+    head = summary(a.precision, a.steps, wall, phases, form)
 
     ex_ms, ex_cnt = phases["exchange"]
     ex_avg_s = ex_ms / 1e3 / max(ex_cnt, 1)
@@ -454,67 +555,71 @@ def main(argv=None):
         # symmetric half-rotated tensor: (N M)^2 / 2 real-by-complex multiply-adds
         # (4 flop each) per walker and spin; spins that share the tensor are
         # contracted in one launch (one exchange phase per step), else one each
-        NM = nu * M
         spins_per_launch = 2 if ex_cnt <= a.steps else 1
-        per_launch_flops = 2.0 * NM * NM * nw * spins_per_launch
+        per_launch_flops = exchange_flops_executed(form, M, nu, X, nw, spins_per_launch)
         traffic = None
-        if a.workload == "m400" and nw == 512:
+        if a.workload == "m400" and nw == 512 and a.precision == "bf16x3":
             traffic = profiled_traffic(os.path.join(csrc, "eri.hip"),
                                        os.path.join(ROOT, "profiles", "eri_bf16x3_m400.md"), "eri")
+        kernel = ("four-index exchange kernel (W'' Theta-hat in split BF16x3, FP64 epilogue) plus its per-walker "
+                  "reductions" if a.precision == "bf16x3" else
+                  "four-index exchange (FP64 GEMMs over the upper block triangle of W', then per-walker dots)")
         roofline = {"bound": "mfma", "achieved": round(per_launch_flops / ex_avg_s / 1e12, 3), "peak": peak,
                     "unit": "TFLOP/s", "traffic": traffic,
-                    "kernel": "four-index exchange kernel (W'' Theta-hat in split BF16x3, FP64 epilogue) "
-                              "plus its per-walker reductions, %d spin%s per launch"
-                              % (spins_per_launch, "s" if spins_per_launch > 1 else ""),
+                    "kernel": kernel + ", %d spin%s per launch" % (spins_per_launch, "s" if spins_per_launch > 1
+                                                                    else ""),
                     "flop_per_launch": per_launch_flops,
                     "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt}
-        roofline["frac"] = round(roofline["achieved"] / peak, 4)
-        # every algorithmic product is three BF16 products (hi*hi + hi*lo + lo*hi)
-        roofline["bf16_products_per_flop"] = 3
-        roofline["mfma_pipe_frac"] = round(3 * roofline["achieved"] / peak, 4)
-        # the same exchange term counted with the Cholesky-form model, for comparison
-        roofline["cholesky_model_equivalent_tflops"] = round(
-            (8.0 * X * nu * nu * M + 8.0 * X * nu * nu) * nw * spins_per_launch / ex_avg_s / 1e12, 3)
     else:
-        # the exchange term of the general (complex L~) flop model, one spin per
-        # launch; the real-L~ count the kernel actually needs is beside it
-        per_launch_flops = (8.0 * X * nu * nu * M + 8.0 * X * nu * nu) * nw
-        per_launch_real = flop_parts["exchange"] / 2 * nw
-        achieved = per_launch_flops / ex_avg_s / 1e12
+        # the Cholesky form: Omega = Lt Theta with the real half-rotated vectors of
+        # the real trial, one spin per launch
+        per_launch_flops = exchange_flops_executed(form, M, nu, X, nw, 1)
         traffic = None
         if a.precision == "bf16x3" and a.workload == "m400" and nw == 512:
             traffic = profiled_traffic(os.path.join(csrc, "exchange_big.hip"),
                                        os.path.join(ROOT, "profiles", "exchange_bf16x3_m400.md"), "exchange_big")
-        roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                    "frac": round(achieved / peak, 4), "traffic": traffic,
+        roofline = {"bound": "mfma", "achieved": round(per_launch_flops / ex_avg_s / 1e12, 3), "peak": peak,
+                    "unit": "TFLOP/s", "traffic": traffic,
                     "kernel": "exchange kernel (fused Omega = Lt Theta, tr Omega, tr Omega^2), one spin per launch",
                     "flop_per_launch": per_launch_flops,
-                    "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt,
-                    "achieved_real_lt": round(per_launch_real / ex_avg_s / 1e12, 3)}
-        if a.precision == "bf16x3":
-            # split-BF16x3 issues three BF16 products per FP32-class product; against
-            # that effective peak, count only the multiply-adds the real L~ needs
-            roofline["real_lt_frac_of_bf16x3_effective_peak"] = round(roofline["achieved_real_lt"] / (peak / 3), 4)
+                    "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt}
+    roofline["frac"] = round(roofline["achieved"] / peak, 4)
+    if a.precision == "bf16x3":
+        # every algorithmic product is three BF16 products (hi*hi + hi*lo + lo*hi):
+        # the MFMA pipes are busy about three times the fraction above
+        roofline["bf16_products_per_flop"] = 3
+        roofline["bf16_product_frac_of_peak"] = round(3 * roofline["achieved"] / peak, 4)
 
     extra = {}
     if not a.no_extras:
         measure_extras(a, extra, sysg, api, lib, _lib, torch, nw, dt, qr, e_var, M, nu, nd)
-    if a.compare_steps > 0:
-        for prec in ("fp64", "cfp32", "bf16x3"):
-            if prec == a.precision:
-                continue
-            print(f"[bench] timing {prec}: {a.compare_steps} steps", file=sys.stderr, flush=True)
-            w2, ph2, _ = timed(prec, a.compare_steps, 1)
-            extra[f"{prec}_walker_steps_per_s"] = round(nw * a.compare_steps / w2, 3)
-            exm, exc = ph2["exchange"]
-            # the other precisions run the Cholesky form: its complex-model count
-            chol_launch = (8.0 * X * nu * nu * M + 8.0 * X * nu * nu) * nw
-            extra[f"{prec}_exchange_tflops"] = round(chol_launch / (exm / 1e3 / max(exc, 1)) / 1e12, 3)
-        sysg.set_precision(a.precision)
-        if "fp64_walker_steps_per_s" in extra:
-            extra["speedup_vs_fp64_path"] = round(value / extra["fp64_walker_steps_per_s"], 3)
 
-    # error against the FP64 oracle and the oracle's own rate, on a 4-walker subset
+    # like-for-like comparisons on the same GPU: the FP64 path with the same
+    # exchange form as the headline, then every precision with the Cholesky form
+    cmp = {}
+    if a.compare_steps > 0:
+        runs = [("fp64", "auto")] if form == "four_index" else []
+        runs += [(p, "cholesky") for p in ("bf16x3", "fp64", "cfp32")]
+        for prec, frm in runs:
+            print(f"[bench] timing {prec} ({frm} form): {a.compare_steps} steps", file=sys.stderr, flush=True)
+            w2, ph2, _, used = timed(prec, a.compare_steps, 1, frm)
+            cmp[f"{prec}_{used}"] = summary(prec, a.compare_steps, w2, ph2, used)
+        sysg.set_exchange_form(a.exchange_form)
+        sysg.set_precision(a.precision)
+        same = cmp.get(f"fp64_{form}")
+        if same is not None:
+            # the headline against the plain FP64 path running the same algorithm
+            extra["fp64_walker_steps_per_s"] = same["walker_steps_per_s"]
+            extra["speedup_vs_fp64_path"] = round(value / same["walker_steps_per_s"], 3)
+            extra["speedup_vs_fp64_path_form"] = form
+        bc, fc = cmp.get("bf16x3_cholesky"), cmp.get("fp64_cholesky")
+        if bc and fc:
+            extra["speedup_bf16x3_vs_fp64_cholesky_form"] = round(bc["walker_steps_per_s"] / fc["walker_steps_per_s"],
+                                                                  3)
+        extra["compare"] = cmp
+
+    # error against the FP64 oracle and the oracle's own rate, on a 4-walker
+    # subset over check_steps steps (6 by default: QR after the fifth)
     err, cpu = None, None
     if a.check_steps > 0:
         from oracle import afqmc
@@ -524,16 +629,19 @@ def main(argv=None):
         wk = api.Walkers(sysg, nsub)
         g = wk.step(ks, dt, fields=fields, qr_every=qr, e_shift=e_var)
         el, parts, _, _ = wk.energy()
+        Wg = wk.get()["W"].cpu().numpy()
         torch.cuda.synchronize()
         g = {k: v.cpu().numpy() for k, v in g.items()}
         if not a.no_cpu:
-            try:
-                import threadpoolctl
-                threads = max([p.get("num_threads", 0) for p in threadpoolctl.threadpool_info()
-                               if p.get("user_api") == "blas"] or [os.cpu_count()])
-            except Exception:
-                threads = os.cpu_count()
-            print(f"[bench] oracle: {nsub} walkers x {ks} steps on the host", file=sys.stderr, flush=True)
+            import threadpoolctl
+
+            def blas_threads():
+                return max([p.get("num_threads", 0) for p in threadpoolctl.threadpool_info()
+                            if p.get("user_api") == "blas"] or [0])
+
+            threads = blas_threads() or os.cpu_count()
+            print(f"[bench] oracle: {nsub} walkers x {ks} steps on the host ({threads} BLAS threads)",
+                  file=sys.stderr, flush=True)
             pre = afqmc.prepare(s.h1, s.chol, s.phi_t, nu, nd, dt)
             t = time.perf_counter()
             o = afqmc.run(s.h1, s.chol, s.phi_t, nu, nd, W0, np.ones(nsub), fields, dt, qr_every=qr,
@@ -543,16 +651,33 @@ def main(argv=None):
             cpu = {"value": round(nsub * ks / tc, 4), "unit": "walker-steps/s", "cores": threads,
                    "kind": "oracle",
                    "sample": f"{nsub} walkers x {ks} steps of the same workload (numpy FP64, half-rotated "
-                             f"energy), {tc:.1f}s; walkers are independent so the rate scales linearly",
+                             f"energy, QR after step 5), {tc:.1f}s; walkers are independent so the rate scales "
+                             f"linearly",
                    "host_cpus": os.cpu_count()}
+            if a.single_thread_steps > 0:
+                n1 = a.single_thread_steps
+                print(f"[bench] oracle: 1 walker x {n1} steps on 1 BLAS thread", file=sys.stderr, flush=True)
+                with threadpoolctl.threadpool_limits(1, user_api="blas"):
+                    t = time.perf_counter()
+                    afqmc.run(s.h1, s.chol, s.phi_t, nu, nd, W0[:1], np.ones(1), fields[:n1, :1], dt,
+                              qr_every=qr, e_shift=e_var, pre=pre)
+                    t1 = time.perf_counter() - t
+                cpu["single_thread"] = {"value": round(n1 / t1, 4), "unit": "walker-steps/s", "cores": 1,
+                                        "sample": f"1 walker x {n1} steps, {t1:.1f}s"}
             pg = parts.cpu().numpy()
-            err = {"precision": a.precision, "E_mix": rel_max(g["emix"], o["emix"]),
+            err = {"precision": a.precision, "exchange_form": form, "steps": ks,
+                   "E_mix": rel_max(g["emix"], o["emix"]),
                    "E_L": rel_max(g["eloc"], o["eloc"]), "weights": rel_max(g["weights"], o["weights"]),
                    "ratio": rel_max(g["ratio"], o["ratio"]),
                    "E1": rel_max(pg[:, 0], oparts[:, 0]), "EJ": rel_max(pg[:, 1], oparts[:, 1]),
-                   "EK": rel_max(pg[:, 2], oparts[:, 2])}
-            err = {k: (v if isinstance(v, str) else float(f"{v:.3e}")) for k, v in err.items()}
+                   "EK": rel_max(pg[:, 2], oparts[:, 2]),
+                   "W": float(np.linalg.norm(Wg - o["W"]) / np.linalg.norm(o["W"]))}
+            err = {k: (v if isinstance(v, (str, int)) else float(f"{v:.3e}")) for k, v in err.items()}
         wk.close()
+
+    grad = None
+    if a.grad and not a.no_cpu:
+        grad = measure_gradient(api, torch, synth)
 
     line = {
         "metric": "walker-steps/s + MFMA TFLOP/s at M=400 vs plain FP64 path, err vs FP64 oracle",
@@ -563,18 +688,19 @@ def main(argv=None):
                                f"QR every {qr}, Taylor order 6, energy every step, Philox fields",
                    "precision": a.precision, "walkers": nw, "parallelism": "single GPU",
                    "exchange_form": form, "four_index_tensor_gb": round(tensor_bytes / 1e9, 3)},
-        "alg_tflops": round(flop_model * nw * a.steps / wall / 1e12, 3),
-        "alg_tflops_real_lt": round(alg_tflops, 3),
-        "flop_per_walker_step": flop_model,
-        "flop_per_walker_step_real_lt": flop_ws,
-        # the algorithm actually run: with the four-index form the exchange term
-        # is 2 (N M)^2 flop per spin instead of the Cholesky form's count
+        # TFLOP/s of the work this run executed (the exchange term counted for the
+        # form that ran) and its fraction of the peak of the MFMA type used
+        "tflops": head["step_tflops_executed"],
+        "tflops_frac_of_peak": head["step_frac_of_peak"],
         "flop_per_walker_step_executed": flop_exec,
-        "alg_tflops_executed": round(flop_exec * nw * a.steps / wall / 1e12, 3),
+        # the general complex flop model (8 flop per complex multiply-add, Cholesky
+        # form): a count for reference, not a rate of this run
+        "flop_per_walker_step_model": flop_model,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "err_vs_fp64_oracle": err,
-        "phase_ms_per_step": {k: round(v[0] / a.steps, 3) for k, v in phases.items()},
+        "gradient": grad,
+        "phase_ms_per_step": head["phase_ms_per_step"],
         "emix_last": float(emix[-1]),
     }
     line.update(extra)

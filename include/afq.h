@@ -124,11 +124,12 @@ int afq_system_set_precision(afq_system s, int precision);
  *   sum_n tr(Omega_n Omega_n) = Theta^T W Theta,
  *   W[(b,k),(a,l)] = sum_n (T^H L^n)[a][k] (T^H L^n)[b][l],
  * the half-rotated two-electron tensor, built once per system, which needs
- * (N M)^2 / 2 products (its symmetric upper block triangle) and N^2 M^2 stored
- * entries per distinct spin block (split into BF16 hi / lo planes). The
- * four-index form exists in split-BF16x3 mode for a real trial on plain
- * (single-determinant, not k-point-blocked) systems; elsewhere the Cholesky
- * form is used whatever the setting. */
+ * about (N M)^2 / 2 products (its symmetric upper block triangle) and N^2 M^2
+ * stored entries per distinct spin block (split-BF16x3: BF16 hi / lo planes;
+ * FP64: the FP64 tensor itself, contracted by FP64 GEMMs). The four-index
+ * form exists in split-BF16x3 and FP64 modes for a real trial on plain
+ * (single-determinant, not k-point-blocked) systems; elsewhere (complex FP32
+ * mode included) the Cholesky form is used whatever the setting. */
 typedef enum {
   AFQ_EXCH_AUTO = 0,       /* four-index form when it needs fewer products (M < 2X),
                               N M >= 4096, and its tensor takes at most a quarter
@@ -140,7 +141,8 @@ typedef enum {
 /* Sets the exchange form (AFQ_EXCH_*). Builds the four-index tensor at once
  * when it will be used, or frees it when it will not (synchronises; may
  * allocate N^2 M^2 * 4 bytes per distinct spin block plus an FP64 set-up
- * transient of N^2 M^2 * 8 bytes). A batch holding the system captures its
+ * transient of N^2 M^2 * 8 bytes in split-BF16x3 mode, N^2 M^2 * 8 bytes in
+ * FP64 mode; a precision switch rebuilds it). A batch holding the system captures its
  * step again on its next call. AFQ_E_INVALID for an unknown form,
  * AFQ_E_NOMEM when the tensor does not fit. */
 int afq_system_set_exchange_form(afq_system s, int form);

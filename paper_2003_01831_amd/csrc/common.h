@@ -171,7 +171,9 @@ struct afq_system_s {
   bool eri_ready = false;      // planes built for the current configuration
   bool eri_share = false;      // both spins use block 0 (equal trial blocks)
   bool eri_declined = false;   // the automatic choice said no for this configuration
-  DevBuf eri_w[2];             // hi and lo planes, chunk-major [chunk][rows][32] bf16
+  int eri_prec = -1;           // precision the tensor was built for (AFQ_BF16X3 or AFQ_FP64)
+  DevBuf eri_w[2];             // BF16x3: hi and lo planes, chunk-major [chunk][rows][32] bf16;
+                               // FP64: the full symmetric W' (N M x N M f64)
   DevBuf eri_units[2];         // work units (row block, first chunk, chunks, 0)
   int eri_nunit[2] = {0, 0};
   unsigned version = 0;        // bumped when the step's kernel sequence changes (batches capture again)
@@ -245,7 +247,8 @@ struct afq_walkers_s {
   DevBuf r32_b1w;              // walker rows (n, Re|Im) packed for the B1 products
   // four-index exchange scratch
   DevBuf eri_theta;            // packed Theta-hat hi / lo planes of one spin
-  DevBuf eri_part;             // per (work unit, column) complex partial sums
+  DevBuf eri_part;             // BF16x3: per (work unit, column) complex partial sums;
+                               // FP64: Z^T = Theta-hat^T W'' rows of one spin (nw x N M complex)
 };
 
 // ---------------------------------------------------------------------------

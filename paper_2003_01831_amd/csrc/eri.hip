@@ -20,6 +20,14 @@
 // a contiguous run of contraction chunks; its epilogue contracts the FP32 tile
 // with Theta-hat in FP64 (no output matrix is stored) and writes one complex
 // partial per (unit, column); a fixed-order reduction gives every walker's sum.
+//
+// FP64 mode keeps W' itself (N M x N M doubles, 12.8 GB at M = 400; its set-up
+// needs the same again for the Gram matrix before the permutation) and runs
+// the same quadratic form on FP64 MFMA through the tiled GEMM: with the
+// columns cut into NB blocks J, Z_J^T = 2 Theta-hat_{<J}^T W'_{<J,J} +
+// Theta-hat_J^T W'_JJ (two GEMMs per block, the upper block triangle plus the
+// diagonal blocks: (1/2 + 1/(2 NB)) of the full square), then one FP64 dot
+// product per walker, sum_I Theta-hat_I Z_I.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -271,6 +279,17 @@ __global__ __launch_bounds__(256) void eri_reduce_kernel(const double2* __restri
   for (int n = 1 + t; n < X; n += 256) o[n] = make_double2(0.0, 0.0);
 }
 
+// W'[I = (b,k)][J = (a,l)] = W[(a,k)][(b,l)] in FP64 (the operand of the FP64
+// form); both the read and the write run along l
+__global__ void eri_perm_w_kernel(const double* __restrict__ W, int M, long NM, double* __restrict__ out) {
+  const long total = NM * NM;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const long I = e / NM, J = e - I * NM;
+    const long b = I / M, k = I - b * M, a = J / M, l = J - a * M;
+    out[e] = W[(a * M + k) * NM + b * M + l];
+  }
+}
+
 // out[c][r] = in[r * ld_in + c]  (rows x cols -> cols x rows)
 __global__ void transpose_real_kernel(const double* __restrict__ in, long rows, long cols, long ld_in,
                                       double* __restrict__ out) {
@@ -338,7 +357,18 @@ void eri_free(afq_system s) {
     s->eri_nunit[sp] = 0;
   }
   s->eri_ready = false;
+  s->eri_prec = -1;
 }
+
+// bytes of the stored tensor of one distinct spin block in the given precision
+size_t tensor_bytes_of(const Shape& h, int prec) {
+  return prec == AFQ_FP64 ? (size_t)h.NM * h.NM * 8 : 2 * plane_bytes(h.rows_a, h.nchunk);
+}
+
+// column blocks of the FP64 form: NB about 8, widths a multiple of 32 (16-byte
+// aligned column offsets for the tiled GEMM)
+constexpr int NB64 = 8;
+long blk64(long NM) { return std::max<long>(32, (NM + NB64 - 1) / NB64 + 31) / 32 * 32; }
 
 // the four-index form pays when it needs fewer products than the Cholesky form
 // ((N M)^2 / 2 against X N^2 M per walker and spin, i.e. M < 2 X), the system
@@ -350,12 +380,13 @@ bool eri_pays(afq_system s) {
   for (int sp = 0; sp < (s->n_up == s->n_dn ? 1 : 2); ++sp) {
     const Shape h = shape_of(s, sp);
     if (h.NM < 4096) return false;
-    bytes += 2 * plane_bytes(h.rows_a, h.nchunk);
+    bytes += tensor_bytes_of(h, s->prec);
   }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
   const long nm = std::max(shape_of(s, 0).NM, shape_of(s, 1).NM);
-  const size_t transient = (size_t)nm * nm * 8 + (size_t)nm * s->X * 8;
+  // set-up transients: Lt transposed and the FP64 Gram matrix before its permutation
+  const size_t transient = (size_t)nm * s->X * 8 + (size_t)nm * nm * 8;
   return bytes <= free_b / 4 && bytes + transient <= free_b / 2;
 }
 
@@ -380,12 +411,13 @@ int eri_prepare(afq_system s) {
     const int off = s->spin_off(sp);
     const Shape h = shape_of(s, sp);
     AFQ_CHECK(h.NM <= 65535L * 32, AFQ_E_UNSUPPORTED, "exchange (four-index): N M too large");
-    const std::vector<int> units = make_units(h, choose_kper(h));
+    const bool f64 = s->prec == AFQ_FP64;
+    const std::vector<int> units = f64 ? std::vector<int>() : make_units(h, choose_kper(h));
     DevBuf LT, W;
     int rc = LT.alloc((size_t)h.NM * X * 8);
+    if (rc == AFQ_OK) rc = s->eri_w[sp].alloc(tensor_bytes_of(h, s->prec));
     if (rc == AFQ_OK) rc = W.alloc((size_t)h.NM * h.NM * 8);
-    if (rc == AFQ_OK) rc = s->eri_w[sp].alloc(2 * plane_bytes(h.rows_a, h.nchunk));
-    if (rc == AFQ_OK) rc = s->eri_units[sp].alloc(units.size() * sizeof(int));
+    if (rc == AFQ_OK && !f64) rc = s->eri_units[sp].alloc(units.size() * sizeof(int));
     if (rc == AFQ_OK) {
       // LT[(a,k)][n] = Lt_n[a][k]
       hipLaunchKernelGGL(transpose_real_kernel, dim3(grid_of((long)X * h.NM)), dim3(256), 0, st,
@@ -401,14 +433,19 @@ int eri_prepare(afq_system s) {
       g.C = W.as<double>(); g.ldc = h.NM; g.cC = false;
       rc = gemm<double>(g, st);
     }
-    if (rc == AFQ_OK) {
+    if (rc == AFQ_OK && f64) {   // FP64 mode keeps W' itself as the operand
+      hipLaunchKernelGGL(eri_perm_w_kernel, dim3(grid_of(h.NM * h.NM)), dim3(256), 0, st, W.as<double>(), M, h.NM,
+                         s->eri_w[sp].as<double>());
+      rc = hip_status(hipGetLastError(), "exchange (four-index): permute");
+    }
+    if (rc == AFQ_OK && !f64) {
       unsigned short* hi = s->eri_w[sp].as<unsigned short>();
       const size_t pe = plane_bytes(h.rows_a, h.nchunk) / 2;   // elements per plane
       hipLaunchKernelGGL(eri_pack_w_kernel, dim3(grid_of((long)h.nchunk * h.rows_a * KC)), dim3(256), 0, st,
                          W.as<double>(), M, (int)h.NM, h.rows_a, h.nchunk, hi, hi + pe);
       rc = hip_status(hipGetLastError(), "exchange (four-index): pack");
     }
-    if (rc == AFQ_OK)
+    if (rc == AFQ_OK && !f64)
       rc = hip_status(hipMemcpyAsync(s->eri_units[sp].p, units.data(), units.size() * sizeof(int),
                                      hipMemcpyHostToDevice, st),
                       "exchange (four-index): units");
@@ -422,20 +459,21 @@ int eri_prepare(afq_system s) {
     s->eri_nunit[sp] = (int)(units.size() / 4);
   }
   s->eri_ready = true;
+  s->eri_prec = s->prec;
   return AFQ_OK;
 }
 
 }  // namespace
 
 int eri_sync(afq_system s) {
-  const bool can = s->kp_nk == 0 && s->msd_n == 0 && s->prec == AFQ_BF16X3 && s->real_trial &&
-                   s->eri_form != AFQ_EXCH_CHOLESKY;
-  if (!can) {
+  const bool can = s->kp_nk == 0 && s->msd_n == 0 && (s->prec == AFQ_BF16X3 || s->prec == AFQ_FP64) &&
+                   s->real_trial && s->eri_form != AFQ_EXCH_CHOLESKY;
+  if (!can || (s->eri_ready && s->eri_prec != s->prec)) {
     if (s->eri_ready) {
       eri_free(s);
       ++s->version;
     }
-    return AFQ_OK;
+    if (!can) return AFQ_OK;
   }
   if (s->eri_ready) return AFQ_OK;
   if (s->eri_form == AFQ_EXCH_AUTO) {
@@ -458,6 +496,11 @@ static int eri_nsp(afq_system s) { return s->eri_share ? 2 : 1; }
 
 int eri_alloc_scratch(afq_system s, afq_walkers w) {
   if (!s->eri_ready) return AFQ_OK;
+  if (s->eri_prec == AFQ_FP64) {   // Z^T of one spin at a time
+    const size_t zb = (size_t)w->nw * std::max(shape_of(s, 0).NM, shape_of(s, 1).NM) * sizeof(double2);
+    if (w->eri_part.bytes < zb) AFQ_RET(w->eri_part.alloc(zb));
+    return AFQ_OK;
+  }
   const long rows_b = rows_b_of(eri_nsp(s) * w->nw);
   size_t tb = 0, pb = 0;
   for (int sp = 0; sp < 2; ++sp) {
@@ -471,6 +514,7 @@ int eri_alloc_scratch(afq_system s, afq_walkers w) {
 }
 
 int eri_pack(afq_system s, afq_walkers w, int sp, hipStream_t st) {
+  if (s->eri_prec == AFQ_FP64) return AFQ_OK;   // the GEMMs read Theta^T in place
   const Shape h = shape_of(s, sp);
   const int nsp = eri_nsp(s);
   const long rows_b = rows_b_of(nsp * w->nw);
@@ -486,7 +530,78 @@ int eri_pack(afq_system s, afq_walkers w, int sp, hipStream_t st) {
   return AFQ_OK;
 }
 
+// out[w * ld_out] = sum_{i < n} a[w * lda + i] z[w * ldz + i] (complex, no
+// conjugate), one 256-thread workgroup per walker, fixed-order tree; the
+// entries 1..X-1 after it are zeroed (the assembly sums over all X entries)
+__global__ __launch_bounds__(256) void cdot_rows_kernel(const double2* __restrict__ a, long lda,
+                                                        const double2* __restrict__ z, long ldz, long n,
+                                                        double2* __restrict__ out, long ld_out, int X) {
+  __shared__ double2 red[256];
+  const int w = blockIdx.x, t = threadIdx.x;
+  const double2* aw = a + (long)w * lda;
+  const double2* zw = z + (long)w * ldz;
+  double2 acc = make_double2(0.0, 0.0);
+  for (long i = t; i < n; i += 256) acc = cadd(acc, cmul(aw[i], zw[i]));
+  red[t] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] = cadd(red[t], red[t + h]);
+    __syncthreads();
+  }
+  double2* o = out + (long)w * ld_out;
+  if (t == 0) o[0] = red[0];
+  for (int k = 1 + t; k < X; k += 256) o[k] = make_double2(0.0, 0.0);
+}
+
+static int launch_cdot_rows(const double2* a, long lda, const double2* z, long ldz, long n, int nw, double2* out,
+                            long ld_out, int X, hipStream_t st) {
+  hipLaunchKernelGGL(cdot_rows_kernel, dim3(nw), dim3(256), 0, st, a, lda, z, ldz, n, out, ld_out, X);
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+
+// FP64 form, one spin: Z^T (nw x NM) over the column blocks, then the dot products
+static int eri_exchange_f64(afq_system s, afq_walkers w, int sp, hipStream_t st) {
+  const Shape h = shape_of(s, sp);
+  const int wsp = s->eri_share ? 0 : sp;
+  const long NM = h.NM, ldt = (long)s->ntot * s->M;
+  AFQ_CHECK(s->eri_ready && s->eri_w[wsp].bytes >= (size_t)NM * NM * 8, AFQ_E_STATE,
+            "exchange (four-index, FP64): tensor not prepared");
+  AFQ_CHECK(w->eri_part.bytes >= (size_t)w->nw * NM * sizeof(double2), AFQ_E_STATE,
+            "exchange (four-index, FP64): walker scratch not prepared");
+  const double* Wt = s->eri_w[wsp].as<double>();
+  const double* th = w->theta.as<double>() + 2L * s->spin_off(sp) * s->M;   // row w: Theta-hat of walker w
+  double* Z = w->eri_part.as<double>();
+  const long bw = blk64(NM);
+  for (long j0 = 0; j0 < NM; j0 += bw) {
+    const long nj = std::min(bw, NM - j0);
+    GemmArgs<double> g = gemm_args<double>();
+    g.m = w->nw; g.n = (int)nj;
+    g.A = th; g.lda = ldt; g.cA = true;
+    g.ldb = NM; g.cB = false;
+    g.C = Z + 2 * j0; g.ldc = NM; g.cC = true;
+    // Z_J = Theta-hat_J^T W'_JJ
+    g.k = (int)nj;
+    g.A = th + 2 * j0;
+    g.B = Wt + j0 * NM + j0;
+    AFQ_RET(gemm<double>(g, st));
+    if (j0 > 0) {   // Z_J += 2 Theta-hat_{<J}^T W'_{<J,J}
+      g.k = (int)j0;
+      g.A = th;
+      g.B = Wt + j0;
+      g.ar = 2.0; g.ai = 0.0; g.br = 1.0; g.bi = 0.0;
+      AFQ_RET(gemm<double>(g, st));
+    }
+  }
+  return launch_cdot_rows(reinterpret_cast<const double2*>(th), ldt, reinterpret_cast<const double2*>(Z), NM,
+                          NM, w->nw, w->troo.as<double2>() + (long)sp * s->X, 2L * s->X, s->X, st);
+}
+
 int eri_exchange(afq_system s, afq_walkers w, int sp, hipStream_t st) {
+  if (s->eri_prec == AFQ_FP64) {
+    for (int q = 0; q < eri_nsp(s); ++q) AFQ_RET(eri_exchange_f64(s, w, sp + q, st));
+    return AFQ_OK;
+  }
   const Shape h = shape_of(s, sp);
   const int wsp = s->eri_share ? 0 : sp;
   const int nsp = eri_nsp(s);

@@ -63,7 +63,7 @@ int system_prepare_pack(afq_system s, int prec) {
     AFQ_RET(pack_a(prec, s->Lt.as<double2>(), s->X, s->ntot, s->M, s->spin_off(sp), ps, s->real_trial,
                    s->apack[sp].p, s->apack_lo[sp].p, s->stream));
   }
-  if (prec == AFQ_BF16X3 && s->real_trial && !s->LtRe.p) {
+  if ((prec == AFQ_BF16X3 || prec == AFQ_FP64) && s->real_trial && !s->LtRe.p) {   // Coulomb GEMM and four-index set-up
     const long n = (long)s->X * s->ntot * s->M;
     AFQ_RET(s->LtRe.alloc(n * sizeof(double)));
     AFQ_RET(real_part(s->Lt.as<double2>(), s->LtRe.as<double>(), n, s->stream));

@@ -1,5 +1,5 @@
-"""The four-index exchange form (split-BF16x3, real trial) against the FP64
-oracle and against the Cholesky form: sum_n tr(Omega_n Omega_n) as the
+"""The four-index exchange form (split-BF16x3 and FP64 modes, real trial)
+against the FP64 oracle and against the Cholesky form: sum_n tr(Omega_n Omega_n) as the
 quadratic form of the half-rotated two-electron tensor, contracted over its
 upper block triangle. Shapes cover one and several 256-row blocks with ragged
 tails, work units of a single chunk and several runs per row block, walker
@@ -53,8 +53,12 @@ CASES = [(20, 14, 14, 50, 5, False), (64, 20, 17, 100, 70, False), (50, 9, 9, 12
          (30, 5, 3, 40, 3, False)]
 
 
+TOL = {"bf16x3": 1e-5, "fp64": 1e-10}
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
 @pytest.mark.parametrize("case", CASES)
-def test_four_index_energy_matches_the_oracle(api, case):
+def test_four_index_energy_matches_the_oracle(api, case, prec):
     M, nu, nd, X, nw, distinct = case
     s = synth.make_system(M, nu, nd, X, seed=M + X + 7)
     s.e_core = 0.21
@@ -62,7 +66,7 @@ def test_four_index_energy_matches_the_oracle(api, case):
         s = _rotate_down_block(s, seed=M)
     W = synth.perturbed_walkers(s, nw, 0.15, seed=11)
     w = synth.random_weights(nw, seed=12)
-    sysg = api.System.from_synth(s, precision="bf16x3", exchange_form="four_index")
+    sysg = api.System.from_synth(s, precision=prec, exchange_form="four_index")
     form, nbytes = sysg.exchange_form()
     assert form == "four_index" and nbytes > 0
     wk = api.Walkers(sysg, nw, W, w)
@@ -71,39 +75,41 @@ def test_four_index_energy_matches_the_oracle(api, case):
     errs = {"E_L": rel_vec(el, rel), "E1": rel_vec(parts[:, 0], rparts[:, 0]),
             "EJ": rel_vec(parts[:, 1], rparts[:, 1]), "EK": rel_vec(parts[:, 2], rparts[:, 2]),
             "vbar": rel_fro(vb, rvb), "E_mix": rel_scalar(float(em[0]), rem)}
-    print(case, {k: f"{v:.2e}" for k, v in errs.items()})
+    print(prec, case, {k: f"{v:.2e}" for k, v in errs.items()})
     for k, v in errs.items():
-        assert v < 1e-5, (k, v)
+        assert v < TOL[prec], (k, v)
     # the Cholesky form of the same mode gives the same exchange energy
-    chol = api.System.from_synth(s, precision="bf16x3", exchange_form="cholesky")
+    chol = api.System.from_synth(s, precision=prec, exchange_form="cholesky")
     assert chol.exchange_form() == ("cholesky", 0)
     parts_c = to_np(api.Walkers(chol, nw, W, w).energy()[1])
-    assert rel_vec(parts[:, 2], parts_c[:, 2]) < 1e-5
+    assert rel_vec(parts[:, 2], parts_c[:, 2]) < TOL[prec]
 
 
-def test_four_index_walk_matches_the_oracle(api):
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
+def test_four_index_walk_matches_the_oracle(api, prec):
     """Ten steps with QR every 5 through the four-index exchange (N M = 1024)."""
     s = synth.make_system(64, 16, 16, 256, seed=3)
     nw, steps, dt = 6, 10, 0.005
     fields = synth.make_fields(steps, nw, 256, seed=1003)
     W0 = synth.perturbed_walkers(s, nw, 0.05, seed=9)
-    sysg = api.System.from_synth(s, precision="bf16x3", exchange_form="four_index")
+    sysg = api.System.from_synth(s, precision=prec, exchange_form="four_index")
     wk = api.Walkers(sysg, nw, W0, np.ones(nw))
     out = wk.step(steps, dt, fields=fields, qr_every=5)
     torch.cuda.synchronize()
     o = afqmc.run(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, W0, np.ones(nw), fields, dt, qr_every=5)
     for k in ("emix", "eloc", "weights", "ratio"):
         err = rel_vec(to_np(out[k]), o[k])
-        print(k, f"{err:.2e}")
-        assert err < 1e-5, k
+        print(prec, k, f"{err:.2e}")
+        assert err < TOL[prec], k
 
 
-def test_four_index_is_repeatable_bitwise(api):
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
+def test_four_index_is_repeatable_bitwise(api, prec):
     """Fixed-order partial sums: two identical runs agree bit for bit."""
     s = synth.make_system(48, 12, 11, 60, seed=21)
     outs = []
     for _ in range(2):
-        sysg = api.System.from_synth(s, precision="bf16x3", exchange_form="four_index")
+        sysg = api.System.from_synth(s, precision=prec, exchange_form="four_index")
         wk = api.Walkers(sysg, 9)
         outs.append(wk.step(3, 0.005, seed=4, qr_every=2))
     torch.cuda.synchronize()
@@ -118,8 +124,10 @@ def test_exchange_form_selection(api):
     g.set_exchange_form("four_index")
     form, nbytes = g.exchange_form()
     assert form == "four_index" and nbytes > 0
-    g.set_precision("fp64")                               # the form exists in split-BF16x3 mode only
+    g.set_precision("cfp32")                              # not in complex FP32 mode
     assert g.exchange_form() == ("cholesky", 0)
+    g.set_precision("fp64")                               # FP64 keeps W' itself: (N M)^2 doubles
+    assert g.exchange_form() == ("four_index", (4 * 24) ** 2 * 8)
     g.set_precision("bf16x3")
     assert g.exchange_form()[0] == "four_index"
     g.set_exchange_form("cholesky")
