@@ -28,7 +28,15 @@ eye against the definitions:
     A = i sqrt(dt) sum_n (x_n - xbar_n) L^n and T_K the order-K Taylor series;
   - importance function I = (O'/O) exp(sum_n x_n xbar_n - xbar_n^2/2) exp(dt E_shift),
     phaseless weight w <- w |I| max(0, cos(arg(O'/O)));
-  - periodic thin QR with a positive diagonal R, O <- O / prod_s det R^s.
+  - periodic thin QR with a positive diagonal R, O <- O / prod_s det R^s;
+  - optional mean-field background subtraction (cited with the phaseless
+    method, not described in the paper): for any real vector c (normally the
+    trial's mean field c_n = sum_s tr(L^n G_T^s)) the two-body term is
+    1/2 sum_n (v_n - c_n)^2 + sum_n c_n v_n - 1/2 sum_n c_n^2, so the one-body
+    factor uses h' + sum_n c_n L^n, the force bias is taken for v_n - c_n, the
+    c-number part of exp(i sqrt(dt) (x - xbar)(v - c)) multiplies the
+    overlap ratio (and so enters the phaseless angle), and the constant
+    exp(dt/2 sum_n c_n^2) multiplies every weight.
 
 Walkers are stored as W[w] with shape (M, n_up + n_dn): up columns first.
 """
@@ -170,6 +178,16 @@ def force_bias_shift(vbar, dt, cap=0.0):
     return xbar
 
 
+def mean_field_bias(chol, phi_t, n_up, n_dn):
+    """c_n = sum_s tr(L^n G_T^s), G_T^s = T^s T^sH: the force bias of the trial
+    itself (real for real symmetric L^n), the usual background vector."""
+    out = np.zeros(chol.shape[0])
+    for b in spin_blocks(n_up, n_dn):
+        T = phi_t[:, b]
+        out += np.einsum("nik,ki->n", chol, T @ T.conj().T).real
+    return out
+
+
 def hs_operator(chol, x, xbar, dt):
     """A = i sqrt(dt) sum_n (x_n - xbar_n) L^n (M x M)."""
     return np.tensordot(1j * np.sqrt(dt) * (x - xbar), chol, axes=1)
@@ -183,16 +201,21 @@ def importance_log_factor(x, xbar):
 # ---------------------------------------------------------------------------
 # The walk
 # ---------------------------------------------------------------------------
-def prepare(h1, chol, phi_t, n_up, n_dn, dt):
+def prepare(h1, chol, phi_t, n_up, n_dn, dt, vmf=None):
+    """One-time set-up of the walk. With a background vector vmf (mean-field
+    subtraction) the one-body factor is exp(-dt/2 (h' + sum_n vmf_n L^n))."""
     hp = one_body_corrected(h1, chol)
+    if vmf is not None:
+        vmf = np.asarray(vmf, dtype=np.float64)
+        hp = hp + np.tensordot(vmf, chol, axes=1)
     B1 = sym_expm(-0.5 * dt * hp)
     ht, Lt = half_rotate(h1, chol, phi_t, n_up, n_dn)
-    return dict(hp=hp, B1=B1, ht=ht, Lt=Lt)
+    return dict(hp=hp, B1=B1, ht=ht, Lt=Lt, vmf=vmf)
 
 
 def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
         e_shift=0.0, order=6, e_core=0.0, energy="half", record_walkers=False, pre=None,
-        fb_cap=0.0, w_cap=0.0, comb_every=0, comb_xi=None, bp_start=None, bp_len=0, msd=None):
+        fb_cap=0.0, w_cap=0.0, comb_every=0, comb_xi=None, bp_start=None, bp_len=0, msd=None, vmf=None):
     """Run len(fields) steps. fields[k, w, n] are the standard-normal HS fields.
     `pre` may hold prepare(h1, chol, phi_t, n_up, n_dn, dt) computed beforehand.
 
@@ -216,6 +239,10 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
     out["log_I"][k, w] is the complex log of the importance factor I of
     walker w in step k, before the phaseless projection (zero for frozen
     walkers).
+    With vmf (a real vector of n_chol entries, or taken from `pre`) the walk
+    subtracts that background: B1 from h' + sum vmf L, xbar for vbar - vmf,
+    log I += c0 + dt/2 sum vmf^2 with c0 = -i sqrt(dt) sum_n (x_n - xbar_n)
+    vmf_n, and the phaseless angle is Im(log r + c0).
     With msd = dict(dets=[...], coeffs=[...]) the trial is the orthogonal
     multi-determinant expansion of oracle/msd.py (phi_t is then unused):
     overlaps, E_L and the force bias come from its determinant sums, and the
@@ -224,8 +251,11 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
     M = h1.shape[0]
     nw = W0.shape[0]
     if pre is None:
-        pre = prepare(h1, chol, phi_t, n_up, n_dn, dt)
+        pre = prepare(h1, chol, phi_t, n_up, n_dn, dt, vmf=vmf)
+    elif vmf is not None:
+        assert pre.get("vmf") is not None and np.array_equal(pre["vmf"], vmf), "pre was prepared for another vmf"
     B1, ht, Lt = pre["B1"], pre["ht"], pre["Lt"]
+    vmf = pre.get("vmf")
     W = W0.astype(np.complex128).copy()
     w = np.asarray(weights0, dtype=np.float64).copy()
     if msd is not None:
@@ -278,7 +308,7 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
             if not alive[i]:
                 continue
             x = fields[k, i]
-            xbar = force_bias_shift(vb[i], dt, fb_cap)
+            xbar = force_bias_shift(vb[i] if vmf is None else vb[i] - vmf, dt, fb_cap)
             A = hs_operator(chol, x, xbar, dt)
             if in_window(k):
                 out["bp_coefs"][k - bp_start, i] = 1j * np.sqrt(dt) * (x - xbar)
@@ -287,8 +317,13 @@ def run(h1, chol, phi_t, n_up, n_dn, W0, weights0, fields, dt, qr_every=5,
             log_r = logOn - logO[i]
             r = np.exp(log_r)
             log_I = log_r + importance_log_factor(x, xbar) + dt * e_shift
+            phase = log_r.imag
+            if vmf is not None:        # c-number part of the shifted operators, and the constant
+                c0 = -1j * np.sqrt(dt) * np.sum((x - xbar) * vmf)
+                log_I = log_I + c0 + 0.5 * dt * np.sum(vmf * vmf)
+                phase = phase + c0.imag
             out["log_I"][k, i] = log_I
-            cos_dth = np.cos(log_r.imag)
+            cos_dth = np.cos(phase)
             wn = w[i] * np.exp(log_I.real) * cos_dth if cos_dth > 0.0 else 0.0
             out["ratio"][k, i] = r
             out["cosdt"][k, i] = cos_dth

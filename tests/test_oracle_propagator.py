@@ -17,35 +17,12 @@ tests patch the oracle on the CPU and check that the pin catches it.
 """
 import numpy as np
 import pytest
-from numpy.polynomial.hermite_e import hermegauss
 from scipy.linalg import expm
 
 from oracle import afqmc, fci, kpoint
 from paper_2003_01831_amd import synth
 
-N_NODES = 16          # per field; the integrand is a degree-24 polynomial times exp(x xbar)
-
-
-def _grid(n_fields):
-    t, g = hermegauss(N_NODES)
-    g = g / np.sqrt(2.0 * np.pi)
-    xs = np.stack([m.ravel() for m in np.meshgrid(*([t] * n_fields), indexing="ij")], axis=1)
-    gs = np.prod(np.stack([m.ravel() for m in np.meshgrid(*([g] * n_fields), indexing="ij")], axis=1), axis=1)
-    return xs, gs
-
-
-def _averaged_step_error(step, H, W, n_up, n_dn, n_fields, dt, e_shift):
-    """|| sum_q g_q exp(log I_q - log r_q) c(W'_q) - exp(-dt (H - E_shift)) c(W) || / ||.||"""
-    xs, gs = _grid(n_fields)
-    nq = len(gs)
-    o = step(np.repeat(W[None], nq, axis=0), xs[None], dt, e_shift)
-    assert o["alive"].all(), "a quadrature node was killed by the phaseless projection"
-    acc = 0.0
-    for q in range(nq):
-        acc = acc + gs[q] * np.exp(o["log_I"][0, q] - np.log(o["ratio"][0, q])) * fci.coefficients(
-            o["W"][q], n_up, n_dn)
-    exact = expm(-dt * (H - e_shift * np.eye(len(H)))) @ fci.coefficients(W, n_up, n_dn)
-    return np.linalg.norm(acc - exact) / np.linalg.norm(exact)
+from prop_pin import averaged_step_error as _averaged_step_error
 
 
 # --------------------------------------------------------------------------
