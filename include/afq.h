@@ -201,6 +201,27 @@ int afq_kp_system_create(afq_system *out, int nk, const int32_t *kq, int m, int 
  * Synchronises. */
 int afq_system_set_msd(afq_system s, const double *C, int n_det, const double *coeffs,
                        const int32_t *exc);
+/* Mean-field background subtraction, a standard part of the phaseless method
+ * that Section sec:afqmc cites (the paper gives no formulas). For a real
+ * vector c the two-body term of Eq. eq:hamil in Cholesky form is
+ *   1/2 sum_n (v_n - c_n)^2 + sum_n c_n v_n - 1/2 sum_n c_n^2,
+ * so later steps sample the shifted operators v_n - c_n: the one-body factor
+ * becomes B1 = exp(-dt (h' + sum_n c_n L^n) / 2), the force bias is
+ * xbar_n = -i sqrt(dt) (vbar_n - c_n), and the importance factor gains the
+ * c-number c0 = -i sqrt(dt) sum_n (x_n - xbar_n) c_n and exp(dt/2 sum c_n^2);
+ * the phaseless angle is arg(r) + Im c0 (the overlap ratio of the whole
+ * shifted propagator). Local energies are unchanged; ratio outputs stay O'/O.
+ *   on          0: off (the default); 1: on
+ *   background  NULL: c is the trial's own force bias, c_n = sum_s tr(L^n
+ *               T^s T^sH) (the mean field); else a device vector of n_chol
+ *               float64 (any finite real vector is exact)
+ * Plain and multi-determinant systems (the reference determinant's mean
+ * field); AFQ_E_UNSUPPORTED for k-point systems. A back-propagation window
+ * must not span a change (AFQ_E_STATE), batches capture again. Synchronises. */
+int afq_system_set_background(afq_system s, int on, const double *background);
+/* *on = 1 while a background is subtracted; background (device, n_chol
+ * float64, may be NULL) receives c_n then. */
+int afq_system_background(afq_system s, int *on, double *background);
 /* Frees device memory. NULL-safe. */
 int afq_system_destroy(afq_system s);
 

@@ -26,6 +26,8 @@ SIGNATURES = {
     "afq_system_create": (_i, [C.POINTER(_vp), _i, _i, _i, _i, _vp, _vp, _vp, _d, _i, _vp, _u32]),
     "afq_system_set_precision": (_i, [_vp, _i]),
     "afq_system_set_msd": (_i, [_vp, _vp, _i, _vp, _vp]),
+    "afq_system_set_background": (_i, [_vp, _i, _vp]),
+    "afq_system_background": (_i, [_vp, C.POINTER(_i), _vp]),
     "afq_system_set_exchange_form": (_i, [_vp, _i]),
     "afq_system_exchange_form": (_i, [_vp, C.POINTER(_i), C.POINTER(_u64)]),
     "afq_kp_system_create": (_i, [C.POINTER(_vp), _i, _vp, _i, _i, _i, _i, _vp, _vp, _vp, _d, _i, _vp]),

@@ -120,6 +120,20 @@ class System:
         names = {v: k for k, v in EXCHANGE_FORM.items()}
         return names[f.value], int(b.value)
 
+    def set_background(self, on=True, vector=None):
+        """Mean-field background subtraction for later steps: on with vector None
+        uses the trial's own force bias; a vector (n_chol reals) is used as given."""
+        v = None if vector is None else _as_dev(vector, torch.float64)
+        check(self.lib.afq_system_set_background(self.handle, 1 if on else 0, _ptr(v)))
+
+    def background(self):
+        """The subtracted background vector (device tensor), or None when off."""
+        on = C.c_int()
+        out = torch.zeros(self.n_chol, dtype=torch.float64, device=_dev())
+        check(self.lib.afq_system_background(self.handle, C.byref(on), _ptr(out)))
+        torch.cuda.synchronize()
+        return out if on.value else None
+
     MSD_KMAX = 4
 
     def set_msd(self, basis, excitations, coeffs):

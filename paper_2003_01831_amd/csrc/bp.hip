@@ -37,6 +37,7 @@ int bp_begin(afq_walkers w, int n_bp) {
   w->bp_dt = -1.0;
   w->bp_order = 0;
   w->bp_prec = s->prec;
+  w->bp_b1 = s->b1_serial;
   return AFQ_OK;
 }
 
@@ -55,6 +56,8 @@ int bp_check_step(afq_walkers w, int n_steps, double dt, int order) {
   if (w->bp_n < 0 || w->bp_rec >= w->bp_n || n_steps == 0) return AFQ_OK;
   AFQ_CHECK(w->sys->prec == w->bp_prec, AFQ_E_STATE,
             "afq_step: the precision changed while a back-propagation window records");
+  AFQ_CHECK(w->sys->b1_serial == w->bp_b1, AFQ_E_STATE,
+            "afq_step: the background subtraction changed while a back-propagation window records");
   if (w->bp_rec > 0) {
     AFQ_CHECK(dt == w->bp_dt && order == w->bp_order, AFQ_E_INVALID,
               "afq_step: dt and the Taylor order must stay fixed while a back-propagation window records");
@@ -103,6 +106,8 @@ int bp_rdm1(afq_walkers w, int qr_every, double* rdm_out, double* wsum_out) {
   AFQ_CHECK(w->counter == w->bp_start + (uint64_t)w->bp_n, AFQ_E_STATE,
             "afq_bp_rdm1: steps were taken after the window filled (the weights must be those at its end)");
   AFQ_CHECK(s->prec == w->bp_prec, AFQ_E_STATE, "afq_bp_rdm1: the precision changed since the window opened");
+  AFQ_CHECK(s->b1_serial == w->bp_b1, AFQ_E_STATE,
+            "afq_bp_rdm1: the background subtraction changed since the window opened");
   hipStream_t st = s->stream;
   const int M = s->M, ntot = s->ntot, nw = w->nw, X = s->X;
   const long per = (long)M * ntot;

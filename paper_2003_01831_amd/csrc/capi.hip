@@ -87,6 +87,27 @@ int afq_system_set_msd(afq_system s, const double* C, int n_det, const double* c
   AFQ_GUARD(AFQ_RET(check_device(s)); return msd_set(s, C, n_det, coeffs, exc);)
 }
 
+int afq_system_set_background(afq_system s, int on, const double* background) {
+  AFQ_CHECK(s, AFQ_E_INVALID, "afq_system_set_background: system is NULL");
+  AFQ_CHECK(on == 0 || on == 1, AFQ_E_INVALID, "afq_system_set_background: on must be 0 or 1");
+  AFQ_CHECK(s->kp_nk == 0, AFQ_E_UNSUPPORTED,
+            "afq_system_set_background: not available for k-point systems (complex vectors)");
+  AFQ_GUARD(AFQ_RET(check_device(s)); return system_set_background(s, on, on ? background : nullptr);)
+}
+
+int afq_system_background(afq_system s, int* on, double* background) {
+  AFQ_CHECK(s && on, AFQ_E_INVALID, "afq_system_background: NULL argument");
+  *on = s->mf_on ? 1 : 0;
+  if (background && s->mf_on)
+    AFQ_GUARD({
+      AFQ_RET(check_device(s));
+      AFQ_TRY_HIP(hipMemcpyAsync(background, s->vmf.p, (size_t)s->X * sizeof(double), hipMemcpyDeviceToDevice,
+                                 s->stream));
+      return AFQ_OK;
+    })
+  return AFQ_OK;
+}
+
 int afq_system_destroy(afq_system s) {
   if (!s) return AFQ_OK;
   AFQ_GUARD((void)hipStreamSynchronize(s->stream); delete s; return AFQ_OK;)

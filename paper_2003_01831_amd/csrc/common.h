@@ -128,8 +128,12 @@ struct afq_system_s {
   bool lt_share = false;       // the two trial blocks are equal: lt32[1] is not built, the force bias contracts
                                // Theta_up + Theta_dn with lt32[0]
   DevBuf hp;                   // h' = h - 1/2 sum L L   (M x M f64)
-  DevBuf B1;                   // exp(-dt h'/2)          (M x M f64)
+  DevBuf B1;                   // exp(-dt h'/2)          (M x M f64), or exp(-dt h_mf/2) with a background
   double B1_dt = -1.0;
+  bool mf_on = false;          // mean-field background subtraction
+  DevBuf vmf;                  // X f64: the background vector c_n
+  DevBuf hp_mf;                // h' + sum_n c_n L^n (M x M f64)
+  unsigned b1_serial = 0;      // bumped when the one-body factor changes other than through dt
   DevBuf ht;                   // (T^H h)  ntot x M complex
   DevBuf Lt;                   // (T^H L^n) X x ntot x M complex
   DevBuf LtRe;                 // real part of Lt (real trial, split-BF16x3 force bias)
@@ -202,6 +206,7 @@ struct afq_walkers_s {
   double bp_dt = -1.0;         // time step of the recorded steps
   int bp_order = 0;            // Taylor order of the recorded steps
   int bp_prec = -1;            // precision of the recorded coefficients
+  unsigned bp_b1 = 0;          // system b1_serial when the window opened
   DevBuf bp_W0;                // walkers when the window opened (nw x M x ntot c128)
   DevBuf bp_coef, bp_tmp;      // bp_n x nw x X conj(c) (f64 or f32 complex); gather scratch
   DevBuf bp_psi;               // back-propagated trial (nw x M x ntot c128)
@@ -218,7 +223,7 @@ struct afq_walkers_s {
   DevBuf e1;                   // nw complex
   DevBuf eloc, parts, vbar;    // nw complex, nw x 3 complex, nw x X complex
   DevBuf coef;                 // nw x X complex (f64 or f32)
-  DevBuf lfac;                 // nw complex: sum_n x xbar - xbar^2/2
+  DevBuf lfac;                 // nw: (Re log of the importance factor without the ratio, background phase)
   DevBuf amat;                 // nw x M x M complex (f64 or f32)
   DevBuf t1, t2;               // Taylor terms (nw x M x ntot, f64 or f32)
   DevBuf u;                    // Taylor sum (nw x M x ntot c128)
@@ -352,6 +357,7 @@ int r32_coulomb(afq_system s, afq_walkers w, hipStream_t st);
 
 // four-index exchange (eri.hip)
 // builds or frees the W'' planes to match the system's precision, trial and form
+int system_set_background(afq_system s, int on, const double* vmf);
 int eri_sync(afq_system s);
 int eri_alloc_scratch(afq_system s, afq_walkers w);
 size_t eri_tensor_bytes(afq_system s);

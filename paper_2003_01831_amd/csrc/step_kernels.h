@@ -19,7 +19,9 @@ struct AssembleArgs {
   double2* eloc_out;       // nw (optional, caller)
   double2* parts;          // nw x 3 (optional)
   double2* vbar_out;       // nw x X (optional)
-  double2* lfac;           // nw (when coefficients are produced)
+  double2* lfac;           // nw (when coefficients are produced): (Re of sum_n x xbar - xbar^2/2 plus the
+                           // background's c-number and constant, Im of the c-number = phase of the ratio)
+  const double* vmf;       // X background c_n (mean-field subtraction) or NULL
   const double2* parts_in; // nw x 3 (E1, EJ, EK) given instead of computed (multi-determinant trial)
   const double2* vbar_in;  // nw x X force bias given with parts_in
 };

@@ -312,7 +312,8 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs a, CT* __res
   const int w = blockIdx.x, t = threadIdx.x;
   const long per = (long)a.ntot * a.M;
   const double2* th = a.thetaT + w * per;
-  double2 v[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+  double2 v[5] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0),
+                  make_double2(0, 0)};
   const bool given = a.parts_in != nullptr;
   if (!given)
     for (long e = t; e < per; e += 256) v[0] = cadd(v[0], cmul(a.ht[e], th[e]));
@@ -347,21 +348,27 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs a, CT* __res
       if (a.vbar_out) a.vbar_out[(long)w * a.X + n] = vb;
       if (coef) {
         const double x = xs[h];
-        double2 xb = make_double2(sdt * vb.y, -sdt * vb.x);  // -i sqrt(dt) vbar
+        const double mfn = a.vmf ? a.vmf[n] : 0.0;           // background c_n (0: none)
+        double2 xb = make_double2(sdt * vb.y, -sdt * (vb.x - mfn));  // -i sqrt(dt) (vbar - c)
         if (a.fb_cap > 0.0) {                               // cap |xbar|, keep its phase
           const double m = sqrt(cabs2(xb));
           if (m > a.fb_cap) xb = cscale(xb, a.fb_cap / m);
         }
-        CT c;                                               // i sqrt(dt) (x - xbar)
-        c.x = sdt * xb.y;
-        c.y = sdt * (x - xb.x);
+        const double cr = sdt * xb.y, ci = sdt * (x - xb.x);   // i sqrt(dt) (x - xbar)
+        CT c;
+        c.x = cr;
+        c.y = ci;
         coef[(long)w * a.X + n] = c;
         const double2 xb2 = cmul(xb, xb);
         v[3] = cadd(v[3], make_double2(x * xb.x - 0.5 * xb2.x, x * xb.y - 0.5 * xb2.y));
+        if (a.vmf) {   // c-number -c_n i sqrt(dt) (x - xbar) of the shifted operator, and dt/2 c_n^2
+          v[3].x += -mfn * cr + 0.5 * a.dt * mfn * mfn;
+          v[4].x += -mfn * ci;
+        }
       }
     }
   }
-  block_sum<4>(v);
+  block_sum<5>(v);
   if (t == 0) {
     const double2 e1 = given ? a.parts_in[3 * w] : v[0];
     const double2 ej = given ? a.parts_in[3 * w + 1] : cscale(v[1], 0.5);
@@ -370,7 +377,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs a, CT* __res
     a.eloc[w] = el;
     if (a.eloc_out) a.eloc_out[w] = el;
     if (a.parts) { a.parts[3 * w] = e1; a.parts[3 * w + 1] = ej; a.parts[3 * w + 2] = ek; }
-    if (a.lfac) a.lfac[w] = v[3];
+    if (a.lfac) a.lfac[w] = make_double2(v[3].x, v[4].x);
   }
 }
 
@@ -402,8 +409,9 @@ int launch_emix(const double2* eloc, const double* wt, int nw, double* out, hipS
 }
 
 // Phaseless weight update and walker commit (one workgroup per walker):
-//   log r = log O' - log O, I = r exp(lfac) exp(dt E_shift),
-//   w <- w |I| max(0, cos Im log r); a walker whose weight is not positive and
+//   log r = log O' - log O, |I| = |r| exp(Re lfac) exp(dt E_shift),
+//   w <- w |I| max(0, cos(Im log r + Im lfac)) (Im lfac: the phase of the
+//   background's c-number factor, 0 without one); a walker whose weight is not positive and
 //   finite (or whose new overlap is singular) dies and is frozen; otherwise
 //   W <- W'.
 __global__ __launch_bounds__(256) void weight_kernel(WeightArgs a) {
@@ -419,7 +427,7 @@ __global__ __launch_bounds__(256) void weight_kernel(WeightArgs a) {
       const double2 lr = csub(ln_new, ln_cur);
       const double mag = exp(lr.x);
       ratio = make_double2(mag * cos(lr.y), mag * sin(lr.y));
-      const double cs = cos(lr.y);
+      const double cs = cos(lr.y + a.lfac[w].y);
       double wn = 0.0;
       if (cs > 0.0) wn = a.weights[w] * exp(lr.x + a.lfac[w].x + a.dt * a.e_shift) * cs;
       if (!sing && wn > 0.0 && isfinite(wn)) {

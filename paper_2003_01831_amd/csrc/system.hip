@@ -76,8 +76,9 @@ int system_prepare_pack(afq_system s, int prec) {
   return eri_sync(s);
 }
 
-// B1 = exp(Z), Z = -dt h'/2: Z' = Z / 2^q with ||Z'||_inf <= 1/2, Horner
-// evaluation of the order-18 Taylor polynomial, then q squarings.
+// B1 = exp(Z), Z = -dt h'/2 (h' + sum_n c_n L^n with a background c): Z' =
+// Z / 2^q with ||Z'||_inf <= 1/2, Horner evaluation of the order-18 Taylor
+// polynomial, then q squarings.
 int system_prepare_dt(afq_system s, double dt) {
   if (s->kp_nk > 0) return kp_prepare_dt(s, dt);
   if (s->B1.p && s->B1_dt == dt) return AFQ_OK;
@@ -90,7 +91,8 @@ int system_prepare_dt(afq_system s, double dt) {
   AFQ_RET(e0.alloc(mm * sizeof(double)));
   AFQ_RET(e1.alloc(mm * sizeof(double)));
   AFQ_RET(nrm.alloc(sizeof(double)));
-  AFQ_RET(launch_infnorm(s->hp.as<double>(), M, nrm.as<double>(), st));
+  const double* hsrc = s->mf_on ? s->hp_mf.as<double>() : s->hp.as<double>();
+  AFQ_RET(launch_infnorm(hsrc, M, nrm.as<double>(), st));
   double hn = 0.0;
   AFQ_TRY_HIP(hipMemcpyAsync(&hn, nrm.p, sizeof(double), hipMemcpyDeviceToHost, st));
   AFQ_TRY_HIP(hipStreamSynchronize(st));
@@ -100,7 +102,7 @@ int system_prepare_dt(afq_system s, double dt) {
   const double scale = -0.5 * dt / std::ldexp(1.0, q);
   // z = h'; the factor `scale` is folded into each Horner step:
   // E_j = I + (scale / j) h' E_{j+1}, E_19 = I, E_1 = exp(scale h')
-  AFQ_RET(copy_d(s->hp.as<double>(), z.as<double>(), (long)mm, st));
+  AFQ_RET(copy_d(hsrc, z.as<double>(), (long)mm, st));
   const int order = 18;
   double* cur = e0.as<double>();
   double* nxt = e1.as<double>();
@@ -197,5 +199,94 @@ int system_create_impl(afq_system* out, int M, int n_up, int n_dn, int X, const 
     return rc;
   }
   *out = s;
+  return AFQ_OK;
+}
+
+// vmf[n] = Re sum_s tr(L^n T^s T^sH) = Re sum_{c,k} Lt[n][c][k] T[k][c], the
+// trial's own force bias (one workgroup per vector, fixed-order tree)
+__global__ __launch_bounds__(256) void mean_field_kernel(const double2* __restrict__ Lt,
+                                                         const double2* __restrict__ phi, int ntot, int M,
+                                                         double* __restrict__ vmf) {
+  __shared__ double red[256];
+  const int n = blockIdx.x, t = threadIdx.x;
+  const long per = (long)ntot * M;
+  const double2* l = Lt + (long)n * per;
+  double acc = 0.0;
+  for (long e = t; e < per; e += 256) {
+    const long c = e / M, k = e - c * M;
+    const double2 a = l[e], b = phi[k * ntot + c];
+    acc += a.x * b.x - a.y * b.y;
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) vmf[n] = red[0];
+}
+
+// bad[0] = number of non-finite entries of x (one workgroup)
+__global__ __launch_bounds__(256) void finite_count_kernel(const double* __restrict__ x, int n,
+                                                           int* __restrict__ bad) {
+  __shared__ int red[256];
+  const int t = threadIdx.x;
+  int c = 0;
+  for (int i = t; i < n; i += 256) c += isfinite(x[i]) ? 0 : 1;
+  red[t] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  if (t == 0) bad[0] = red[0];
+}
+
+// Mean-field background subtraction: on = 0 switches it off; otherwise the
+// background is the trial's own force bias (vmf_in NULL) or the caller's
+// device vector of X doubles. Builds h' + sum_n c_n L^n and invalidates B1.
+int system_set_background(afq_system s, int on, const double* vmf_in) {
+  hipStream_t st = s->stream;
+  const int M = s->M, X = s->X;
+  const size_t mm = (size_t)M * M;
+  if (!on) {
+    if (!s->mf_on) return AFQ_OK;
+    AFQ_TRY_HIP(hipStreamSynchronize(st));
+    s->mf_on = false;
+    s->vmf.free();
+    s->hp_mf.free();
+  } else {
+    AFQ_RET(s->vmf.alloc((size_t)X * sizeof(double)));
+    AFQ_RET(s->hp_mf.alloc(mm * sizeof(double)));
+    if (vmf_in) {
+      AFQ_TRY_HIP(hipMemcpyAsync(s->vmf.p, vmf_in, (size_t)X * sizeof(double), hipMemcpyDeviceToDevice, st));
+      DevBuf bad;
+      AFQ_RET(bad.alloc(sizeof(int)));
+      hipLaunchKernelGGL(finite_count_kernel, dim3(1), dim3(256), 0, st, s->vmf.as<double>(), X, bad.as<int>());
+      AFQ_TRY_HIP(hipGetLastError());
+      int nbad = 0;
+      AFQ_TRY_HIP(hipMemcpyAsync(&nbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+      AFQ_TRY_HIP(hipStreamSynchronize(st));
+      if (nbad) {
+        s->mf_on = false;
+        s->vmf.free();
+        s->hp_mf.free();
+        AFQ_CHECK(false, AFQ_E_INVALID, "afq_system_set_background: the background vector is not finite");
+      }
+    } else {
+      hipLaunchKernelGGL(mean_field_kernel, dim3(X), dim3(256), 0, st, s->Lt.as<double2>(), s->phi.as<double2>(),
+                         s->ntot, M, s->vmf.as<double>());
+      AFQ_TRY_HIP(hipGetLastError());
+    }
+    // h_mf = h' + sum_n c_n L^n : [1 x X] x [X x M^2]
+    AFQ_RET(copy_d(s->hp.as<double>(), s->hp_mf.as<double>(), (long)mm, st));
+    AFQ_RET(real_gemm(1, (int)mm, X, s->vmf.as<double>(), X, OP_N, s->chol.as<double>(), (long)mm, OP_N,
+                      s->hp_mf.as<double>(), (long)mm, 1.0, 1.0, st));
+    AFQ_TRY_HIP(hipStreamSynchronize(st));
+    s->mf_on = true;
+  }
+  s->B1_dt = s->b1x_dt = s->b1x3_dt = -1.0;   // rebuilt by the next step's set-up
+  ++s->b1_serial;
+  ++s->version;
   return AFQ_OK;
 }

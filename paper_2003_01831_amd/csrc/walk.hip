@@ -359,6 +359,7 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
   a.step_off = step_off;
   a.sys_id = sys_id;
   a.fb_cap = w->fb_cap;
+  a.vmf = s->mf_on ? s->vmf.as<double>() : nullptr;
   a.eloc_out = reinterpret_cast<double2*>(eloc_out);
   AFQ_RET(energy_from_theta(s, w, a, true, w->logdet.as<double2>()));
   if (coef_record)   // back-propagation window: conj(c) of this step, the coefficients of B^H
