@@ -1,9 +1,14 @@
-// Many uneven systems stepped together. The systems run as concurrent
-// branches (one stream each, forked from and joined back to the systems'
-// common stream); after eager warm-up steps that size every buffer, one cycle
-// of `qr_every` steps (one step when QR is off) is captured into a HIP graph
-// and replayed, so a whole cycle of all systems is one graph launch. Step
-// counters live in device memory, so replays advance the Philox fields.
+// Many uneven systems stepped together. Every step runs in three stages that
+// end where overlap inverses are needed; each stage runs as concurrent
+// branches (one stream per system, forked from and joined back to a root
+// stream), and between the stages the Gauss-Jordan inverses of every system
+// and spin run as grouped launches on the root stream: one launch per
+// register-block layout walks a work table of (system, spin) tasks, so a step
+// of 24 systems takes a handful of inverse launches instead of 96 small ones.
+// After eager warm-up steps that size every buffer, one cycle of `qr_every`
+// steps (one step when QR is off) is captured into a HIP graph and replayed,
+// so a whole cycle of all systems is one graph launch. Step counters live in
+// device memory, so replays advance the Philox fields.
 #include <algorithm>
 #include "common.h"
 #include "step_kernels.h"
@@ -53,32 +58,42 @@ __global__ void scatter_emix(const double* __restrict__ cyc, int n, int cycle, i
   }
 }
 
-// Enqueue `steps` steps of every system on its branch stream; step k of the
-// sequence uses Philox step (*counter + k) and writes E_mix to emix[i][k0 + k].
+// Enqueue `steps` steps of every system; step k of the sequence uses Philox
+// step (*counter + k) and writes E_mix to emix[i][k0 + k]. Per step and stage:
+// fork from the root stream, the stage of every system on its branch (its
+// overlap inverses deferred), join, the grouped inverses on the root stream.
 int enqueue_steps(afq_batch b, hipStream_t root, int steps, bool capture_layout, double* emix_user,
                   int n_steps_user, int base) {
   const int n = (int)b->sys.size();
-  AFQ_TRY_HIP(hipEventRecord(b->fork[0], root));
-  for (int i = 0; i < n; ++i) {
-    afq_system s = b->sys[i];
-    afq_walkers w = b->wk[i];
-    hipStream_t saved = s->stream;
-    s->stream = b->streams[i];
-    AFQ_TRY_HIP(hipStreamWaitEvent(b->streams[i], b->fork[0], 0));
-    int rc = AFQ_OK;
-    for (int k = 0; k < steps && rc == AFQ_OK; ++k) {
-      const uint64_t idx = w->counter + k;
-      const bool do_qr = b->qr_every > 0 && (idx + 1) % (uint64_t)b->qr_every == 0;
-      double* em = capture_layout ? b->emix_cycle.as<double>() + (long)i * b->cycle + k
-                                  : (emix_user ? emix_user + (long)i * n_steps_user + base + k : nullptr);
-      rc = step_once(s, w, b->dt, nullptr, b->seed, (uint32_t)i, k, do_qr, b->e_shift[i], b->order, em, nullptr,
-                     nullptr, nullptr);
+  std::vector<GjTask> tasks;
+  for (int k = 0; k < steps; ++k) {
+    for (int stage = 0; stage < 3; ++stage) {
+      tasks.clear();
+      AFQ_TRY_HIP(hipEventRecord(b->fork[0], root));
+      for (int i = 0; i < n; ++i) {
+        afq_system s = b->sys[i];
+        afq_walkers w = b->wk[i];
+        const uint64_t idx = w->counter + k;
+        const bool do_qr = b->qr_every > 0 && (idx + 1) % (uint64_t)b->qr_every == 0;
+        double* em = capture_layout ? b->emix_cycle.as<double>() + (long)i * b->cycle + k
+                                    : (emix_user ? emix_user + (long)i * n_steps_user + base + k : nullptr);
+        hipStream_t saved = s->stream;
+        s->stream = b->streams[i];
+        int rc = hip_status(hipStreamWaitEvent(b->streams[i], b->fork[0], 0), "afq_batch_step: fork");
+        lu_defer(&tasks);
+        if (rc == AFQ_OK)
+          rc = step_stage(stage, s, w, b->dt, nullptr, b->seed, (uint32_t)i, k, do_qr, b->e_shift[i], b->order, em,
+                          nullptr, nullptr, nullptr);
+        lu_defer(nullptr);
+        if (rc == AFQ_OK && stage == 2 && k == steps - 1)
+          rc = counter_add(w->d_counter.as<uint64_t>(), (uint64_t)steps, b->streams[i]);
+        s->stream = saved;
+        AFQ_RET(rc);
+        AFQ_TRY_HIP(hipEventRecord(b->join[i], b->streams[i]));
+        AFQ_TRY_HIP(hipStreamWaitEvent(root, b->join[i], 0));
+      }
+      if (!tasks.empty()) AFQ_RET(lu_inverse_grouped(tasks, root));
     }
-    if (rc == AFQ_OK) rc = counter_add(w->d_counter.as<uint64_t>(), (uint64_t)steps, b->streams[i]);
-    s->stream = saved;
-    AFQ_RET(rc);
-    AFQ_TRY_HIP(hipEventRecord(b->join[i], b->streams[i]));
-    AFQ_TRY_HIP(hipStreamWaitEvent(root, b->join[i], 0));
   }
   return AFQ_OK;
 }

@@ -282,6 +282,19 @@ void gemm_release_workspace(hipStream_t st);   // frees the split-k workspace of
 // NULL: log det only), logdet (complex, per matrix), sing flag per matrix.
 int lu_inverse(const double2* S, long stride, int n, int batch, double2* inv,
                double2* logdet, long ld_logdet, int* sing, long ld_sing, hipStream_t st);
+// One deferred lu_inverse call (a batch of matrices of one system and spin).
+struct GjTask {
+  const double2* S;
+  double2* inv;
+  double2* logdet;
+  int* sing;
+  int stride, n, batch, ld_logdet, ld_sing;
+};
+// While a sink is installed on the calling thread, lu_inverse records its work
+// there instead of launching it; lu_inverse_grouped then runs all recorded
+// tasks of one register-block layout in one launch (the batch of many systems).
+void lu_defer(std::vector<GjTask>* sink);
+int lu_inverse_grouped(const std::vector<GjTask>& tasks, hipStream_t st);
 // Cholesky of Hermitian G = R^H R then R^-1 (upper); logdet gets log det R (real part).
 int chol_inverse(const double2* G, long stride, int n, int batch, double2* rinv,
                  double2* logdet, long ld_logdet, int* sing, long ld_sing, hipStream_t st);
@@ -301,6 +314,10 @@ int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool
 // counter itself is advanced by counter_add after the steps of a call)
 // coef_record (optional): where conj of this step's propagator coefficients go
 int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed,
+              uint32_t sys_id, uint64_t step_off, bool do_qr, double e_shift, int order,
+              double* emix_out, double* eloc_out, double* weights_out, double* ratio_out,
+              void* coef_record = nullptr);
+int step_stage(int stage, afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed,
               uint32_t sys_id, uint64_t step_off, bool do_qr, double e_shift, int order,
               double* emix_out, double* eloc_out, double* weights_out, double* ratio_out,
               void* coef_record = nullptr);

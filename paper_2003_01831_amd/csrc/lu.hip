@@ -213,12 +213,12 @@ __device__ void blocks_load(double2 (&a)[RB][CB], const double2* __restrict__ m,
   __syncthreads();
 }
 
+// matrix b of the batch at S (stride elements apart)
 template <int NT, int RB, int CB, bool FULL>
-__device__ void gj_body(const double2* __restrict__ S, long stride, int n,
+__device__ __forceinline__ void gj_body(const double2* __restrict__ S, long stride, int n,
                                                 double2* __restrict__ inv, double2* __restrict__ logdet,
-                                                long ld_logdet, int* __restrict__ sing, long ld_sing) {
+                                                long ld_logdet, int* __restrict__ sing, long ld_sing, long b) {
   __shared__ GjShared<NT> sh;
-  const long b = blockIdx.x;
   const int tid = threadIdx.x;
   double2 a[RB][CB];
   int nrg, rg, cg;
@@ -354,14 +354,84 @@ __global__ __launch_bounds__(NT) void chol_inv_kernel(
 template <int NT, int RB, int CB>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void gj_kernel_full(const double2* S, long stride, int n, double2* inv,
                                                      double2* logdet, long ld_logdet, int* sing, long ld_sing) {
-  gj_body<NT, RB, CB, true>(S, stride, n, inv, logdet, ld_logdet, sing, ld_sing);
+  gj_body<NT, RB, CB, true>(S, stride, n, inv, logdet, ld_logdet, sing, ld_sing, blockIdx.x);
 }
 template <int NT, int RB, int CB>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void gj_kernel_det(const double2* S, long stride, int n, double2* inv,
                                                     double2* logdet, long ld_logdet, int* sing, long ld_sing) {
-  gj_body<NT, RB, CB, false>(S, stride, n, inv, logdet, ld_logdet, sing, ld_sing);
+  gj_body<NT, RB, CB, false>(S, stride, n, inv, logdet, ld_logdet, sing, ld_sing, blockIdx.x);
 }
+
+// Work table of a grouped launch: the batches of up to GJ_GROUP tasks (other
+// systems, both spins) of one register-block layout, passed by value (so a
+// captured graph holds it); workgroup x runs matrix x - first[t] of the task t
+// with first[t] <= x < first[t + 1].
+constexpr int GJ_GROUP = 40;
+struct GjGroupArgs {
+  const double2* S[GJ_GROUP];
+  double2* inv[GJ_GROUP];
+  double2* logdet[GJ_GROUP];
+  int* sing[GJ_GROUP];
+  int stride[GJ_GROUP], n[GJ_GROUP], ld_logdet[GJ_GROUP], ld_sing[GJ_GROUP];
+  int first[GJ_GROUP + 1];
+  int ntask;
+};
+
+template <int NT, int RB, int CB, bool FULL>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void gj_grouped_kernel(GjGroupArgs g) {
+  const int x = blockIdx.x;
+  int t = 0;
+  while (t + 1 < g.ntask && x >= g.first[t + 1]) ++t;
+  gj_body<NT, RB, CB, FULL>(g.S[t], g.stride[t], g.n[t], g.inv[t], g.logdet[t], g.ld_logdet[t], g.sing[t],
+                            g.ld_sing[t], x - g.first[t]);
+}
+
+// register-block layout of an order-n matrix (the dispatch below)
+int gj_bucket(int n) { return n <= 32 ? 0 : n <= 64 ? 1 : n <= 100 ? 2 : 3; }
+
+thread_local std::vector<GjTask>* t_gj_sink = nullptr;
 }  // namespace
+
+void lu_defer(std::vector<GjTask>* sink) { t_gj_sink = sink; }
+
+// the tasks as few launches as possible: one per (layout, inverse or not) and
+// GJ_GROUP tasks, each workgroup one matrix
+int lu_inverse_grouped(const std::vector<GjTask>& tasks, hipStream_t st) {
+  for (int bucket = 0; bucket < 4; ++bucket)
+    for (int full = 0; full < 2; ++full) {
+      GjGroupArgs g{};
+      int blocks = 0;
+      auto flush = [&]() -> int {
+        if (g.ntask == 0) return AFQ_OK;
+        g.first[g.ntask] = blocks;
+#define AFQ_GJG(NT_, RB_, CB_)                                                                       \
+  do {                                                                                               \
+    if (full) hipLaunchKernelGGL((gj_grouped_kernel<NT_, RB_, CB_, true>), dim3(blocks), dim3(NT_), 0, st, g); \
+    else hipLaunchKernelGGL((gj_grouped_kernel<NT_, RB_, CB_, false>), dim3(blocks), dim3(NT_), 0, st, g);     \
+  } while (0)
+        if (bucket == 0) AFQ_GJG(256, 2, 2);
+        else if (bucket == 1) AFQ_GJG(256, 4, 4);
+        else if (bucket == 2) AFQ_GJG(512, 4, 5);
+        else AFQ_GJG(1024, 4, 4);
+#undef AFQ_GJG
+        AFQ_TRY_HIP(hipGetLastError());
+        g = GjGroupArgs{};
+        blocks = 0;
+        return AFQ_OK;
+      };
+      for (const GjTask& k : tasks) {
+        if (gj_bucket(k.n) != bucket || (k.inv != nullptr) != (full != 0) || k.batch <= 0) continue;
+        const int t = g.ntask++;
+        g.S[t] = k.S; g.inv[t] = k.inv; g.logdet[t] = k.logdet; g.sing[t] = k.sing;
+        g.stride[t] = k.stride; g.n[t] = k.n; g.ld_logdet[t] = k.ld_logdet; g.ld_sing[t] = k.ld_sing;
+        g.first[t] = blocks;
+        blocks += k.batch;
+        if (g.ntask == GJ_GROUP) AFQ_RET(flush());
+      }
+      AFQ_RET(flush());
+    }
+  return AFQ_OK;
+}
 
 // thread blocks: ceil(n / RB) * ceil(n / CB) <= NT
 #define AFQ_GJ_DISPATCH(KERNEL, ...)                                                          \
@@ -381,6 +451,12 @@ int lu_inverse(const double2* S, long stride, int n, int batch, double2* inv, do
   AFQ_CHECK(n >= 1 && n <= NMAX, AFQ_E_UNSUPPORTED, "lu_inverse: n must be in [1, 128]");
   AFQ_CHECK(stride >= (long)n * n, AFQ_E_INVALID, "lu_inverse: stride < n*n");
   if (batch <= 0) return AFQ_OK;
+  if (t_gj_sink) {   // deferred into a grouped launch of many systems
+    AFQ_CHECK(stride <= INT32_MAX && ld_logdet <= INT32_MAX && ld_sing <= INT32_MAX, AFQ_E_INVALID,
+              "lu_inverse: stride too large to defer");
+    t_gj_sink->push_back(GjTask{S, inv, logdet, sing, (int)stride, n, batch, (int)ld_logdet, (int)ld_sing});
+    return AFQ_OK;
+  }
   if (inv) AFQ_GJ_DISPATCH(gj_kernel_full, S, stride, n, inv, logdet, ld_logdet, sing, ld_sing);
   else AFQ_GJ_DISPATCH(gj_kernel_det, S, stride, n, inv, logdet, ld_logdet, sing, ld_sing);
   AFQ_TRY_HIP(hipGetLastError());

@@ -337,50 +337,67 @@ static int qr_walkers(afq_system s, afq_walkers w) {
                      s->stream);
 }
 
-int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed, uint32_t sys_id,
-              uint64_t step_off, bool do_qr, double e_shift, int order, double* emix_out, double* eloc_out,
-              double* weights_out, double* ratio_out, void* coef_record) {
+// One step in three stages that end where an overlap inverse is needed: stage
+// 0 forms S = T^H W (when S^-1 was not carried over) and requests its inverse;
+// stage 1 forms Theta, the energy, the propagated walkers and S' = T^H W' and
+// requests its inverse (or log det); stage 2 applies the phaseless weight and
+// QR. step_once runs them back to back; a batch of systems runs each stage on
+// every system and the requested inverses of all systems as grouped launches
+// in between (lu_defer).
+int step_stage(int stage, afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed,
+               uint32_t sys_id, uint64_t step_off, bool do_qr, double e_shift, int order, double* emix_out,
+               double* eloc_out, double* weights_out, double* ratio_out, void* coef_record) {
   hipStream_t st = s->stream;
   const int nw = w->nw;
-  // overlap, Theta and the energy at the start-of-step walkers; S^-1 and log det
-  // are still those the previous step's weight phase carried over with W
-  // unless something has changed W since
-  {
+  // with QR at the end of the step (or a multi-determinant trial) the new
+  // overlap's inverse is not carried to the next step
+  const bool carry = s->msd_n == 0 && !do_qr;
+  if (stage == 0) {
+    // S^-1 and log det are still those the previous step's weight phase
+    // carried over with W unless something has changed W since
     TraceScope t(AFQ_PH_OVERLAP, st);
     if (!w->s_carried || s->msd_n > 0)   // a multi-determinant trial leaves its own overlap in logdet
       AFQ_RET(overlap_inverse(s, w, w->W.as<double2>(), w->Sinv.as<double2>(), w->logdet.as<double2>()));
-    AFQ_RET(theta_from_inverse(s, w, w->W.as<double2>()));
+    return AFQ_OK;
   }
-  AssembleArgs a{};
-  a.dt = dt;
-  a.fields = fields;
-  a.seed = seed;
-  a.step_ptr = w->d_counter.as<uint64_t>();
-  a.step_off = step_off;
-  a.sys_id = sys_id;
-  a.fb_cap = w->fb_cap;
-  a.vmf = s->mf_on ? s->vmf.as<double>() : nullptr;
-  a.eloc_out = reinterpret_cast<double2*>(eloc_out);
-  AFQ_RET(energy_from_theta(s, w, a, true, w->logdet.as<double2>()));
-  if (coef_record)   // back-propagation window: conj(c) of this step, the coefficients of B^H
-    AFQ_RET(launch_conj_copy(w->coef.p, coef_record, (long)nw * s->X, s->prec != AFQ_FP64, st));
-  if (emix_out) {
-    TraceScope t(AFQ_PH_ASSEMBLE, st);
-    AFQ_RET(launch_emix(w->eloc.as<double2>(), w->weights.as<double>(), nw, emix_out, st));
+  if (stage == 1) {
+    {
+      TraceScope t(AFQ_PH_OVERLAP, st);
+      AFQ_RET(theta_from_inverse(s, w, w->W.as<double2>()));
+    }
+    AssembleArgs a{};
+    a.dt = dt;
+    a.fields = fields;
+    a.seed = seed;
+    a.step_ptr = w->d_counter.as<uint64_t>();
+    a.step_off = step_off;
+    a.sys_id = sys_id;
+    a.fb_cap = w->fb_cap;
+    a.vmf = s->mf_on ? s->vmf.as<double>() : nullptr;
+    a.eloc_out = reinterpret_cast<double2*>(eloc_out);
+    AFQ_RET(energy_from_theta(s, w, a, true, w->logdet.as<double2>()));
+    if (coef_record)   // back-propagation window: conj(c) of this step, the coefficients of B^H
+      AFQ_RET(launch_conj_copy(w->coef.p, coef_record, (long)nw * s->X, s->prec != AFQ_FP64, st));
+    if (emix_out) {
+      TraceScope t(AFQ_PH_ASSEMBLE, st);
+      AFQ_RET(launch_emix(w->eloc.as<double2>(), w->weights.as<double>(), nw, emix_out, st));
+    }
+    AFQ_RET(propagate_walkers(s, w, order, w->coef.p, w->W.as<double2>(), w->Wn.as<double2>()));
+    // new overlap: its full inverse when it is carried to the next step with
+    // the walkers the weight kernel keeps (hardly dearer than its determinant),
+    // or with a multi-determinant trial (whose Theta of W' the ratio needs)
+    TraceScope tw(AFQ_PH_WEIGHT, st);
+    const bool want_inv = carry || s->msd_n > 0;
+    return overlap_inverse(s, w, w->Wn.as<double2>(),
+                           want_inv ? (carry ? w->Sinv_new.as<double2>() : w->Sinv.as<double2>()) : nullptr,
+                           w->logdet_new.as<double2>());
   }
-  AFQ_RET(propagate_walkers(s, w, order, w->coef.p, w->W.as<double2>(), w->Wn.as<double2>()));
-  // new overlap and the phaseless weight. Without a multi-determinant trial
-  // and QR at the end of the step the full inverse of the new overlap is
-  // formed (hardly dearer than its determinant) and carried to the next step
-  // with the walkers the weight kernel keeps.
-  const bool carry = s->msd_n == 0 && !do_qr;
   {
     TraceScope tw(AFQ_PH_WEIGHT, st);
-    if (carry)
-      AFQ_RET(overlap_inverse(s, w, w->Wn.as<double2>(), w->Sinv_new.as<double2>(), w->logdet_new.as<double2>()));
-    else
-      AFQ_RET(compute_overlap_theta(s, w, w->Wn.as<double2>(), s->msd_n > 0, w->logdet_new.as<double2>()));
-    if (s->msd_n > 0) AFQ_RET(msd_overlap(s, w, w->logdet_new.as<double2>(), st));
+    if (s->msd_n > 0) {
+      AFQ_RET(theta_from_inverse(s, w, w->Wn.as<double2>()));
+      AFQ_RET(msd_overlap(s, w, w->logdet_new.as<double2>(), st));
+    }
     WeightArgs wa{};
     wa.logdet_new = w->logdet_new.as<double2>();
     wa.logdet_cur = w->logdet.as<double2>();
@@ -408,6 +425,15 @@ int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint
   }
   w->s_carried = carry;
   if (do_qr) AFQ_RET(qr_walkers(s, w));
+  return AFQ_OK;
+}
+
+int step_once(afq_system s, afq_walkers w, double dt, const double* fields, uint64_t seed, uint32_t sys_id,
+              uint64_t step_off, bool do_qr, double e_shift, int order, double* emix_out, double* eloc_out,
+              double* weights_out, double* ratio_out, void* coef_record) {
+  for (int stage = 0; stage < 3; ++stage)
+    AFQ_RET(step_stage(stage, s, w, dt, fields, seed, sys_id, step_off, do_qr, e_shift, order, emix_out, eloc_out,
+                       weights_out, ratio_out, coef_record));
   return AFQ_OK;
 }
 
