@@ -65,8 +65,9 @@ class System:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.precision = precision
         # a non-default exchange form is set before the precision, so that the
-        # automatic choice never builds a tensor that is dropped at once
-        first = precision if exchange_form == "auto" else "fp64"
+        # automatic choice never builds a tensor that is dropped at once (complex
+        # FP32 mode has no four-index form)
+        first = precision if exchange_form == "auto" else "cfp32"
         h = C.c_void_p()
         check(self.lib.afq_system_create(C.byref(h), self.M, self.n_up, self.n_dn, self.n_chol, *ptrs,
                                          self.e_core, PRECISION[first], _stream_handle(self.stream), flags))
