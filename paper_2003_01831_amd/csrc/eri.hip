@@ -1,19 +1,22 @@
-// Exchange through the half-rotated four-index tensor (split-BF16x3 mode,
-// real trial). With Theta-hat = vec(Theta^s), index (a, k) -> a M + k, the sum
-// over Cholesky vectors of tr(Omega_n Omega_n) is one quadratic form,
+// Exchange through the half-rotated four-index tensor (split-BF16x3 and FP64
+// modes, real trial). With Theta-hat = vec(Theta^s), index (a, k) -> a M + k,
+// the sum over Cholesky vectors of tr(Omega_n Omega_n) is one quadratic form,
 //   sum_n tr(Omega_n Omega_n) = Theta-hat^T W' Theta-hat,
 //   W'[(b,k),(a,l)] = sum_n Lt_n[a][k] Lt_n[b][l]      (Lt_n = T^H L^n, N x M),
 // W' symmetric of order N M. Cut into blocks of RA rows, the form is
 //   sum_p theta_p^T W'_pp theta_p + 2 sum_{p<q} theta_p^T W'_pq theta_q,
-// so only the upper block triangle is contracted: W'' = W' on the diagonal
-// blocks, 2 W' above them (exact in BF16), and row block p runs over the
-// contraction columns from its own diagonal block on. Per walker and spin
+// so only the upper block triangle is stored and contracted: W'' = W' on the
+// diagonal blocks, 2 W' above them (exact in BF16), and row block p runs over
+// the contraction columns from its own diagonal block on. Per walker and spin
 // that is (N M)^2 / 2 multiply-adds instead of the X N^2 M of the Cholesky
-// form (1/8 of it at M = 400, X = 1600), for N^2 M^2 stored entries (BF16 hi
-// and lo planes: 6.4 GB per distinct spin block at M = 400, N = 100).
+// form (1/8 of it at M = 400, X = 1600), for about (N M)^2 / 2 stored entries
+// (BF16 hi and lo planes: 3.2 GB per distinct spin block at M = 400, N = 100).
 //
-// W' is formed once per system: Lt transposed to [(a,k)][n], an FP64 GEMM over
-// n, then the permutation and block weighting into chunk-major BF16 planes.
+// W' is formed once per system, one column slab a (columns (a, l), l < M) at
+// a time: with LT[(a,k)][n] = Lt_n[a][k], the FP64 GEMM LT_a LT^T over n gives
+// W[(a,k)][(b,l)] = W'[(b,k)][(a,l)] for the rows the triangle keeps, and a
+// pack kernel permutes, weights and splits them into the stored layout (the
+// transients are LT and one M x N M slab, not the whole N M x N M matrix).
 // Per step: Theta-hat of every walker is packed into rows (w, Re|Im); the
 // kernel multiplies W'' (rows I) by Theta-hat (rows C) in split BF16x3 through
 // the three-stage direct global->LDS ring, one work unit being a row block and
@@ -21,13 +24,12 @@
 // with Theta-hat in FP64 (no output matrix is stored) and writes one complex
 // partial per (unit, column); a fixed-order reduction gives every walker's sum.
 //
-// FP64 mode keeps W' itself (N M x N M doubles, 12.8 GB at M = 400; its set-up
-// needs the same again for the Gram matrix before the permutation) and runs
-// the same quadratic form on FP64 MFMA through the tiled GEMM: with the
-// columns cut into NB blocks J, Z_J^T = 2 Theta-hat_{<J}^T W'_{<J,J} +
-// Theta-hat_J^T W'_JJ (two GEMMs per block, the upper block triangle plus the
-// diagonal blocks: (1/2 + 1/(2 NB)) of the full square), then one FP64 dot
-// product per walker, sum_I Theta-hat_I Z_I.
+// FP64 mode keeps W' itself, its columns cut into NB blocks J and block column
+// J stored down to the end of its diagonal block ((1/2 + 1/(2 NB)) of the
+// square, 7.2 GB at M = 400), and runs the same quadratic form on FP64 MFMA
+// through the tiled GEMM: Z_J^T = 2 Theta-hat_{<J}^T W'_{<J,J} +
+// Theta-hat_J^T W'_JJ (two GEMMs per block), then one FP64 dot product per
+// walker, sum_I Theta-hat_I Z_I.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -56,11 +58,24 @@ constexpr int NT = STAGE / 1024;            // 1 KB load instructions per stage
 constexpr int NQ = NT / NWAVE;              // per wave
 static_assert(NT % NWAVE == 0, "loads must split evenly over the waves");
 constexpr int NXCD = 8;
+constexpr int CPB = RA / KC;                // contraction chunks per row block
+// the loads of the A regions (W'' hi, lo) are the first QA of every wave's NQ
+constexpr int QA = (RA / 8) / NWAVE;
+static_assert((RA / 8) % NWAVE == 0, "every wave's loads must split into A and B regions at the same index");
+
+// Upper block triangle of W'' in chunk-major planes: chunk c (columns
+// [KC c, KC c + KC)) stores the rows of the row blocks 0 .. c / CPB, whose
+// diagonal block it reaches, after the rows of all earlier chunks
+__host__ __device__ inline long tri_rows(long c) { return (c / CPB + 1) * RA; }
+__host__ __device__ inline long tri_rows_before(long c) {
+  const long q = c / CPB, r = c - q * CPB;
+  return RA * (CPB * q * (q + 1) / 2 + r * (q + 1));
+}
 
 struct EriArgs {
-  const unsigned char* a[2];   // W'' hi / lo planes: [chunk][rows_a][32] bf16
+  const unsigned char* a[2];   // W'' hi / lo planes: chunk c at row tri_rows_before(c), 32 bf16 per row
   const unsigned char* b[2];   // Theta-hat hi / lo planes: [chunk][rows_b][32] bf16
-  long rows_a, rows_b;
+  long rows_b;
   const int4* units;           // (row block, first chunk, chunks, 0)
   int nunit, nblk_b, grid;     // grid: units x column blocks
   const double2* thetaT;       // nw x ntot x M
@@ -88,9 +103,11 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
   const int c0 = un.y, nc = un.z;                 // nc >= 1
   const long arow0 = (long)un.x * RA, brow0 = (long)bb * RBR;
   // load q of this wave: instruction t = q * 4 + wave of the stage, 16 rows of
-  // one region; lane l writes LDS bytes 1024 t + 16 l (row l / 4, swizzled piece)
+  // one region; lane l writes LDS bytes 1024 t + 16 l (row l / 4, swizzled
+  // piece). src[q] points at chunk c0; a later chunk of W'' starts at its
+  // triangle offset, one of Theta-hat rows_b rows further per chunk
   const unsigned char* src[NQ];
-  long cstride[NQ];
+  const long bstride = g.rows_b * ROWB, aoff0 = tri_rows_before(c0) * ROWB;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int t = q * NWAVE + wave;
@@ -98,13 +115,13 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
     const int j = reg == 0 ? t : reg == 1 ? t - RA / 16 : reg == 2 ? t - RA / 8 : t - RA / 8 - RBR / 16;
     const int row = 16 * j + (lane >> 2), c = swz(row, lane & 3);
     const unsigned char* base = reg == 0 ? g.a[0] : reg == 1 ? g.a[1] : reg == 2 ? g.b[0] : g.b[1];
-    cstride[q] = (reg < 2 ? g.rows_a : g.rows_b) * (long)ROWB;
-    src[q] = base + ((reg < 2 ? arow0 : brow0) + row) * ROWB + 16 * c + (long)c0 * cstride[q];
+    src[q] = base + ((q < QA ? arow0 : brow0) + row) * ROWB + 16 * c + (q < QA ? aoff0 : (long)c0 * bstride);
   }
   auto issue = [&](int chunk, unsigned char* buf) {
     lds_t* l = (lds_t*)buf;
+    const long da = tri_rows_before(c0 + chunk) * ROWB - aoff0, db = chunk * bstride;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) dma16(src[q] + chunk * cstride[q], l + (q * NWAVE + wave) * 1024);
+    for (int q = 0; q < NQ; ++q) dma16(src[q] + (q < QA ? da : db), l + (q * NWAVE + wave) * 1024);
   };
   // the last two steps have no chunk to prefetch: tiny loads into this wave's
   // trash slice keep the wait count of every step the same
@@ -207,25 +224,50 @@ __device__ inline unsigned short bf16_rne(float f) {
 }
 __device__ inline float bf16_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
-// W''[I = (b,k)][J = (a,l)] = s W[(a,k)][(b,l)], s = 1 on the diagonal blocks
-// (I / RA = J / RA), 2 above, 0 below, into chunk-major hi / lo planes
-// (rows I >= NM and columns J >= NM are zero)
-__global__ void eri_pack_w_kernel(const double* __restrict__ W, int M, int NM, long rows_a, int nchunk,
-                                  unsigned short* __restrict__ hi, unsigned short* __restrict__ lo) {
-  const long total = (long)nchunk * rows_a * KC;
+// Column slab a of W'' into the triangle planes. C[k][b M + l] =
+// W[(a,k)][(b,l)] = W'[(b,k)][(a,l)] for the rows b M + k < n_rows of the slab
+// GEMM. Chunks c_first .. c_first + ncs - 1 overlap the slab; the slab writes
+// the columns J = a M + l it owns (the last slab also the zero columns
+// J >= NM) of every stored row I < tri_rows(c): W'' = s W', s = 1 on the
+// diagonal block (I / RA = J / RA) and 2 above it, zero in the rows I >= NM.
+// One thread per element, consecutive threads along a row (contiguous reads
+// of C and writes of the planes).
+__global__ void eri_pack_slab_kernel(const double* __restrict__ C, long ldc, int M, long NM, int a, long c_first,
+                                     int ncs, long rmax, int last, unsigned short* __restrict__ hi,
+                                     unsigned short* __restrict__ lo) {
+  const long total = (long)ncs * rmax * KC, j_lo = (long)a * M, j_hi = j_lo + M;
   for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
-    const long c = e / (rows_a * KC), rem = e - c * rows_a * KC;
-    const long I = rem / KC, J = c * KC + (rem - I * KC);
-    const long p = I / RA, q = J / RA;
+    const long ci = e / (rmax * KC), rem = e - ci * rmax * KC;
+    const long I = rem / KC, jj = rem - I * KC, c = c_first + ci, J = c * KC + jj;
+    if (I >= tri_rows(c) || J < j_lo || (J >= j_hi && !(last && J >= NM))) continue;
     float f = 0.f;
-    if (I < NM && J < NM && q >= p) {
-      const long b = I / M, k = I - b * M, a = J / M, l = J - a * M;
-      const double v = W[(a * M + k) * NM + b * M + l];
-      f = (float)(q == p ? v : 2.0 * v);
+    if (I < NM && J < NM) {
+      const long b = I / M, k = I - b * M, l = J - j_lo;
+      const double v = C[k * ldc + b * M + l];
+      f = (float)(I / RA == J / RA ? v : 2.0 * v);
     }
+    const long o = tri_rows_before(c) * KC + I * KC + jj;
     const unsigned short h = bf16_rne(f);
-    hi[e] = h;
-    lo[e] = bf16_rne(f - bf16_f(h));
+    hi[o] = h;
+    lo[o] = bf16_rne(f - bf16_f(h));
+  }
+}
+
+// Column slab a of W' into the FP64 block columns: column J = a M + l belongs
+// to block Jb = J / bw (columns [j0, j0 + nj)), stored row-major with ld
+// f64_ld(nj) down to row j0 + nj (the blocks above the diagonal and the
+// diagonal block) at f64_base(Jb); C as for eri_pack_slab_kernel
+__host__ __device__ inline long f64_ld(long nj) { return (nj + 1) / 2 * 2; }
+__host__ __device__ inline long f64_base(long Jb, long bw) { return bw * bw * Jb * (Jb + 1) / 2; }
+__global__ void eri_pack_slab_f64_kernel(const double* __restrict__ C, long ldc, int M, long NM, int a, long bw,
+                                         long rmax, double* __restrict__ out) {
+  const long total = rmax * M;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
+    const long I = e / M, l = e - I * M, J = (long)a * M + l;
+    const long Jb = J / bw, j0 = Jb * bw, nj = NM - j0 < bw ? NM - j0 : bw;
+    if (I >= j0 + nj) continue;
+    const long b = I / M, k = I - b * M;
+    out[f64_base(Jb, bw) + I * f64_ld(nj) + (J - j0)] = C[k * ldc + b * M + l];
   }
 }
 
@@ -279,17 +321,6 @@ __global__ __launch_bounds__(256) void eri_reduce_kernel(const double2* __restri
   for (int n = 1 + t; n < X; n += 256) o[n] = make_double2(0.0, 0.0);
 }
 
-// W'[I = (b,k)][J = (a,l)] = W[(a,k)][(b,l)] in FP64 (the operand of the FP64
-// form); both the read and the write run along l
-__global__ void eri_perm_w_kernel(const double* __restrict__ W, int M, long NM, double* __restrict__ out) {
-  const long total = NM * NM;
-  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256) {
-    const long I = e / NM, J = e - I * NM;
-    const long b = I / M, k = I - b * M, a = J / M, l = J - a * M;
-    out[e] = W[(a * M + k) * NM + b * M + l];
-  }
-}
-
 // out[c][r] = in[r * ld_in + c]  (rows x cols -> cols x rows)
 __global__ void transpose_real_kernel(const double* __restrict__ in, long rows, long cols, long ld_in,
                                       double* __restrict__ out) {
@@ -315,6 +346,8 @@ Shape shape_of(afq_system s, int sp) {
   return h;
 }
 size_t plane_bytes(long rows, int nchunk) { return (size_t)rows * nchunk * KC * 2; }
+// one plane of the W'' triangle
+size_t plane_a_bytes(const Shape& h) { return (size_t)tri_rows_before(h.nchunk) * ROWB; }
 long rows_b_of(int nw) { return (2L * nw + RBR - 1) / RBR * RBR; }
 
 // work units: row block p covers chunks [TA p, nchunk) in runs of kper chunks;
@@ -325,7 +358,7 @@ std::vector<int> make_units(const Shape& h, int kper) {
   for (int j = 0;; ++j) {
     bool any = false;
     for (int p = 0; p < h.nblk_a; ++p) {
-      const long c0 = (long)TA * p + (long)j * kper;
+      const long c0 = (long)CPB * p + (long)j * kper;
       if (c0 >= h.nchunk) continue;
       any = true;
       u.push_back(p);
@@ -345,7 +378,7 @@ std::vector<int> make_units(const Shape& h, int kper) {
 // stays balanced (measured best among 128 to 2048 units)
 int choose_kper(const Shape& h) {
   long total = 0;
-  for (int p = 0; p < h.nblk_a; ++p) total += h.nchunk - (long)TA * p;
+  for (int p = 0; p < h.nblk_a; ++p) total += h.nchunk - (long)CPB * p;
   const long target = 256;
   return (int)std::max<long>(16, (total + target - 1) / target);
 }
@@ -360,15 +393,17 @@ void eri_free(afq_system s) {
   s->eri_prec = -1;
 }
 
-// bytes of the stored tensor of one distinct spin block in the given precision
-size_t tensor_bytes_of(const Shape& h, int prec) {
-  return prec == AFQ_FP64 ? (size_t)h.NM * h.NM * 8 : 2 * plane_bytes(h.rows_a, h.nchunk);
-}
-
 // column blocks of the FP64 form: NB about 8, widths a multiple of 32 (16-byte
 // aligned column offsets for the tiled GEMM)
 constexpr int NB64 = 8;
 long blk64(long NM) { return std::max<long>(32, (NM + NB64 - 1) / NB64 + 31) / 32 * 32; }
+
+// bytes of the stored tensor of one distinct spin block in the given precision
+size_t tensor_bytes_of(const Shape& h, int prec) {
+  if (prec != AFQ_FP64) return 2 * plane_a_bytes(h);
+  const long bw = blk64(h.NM), nb = (h.NM + bw - 1) / bw, nj = h.NM - (nb - 1) * bw;
+  return (size_t)(f64_base(nb - 1, bw) + h.NM * f64_ld(nj)) * 8;
+}
 
 // the four-index form pays when it needs fewer products than the Cholesky form
 // ((N M)^2 / 2 against X N^2 M per walker and spin, i.e. M < 2 X), the system
@@ -385,8 +420,8 @@ bool eri_pays(afq_system s) {
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
   const long nm = std::max(shape_of(s, 0).NM, shape_of(s, 1).NM);
-  // set-up transients: Lt transposed and the FP64 Gram matrix before its permutation
-  const size_t transient = (size_t)nm * s->X * 8 + (size_t)nm * nm * 8;
+  // set-up transients: Lt transposed and one column slab of the Gram matrix
+  const size_t transient = (size_t)nm * s->X * 8 + (size_t)s->M * nm * 8;
   return bytes <= free_b / 4 && bytes + transient <= free_b / 2;
 }
 
@@ -413,10 +448,10 @@ int eri_prepare(afq_system s) {
     AFQ_CHECK(h.NM <= 65535L * 32, AFQ_E_UNSUPPORTED, "exchange (four-index): N M too large");
     const bool f64 = s->prec == AFQ_FP64;
     const std::vector<int> units = f64 ? std::vector<int>() : make_units(h, choose_kper(h));
-    DevBuf LT, W;
-    int rc = LT.alloc((size_t)h.NM * X * 8);
-    if (rc == AFQ_OK) rc = s->eri_w[sp].alloc(tensor_bytes_of(h, s->prec));
-    if (rc == AFQ_OK) rc = W.alloc((size_t)h.NM * h.NM * 8);
+    DevBuf LT, SL;
+    int rc = s->eri_w[sp].alloc(tensor_bytes_of(h, s->prec));
+    if (rc == AFQ_OK) rc = LT.alloc((size_t)h.NM * X * 8);
+    if (rc == AFQ_OK) rc = SL.alloc((size_t)M * h.NM * 8);
     if (rc == AFQ_OK && !f64) rc = s->eri_units[sp].alloc(units.size() * sizeof(int));
     if (rc == AFQ_OK) {
       // LT[(a,k)][n] = Lt_n[a][k]
@@ -424,32 +459,38 @@ int eri_prepare(afq_system s) {
                          s->LtRe.as<double>() + (long)off * M, (long)X, h.NM, (long)ntot * M, LT.as<double>());
       rc = hip_status(hipGetLastError(), "exchange (four-index): transpose");
     }
-    if (rc == AFQ_OK) {
-      // W[(a,k)][(b,l)] = sum_n LT[(a,k)][n] LT[(b,l)][n]
+    const int N = s->nspin_n(sp);
+    const long bw = blk64(h.NM);
+    for (int a = 0; a < N && rc == AFQ_OK; ++a) {
+      // rows the stored triangle keeps in the slab's columns [a M, a M + M)
+      const long j_lo = (long)a * M, j_hi = j_lo + M;
+      const long c_first = j_lo / KC, c_last = (j_hi - 1) / KC;
+      const long rmax = f64 ? std::min(h.NM, ((j_hi - 1) / bw + 1) * bw) : tri_rows(c_last);
+      const long n = (std::min(rmax, h.NM) + M - 1) / M * M;
+      // SL[k][(b,l)] = sum_n LT[(a,k)][n] LT[(b,l)][n], b < n / M
       GemmArgs<double> g = gemm_args<double>();
-      g.m = (int)h.NM; g.n = (int)h.NM; g.k = X;
-      g.A = LT.as<double>(); g.lda = X; g.cA = false;
+      g.m = M; g.n = (int)n; g.k = X;
+      g.A = LT.as<double>() + j_lo * X; g.lda = X; g.cA = false;
       g.B = LT.as<double>(); g.ldb = X; g.opB = OP_T; g.cB = false;
-      g.C = W.as<double>(); g.ldc = h.NM; g.cC = false;
+      g.C = SL.as<double>(); g.ldc = n; g.cC = false;
       rc = gemm<double>(g, st);
-    }
-    if (rc == AFQ_OK && f64) {   // FP64 mode keeps W' itself as the operand
-      hipLaunchKernelGGL(eri_perm_w_kernel, dim3(grid_of(h.NM * h.NM)), dim3(256), 0, st, W.as<double>(), M, h.NM,
-                         s->eri_w[sp].as<double>());
-      rc = hip_status(hipGetLastError(), "exchange (four-index): permute");
-    }
-    if (rc == AFQ_OK && !f64) {
-      unsigned short* hi = s->eri_w[sp].as<unsigned short>();
-      const size_t pe = plane_bytes(h.rows_a, h.nchunk) / 2;   // elements per plane
-      hipLaunchKernelGGL(eri_pack_w_kernel, dim3(grid_of((long)h.nchunk * h.rows_a * KC)), dim3(256), 0, st,
-                         W.as<double>(), M, (int)h.NM, h.rows_a, h.nchunk, hi, hi + pe);
+      if (rc != AFQ_OK) break;
+      if (f64) {
+        hipLaunchKernelGGL(eri_pack_slab_f64_kernel, dim3(grid_of(rmax * M)), dim3(256), 0, st, SL.as<double>(), n,
+                           M, h.NM, a, bw, rmax, s->eri_w[sp].as<double>());
+      } else {
+        unsigned short* hi = s->eri_w[sp].as<unsigned short>();
+        const int ncs = (int)(c_last - c_first + 1);
+        hipLaunchKernelGGL(eri_pack_slab_kernel, dim3(grid_of(ncs * rmax * KC)), dim3(256), 0, st, SL.as<double>(),
+                           n, M, h.NM, a, c_first, ncs, rmax, (int)(a == N - 1), hi, hi + plane_a_bytes(h) / 2);
+      }
       rc = hip_status(hipGetLastError(), "exchange (four-index): pack");
     }
     if (rc == AFQ_OK && !f64)
       rc = hip_status(hipMemcpyAsync(s->eri_units[sp].p, units.data(), units.size() * sizeof(int),
                                      hipMemcpyHostToDevice, st),
                       "exchange (four-index): units");
-    // W and LT are freed on return: wait for the kernels that read them
+    // SL and LT are freed on return: wait for the kernels that read them
     if (rc == AFQ_OK) rc = hip_status(hipStreamSynchronize(st), "exchange (four-index): set-up");
     if (rc != AFQ_OK) {
       (void)hipStreamSynchronize(st);
@@ -565,7 +606,7 @@ static int eri_exchange_f64(afq_system s, afq_walkers w, int sp, hipStream_t st)
   const Shape h = shape_of(s, sp);
   const int wsp = s->eri_share ? 0 : sp;
   const long NM = h.NM, ldt = (long)s->ntot * s->M;
-  AFQ_CHECK(s->eri_ready && s->eri_w[wsp].bytes >= (size_t)NM * NM * 8, AFQ_E_STATE,
+  AFQ_CHECK(s->eri_ready && s->eri_w[wsp].bytes >= tensor_bytes_of(h, AFQ_FP64), AFQ_E_STATE,
             "exchange (four-index, FP64): tensor not prepared");
   AFQ_CHECK(w->eri_part.bytes >= (size_t)w->nw * NM * sizeof(double2), AFQ_E_STATE,
             "exchange (four-index, FP64): walker scratch not prepared");
@@ -573,22 +614,23 @@ static int eri_exchange_f64(afq_system s, afq_walkers w, int sp, hipStream_t st)
   const double* th = w->theta.as<double>() + 2L * s->spin_off(sp) * s->M;   // row w: Theta-hat of walker w
   double* Z = w->eri_part.as<double>();
   const long bw = blk64(NM);
-  for (long j0 = 0; j0 < NM; j0 += bw) {
+  for (long j0 = 0, jb = 0; j0 < NM; j0 += bw, ++jb) {
     const long nj = std::min(bw, NM - j0);
+    const double* col = Wt + f64_base(jb, bw);   // block column J: rows 0 .. j0 + nj, ld f64_ld(nj)
     GemmArgs<double> g = gemm_args<double>();
     g.m = w->nw; g.n = (int)nj;
     g.A = th; g.lda = ldt; g.cA = true;
-    g.ldb = NM; g.cB = false;
+    g.ldb = f64_ld(nj); g.cB = false;
     g.C = Z + 2 * j0; g.ldc = NM; g.cC = true;
     // Z_J = Theta-hat_J^T W'_JJ
     g.k = (int)nj;
     g.A = th + 2 * j0;
-    g.B = Wt + j0 * NM + j0;
+    g.B = col + j0 * g.ldb;
     AFQ_RET(gemm<double>(g, st));
     if (j0 > 0) {   // Z_J += 2 Theta-hat_{<J}^T W'_{<J,J}
       g.k = (int)j0;
       g.A = th;
-      g.B = Wt + j0;
+      g.B = col;
       g.ar = 2.0; g.ai = 0.0; g.br = 1.0; g.bi = 0.0;
       AFQ_RET(gemm<double>(g, st));
     }
@@ -607,7 +649,7 @@ int eri_exchange(afq_system s, afq_walkers w, int sp, hipStream_t st) {
   const int nsp = eri_nsp(s);
   AFQ_CHECK(nsp == 1 || sp == 0, AFQ_E_INVALID, "exchange (four-index): shared tensor contracts both spins at once");
   const long rows_b = rows_b_of(nsp * w->nw);
-  const size_t pa = plane_bytes(h.rows_a, h.nchunk), pb = plane_bytes(rows_b, h.nchunk);
+  const size_t pa = plane_a_bytes(h), pb = plane_bytes(rows_b, h.nchunk);
   const int nunit = s->eri_nunit[wsp];
   AFQ_CHECK(s->eri_ready && nunit > 0 && s->eri_w[wsp].bytes >= 2 * pa, AFQ_E_STATE,
             "exchange (four-index): tensor not prepared");
@@ -618,7 +660,6 @@ int eri_exchange(afq_system s, afq_walkers w, int sp, hipStream_t st) {
   g.a[1] = g.a[0] + pa;
   g.b[0] = w->eri_theta.as<unsigned char>();
   g.b[1] = g.b[0] + pb;
-  g.rows_a = h.rows_a;
   g.rows_b = rows_b;
   g.units = s->eri_units[wsp].as<int4>();
   g.nunit = nunit;

@@ -122,12 +122,13 @@ def test_exchange_form_selection(api):
     g = api.System.from_synth(s, precision="bf16x3")
     assert g.exchange_form() == ("cholesky", 0)          # auto: N M = 96 is below the size floor
     g.set_exchange_form("four_index")
-    form, nbytes = g.exchange_form()
-    assert form == "four_index" and nbytes > 0
+    # split BF16: hi and lo planes of the upper block triangle, N M = 96 in three
+    # 32-column chunks that each keep one 256-row block of 64-byte rows
+    assert g.exchange_form() == ("four_index", 2 * 3 * 256 * 64)
     g.set_precision("cfp32")                              # not in complex FP32 mode
     assert g.exchange_form() == ("cholesky", 0)
-    g.set_precision("fp64")                               # FP64 keeps W' itself: (N M)^2 doubles
-    assert g.exchange_form() == ("four_index", (4 * 24) ** 2 * 8)
+    g.set_precision("fp64")   # FP64 keeps W' in three 32-column blocks, each down to its diagonal block
+    assert g.exchange_form() == ("four_index", (32 + 64 + 96) * 32 * 8)
     g.set_precision("bf16x3")
     assert g.exchange_form()[0] == "four_index"
     g.set_exchange_form("cholesky")
