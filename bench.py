@@ -269,6 +269,9 @@ def bench_kp(a, torch, synth, api, _lib):
     e_var = float(probe.energy()[3][0])
     probe.close()
     wk = api.Walkers(sysg, nw)
+    if a.kp_trace == "valu":
+        wk.set_exchange_variant(0, 1)
+        wk.set_exchange_variant(1, 1)
     wk.step(a.warmup, dt, seed=11, qr_every=qr, e_shift=e_var, outputs=())
     torch.cuda.synchronize()
     lib.afq_trace_reset()
@@ -282,7 +285,8 @@ def bench_kp(a, torch, synth, api, _lib):
     lib.afq_trace_reset()
     value = nw * a.steps / wall
     # trace kernel: per walker, spin, vector (Q, n), row block k1 and pair (a, k', b):
-    # two length-m complex dot products (8 flop per multiply-add)
+    # two length-m complex dot products (8 flop per multiply-add; the MFMA
+    # kernel's padded tiles are not counted)
     tr_flop = sum(8.0 * 2 * m * (n * nk * n) * nk * XL for n in (nu, nd)) * nw
     ex_ms, ex_cnt = ph["exchange"]
     ex_avg_s = ex_ms / 1e3 / max(ex_cnt, 1)
@@ -311,10 +315,13 @@ def bench_kp(a, torch, synth, api, _lib):
                                f"N={Nu}+{Nd}), {xq} vectors per Q ({XL} complex vectors, {2 * XL} fields), "
                                f"{nw} walkers, dt={dt}, QR every {qr}",
                    "precision": "fp64", "walkers": nw, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma" if a.kp_trace == "mfma" else "alu", "achieved": round(achieved, 3),
+                     "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_TFLOPS["fp64"], 4), "traffic": None,
-                     "kernel": "k-point trace kernel (per row block and Q: Omega, Omega' blocks, FP64 VALU) "
-                               "+ its row-block reduction",
+                     "kernel": ("k-point trace kernel on FP64 MFMA (per group of row blocks and Q: Omega' tiles "
+                                "to LDS, Omega tiles paired in their epilogue)" if a.kp_trace == "mfma" else
+                                "k-point trace kernel on FP64 VALU (per row block and Q: Omega, Omega' blocks)")
+                               + " + its row-block reduction",
                      "flop_per_launch": tr_flop, "avg_launch_ms": round(ex_avg_s * 1e3, 3), "launches": ex_cnt,
                      "dense_equivalent_flop": dense_flop},
         "cpu_baseline": cpu,
@@ -442,6 +449,8 @@ def main(argv=None):
     ap.add_argument("--no-grad", dest="grad", action="store_false",
                     help="skip the adjoint measurement on the differentiation workload")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kp-trace", default="mfma", choices=["mfma", "valu"],
+                    help="k-point workload: exchange-trace kernel (FP64 MFMA or the FP64 VALU one)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary measurements (comb, back-propagation window) after the timed steps")
     ap.add_argument("--exchange-form", default="auto", choices=["auto", "cholesky", "four_index"],

@@ -382,7 +382,10 @@ int afq_autotune(afq_system s, afq_walkers w, int reps, int *choice_out);
 /* Pins the exchange launch variant of one spin for this walker set (0..2, or
  * -1 to return to the tuned/default choice), e.g. to replay a tuning table
  * saved from an earlier process. A variant that does not fit the shape makes
- * the next step or energy call fail with AFQ_E_UNSUPPORTED. */
+ * the next step or energy call fail with AFQ_E_UNSUPPORTED. For a k-point
+ * system the variant picks the exchange-trace kernel of the spin: 1 the FP64
+ * VALU kernel, any other value the FP64 MFMA kernel where the shape allows it
+ * (m <= 32 and its LDS fits), else the VALU kernel. */
 int afq_exchange_variant(afq_walkers w, int spin, int variant);
 
 /* ------------------------------------------------------------------------ */

@@ -334,7 +334,9 @@ int kp_abuild(afq_system s, afq_walkers w, const double2* coef, hipStream_t st) 
 }
 
 // ---------------------------------------------------------------------------
-// traces: one workgroup per (row block k1, Q, walker x spin). With k2 + Q = k1,
+// traces: one workgroup per (row block k1, walker, Q) and spin; the workgroups
+// running together share Q (Q is the slowest grid index), so the Lt and Ltd
+// rows of that Q stay in L2 while the walkers go by. With k2 + Q = k1,
 // for every vector n and every column c = (k', b) of the spin's trial block:
 //   Omega[(k1,a), c]      = sum_l Lt^{Q,k2}_n[a][l]  Theta[(k2, l), c]
 //   Omega'[c, (k1,a)]     = sum_l Ltd^{Q,k'}_n[b][l] Theta[(k'+Q, l), (k1, a)]
@@ -358,7 +360,7 @@ struct KpTraceArgs {
 template <int NS>
 __global__ __launch_bounds__(256) void kp_trace_kernel(KpTraceArgs a, int sp) {
   extern __shared__ double2 lds[];
-  const int k1 = blockIdx.x, Q = blockIdx.y, w = blockIdx.z, t = threadIdx.x;
+  const int k1 = blockIdx.x, w = blockIdx.y, Q = blockIdx.z, t = threadIdx.x;
   const int nk = a.nk, m = a.m, M = a.M;
   const int ns = NS, N = nk * ns, off = sp ? nk * a.nu : 0, aoff = sp ? a.nu : 0;
   const int nkn = a.nu + a.nd;
@@ -443,6 +445,282 @@ __global__ __launch_bounds__(256) void kp_trace_kernel(KpTraceArgs a, int sp) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// the same traces on FP64 MFMA (v_mfma_f64_16x16x4f64, a complex product as
+// four real ones). One workgroup per (group of G row blocks k1_j = G grp + j,
+// walker, Q) and spin, G ns <= 16, Q the slowest grid index as in the VALU
+// kernel. For each block of VB vectors, rows (n, a):
+//   Omega'_{k'}[(n,b), (j,a)] = sum_l Ltd^{Q,k'}_n[b][l] Theta[(k'+Q, l), (k1_j, a)]
+//     for every k', computed transposed (rows (j, a): one 16-row tile, the
+//     staged Theta columns the A operand shared by KT column tiles (n, b) of
+//     Ltd rows) and kept in LDS;
+//   Omega_j[(n,a), c] = sum_l Lt^{Q,k2_j}_n[a][l] Theta[(k2_j, l), c]
+//     (k2_j + Q = k1_j, c = (k', b) over the trial block), computed
+//     transposed too (KT row tiles c of the staged Theta rows against one
+//     column tile (n, a) of Lt rows), whose epilogue pairs every element with
+//     Omega'_{k'}[(n,b), (j,a)].
+// A unit is KT output tiles sharing one operand (2 KT independent accumulator
+// chains), the contraction over l in KS steps of 4; the operand read from
+// global memory (Ltd or Lt rows) goes straight into registers, the next
+// unit's while this one multiplies. A lane's share of tr(Omega Omega') for its
+// column (n, a) is summed over its rows and the unit's tiles in registers,
+// then over the four row groups of the tile, the units and the rows of a
+// vector in a fixed order (bitwise repeatable). The Omega' rows in LDS are an
+// odd number of 16-byte slots apart, so a wave's accesses along (n, b) do not
+// collide in the banks.
+// ---------------------------------------------------------------------------
+typedef __attribute__((ext_vector_type(4))) double kd4;
+typedef __attribute__((ext_vector_type(2))) double kv2;         // (Re, Im)
+typedef const __attribute__((address_space(1))) kv2 kp_g2;       // global memory
+typedef __attribute__((address_space(3))) kv2 kp_l2;             // LDS
+constexpr int KT = 3;             // output tiles per unit
+constexpr int KP_MFMA_MAX_M = 32; // larger m: the unit's operand registers would spill
+constexpr int KP_MFMA_MAX_NK = 64;
+
+// dynamic LDS of the MFMA trace kernel: the Theta blocks G x 4KS x N and
+// nk x 4KS x G ns (contraction rows padded with zeros to a multiple of 4), the
+// Omega' of a vector block (VB vectors of nk ns rows GSP apart, one slot of
+// padding per vector) and the row partials
+static size_t kp_mfma_lds(int nk, int m, int ns, int G, int VB) {
+  const size_t N = (size_t)nk * ns, GS = (size_t)G * ns, m4 = ((size_t)m + 3) / 4 * 4;
+  const size_t r16 = ((size_t)VB * ns + 15) / 16 * 16, nch = ((N + 15) / 16 + KT - 1) / KT;
+  return ((size_t)G * m4 * N + (size_t)nk * m4 * GS + (size_t)VB * (nk * ns * (GS | 1) + 1) +
+          (size_t)G * (nch + 1) * r16) * 16;
+}
+
+// G: the largest divisor of nk with G ns <= 16; VB: the largest vector block
+// that fits in LDS. False when the shape needs the VALU kernel.
+static bool kp_mfma_shape(int nk, int m, int ns, int xq, int* G_out, int* VB_out, size_t* lds_out) {
+  if (ns < 1 || ns > 16 || m > KP_MFMA_MAX_M || nk > KP_MFMA_MAX_NK) return false;
+  int G = 1;
+  for (int g = 1; g <= nk; ++g)
+    if (nk % g == 0 && g * ns <= 16) G = g;
+  int VB = 0;
+  for (int v = 1; v <= xq; ++v)   // 1 KB left for the kernel's static tables
+    if (kp_mfma_lds(nk, m, ns, G, v) + 1024 <= KP_MAX_LDS) VB = v;
+  if (VB == 0) return false;
+  *G_out = G;
+  *VB_out = VB;
+  *lds_out = kp_mfma_lds(nk, m, ns, G, VB);
+  return true;
+}
+
+// x / d for 0 <= x < 2^22, rcp = 1 / d: (x + 1/2) / d lies at least 1 / (2 d)
+// from an integer, and the float products err by less than (x + 1/2) 2^-23 / d
+__device__ inline int kp_div(int x, float rcp) { return (int)(((float)x + 0.5f) * rcp); }
+
+// KT complex tile products, one shared operand sh (A when SH_A, else B) and
+// one per tile: the four real products of each tile are issued in four
+// rounds over the tiles, so products into one accumulator are 2 KT - 1 apart;
+// the shared operand's imaginary part is negated once
+template <bool SH_A>
+__device__ inline void kp_cmma_kt(kd4 (&cr)[KT], kd4 (&ci)[KT], kv2 sh, const kv2 (&v)[KT]) {
+  const double nsy = -sh.y;
+#pragma unroll
+  for (int c = 0; c < KT; ++c)
+    cr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(SH_A ? sh.x : v[c].x, SH_A ? v[c].x : sh.x, cr[c], 0, 0, 0);
+#pragma unroll
+  for (int c = 0; c < KT; ++c)   // Re A Im B
+    ci[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(SH_A ? sh.x : v[c].x, SH_A ? v[c].y : sh.y, ci[c], 0, 0, 0);
+#pragma unroll
+  for (int c = 0; c < KT; ++c)   // - Im A Im B
+    cr[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(SH_A ? nsy : v[c].y, SH_A ? v[c].y : nsy, cr[c], 0, 0, 0);
+#pragma unroll
+  for (int c = 0; c < KT; ++c)   // Im A Re B
+    ci[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(SH_A ? sh.y : v[c].y, SH_A ? v[c].x : sh.x, ci[c], 0, 0, 0);
+}
+
+// Lt / Ltd row (n, b) of the vector block at blk (row < R: (n0 + n) nkn + aoff
+// + b after the block start), contraction elements 4 s + lq (clamped to m - 1:
+// the staged Theta rows past m are zero)
+template <int KS>
+__device__ inline void kp_load_row(kp_g2* blk, int row, float rns, int ns, int nkn, int m, int lq, kv2 (&v)[KS]) {
+  const int nl = kp_div(row, rns), b = row - nl * ns;
+  kp_g2* p = blk + ((long)nl * nkn + b) * m;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) v[s] = p[min(4 * s + lq, m - 1)];
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void kp_trace_mfma_kernel(KpTraceArgs a, int sp, int G, int VB) {
+  constexpr int M4 = 4 * KS;
+  extern __shared__ kv2 lds_raw[];
+  __shared__ int k2s[16], kqs[KP_MFMA_MAX_NK];
+  const int grp = blockIdx.x, w = blockIdx.y, Q = blockIdx.z, t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6, lr = lane & 15, lq = lane >> 4;
+  const int nk = a.nk, m = a.m, M = a.M, xq = a.xq;
+  const int ns = sp ? a.nd : a.nu, N = nk * ns, GS = G * ns, GSP = GS | 1;
+  const float rns = 1.0f / (float)ns;
+  const int off = sp ? nk * a.nu : 0, aoff = sp ? a.nu : 0, nkn = a.nu + a.nd;
+  const int R16 = (VB * ns + 15) / 16 * 16, nrt = R16 / 16, nct = (N + 15) / 16;
+  const int nch1 = (nrt + KT - 1) / KT, nch2 = (nct + KT - 1) / KT;   // tile chunks
+  const float rnch1 = 1.0f / (float)nch1, rnch2 = 1.0f / (float)nch2, rnrt2 = 1.0f / (float)(nrt * nch2);
+  const long OPV = (long)nk * ns * GSP + 1;   // Omega' slots per vector
+  kp_l2* thA = (kp_l2*)lds_raw;                 // [j][l < M4][c]: Theta[(k2_j, l), c], zero for l >= m
+  kp_l2* thB = thA + (long)G * M4 * N;          // [k][l < M4][j ns + a]: Theta[(k, l), (k1_j, a)], zero for l >= m
+  kp_l2* OP = thB + (long)nk * M4 * GS;         // [nl][k'][b][j ns + a]: Omega'_{k'}[(n0 + nl, b), (j, a)]
+  kp_l2* rp = OP + (long)VB * OPV;              // [j][chunk][(n, a)]: shares of tr(Omega Omega')
+  kp_l2* tp = rp + (long)G * nch2 * R16;        // [j][(n, a)]: the diagonal of Omega_j
+  if (t < nk) kqs[t] = a.kq[Q * nk + t];        // the row block k' + Q
+  __syncthreads();
+  if (t < G) {
+    const int k1 = grp * G + t;
+    int k2 = 0;
+    for (int c = 0; c < nk; ++c)
+      if (kqs[c] == k1) k2 = c;
+    k2s[t] = k2;
+  }
+  __syncthreads();
+  kp_g2* th = (kp_g2*)a.thetaT + (long)w * a.ntot * M;
+  for (int e = t; e < G * N * M4; e += 256) {   // l fastest: contiguous global reads
+    const int j = e / (N * M4), r = e - j * N * M4, c = r / M4, l = r - c * M4;
+    kv2 v = {0.0, 0.0};
+    if (l < m) v = th[(long)(off + c) * M + k2s[j] * m + l];
+    thA[((long)j * M4 + l) * N + c] = v;
+  }
+  for (int e = t; e < GS * nk * M4; e += 256) {
+    const int ja = e / (nk * M4), r = e - ja * nk * M4, k = r / M4, l = r - k * M4, j = ja / ns, aa = ja - j * ns;
+    kv2 v = {0.0, 0.0};
+    if (l < m) v = th[(long)(off + (grp * G + j) * ns + aa) * M + k * m + l];
+    thB[((long)k * M4 + l) * GS + ja] = v;
+  }
+  __syncthreads();
+  double2* out = a.part + ((((long)w * 2 + sp) * nk + Q) * xq) * nk * 3;
+  const int lrB = min(lr, GS - 1);   // A rows (j, a) past G ns: clamped reads, outputs dropped
+
+  for (int n0 = 0; n0 < xq; n0 += VB) {
+    const int vb = min(VB, xq - n0), R = vb * ns;
+    // step 1: Omega'^T tiles, unit u = (k', chunk of KT column tiles (n, b))
+    {
+      const int nu = nk * nch1;
+      kv2 cur[KT][KS], nxt[KT][KS];
+      int u = wave;
+      if (u < nu) {
+        const int kp = kp_div(u, rnch1), ch = u - kp * nch1;
+        kp_g2* blk = (kp_g2*)a.Ltd + ((((long)Q * nk + kp) * xq + n0) * nkn + aoff) * m;
+#pragma unroll
+        for (int c = 0; c < KT; ++c) kp_load_row<KS>(blk, min(16 * (KT * ch + c) + lr, R - 1), rns, ns, nkn, m, lq, cur[c]);
+      }
+      for (; u < nu; u += 4) {
+        if (u + 4 < nu) {
+          const int kp = kp_div(u + 4, rnch1), ch = u + 4 - kp * nch1;
+          kp_g2* blk = (kp_g2*)a.Ltd + ((((long)Q * nk + kp) * xq + n0) * nkn + aoff) * m;
+#pragma unroll
+          for (int c = 0; c < KT; ++c)
+            kp_load_row<KS>(blk, min(16 * (KT * ch + c) + lr, R - 1), rns, ns, nkn, m, lq, nxt[c]);
+        }
+        const int kp = kp_div(u, rnch1), ch = u - kp * nch1;
+        kp_l2* bsrc = thB + (long)kqs[kp] * M4 * GS + lrB;
+        kd4 cr[KT], ci[KT];
+#pragma unroll
+        for (int c = 0; c < KT; ++c) cr[c] = ci[c] = kd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const kv2 av = bsrc[(4 * s + lq) * GS];
+          kv2 bv[KT];
+#pragma unroll
+          for (int c = 0; c < KT; ++c) bv[c] = cur[c][s];
+          kp_cmma_kt<true>(cr, ci, av, bv);
+        }
+        // lane: column (n, b) = 16 ct + lr, rows (j, a) = lq + 4 i
+#pragma unroll
+        for (int c = 0; c < KT; ++c) {
+          const int col = 16 * (KT * ch + c) + lr;
+          if (col < R) {
+            const int nl = kp_div(col, rns), b = col - nl * ns;
+            kp_l2* o = OP + nl * OPV + ((long)kp * ns + b) * GSP;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (lq + 4 * i < GS) o[lq + 4 * i] = kv2{cr[c][i], ci[c][i]};
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < KT; ++c)
+#pragma unroll
+          for (int s = 0; s < KS; ++s) cur[c][s] = nxt[c][s];
+      }
+    }
+    __syncthreads();
+    // step 2: Omega^T tiles, unit u = (j, column tile (n, a), chunk of KT row
+    // tiles c), paired with Omega' in the epilogue
+    {
+      const int nu = G * nrt * nch2;
+      kv2 cur[KS], nxt[KS];
+      int u = wave;
+      if (u < nu) {
+        const int j = kp_div(u, rnrt2), ct = kp_div(u - j * nrt * nch2, rnch2);
+        kp_g2* blk = (kp_g2*)a.Lt + ((((long)Q * nk + k2s[j]) * xq + n0) * nkn + aoff) * m;
+        kp_load_row<KS>(blk, min(16 * ct + lr, R - 1), rns, ns, nkn, m, lq, cur);
+      }
+      for (; u < nu; u += 4) {
+        if (u + 4 < nu) {
+          const int j = kp_div(u + 4, rnrt2), ct = kp_div(u + 4 - j * nrt * nch2, rnch2);
+          kp_g2* blk = (kp_g2*)a.Lt + ((((long)Q * nk + k2s[j]) * xq + n0) * nkn + aoff) * m;
+          kp_load_row<KS>(blk, min(16 * ct + lr, R - 1), rns, ns, nkn, m, lq, nxt);
+        }
+        const int j = kp_div(u, rnrt2), rem = u - j * nrt * nch2, ct = kp_div(rem, rnch2), ch = rem - ct * nch2;
+        const int k1 = grp * G + j;
+        kp_l2* asrc = thA + (long)j * M4 * N;
+        int arow[KT];
+#pragma unroll
+        for (int c = 0; c < KT; ++c) arow[c] = min(16 * (KT * ch + c) + lr, N - 1);   // rows c past N: dropped
+        kd4 cr[KT], ci[KT];
+#pragma unroll
+        for (int c = 0; c < KT; ++c) cr[c] = ci[c] = kd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          kv2 av[KT];
+#pragma unroll
+          for (int c = 0; c < KT; ++c) av[c] = asrc[(long)(4 * s + lq) * N + arow[c]];
+          kp_cmma_kt<false>(cr, ci, cur[s], av);
+        }
+        // lane: column (n, a) = 16 ct + lr, rows c = 16 (KT ch + c) + lq + 4 i
+        const int col = 16 * ct + lr, nl = kp_div(col, rns), aa = col - nl * ns;
+        const bool cok = col < R;
+        kp_l2* opn = OP + nl * OPV + j * ns + aa;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int c = 0; c < KT; ++c)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int rc = 16 * (KT * ch + c) + lq + 4 * i;
+            if (cok && rc < N) {
+              const int kpc = kp_div(rc, rns), bc = rc - kpc * ns;
+              const kv2 o = opn[((long)kpc * ns + bc) * GSP];
+              sr += cr[c][i] * o.x - ci[c][i] * o.y;
+              si += cr[c][i] * o.y + ci[c][i] * o.x;
+              if (kpc == k1 && bc == aa) tp[(long)j * R16 + col] = kv2{cr[c][i], ci[c][i]};
+            }
+          }
+        sr += __shfl_xor(sr, 16);
+        si += __shfl_xor(si, 16);
+        sr += __shfl_xor(sr, 32);
+        si += __shfl_xor(si, 32);
+        if (lq == 0) rp[((long)j * nch2 + ch) * R16 + col] = kv2{sr, si};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) cur[s] = nxt[s];
+      }
+    }
+    __syncthreads();
+    // step 3: per (vector, j): tr(Omega Omega'), tr Omega, tr Omega'
+    for (int e = t; e < vb * G; e += 256) {
+      const int nl = e / G, j = e - nl * G, k1 = grp * G + j;
+      kv2 ek = {0.0, 0.0}, tl = ek, tld = ek;
+      for (int aa = 0; aa < ns; ++aa) {
+        const int rr = nl * ns + aa;
+        for (int ch = 0; ch < nch2; ++ch) ek += rp[((long)j * nch2 + ch) * R16 + rr];
+        tl += tp[(long)j * R16 + rr];
+        tld += OP[nl * OPV + ((long)k1 * ns + aa) * GSP + j * ns + aa];
+      }
+      double2* o = out + ((long)(n0 + nl) * nk + k1) * 3;
+      o[0] = make_double2(ek.x, ek.y);
+      o[1] = make_double2(tl.x, tl.y);
+      o[2] = make_double2(tld.x, tld.y);
+    }
+    __syncthreads();
+  }
+}
+
 // per (walker, spin): sum the row blocks (fixed order) into the 2X-field layout
 //   tro[g] = (tr L G + tr L^+ G)/2, tro[XL + g] = (tr L G - tr L^+ G)/(2i),
 //   troo[g] = tr(Omega Omega'), troo[XL + g] = 0
@@ -480,13 +758,34 @@ int kp_energy_traces(afq_system s, afq_walkers w, hipStream_t st) {
   a.part = w->kp_part.as<double2>();
   for (int sp = 0; sp < 2; ++sp) {
     const int ns = sp ? s->kp_nd : s->kp_nu;
+    int G = 0, VB = 0;
+    size_t lds = 0;
+    // the MFMA kernel unless the walker set pins the VALU one (variant 1) or the shape needs it
+    if (w->exch_var[sp] != 1 && kp_mfma_shape(nk, s->kp_m, ns, xq, &G, &VB, &lds)) {
+      const int ks = ceil_div(s->kp_m, 4);
+      switch (ks) {
+#define AFQ_KP_KS(V)                                                                                          \
+  case V:                                                                                                     \
+    if (lds > 64 * 1024)                                                                                      \
+      AFQ_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kp_trace_mfma_kernel<V>),                \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));                \
+    hipLaunchKernelGGL(kp_trace_mfma_kernel<V>, dim3(nk / G, nw, nk), dim3(256), lds, st, a, sp, G, VB);     \
+    break;
+        AFQ_KP_KS(1) AFQ_KP_KS(2) AFQ_KP_KS(3) AFQ_KP_KS(4) AFQ_KP_KS(5) AFQ_KP_KS(6) AFQ_KP_KS(7) AFQ_KP_KS(8)
+#undef AFQ_KP_KS
+        default:
+          AFQ_CHECK(false, AFQ_E_INVALID, "k-point trace kernel (MFMA): bad contraction length");
+      }
+      AFQ_TRY_HIP(hipGetLastError());
+      continue;
+    }
     switch (ns) {
 #define AFQ_KP_NS(V)                                                                                   \
   case V:                                                                                              \
     if (s->kp_lds > 64 * 1024)                                                                         \
       AFQ_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kp_trace_kernel<V>),              \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)s->kp_lds));   \
-    hipLaunchKernelGGL(kp_trace_kernel<V>, dim3(nk, nk, nw), dim3(256), s->kp_lds, st, a, sp);          \
+    hipLaunchKernelGGL(kp_trace_kernel<V>, dim3(nk, nw, nk), dim3(256), s->kp_lds, st, a, sp);          \
     break;
       AFQ_KP_NS(1) AFQ_KP_NS(2) AFQ_KP_NS(3) AFQ_KP_NS(4) AFQ_KP_NS(5) AFQ_KP_NS(6) AFQ_KP_NS(7) AFQ_KP_NS(8)
       AFQ_KP_NS(9) AFQ_KP_NS(10) AFQ_KP_NS(11) AFQ_KP_NS(12) AFQ_KP_NS(13) AFQ_KP_NS(14) AFQ_KP_NS(15)

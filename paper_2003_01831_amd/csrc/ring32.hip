@@ -66,7 +66,7 @@ template <int TA_, int TB_> struct Geo {
 using GeoAB = Geo<8, 4>;   // propagator build, force bias
 using GeoTY = Geo<7, 5>;   // Taylor products
 
-enum { EPI_XFORM = 0, EPI_PART = 1, EPI_HORNER = 2, EPI_B1 = 3, EPI_XFORM_B3 = 4, EPI_HORNER_LAST = 5 };
+enum { EPI_XFORM = 0, EPI_PART = 1, EPI_HORNER = 2, EPI_B1 = 3, EPI_HORNER_LAST = 5 };
 
 // split BF16 of an FP32 value: hi = bf16(f), lo = bf16(f - hi), both rounded
 // to nearest even; a pair (x, y) of them packed as two BF16 (x low) per plane
@@ -94,9 +94,6 @@ struct R32Args {
   const int* tri;
   float* x;
   long x_wstride, x_rows, ncol;
-  // EPI_XFORM_B3: the same as BF16 hi / lo planes of 32-element chunks,
-  // xb_plane bytes apart, walkers xb_wstride bytes apart
-  long xb_plane, xb_wstride;
   int M, nw;
   // EPI_PART: part[(run * rows_a + row) * rows_b + col]
   float* part;
@@ -199,7 +196,7 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
 
   // lane (lr, lq) holds rows 4 lq .. 4 lq + 3 of column lr of every tile
   const int lr = lane & 15, lq = lane >> 4;
-  if constexpr (EPI == EPI_XFORM || EPI == EPI_XFORM_B3) {
+  if constexpr (EPI == EPI_XFORM) {
 #pragma unroll
     for (int i = 0; i < TA; ++i)
 #pragma unroll
@@ -213,34 +210,6 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
         const int code = g.tri[col >> 6], bm = code >> 16, bk = code & 0xffff;
         const int m = 8 * bm + (int)((col >> 3) & 7), k = 8 * bk + (int)(col & 7);
         if (m >= g.M || k >= g.M) continue;
-        if constexpr (EPI == EPI_XFORM_B3) {
-          // rows (m, Re) = [.., ar, -ai, ..] and (m, Im) = [.., ai, ar, ..] at
-          // contraction elements 2k, 2k + 1: one 4-byte pair per plane and row
-          const long b0 = ((long)(k >> 4) * g.x_rows + 2 * m) * ROWB + 4 * (k & 15);
-          const long b1 = ((long)(m >> 4) * g.x_rows + 2 * k) * ROWB + 4 * (m & 15);
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int w = (int)(row0 >> 1) + h;
-            if (w < g.nw) {
-              const float ar = acc[i][j][2 * h], ai = acc[i][j][2 * h + 1];
-              unsigned char* X = reinterpret_cast<unsigned char*>(g.x) + (long)w * g.xb_wstride;
-              unsigned rh, rl, ih, il;
-              split_pair(ar, -ai, rh, rl);
-              split_pair(ai, ar, ih, il);
-              *reinterpret_cast<unsigned*>(X + b0) = rh;
-              *reinterpret_cast<unsigned*>(X + b0 + ROWB) = ih;
-              *reinterpret_cast<unsigned*>(X + g.xb_plane + b0) = rl;
-              *reinterpret_cast<unsigned*>(X + g.xb_plane + b0 + ROWB) = il;
-              if (bm != bk) {
-                *reinterpret_cast<unsigned*>(X + b1) = rh;
-                *reinterpret_cast<unsigned*>(X + b1 + ROWB) = ih;
-                *reinterpret_cast<unsigned*>(X + g.xb_plane + b1) = rl;
-                *reinterpret_cast<unsigned*>(X + g.xb_plane + b1 + ROWB) = il;
-              }
-            }
-          }
-          continue;
-        } else {
         const long o0 = ((long)(k >> 3) * g.x_rows + 2 * m) * RK + 2 * (k & 7);
         const long o1 = ((long)(m >> 3) * g.x_rows + 2 * k) * RK + 2 * (m & 7);
 #pragma unroll
@@ -256,7 +225,6 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
               *reinterpret_cast<float2*>(X + o1 + RK) = make_float2(ai, ar);
             }
           }
-        }
         }
       }
   } else if constexpr (EPI == EPI_PART) {
@@ -366,9 +334,10 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
 //     against the real form of A, rows 2m + part);
 //   * B3_B1: the contraction of EPI_B1 (walker rows (n, Re|Im) against the rows
 //     m of B1 - I, shared by all walkers: b_wstride 0), added to U_base in FP64;
-//   * B3_XFORM: the propagator build of EPI_XFORM_B3 (coefficient rows against
-//     the upper block triangle of L, one batch; consecutive workgroups take
-//     consecutive coefficient row blocks, so they share an L block in L2).
+//   * B3_XFORM: the propagator build (coefficient rows against the upper block
+//     triangle of L, one batch; consecutive workgroups take consecutive
+//     coefficient row blocks, so they share an L block in L2), A_w written in
+//     real form as BF16 hi / lo planes.
 struct HornerB3Args {
   const unsigned char* a;   // terms h: rows n, contraction 2m + part
   const unsigned char* b;   // real form of A: rows 2m + part, contraction 2k + part
@@ -1277,18 +1246,9 @@ int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st) {
   g.x = w->r32_x.as<float>();
   g.x_wstride = ts.x_wstride;
   g.x_rows = ts.x_rows;
-  if (taylor_b3(s)) {
-    const TaylorB3Shape tb = taylor_b3_shape(s);
-    AFQ_CHECK(w->r32_layout == 2 && w->r32_x.bytes >= (size_t)w->nw * tb.x_wstride, AFQ_E_STATE,
-              "propagator build (split BF16): walker scratch not prepared");
-    g.x_rows = tb.x_rows;
-    g.xb_plane = tb.x_plane;
-    g.xb_wstride = tb.x_wstride;
-  }
   g.ncol = tc.ncol;
   g.M = s->M;
   g.nw = w->nw;
-  if (taylor_b3(s)) return launch<GeoAB, EPI_XFORM_B3>(g, st);
   return launch<GeoAB, EPI_XFORM>(g, st);
 }
 

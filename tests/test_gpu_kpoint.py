@@ -34,11 +34,21 @@ def _walkers(T, nw, scale, seed):
     return T[None] + scale * z / np.sqrt(2.0)
 
 
+def _pin_valu(wk):
+    """Pins the FP64 VALU trace kernel (variant 1) instead of the MFMA one."""
+    wk.set_exchange_variant(0, 1)
+    wk.set_exchange_variant(1, 1)
+
+
 # (4, 5, 4, 5) and (5, 4, 3, 4): the spin with fewer electrons per k-point runs
-# more vectors per pass and needs the larger LDS layout of the trace kernel
+# more vectors per pass and needs the larger LDS layout of the VALU trace
+# kernel; (8, 4, 1, 1, 5): eight row blocks per MFMA workgroup (G ns = 8);
+# (3, 5, 1, 2, 6): three (k-point counts without a power of two); (2, 68, 1, 1,
+# 3): m > 32, which only the VALU kernel takes (both parametrisations run it)
+@pytest.mark.parametrize("kernel", ["mfma", "valu"])
 @pytest.mark.parametrize("nk,m,nu,nd,xq", [(4, 6, 2, 1, 8), (3, 5, 1, 2, 6), (8, 4, 1, 1, 5), (4, 5, 4, 5, 8),
-                                          (5, 4, 3, 4, 3)])
-def test_kpoint_energy_and_force_bias_match_the_oracle(api, nk, m, nu, nd, xq):
+                                          (5, 4, 3, 4, 3), (2, 68, 1, 1, 3)])
+def test_kpoint_energy_and_force_bias_match_the_oracle(api, nk, m, nu, nd, xq, kernel):
     ks = synth.make_kpoint_system(nk, m, nu, nd, xq, seed=400 + nk)
     ks.Lk = ks.Lk * 3.0
     ks.e_core = 0.25
@@ -48,6 +58,8 @@ def test_kpoint_energy_and_force_bias_match_the_oracle(api, nk, m, nu, nd, xq):
     W = _walkers(T, nw, 0.2, seed=401)
     g = api.System.from_kpoint(ks)
     wk = api.Walkers(g, nw, W)
+    if kernel == "valu":
+        _pin_valu(wk)
     el, parts, vb, _ = wk.energy(want_vbar=True)
     el, parts, vb = to_np(el), to_np(parts), to_np(vb)
     for i in range(nw):
@@ -77,6 +89,26 @@ def test_kpoint_walk_matches_the_oracle(api):
         print("kpoint walk", k, f"{err:.2e}")
         assert err < 1e-10, k
     assert rel_vec(to_np(out["emix"]), o["emix"]) < 1e-10
+
+
+def test_kpoint_trace_kernels_agree_and_repeat(api):
+    """The MFMA and VALU trace kernels sum in different orders: their energies
+    agree to rounding, and each is bitwise repeatable."""
+    ks = synth.make_kpoint_system(4, 8, 3, 2, 10, seed=430)
+    ks.Lk = ks.Lk * 3.0
+    _, _, T = _dense(ks)
+    W = _walkers(T, 7, 0.2, seed=431)
+    g = api.System.from_kpoint(ks)
+    res = {}
+    for kernel in ("mfma", "valu"):
+        wk = api.Walkers(g, 7, W)
+        if kernel == "valu":
+            _pin_valu(wk)
+        a = to_np(wk.energy()[1])
+        b = to_np(wk.energy()[1])
+        assert np.array_equal(a, b), kernel
+        res[kernel] = a
+    assert np.max(np.abs(res["mfma"] - res["valu"])) < 1e-12 * np.max(np.abs(res["valu"]))
 
 
 def test_kpoint_setup_errors(api):

@@ -144,14 +144,15 @@ def _kp_lds(nk, m, ns, xq):
     return (m * N + M * ns + npar * N * 3 + xq * 3 + npar * ns * m) * 16
 
 
-@pytest.mark.parametrize("case", ["kp_m192", "lds96k"])
-def test_kpoint_six_electrons_sampled(api, case):
-    """Six electrons per k-point and spin (the 6-electron trace kernel):
-    kp_m192 is the k-point workload itself (8 k-points on a ring, m=24, 96
-    vectors per Q: M=192, N=48+48, 1536 fields, 63 KB of LDS) at 256 walkers,
-    one sampled walker; lds96k (4 k-points, m=48, 32 vectors per Q) needs 96 KB
-    of LDS, the launch above the default 64 KB limit. 2 steps with QR after
-    each (N = 48 and 24: the <256,4,4> and <256,2,2> QR blocks)."""
+@pytest.mark.parametrize("case,kernel", [("kp_m192", "mfma"), ("kp_m192", "valu"), ("lds96k", "valu")])
+def test_kpoint_six_electrons_sampled(api, case, kernel):
+    """Six electrons per k-point and spin: kp_m192 is the k-point workload
+    itself (8 k-points on a ring, m=24, 96 vectors per Q: M=192, N=48+48, 1536
+    fields) at 256 walkers, one sampled walker, on both trace kernels (the
+    MFMA one: two row blocks per workgroup, 8-vector blocks, 150 KB of LDS);
+    lds96k (4 k-points, m=48, 32 vectors per Q: m > 32 takes the VALU kernel)
+    needs 96 KB of LDS, the launch above the default 64 KB limit. 2 steps with
+    QR after each (N = 48 and 24: the <256,4,4> and <256,2,2> QR blocks)."""
     if case == "kp_m192":
         cfg = synth.WORKLOADS["kp_m192"]
         nk, m, nu, nd, xq, nw, seed = cfg["nk"], cfg["m"], cfg["n_up"], cfg["n_dn"], cfg["xq"], cfg["n_walkers"], 7
@@ -160,7 +161,7 @@ def test_kpoint_six_electrons_sampled(api, case):
         nk, m, nu, nd, xq, nw, seed = 4, 48, 6, 6, 32, 16, 17
         smp = np.array([0, 15])
     lds = max(_kp_lds(nk, m, nu, xq), _kp_lds(nk, m, nd, xq))
-    print(case, "trace-kernel LDS bytes", lds)
+    print(case, kernel, "VALU trace-kernel LDS bytes", lds)
     if case == "lds96k":
         assert lds > 64 * 1024
     ks = synth.make_kpoint_system(nk, m, nu, nd, xq, seed=seed)
@@ -174,6 +175,9 @@ def test_kpoint_six_electrons_sampled(api, case):
     fields = rng.standard_normal((steps, nw, 2 * L.shape[0]))
     g = api.System.from_kpoint(ks)
     wk = api.Walkers(g, nw, W0, w0)
+    if kernel == "valu":
+        wk.set_exchange_variant(0, 1)
+        wk.set_exchange_variant(1, 1)
     out = wk.step(steps, dt, fields=fields, qr_every=1, outputs=("eloc", "weights", "ratio"))
     torch.cuda.synchronize()
     o = kpoint.run(h, L, T, nk * nu, nk * nd, W0[smp], w0[smp], fields[:, smp], dt, qr_every=1)
