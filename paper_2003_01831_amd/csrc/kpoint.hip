@@ -541,6 +541,116 @@ __device__ inline void kp_load_row(kp_g2* blk, int row, float rns, int ns, int n
   for (int s = 0; s < KS; ++s) v[s] = p[min(4 * s + lq, m - 1)];
 }
 
+// operands of a unit. Step 1 (Omega'^T), unit u = (k', chunk of KT column
+// tiles): the KT Ltd row tiles of the vector block starting at n0 (R rows).
+// Step 2 (Omega^T), unit u = (j, column tile, chunk): one Lt row tile of the
+// block (Q, k2), whose (n, 0) rows start at blk2.
+struct KpUnitGeo {
+  int nk, xq, nkn, aoff, m, ns, nch1, nrt, nch2;
+  float rns, rnch1, rnch2, rnrt2;
+};
+template <int KS>
+__device__ inline void kp_load_u1(kp_g2* Ltd, int Q, const KpUnitGeo& g, int n0, int R, int u, int lr, int lq,
+                                  kv2 (&v)[KT][KS]) {
+  const int kp = kp_div(u, g.rnch1), ch = u - kp * g.nch1;
+  kp_g2* blk = Ltd + ((((long)Q * g.nk + kp) * g.xq + n0) * g.nkn + g.aoff) * g.m;
+#pragma unroll
+  for (int c = 0; c < KT; ++c)
+    kp_load_row<KS>(blk, min(16 * (KT * ch + c) + lr, R - 1), g.rns, g.ns, g.nkn, g.m, lq, v[c]);
+}
+template <int KS>
+__device__ inline void kp_load_u2(kp_g2* Lt, int Q, int k2, const KpUnitGeo& g, int n0, int R, int u, int lr, int lq,
+                                  kv2 (&v)[KS]) {
+  const int j = kp_div(u, g.rnrt2), ct = kp_div(u - j * g.nrt * g.nch2, g.rnch2);
+  kp_g2* blk = Lt + ((((long)Q * g.nk + k2) * g.xq + n0) * g.nkn + g.aoff) * g.m;
+  kp_load_row<KS>(blk, min(16 * ct + lr, R - 1), g.rns, g.ns, g.nkn, g.m, lq, v);
+}
+
+// The LDS side of the kernel a unit needs
+struct KpLdsGeo {
+  kp_l2 *thA, *thB, *OP, *rp, *tp;
+  long OPV;
+  int M4, N, GS, GSP, R16, nch2, nrt, ns, grp, G;
+  float rns, rnch2, rnrt2;
+};
+
+// step-1 unit u = (k', chunk ch of KT column tiles (n, b)): Omega'^T tiles
+// into OP; rb = the Theta row block k' + Q
+template <int KS>
+__device__ inline void kp_unit1(const KpLdsGeo& L, const kv2 (&op)[KT][KS], int kp, int ch, int rb, int R, int lr,
+                                int lq, int lrB) {
+  kp_l2* bsrc = L.thB + (long)rb * L.M4 * L.GS + lrB;
+  kd4 cr[KT], ci[KT];
+#pragma unroll
+  for (int c = 0; c < KT; ++c) cr[c] = ci[c] = kd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const kv2 av = bsrc[(4 * s + lq) * L.GS];
+    kv2 bv[KT];
+#pragma unroll
+    for (int c = 0; c < KT; ++c) bv[c] = op[c][s];
+    kp_cmma_kt<true>(cr, ci, av, bv);
+  }
+  // lane: column (n, b) = 16 ct + lr, rows (j, a) = lq + 4 i
+#pragma unroll
+  for (int c = 0; c < KT; ++c) {
+    const int col = 16 * (KT * ch + c) + lr;
+    if (col < R) {
+      const int nl = kp_div(col, L.rns), b = col - nl * L.ns;
+      kp_l2* o = L.OP + nl * L.OPV + ((long)kp * L.ns + b) * L.GSP;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (lq + 4 * i < L.GS) o[lq + 4 * i] = kv2{cr[c][i], ci[c][i]};
+    }
+  }
+}
+
+// step-2 unit u = (j, column tile ct (n, a), chunk ch of KT row tiles c):
+// Omega^T tiles paired with Omega' (rp: the lane group's share of tr(Omega
+// Omega'), tp: the diagonal of Omega_j)
+template <int KS>
+__device__ inline void kp_unit2(const KpLdsGeo& L, const kv2 (&op)[KS], int u, int R, int lr, int lq) {
+  const int j = kp_div(u, L.rnrt2), rem = u - j * L.nrt * L.nch2, ct = kp_div(rem, L.rnch2), ch = rem - ct * L.nch2;
+  const int k1 = L.grp * L.G + j, N = L.N, ns = L.ns;
+  kp_l2* asrc = L.thA + (long)j * L.M4 * N;
+  int arow[KT];
+#pragma unroll
+  for (int c = 0; c < KT; ++c) arow[c] = min(16 * (KT * ch + c) + lr, N - 1);   // rows c past N: dropped
+  kd4 cr[KT], ci[KT];
+#pragma unroll
+  for (int c = 0; c < KT; ++c) cr[c] = ci[c] = kd4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    kv2 av[KT];
+#pragma unroll
+    for (int c = 0; c < KT; ++c) av[c] = asrc[(long)(4 * s + lq) * N + arow[c]];
+    kp_cmma_kt<false>(cr, ci, op[s], av);
+  }
+  // lane: column (n, a) = 16 ct + lr, rows c = 16 (KT ch + c) + lq + 4 i
+  const int col = 16 * ct + lr, nl = kp_div(col, L.rns), aa = col - nl * ns;
+  const bool cok = col < R;
+  kp_l2* opn = L.OP + nl * L.OPV + j * ns + aa;
+  double sr = 0.0, si = 0.0;
+#pragma unroll
+  for (int c = 0; c < KT; ++c)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rc = 16 * (KT * ch + c) + lq + 4 * i;
+      if (cok && rc < N) {
+        const int kpc = kp_div(rc, L.rns), bc = rc - kpc * ns;
+        const kv2 o = opn[((long)kpc * ns + bc) * L.GSP];
+        sr += cr[c][i] * o.x - ci[c][i] * o.y;
+        si += cr[c][i] * o.y + ci[c][i] * o.x;
+        if (kpc == k1 && bc == aa) L.tp[(long)j * L.R16 + col] = kv2{cr[c][i], ci[c][i]};
+      }
+    }
+  sr += __shfl_xor(sr, 16);
+  si += __shfl_xor(si, 16);
+  sr += __shfl_xor(sr, 32);
+  si += __shfl_xor(si, 32);
+  if (lq == 0) L.rp[((long)j * L.nch2 + ch) * L.R16 + col] = kv2{sr, si};
+}
+
 template <int KS>
 __global__ __launch_bounds__(256) void kp_trace_mfma_kernel(KpTraceArgs a, int sp, int G, int VB) {
   constexpr int M4 = 4 * KS;
@@ -588,118 +698,50 @@ __global__ __launch_bounds__(256) void kp_trace_mfma_kernel(KpTraceArgs a, int s
   double2* out = a.part + ((((long)w * 2 + sp) * nk + Q) * xq) * nk * 3;
   const int lrB = min(lr, GS - 1);   // A rows (j, a) past G ns: clamped reads, outputs dropped
 
+  KpUnitGeo ug;
+  ug.nk = nk; ug.xq = xq; ug.nkn = nkn; ug.aoff = aoff; ug.m = m; ug.ns = ns;
+  ug.nch1 = nch1; ug.nrt = nrt; ug.nch2 = nch2;
+  ug.rns = rns; ug.rnch1 = rnch1; ug.rnch2 = rnch2; ug.rnrt2 = rnrt2;
+  KpLdsGeo L;
+  L.thA = thA; L.thB = thB; L.OP = OP; L.rp = rp; L.tp = tp; L.OPV = OPV;
+  L.M4 = M4; L.N = N; L.GS = GS; L.GSP = GSP; L.R16 = R16; L.nch2 = nch2; L.nrt = nrt; L.ns = ns;
+  L.grp = grp; L.G = G; L.rns = rns; L.rnch2 = rnch2; L.rnrt2 = rnrt2;
+  kp_g2* Ltd = (kp_g2*)a.Ltd;
+  kp_g2* Lt = (kp_g2*)a.Lt;
+  const int nu1 = nk * nch1, nu2 = G * nrt * nch2;
+  // Operands come from global memory one unit ahead, in two register sets
+  // used in turn (a copy between them would wait for the loads it copies).
+  // Every unit issues the same loads, the last one of a wave re-reading its
+  // own rows, so the wait before each multiply covers exactly the loads of
+  // the unit it multiplies on every path.
+  kv2 o1a[KT][KS], o1b[KT][KS], o2a[KS], o2b[KS];
+
   for (int n0 = 0; n0 < xq; n0 += VB) {
     const int vb = min(VB, xq - n0), R = vb * ns;
-    // step 1: Omega'^T tiles, unit u = (k', chunk of KT column tiles (n, b))
-    {
-      const int nu = nk * nch1;
-      kv2 cur[KT][KS], nxt[KT][KS];
-      int u = wave;
-      if (u < nu) {
-        const int kp = kp_div(u, rnch1), ch = u - kp * nch1;
-        kp_g2* blk = (kp_g2*)a.Ltd + ((((long)Q * nk + kp) * xq + n0) * nkn + aoff) * m;
-#pragma unroll
-        for (int c = 0; c < KT; ++c) kp_load_row<KS>(blk, min(16 * (KT * ch + c) + lr, R - 1), rns, ns, nkn, m, lq, cur[c]);
+    // step 1: unit u in set A, u + 4 in set B, ...
+    if (wave < nu1) kp_load_u1<KS>(Ltd, Q, ug, n0, R, wave, lr, lq, o1a);
+    for (int u = wave; u < nu1; u += 8) {
+      kp_load_u1<KS>(Ltd, Q, ug, n0, R, u + 4 < nu1 ? u + 4 : u, lr, lq, o1b);
+      {
+        const int kp = kp_div(u, rnch1);
+        kp_unit1<KS>(L, o1a, kp, u - kp * nch1, kqs[kp], R, lr, lq, lrB);
       }
-      for (; u < nu; u += 4) {
-        if (u + 4 < nu) {
-          const int kp = kp_div(u + 4, rnch1), ch = u + 4 - kp * nch1;
-          kp_g2* blk = (kp_g2*)a.Ltd + ((((long)Q * nk + kp) * xq + n0) * nkn + aoff) * m;
-#pragma unroll
-          for (int c = 0; c < KT; ++c)
-            kp_load_row<KS>(blk, min(16 * (KT * ch + c) + lr, R - 1), rns, ns, nkn, m, lq, nxt[c]);
-        }
-        const int kp = kp_div(u, rnch1), ch = u - kp * nch1;
-        kp_l2* bsrc = thB + (long)kqs[kp] * M4 * GS + lrB;
-        kd4 cr[KT], ci[KT];
-#pragma unroll
-        for (int c = 0; c < KT; ++c) cr[c] = ci[c] = kd4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const kv2 av = bsrc[(4 * s + lq) * GS];
-          kv2 bv[KT];
-#pragma unroll
-          for (int c = 0; c < KT; ++c) bv[c] = cur[c][s];
-          kp_cmma_kt<true>(cr, ci, av, bv);
-        }
-        // lane: column (n, b) = 16 ct + lr, rows (j, a) = lq + 4 i
-#pragma unroll
-        for (int c = 0; c < KT; ++c) {
-          const int col = 16 * (KT * ch + c) + lr;
-          if (col < R) {
-            const int nl = kp_div(col, rns), b = col - nl * ns;
-            kp_l2* o = OP + nl * OPV + ((long)kp * ns + b) * GSP;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (lq + 4 * i < GS) o[lq + 4 * i] = kv2{cr[c][i], ci[c][i]};
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < KT; ++c)
-#pragma unroll
-          for (int s = 0; s < KS; ++s) cur[c][s] = nxt[c][s];
-      }
+      if (u + 4 >= nu1) break;
+      kp_load_u1<KS>(Ltd, Q, ug, n0, R, u + 8 < nu1 ? u + 8 : u + 4, lr, lq, o1a);
+      const int kp = kp_div(u + 4, rnch1);
+      kp_unit1<KS>(L, o1b, kp, u + 4 - kp * nch1, kqs[kp], R, lr, lq, lrB);
     }
     __syncthreads();
-    // step 2: Omega^T tiles, unit u = (j, column tile (n, a), chunk of KT row
-    // tiles c), paired with Omega' in the epilogue
-    {
-      const int nu = G * nrt * nch2;
-      kv2 cur[KS], nxt[KS];
-      int u = wave;
-      if (u < nu) {
-        const int j = kp_div(u, rnrt2), ct = kp_div(u - j * nrt * nch2, rnch2);
-        kp_g2* blk = (kp_g2*)a.Lt + ((((long)Q * nk + k2s[j]) * xq + n0) * nkn + aoff) * m;
-        kp_load_row<KS>(blk, min(16 * ct + lr, R - 1), rns, ns, nkn, m, lq, cur);
-      }
-      for (; u < nu; u += 4) {
-        if (u + 4 < nu) {
-          const int j = kp_div(u + 4, rnrt2), ct = kp_div(u + 4 - j * nrt * nch2, rnch2);
-          kp_g2* blk = (kp_g2*)a.Lt + ((((long)Q * nk + k2s[j]) * xq + n0) * nkn + aoff) * m;
-          kp_load_row<KS>(blk, min(16 * ct + lr, R - 1), rns, ns, nkn, m, lq, nxt);
-        }
-        const int j = kp_div(u, rnrt2), rem = u - j * nrt * nch2, ct = kp_div(rem, rnch2), ch = rem - ct * nch2;
-        const int k1 = grp * G + j;
-        kp_l2* asrc = thA + (long)j * M4 * N;
-        int arow[KT];
-#pragma unroll
-        for (int c = 0; c < KT; ++c) arow[c] = min(16 * (KT * ch + c) + lr, N - 1);   // rows c past N: dropped
-        kd4 cr[KT], ci[KT];
-#pragma unroll
-        for (int c = 0; c < KT; ++c) cr[c] = ci[c] = kd4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          kv2 av[KT];
-#pragma unroll
-          for (int c = 0; c < KT; ++c) av[c] = asrc[(long)(4 * s + lq) * N + arow[c]];
-          kp_cmma_kt<false>(cr, ci, cur[s], av);
-        }
-        // lane: column (n, a) = 16 ct + lr, rows c = 16 (KT ch + c) + lq + 4 i
-        const int col = 16 * ct + lr, nl = kp_div(col, rns), aa = col - nl * ns;
-        const bool cok = col < R;
-        kp_l2* opn = OP + nl * OPV + j * ns + aa;
-        double sr = 0.0, si = 0.0;
-#pragma unroll
-        for (int c = 0; c < KT; ++c)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int rc = 16 * (KT * ch + c) + lq + 4 * i;
-            if (cok && rc < N) {
-              const int kpc = kp_div(rc, rns), bc = rc - kpc * ns;
-              const kv2 o = opn[((long)kpc * ns + bc) * GSP];
-              sr += cr[c][i] * o.x - ci[c][i] * o.y;
-              si += cr[c][i] * o.y + ci[c][i] * o.x;
-              if (kpc == k1 && bc == aa) tp[(long)j * R16 + col] = kv2{cr[c][i], ci[c][i]};
-            }
-          }
-        sr += __shfl_xor(sr, 16);
-        si += __shfl_xor(si, 16);
-        sr += __shfl_xor(sr, 32);
-        si += __shfl_xor(si, 32);
-        if (lq == 0) rp[((long)j * nch2 + ch) * R16 + col] = kv2{sr, si};
-#pragma unroll
-        for (int s = 0; s < KS; ++s) cur[s] = nxt[s];
-      }
+    // step 2: the same with the Omega units
+    if (wave < nu2) kp_load_u2<KS>(Lt, Q, k2s[kp_div(wave, rnrt2)], ug, n0, R, wave, lr, lq, o2a);
+    for (int u = wave; u < nu2; u += 8) {
+      const int ub = u + 4 < nu2 ? u + 4 : u;
+      kp_load_u2<KS>(Lt, Q, k2s[kp_div(ub, rnrt2)], ug, n0, R, ub, lr, lq, o2b);
+      kp_unit2<KS>(L, o2a, u, R, lr, lq);
+      if (u + 4 >= nu2) break;
+      const int ua = u + 8 < nu2 ? u + 8 : u + 4;
+      kp_load_u2<KS>(Lt, Q, k2s[kp_div(ua, rnrt2)], ug, n0, R, ua, lr, lq, o2a);
+      kp_unit2<KS>(L, o2b, u + 4, R, lr, lq);
     }
     __syncthreads();
     // step 3: per (vector, j): tr(Omega Omega'), tr Omega, tr Omega'
