@@ -140,9 +140,10 @@ typedef enum {
 
 /* Sets the exchange form (AFQ_EXCH_*). Builds the four-index tensor at once
  * when it will be used, or frees it when it will not (synchronises; may
- * allocate N^2 M^2 * 4 bytes per distinct spin block plus an FP64 set-up
- * transient of N^2 M^2 * 8 bytes in split-BF16x3 mode, N^2 M^2 * 8 bytes in
- * FP64 mode; a precision switch rebuilds it). A batch holding the system captures its
+ * allocate about N^2 M^2 * 2 bytes per distinct spin block in split-BF16x3
+ * mode, its upper block triangle, and (1/2 + 1/16) N^2 M^2 * 8 bytes in FP64
+ * mode, plus FP64 set-up transients of (N M X + M N M) * 8 bytes; a precision
+ * switch rebuilds it). A batch holding the system captures its
  * step again on its next call. AFQ_E_INVALID for an unknown form,
  * AFQ_E_NOMEM when the tensor does not fit. */
 int afq_system_set_exchange_form(afq_system s, int form);
@@ -373,12 +374,27 @@ int afq_fields_generate(uint64_t seed, uint32_t sys_id, uint64_t step0, int n_st
  * each launch variant (waves per workgroup, accumulator budget) of both spins
  * on these walkers' own shapes with HIP events, `reps` launches each, and keeps
  * the fastest for this walker set and for later walker sets of the same shape
- * (a process-wide table). Recomputes Theta from the current walkers and writes
+ * (a process-wide table). In split-BF16x3 mode it also times one step's
+ * propagator products (a B1 product and the Horner chain) with every tile of
+ * afq_system_set_propagator_tile and pins the fastest for the system. Recomputes Theta from the current walkers and writes
  * only per-step scratch: W, weights and counters are unchanged. Synchronises
  * the system stream. choice_out (host, 2 ints, may be NULL) receives the
  * variant per spin, -1 where the shape has a single kernel (split-BF16x3 with
  * 65..100 electrons per spin). */
 int afq_autotune(afq_system s, afq_walkers w, int reps, int *choice_out);
+/* Tile of the split-BF16x3 propagator products (the Taylor products of
+ * A = sum_n c_n L^n in Horner form and the two B1 products, Section
+ * "Auxiliary Field Quantum Monte Carlo" and Table tab:afqmc_comp): 0 = 224 x
+ * 160 (walker-term rows x real-form columns per workgroup), 1 = 128 x 128,
+ * 2 = 64 x 64; -1 = chosen per system by the least padded work (a larger tile
+ * winning within 10%). The walkers' packed operands follow the tile: every
+ * walker set clears them for the new layout at its next call, and a batch
+ * holding the system captures its step again (synchronises). AFQ_E_INVALID
+ * outside -1..2. The results do not depend on the tile beyond rounding of the
+ * FP32 accumulation order. */
+int afq_system_set_propagator_tile(afq_system s, int tile);
+/* The tile the next step uses (0..2), into *tile (host int). */
+int afq_system_propagator_tile(afq_system s, int* tile);
 /* Pins the exchange launch variant of one spin for this walker set (0..2, or
  * -1 to return to the tuned/default choice), e.g. to replay a tuning table
  * saved from an earlier process. A variant that does not fit the shape makes

@@ -46,6 +46,8 @@ SIGNATURES = {
     "afq_energy_backward": (_i, [_vp, _vp, _d, _vp, _vp, _vp]),
     "afq_fields_generate": (_i, [_u64, _u32, _u64, _i, _i, _i, _vp, _vp]),
     "afq_autotune": (_i, [_vp, _vp, _i, _vp]),
+    "afq_system_set_propagator_tile": (_i, [_vp, _i]),
+    "afq_system_propagator_tile": (_i, [_vp, _vp]),
     "afq_exchange_variant": (_i, [_vp, _i, _i]),
     "afq_bp_begin": (_i, [_vp, _i]),
     "afq_bp_rdm1": (_i, [_vp, _i, _vp, C.POINTER(_d)]),

@@ -114,6 +114,17 @@ class System:
         tensor; split-BF16x3 mode with a real trial only)."""
         check(self.lib.afq_system_set_exchange_form(self.handle, EXCHANGE_FORM[form]))
 
+    def set_propagator_tile(self, tile):
+        """Tile of the split-BF16x3 propagator products: 0 (224 x 160), 1 (128 x
+        128), 2 (64 x 64), or -1 for the per-system choice by padded work."""
+        check(self.lib.afq_system_set_propagator_tile(self.handle, int(tile)))
+
+    def propagator_tile(self):
+        """The propagator-product tile the next step uses (0..2)."""
+        t = C.c_int()
+        check(self.lib.afq_system_propagator_tile(self.handle, C.byref(t)))
+        return int(t.value)
+
     def exchange_form(self):
         """(form the next step uses, device bytes of the four-index tensor)."""
         f, b = C.c_int(), C.c_uint64()
@@ -233,7 +244,9 @@ class Walkers:
         return int(na.value), int(nk.value)
 
     def autotune(self, reps=3):
-        """Pick the fastest exchange-kernel variant for these walkers; returns the choice per spin."""
+        """Pick the fastest exchange-kernel variant for these walkers (returned
+        per spin) and, in split-BF16x3 mode, the fastest propagator-product
+        tile for the system (System.propagator_tile)."""
         ch = (C.c_int * 2)()
         check(self.lib.afq_autotune(self.sys.handle, self.handle, int(reps), C.cast(ch, C.c_void_p)))
         return int(ch[0]), int(ch[1])

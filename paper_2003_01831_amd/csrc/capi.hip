@@ -68,6 +68,18 @@ int afq_system_set_exchange_form(afq_system s, int form) {
   })
 }
 
+int afq_system_set_propagator_tile(afq_system s, int tile) {
+  AFQ_CHECK(s, AFQ_E_INVALID, "afq_system_set_propagator_tile: system is NULL");
+  AFQ_CHECK(tile >= -1 && tile < b3_num_tiles(), AFQ_E_INVALID, "afq_system_set_propagator_tile: tile must be -1..2");
+  AFQ_GUARD(AFQ_RET(check_device(s)); return system_set_b3_tile(s, tile);)
+}
+
+int afq_system_propagator_tile(afq_system s, int* tile) {
+  AFQ_CHECK(s && tile, AFQ_E_INVALID, "afq_system_propagator_tile: NULL argument");
+  *tile = b3_tile_of(s);
+  return AFQ_OK;
+}
+
 int afq_system_exchange_form(afq_system s, int* in_use, uint64_t* tensor_bytes) {
   AFQ_CHECK(s && in_use, AFQ_E_INVALID, "afq_system_exchange_form: NULL argument");
   *in_use = s->eri_ready ? AFQ_EXCH_FOUR_INDEX : AFQ_EXCH_CHOLESKY;
@@ -266,6 +278,7 @@ int afq_autotune(afq_system s, afq_walkers w, int reps, int* choice_out) {
   AFQ_CHECK(w->sys == s, AFQ_E_STATE, "afq_autotune: walkers belong to another system");
   AFQ_CHECK(reps >= 1 && reps <= 1000, AFQ_E_INVALID, "afq_autotune: reps must be in 1..1000");
   AFQ_GUARD(AFQ_RET(check_device(s)); int c[2] = {-1, -1}; AFQ_RET(exchange_autotune(s, w, reps, c));
+            int tile = -1; AFQ_RET(r32_autotune(s, w, reps, &tile));
             if (choice_out) { choice_out[0] = c[0]; choice_out[1] = c[1]; } return AFQ_OK;)
 }
 

@@ -124,6 +124,9 @@ struct afq_system_s {
   double b1x_dt = -1.0;
   DevBuf b1x3;                 // split-BF16x3 mode: the same as BF16 hi / lo planes
   double b1x3_dt = -1.0;
+  int b1x3_tile = -1;          // the product tile its rows were padded for
+  int b3_tile = -1;            // split-BF16x3 Taylor and B1 product tile (index into the tile table; -1: the
+                               // padded-work model chooses; afq_autotune or afq_system_set_propagator_tile pin it)
   DevBuf lt32[2];              // split-BF16x3, real trial: Lt rows n of each spin, FP32 packed [J / 16][n][J % 16]
   bool lt_share = false;       // the two trial blocks are equal: lt32[1] is not built, the force bias contracts
                                // Theta_up + Theta_dn with lt32[0]
@@ -248,7 +251,8 @@ struct afq_walkers_s {
   DevBuf r32_coef, r32_theta, r32_part;
   DevBuf r32_x;                // real form of A_w, packed for the Taylor products (FP32, or BF16 hi / lo planes)
   DevBuf r32_y[3];             // packed Taylor terms: V (FP32), then two alternating Horner terms
-  int r32_layout = 0;          // layout r32_x / r32_y[1..2] were last cleared for: 1 FP32, 2 split BF16
+  int r32_layout = 0;          // layout r32_x / r32_y[1..2] were last cleared for: 1 FP32, 2 + t split BF16
+                               // with product tile t
   DevBuf r32_b1w;              // walker rows (n, Re|Im) packed for the B1 products
   // four-index exchange scratch
   DevBuf eri_theta;            // packed Theta-hat hi / lo planes of one spin
@@ -358,6 +362,10 @@ int kp_abuild(afq_system s, afq_walkers w, const double2* coef, hipStream_t st);
 int r32_prepare(afq_system s);                     // packed L (reduced modes) and Lt (split-BF16x3, real trial)
 int r32_alloc_scratch(afq_system s, afq_walkers w);
 bool r32_coulomb_used(afq_system s);
+int b3_tile_of(afq_system s);       // the split-BF16x3 Taylor / B1 product tile a system uses
+int b3_num_tiles();
+int system_set_b3_tile(afq_system s, int tile);
+int r32_autotune(afq_system s, afq_walkers w, int reps, int* tile_out);
 bool r32_taylor_used(afq_system s);
 // A_w = sum_n coef[w][n] L^n, written in packed real form to w->r32_x
 int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st);

@@ -902,29 +902,76 @@ TriCols tri_cols(afq_system s) {
   return t;
 }
 
-// packed real form of A_w (rows 2M, contraction 2M) and packed terms (rows n_tot)
+bool taylor_b3(afq_system s) { return s->prec == AFQ_BF16X3; }
+
+// Tiles of the split-BF16x3 Taylor and B1 products (TA x TB MFMA tiles of
+// 16 x 16 per wave, 2 x 2 waves: 32 TA term rows x 32 TB output columns per
+// workgroup). The large tile suits the M = 400 walker (n_tot = 200 columns,
+// 2M = 800 real-form rows: 89% of its products useful); small systems waste
+// most of it on padding (at M = 64, n_tot = 32: 11%), which the small tiles
+// avoid at the price of more workgroups and operand reloads.
+struct B3Tile {
+  int ta, tb;
+};
+constexpr B3Tile kB3Tiles[] = {{7, 5}, {4, 4}, {2, 2}};
+constexpr int kNumB3Tiles = 3;
+
+// padded MFMA work of one step's products with tile t: six Horner products
+// (n_tot term rows, 2M columns, contraction 2M) and two B1 products (2 n_tot
+// walker rows, M columns, contraction M)
+double b3_tile_work(afq_system s, int t) {
+  const long ra = 32L * kB3Tiles[t].ta, rb = 32L * kB3Tiles[t].tb, M = s->M, n = s->ntot;
+  return 6.0 * pad_to(n, ra) * pad_to(2 * M, rb) * pad_to(2 * M, 32) + 2.0 * pad_to(2 * n, ra) * pad_to(M, rb) * pad_to(M, 32);
+}
+
+}  // namespace
+
+// the tile a system uses: its pinned one, else the one with the least padded
+// work, a larger tile winning when it needs at most 10% more (fewer
+// workgroups, each reloading its operands less often)
+int b3_tile_of(afq_system s) {
+  if (s->b3_tile >= 0) return s->b3_tile;
+  int best = 0;
+  double best_w = b3_tile_work(s, 0);
+  for (int t = 1; t < kNumB3Tiles; ++t) {
+    const double w = b3_tile_work(s, t);
+    if (w * 1.1 < best_w) {
+      best = t;
+      best_w = w;
+    }
+  }
+  return best;
+}
+int b3_num_tiles() { return kNumB3Tiles; }
+
+namespace {
+
+// packed real form of A_w (rows 2M, contraction 2M) and packed terms (rows n_tot;
+// in split-BF16x3 mode padded to that mode's product tile, for V in FP32)
 struct TaylorShape {
   long x_rows, y_rows, kchunk, x_wstride, y_wstride;   // strides in floats
 };
 TaylorShape taylor_shape(afq_system s) {
   TaylorShape t;
   t.x_rows = pad_to(2L * s->M, GeoTY::RB);
-  t.y_rows = pad_to(s->ntot, GeoTY::RA);
+  t.y_rows = pad_to(s->ntot, taylor_b3(s) ? 32L * kB3Tiles[b3_tile_of(s)].ta : (long)GeoTY::RA);
   t.kchunk = pad_to(2L * s->M, RK) / RK;
   t.x_wstride = t.x_rows * t.kchunk * RK;
   t.y_wstride = t.y_rows * t.kchunk * RK;
   return t;
 }
 
-// the same operands as BF16 hi / lo planes of 32-element chunks (bytes)
+// the same operands as BF16 hi / lo planes of 32-element chunks (bytes),
+// rows padded to the system's product tile
 struct TaylorB3Shape {
   long x_rows, y_rows, kchunk, x_plane, x_wstride, y_plane, y_wstride;
+  int tile;
 };
-constexpr int B3_TA = 7, B3_TB = 5;   // 224 x 160 tiles, as the FP32 Taylor products
 TaylorB3Shape taylor_b3_shape(afq_system s) {
   TaylorB3Shape t;
-  t.x_rows = pad_to(2L * s->M, 32 * B3_TB);
-  t.y_rows = pad_to(s->ntot, 32 * B3_TA);
+  t.tile = b3_tile_of(s);
+  t.x_rows = pad_to(2L * s->M, 32L * kB3Tiles[t.tile].tb);
+  t.y_rows = pad_to(s->ntot, 32L * kB3Tiles[t.tile].ta);
   t.kchunk = pad_to(2L * s->M, ring::KC) / ring::KC;
   t.x_plane = t.kchunk * t.x_rows * ROWB;
   t.y_plane = t.kchunk * t.y_rows * ROWB;
@@ -932,16 +979,16 @@ TaylorB3Shape taylor_b3_shape(afq_system s) {
   t.y_wstride = 2 * t.y_plane;
   return t;
 }
-bool taylor_b3(afq_system s) { return s->prec == AFQ_BF16X3; }
-
 // the B1 products' operands as BF16 hi / lo planes (bytes)
 struct B1B3Shape {
   long a_rows, b_rows, kchunk, a_plane, a_wstride, b_plane;
+  int tile;
 };
 B1B3Shape b1_b3_shape(afq_system s) {
   B1B3Shape b;
-  b.a_rows = pad_to(2L * s->ntot, 32 * B3_TA);
-  b.b_rows = pad_to(s->M, 32 * B3_TB);
+  b.tile = b3_tile_of(s);
+  b.a_rows = pad_to(2L * s->ntot, 32L * kB3Tiles[b.tile].ta);
+  b.b_rows = pad_to(s->M, 32L * kB3Tiles[b.tile].tb);
   b.kchunk = pad_to(s->M, ring::KC) / ring::KC;
   b.a_plane = b.kchunk * b.a_rows * ROWB;
   b.a_wstride = 2 * b.a_plane;
@@ -966,8 +1013,21 @@ B1Shape b1_shape(afq_system s) {
 
 bool r32_coulomb_used(afq_system s) { return s->lt32[0].p != nullptr; }
 
+// one split-BF16x3 product launch with tile t
+template <int MODE>
+static int launch_b3(int t, const HornerB3Args& g, hipStream_t st) {
+  const long launch = ((long)g.grid + NXCD - 1) / NXCD * NXCD;
+  switch (t) {
+    case 0: hipLaunchKernelGGL((horner_bf3_kernel<7, 5, MODE>), dim3((unsigned)launch), dim3(256), 0, st, g); break;
+    case 1: hipLaunchKernelGGL((horner_bf3_kernel<4, 4, MODE>), dim3((unsigned)launch), dim3(256), 0, st, g); break;
+    case 2: hipLaunchKernelGGL((horner_bf3_kernel<2, 2, MODE>), dim3((unsigned)launch), dim3(256), 0, st, g); break;
+    default: AFQ_CHECK(false, AFQ_E_INVALID, "split-BF16x3 product: bad tile");
+  }
+  return hip_status(hipGetLastError(), "split-BF16x3 product");
+}
+
 int r32_prepare_b1(afq_system s) {
-  if (s->chol32t.p && s->B1.p && taylor_b3(s) && s->b1x3_dt != s->B1_dt) {
+  if (s->chol32t.p && s->B1.p && taylor_b3(s) && (s->b1x3_dt != s->B1_dt || s->b1x3_tile != b3_tile_of(s))) {
     const B1B3Shape b = b1_b3_shape(s);
     AFQ_RET(s->b1x3.alloc((size_t)2 * b.b_plane));
     hipLaunchKernelGGL(pack_b1_bf3_kernel, dim3(grid_of(b.kchunk * b.b_rows * 32)), dim3(256), 0, s->stream,
@@ -975,6 +1035,7 @@ int r32_prepare_b1(afq_system s) {
                        s->b1x3.as<unsigned short>());
     AFQ_TRY_HIP(hipGetLastError());
     s->b1x3_dt = s->B1_dt;
+    s->b1x3_tile = b.tile;
   }
   if (!s->chol32t.p || !s->B1.p || s->b1x_dt == s->B1_dt) return AFQ_OK;
   const B1Shape b = b1_shape(s);
@@ -991,7 +1052,7 @@ bool r32_b1_packs_terms(afq_system s) { return taylor_b3(s); }
 int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStream_t st, bool pack_terms) {
   if (taylor_b3(s)) {
     const B1B3Shape b = b1_b3_shape(s);
-    AFQ_CHECK(s->b1x3.p && s->b1x3_dt == s->B1_dt && w->r32_layout == 2 &&
+    AFQ_CHECK(s->b1x3.p && s->b1x3_dt == s->B1_dt && s->b1x3_tile == b.tile && w->r32_layout == 2 + b.tile &&
                   w->r32_b1w.bytes >= (size_t)w->nw * b.a_wstride,
               AFQ_E_STATE, "B1 product (split BF16): operands not prepared");
     hipLaunchKernelGGL(pack_walker_rows_bf3_kernel, dim3(ceil_div(s->ntot, 8), (unsigned)b.kchunk, w->nw), dim3(256),
@@ -1007,8 +1068,8 @@ int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStre
     g.a_wstride = b.a_wstride;
     g.b_wstride = 0;
     g.nchunk = (int)b.kchunk;
-    g.nblk_a = (int)(b.a_rows / (32 * B3_TA));
-    g.nblk_b = (int)(b.b_rows / (32 * B3_TB));
+    g.nblk_a = (int)(b.a_rows / (32 * kB3Tiles[b.tile].ta));
+    g.nblk_b = (int)(b.b_rows / (32 * kB3Tiles[b.tile].tb));
     g.nw = w->nw;
     const long grid = (long)g.nblk_a * g.nblk_b * w->nw;
     AFQ_CHECK(grid < (1L << 30), AFQ_E_INVALID, "B1 product (split BF16): too many workgroups");
@@ -1031,9 +1092,7 @@ int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStre
       g.vb_plane = t3.y_plane;
       g.vb_wstride = t3.y_wstride;
     }
-    const long launch = (grid + NXCD - 1) / NXCD * NXCD;
-    hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, B3_B1>), dim3((unsigned)launch), dim3(256), 0, st, g);
-    return hip_status(hipGetLastError(), "B1 product (split BF16)");
+    return launch_b3<B3_B1>(b.tile, g, st);
   }
   const B1Shape b = b1_shape(s);
   AFQ_CHECK(s->b1x.p && s->b1x_dt == s->B1_dt && w->r32_b1w.bytes >= (size_t)w->nw * b.a_wstride * sizeof(float),
@@ -1161,7 +1220,7 @@ int r32_alloc_scratch(afq_system s, afq_walkers w) {
                                              (size_t)b1_b3_shape(s).a_wstride) * w->nw, st));
   // the FP32 and the BF16 layouts put their zero padding in different places:
   // clear the buffers when the layout changes
-  const int layout = taylor_b3(s) ? 2 : 1;
+  const int layout = taylor_b3(s) ? 2 + b3_tile_of(s) : 1;
   if (w->r32_layout != layout) {
     AFQ_TRY_HIP(hipMemsetAsync(w->r32_x.p, 0, w->r32_x.bytes, st));
     for (int i = 1; i < 3; ++i) AFQ_TRY_HIP(hipMemsetAsync(w->r32_y[i].p, 0, w->r32_y[i].bytes, st));
@@ -1192,7 +1251,7 @@ int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st) {
     const TriCols tc = tri_cols(s);
     const TaylorB3Shape tb = taylor_b3_shape(s);
     const long aplane = (long)nchunk * rows * ROWB, bplane = (long)nchunk * tc.rows * ROWB;
-    AFQ_CHECK(s->chol3.p && s->chol3.bytes >= (size_t)2 * bplane && w->r32_layout == 2 &&
+    AFQ_CHECK(s->chol3.p && s->chol3.bytes >= (size_t)2 * bplane && w->r32_layout == 2 + tb.tile &&
                   w->r32_coef.bytes >= (size_t)2 * aplane && w->r32_x.bytes >= (size_t)w->nw * tb.x_wstride,
               AFQ_E_STATE, "propagator build (split BF16): operands not prepared");
     hipLaunchKernelGGL(pack_cplx_rows_bf3_kernel, dim3(grid_of((long)nchunk * rows * 32)), dim3(256), 0, st, coef,
@@ -1256,11 +1315,12 @@ int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st) {
 static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st, bool terms_packed) {
   const TaylorShape ts = taylor_shape(s);
   const TaylorB3Shape tb = taylor_b3_shape(s);
-  AFQ_CHECK(w->r32_layout == 2 && w->r32_x.bytes >= (size_t)w->nw * tb.x_wstride &&
+  AFQ_CHECK(w->r32_layout == 2 + tb.tile && w->r32_x.bytes >= (size_t)w->nw * tb.x_wstride &&
                 w->r32_y[0].bytes >= (size_t)w->nw * ts.y_wstride * sizeof(float) &&
                 w->r32_y[1].bytes >= (size_t)w->nw * tb.y_wstride && w->r32_y[2].bytes >= (size_t)w->nw * tb.y_wstride,
             AFQ_E_STATE, "Taylor propagator (split BF16): walker scratch not prepared");
-  AFQ_CHECK(ts.y_rows == tb.y_rows && tb.y_rows % (32 * B3_TA) == 0 && tb.x_rows % (32 * B3_TB) == 0, AFQ_E_INVALID,
+  const B3Tile tl = kB3Tiles[tb.tile];
+  AFQ_CHECK(ts.y_rows == tb.y_rows && tb.y_rows % (32 * tl.ta) == 0 && tb.x_rows % (32 * tl.tb) == 0, AFQ_E_INVALID,
             "Taylor propagator (split BF16): bad shape");
   if (order < 1) return AFQ_OK;
   // V in FP32 (added by every epilogue) and as BF16 planes (the first input),
@@ -1283,8 +1343,8 @@ static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st,
   g.a_wstride = tb.y_wstride;
   g.b_wstride = tb.x_wstride;
   g.nchunk = (int)tb.kchunk;
-  g.nblk_a = (int)(tb.y_rows / (32 * B3_TA));
-  g.nblk_b = (int)(tb.x_rows / (32 * B3_TB));
+  g.nblk_a = (int)(tb.y_rows / (32 * tl.ta));
+  g.nblk_b = (int)(tb.x_rows / (32 * tl.tb));
   g.nw = w->nw;
   const long grid = (long)g.nblk_a * g.nblk_b * w->nw;
   AFQ_CHECK(grid < (1L << 30), AFQ_E_INVALID, "Taylor propagator (split BF16): too many workgroups");
@@ -1295,18 +1355,14 @@ static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st,
   g.u = w->u.as<double2>();
   g.ntot = s->ntot;
   g.M = s->M;
-  const long launch = (grid + NXCD - 1) / NXCD * NXCD;
   const unsigned char* in = w->r32_y[2].as<unsigned char>();
   for (int j = order; j >= 1; --j) {
     unsigned char* out = w->r32_y[1 + (order - j) % 2].as<unsigned char>();
     g.a = in;
     g.yout = out;
     g.scale = 1.0f / (float)j;
-    if (j == 1)
-      hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, B3_HORNER_LAST>), dim3((unsigned)launch), dim3(256), 0, st, g);
-    else
-      hipLaunchKernelGGL((horner_bf3_kernel<B3_TA, B3_TB, B3_HORNER>), dim3((unsigned)launch), dim3(256), 0, st, g);
-    AFQ_RET(hip_status(hipGetLastError(), "Taylor propagator (split BF16)"));
+    if (j == 1) AFQ_RET(launch_b3<B3_HORNER_LAST>(tb.tile, g, st));
+    else AFQ_RET(launch_b3<B3_HORNER>(tb.tile, g, st));
     in = out;
   }
   return AFQ_OK;
@@ -1394,3 +1450,64 @@ int r32_coulomb(afq_system s, afq_walkers w, hipStream_t st) {
   }
   return AFQ_OK;
 }
+
+// Pins the split-BF16x3 product tile (-1: the padded-work model) and repacks
+// B1 - I for it; walker sets clear their packed operands for the new layout
+// at their next call, and captured batches capture again (version).
+int system_set_b3_tile(afq_system s, int tile) {
+  AFQ_CHECK(tile >= -1 && tile < kNumB3Tiles, AFQ_E_INVALID, "propagator tile must be -1.." + std::to_string(kNumB3Tiles - 1));
+  if (s->b3_tile == tile) return AFQ_OK;
+  s->b3_tile = tile;
+  if (s->B1.p) AFQ_RET(r32_prepare_b1(s));
+  AFQ_TRY_HIP(hipStreamSynchronize(s->stream));
+  ++s->version;
+  return AFQ_OK;
+}
+
+// Times one step's split-BF16x3 products (the first B1 product, which packs
+// the Taylor terms, and the order-6 Horner chain; the second B1 product is
+// the first's kind) with every tile on these walkers' own shapes, `reps`
+// times each with HIP events, and pins the fastest. Writes only per-step
+// scratch (U, the packed terms and operands); W is read.
+int r32_autotune(afq_system s, afq_walkers w, int reps, int* tile_out) {
+  *tile_out = -1;
+  if (!taylor_b3(s) || !s->chol32t.p || s->kp_nk > 0) return AFQ_OK;   // the ring products are not in use
+  hipStream_t st = s->stream;
+  if (!s->B1.p) AFQ_RET(system_prepare_dt(s, 0.01));   // any step size: only the timing matters
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  AFQ_TRY_HIP(hipEventCreate(&e0));
+  AFQ_TRY_HIP(hipEventCreate(&e1));
+  int rc = AFQ_OK, best = -1;
+  float best_ms = 0.f;
+  const int pinned = s->b3_tile;
+  for (int t = 0; t < kNumB3Tiles && rc == AFQ_OK; ++t) {
+    if ((rc = system_set_b3_tile(s, t)) != AFQ_OK) break;
+    if ((rc = walkers_alloc_scratch(w)) != AFQ_OK) break;
+    if ((rc = hip_status(hipEventRecord(e0, st), "hipEventRecord")) != AFQ_OK) break;
+    for (int r = 0; r < reps && rc == AFQ_OK; ++r) {
+      rc = r32_b1(s, w, w->W.as<double2>(), w->u.as<double2>(), st, true);
+      if (rc == AFQ_OK) rc = r32_taylor(s, w, 6, st, true);
+    }
+    if (rc != AFQ_OK) break;
+    if ((rc = hip_status(hipEventRecord(e1, st), "hipEventRecord")) != AFQ_OK) break;
+    if ((rc = hip_status(hipEventSynchronize(e1), "hipEventSynchronize")) != AFQ_OK) break;
+    float ms = 0.f;
+    if ((rc = hip_status(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")) != AFQ_OK) break;
+    if (best < 0 || ms < best_ms) {
+      best = t;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != AFQ_OK) {
+    (void)system_set_b3_tile(s, pinned);
+    (void)walkers_alloc_scratch(w);
+    return rc;
+  }
+  AFQ_RET(system_set_b3_tile(s, best));
+  AFQ_RET(walkers_alloc_scratch(w));
+  *tile_out = best;
+  return AFQ_OK;
+}
+
