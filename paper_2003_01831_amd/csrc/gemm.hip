@@ -502,14 +502,18 @@ void launch_tile_cfg(const GemmArgs<T>& g, int cfg, dim3 grid, int ksplit, int k
     case 0: launch_tile<T, CA, CB, BT, 2, 2>(g, grid, ksplit, kchunk, ws, st); break;
     case 1: launch_tile<T, CA, CB, BT, 2, 4>(g, grid, ksplit, kchunk, ws, st); break;
     case 2: launch_tile<T, CA, CB, BT, 4, 2>(g, grid, ksplit, kchunk, ws, st); break;
+    case 4: launch_tile<T, CA, CB, BT, 1, 2>(g, grid, ksplit, kchunk, ws, st); break;
+    case 5: launch_tile<T, CA, CB, BT, 1, 4>(g, grid, ksplit, kchunk, ws, st); break;
     default:
       if constexpr (sizeof(T) == 4) launch_tile<T, CA, CB, BT, 4, 4>(g, grid, ksplit, kchunk, ws, st);
       break;   // not chosen for double (tile_config)
   }
 }
 
-// (WM, WN) of the tile configurations
-constexpr int kTileWM[4] = {2, 2, 4, 4}, kTileWN[4] = {2, 4, 2, 4};
+// (WM, WN) of the tile configurations; the 32-row ones serve the overlap
+// matrices of systems with few electrons (m = N of 8 .. 32)
+constexpr int kNumTileCfg = 6;
+constexpr int kTileWM[kNumTileCfg] = {2, 2, 4, 4, 1, 1}, kTileWN[kNumTileCfg] = {2, 4, 2, 4, 2, 4};
 
 // the tiled kernel applies: A untransposed (k contiguous), B untransposed or
 // transposed, no conjugation, 16-byte aligned rows and bases
@@ -528,7 +532,7 @@ template <typename T> bool tile_applies(const GemmArgs<T>& g) {
 template <typename T> int tile_config(const GemmArgs<T>& g) {
   int best = -1;
   long best_area = 0;
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < kNumTileCfg; ++c) {
     if (sizeof(T) == 8 && c == 3) continue;
     const long bm = 32 * kTileWM[c], bn = 32 * kTileWN[c];
     const long area = ceil_div(g.m, (int)bm) * bm * ceil_div(g.n, (int)bn) * bn;
