@@ -510,8 +510,8 @@ void launch_tile_cfg(const GemmArgs<T>& g, int cfg, dim3 grid, int ksplit, int k
   }
 }
 
-// (WM, WN) of the tile configurations; the 32-row ones serve the overlap
-// matrices of systems with few electrons (m = N of 8 .. 32)
+// (WM, WN) of the tile configurations; the 32-row ones serve only m <= 32
+// (the overlap matrices of systems with few electrons)
 constexpr int kNumTileCfg = 6;
 constexpr int kTileWM[kNumTileCfg] = {2, 2, 4, 4, 1, 1}, kTileWN[kNumTileCfg] = {2, 4, 2, 4, 2, 4};
 
@@ -534,6 +534,7 @@ template <typename T> int tile_config(const GemmArgs<T>& g) {
   long best_area = 0;
   for (int c = 0; c < kNumTileCfg; ++c) {
     if (sizeof(T) == 8 && c == 3) continue;
+    if (kTileWM[c] == 1 && g.m > 32) continue;   // 32-row tiles reuse operands half as often
     const long bm = 32 * kTileWM[c], bn = 32 * kTileWN[c];
     const long area = ceil_div(g.m, (int)bm) * bm * ceil_div(g.n, (int)bn) * bn;
     if (best < 0 || area < best_area || (area == best_area && bm * bn > 32L * kTileWM[best] * 32 * kTileWN[best])) {
