@@ -41,7 +41,6 @@ namespace {
 
 using ring::bf16x8;
 using ring::dma16;
-using ring::dma4;
 using ring::f4;
 using ring::KC;
 using ring::lds_t;
@@ -88,7 +87,7 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
   __shared__ __align__(16) unsigned char L0[STAGE];
   __shared__ __align__(16) unsigned char L1[STAGE];
   __shared__ __align__(16) unsigned char L2[STAGE];
-  __shared__ float trash[NWAVE * 64];
+  __shared__ __align__(16) unsigned char trash[NWAVE * 1024];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rb = wave >> 1, cb = wave & 1;        // row half (W''), column half (Theta-hat)
   // XCD-aware order: workgroup i runs on XCD i % 8. XCD x takes the units
@@ -117,18 +116,14 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
     const unsigned char* base = reg == 0 ? g.a[0] : reg == 1 ? g.a[1] : reg == 2 ? g.b[0] : g.b[1];
     src[q] = base + ((q < QA ? arow0 : brow0) + row) * ROWB + 16 * c + (q < QA ? aoff0 : (long)c0 * bstride);
   }
-  auto issue = [&](int chunk, unsigned char* buf) {
-    lds_t* l = (lds_t*)buf;
+  // load q of chunk `chunk` into buffer buf; past the unit's last chunk the
+  // same instruction fetches chunk 0 again into this wave's trash slice, so
+  // that every step keeps the same wait count and the same code shape
+  lds_t* const my_trash = (lds_t*)trash + wave * 1024;
+  auto load = [&](int q, int chunk, lds_t* buf) {
+    const bool real = chunk < nc;
     const long da = tri_rows_before(c0 + chunk) * ROWB - aoff0, db = chunk * bstride;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) dma16(src[q] + (q < QA ? da : db), l + (q * NWAVE + wave) * 1024);
-  };
-  // the last two steps have no chunk to prefetch: tiny loads into this wave's
-  // trash slice keep the wait count of every step the same
-  auto issue_dummy = [&]() {
-    lds_t* l = (lds_t*)(trash + wave * 64);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) dma4(src[q], l);
+    dma16(src[q] + (real ? (q < QA ? da : db) : 0), real ? buf + (q * NWAVE + wave) * 1024 : my_trash);
   };
   f4 acc[TA][TB];
 #pragma unroll
@@ -136,31 +131,96 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
 #pragma unroll
     for (int j = 0; j < TB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int arow = rb * (RA / 2), brow = cb * (RBR / 2);
-  issue(0, L0);
-  if (nc > 1) issue(1, L1);
-  else issue_dummy();
-  wait_vm_barrier<NQ>();
-  // step c: prefetch chunk c+2 into the buffer chunk c-1 used, multiply
-  // chunk c, wait until chunk c+1 has landed. One step per chunk with the three
-  // buffers rotated (the unrolled form with a fixed buffer per step makes the
-  // register allocator copy the accumulators between register files at every step).
-  unsigned char* cur = L0;
-  unsigned char* nxt = L1;
-  unsigned char* pf = L2;
-  for (int c = 0; c < nc; ++c) {
-    // the prefetch is issued after the chunk's first fragment reads, which
-    // complete while the loads go out
-    ring::mma_rect_then<TA, TB, REGA, REGB>(acc, cur, cur + 2 * REGA, arow, brow, lane, [&]() {
-      if (c + 2 < nc) issue(c + 2, pf);
-      else issue_dummy();
-    });
-    __builtin_amdgcn_sched_barrier(0);
-    wait_vm_barrier<NQ>();
-    unsigned char* t = cur;
-    cur = nxt;
-    nxt = pf;
-    pf = t;
+  const int lr = lane & 15, lq = lane >> 4;
+  // The fragments of one chunk live in registers (A hi / lo: TA tiles, B hi /
+  // lo: TB tiles). Each register is refilled with the next chunk's fragment
+  // right after its last MFMA of the current chunk, so the reads overlap the
+  // MFMAs and need no second register set.
+  bf16x8 ah[TA], al[TA], bh[TB], bl[TB];
+  auto rd_a = [&](int i, const lds_t* buf) {
+    ah[i] = ring::frag3(buf, arow + 16 * i + lr, lq);
+    al[i] = ring::frag3(buf + REGA, arow + 16 * i + lr, lq);
+  };
+  auto rd_bh = [&](int j, const lds_t* buf) { bh[j] = ring::frag3(buf + 2 * REGA, brow + 16 * j + lr, lq); };
+  auto rd_bl = [&](int j, const lds_t* buf) { bl[j] = ring::frag3(buf + 2 * REGA + REGB, brow + 16 * j + lr, lq); };
+  lds_t* b0 = (lds_t*)L0;                         // chunk c (its fragments are in registers)
+  lds_t* b1 = (lds_t*)L1;                         // chunk c + 1 (landed)
+  lds_t* b2 = (lds_t*)L2;                         // chunk c + 2 (in flight)
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) load(q, 0, b0);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) load(q, 1, b1);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) load(q, 2, b2);
+  wait_vm_barrier<2 * NQ>();                      // chunk 0 has landed
+#pragma unroll
+  for (int i = 0; i < TA; ++i) rd_a(i, b0);
+#pragma unroll
+  for (int j = 0; j < TB; ++j) {
+    rd_bh(j, b0);
+    rd_bl(j, b0);
   }
+  wait_vm_barrier<NQ>();                          // chunk 1 has landed
+  // Step c multiplies chunk c out of registers, row tile by row tile: for tile
+  // i the products hi*hi (p0), lo*hi (p2), hi*lo (p1) over the TB column
+  // tiles (each accumulator's three MFMAs at least TB apart). After p2 the A
+  // lo fragment of tile i is refilled from chunk c + 1, after p1 the A hi one.
+  // The B fragments serve every tile: the last KD tiles defer their p1, so
+  // that the B hi fragments are refilled after the last p2 with 4 KD MFMAs
+  // still to go, and the B lo ones at the end. After p2 of tile 0 every wave
+  // has consumed chunk c's fragments: a barrier there (with this wave's reads
+  // returned) frees chunk c's buffer, into which the loads of chunk c + 3
+  // then go, spread over the tiles. The step ends once chunk c + 2 has
+  // landed. Scheduling barriers keep this order (a macro rather than a
+  // lambda: the barrier and wait builtins must stay in device-only code).
+  constexpr int QPT = (NQ + TA - 1) / TA;         // loads per row tile
+  constexpr int KD = 2;
+#define AFQ_ERI_MFMA(X, Y, i, j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(X, Y, acc[i][j], 0, 0, 0)
+  for (int c = 0; c < nc; ++c) {
+#pragma unroll
+    for (int i = 0; i < TA; ++i) {
+#pragma unroll
+      for (int j = 0; j < TB; ++j) AFQ_ERI_MFMA(ah[i], bh[j], i, j);
+#pragma unroll
+      for (int j = 0; j < TB; ++j) AFQ_ERI_MFMA(al[i], bh[j], i, j);
+      __builtin_amdgcn_sched_barrier(0);
+      if (i == 0) {
+        ring::lgkm_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      al[i] = ring::frag3(b1 + REGA, arow + 16 * i + lr, lq);
+#pragma unroll
+      for (int q = QPT * i; q < QPT * (i + 1); ++q)
+        if (q < NQ) load(q, c + 3, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (i < TA - KD) {
+#pragma unroll
+        for (int j = 0; j < TB; ++j) AFQ_ERI_MFMA(ah[i], bl[j], i, j);
+        __builtin_amdgcn_sched_barrier(0);
+        ah[i] = ring::frag3(b1, arow + 16 * i + lr, lq);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < TB; ++j) rd_bh(j, b1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = TA - KD; i < TA; ++i) {
+#pragma unroll
+      for (int j = 0; j < TB; ++j) AFQ_ERI_MFMA(ah[i], bl[j], i, j);
+      __builtin_amdgcn_sched_barrier(0);
+      ah[i] = ring::frag3(b1, arow + 16 * i + lr, lq);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int j = 0; j < TB; ++j) rd_bl(j, b1);
+    wait_vm_barrier<NQ>();
+    lds_t* const t_ = b0;
+    b0 = b1;
+    b1 = b2;
+    b2 = t_;
+  }
+#undef AFQ_ERI_MFMA
   wait_vm_barrier<0>();
   __syncthreads();
 
@@ -168,7 +228,6 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
   // (W'' Theta-hat_w) over this unit's chunks; its share of the complex form
   // Theta-hat_w . (W'' Theta-hat_w) is theta Z (part 0) or i theta Z (part 1),
   // with the products in FP64
-  const int lr = lane & 15, lq = lane >> 4;
   double sre[TB], sim[TB];
 #pragma unroll
   for (int j = 0; j < TB; ++j) {

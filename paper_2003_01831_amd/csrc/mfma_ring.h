@@ -34,6 +34,14 @@ __device__ inline bf16x8 frag(const unsigned char* plane, int row, int lq) {
   return __builtin_bit_cast(bf16x8, lds16(plane + row * ROWB + 16 * swz(row, lq)));
 }
 
+// The same fragment read from an LDS-qualified plane pointer (a ds_read_b128
+// whatever the caller's pointer arithmetic hides from address-space inference)
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
+__device__ inline bf16x8 frag3(const lds_t* plane, int row, int lq) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<lds_u32x4*>(plane + row * ROWB + 16 * swz(row, lq)));
+}
+
 // One chunk (32 contraction elements) of this wave's TA x TB block of 16 x 16
 // tiles. A planes at la (hi, then lo PA bytes later), B planes at lb (lo PB
 // bytes after hi); the wave's rows start at arow (A) and brow (B). The
@@ -165,5 +173,9 @@ template <int W> __device__ inline void wait_vm_barrier() {
   static_assert(W >= 0 && W < 64, "vmcnt is 6 bits");
   asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(W) : "memory");
 }
+
+// s_waitcnt lgkmcnt(0) followed by s_barrier: every LDS read of every wave
+// has returned, so the buffers they read may be refilled after it
+__device__ inline void lgkm_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 }  // namespace ring
