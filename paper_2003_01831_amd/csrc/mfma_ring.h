@@ -165,6 +165,13 @@ __device__ inline void dma4(const unsigned char* src, lds_t* dst) {
   const unsigned m = __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)dst);
   asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(src), "s"(m) : "memory", "m0");
 }
+// The same load with a wave-uniform 64-bit base in SGPRs and a per-lane 32-bit
+// byte offset: the address arithmetic of a load is then scalar. m is the LDS
+// byte address the wave's lane 0 writes (wave-uniform).
+__device__ inline void dma16s(const unsigned char* base, unsigned voff, unsigned m) {
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(base), "s"(m)
+               : "memory", "m0");
+}
 #pragma clang diagnostic pop
 
 // s_waitcnt vmcnt(W) followed by s_barrier, one opaque statement: it is also a
