@@ -83,6 +83,18 @@ struct EriArgs {
   double2* part;               // [unit][rows_b]
 };
 
+// the wave-uniform base of load q of chunk ch of a work unit (chunk c0 + ch
+// of the run): W'' chunks start at their triangle row offset, Theta-hat
+// chunks rows_b rows apart; qb[q] is the load's first row in chunk 0
+struct EriLoader {
+  const unsigned char* qb[NQ];
+  long bstride;
+  int c0;
+  __device__ const unsigned char* src(int q, int ch) const {
+    return qb[q] + (q < QA ? tri_rows_before(c0 + ch) * ROWB : (long)(c0 + ch) * bstride);
+  }
+};
+
 __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
   __shared__ __align__(16) unsigned char L0[STAGE];
   __shared__ __align__(16) unsigned char L1[STAGE];
@@ -102,160 +114,29 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
   const int4 un = g.units[u];
   const int c0 = un.y, nc = un.z;                 // nc >= 1
   const long arow0 = (long)un.x * RA, brow0 = (long)bb * RBR;
-  // Load q of this wave moves 1 KB: instruction t = q * 4 + wave of the stage,
-  // 16 rows of one region (A hi, A lo, B hi, B lo); lane l writes LDS bytes
-  // 1024 t + 16 l: row l / 4, swizzled piece. The swizzle of a row depends on
-  // (row / 2) mod 4 only, the same for the row l / 4 of every load, so every
-  // load takes the same per-lane offset voff from a wave-uniform base: qb[q]
-  // (the load's first row) plus the chunk's offset (a chunk of W'' starts at
-  // its triangle row offset, one of Theta-hat rows_b rows further per chunk).
-  const unsigned voff = (unsigned)((lane >> 2) * ROWB + 16 * swz(lane >> 2, lane & 3));
-  const unsigned char* qb[NQ];
-  const long bstride = g.rows_b * ROWB;
+  // load q of this wave: instruction t = q * 4 + wave of the stage, 16 rows of
+  // one region (A hi, A lo, B hi, B lo) starting at row 16 j of the region
+  EriLoader ld;
+  ld.bstride = g.rows_b * ROWB;
+  ld.c0 = c0;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int t = q * NWAVE + wave;
     const int reg = t < RA / 16 ? 0 : t < RA / 8 ? 1 : t < RA / 8 + RBR / 16 ? 2 : 3;
     const int j = reg == 0 ? t : reg == 1 ? t - RA / 16 : reg == 2 ? t - RA / 8 : t - RA / 8 - RBR / 16;
     const unsigned char* base = reg == 0 ? g.a[0] : reg == 1 ? g.a[1] : reg == 2 ? g.b[0] : g.b[1];
-    qb[q] = base + ((q < QA ? arow0 : brow0) + 16 * j) * ROWB;
+    ld.qb[q] = base + ((q < QA ? arow0 : brow0) + 16 * j) * ROWB;
   }
-  const unsigned lds0 = (unsigned)(uintptr_t)(lds_t*)L0 + wave * 1024;
-  const unsigned lds1 = (unsigned)(uintptr_t)(lds_t*)L1 + wave * 1024;
-  const unsigned lds2 = (unsigned)(uintptr_t)(lds_t*)L2 + wave * 1024;
-  const unsigned trash_m = (unsigned)(uintptr_t)(lds_t*)trash + wave * 1024;
-  // chunk offsets (bytes) of the A and B loads of chunk `chunk`; past the
-  // unit's last chunk the loads fetch chunk 0 again into this wave's trash
-  // slice, so that every step keeps the same wait count and code shape
-  struct ChunkOff { long a, b; unsigned m_or_trash; bool real; };
-  auto chunk_off = [&](int chunk, unsigned buf_m) {
-    ChunkOff o;
-    o.real = chunk < nc;
-    const int ch = o.real ? chunk : 0;
-    o.a = tri_rows_before(c0 + ch) * ROWB;
-    o.b = (long)(c0 + ch) * bstride;
-    o.m_or_trash = o.real ? buf_m : trash_m;
-    return o;
-  };
-  auto load = [&](int q, const ChunkOff& o) {
-    dma16s(qb[q] + (q < QA ? o.a : o.b), voff, o.real ? o.m_or_trash + q * NWAVE * 1024 : o.m_or_trash);
-  };
   f4 acc[TA][TB];
 #pragma unroll
   for (int i = 0; i < TA; ++i)
 #pragma unroll
     for (int j = 0; j < TB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int arow = rb * (RA / 2), brow = cb * (RBR / 2);
-  const int lr = lane & 15, lq = lane >> 4;
-  // The fragments of one chunk live in registers (A hi / lo: TA tiles, B hi /
-  // lo: TB tiles). Each register is refilled with the next chunk's fragment
-  // right after its last MFMA of the current chunk, so the reads overlap the
-  // MFMAs and need no second register set.
-  bf16x8 ah[TA], al[TA], bh[TB], bl[TB];
-  // b0: chunk c (its fragments are in registers), b1: chunk c + 1 (landed),
-  // b2: chunk c + 2 (in flight); LDS byte addresses of this wave's first load
-  unsigned m0b = lds0, m1b = lds1, m2b = lds2;
-  {
-    const ChunkOff o0 = chunk_off(0, lds0), o1 = chunk_off(1, lds1), o2 = chunk_off(2, lds2);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) load(q, o0);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) load(q, o1);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) load(q, o2);
-  }
-  wait_vm_barrier<2 * NQ>();                      // chunk 0 has landed
-  {
-    const lds_t* b = (const lds_t*)L0;
-#pragma unroll
-    for (int i = 0; i < TA; ++i) {
-      ah[i] = ring::frag3(b, arow + 16 * i + lr, lq);
-      al[i] = ring::frag3(b + REGA, arow + 16 * i + lr, lq);
-    }
-#pragma unroll
-    for (int j = 0; j < TB; ++j) {
-      bh[j] = ring::frag3(b + 2 * REGA, brow + 16 * j + lr, lq);
-      bl[j] = ring::frag3(b + 2 * REGA + REGB, brow + 16 * j + lr, lq);
-    }
-  }
-  wait_vm_barrier<NQ>();                          // chunk 1 has landed
-  // Step c multiplies chunk c out of registers, row tile by row tile: for tile
-  // i the products hi*hi (p0), lo*hi (p2), hi*lo (p1) over the TB column
-  // tiles (each accumulator's three MFMAs at least TB apart). After p2 the A
-  // lo fragment of tile i is refilled from chunk c + 1, after p1 the A hi one.
-  // The B fragments serve every tile: the last KD tiles defer their p1, so
-  // that the B hi fragments are refilled after the last p2 with 4 KD MFMAs
-  // still to go, and each B lo one after its last MFMA. After p2 of tile 0
-  // every wave has consumed chunk c's fragments: a barrier there (with this
-  // wave's reads returned) frees chunk c's buffer, into which the loads of
-  // chunk c + 3 then go, QPT per tile. Every read or load sits between two
-  // MFMAs, so that the matrix pipe is never left without queued work while
-  // the wave issues them; scheduling barriers keep this order (macros rather
-  // than lambdas: the barrier and wait builtins must stay in device-only code).
-  constexpr int QPT = (NQ + TA - 1) / TA;         // loads per row tile
-  constexpr int KD = 2;
-  static_assert(QPT <= TB && QPT * (TA - KD) >= NQ, "the loads fit between the p1 MFMAs of the first tiles");
-#define AFQ_ERI_MFMA(X, Y, i, j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(X, Y, acc[i][j], 0, 0, 0)
-#define AFQ_SB __builtin_amdgcn_sched_barrier(0)
-  for (int c = 0; c < nc; ++c) {
-    const lds_t* const b1 = (const lds_t*)(uintptr_t)(m1b - wave * 1024);
-    const ChunkOff o3 = chunk_off(c + 3, m0b);
-#pragma unroll
-    for (int i = 0; i < TA; ++i) {
-#pragma unroll
-      for (int j = 0; j < TB; ++j) {
-        AFQ_ERI_MFMA(ah[i], bh[j], i, j);
-        AFQ_SB;
-      }
-#pragma unroll
-      for (int j = 0; j < TB; ++j) {
-        AFQ_ERI_MFMA(al[i], bh[j], i, j);
-        AFQ_SB;
-      }
-      if (i == 0) {
-        ring::lgkm_barrier();
-        AFQ_SB;
-      }
-      al[i] = ring::frag3(b1 + REGA, arow + 16 * i + lr, lq);
-      AFQ_SB;
-      if (i < TA - KD) {
-#pragma unroll
-        for (int j = 0; j < TB; ++j) {
-          AFQ_ERI_MFMA(ah[i], bl[j], i, j);
-          AFQ_SB;
-          if (j < QPT && QPT * i + j < NQ) {
-            load(QPT * i + j, o3);
-            AFQ_SB;
-          }
-        }
-        ah[i] = ring::frag3(b1, arow + 16 * i + lr, lq);
-        AFQ_SB;
-      }
-    }
-    // deferred p1 of the last KD tiles, the B fragments refilled in between
-#pragma unroll
-    for (int i = TA - KD; i < TA; ++i) {
-#pragma unroll
-      for (int j = 0; j < TB; ++j) {
-        AFQ_ERI_MFMA(ah[i], bl[j], i, j);
-        AFQ_SB;
-        if (i == TA - KD) bh[j] = ring::frag3(b1 + 2 * REGA, brow + 16 * j + lr, lq);
-        else bl[j] = ring::frag3(b1 + 2 * REGA + REGB, brow + 16 * j + lr, lq);
-        AFQ_SB;
-      }
-      ah[i] = ring::frag3(b1, arow + 16 * i + lr, lq);
-      AFQ_SB;
-    }
-    wait_vm_barrier<NQ>();
-    const unsigned t_ = m0b;
-    m0b = m1b;
-    m1b = m2b;
-    m2b = t_;
-  }
-#undef AFQ_SB
-#undef AFQ_ERI_MFMA
-  wait_vm_barrier<0>();
+  ring::bf3_stream<TA, TB, REGA, REGB, NQ>(acc, (const lds_t*)L0, (const lds_t*)L1, (const lds_t*)L2,
+                                           (unsigned)(uintptr_t)(lds_t*)trash, nc, arow, brow, lane, wave, ld);
   __syncthreads();
+  const int lr = lane & 15, lq = lane >> 4;
 
   // epilogue: column C = (w, part) holds Re (part 0) or Im (part 1) of
   // (W'' Theta-hat_w) over this unit's chunks; its share of the complex form

@@ -185,4 +185,150 @@ template <int W> __device__ inline void wait_vm_barrier() {
 // has returned, so the buffers they read may be refilled after it
 __device__ inline void lgkm_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// Loader of bf3_stream for operands whose chunks are a fixed stride apart:
+// loads q < QA move A rows (chunks astride bytes apart), the others B rows
+template <int NQ, int QA> struct StrideLoader {
+  const unsigned char* qb[NQ];   // load q's first row in chunk 0
+  long astride, bstride;
+  __device__ const unsigned char* src(int q, int ch) const { return qb[q] + (long)ch * (q < QA ? astride : bstride); }
+};
+
+// The split-BF16x3 chunk loop of a TA x TB wave tile with the fragments in
+// registers. Operands are chunk-major planes as above, one LDS stage holding
+// A hi (REGA bytes), A lo, B hi (REGB bytes), B lo; a wave moves NQ 1 KB
+// loads per chunk: load q is instruction t = NQ-major (q * 4 + wave) of the
+// stage, 16 rows whose global base for chunk ch is ld.src(q, ch) (wave-uniform)
+// and whose lane l reads row l / 4, swizzled piece, i.e. the per-lane offset
+// voff below (the swizzle of row 16 j + l / 4 does not depend on j).
+//
+// Chunk c's fragments live in registers; each register is refilled from
+// chunk c + 1 right after its last MFMA of chunk c, so the reads overlap the
+// MFMAs without a second register set. Row tile by row tile: products hi*hi
+// (p0), lo*hi (p2), hi*lo (p1) over the TB column tiles (an accumulator's
+// MFMAs at least TB apart); A lo refilled after p2, A hi after p1. The B
+// fragments serve every tile: the last KD tiles defer their p1, so that the
+// B hi fragments are refilled after the last p2 with KD * TB MFMAs to go and
+// each B lo one after its last MFMA. After p2 of tile 0 every wave has
+// consumed chunk c's fragments: a barrier there (this wave's reads returned)
+// frees chunk c's buffer for the loads of chunk c + 3, spread over the MFMAs
+// that follow. The step ends once chunk c + 2 has landed. Every read and
+// load sits between two MFMAs, so the matrix pipe always has queued work
+// while the wave issues them; scheduling barriers keep the order. Past the
+// last chunk the loads fetch chunk 0 again into this wave's trash slice
+// (trash_m, 1 KB), so every step keeps the same wait count.
+//
+// On return every load has landed; the caller's epilogue may reuse the LDS
+// after a __syncthreads().
+template <int TA, int TB, int REGA, int REGB, int NQ, class Loader>
+__device__ __forceinline__ void bf3_stream(f4 (&acc)[TA][TB], const lds_t* L0, const lds_t* L1, const lds_t* L2,
+                                           unsigned trash_m, int nc, int arow, int brow, int lane, int wave,
+                                           const Loader& ld) {
+  constexpr int NW = 4;
+  constexpr int KD = TA > 2 ? 2 : 1;
+  // MFMAs after the barrier outside the deferred tail: the slots of the loads
+  constexpr int SPAN = 3 * TA * TB - 2 * TB - KD * TB;
+  static_assert(SPAN > 0, "tile too small for the chunk loop");
+  const int lr = lane & 15, lq = lane >> 4;
+  const unsigned voff = (unsigned)((lane >> 2) * ROWB + 16 * swz(lane >> 2, lane & 3));
+  auto addr = [](const lds_t* p) { return (unsigned)(uintptr_t)p; };
+  const unsigned lds0 = addr(L0) + wave * 1024, lds1 = addr(L1) + wave * 1024, lds2 = addr(L2) + wave * 1024;
+  const unsigned tw = trash_m + wave * 1024;
+  auto load = [&](int q, int chunk, unsigned mbuf) {
+    const bool real = chunk < nc;
+    dma16s(ld.src(q, real ? chunk : 0), voff, real ? mbuf + q * NW * 1024 : tw);
+  };
+  bf16x8 ah[TA], al[TA], bh[TB], bl[TB];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) load(q, 0, lds0);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) load(q, 1, lds1);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) load(q, 2, lds2);
+  wait_vm_barrier<2 * NQ>();                      // chunk 0 has landed
+#pragma unroll
+  for (int i = 0; i < TA; ++i) {
+    ah[i] = frag3(L0, arow + 16 * i + lr, lq);
+    al[i] = frag3(L0 + REGA, arow + 16 * i + lr, lq);
+  }
+#pragma unroll
+  for (int j = 0; j < TB; ++j) {
+    bh[j] = frag3(L0 + 2 * REGA, brow + 16 * j + lr, lq);
+    bl[j] = frag3(L0 + 2 * REGA + REGB, brow + 16 * j + lr, lq);
+  }
+  wait_vm_barrier<NQ>();                          // chunk 1 has landed
+  // b0: chunk c (in registers), b1: chunk c + 1 (landed), b2: chunk c + 2
+  unsigned m0b = lds0, m1b = lds1, m2b = lds2;
+#define AFQ_RING_MFMA(X, Y, i, j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(X, Y, acc[i][j], 0, 0, 0)
+#define AFQ_RING_SB __builtin_amdgcn_sched_barrier(0)
+  for (int c = 0; c < nc; ++c) {
+    const lds_t* const b1 = (const lds_t*)(uintptr_t)(m1b - wave * 1024);
+    int s = 0;                                    // MFMA slot after the barrier (folds to a constant)
+    // the loads of chunk c + 3 placed after slot s
+#define AFQ_RING_LOADS                                  \
+  do {                                                  \
+    _Pragma("unroll") for (int q = 0; q < NQ; ++q) {    \
+      if (q * SPAN / NQ == s) {                         \
+        load(q, c + 3, m0b);                            \
+        AFQ_RING_SB;                                    \
+      }                                                 \
+    }                                                   \
+    ++s;                                                \
+  } while (0)
+#pragma unroll
+    for (int i = 0; i < TA; ++i) {
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        AFQ_RING_MFMA(ah[i], bh[j], i, j);
+        AFQ_RING_SB;
+        if (i > 0) AFQ_RING_LOADS;
+      }
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        AFQ_RING_MFMA(al[i], bh[j], i, j);
+        AFQ_RING_SB;
+        if (i > 0) AFQ_RING_LOADS;
+      }
+      if (i == 0) {
+        lgkm_barrier();
+        AFQ_RING_SB;
+      }
+      al[i] = frag3(b1 + REGA, arow + 16 * i + lr, lq);
+      AFQ_RING_SB;
+      if (i < TA - KD) {
+#pragma unroll
+        for (int j = 0; j < TB; ++j) {
+          AFQ_RING_MFMA(ah[i], bl[j], i, j);
+          AFQ_RING_SB;
+          AFQ_RING_LOADS;
+        }
+        ah[i] = frag3(b1, arow + 16 * i + lr, lq);
+        AFQ_RING_SB;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < KD; ++d) {
+      const int i = TA - KD + d;
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        AFQ_RING_MFMA(ah[i], bl[j], i, j);
+        AFQ_RING_SB;
+        if (d == 0) bh[j] = frag3(b1 + 2 * REGA, brow + 16 * j + lr, lq);
+        if (d == KD - 1) bl[j] = frag3(b1 + 2 * REGA + REGB, brow + 16 * j + lr, lq);
+        AFQ_RING_SB;
+      }
+      ah[i] = frag3(b1, arow + 16 * i + lr, lq);
+      AFQ_RING_SB;
+    }
+    wait_vm_barrier<NQ>();
+    const unsigned t_ = m0b;
+    m0b = m1b;
+    m1b = m2b;
+    m2b = t_;
+  }
+#undef AFQ_RING_LOADS
+#undef AFQ_RING_SB
+#undef AFQ_RING_MFMA
+  wait_vm_barrier<0>();
+}
+
 }  // namespace ring

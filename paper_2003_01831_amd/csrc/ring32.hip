@@ -371,12 +371,14 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
   constexpr bool LAST = MODE != B3_HORNER;   // the input is U (or U_base): FP64
   constexpr int RA = 32 * TA, RB = 32 * TB, REGA = RA * ROWB, REGB = RB * ROWB;
   constexpr int STAGE = 2 * REGA + 2 * REGB, NT = STAGE / 1024, NQ = NT / NWAVE;
-  static_assert(NT % NWAVE == 0, "loads must split evenly over the waves");
+  constexpr int QA = (RA / 8) / NWAVE;        // the first QA loads of every wave move A rows
+  static_assert(NT % NWAVE == 0 && (RA / 8) % NWAVE == 0, "loads must split evenly over the waves");
   __shared__ __align__(16) unsigned char L0[STAGE];
   __shared__ __align__(16) unsigned char L1[STAGE];
   __shared__ __align__(16) unsigned char L2[STAGE];
-  __shared__ float trash[NWAVE * 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ __align__(16) unsigned char trash[NWAVE * 1024];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar address arithmetic
   const int rb = wave >> 1, cb = wave & 1;
   // XCD-aware order: workgroup i runs on XCD i % 8; each XCD takes a
   // contiguous range of the logical order (B blocks fastest, so the blocks of
@@ -399,58 +401,26 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
   const unsigned char* abase = g.a + (long)w * g.a_wstride;
   const unsigned char* bbase = g.b + (long)w * g.b_wstride;
   // load q of this wave: instruction t = q * 4 + wave of the stage, 16 rows of
-  // one region (A hi, A lo, B hi, B lo); lane l writes LDS bytes 1024 t + 16 l
-  const unsigned char* src[NQ];
-  long cstride[NQ];
+  // one region (A hi, A lo, B hi, B lo) starting at row 16 j of the region
+  ring::StrideLoader<NQ, QA> ld;
+  ld.astride = g.rows_a * (long)ROWB;
+  ld.bstride = g.rows_b * (long)ROWB;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int t = q * NWAVE + wave;
     const int reg = t < RA / 16 ? 0 : t < RA / 8 ? 1 : t < RA / 8 + RB / 16 ? 2 : 3;
     const int j = reg == 0 ? t : reg == 1 ? t - RA / 16 : reg == 2 ? t - RA / 8 : t - RA / 8 - RB / 16;
-    const int row = 16 * j + (lane >> 2), c = swz(row, lane & 3);
     const unsigned char* base = reg == 0 ? abase : reg == 1 ? abase + g.a_plane : reg == 2 ? bbase : bbase + g.b_plane;
-    cstride[q] = (reg < 2 ? g.rows_a : g.rows_b) * (long)ROWB;
-    src[q] = base + ((reg < 2 ? arow0 : brow0) + row) * ROWB + 16 * c;
+    ld.qb[q] = base + ((q < QA ? arow0 : brow0) + 16 * j) * ROWB;
   }
-  auto issue = [&](int chunk, unsigned char* buf) {
-    lds_t* l = (lds_t*)buf;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) ring::dma16(src[q] + chunk * cstride[q], l + (q * NWAVE + wave) * 1024);
-  };
-  // the last two steps have no chunk to prefetch: tiny loads into this wave's
-  // trash slice keep the wait count of every step the same
-  auto issue_dummy = [&]() {
-    lds_t* l = (lds_t*)(trash + wave * 64);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) ring::dma4(src[q], l);
-  };
   f4 acc[TA][TB];
 #pragma unroll
   for (int i = 0; i < TA; ++i)
 #pragma unroll
     for (int j = 0; j < TB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int arow = rb * (RA / 2), brow = cb * (RB / 2);
-  const int nc = g.nchunk;
-  issue(0, L0);
-  if (nc > 1) issue(1, L1);
-  else issue_dummy();
-  wait_vm_barrier<NQ>();
-  unsigned char* cur = L0;
-  unsigned char* nxt = L1;
-  unsigned char* pf = L2;
-  for (int c = 0; c < nc; ++c) {
-    ring::mma_rect_then<TA, TB, REGA, REGB>(acc, cur, cur + 2 * REGA, arow, brow, lane, [&]() {
-      if (c + 2 < nc) issue(c + 2, pf);
-      else issue_dummy();
-    });
-    __builtin_amdgcn_sched_barrier(0);
-    wait_vm_barrier<NQ>();
-    unsigned char* t = cur;
-    cur = nxt;
-    nxt = pf;
-    pf = t;
-  }
-  wait_vm_barrier<0>();
+  ring::bf3_stream<TA, TB, REGA, REGB, NQ>(acc, (const lds_t*)L0, (const lds_t*)L1, (const lds_t*)L2,
+                                           (unsigned)(uintptr_t)(lds_t*)trash, g.nchunk, arow, brow, lane, wave, ld);
 
   if constexpr (MODE == B3_XFORM) {
     // rows (w0, Re), (w0, Im), (w0 + 1, Re), (w0 + 1, Im); a wave's 64 columns
