@@ -99,7 +99,6 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
   __shared__ __align__(16) unsigned char L0[STAGE];
   __shared__ __align__(16) unsigned char L1[STAGE];
   __shared__ __align__(16) unsigned char L2[STAGE];
-  __shared__ __align__(16) unsigned char trash[NWAVE * 1024];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar address arithmetic
   const int rb = wave >> 1, cb = wave & 1;        // row half (W''), column half (Theta-hat)
@@ -134,7 +133,7 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
     for (int j = 0; j < TB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int arow = rb * (RA / 2), brow = cb * (RBR / 2);
   ring::bf3_stream<TA, TB, REGA, REGB, NQ>(acc, (const lds_t*)L0, (const lds_t*)L1, (const lds_t*)L2,
-                                           (unsigned)(uintptr_t)(lds_t*)trash, nc, arow, brow, lane, wave, ld);
+                                           nc, arow, brow, lane, wave, ld);
   __syncthreads();
   const int lr = lane & 15, lq = lane >> 4;
 

@@ -8,13 +8,12 @@
 //     padding in the packed operands;
 //   * the waves share the walker operand (B) and the Cholesky operand (A)
 //     through LDS. k advances in chunks of 32 through a three-stage ring of
-//     LDS buffers filled by direct global->LDS loads (no register staging):
-//     all loads of chunk c+2 are issued before the MFMAs of chunk c, so two
-//     chunks are in flight while one is consumed. The packed operands are
-//     chunk-major in HBM (all rows of k-chunk 0, then chunk 1, ...), so the
-//     rows of one chunk are one contiguous run. The three buffers are
-//     distinct LDS objects so the compiler can tell the one being read from
-//     the ones being filled;
+//     LDS buffers filled by direct global->LDS loads (no register staging)
+//     from wave-uniform addresses; the packed operands are chunk-major in HBM
+//     (all rows of k-chunk 0, then chunk 1, ...), so the rows of one chunk
+//     are one contiguous run. A chunk's fragments are held in registers and
+//     refilled from the next chunk right after their last MFMA (the shared
+//     split-BF16x3 chunk loop);
 //   * fragments are read with 16-byte LDS loads from an XOR-swizzled layout;
 //   * epilogue: every wave stores the lower triangle of its plane in LDS
 //     (packed triangular layout) and reads the transposed partners of its
@@ -24,8 +23,7 @@
 //     the operands of resident workgroups are shared in each XCD's L2.
 //
 // Arithmetic: split-BF16x3 on v_mfma_f32_16x16x32_bf16 (hi*hi + hi*lo + lo*hi),
-// FP32 accumulation, in two passes per chunk (hi*hi + hi*lo with the A hi
-// fragments resident, then lo*hi with the A lo fragments resident).
+// FP32 accumulation.
 #include <algorithm>
 #include "common.h"
 #include "mfma_ring.h"
@@ -33,16 +31,10 @@
 
 namespace {
 
-using ring::bf16x8;
-using ring::CPR;
-using ring::dma16;
-using ring::dma4;
 using ring::f4;
 using ring::KC;
 using ring::lds_t;
 using ring::ROWB;
-using ring::swz;
-using ring::wait_vm_barrier;
 
 constexpr int NWAVE = 4;
 
@@ -76,6 +68,15 @@ template <int TM> struct Geo {
 // workgroups resident on one XCD form TB n-pairs x TW walkers tiles
 constexpr int NXCD = 8, TB = 4, TW = 8;
 
+// the wave-uniform base of load q of chunk ch: qb[q] (the load's first row
+// in chunk 0) plus ch chunk strides of its operand (A: rows_a rows, B: rows_b)
+template <int NQ> struct ExbLoader {
+  const unsigned char* qb[NQ];
+  long astride, bstride;
+  bool is_a[NQ];
+  __device__ const unsigned char* src(int q, int ch) const { return qb[q] + (long)ch * (is_a[q] ? astride : bstride); }
+};
+
 template <int TM>
 __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
   using G = Geo<TM>;
@@ -83,7 +84,8 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
   __shared__ __align__(16) unsigned char L0[G::STAGE];
   __shared__ __align__(16) unsigned char L1[G::STAGE];
   __shared__ __align__(16) unsigned char L2[G::STAGE];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar address arithmetic
   const int N = g.n;
   const int nb = wave >> 1, part = wave & 1;      // n-block within the pair, plane
   // XCD-aware order: workgroup i runs on XCD i % 8; each XCD owns nw/8 walkers
@@ -109,72 +111,26 @@ __global__ __launch_bounds__(256, 1) void exchange_big_kernel(ExchBigArgs g) {
 
   // Load q of this wave (q < RI) moves 1 KB: instruction t = 4 q + wave of the
   // chunk, region t / RI (A hi, A lo, B hi, B lo), rows 16 (t % RI) ... + 15.
-  // Lane l writes LDS bytes base + 16 l: row (l / 4), swizzled piece.
-  const unsigned char* src[RI];
-  long cstride[RI];                               // bytes from one k-chunk to the next
+  ExbLoader<RI> ld;
+  ld.astride = g.rows_a * (long)ROWB;
+  ld.bstride = g.rows_b * (long)ROWB;
 #pragma unroll
   for (int q = 0; q < RI; ++q) {
     const int t = q * NWAVE + wave, reg = t / RI, j = t - reg * RI;
-    const int sidx = j * 64 + lane, row = sidx / CPR, c = swz(row, sidx % CPR);
     const unsigned char* base = static_cast<const unsigned char*>(reg == 0 ? g.a[0] : reg == 1 ? g.a[1]
                                                                    : reg == 2 ? g.b[0] : g.b[1]);
-    src[q] = base + ((reg < 2 ? arow0 : brow0) + row) * ROWB + 16 * c;
-    cstride[q] = (reg < 2 ? g.rows_a : g.rows_b) * (long)ROWB;
+    ld.is_a[q] = reg < 2;
+    ld.qb[q] = base + ((reg < 2 ? arow0 : brow0) + 16 * j) * ROWB;
   }
-  auto issue = [&](int chunk, unsigned char* buf) {
-    lds_t* l = (lds_t*)buf;
-#pragma unroll
-    for (int q = 0; q < RI; ++q) {
-      const int t = q * NWAVE + wave, reg = t / RI, j = t - reg * RI;
-      dma16(src[q] + chunk * cstride[q], l + reg * REG + j * 1024);
-    }
-  };
-  // The last two steps have no chunk to prefetch: they issue RI tiny loads
-  // (4 bytes per lane, into this wave's slice of the epilogue trash area) so
-  // that every step keeps the same wait count and the same code shape.
-  __shared__ float trash[NWAVE * 64];
-  auto issue_dummy = [&]() {
-    lds_t* l = (lds_t*)(trash + wave * 64);
-#pragma unroll
-    for (int q = 0; q < RI; ++q) dma4(src[q], l);
-  };
-
+  __shared__ float trash[NWAVE * 64];             // the epilogue's sink for out-of-range elements
   f4 acc[TM][TM];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TM; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-
-  const int nc = g.kp / KC;                       // >= 2
   const int arow = nb * N, brow = part * N;       // this wave's first rows in the A / B regions
-  issue(0, L0);
-  issue(1, L1);
-  // chunk 0 has landed (chunk 1 may be in flight). A plain s_barrier, not
-  // __syncthreads(): its release fence would wait for every load in flight
-  // (vmcnt(0)) and serialise the pipeline. Each wave has waited for its own
-  // loads of the chunk consumed next, and its LDS reads of the previous chunk
-  // have returned (their MFMAs consumed them), so the barrier alone orders the
-  // buffer hand-over.
-  wait_vm_barrier<RI>();
-  // step c: prefetch chunk c+2 into the buffer freed by chunk c-1, consume
-  // chunk c, then wait until chunk c+1 has landed (a macro rather than a
-  // lambda: the barrier and wait builtins must stay in device-only code)
-#define AFQ_EXB_STEP(c, cur, pf)                                     \
-  do {                                                               \
-    if ((c) + 2 < nc) issue((c) + 2, pf);                            \
-    else issue_dummy();                                              \
-    __builtin_amdgcn_sched_barrier(0);                               \
-    ring::mma_chunk<TM, REG>(acc, cur, cur + 2 * REG, arow, brow, lane);        \
-    __builtin_amdgcn_sched_barrier(0);                               \
-    wait_vm_barrier<RI>();                                           \
-  } while (0)
-  for (int c = 0; c < nc; c += 3) {
-    AFQ_EXB_STEP(c, L0, L2);
-    if (c + 1 < nc) AFQ_EXB_STEP(c + 1, L1, L0);
-    if (c + 2 < nc) AFQ_EXB_STEP(c + 2, L2, L1);
-  }
-#undef AFQ_EXB_STEP
-  wait_vm_barrier<0>();                           // the tail's tiny loads
+  ring::bf3_stream<TM, TM, REG, REG, RI>(acc, (const lds_t*)L0, (const lds_t*)L1, (const lds_t*)L2, g.kp / KC, arow,
+                                         brow, lane, wave, ld);
   __syncthreads();
 
   // ---- epilogue: lower triangles of both planes of each block in LDS ----

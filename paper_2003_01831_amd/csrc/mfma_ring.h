@@ -8,9 +8,10 @@
 //   * one LDS stage holds four regions (A hi, A lo, B hi, B lo) of REG bytes;
 //     rows are 64 bytes whose 16-byte pieces are XOR-swizzled, so fragment
 //     reads (16 bytes per lane) spread over the banks;
-//   * mma_rect_then multiplies one chunk of a wave's TA x TB block of 16 x 16
+//   * bf3_stream runs the chunk loop of a wave's TA x TB block of 16 x 16
 //     tiles as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
-//     accumulators, in two passes (the A hi fragments resident, then the A lo).
+//     accumulators and the fragments in registers; mma_f32 multiplies one
+//     FP32 chunk on v_mfma_f32_16x16x4f32.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -30,96 +31,14 @@ __device__ inline int swz(int row, int c) { return c ^ ((row >> 1) & 3); }
 
 __device__ inline uint4 lds16(const unsigned char* p) { return *reinterpret_cast<const uint4*>(p); }
 
-__device__ inline bf16x8 frag(const unsigned char* plane, int row, int lq) {
-  return __builtin_bit_cast(bf16x8, lds16(plane + row * ROWB + 16 * swz(row, lq)));
-}
-
-// The same fragment read from an LDS-qualified plane pointer (a ds_read_b128
-// whatever the caller's pointer arithmetic hides from address-space inference)
+// The bf16 fragment of lane (lr, lq) of a 16 x 32 tile starting at `row`: row
+// row + lr, elements 8 lq .. 8 lq + 7, read from an LDS-qualified plane
+// pointer (a ds_read_b128 whatever the caller's pointer arithmetic hides from
+// address-space inference)
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
 typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
 __device__ inline bf16x8 frag3(const lds_t* plane, int row, int lq) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<lds_u32x4*>(plane + row * ROWB + 16 * swz(row, lq)));
-}
-
-// One chunk (32 contraction elements) of this wave's TA x TB block of 16 x 16
-// tiles. A planes at la (hi, then lo PA bytes later), B planes at lb (lo PB
-// bytes after hi); the wave's rows start at arow (A) and brow (B). The
-// callback runs right after the first fragment reads are issued and before
-// the first MFMA: work placed there (the next chunk's global->LDS loads)
-// overlaps the latency of those reads. hi*hi for every row tile, then hi*lo,
-// so consecutive MFMAs never depend on each other's result.
-template <int TA, int TB, int PA, int PB, class F>
-__device__ inline void mma_rect_then(f4 (&acc)[TA][TB], const unsigned char* la, const unsigned char* lb, int arow,
-                                     int brow, int lane, F&& between) {
-  const int lr = lane & 15, lq = lane >> 4;
-  bf16x8 a[TA];
-  bf16x8 bh = frag(lb, brow + lr, lq), bl = frag(lb + PB, brow + lr, lq);
-#pragma unroll
-  for (int i = 0; i < TA; ++i) a[i] = frag(la, arow + 16 * i + lr, lq);
-  between();
-#pragma unroll
-  for (int j = 0; j < TB; ++j) {
-    bf16x8 nh = bh, nl = bl;
-    if (j + 1 < TB) {
-      nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
-      nl = frag(lb + PB, brow + 16 * (j + 1) + lr, lq);
-    }
-#pragma unroll
-    for (int i = 0; i < TA; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < TA; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl, acc[i][j], 0, 0, 0);
-    bh = nh;
-    bl = nl;
-  }
-#pragma unroll
-  for (int i = 0; i < TA; ++i) a[i] = frag(la + PA, arow + 16 * i + lr, lq);
-  bh = frag(lb, brow + lr, lq);
-#pragma unroll
-  for (int j = 0; j < TB; ++j) {
-    bf16x8 nh = bh;
-    if (j + 1 < TB) nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
-#pragma unroll
-    for (int i = 0; i < TA; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
-    bh = nh;
-  }
-}
-
-// The square case with equal plane offsets for the Cholesky-form exchange
-// kernel, whose schedule and register allocation were tuned on this form.
-template <int TM, int RB>
-__device__ inline void mma_chunk(f4 (&acc)[TM][TM], const unsigned char* la, const unsigned char* lb, int arow,
-                                 int brow, int lane) {
-  const int lr = lane & 15, lq = lane >> 4;
-  bf16x8 a[TM];
-#pragma unroll
-  for (int i = 0; i < TM; ++i) a[i] = frag(la, arow + 16 * i + lr, lq);
-  bf16x8 bh = frag(lb, brow + lr, lq), bl = frag(lb + RB, brow + lr, lq);
-#pragma unroll
-  for (int j = 0; j < TM; ++j) {
-    bf16x8 nh = bh, nl = bl;
-    if (j + 1 < TM) {
-      nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
-      nl = frag(lb + RB, brow + 16 * (j + 1) + lr, lq);
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
-#pragma unroll
-    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl, acc[i][j], 0, 0, 0);
-    bh = nh;
-    bl = nl;
-  }
-#pragma unroll
-  for (int i = 0; i < TM; ++i) a[i] = frag(la + RB, arow + 16 * i + lr, lq);
-  bh = frag(lb, brow + lr, lq);
-#pragma unroll
-  for (int j = 0; j < TM; ++j) {
-    bf16x8 nh = bh;
-    if (j + 1 < TM) nh = frag(lb, brow + 16 * (j + 1) + lr, lq);
-#pragma unroll
-    for (int i = 0; i < TM; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bh, acc[i][j], 0, 0, 0);
-    bh = nh;
-  }
 }
 
 // One chunk (16 FP32 contraction elements, 64-byte rows) of this wave's TA x TB
@@ -210,32 +129,29 @@ template <int NQ, int QA> struct StrideLoader {
 // B hi fragments are refilled after the last p2 with KD * TB MFMAs to go and
 // each B lo one after its last MFMA. After p2 of tile 0 every wave has
 // consumed chunk c's fragments: a barrier there (this wave's reads returned)
-// frees chunk c's buffer for the loads of chunk c + 3, spread over the MFMAs
-// that follow. The step ends once chunk c + 2 has landed. Every read and
+// frees chunk c's buffer for the loads of chunk c + 3, one after each of the
+// next NQ MFMAs. The step ends once chunk c + 2 has landed. Every read and
 // load sits between two MFMAs, so the matrix pipe always has queued work
 // while the wave issues them; scheduling barriers keep the order. Past the
-// last chunk the loads fetch chunk 0 again into this wave's trash slice
-// (trash_m, 1 KB), so every step keeps the same wait count.
+// last chunk the loads fetch chunk 0 again into the buffer being refilled
+// (free, and never read as data), so every step keeps the same wait count.
 //
 // On return every load has landed; the caller's epilogue may reuse the LDS
 // after a __syncthreads().
 template <int TA, int TB, int REGA, int REGB, int NQ, class Loader>
 __device__ __forceinline__ void bf3_stream(f4 (&acc)[TA][TB], const lds_t* L0, const lds_t* L1, const lds_t* L2,
-                                           unsigned trash_m, int nc, int arow, int brow, int lane, int wave,
-                                           const Loader& ld) {
+                                           int nc, int arow, int brow, int lane, int wave, const Loader& ld) {
   constexpr int NW = 4;
   constexpr int KD = TA > 2 ? 2 : 1;
   // MFMAs after the barrier outside the deferred tail: the slots of the loads
   constexpr int SPAN = 3 * TA * TB - 2 * TB - KD * TB;
-  static_assert(SPAN > 0, "tile too small for the chunk loop");
+  static_assert(SPAN >= NQ, "tile too small for the chunk loop");
   const int lr = lane & 15, lq = lane >> 4;
   const unsigned voff = (unsigned)((lane >> 2) * ROWB + 16 * swz(lane >> 2, lane & 3));
   auto addr = [](const lds_t* p) { return (unsigned)(uintptr_t)p; };
   const unsigned lds0 = addr(L0) + wave * 1024, lds1 = addr(L1) + wave * 1024, lds2 = addr(L2) + wave * 1024;
-  const unsigned tw = trash_m + wave * 1024;
   auto load = [&](int q, int chunk, unsigned mbuf) {
-    const bool real = chunk < nc;
-    dma16s(ld.src(q, real ? chunk : 0), voff, real ? mbuf + q * NW * 1024 : tw);
+    dma16s(ld.src(q, chunk < nc ? chunk : 0), voff, mbuf + q * NW * 1024);
   };
   bf16x8 ah[TA], al[TA], bh[TB], bl[TB];
 #pragma unroll
@@ -263,16 +179,14 @@ __device__ __forceinline__ void bf3_stream(f4 (&acc)[TA][TB], const lds_t* L0, c
   for (int c = 0; c < nc; ++c) {
     const lds_t* const b1 = (const lds_t*)(uintptr_t)(m1b - wave * 1024);
     int s = 0;                                    // MFMA slot after the barrier (folds to a constant)
-    // the loads of chunk c + 3 placed after slot s
-#define AFQ_RING_LOADS                                  \
-  do {                                                  \
-    _Pragma("unroll") for (int q = 0; q < NQ; ++q) {    \
-      if (q * SPAN / NQ == s) {                         \
-        load(q, c + 3, m0b);                            \
-        AFQ_RING_SB;                                    \
-      }                                                 \
-    }                                                   \
-    ++s;                                                \
+    // load s of chunk c + 3 after slot s (one per slot, the first NQ slots)
+#define AFQ_RING_LOADS                \
+  do {                                \
+    if (s < NQ) {                     \
+      load(s, c + 3, m0b);            \
+      AFQ_RING_SB;                    \
+    }                                 \
+    ++s;                              \
   } while (0)
 #pragma unroll
     for (int i = 0; i < TA; ++i) {

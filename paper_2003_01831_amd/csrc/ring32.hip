@@ -376,7 +376,6 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
   __shared__ __align__(16) unsigned char L0[STAGE];
   __shared__ __align__(16) unsigned char L1[STAGE];
   __shared__ __align__(16) unsigned char L2[STAGE];
-  __shared__ __align__(16) unsigned char trash[NWAVE * 1024];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar address arithmetic
   const int rb = wave >> 1, cb = wave & 1;
@@ -420,7 +419,7 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
     for (int j = 0; j < TB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int arow = rb * (RA / 2), brow = cb * (RB / 2);
   ring::bf3_stream<TA, TB, REGA, REGB, NQ>(acc, (const lds_t*)L0, (const lds_t*)L1, (const lds_t*)L2,
-                                           (unsigned)(uintptr_t)(lds_t*)trash, g.nchunk, arow, brow, lane, wave, ld);
+                                           g.nchunk, arow, brow, lane, wave, ld);
 
   if constexpr (MODE == B3_XFORM) {
     // rows (w0, Re), (w0, Im), (w0 + 1, Re), (w0 + 1, Im); a wave's 64 columns
