@@ -181,8 +181,10 @@ struct afq_system_s {
   int eri_prec = -1;           // precision the tensor was built for (AFQ_BF16X3 or AFQ_FP64)
   DevBuf eri_w[2];             // BF16x3: hi and lo planes, chunk-major [chunk][rows][32] bf16;
                                // FP64: the full symmetric W' (N M x N M f64)
-  DevBuf eri_units[2];         // work units (row block, first chunk, chunks, 0)
+  DevBuf eri_units[2];         // work units (row block, first chunk, chunks, interval)
   int eri_nunit[2] = {0, 0};
+  std::vector<int> eri_units_host[2];   // the same, on the host (the walkers' launch layouts)
+  unsigned eri_gen = 0;        // changes whenever the units are rebuilt
   unsigned version = 0;        // bumped when the step's kernel sequence changes (batches capture again)
   int nspin_n(int s) const { return s == 0 ? n_up : n_dn; }
   int spin_off(int s) const { return s == 0 ? 0 : n_up; }
@@ -258,6 +260,10 @@ struct afq_walkers_s {
   DevBuf eri_theta;            // packed Theta-hat hi / lo planes of one spin
   DevBuf eri_part;             // BF16x3: per (work unit, column) complex partial sums;
                                // FP64: Z^T = Theta-hat^T W'' rows of one spin (nw x N M complex)
+  DevBuf eri_wg[2];            // BF16x3: (work unit, column block) of every workgroup of the launch
+  std::vector<int> eri_wg_host[2];
+  int eri_wg_launch[2] = {0, 0};
+  long eri_wg_key[2] = {-1, -1};   // (units generation, column blocks) the layout was built for
 };
 
 // ---------------------------------------------------------------------------

@@ -75,8 +75,8 @@ struct EriArgs {
   const unsigned char* a[2];   // W'' hi / lo planes: chunk c at row tri_rows_before(c), 32 bf16 per row
   const unsigned char* b[2];   // Theta-hat hi / lo planes: [chunk][rows_b][32] bf16
   long rows_b;
-  const int4* units;           // (row block, first chunk, chunks, 0)
-  int nunit, nblk_b, grid;     // grid: units x column blocks
+  const int4* units;           // (row block, first chunk, chunks, interval)
+  const int2* wg;              // (unit, column block) of workgroup i, unit < 0: idle
   const double2* thetaT;       // nw x ntot x M
   int ntot, M, off, NM, nw;
   int off1, nsp;               // column walkers nsp * nw: walker w of spin 1 (offset off1) at nw + w
@@ -102,14 +102,11 @@ __global__ __launch_bounds__(256, 1) void eri_kernel(EriArgs g) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar address arithmetic
   const int rb = wave >> 1, cb = wave & 1;        // row half (W''), column half (Theta-hat)
-  // XCD-aware order: workgroup i runs on XCD i % 8. XCD x takes the units
-  // x, x + 8, x + 16, ..., each with all its column blocks in a row, which
-  // share the unit's W'' chunks in that XCD's L2; dealing the units out in
-  // turn gives every XCD the same mix of full runs and short tail runs (a
-  // contiguous share per XCD measured 4% slower)
-  const int xcd = (int)(blockIdx.x % NXCD), k = (int)(blockIdx.x / NXCD);
-  const int u = xcd + NXCD * (k / g.nblk_b), bb = k % g.nblk_b;
-  if (u >= g.nunit) return;
+  // the launch layout (host-built, XCD-aware) names this workgroup's unit
+  // and column block
+  const int2 e = g.wg[blockIdx.x];
+  if (e.x < 0) return;
+  const int u = e.x, bb = e.y;
   const int4 un = g.units[u];
   const int c0 = un.y, nc = un.z;                 // nc >= 1
   const long arow0 = (long)un.x * RA, brow0 = (long)bb * RBR;
@@ -322,37 +319,87 @@ size_t plane_bytes(long rows, int nchunk) { return (size_t)rows * nchunk * KC * 
 size_t plane_a_bytes(const Shape& h) { return (size_t)tri_rows_before(h.nchunk) * ROWB; }
 long rows_b_of(int nw) { return (2L * nw + RBR - 1) / RBR * RBR; }
 
-// work units: row block p covers chunks [TA p, nchunk) in runs of kper chunks;
-// ordered run-major (run 0 of every row block, then run 1, ...), so row blocks
-// resident together on one XCD read nearby Theta-hat chunks
-std::vector<int> make_units(const Shape& h, int kper) {
+// work units: row block p covers chunks [CPB p, nchunk), cut at the multiples
+// of the interval length R, so that the units of different row blocks in one
+// interval cover the same chunks (their Theta-hat chunks are then shared by
+// the workgroups resident together on an XCD); unit = (p, first chunk,
+// chunks, interval)
+std::vector<int> make_units(const Shape& h, int R) {
   std::vector<int> u;
-  for (int j = 0;; ++j) {
-    bool any = false;
+  for (int k = 0; (long)k * R < h.nchunk; ++k)
     for (int p = 0; p < h.nblk_a; ++p) {
-      const long c0 = (long)CPB * p + (long)j * kper;
-      if (c0 >= h.nchunk) continue;
-      any = true;
+      const long lo = std::max((long)k * R, (long)CPB * p), hi = std::min((long)(k + 1) * R, (long)h.nchunk);
+      if (lo >= hi) continue;
       u.push_back(p);
-      u.push_back((int)c0);
-      u.push_back((int)std::min<long>(kper, h.nchunk - c0));
-      u.push_back(0);
+      u.push_back((int)lo);
+      u.push_back((int)(hi - lo));
+      u.push_back(k);
     }
-    if (!any) break;
-  }
   return u;
 }
 
-// chunks per unit: about 256 units (with the walker blocks, several thousand
-// workgroups to fill the device many times over), runs of at least 16 chunks;
-// longer runs spread the fixed cost of a workgroup's epilogue and partial sums
-// over more chunks, and with the units dealt out to the XCDs in turn the tail
-// stays balanced (measured best among 128 to 2048 units)
-int choose_kper(const Shape& h) {
+// interval length: the longer the runs, the fewer workgroups pay the fixed
+// cost of the prologue, epilogue and partial sums (at M = 400 whole rows ran
+// 5% faster than runs of 256 chunks and 2% faster than 512). With at least
+// 128 row blocks whole rows fill the device (times the walkers' column
+// blocks); fewer row blocks are cut into about 256 runs of at least 16 chunks.
+int choose_interval(const Shape& h) {
+  if (h.nblk_a >= 128) return h.nchunk;
   long total = 0;
   for (int p = 0; p < h.nblk_a; ++p) total += h.nchunk - (long)CPB * p;
-  const long target = 256;
-  return (int)std::max<long>(16, (total + target - 1) / target);
+  return (int)std::min<long>(h.nchunk, std::max<long>(16, (total + 255) / 256));
+}
+
+// Launch layout: tiles of G row blocks x CBG column blocks (about one XCD's
+// 32 workgroups at one per CU) on one interval, so that each W'' chunk is read
+// by the CBG workgroups of its row block and each Theta-hat chunk by the G
+// row blocks, all resident on one XCD at the same time and sharing its L2.
+// Tiles are dealt to the XCDs longest first, each to the least loaded one
+// (work: chunks plus a fixed cost per workgroup), and laid out so that
+// workgroup i runs on XCD i % 8 (the hardware's round-robin) in that order.
+// Returns (unit, column block) pairs, (-1, -1) for the idle padding.
+std::vector<int> make_wg_layout(const std::vector<int>& units, int nblk_a, int nblk_b) {
+  constexpr long kOverhead = 6;   // fixed cost of a workgroup, in chunks
+  const int CBG = std::min(nblk_b, 8), G = std::max(1, 32 / CBG);
+  const int nu = (int)(units.size() / 4);
+  int nk = 0;
+  for (int i = 0; i < nu; ++i) nk = std::max(nk, units[4 * i + 3] + 1);
+  std::vector<int> at((size_t)nk * nblk_a, -1);   // unit of (interval, row block)
+  for (int i = 0; i < nu; ++i) at[(size_t)units[4 * i + 3] * nblk_a + units[4 * i]] = i;
+  struct Tile { long work; std::vector<int> wg; };
+  std::vector<Tile> tiles;
+  for (int k = 0; k < nk; ++k)
+    for (int p0 = 0; p0 < nblk_a; p0 += G)
+      for (int b0 = 0; b0 < nblk_b; b0 += CBG) {
+        Tile t{0, {}};
+        for (int p = p0; p < std::min(p0 + G, nblk_a); ++p) {
+          const int u = at[(size_t)k * nblk_a + p];
+          if (u < 0) continue;
+          for (int b = b0; b < std::min(b0 + CBG, nblk_b); ++b) {
+            t.wg.push_back(u);
+            t.wg.push_back(b);
+            t.work += units[4 * u + 2] + kOverhead;
+          }
+        }
+        if (!t.wg.empty()) tiles.push_back(std::move(t));
+      }
+  std::stable_sort(tiles.begin(), tiles.end(), [](const Tile& a, const Tile& b) { return a.work > b.work; });
+  std::vector<std::vector<int>> per(NXCD);
+  long load[NXCD] = {};
+  for (const Tile& t : tiles) {
+    const int x = (int)(std::min_element(load, load + NXCD) - load);
+    load[x] += t.work;
+    per[x].insert(per[x].end(), t.wg.begin(), t.wg.end());
+  }
+  size_t len = 0;
+  for (auto& v : per) len = std::max(len, v.size() / 2);
+  std::vector<int> out(2 * NXCD * len, -1);
+  for (int x = 0; x < NXCD; ++x)
+    for (size_t i = 0; i < per[x].size() / 2; ++i) {
+      out[2 * (i * NXCD + x)] = per[x][2 * i];
+      out[2 * (i * NXCD + x) + 1] = per[x][2 * i + 1];
+    }
+  return out;
 }
 
 void eri_free(afq_system s) {
@@ -360,6 +407,7 @@ void eri_free(afq_system s) {
     s->eri_w[sp].free();
     s->eri_units[sp].free();
     s->eri_nunit[sp] = 0;
+    s->eri_units_host[sp].clear();
   }
   s->eri_ready = false;
   s->eri_prec = -1;
@@ -419,7 +467,7 @@ int eri_prepare(afq_system s) {
     const Shape h = shape_of(s, sp);
     AFQ_CHECK(h.NM <= 65535L * 32, AFQ_E_UNSUPPORTED, "exchange (four-index): N M too large");
     const bool f64 = s->prec == AFQ_FP64;
-    const std::vector<int> units = f64 ? std::vector<int>() : make_units(h, choose_kper(h));
+    const std::vector<int> units = f64 ? std::vector<int>() : make_units(h, choose_interval(h));
     DevBuf LT, SL;
     int rc = s->eri_w[sp].alloc(tensor_bytes_of(h, s->prec));
     if (rc == AFQ_OK) rc = LT.alloc((size_t)h.NM * X * 8);
@@ -470,7 +518,9 @@ int eri_prepare(afq_system s) {
       return rc;
     }
     s->eri_nunit[sp] = (int)(units.size() / 4);
+    s->eri_units_host[sp] = units;
   }
+  ++s->eri_gen;
   s->eri_ready = true;
   s->eri_prec = s->prec;
   return AFQ_OK;
@@ -523,6 +573,37 @@ int eri_alloc_scratch(afq_system s, afq_walkers w) {
   }
   if (w->eri_theta.bytes < tb) AFQ_RET(w->eri_theta.alloc(tb));
   if (w->eri_part.bytes < pb) AFQ_RET(w->eri_part.alloc(pb));
+  // launch layouts of the tensor blocks (rebuilt when the units or the
+  // column blocks change; outside any step, so the upload may synchronise)
+  const int nblk_b = (int)(rows_b / RBR);
+  const long key = (long)s->eri_gen * 65536 + nblk_b;
+  bool uploaded = false;
+  for (int wsp = 0; wsp < (s->eri_share ? 1 : 2); ++wsp) {
+    if (w->eri_wg_key[wsp] == key) continue;
+    std::vector<int>& lay = w->eri_wg_host[wsp];
+    lay = make_wg_layout(s->eri_units_host[wsp], shape_of(s, wsp).nblk_a, nblk_b);
+    {   // every (unit, column block) exactly once
+      const long nu = (long)s->eri_units_host[wsp].size() / 4;
+      std::vector<char> seen((size_t)(nu * nblk_b), 0);
+      long n = 0;
+      for (size_t i = 0; i + 1 < lay.size(); i += 2) {
+        if (lay[i] < 0) continue;
+        const long k = (long)lay[i] * nblk_b + lay[i + 1];
+        AFQ_CHECK(lay[i] < nu && lay[i + 1] >= 0 && lay[i + 1] < nblk_b && !seen[k], AFQ_E_STATE,
+                  "exchange (four-index): launch layout");
+        seen[k] = 1;
+        ++n;
+      }
+      AFQ_CHECK(n == nu * nblk_b, AFQ_E_STATE, "exchange (four-index): launch layout incomplete");
+    }
+    AFQ_RET(w->eri_wg[wsp].alloc(lay.size() * sizeof(int)));
+    AFQ_TRY_HIP(hipMemcpyAsync(w->eri_wg[wsp].p, lay.data(), lay.size() * sizeof(int), hipMemcpyHostToDevice,
+                               s->stream));
+    w->eri_wg_launch[wsp] = (int)(lay.size() / 2);
+    w->eri_wg_key[wsp] = key;
+    uploaded = true;
+  }
+  if (uploaded) AFQ_TRY_HIP(hipStreamSynchronize(s->stream));
   return AFQ_OK;
 }
 
@@ -634,17 +715,14 @@ int eri_exchange(afq_system s, afq_walkers w, int sp, hipStream_t st) {
   g.b[1] = g.b[0] + pb;
   g.rows_b = rows_b;
   g.units = s->eri_units[wsp].as<int4>();
-  g.nunit = nunit;
-  g.nblk_b = (int)(rows_b / RBR);
-  const long grid = (long)nunit * g.nblk_b;
-  AFQ_CHECK(grid < (1L << 30), AFQ_E_INVALID, "exchange (four-index): grid too large");
-  g.grid = (int)grid;
+  AFQ_CHECK(w->eri_wg_key[wsp] == (long)s->eri_gen * 65536 + rows_b / RBR && w->eri_wg_launch[wsp] > 0,
+            AFQ_E_STATE, "exchange (four-index): launch layout not prepared");
+  g.wg = w->eri_wg[wsp].as<int2>();
   g.thetaT = w->theta.as<double2>();
   g.ntot = s->ntot; g.M = s->M; g.off = s->spin_off(sp); g.NM = (int)h.NM; g.nw = w->nw;
   g.off1 = s->spin_off(1); g.nsp = nsp;
   g.part = w->eri_part.as<double2>();
-  const long launch = (long)NXCD * ceil_div(nunit, NXCD) * g.nblk_b;   // units interleaved over the XCDs
-  hipLaunchKernelGGL(eri_kernel, dim3((unsigned)launch), dim3(256), 0, st, g);
+  hipLaunchKernelGGL(eri_kernel, dim3((unsigned)w->eri_wg_launch[wsp]), dim3(256), 0, st, g);
   AFQ_TRY_HIP(hipGetLastError());
   for (int q = 0; q < nsp; ++q) {   // spin sp + q: columns 2 (q nw + w) + part
     hipLaunchKernelGGL(eri_reduce_kernel, dim3(w->nw), dim3(256), 0, st, w->eri_part.as<double2>() + 2L * q * w->nw,
