@@ -129,8 +129,8 @@ template <int NQ, int QA> struct StrideLoader {
 // B hi fragments are refilled after the last p2 with KD * TB MFMAs to go and
 // each B lo one after its last MFMA. After p2 of tile 0 every wave has
 // consumed chunk c's fragments: a barrier there (this wave's reads returned)
-// frees chunk c's buffer for the loads of chunk c + 3, one after each of the
-// next NQ MFMAs. The step ends once chunk c + 2 has landed. Every read and
+// frees chunk c's buffer for the loads of chunk c + 3, spread evenly over the
+// MFMAs that follow. The step ends once chunk c + 2 has landed. Every read and
 // load sits between two MFMAs, so the matrix pipe always has queued work
 // while the wave issues them; scheduling barriers keep the order. Past the
 // last chunk the loads fetch chunk 0 again into the buffer being refilled
@@ -146,6 +146,9 @@ __device__ __forceinline__ void bf3_stream(f4 (&acc)[TA][TB], const lds_t* L0, c
   // MFMAs after the barrier outside the deferred tail: the slots of the loads
   constexpr int SPAN = 3 * TA * TB - 2 * TB - KD * TB;
   static_assert(SPAN >= NQ, "tile too small for the chunk loop");
+  // the loads spread evenly over those slots: issued in a burst they queue up
+  // in the CU's vector memory path (1 KB each) and stall the wave's MFMAs
+  constexpr int LSTRIDE = SPAN / NQ;
   const int lr = lane & 15, lq = lane >> 4;
   const unsigned voff = (unsigned)((lane >> 2) * ROWB + 16 * swz(lane >> 2, lane & 3));
   auto addr = [](const lds_t* p) { return (unsigned)(uintptr_t)p; };
@@ -179,14 +182,14 @@ __device__ __forceinline__ void bf3_stream(f4 (&acc)[TA][TB], const lds_t* L0, c
   for (int c = 0; c < nc; ++c) {
     const lds_t* const b1 = (const lds_t*)(uintptr_t)(m1b - wave * 1024);
     int s = 0;                                    // MFMA slot after the barrier (folds to a constant)
-    // load s of chunk c + 3 after slot s (one per slot, the first NQ slots)
-#define AFQ_RING_LOADS                \
-  do {                                \
-    if (s < NQ) {                     \
-      load(s, c + 3, m0b);            \
-      AFQ_RING_SB;                    \
-    }                                 \
-    ++s;                              \
+    // load q of chunk c + 3 after slot q * LSTRIDE
+#define AFQ_RING_LOADS                                  \
+  do {                                                  \
+    if (s % LSTRIDE == 0 && s / LSTRIDE < NQ) {         \
+      load(s / LSTRIDE, c + 3, m0b);                    \
+      AFQ_RING_SB;                                      \
+    }                                                   \
+    ++s;                                                \
   } while (0)
 #pragma unroll
     for (int i = 0; i < TA; ++i) {
