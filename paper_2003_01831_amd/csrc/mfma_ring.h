@@ -142,7 +142,7 @@ template <int TA, int TB, int REGA, int REGB, int NQ, class Loader>
 __device__ __forceinline__ void bf3_stream(f4 (&acc)[TA][TB], const lds_t* L0, const lds_t* L1, const lds_t* L2,
                                            int nc, int arow, int brow, int lane, int wave, const Loader& ld) {
   constexpr int NW = 4;
-  constexpr int KD = TA > 2 ? 2 : 1;
+  constexpr int KD = TA > 3 ? 3 : TA > 2 ? 2 : 1;
   // MFMAs after the barrier outside the deferred tail: the slots of the loads
   constexpr int SPAN = 3 * TA * TB - 2 * TB - KD * TB;
   static_assert(SPAN >= NQ, "tile too small for the chunk loop");
