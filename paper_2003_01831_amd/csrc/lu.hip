@@ -122,11 +122,17 @@ __device__ __forceinline__ void gj_step(double2 (&a)[RB][CB], int k0, int n, int
           if (cc < n) sh.rowp[cc] = c == KC && cg == cgk ? ipiv : cmul(a[i][c], ipiv);
         }
   }
+  // pivot column entry r = rg RB + i at colk[i CKS + rg]: a lane's RB entries
+  // are CKS apart and neighbouring lanes' adjacent, so the 16-byte reads of
+  // the update below do not conflict on banks (the plain order put the lanes
+  // 64 bytes apart)
+  constexpr int CKS = NMAX / RB;
+  static_assert(NMAX % RB == 0, "pivot column layout");
   if (act && cg == cgk) {
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
       const int r = rg * RB + i;
-      if (r < n) sh.colk[r] = a[i][KC];
+      if (r < n) sh.colk[i * CKS + rg] = a[i][KC];
       a[i][KC] = make_double2(0.0, 0.0);
     }
   }
@@ -135,7 +141,7 @@ __device__ __forceinline__ void gj_step(double2 (&a)[RB][CB], int k0, int n, int
   if (act) {
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
-      const double2 ck = sh.colk[rg * RB + i];
+      const double2 ck = sh.colk[i * CKS + rg];
 #pragma unroll
       for (int c = 0; c < CB; ++c) a[i][c] = csub(a[i][c], cmul(ck, sh.rowp[cg * CB + c]));
     }

@@ -408,53 +408,62 @@ int launch_emix(const double2* eloc, const double* wt, int nw, double* out, hipS
   return AFQ_OK;
 }
 
-// Phaseless weight update and walker commit (one workgroup per walker):
+// Phaseless weight update (one thread per walker):
 //   log r = log O' - log O, |I| = |r| exp(Re lfac) exp(dt E_shift),
 //   w <- w |I| max(0, cos(Im log r + Im lfac)) (Im lfac: the phase of the
 //   background's c-number factor, 0 without one); a walker whose weight is not positive and
-//   finite (or whose new overlap is singular) dies and is frozen; otherwise
-//   W <- W'.
-__global__ __launch_bounds__(256) void weight_kernel(WeightArgs a) {
-  const int w = blockIdx.x, t = threadIdx.x;
-  __shared__ int commit;
-  if (t == 0) {
-    int ok = 0;
-    double2 ratio = make_double2(0.0, 0.0);
-    if (a.alive[w]) {
-      const double2 ln_new = cadd(a.logdet_new[2 * w], a.logdet_new[2 * w + 1]);
-      const double2 ln_cur = cadd(a.logdet_cur[2 * w], a.logdet_cur[2 * w + 1]);
-      const bool sing = a.sing_new[2 * w] || a.sing_new[2 * w + 1];
-      const double2 lr = csub(ln_new, ln_cur);
-      const double mag = exp(lr.x);
-      ratio = make_double2(mag * cos(lr.y), mag * sin(lr.y));
-      const double cs = cos(lr.y + a.lfac[w].y);
-      double wn = 0.0;
-      if (cs > 0.0) wn = a.weights[w] * exp(lr.x + a.lfac[w].x + a.dt * a.e_shift) * cs;
-      if (!sing && wn > 0.0 && isfinite(wn)) {
-        if (a.w_cap > 0.0) wn = fmin(wn, a.w_cap);
-        a.weights[w] = wn;
-        ok = 1;
-      } else {
-        a.weights[w] = 0.0;
-        a.alive[w] = 0;
-        atomicAdd(reinterpret_cast<unsigned long long*>(a.killed), 1ull);
-      }
+//   finite (or whose new overlap is singular) dies and is frozen. The walkers
+//   still alive afterwards are exactly those that commit W <- W' (commit_kernel).
+__global__ __launch_bounds__(256) void weight_kernel(WeightArgs a, int nw) {
+  const int w = blockIdx.x * 256 + threadIdx.x;
+  if (w >= nw) return;
+  double2 ratio = make_double2(0.0, 0.0);
+  if (a.alive[w]) {
+    const double2 ln_new = cadd(a.logdet_new[2 * w], a.logdet_new[2 * w + 1]);
+    const double2 ln_cur = cadd(a.logdet_cur[2 * w], a.logdet_cur[2 * w + 1]);
+    const bool sing = a.sing_new[2 * w] || a.sing_new[2 * w + 1];
+    const double2 lr = csub(ln_new, ln_cur);
+    const double mag = exp(lr.x);
+    ratio = make_double2(mag * cos(lr.y), mag * sin(lr.y));
+    const double cs = cos(lr.y + a.lfac[w].y);
+    double wn = 0.0;
+    if (cs > 0.0) wn = a.weights[w] * exp(lr.x + a.lfac[w].x + a.dt * a.e_shift) * cs;
+    if (!sing && wn > 0.0 && isfinite(wn)) {
+      if (a.w_cap > 0.0) wn = fmin(wn, a.w_cap);
+      a.weights[w] = wn;
+    } else {
+      a.weights[w] = 0.0;
+      a.alive[w] = 0;
+      atomicAdd(reinterpret_cast<unsigned long long*>(a.killed), 1ull);
     }
-    if (a.ratio_out) a.ratio_out[w] = ratio;
-    if (a.weights_out) a.weights_out[w] = a.weights[w];
-    commit = ok;
   }
-  __syncthreads();
-  if (!commit) return;
-  const long per = a.per;
-  for (long i = t; i < per; i += 256) a.W[w * per + i] = a.Wn[w * per + i];
-  if (a.sinv) {
-    for (long i = t; i < a.sinv_per; i += 256) a.sinv[w * a.sinv_per + i] = a.sinv_new[w * a.sinv_per + i];
-    if (t < 2) a.logdet_keep[2 * w + t] = a.logdet_new[2 * w + t];
-  }
+  if (a.ratio_out) a.ratio_out[w] = ratio;
+  if (a.weights_out) a.weights_out[w] = a.weights[w];
 }
+
+// Walker commit: W <- W' (and the carried S^-1, log det) for every walker
+// alive after the weight update; workgroup (x, w) copies elements
+// 1024 x .. 1024 x + 1023 of walker w's W' followed by its S^-1 (coalesced,
+// 16 bytes per lane and load)
+__global__ __launch_bounds__(256) void commit_kernel(WeightArgs a) {
+  const int w = blockIdx.y;
+  if (!a.alive[w]) return;
+  const long per = a.per, sper = a.sinv ? a.sinv_per : 0;
+  const long base = (long)blockIdx.x * 1024 + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const long i = base + 256L * u;
+    if (i < per) a.W[w * per + i] = a.Wn[w * per + i];
+    else if (i - per < sper) a.sinv[w * sper + (i - per)] = a.sinv_new[w * sper + (i - per)];
+  }
+  if (a.sinv && blockIdx.x == 0 && threadIdx.x < 2) a.logdet_keep[2 * w + threadIdx.x] = a.logdet_new[2 * w + threadIdx.x];
+}
+
 int launch_weights(const WeightArgs& a, int nw, hipStream_t st) {
-  hipLaunchKernelGGL(weight_kernel, dim3(nw), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(weight_kernel, dim3((nw + 255) / 256), dim3(256), 0, st, a, nw);
+  AFQ_TRY_HIP(hipGetLastError());
+  const long total = a.per + (a.sinv ? a.sinv_per : 0);
+  hipLaunchKernelGGL(commit_kernel, dim3((unsigned)((total + 1023) / 1024), nw), dim3(256), 0, st, a);
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }
