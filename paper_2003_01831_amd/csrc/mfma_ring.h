@@ -136,9 +136,16 @@ template <int NQ, int QA> struct StrideLoader {
 // last chunk the loads fetch chunk 0 again into the buffer being refilled
 // (free, and never read as data), so every step keeps the same wait count.
 //
+// With CB (compact B) the B operand is the real form of a complex matrix,
+// rows 2m + part, contraction 2k + p: row (m, 0) = [Re a, -Im a], row (m, 1)
+// = [Im a, Re a] over k (a = a_mk). Only rows m = [Re a, Im a] are stored
+// (REGB holds half as many rows); lane lr reads row (brow + 16 j + lr) / 2
+// and forms its real-form row in registers, exactly: part 0 flips the sign
+// of the odd elements, part 1 swaps each pair.
+//
 // On return every load has landed; the caller's epilogue may reuse the LDS
 // after a __syncthreads().
-template <int TA, int TB, int REGA, int REGB, int NQ, class Loader>
+template <int TA, int TB, int REGA, int REGB, int NQ, bool CB = false, class Loader>
 __device__ __forceinline__ void bf3_stream(f4 (&acc)[TA][TB], const lds_t* L0, const lds_t* L1, const lds_t* L2,
                                            int nc, int arow, int brow, int lane, int wave, const Loader& ld) {
   constexpr int NW = 4;
@@ -156,6 +163,18 @@ __device__ __forceinline__ void bf3_stream(f4 (&acc)[TA][TB], const lds_t* L0, c
   auto load = [&](int q, int chunk, unsigned mbuf) {
     dma16s(ld.src(q, chunk < nc ? chunk : 0), voff, mbuf + q * NW * 1024);
   };
+  // B fragment j of the plane at p (real-form row brow + 16 j + lr)
+  const unsigned rot = CB && (lr & 1) ? 16u : 0u, flip = CB && !(lr & 1) ? 0x80000000u : 0u;
+  auto fragb = [&](const lds_t* p, int j) -> bf16x8 {
+    if constexpr (!CB) {
+      return frag3(p, brow + 16 * j + lr, lq);
+    } else {
+      u32x4 d = __builtin_bit_cast(u32x4, frag3(p, (brow + 16 * j + lr) >> 1, lq));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) d[e] = __builtin_amdgcn_alignbit(d[e], d[e], rot) ^ flip;
+      return __builtin_bit_cast(bf16x8, d);
+    }
+  };
   bf16x8 ah[TA], al[TA], bh[TB], bl[TB];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) load(q, 0, lds0);
@@ -171,8 +190,8 @@ __device__ __forceinline__ void bf3_stream(f4 (&acc)[TA][TB], const lds_t* L0, c
   }
 #pragma unroll
   for (int j = 0; j < TB; ++j) {
-    bh[j] = frag3(L0 + 2 * REGA, brow + 16 * j + lr, lq);
-    bl[j] = frag3(L0 + 2 * REGA + REGB, brow + 16 * j + lr, lq);
+    bh[j] = fragb(L0 + 2 * REGA, j);
+    bl[j] = fragb(L0 + 2 * REGA + REGB, j);
   }
   wait_vm_barrier<NQ>();                          // chunk 1 has landed
   // b0: chunk c (in registers), b1: chunk c + 1 (landed), b2: chunk c + 2
@@ -229,8 +248,8 @@ __device__ __forceinline__ void bf3_stream(f4 (&acc)[TA][TB], const lds_t* L0, c
       for (int j = 0; j < TB; ++j) {
         AFQ_RING_MFMA(ah[i], bl[j], i, j);
         AFQ_RING_SB;
-        if (d == 0) bh[j] = frag3(b1 + 2 * REGA, brow + 16 * j + lr, lq);
-        if (d == KD - 1) bl[j] = frag3(b1 + 2 * REGA + REGB, brow + 16 * j + lr, lq);
+        if (d == 0) bh[j] = fragb(b1 + 2 * REGA, j);
+        if (d == KD - 1) bl[j] = fragb(b1 + 2 * REGA + REGB, j);
         AFQ_RING_SB;
       }
       ah[i] = frag3(b1, arow + 16 * i + lr, lq);

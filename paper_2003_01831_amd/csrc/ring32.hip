@@ -369,10 +369,16 @@ enum { B3_HORNER = 0, B3_HORNER_LAST = 1, B3_B1 = 2, B3_XFORM = 3 };
 template <int TA, int TB, int MODE>
 __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
   constexpr bool LAST = MODE != B3_HORNER;   // the input is U (or U_base): FP64
-  constexpr int RA = 32 * TA, RB = 32 * TB, REGA = RA * ROWB, REGB = RB * ROWB;
-  constexpr int STAGE = 2 * REGA + 2 * REGB, NT = STAGE / 1024, NQ = NT / NWAVE;
+  // the Horner products read A_w in compact form (half the rows, see bf3_stream)
+  constexpr bool CB = MODE == B3_HORNER || MODE == B3_HORNER_LAST;
+  constexpr int RA = 32 * TA, RB = 32 * TB, RBS = CB ? RB / 2 : RB;   // RBS: stored B rows per tile
+  constexpr int REGA = RA * ROWB, REGB = RBS * ROWB;
+  // loads: A hi, A lo, B hi, B lo, then padding to a multiple of the waves
+  // (extra loads fetch B rows again into the padding of the stage)
+  constexpr int NTR = (2 * REGA + 2 * REGB) / 1024, NT = (NTR + NWAVE - 1) / NWAVE * NWAVE, NQ = NT / NWAVE;
+  constexpr int STAGE = NT * 1024;
   constexpr int QA = (RA / 8) / NWAVE;        // the first QA loads of every wave move A rows
-  static_assert(NT % NWAVE == 0 && (RA / 8) % NWAVE == 0, "loads must split evenly over the waves");
+  static_assert((RA / 8) % NWAVE == 0, "A loads must split evenly over the waves");
   __shared__ __align__(16) unsigned char L0[STAGE];
   __shared__ __align__(16) unsigned char L1[STAGE];
   __shared__ __align__(16) unsigned char L2[STAGE];
@@ -407,10 +413,11 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int t = q * NWAVE + wave;
-    const int reg = t < RA / 16 ? 0 : t < RA / 8 ? 1 : t < RA / 8 + RB / 16 ? 2 : 3;
-    const int j = reg == 0 ? t : reg == 1 ? t - RA / 16 : reg == 2 ? t - RA / 8 : t - RA / 8 - RB / 16;
+    const int tt = t < NTR ? t : RA / 8;      // padding loads: B hi rows again
+    const int reg = tt < RA / 16 ? 0 : tt < RA / 8 ? 1 : tt < RA / 8 + RBS / 16 ? 2 : 3;
+    const int j = reg == 0 ? tt : reg == 1 ? tt - RA / 16 : reg == 2 ? tt - RA / 8 : tt - RA / 8 - RBS / 16;
     const unsigned char* base = reg == 0 ? abase : reg == 1 ? abase + g.a_plane : reg == 2 ? bbase : bbase + g.b_plane;
-    ld.qb[q] = base + ((q < QA ? arow0 : brow0) + 16 * j) * ROWB;
+    ld.qb[q] = base + ((q < QA ? arow0 : (long)bb * RBS) + 16 * j) * ROWB;
   }
   f4 acc[TA][TB];
 #pragma unroll
@@ -418,14 +425,15 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
 #pragma unroll
     for (int j = 0; j < TB; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int arow = rb * (RA / 2), brow = cb * (RB / 2);
-  ring::bf3_stream<TA, TB, REGA, REGB, NQ>(acc, (const lds_t*)L0, (const lds_t*)L1, (const lds_t*)L2,
-                                           g.nchunk, arow, brow, lane, wave, ld);
+  ring::bf3_stream<TA, TB, REGA, REGB, NQ, CB>(acc, (const lds_t*)L0, (const lds_t*)L1, (const lds_t*)L2,
+                                               g.nchunk, arow, brow, lane, wave, ld);
 
   if constexpr (MODE == B3_XFORM) {
     // rows (w0, Re), (w0, Im), (w0 + 1, Re), (w0 + 1, Im); a wave's 64 columns
     // are one block pair (m in block bm, k in block bk): A_w[m][k] and, off the
-    // diagonal blocks, its mirror A_w[k][m], each as rows (m, Re) = [.., ar,
-    // -ai, ..] and (m, Im) = [.., ai, ar, ..] at elements 2k, 2k + 1
+    // diagonal blocks, its mirror A_w[k][m], in compact form: row m = [.., ar,
+    // ai, ..] at elements 2k, 2k + 1 (the Horner products form the real-form
+    // rows (m, Re) = [ar, -ai] and (m, Im) = [ai, ar] from it in registers)
     const int lr = lane & 15, lq = lane >> 4;
 #pragma unroll
     for (int i = 0; i < TA; ++i)
@@ -437,26 +445,21 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
         const int code = g.tri[col >> 6], bm = code >> 16, bk = code & 0xffff;
         const int m = 8 * bm + (int)((col >> 3) & 7), k = 8 * bk + (int)(col & 7);
         if (m >= g.M || k >= g.M) continue;
-        const long b0 = ((long)(k >> 4) * g.x_rows + 2 * m) * ROWB + 4 * (k & 15);
-        const long b1 = ((long)(m >> 4) * g.x_rows + 2 * k) * ROWB + 4 * (m & 15);
+        const long b0 = ((long)(k >> 4) * g.x_rows + m) * ROWB + 4 * (k & 15);
+        const long b1 = ((long)(m >> 4) * g.x_rows + k) * ROWB + 4 * (m & 15);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int wk = (int)(row0 >> 1) + h;
           if (wk < g.nw) {
             const float ar = acc[i][j][2 * h], ai = acc[i][j][2 * h + 1];
             unsigned char* X = g.x + (long)wk * g.x_wstride;
-            unsigned rh, rl, ih, il;
-            split_pair(ar, -ai, rh, rl);
-            split_pair(ai, ar, ih, il);
-            *reinterpret_cast<unsigned*>(X + b0) = rh;
-            *reinterpret_cast<unsigned*>(X + b0 + ROWB) = ih;
-            *reinterpret_cast<unsigned*>(X + g.x_plane + b0) = rl;
-            *reinterpret_cast<unsigned*>(X + g.x_plane + b0 + ROWB) = il;
+            unsigned ch, cl;
+            split_pair(ar, ai, ch, cl);
+            *reinterpret_cast<unsigned*>(X + b0) = ch;
+            *reinterpret_cast<unsigned*>(X + g.x_plane + b0) = cl;
             if (bm != bk) {
-              *reinterpret_cast<unsigned*>(X + b1) = rh;
-              *reinterpret_cast<unsigned*>(X + b1 + ROWB) = ih;
-              *reinterpret_cast<unsigned*>(X + g.x_plane + b1) = rl;
-              *reinterpret_cast<unsigned*>(X + g.x_plane + b1 + ROWB) = il;
+              *reinterpret_cast<unsigned*>(X + b1) = ch;
+              *reinterpret_cast<unsigned*>(X + g.x_plane + b1) = cl;
             }
           }
         }
@@ -939,7 +942,7 @@ struct TaylorB3Shape {
 TaylorB3Shape taylor_b3_shape(afq_system s) {
   TaylorB3Shape t;
   t.tile = b3_tile_of(s);
-  t.x_rows = pad_to(2L * s->M, 32L * kB3Tiles[t.tile].tb);
+  t.x_rows = pad_to((long)s->M, 16L * kB3Tiles[t.tile].tb);   // compact rows m of A_w
   t.y_rows = pad_to(s->ntot, 32L * kB3Tiles[t.tile].ta);
   t.kchunk = pad_to(2L * s->M, ring::KC) / ring::KC;
   t.x_plane = t.kchunk * t.x_rows * ROWB;
@@ -1289,7 +1292,7 @@ static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st,
                 w->r32_y[1].bytes >= (size_t)w->nw * tb.y_wstride && w->r32_y[2].bytes >= (size_t)w->nw * tb.y_wstride,
             AFQ_E_STATE, "Taylor propagator (split BF16): walker scratch not prepared");
   const B3Tile tl = kB3Tiles[tb.tile];
-  AFQ_CHECK(ts.y_rows == tb.y_rows && tb.y_rows % (32 * tl.ta) == 0 && tb.x_rows % (32 * tl.tb) == 0, AFQ_E_INVALID,
+  AFQ_CHECK(ts.y_rows == tb.y_rows && tb.y_rows % (32 * tl.ta) == 0 && tb.x_rows % (16 * tl.tb) == 0, AFQ_E_INVALID,
             "Taylor propagator (split BF16): bad shape");
   if (order < 1) return AFQ_OK;
   // V in FP32 (added by every epilogue) and as BF16 planes (the first input),
@@ -1313,7 +1316,7 @@ static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st,
   g.b_wstride = tb.x_wstride;
   g.nchunk = (int)tb.kchunk;
   g.nblk_a = (int)(tb.y_rows / (32 * tl.ta));
-  g.nblk_b = (int)(tb.x_rows / (32 * tl.tb));
+  g.nblk_b = (int)(tb.x_rows / (16 * tl.tb));
   g.nw = w->nw;
   const long grid = (long)g.nblk_a * g.nblk_b * w->nw;
   AFQ_CHECK(grid < (1L << 30), AFQ_E_INVALID, "Taylor propagator (split BF16): too many workgroups");
