@@ -33,12 +33,14 @@
 // 72-74 KB of LDS, two workgroups per CU.
 //
 // In split-BF16x3 mode the Horner products run on v_mfma_f32_16x16x32_bf16
-// instead (hi*hi + hi*lo + lo*hi, FP32 accumulation): the propagator build
-// writes A in the same real form as BF16 hi / lo planes, and each product's
-// epilogue adds V (FP32) and splits the next term into hi / lo planes. Every
-// term is multiplied by A again before it reaches U, and |A| is small
-// (O(sqrt(dt)) per Cholesky vector), so the BF16 products' rounding reaches U
-// damped by |A|; the last product is still added to V in FP64.
+// instead (hi*hi + hi*lo + lo*hi, FP32 accumulation; the shared chunk loop
+// of mfma_ring.h): the propagator build writes A in compact form as BF16 hi /
+// lo planes (rows m = [Re A, Im A] over k, the products form the real-form
+// rows in registers), and each product's epilogue adds V (FP32) and splits
+// the next term into hi / lo planes. Every term is multiplied by A again
+// before it reaches U, and |A| is small (O(sqrt(dt)) per Cholesky vector), so
+// the BF16 products' rounding reaches U damped by |A|; the last product is
+// still added to V in FP64.
 #include <algorithm>
 #include <vector>
 #include <type_traits>
@@ -331,16 +333,17 @@ __global__ __launch_bounds__(256, 2) void ring32_kernel(R32Args g) {
 // hi / lo planes of 32-element chunks, [chunk][rows][32] per plane, a walker's
 // hi plane then its lo plane:
 //   * B3_HORNER(_LAST): the contraction of EPI_HORNER (walker columns h, rows n,
-//     against the real form of A, rows 2m + part);
+//     against the real form of A, rows 2m + part, formed in registers from
+//     the compact rows m = [Re A, Im A] that are stored);
 //   * B3_B1: the contraction of EPI_B1 (walker rows (n, Re|Im) against the rows
 //     m of B1 - I, shared by all walkers: b_wstride 0), added to U_base in FP64;
 //   * B3_XFORM: the propagator build (coefficient rows against the upper block
 //     triangle of L, one batch; consecutive workgroups take consecutive
 //     coefficient row blocks, so they share an L block in L2), A_w written in
-//     real form as BF16 hi / lo planes.
+//     compact form (rows m = [Re A, Im A] over k) as BF16 hi / lo planes.
 struct HornerB3Args {
   const unsigned char* a;   // terms h: rows n, contraction 2m + part
-  const unsigned char* b;   // real form of A: rows 2m + part, contraction 2k + part
+  const unsigned char* b;   // A in compact form, rows m (Horner), or B1 - I (rows m)
   long rows_a, rows_b, a_plane, b_plane, a_wstride, b_wstride;   // bytes (planes, walkers)
   int nchunk, nblk_a, nblk_b, nw, grid;
   const float* vy;          // V in the FP32 packed term layout (16-element chunks)
@@ -351,8 +354,8 @@ struct HornerB3Args {
   float scale;
   int ntot, M;
   // B3_XFORM: coefficient rows (w, Re|Im) against the block-pair columns of L
-  // (tri, ncol); A_w in real form to BF16 planes x (x_rows rows, x_plane bytes
-  // apart, walkers x_wstride bytes apart)
+  // (tri, ncol); A_w in compact form to BF16 planes x (x_rows rows, x_plane
+  // bytes apart, walkers x_wstride bytes apart)
   const int* tri;
   unsigned char* x;
   long x_rows, x_plane, x_wstride, ncol;
