@@ -169,6 +169,9 @@ def test_uneven_spins_and_dead_walkers(api):
     live = o["alive"]
     assert rel_vec(g["weights"][-1][live], o["weights"][-1][live]) < 1e-9
     assert rel_vec(g["emix"], o["emix"]) < 1e-9
+    # a dead walker keeps the W of its last committed step; a live one took every step's W'
+    assert rel_fro(g["W"][~live], o["W"][~live]) < 1e-8
+    assert rel_fro(g["W"][live], o["W"][live]) < 1e-8
 
 
 def test_device_philox_matches_cpu(api):
