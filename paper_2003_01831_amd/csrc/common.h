@@ -140,7 +140,7 @@ struct afq_system_s {
   DevBuf ht;                   // (T^H h)  ntot x M complex
   DevBuf Lt;                   // (T^H L^n) X x ntot x M complex
   DevBuf LtRe;                 // real part of Lt (real trial, split-BF16x3 force bias)
-  DevBuf phitr;                // real trial: T^T (ntot x M f64), the overlap GEMM's k-contiguous operand
+  DevBuf phir;                 // real trial: Re T (M x ntot f64), the overlap kernel's trial operand
   DevBuf apack[2];             // packed A operand per spin (precision of prec)
   DevBuf apack_lo[2];          // BF16x3 low parts
   int apack_prec = -1;
@@ -217,7 +217,7 @@ struct afq_walkers_s {
   DevBuf bp_psi;               // back-propagated trial (nw x M x ntot c128)
   DevBuf bp_stats;             // 2 doubles: sum of weights, singular count
   // per-step scratch
-  DevBuf S, Sinv, SinvT;       // per (w, spin): n x n complex (max n^2 stride); SinvT = (S^-1)^T
+  DevBuf S, Sinv;              // per (w, spin): n x n complex (max n^2 stride)
   DevBuf Sinv_new;             // S^-1 of the propagated walkers (carried to the next step)
   bool s_carried = false;      // Sinv and logdet are those of the current W (set by a step's weight phase)
   DevBuf logdet, logdet_new;   // nw x 2 complex

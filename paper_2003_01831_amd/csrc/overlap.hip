@@ -1,0 +1,316 @@
+// The two FP64 walker products around the overlap inverse (sec:afqmc: the
+// mixed Green's function G = W (T^H W)^-1 T^H), on v_mfma_f64_16x16x4f64:
+//
+//   overlap  S^s_w = T^sH W^s_w          (n x n per walker and spin, contraction over the M basis functions)
+//   theta    Theta^s_w = W^s_w (S^s_w)^-1, stored transposed as thetaT[w][off_s + b][k]
+//
+// Both have an output side of n <= 128 electrons, which the general tiled GEMM
+// pads to 32-row wave tiles (100 -> 128); here every wave owns whole 16-wide
+// MFMA blocks over all of n (100 -> 112), the spins share one launch, and the
+// contraction runs to its exact length in steps of 4 (no padding of k or j).
+// Complex products are four real MFMAs (Re += ar br - ai bi, Im += ar bi +
+// ai br); a real trial drops the terms of its zero imaginary part.
+//
+// Contraction index of MFMA step s in a 16-wide chunk c: lanes of quarter q
+// (lane >> 4) supply index 16 c + 4 s + q for both operands; a chunk's
+// trailing steps past the end are skipped (uniform branch) and the entries
+// past the end inside a step are zero.
+#include "common.h"
+#include <type_traits>
+#include "step_kernels.h"
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mma(d4 c, double a, double b) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+struct OvlArgs {
+  const double2* W;      // walker w at W + w * M * ntot; (k, c) at k * ntot + c
+  const double* phir;    // real trial: Re T, [M][ntot]; else NULL
+  const double2* phi;    // complex trial: T, [M][ntot]
+  double2* S;            // (w, s) at S + (2 w + s) * nm2, row-major n_s x n_s
+  long nm2;
+  int M, ntot, nw;
+  int n[2], off[2];
+};
+
+// S^s_w[a][j] = sum_k conj(T[k][off + a]) W_w[k][off + j]. The columns (w, j)
+// of all walkers of a spin are numbered w n + j and cut into 16-wide blocks
+// (a block may straddle two walkers: every lane finds its own); workgroups of
+// four waves, one column block each, every wave holding all row blocks a. The
+// trial's rows are the operand all waves share: staged through LDS 16 basis
+// functions at a time (double buffered, one barrier per chunk); the walker
+// fragments come straight from memory, one chunk ahead.
+template <int NB, bool CA>
+__global__ __launch_bounds__(256) void overlap_kernel(OvlArgs g) {
+  using TE = typename std::conditional<CA, double2, double>::type;
+  constexpr int NC = NB * 16, PER = 16 * NC / 256;   // PER = NB
+  __shared__ TE As[2][16][NC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int sp = blockIdx.y;
+  const int n = g.n[sp], off = g.off[sp], M = g.M, ntot = g.ntot;
+  const long ncol = (long)g.nw * n;
+  if (64L * blockIdx.x >= ncol) return;   // whole workgroup (the grid covers the larger spin)
+  const int r = lane & 15, q = lane >> 4;
+  const long col0 = 16L * (4 * blockIdx.x + wave), col = col0 + r;
+  const bool cok = col < ncol;
+  const int w = cok ? (int)(col / n) : 0, j = cok ? (int)(col - (long)w * n) : 0;
+  const double2* Wl = g.W + (long)w * M * ntot + off + j;   // this lane's column; row k at k * ntot
+  const int nchunk = (M + 15) / 16;
+
+  TE st[PER];
+  auto fetch_a = [&](int c) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, row = e / NC, a = e - row * NC, k = 16 * c + row;
+      const bool ok = k < M && a < n;
+      if constexpr (CA) st[u] = ok ? g.phi[(long)k * ntot + off + a] : make_double2(0.0, 0.0);
+      else st[u] = ok ? g.phir[(long)k * ntot + off + a] : 0.0;
+    }
+  };
+  auto stash_a = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, row = e / NC, a = e - row * NC;
+      As[buf][row][a] = st[u];
+    }
+  };
+  double2 bv[4], nb[4];
+  auto fetch_b = [&](int c, double2 (&x)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 16 * c + 4 * s + q;
+      x[s] = cok && k < M ? Wl[(long)k * ntot] : make_double2(0.0, 0.0);
+    }
+  };
+
+  d4 accr[NB], acci[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) accr[i] = acci[i] = d4{0.0, 0.0, 0.0, 0.0};
+
+  fetch_a(0);
+  fetch_b(0, bv);
+  stash_a(0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunk) {
+      fetch_a(c + 1);
+      fetch_b(c + 1, nb);
+    }
+    // MFMA steps of this chunk (none for a column block past the last walker, which only helps stage)
+    const int ns = col0 < ncol ? min(4, (M - 16 * c + 3) / 4) : 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (s < ns) {
+        TE a[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) a[i] = As[buf][4 * s + q][16 * i + r];
+        const double br = bv[s].x, bi = bv[s].y;
+        if constexpr (CA) {   // A = conj(T): Re a, -Im a
+#pragma unroll
+          for (int i = 0; i < NB; ++i) accr[i] = mma(accr[i], a[i].x, br);
+#pragma unroll
+          for (int i = 0; i < NB; ++i) acci[i] = mma(acci[i], a[i].x, bi);
+#pragma unroll
+          for (int i = 0; i < NB; ++i) accr[i] = mma(accr[i], a[i].y, bi);
+#pragma unroll
+          for (int i = 0; i < NB; ++i) acci[i] = mma(acci[i], -a[i].y, br);
+        } else {
+#pragma unroll
+          for (int i = 0; i < NB; ++i) accr[i] = mma(accr[i], a[i], br);
+#pragma unroll
+          for (int i = 0; i < NB; ++i) acci[i] = mma(acci[i], a[i], bi);
+        }
+      }
+    }
+    if (c + 1 < nchunk) {
+      stash_a(buf ^ 1);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) bv[s] = nb[s];
+    }
+    __syncthreads();
+  }
+  // lane holds rows 16 i + q + 4 t (a) of its column (w, j)
+  if (cok) {
+    double2* Sw = g.S + (2L * w + sp) * g.nm2 + j;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int a = 16 * i + q + 4 * t;
+        if (a < n) Sw[(long)a * n] = make_double2(accr[i][t], acci[i][t]);
+      }
+  }
+}
+
+struct ThetaArgs {
+  const double2* W;      // as in OvlArgs
+  const double2* Sinv;   // (w, s) at Sinv + (2 w + s) * nm2, row-major n_s x n_s
+  double2* thetaT;       // walker w at thetaT + w * ntot * M; (off_s + b, k) at (off_s + b) * M + k
+  long nm2;
+  int M, ntot, nw, nkg, nwv;   // nkg workgroups of nwv waves per walker and spin
+  int n[2], off[2];
+};
+
+// thetaT[w][off + b][k] = sum_j Sinv[j][b] W[k][off + j]: MFMA rows b (A =
+// Sinv^T), columns k (B = W^T), so that a lane quarter stores 16 consecutive
+// basis functions. Workgroup: nwv waves over consecutive 16-wide column
+// blocks of one walker and spin; each wave holds every row block b against
+// its column block. S^-1 is the operand all waves share: staged through LDS
+// 16 rows j at a time (double buffered); the W fragments come straight from
+// memory, one chunk ahead. Workgroups are numbered so that the nkg of one
+// walker land on one XCD (dispatch i goes to XCD i mod 8) and share S^-1 in
+// its L2. At NB = 8 the accumulators leave room for 4 waves only.
+template <int NB>
+__global__ __launch_bounds__(NB == 8 ? 256 : 512) void theta_kernel(ThetaArgs g) {
+  constexpr int NC = NB * 16, PER = 16 * NC / 256;   // staged elements per thread with >= 4 waves
+  __shared__ double2 As[2][16][NC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), nt = blockDim.x;
+  const int sp = blockIdx.y, lin = blockIdx.x;
+  const int w = (lin / (8 * g.nkg)) * 8 + (lin & 7), kg = (lin >> 3) % g.nkg;
+  const int n = g.n[sp], off = g.off[sp], M = g.M, ntot = g.ntot;
+  if (n == 0 || w >= g.nw) return;   // whole workgroup
+  const double2* Ww = g.W + (long)w * M * ntot + off;
+  const double2* Si = g.Sinv + (2L * w + sp) * g.nm2;
+  const int r = lane & 15, q = lane >> 4;
+  const int k0 = 16 * (kg * g.nwv + wave), k = k0 + r;   // this lane's column (basis function)
+  const bool kcol = k < M;
+  const int nchunk = (n + 15) / 16;
+
+  double2 st[PER];
+  auto fetch_a = [&](int c) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + nt * u, row = e / NC, col = e - row * NC, j = 16 * c + row;
+      st[u] = e < 16 * NC && j < n && col < n ? Si[(long)j * n + col] : make_double2(0.0, 0.0);
+    }
+  };
+  auto stash_a = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + nt * u, row = e / NC, col = e - row * NC;
+      if (e < 16 * NC) As[buf][row][col] = st[u];
+    }
+  };
+  double2 bv[4], nb[4];
+  auto fetch_b = [&](int c, double2 (&x)[4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int j = 16 * c + 4 * s + q;
+      x[s] = kcol && j < n ? Ww[(long)k * ntot + j] : make_double2(0.0, 0.0);
+    }
+  };
+
+  d4 accr[NB], acci[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) accr[i] = acci[i] = d4{0.0, 0.0, 0.0, 0.0};
+
+  fetch_a(0);
+  fetch_b(0, bv);
+  stash_a(0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunk) {
+      fetch_a(c + 1);
+      fetch_b(c + 1, nb);
+    }
+    // MFMA steps of this chunk (none for a column block past M, which only helps stage)
+    const int ns = k0 < M ? min(4, (n - 16 * c + 3) / 4) : 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (s < ns) {
+        double2 a[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) a[i] = As[buf][4 * s + q][16 * i + r];
+        const double br = bv[s].x, bi = bv[s].y;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) accr[i] = mma(accr[i], a[i].x, br);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) acci[i] = mma(acci[i], a[i].x, bi);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) accr[i] = mma(accr[i], -a[i].y, bi);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) acci[i] = mma(acci[i], a[i].y, br);
+      }
+    }
+    if (c + 1 < nchunk) {
+      stash_a(buf ^ 1);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) bv[s] = nb[s];
+    }
+    __syncthreads();
+  }
+  // lane holds rows 16 i + q + 4 t (b), column k of each block
+  if (kcol) {
+    double2* Tw = g.thetaT + (long)w * ntot * M + (long)off * M + k;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int b = 16 * i + q + 4 * t;
+        if (b < n) Tw[(long)b * M] = make_double2(accr[i][t], acci[i][t]);
+      }
+  }
+}
+
+// waves per theta workgroup: 4 or 8, so that the two waves per SIMD that the
+// accumulators leave room for are evenly spread; 8 only where it leaves no
+// more column blocks idle
+int theta_waves(int nblk) { return ceil_div(nblk, 8) * 8 == ceil_div(nblk, 4) * 4 ? 8 : 4; }
+
+}  // namespace
+
+int overlap_mfma(const double2* W, const double* phir, const double2* phi, int M, int ntot, int nw, const int n[2],
+                 const int off[2], double2* S, long nm2, hipStream_t st) {
+  const int nmax = std::max(n[0], n[1]);
+  AFQ_CHECK(nmax >= 1 && nmax <= 128 && (phir || phi) && M >= 1 && nw >= 0, AFQ_E_INVALID,
+            "overlap: n must be in [1, 128], a trial is needed");
+  AFQ_CHECK(nm2 >= (long)nmax * nmax, AFQ_E_INVALID, "overlap: matrix stride < n^2");
+  if (nw == 0) return AFQ_OK;
+  OvlArgs g{};
+  g.W = W; g.phir = phir; g.phi = phi; g.S = S; g.nm2 = nm2;
+  g.M = M; g.ntot = ntot; g.nw = nw;
+  for (int s = 0; s < 2; ++s) { g.n[s] = n[s]; g.off[s] = off[s]; }
+  const long blocks = ((long)nw * nmax + 63) / 64;   // four 16-wide column blocks per workgroup
+  AFQ_CHECK(blocks <= INT32_MAX, AFQ_E_INVALID, "overlap: too many workgroups");
+  const dim3 grid((unsigned)blocks, 2);
+  const int nb = (nmax + 15) / 16;
+#define AFQ_OVL(NB_)                                                                                   \
+  case NB_:                                                                                            \
+    if (phir) hipLaunchKernelGGL((overlap_kernel<NB_, false>), grid, dim3(256), 0, st, g);             \
+    else hipLaunchKernelGGL((overlap_kernel<NB_, true>), grid, dim3(256), 0, st, g);                   \
+    break;
+  switch (nb) { AFQ_OVL(1) AFQ_OVL(2) AFQ_OVL(3) AFQ_OVL(4) AFQ_OVL(5) AFQ_OVL(6) AFQ_OVL(7) AFQ_OVL(8) }
+#undef AFQ_OVL
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+
+int theta_mfma(const double2* W, const double2* Sinv, int M, int ntot, int nw, const int n[2], const int off[2],
+               long nm2, double2* thetaT, hipStream_t st) {
+  const int nmax = std::max(n[0], n[1]);
+  AFQ_CHECK(nmax >= 1 && nmax <= 128 && M >= 1 && nw >= 0, AFQ_E_INVALID, "theta: n must be in [1, 128]");
+  AFQ_CHECK(nm2 >= (long)nmax * nmax, AFQ_E_INVALID, "theta: matrix stride < n^2");
+  if (nw == 0) return AFQ_OK;
+  ThetaArgs g{};
+  g.W = W; g.Sinv = Sinv; g.thetaT = thetaT; g.nm2 = nm2;
+  g.M = M; g.ntot = ntot; g.nw = nw;
+  for (int s = 0; s < 2; ++s) { g.n[s] = n[s]; g.off[s] = off[s]; }
+  const int nblk = (M + 15) / 16;
+  const int nb = (nmax + 15) / 16;
+  g.nwv = nb == 8 ? 4 : theta_waves(nblk);
+  g.nkg = ceil_div(nblk, g.nwv);
+  // walkers padded to a multiple of 8 (the XCD numbering); the padding returns at once
+  const long blocks = (long)ceil_div(nw, 8) * 8 * g.nkg;
+  AFQ_CHECK(blocks <= INT32_MAX, AFQ_E_INVALID, "theta: too many workgroups");
+  const dim3 grid((unsigned)blocks, 2), block(64 * g.nwv);
+#define AFQ_TH(NB_) \
+  case NB_: hipLaunchKernelGGL((theta_kernel<NB_>), grid, block, 0, st, g); break;
+  switch (nb) { AFQ_TH(1) AFQ_TH(2) AFQ_TH(3) AFQ_TH(4) AFQ_TH(5) AFQ_TH(6) AFQ_TH(7) AFQ_TH(8) }
+#undef AFQ_TH
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}

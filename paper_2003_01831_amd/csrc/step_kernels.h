@@ -56,10 +56,7 @@ int pack_b(int prec, const double2* thT, int nw, int ntot, int M, int off, const
 int convert_d2f(const double* x, float* y, long n, hipStream_t st);
 int copy_d(const double* x, double* y, long n, hipStream_t st);
 int real_part(const double2* z, double* y, long n, hipStream_t st);
-// out_b = in_b^T for batch n x n complex matrices at the same stride
-int transpose_batched(const double2* in, long stride, int n, int batch, double2* out, hipStream_t st);
 // y[c][i] = Re z[i][c] for a rows x cols complex matrix
-int real_transpose(const double2* z, long rows, long cols, double* y, hipStream_t st);
 int fill_d(double* y, double v, long n, hipStream_t st);
 int fill_i(int* y, int v, long n, hipStream_t st);
 int fill_eye(double* y, int M, hipStream_t st);
@@ -86,3 +83,11 @@ int launch_gather_rows(const void* src, void* dst, long row_bytes, int nrows, in
 int launch_bp_stats(const double* wt, const int* sing, int nw, double* stats, hipStream_t st);
 int launch_bp_pack(double2* Y, double2* Q, const double2* psi, long per, int ntot, int off, int n, int nw, int M,
                    const double* wt, const double* stats, hipStream_t st);
+// Overlaps S^s_w = T^sH W^s_w of both spins in one launch (overlap.hip): T as
+// phir (Re T, [M][ntot], real trial) or phi ([M][ntot] complex); S (w, s) at
+// S + (2 w + s) nm2, row-major n_s x n_s. n_s <= 128.
+int overlap_mfma(const double2* W, const double* phir, const double2* phi, int M, int ntot, int nw, const int n[2],
+                 const int off[2], double2* S, long nm2, hipStream_t st);
+// thetaT[w][off_s + b][k] = sum_j Sinv_ws[j][b] W[w][k][off_s + j], both spins in one launch
+int theta_mfma(const double2* W, const double2* Sinv, int M, int ntot, int nw, const int n[2], const int off[2],
+               long nm2, double2* thetaT, hipStream_t st);

@@ -174,35 +174,6 @@ int convert_d2f(const double* x, float* y, long n, hipStream_t st) {
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }
-// out_b = in_b^T for a batch of n x n complex matrices (strides in elements)
-__global__ void transpose_batched_kernel(const double2* __restrict__ in, long stride, int n, int batch,
-                                         double2* __restrict__ out) {
-  const long nn = (long)n * n, total = nn * batch;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const long b = t / nn, e = t - b * nn, r = e / n, c = e - r * n;
-    out[b * stride + c * n + r] = in[b * stride + e];
-  }
-}
-int transpose_batched(const double2* in, long stride, int n, int batch, double2* out, hipStream_t st) {
-  const long total = (long)n * n * batch;
-  if (total <= 0) return AFQ_OK;
-  hipLaunchKernelGGL(transpose_batched_kernel, dim3(grid_for(total)), dim3(256), 0, st, in, stride, n, batch, out);
-  AFQ_TRY_HIP(hipGetLastError());
-  return AFQ_OK;
-}
-// y[c][i] = Re z[i][c] (rows x cols complex -> cols x rows real)
-__global__ void real_transpose_kernel(const double2* __restrict__ z, long rows, long cols, double* __restrict__ y) {
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < rows * cols; t += (long)gridDim.x * blockDim.x) {
-    const long c = t / rows, i = t - c * rows;
-    y[t] = z[i * cols + c].x;
-  }
-}
-int real_transpose(const double2* z, long rows, long cols, double* y, hipStream_t st) {
-  if (rows * cols <= 0) return AFQ_OK;
-  hipLaunchKernelGGL(real_transpose_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, st, z, rows, cols, y);
-  AFQ_TRY_HIP(hipGetLastError());
-  return AFQ_OK;
-}
 __global__ void real_part_kernel(const double2* __restrict__ z, double* __restrict__ y, long n) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) y[i] = z[i].x;
 }

@@ -169,8 +169,8 @@ int system_create_impl(afq_system* out, int M, int n_up, int n_dn, int X, const 
     AFQ_CHECK(h[2] <= 1e-12 * h[3] + 1e-300, AFQ_E_INVALID, "afq_system_create: a Cholesky vector is not symmetric");
     s->real_trial = h[4] == 0.0;
     if (s->real_trial) {
-      AFQ_RET(s->phitr.alloc((size_t)s->ntot * M * 8));
-      AFQ_RET(real_transpose(s->phi.as<double2>(), M, s->ntot, s->phitr.as<double>(), st));
+      AFQ_RET(s->phir.alloc((size_t)s->ntot * M * 8));
+      AFQ_RET(real_part(s->phi.as<double2>(), s->phir.as<double>(), (long)M * s->ntot, st));
     }
     // h' = h - 1/2 sum_n L^n L^n = h - 1/2 Q^T Q with Q the (X M) x M stack of the symmetric L^n
     AFQ_RET(s->hp.alloc(mm * 8));

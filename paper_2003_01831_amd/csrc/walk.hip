@@ -23,7 +23,6 @@ int walkers_alloc_scratch(afq_walkers w) {
   if (!w->S.p) {
     AFQ_RET(w->S.alloc((size_t)nw * 2 * nmax * nmax * 16));
     AFQ_RET(w->Sinv.alloc((size_t)nw * 2 * nmax * nmax * 16));
-    AFQ_RET(w->SinvT.alloc((size_t)nw * 2 * nmax * nmax * 16));
     AFQ_RET(w->Sinv_new.alloc((size_t)nw * 2 * nmax * nmax * 16));
     AFQ_RET(w->logdet.alloc((size_t)nw * 2 * 16));
     AFQ_RET(w->logdet_new.alloc((size_t)nw * 2 * 16));
@@ -57,51 +56,28 @@ int walkers_alloc_scratch(afq_walkers w) {
   return AFQ_OK;
 }
 
-// S^s = T^sH W^s for every walker; S^-1 into inv (optional) and log det
+// S^s = T^sH W^s for every walker (both spins, one launch); S^-1 into inv
+// (optional) and log det
 static int overlap_inverse(afq_system s, afq_walkers w, const double2* Wsrc, double2* inv, double2* logdet_out) {
   hipStream_t st = s->stream;
-  const int M = s->M, ntot = s->ntot, nw = w->nw;
+  const int nw = w->nw;
   const int nmax = std::max(s->n_up, s->n_dn);
   const long nm2 = (long)nmax * nmax;
-  for (int sp = 0; sp < 2; ++sp) {
-    const int n = s->nspin_n(sp), off = s->spin_off(sp);
-    GemmArgs<double> g = gemm_args<double>();
-    g.m = n; g.n = n; g.k = M; g.batch = nw;
-    if (s->phitr.p) {   // real trial: T^T rows, k-contiguous (real x complex), walkers side by side
-      g.A = s->phitr.as<double>() + (long)off * M; g.lda = M; g.cA = false; g.sA = 0;
-      g.n = nw * n; g.batch = 1; g.vn = n;
-    } else {
-      g.A = s->phi.as<double>() + 2 * off; g.lda = ntot; g.opA = OP_C; g.cA = true; g.sA = 0;
-    }
-    g.B = reinterpret_cast<const double*>(Wsrc) + 2 * off; g.ldb = ntot; g.cB = true; g.sB = (long)M * ntot;
-    g.C = w->S.as<double>() + 2 * sp * nm2; g.ldc = n; g.cC = true; g.sC = 2 * nm2;
-    AFQ_RET(gemm<double>(g, st));
-    AFQ_RET(lu_inverse(w->S.as<double2>() + sp * nm2, 2 * nm2, n, nw, inv ? inv + sp * nm2 : nullptr,
+  const int n[2] = {s->nspin_n(0), s->nspin_n(1)}, off[2] = {s->spin_off(0), s->spin_off(1)};
+  AFQ_RET(overlap_mfma(Wsrc, s->phir.p ? s->phir.as<double>() : nullptr, s->phi.as<double2>(), s->M, s->ntot, nw,
+                       n, off, w->S.as<double2>(), nm2, st));
+  for (int sp = 0; sp < 2; ++sp)
+    AFQ_RET(lu_inverse(w->S.as<double2>() + sp * nm2, 2 * nm2, n[sp], nw, inv ? inv + sp * nm2 : nullptr,
                        logdet_out + sp, 2, w->sing.as<int>() + sp, 2, st));
-  }
   return AFQ_OK;
 }
 
-// Theta^T from w->Sinv: thetaT[w][off + b][k] = sum_j (S^-1)^T[b][j] W[k][off + j]
-// (both operands k-contiguous)
+// Theta^T from w->Sinv: thetaT[w][off + b][k] = sum_j (S^-1)[j][b] W[k][off + j]
 static int theta_from_inverse(afq_system s, afq_walkers w, const double2* Wsrc) {
-  hipStream_t st = s->stream;
-  const int M = s->M, ntot = s->ntot, nw = w->nw;
   const int nmax = std::max(s->n_up, s->n_dn);
-  const long nm2 = (long)nmax * nmax;
-  for (int sp = 0; sp < 2; ++sp) {
-    const int n = s->nspin_n(sp), off = s->spin_off(sp);
-    AFQ_RET(transpose_batched(w->Sinv.as<double2>() + sp * nm2, 2 * nm2, n, nw, w->SinvT.as<double2>() + sp * nm2,
-                              st));
-    GemmArgs<double> t = gemm_args<double>();
-    t.m = n; t.n = M; t.k = n; t.batch = nw;
-    t.A = w->SinvT.as<double>() + 2 * sp * nm2; t.lda = n; t.cA = true; t.sA = 2 * nm2;
-    t.B = reinterpret_cast<const double*>(Wsrc) + 2 * off; t.ldb = ntot; t.opB = OP_T; t.cB = true;
-    t.sB = (long)M * ntot;
-    t.C = w->theta.as<double>() + 2 * (long)off * M; t.ldc = M; t.cC = true; t.sC = (long)ntot * M;
-    AFQ_RET(gemm<double>(t, st));
-  }
-  return AFQ_OK;
+  const int n[2] = {s->nspin_n(0), s->nspin_n(1)}, off[2] = {s->spin_off(0), s->spin_off(1)};
+  return theta_mfma(Wsrc, w->Sinv.as<double2>(), s->M, s->ntot, w->nw, n, off, (long)nmax * nmax,
+                    w->theta.as<double2>(), s->stream);
 }
 
 // S^s = T^sH W^s for every walker; S^-1 (optional) and log det; Theta^T = S^-T W^T

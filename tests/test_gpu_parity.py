@@ -59,6 +59,22 @@ def test_energy_fp64(api, shape):
     assert rel_scalar(em, rem) < 1e-10
 
 
+def test_energy_fp64_many_electrons(api):
+    """113..128 electrons per spin (eight 16-wide MFMA blocks in the overlap
+    and Theta kernels, a ragged basis tail and electron counts that are not
+    multiples of 4): FP64 takes the four-index exchange form here."""
+    s = synth.make_system(136, 120, 117, 48, seed=11)
+    W = synth.perturbed_walkers(s, 3, 0.2, seed=3)
+    w = synth.random_weights(3, seed=4)
+    el, parts, vb, em = _energy_case(api, s, W, w, "fp64", "four_index")
+    rel, rparts, rvb, rem = _oracle_energy(s, W, w)
+    assert rel_vec(el, rel) < 1e-10
+    for c in range(3):
+        assert rel_vec(parts[:, c], rparts[:, c]) < 1e-10, c
+    assert rel_fro(vb, rvb) < 1e-10
+    assert rel_scalar(em, rem) < 1e-10
+
+
 def test_energy_complex_trial(api):
     """A complex trial doubles the contraction length (Re/Im stacked along k)."""
     s = synth.make_system(24, 4, 5, 30, seed=8)
