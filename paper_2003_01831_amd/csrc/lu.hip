@@ -12,6 +12,23 @@ namespace {
 
 constexpr int NMAX = 128;
 
+// z - x y in four fused multiply-adds
+__device__ __forceinline__ double2 cfnma(double2 x, double2 y, double2 z) {
+  const double re = fma(x.y, y.y, fma(-x.x, y.x, z.x));
+  const double im = fma(-x.y, y.x, fma(-x.x, y.y, z.y));
+  return make_double2(re, im);
+}
+
+// 1 / p = conj(p) / |p|^2 with one division: p is first scaled by the power
+// of two that brings its larger part into [1, 2), so |p|^2 neither overflows
+// nor underflows (p != 0, finite)
+__device__ __forceinline__ double2 crecip(double2 p) {
+  const int e = ilogb(fmax(fabs(p.x), fabs(p.y)));
+  const double sx = ldexp(p.x, -e), sy = ldexp(p.y, -e);
+  const double inv = 1.0 / fma(sx, sx, sy * sy);
+  return make_double2(ldexp(sx * inv, -e), ldexp(-sy * inv, -e));
+}
+
 template <int NT>
 struct GjShared {
   double2 rowp[NMAX], colk[NMAX];
@@ -99,7 +116,7 @@ __device__ __forceinline__ void gj_step(double2 (&a)[RB][CB], int k0, int n, int
     bad = true;
     piv = make_double2(1.0, 0.0);
   }
-  const double2 ipiv = cdiv(make_double2(1.0, 0.0), piv);
+  const double2 ipiv = crecip(piv);
   if (tid == 0) {
     if constexpr (PIV) {
       sh.pivs[k] = piv;
@@ -143,7 +160,7 @@ __device__ __forceinline__ void gj_step(double2 (&a)[RB][CB], int k0, int n, int
     for (int i = 0; i < RB; ++i) {
       const double2 ck = sh.colk[i * CKS + rg];
 #pragma unroll
-      for (int c = 0; c < CB; ++c) a[i][c] = csub(a[i][c], cmul(ck, sh.rowp[cg * CB + c]));
+      for (int c = 0; c < CB; ++c) a[i][c] = cfnma(ck, sh.rowp[cg * CB + c], a[i][c]);
     }
     if (pbit) {
 #pragma unroll
@@ -318,7 +335,7 @@ __global__ __launch_bounds__(NT) void chol_inv_kernel(
       for (int i = 0; i < RB; ++i) {
         const double2 ck = cscale(cconj(sh.rowp[rg * RB + i]), id2);
 #pragma unroll
-        for (int c = 0; c < CB; ++c) a[i][c] = csub(a[i][c], cmul(ck, sh.rowp[cg * CB + c]));
+        for (int c = 0; c < CB; ++c) a[i][c] = cfnma(ck, sh.rowp[cg * CB + c], a[i][c]);
       }
       if (kbit) {
 #pragma unroll

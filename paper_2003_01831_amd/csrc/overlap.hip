@@ -149,6 +149,7 @@ struct ThetaArgs {
   const double2* W;      // as in OvlArgs
   const double2* Sinv;   // (w, s) at Sinv + (2 w + s) * nm2, row-major n_s x n_s
   double2* thetaT;       // walker w at thetaT + w * ntot * M; (off_s + b, k) at (off_s + b) * M + k
+                         // (WOUT: in the walker layout, (k, off_s + b) at k * ntot + off_s + b)
   long nm2;
   int M, ntot, nw, nkg, nwv;   // nkg workgroups of nwv waves per walker and spin
   int n[2], off[2];
@@ -162,8 +163,10 @@ struct ThetaArgs {
 // 16 rows j at a time (double buffered); the W fragments come straight from
 // memory, one chunk ahead. Workgroups are numbered so that the nkg of one
 // walker land on one XCD (dispatch i goes to XCD i mod 8) and share S^-1 in
-// its L2. At NB = 8 the accumulators leave room for 4 waves only.
-template <int NB>
+// its L2. At NB = 8 the accumulators leave room for 4 waves only. With WOUT
+// the product is stored in the walker layout instead (Q = W R^-1 of
+// CholeskyQR, R^-1 in place of S^-1).
+template <int NB, bool WOUT>
 __global__ __launch_bounds__(NB == 8 ? 256 : 512) void theta_kernel(ThetaArgs g) {
   constexpr int NC = NB * 16, PER = 16 * NC / 256;   // staged elements per thread with >= 4 waves
   __shared__ double2 As[2][16][NC];
@@ -245,14 +248,109 @@ __global__ __launch_bounds__(NB == 8 ? 256 : 512) void theta_kernel(ThetaArgs g)
   }
   // lane holds rows 16 i + q + 4 t (b), column k of each block
   if (kcol) {
-    double2* Tw = g.thetaT + (long)w * ntot * M + (long)off * M + k;
+    double2* Tw = g.thetaT + (long)w * ntot * M + (WOUT ? (long)k * ntot + off : (long)off * M + k);
+    const long bstep = WOUT ? 1 : M;
 #pragma unroll
     for (int i = 0; i < NB; ++i)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int b = 16 * i + q + 4 * t;
-        if (b < n) Tw[(long)b * M] = make_double2(accr[i][t], acci[i][t]);
+        if (b < n) Tw[b * bstep] = make_double2(accr[i][t], acci[i][t]);
       }
+  }
+}
+
+struct GramArgs {
+  const double2* W;      // as in OvlArgs
+  double2* G;            // (w, s) at G + (2 w + s) * nm2, row-major n_s x n_s
+  long nm2;
+  int M, ntot, nw;
+  int n[2], off[2];
+};
+
+// Gram matrices G^s_w = W^sH_w W^s_w of CholeskyQR, both spins in one launch:
+// workgroup (column group, walker, spin) of four waves, one 16-wide column
+// block b each; W's rows (all n_s columns) are staged through LDS 16 basis
+// functions at a time and serve both operands. A wave forms only the blocks
+// of the upper block triangle (row blocks a <= its column block) and stores
+// each off-diagonal one twice, the second time conjugated at the mirrored
+// place.
+template <int NB>
+__global__ __launch_bounds__(256) void gram_kernel(GramArgs g) {
+  constexpr int NC = NB * 16, PER = 16 * NC / 256;   // PER = NB
+  __shared__ double2 As[2][16][NC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ncg = (NB + 3) / 4;
+  const int cg = blockIdx.x % ncg, w = blockIdx.x / ncg, sp = blockIdx.y;
+  const int n = g.n[sp], off = g.off[sp], M = g.M, ntot = g.ntot;
+  const int jb = 4 * cg + wave;              // this wave's column block
+  if (n == 0 || 64 * cg >= n) return;        // whole workgroup
+  const double2* Ww = g.W + (long)w * M * ntot + off;
+  const int r = lane & 15, q = lane >> 4;
+  const int nchunk = (M + 15) / 16;
+
+  double2 st[PER];
+  auto fetch = [&](int c) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, row = e / NC, col = e - row * NC, k = 16 * c + row;
+      st[u] = k < M && col < n ? Ww[(long)k * ntot + col] : make_double2(0.0, 0.0);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, row = e / NC, col = e - row * NC;
+      As[buf][row][col] = st[u];
+    }
+  };
+
+  d4 accr[NB], acci[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) accr[i] = acci[i] = d4{0.0, 0.0, 0.0, 0.0};
+  const bool active = jb < NB && 16 * jb < n;   // wave-uniform
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunk) fetch(c + 1);
+    const int ns = active ? min(4, (M - 16 * c + 3) / 4) : 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (s < ns) {
+        const double2 b = As[buf][4 * s + q][16 * jb + r];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          if (i <= jb) {   // A = conj(W): Re a, -Im a
+            const double2 a = As[buf][4 * s + q][16 * i + r];
+            accr[i] = mma(accr[i], a.x, b.x);
+            acci[i] = mma(acci[i], a.x, b.y);
+            accr[i] = mma(accr[i], a.y, b.y);
+            acci[i] = mma(acci[i], -a.y, b.x);
+          }
+        }
+      }
+    }
+    if (c + 1 < nchunk) stash(buf ^ 1);
+    __syncthreads();
+  }
+  if (!active) return;
+  // lane holds rows 16 i + q + 4 t (a) of column 16 jb + r (b)
+  double2* Gw = g.G + (2L * w + sp) * g.nm2;
+  const int b = 16 * jb + r;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    if (i > jb) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int a = 16 * i + q + 4 * t;
+      if (a < n && b < n) {
+        Gw[(long)a * n + b] = make_double2(accr[i][t], acci[i][t]);
+        if (i < jb) Gw[(long)b * n + a] = make_double2(accr[i][t], -acci[i][t]);
+      }
+    }
   }
 }
 
@@ -289,14 +387,16 @@ int overlap_mfma(const double2* W, const double* phir, const double2* phi, int M
   return AFQ_OK;
 }
 
-int theta_mfma(const double2* W, const double2* Sinv, int M, int ntot, int nw, const int n[2], const int off[2],
-               long nm2, double2* thetaT, hipStream_t st) {
+namespace {
+template <bool WOUT>
+int launch_theta(const double2* W, const double2* Sinv, int M, int ntot, int nw, const int n[2], const int off[2],
+                 long nm2, double2* out, hipStream_t st) {
   const int nmax = std::max(n[0], n[1]);
   AFQ_CHECK(nmax >= 1 && nmax <= 128 && M >= 1 && nw >= 0, AFQ_E_INVALID, "theta: n must be in [1, 128]");
   AFQ_CHECK(nm2 >= (long)nmax * nmax, AFQ_E_INVALID, "theta: matrix stride < n^2");
   if (nw == 0) return AFQ_OK;
   ThetaArgs g{};
-  g.W = W; g.Sinv = Sinv; g.thetaT = thetaT; g.nm2 = nm2;
+  g.W = W; g.Sinv = Sinv; g.thetaT = out; g.nm2 = nm2;
   g.M = M; g.ntot = ntot; g.nw = nw;
   for (int s = 0; s < 2; ++s) { g.n[s] = n[s]; g.off[s] = off[s]; }
   const int nblk = (M + 15) / 16;
@@ -308,9 +408,42 @@ int theta_mfma(const double2* W, const double2* Sinv, int M, int ntot, int nw, c
   AFQ_CHECK(blocks <= INT32_MAX, AFQ_E_INVALID, "theta: too many workgroups");
   const dim3 grid((unsigned)blocks, 2), block(64 * g.nwv);
 #define AFQ_TH(NB_) \
-  case NB_: hipLaunchKernelGGL((theta_kernel<NB_>), grid, block, 0, st, g); break;
+  case NB_: hipLaunchKernelGGL((theta_kernel<NB_, WOUT>), grid, block, 0, st, g); break;
   switch (nb) { AFQ_TH(1) AFQ_TH(2) AFQ_TH(3) AFQ_TH(4) AFQ_TH(5) AFQ_TH(6) AFQ_TH(7) AFQ_TH(8) }
 #undef AFQ_TH
+  AFQ_TRY_HIP(hipGetLastError());
+  return AFQ_OK;
+}
+}  // namespace
+
+int theta_mfma(const double2* W, const double2* Sinv, int M, int ntot, int nw, const int n[2], const int off[2],
+               long nm2, double2* thetaT, hipStream_t st) {
+  return launch_theta<false>(W, Sinv, M, ntot, nw, n, off, nm2, thetaT, st);
+}
+
+int qr_apply_mfma(const double2* W, const double2* Rinv, int M, int ntot, int nw, const int n[2], const int off[2],
+                  long nm2, double2* Q, hipStream_t st) {
+  AFQ_CHECK(Q != W, AFQ_E_INVALID, "qr: the output must not overwrite the input");
+  return launch_theta<true>(W, Rinv, M, ntot, nw, n, off, nm2, Q, st);
+}
+
+int gram_mfma(const double2* W, int M, int ntot, int nw, const int n[2], const int off[2], double2* G, long nm2,
+              hipStream_t st) {
+  const int nmax = std::max(n[0], n[1]);
+  AFQ_CHECK(nmax >= 1 && nmax <= 128 && M >= 1 && nw >= 0, AFQ_E_INVALID, "gram: n must be in [1, 128]");
+  AFQ_CHECK(nm2 >= (long)nmax * nmax, AFQ_E_INVALID, "gram: matrix stride < n^2");
+  if (nw == 0) return AFQ_OK;
+  GramArgs g{};
+  g.W = W; g.G = G; g.nm2 = nm2;
+  g.M = M; g.ntot = ntot; g.nw = nw;
+  for (int s = 0; s < 2; ++s) { g.n[s] = n[s]; g.off[s] = off[s]; }
+  const int nb = (nmax + 15) / 16, ncg = (nb + 3) / 4;
+  AFQ_CHECK((long)nw * ncg <= INT32_MAX, AFQ_E_INVALID, "gram: too many workgroups");
+  const dim3 grid((unsigned)(nw * ncg), 2);
+#define AFQ_GR(NB_) \
+  case NB_: hipLaunchKernelGGL((gram_kernel<NB_>), grid, dim3(256), 0, st, g); break;
+  switch (nb) { AFQ_GR(1) AFQ_GR(2) AFQ_GR(3) AFQ_GR(4) AFQ_GR(5) AFQ_GR(6) AFQ_GR(7) AFQ_GR(8) }
+#undef AFQ_GR
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }

@@ -91,3 +91,10 @@ int overlap_mfma(const double2* W, const double* phir, const double2* phi, int M
 // thetaT[w][off_s + b][k] = sum_j Sinv_ws[j][b] W[w][k][off_s + j], both spins in one launch
 int theta_mfma(const double2* W, const double2* Sinv, int M, int ntot, int nw, const int n[2], const int off[2],
                long nm2, double2* thetaT, hipStream_t st);
+// CholeskyQR products (overlap.hip), both spins in one launch each: the Gram
+// matrices G_ws = W_ws^H W_ws (G laid out as S above) and Q_ws = W_ws Rinv_ws
+// (Rinv as S^-1 above; Q in the walker layout, not W itself)
+int gram_mfma(const double2* W, int M, int ntot, int nw, const int n[2], const int off[2], double2* G, long nm2,
+              hipStream_t st);
+int qr_apply_mfma(const double2* W, const double2* Rinv, int M, int ntot, int nw, const int n[2], const int off[2],
+                  long nm2, double2* Q, hipStream_t st);

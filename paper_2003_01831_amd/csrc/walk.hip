@@ -274,32 +274,18 @@ int propagate_walkers(afq_system s, afq_walkers w, int order, const void* coef, 
 int qr_orbitals(afq_system s, afq_walkers w, const double2* src0, double2* mid, double2* dst0) {
   hipStream_t st = s->stream;
   const int M = s->M, ntot = s->ntot, nw = w->nw;
-  const long per = (long)M * ntot;
   const int nmax = std::max(s->n_up, s->n_dn);
   const long nm2 = (long)nmax * nmax;
   const int npass = s->prec == AFQ_FP64 ? 2 : 1;
   const double2* in[2] = {src0, mid};
   double2* out[2] = {npass == 2 ? mid : dst0, dst0};
+  const int n[2] = {s->nspin_n(0), s->nspin_n(1)}, off[2] = {s->spin_off(0), s->spin_off(1)};
   for (int pass = 0; pass < npass; ++pass) {
-    const double* src = reinterpret_cast<const double*>(in[pass]);
-    double* dst = reinterpret_cast<double*>(out[pass]);
-    for (int sp = 0; sp < 2; ++sp) {
-      const int n = s->nspin_n(sp), off = s->spin_off(sp);
-      GemmArgs<double> g = gemm_args<double>();
-      g.m = n; g.n = n; g.k = M; g.batch = nw;
-      g.A = src + 2 * off; g.lda = ntot; g.opA = OP_C; g.cA = true; g.sA = per;
-      g.B = src + 2 * off; g.ldb = ntot; g.cB = true; g.sB = per;
-      g.C = w->gram.as<double>() + 2 * sp * nm2; g.ldc = n; g.cC = true; g.sC = 2 * nm2;
-      AFQ_RET(gemm<double>(g, st));
-      AFQ_RET(chol_inverse(w->gram.as<double2>() + sp * nm2, 2 * nm2, n, nw, w->rinv.as<double2>() + sp * nm2,
+    AFQ_RET(gram_mfma(in[pass], M, ntot, nw, n, off, w->gram.as<double2>(), nm2, st));
+    for (int sp = 0; sp < 2; ++sp)
+      AFQ_RET(chol_inverse(w->gram.as<double2>() + sp * nm2, 2 * nm2, n[sp], nw, w->rinv.as<double2>() + sp * nm2,
                            w->logdet_new.as<double2>() + sp, 2, w->sing.as<int>() + sp, 2, st));
-      GemmArgs<double> q = gemm_args<double>();
-      q.m = M; q.n = n; q.k = n; q.batch = nw;
-      q.A = src + 2 * off; q.lda = ntot; q.cA = true; q.sA = per;
-      q.B = w->rinv.as<double>() + 2 * sp * nm2; q.ldb = n; q.cB = true; q.sB = 2 * nm2;
-      q.C = dst + 2 * off; q.ldc = ntot; q.cC = true; q.sC = per;
-      AFQ_RET(gemm<double>(q, st));
-    }
+    AFQ_RET(qr_apply_mfma(in[pass], w->rinv.as<double2>(), M, ntot, nw, n, off, nm2, out[pass], st));
   }
   return AFQ_OK;
 }
