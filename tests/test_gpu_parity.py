@@ -154,6 +154,29 @@ def test_step_moderate_subset(api):
     assert rel_fro(g["W"], o["W"]) < 1e-10
 
 
+def test_step_many_electrons_qr_every_step(api):
+    """120 + 117 electrons (eight 16-wide blocks in the overlap, Theta, Gram
+    and Q kernels, odd electron counts, a ragged basis tail at M = 136) with
+    CholeskyQR after every step: FP64 (two CholeskyQR passes, four-index
+    exchange) against the oracle over 3 steps."""
+    s = synth.make_system(136, 120, 117, 48, seed=12)
+    nw, steps = 3, 3
+    fields = synth.make_fields(steps, nw, 48, seed=1012)
+    W0 = synth.perturbed_walkers(s, nw, 0.1, seed=5)
+    w0 = np.ones(nw)
+    sysg = api.System.from_synth(s, precision="fp64", exchange_form="four_index")
+    wk = api.Walkers(sysg, nw, W0, w0)
+    out = wk.step(steps, 0.005, fields=fields, qr_every=1, e_shift=0.0)
+    st = wk.get()
+    torch.cuda.synchronize()
+    g = {k: to_np(v) for k, v in out.items()}
+    o = afqmc.run(s.h1, s.chol, s.phi_t, s.n_up, s.n_dn, W0, w0, fields, 0.005, qr_every=1, e_shift=0.0,
+                  e_core=s.e_core)
+    for k in ("emix", "eloc", "weights", "ratio"):
+        assert rel_vec(g[k], o[k]) < 1e-10, k
+    assert rel_fro(to_np(st["W"]), o["W"]) < 1e-10
+
+
 @pytest.mark.parametrize("prec", ["cfp32", "bf16x3"])
 @pytest.mark.parametrize("shape", [(64, 16, 16, 256), (37, 9, 6, 70)])
 def test_step_reduced_precision(api, prec, shape):
