@@ -511,7 +511,7 @@ void launch_tile_cfg(const GemmArgs<T>& g, int cfg, dim3 grid, int ksplit, int k
 }
 
 // (WM, WN) of the tile configurations; the 32-row ones serve only m <= 32
-// (the overlap matrices of systems with few electrons)
+// (products with few rows, such as those of systems with few electrons)
 constexpr int kNumTileCfg = 6;
 constexpr int kTileWM[kNumTileCfg] = {2, 2, 4, 4, 1, 1}, kTileWN[kNumTileCfg] = {2, 4, 2, 4, 2, 4};
 
