@@ -1,7 +1,8 @@
 // Batched complex/real GEMM on MFMA for the medium contractions of the walker
-// step (overlaps T^H W, Theta = W S^-1, B1 W, the Taylor products A V, the Gram
-// matrices of QR, the A = sum_n c_n L^n build, the FP64 force-bias traces and
-// the system set-up):
+// step (B1 W, the Taylor products A V, the A = sum_n c_n L^n build, the FP64
+// force-bias traces, the multi-determinant and adjoint products and the system
+// set-up; the overlaps, Theta and the CholeskyQR products have their own
+// kernels in overlap.hip):
 //
 //   C = alpha op(A) op(B) + beta C,   optionally D += alpha op(A) op(B)
 //
