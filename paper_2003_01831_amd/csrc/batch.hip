@@ -1,10 +1,11 @@
 // Many uneven systems stepped together. Every step runs in three stages that
 // end where overlap inverses are needed; each stage runs as concurrent
 // branches (one stream per system, forked from and joined back to a root
-// stream), and between the stages the Gauss-Jordan inverses of every system
-// and spin run as grouped launches on the root stream: one launch per
-// register-block layout walks a work table of (system, spin) tasks, so a step
-// of 24 systems takes a handful of inverse launches instead of 96 small ones.
+// stream), and between the stages the overlaps T^H W, their Gauss-Jordan
+// inverses and the Theta products of every system run as grouped launches on
+// the root stream: one launch per kernel shape walks a work table of
+// per-system tasks, so a step of 24 systems takes a handful of these launches
+// instead of a hundred small ones.
 // After eager warm-up steps that size every buffer, one cycle of `qr_every`
 // steps (one step when QR is off) is captured into a HIP graph and replayed,
 // so a whole cycle of all systems is one graph launch. Step counters live in
@@ -66,9 +67,18 @@ int enqueue_steps(afq_batch b, hipStream_t root, int steps, bool capture_layout,
                   int n_steps_user, int base) {
   const int n = (int)b->sys.size();
   std::vector<GjTask> tasks;
+  std::vector<OvlTask> otasks;
+  std::vector<ThetaTask> ttasks;
   for (int k = 0; k < steps; ++k) {
     for (int stage = 0; stage < 3; ++stage) {
       tasks.clear();
+      otasks.clear();
+      if (stage == 1) {   // Theta of every system (after the inverses) as grouped launches
+        ttasks.clear();
+        for (int i = 0; i < n; ++i) ttasks.push_back(theta_task_of(b->sys[i], b->wk[i]));
+        AFQ_RET(theta_grouped(ttasks, root));
+        for (auto w : b->wk) w->theta_pre = true;
+      }
       AFQ_TRY_HIP(hipEventRecord(b->fork[0], root));
       for (int i = 0; i < n; ++i) {
         afq_system s = b->sys[i];
@@ -81,9 +91,11 @@ int enqueue_steps(afq_batch b, hipStream_t root, int steps, bool capture_layout,
         s->stream = b->streams[i];
         int rc = hip_status(hipStreamWaitEvent(b->streams[i], b->fork[0], 0), "afq_batch_step: fork");
         lu_defer(&tasks);
+        if (stage < 2) overlap_defer(&otasks);
         if (rc == AFQ_OK)
           rc = step_stage(stage, s, w, b->dt, nullptr, b->seed, (uint32_t)i, k, do_qr, b->e_shift[i], b->order, em,
                           nullptr, nullptr, nullptr);
+        overlap_defer(nullptr);
         lu_defer(nullptr);
         if (rc == AFQ_OK && stage == 2 && k == steps - 1)
           rc = counter_add(w->d_counter.as<uint64_t>(), (uint64_t)steps, b->streams[i]);
@@ -92,6 +104,8 @@ int enqueue_steps(afq_batch b, hipStream_t root, int steps, bool capture_layout,
         AFQ_TRY_HIP(hipEventRecord(b->join[i], b->streams[i]));
         AFQ_TRY_HIP(hipStreamWaitEvent(root, b->join[i], 0));
       }
+      // the overlaps the stage requested, then their inverses
+      if (!otasks.empty()) AFQ_RET(overlap_grouped(otasks, root));
       if (!tasks.empty()) AFQ_RET(lu_inverse_grouped(tasks, root));
     }
   }

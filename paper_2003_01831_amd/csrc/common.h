@@ -220,6 +220,7 @@ struct afq_walkers_s {
   DevBuf S, Sinv;              // per (w, spin): n x n complex (max n^2 stride)
   DevBuf Sinv_new;             // S^-1 of the propagated walkers (carried to the next step)
   bool s_carried = false;      // Sinv and logdet are those of the current W (set by a step's weight phase)
+  bool theta_pre = false;      // Theta of the current W already formed (a batch's grouped launch)
   DevBuf logdet, logdet_new;   // nw x 2 complex
   DevBuf sing;                 // nw x 2 int
   DevBuf theta;                // nw x M x ntot complex

@@ -42,18 +42,18 @@ struct OvlArgs {
 // trial's rows are the operand all waves share: staged through LDS 16 basis
 // functions at a time (double buffered, one barrier per chunk); the walker
 // fragments come straight from memory, one chunk ahead.
+// (workgroup bx of spin sp; 256 threads)
 template <int NB, bool CA>
-__global__ __launch_bounds__(256) void overlap_kernel(OvlArgs g) {
+__device__ __forceinline__ void overlap_body(const OvlArgs& g, int bx, int sp) {
   using TE = typename std::conditional<CA, double2, double>::type;
   constexpr int NC = NB * 16, PER = 16 * NC / 256;   // PER = NB
   __shared__ TE As[2][16][NC];
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int sp = blockIdx.y;
   const int n = g.n[sp], off = g.off[sp], M = g.M, ntot = g.ntot;
   const long ncol = (long)g.nw * n;
-  if (64L * blockIdx.x >= ncol) return;   // whole workgroup (the grid covers the larger spin)
+  if (64L * bx >= ncol) return;   // whole workgroup (the grid covers the larger spin)
   const int r = lane & 15, q = lane >> 4;
-  const long col0 = 16L * (4 * blockIdx.x + wave), col = col0 + r;
+  const long col0 = 16L * (4 * bx + wave), col = col0 + r;
   const bool cok = col < ncol;
   const int w = cok ? (int)(col / n) : 0, j = cok ? (int)(col - (long)w * n) : 0;
   const double2* Wl = g.W + (long)w * M * ntot + off + j;   // this lane's column; row k at k * ntot
@@ -145,6 +145,30 @@ __global__ __launch_bounds__(256) void overlap_kernel(OvlArgs g) {
   }
 }
 
+template <int NB, bool CA>
+__global__ __launch_bounds__(256) void overlap_kernel(OvlArgs g) {
+  overlap_body<NB, CA>(g, blockIdx.x, blockIdx.y);
+}
+
+// Work table of a grouped launch (walker sets of several systems, one
+// electron-block count): workgroup x runs block x - first[t] of task t with
+// first[t] <= x < first[t + 1]; passed by value, so a captured graph holds it.
+constexpr int OVL_GROUP = 24;
+struct OvlGroupArgs {
+  OvlArgs g[OVL_GROUP];
+  int first[OVL_GROUP + 1];
+  int ntask;
+};
+
+template <int NB, bool CA>
+__global__ __launch_bounds__(256) void overlap_grouped_kernel(OvlGroupArgs G) {
+  const int x = blockIdx.x;
+  int t = 0;
+  while (t + 1 < G.ntask && x >= G.first[t + 1]) ++t;
+  const OvlArgs& g = G.g[t];
+  overlap_body<NB, CA>(g, x - G.first[t], blockIdx.y);
+}
+
 struct ThetaArgs {
   const double2* W;      // as in OvlArgs
   const double2* Sinv;   // (w, s) at Sinv + (2 w + s) * nm2, row-major n_s x n_s
@@ -166,12 +190,12 @@ struct ThetaArgs {
 // its L2. At NB = 8 the accumulators leave room for 4 waves only. With WOUT
 // the product is stored in the walker layout instead (Q = W R^-1 of
 // CholeskyQR, R^-1 in place of S^-1).
+// (workgroup lin of spin sp; 64 nwv threads)
 template <int NB, bool WOUT>
-__global__ __launch_bounds__(NB == 8 ? 256 : 512) void theta_kernel(ThetaArgs g) {
+__device__ __forceinline__ void theta_body(const ThetaArgs& g, int lin, int sp) {
   constexpr int NC = NB * 16, PER = 16 * NC / 256;   // staged elements per thread with >= 4 waves
   __shared__ double2 As[2][16][NC];
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), nt = blockDim.x;
-  const int sp = blockIdx.y, lin = blockIdx.x;
   const int w = (lin / (8 * g.nkg)) * 8 + (lin & 7), kg = (lin >> 3) % g.nkg;
   const int n = g.n[sp], off = g.off[sp], M = g.M, ntot = g.ntot;
   if (n == 0 || w >= g.nw) return;   // whole workgroup
@@ -258,6 +282,30 @@ __global__ __launch_bounds__(NB == 8 ? 256 : 512) void theta_kernel(ThetaArgs g)
         if (b < n) Tw[b * bstep] = make_double2(accr[i][t], acci[i][t]);
       }
   }
+}
+
+template <int NB, bool WOUT>
+__global__ __launch_bounds__(NB == 8 ? 256 : 512) void theta_kernel(ThetaArgs g) {
+  theta_body<NB, WOUT>(g, blockIdx.x, blockIdx.y);
+}
+
+// grouped Theta launches: as OvlGroupArgs (tasks of one electron-block count
+// and one wave count; every task's block count is a multiple of 8, so the
+// XCD numbering of each task holds)
+constexpr int THETA_GROUP = 24;
+struct ThetaGroupArgs {
+  ThetaArgs g[THETA_GROUP];
+  int first[THETA_GROUP + 1];
+  int ntask;
+};
+
+template <int NB>
+__global__ __launch_bounds__(NB == 8 ? 256 : 512) void theta_grouped_kernel(ThetaGroupArgs G) {
+  const int x = blockIdx.x;
+  int t = 0;
+  while (t + 1 < G.ntask && x >= G.first[t + 1]) ++t;
+  const ThetaArgs& g = G.g[t];
+  theta_body<NB, false>(g, x - G.first[t], blockIdx.y);
 }
 
 struct GramArgs {
@@ -361,6 +409,56 @@ int theta_waves(int nblk) { return ceil_div(nblk, 8) * 8 == ceil_div(nblk, 4) * 
 
 }  // namespace
 
+namespace {
+thread_local std::vector<OvlTask>* t_ovl_sink = nullptr;
+
+OvlArgs ovl_args(const OvlTask& t) {
+  OvlArgs g{};
+  g.W = t.W; g.phir = t.phir; g.phi = t.phi; g.S = t.S; g.nm2 = t.nm2;
+  g.M = t.M; g.ntot = t.ntot; g.nw = t.nw;
+  for (int s = 0; s < 2; ++s) { g.n[s] = t.n[s]; g.off[s] = t.off[s]; }
+  return g;
+}
+int nb_of(const int n[2]) { return (std::max(n[0], n[1]) + 15) / 16; }
+long ovl_blocks(const OvlTask& t) { return ((long)t.nw * std::max(t.n[0], t.n[1]) + 63) / 64; }
+}  // namespace
+
+void overlap_defer(std::vector<OvlTask>* sink) { t_ovl_sink = sink; }
+
+int overlap_grouped(const std::vector<OvlTask>& tasks, hipStream_t st) {
+  for (int nb = 1; nb <= 8; ++nb)
+    for (int ca = 0; ca < 2; ++ca) {
+      OvlGroupArgs G{};
+      long blocks = 0;
+      auto flush = [&]() -> int {
+        if (G.ntask == 0) return AFQ_OK;
+        AFQ_CHECK(blocks <= INT32_MAX, AFQ_E_INVALID, "overlap: too many workgroups");
+        G.first[G.ntask] = (int)blocks;
+        const dim3 grid((unsigned)blocks, 2);
+#define AFQ_OVLG(NB_)                                                                                      \
+  case NB_:                                                                                                \
+    if (ca) hipLaunchKernelGGL((overlap_grouped_kernel<NB_, true>), grid, dim3(256), 0, st, G);            \
+    else hipLaunchKernelGGL((overlap_grouped_kernel<NB_, false>), grid, dim3(256), 0, st, G);              \
+    break;
+        switch (nb) { AFQ_OVLG(1) AFQ_OVLG(2) AFQ_OVLG(3) AFQ_OVLG(4) AFQ_OVLG(5) AFQ_OVLG(6) AFQ_OVLG(7) AFQ_OVLG(8) }
+#undef AFQ_OVLG
+        AFQ_TRY_HIP(hipGetLastError());
+        G = OvlGroupArgs{};
+        blocks = 0;
+        return AFQ_OK;
+      };
+      for (const OvlTask& t : tasks) {
+        if (nb_of(t.n) != nb || (t.phir == nullptr) != (ca != 0) || t.nw <= 0) continue;
+        G.g[G.ntask] = ovl_args(t);
+        G.first[G.ntask++] = (int)blocks;
+        blocks += ovl_blocks(t);
+        if (G.ntask == OVL_GROUP) AFQ_RET(flush());
+      }
+      AFQ_RET(flush());
+    }
+  return AFQ_OK;
+}
+
 int overlap_mfma(const double2* W, const double* phir, const double2* phi, int M, int ntot, int nw, const int n[2],
                  const int off[2], double2* S, long nm2, hipStream_t st) {
   const int nmax = std::max(n[0], n[1]);
@@ -368,6 +466,10 @@ int overlap_mfma(const double2* W, const double* phir, const double2* phi, int M
             "overlap: n must be in [1, 128], a trial is needed");
   AFQ_CHECK(nm2 >= (long)nmax * nmax, AFQ_E_INVALID, "overlap: matrix stride < n^2");
   if (nw == 0) return AFQ_OK;
+  if (t_ovl_sink) {   // deferred into a grouped launch of many systems
+    t_ovl_sink->push_back(OvlTask{W, phir, phi, S, nm2, M, ntot, nw, {n[0], n[1]}, {off[0], off[1]}});
+    return AFQ_OK;
+  }
   OvlArgs g{};
   g.W = W; g.phir = phir; g.phi = phi; g.S = S; g.nm2 = nm2;
   g.M = M; g.ntot = ntot; g.nw = nw;
@@ -419,6 +521,51 @@ int launch_theta(const double2* W, const double2* Sinv, int M, int ntot, int nw,
 int theta_mfma(const double2* W, const double2* Sinv, int M, int ntot, int nw, const int n[2], const int off[2],
                long nm2, double2* thetaT, hipStream_t st) {
   return launch_theta<false>(W, Sinv, M, ntot, nw, n, off, nm2, thetaT, st);
+}
+
+int theta_grouped(const std::vector<ThetaTask>& tasks, hipStream_t st) {
+  for (const ThetaTask& t : tasks) {
+    const int nmax = std::max(t.n[0], t.n[1]);
+    AFQ_CHECK(nmax >= 1 && nmax <= 128 && t.M >= 1 && t.nm2 >= (long)nmax * nmax, AFQ_E_INVALID,
+              "theta: n must be in [1, 128]");
+  }
+  for (int nb = 1; nb <= 8; ++nb)
+    for (int nwv = 4; nwv <= 8; nwv += 4) {
+      ThetaGroupArgs G{};
+      long blocks = 0;
+      auto flush = [&]() -> int {
+        if (G.ntask == 0) return AFQ_OK;
+        AFQ_CHECK(blocks <= INT32_MAX, AFQ_E_INVALID, "theta: too many workgroups");
+        G.first[G.ntask] = (int)blocks;
+        const dim3 grid((unsigned)blocks, 2), block(64 * nwv);
+#define AFQ_THG(NB_) \
+  case NB_: hipLaunchKernelGGL((theta_grouped_kernel<NB_>), grid, block, 0, st, G); break;
+        switch (nb) { AFQ_THG(1) AFQ_THG(2) AFQ_THG(3) AFQ_THG(4) AFQ_THG(5) AFQ_THG(6) AFQ_THG(7) AFQ_THG(8) }
+#undef AFQ_THG
+        AFQ_TRY_HIP(hipGetLastError());
+        G = ThetaGroupArgs{};
+        blocks = 0;
+        return AFQ_OK;
+      };
+      for (const ThetaTask& t : tasks) {
+        if (t.nw <= 0 || nb_of(t.n) != nb) continue;
+        const int nblk = (t.M + 15) / 16;
+        const int v = nb == 8 ? 4 : theta_waves(nblk);
+        if (v != nwv) continue;
+        ThetaArgs g{};
+        g.W = t.W; g.Sinv = t.Sinv; g.thetaT = t.thetaT; g.nm2 = t.nm2;
+        g.M = t.M; g.ntot = t.ntot; g.nw = t.nw;
+        for (int s = 0; s < 2; ++s) { g.n[s] = t.n[s]; g.off[s] = t.off[s]; }
+        g.nwv = v;
+        g.nkg = ceil_div(nblk, v);
+        G.g[G.ntask] = g;
+        G.first[G.ntask++] = (int)blocks;
+        blocks += (long)ceil_div(t.nw, 8) * 8 * g.nkg;   // a multiple of 8: every task's XCD numbering holds
+        if (G.ntask == THETA_GROUP) AFQ_RET(flush());
+      }
+      AFQ_RET(flush());
+    }
+  return AFQ_OK;
 }
 
 int qr_apply_mfma(const double2* W, const double2* Rinv, int M, int ntot, int nw, const int n[2], const int off[2],

@@ -98,3 +98,29 @@ int gram_mfma(const double2* W, int M, int ntot, int nw, const int n[2], const i
               hipStream_t st);
 int qr_apply_mfma(const double2* W, const double2* Rinv, int M, int ntot, int nw, const int n[2], const int off[2],
                   long nm2, double2* Q, hipStream_t st);
+// Grouped launches of many walker sets (systems of a batch), one per
+// electron-block count (and trial kind or wave count), each walking a work
+// table. While an overlap sink is installed on the calling thread,
+// overlap_mfma records its work there instead of launching it.
+struct OvlTask {
+  const double2* W;
+  const double* phir;
+  const double2* phi;
+  double2* S;
+  long nm2;
+  int M, ntot, nw;
+  int n[2], off[2];
+};
+void overlap_defer(std::vector<OvlTask>* sink);
+int overlap_grouped(const std::vector<OvlTask>& tasks, hipStream_t st);
+struct ThetaTask {
+  const double2* W;
+  const double2* Sinv;
+  double2* thetaT;
+  long nm2;
+  int M, ntot, nw;
+  int n[2], off[2];
+};
+int theta_grouped(const std::vector<ThetaTask>& tasks, hipStream_t st);
+// the Theta product of a walker set's current walkers as such a task (walk.hip)
+ThetaTask theta_task_of(afq_system s, afq_walkers w);

@@ -80,6 +80,24 @@ static int theta_from_inverse(afq_system s, afq_walkers w, const double2* Wsrc) 
                     w->theta.as<double2>(), s->stream);
 }
 
+// the Theta product of the current walkers as a task of a grouped launch
+ThetaTask theta_task_of(afq_system s, afq_walkers w) {
+  const int nmax = std::max(s->n_up, s->n_dn);
+  ThetaTask t{};
+  t.W = w->W.as<double2>();
+  t.Sinv = w->Sinv.as<double2>();
+  t.thetaT = w->theta.as<double2>();
+  t.nm2 = (long)nmax * nmax;
+  t.M = s->M;
+  t.ntot = s->ntot;
+  t.nw = w->nw;
+  for (int sp = 0; sp < 2; ++sp) {
+    t.n[sp] = s->nspin_n(sp);
+    t.off[sp] = s->spin_off(sp);
+  }
+  return t;
+}
+
 // S^s = T^sH W^s for every walker; S^-1 (optional) and log det; Theta^T = S^-T W^T
 int compute_overlap_theta(afq_system s, afq_walkers w, const double2* Wsrc, bool want_theta, double2* logdet_out) {
   AFQ_RET(overlap_inverse(s, w, Wsrc, want_theta ? w->Sinv.as<double2>() : nullptr, logdet_out));
@@ -323,7 +341,9 @@ int step_stage(int stage, afq_system s, afq_walkers w, double dt, const double* 
     return AFQ_OK;
   }
   if (stage == 1) {
-    {
+    if (w->theta_pre) {   // formed by a batch's grouped launch before this stage
+      w->theta_pre = false;
+    } else {
       TraceScope t(AFQ_PH_OVERLAP, st);
       AFQ_RET(theta_from_inverse(s, w, w->W.as<double2>()));
     }
