@@ -1,10 +1,16 @@
-// The two FP64 walker products around the overlap inverse (sec:afqmc: the
-// mixed Green's function G = W (T^H W)^-1 T^H), on v_mfma_f64_16x16x4f64:
+// The FP64 walker products whose output side is the electron count, on
+// v_mfma_f64_16x16x4f64: the two around the overlap inverse (sec:afqmc: the
+// mixed Green's function G = W (T^H W)^-1 T^H) and the two of CholeskyQR,
 //
 //   overlap  S^s_w = T^sH W^s_w          (n x n per walker and spin, contraction over the M basis functions)
 //   theta    Theta^s_w = W^s_w (S^s_w)^-1, stored transposed as thetaT[w][off_s + b][k]
+//   gram     G^s_w = W^sH_w W^s_w         (upper block triangle, mirrored)
+//   qr       Q^s_w = W^s_w (R^s_w)^-1      (the theta kernel, stored in the walker layout)
 //
-// Both have an output side of n <= 128 electrons, which the general tiled GEMM
+// plus grouped launches of the overlap and theta kernels that walk a work
+// table of many walker sets (the systems of a batch).
+//
+// All have an output side of n <= 128 electrons, which the general tiled GEMM
 // pads to 32-row wave tiles (100 -> 128); here every wave owns whole 16-wide
 // MFMA blocks over all of n (100 -> 112), the spins share one launch, and the
 // contraction runs to its exact length in steps of 4 (no padding of k or j).
