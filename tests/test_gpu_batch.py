@@ -109,6 +109,43 @@ def test_batch_parameter_change_recaptures(api):
     b.close()
 
 
+def test_batch_grouped_overlaps_mixed_shapes(api):
+    """Grouped overlap and Theta launches over systems of different electron
+    block counts (1 and 2 sixteen-wide blocks), wave counts (M = 72: 4 waves;
+    M = 128: 8 waves) and trial kinds (one complex trial): the batch equals
+    the same systems stepped one by one, QR every 3."""
+    cfg = [dict(M=72, n_up=18, n_dn=17, n_chol=40, n_walkers=5, seed=4601, cplx=False),
+           dict(M=128, n_up=32, n_dn=32, n_chol=48, n_walkers=4, seed=4602, cplx=False),
+           dict(M=40, n_up=10, n_dn=9, n_chol=36, n_walkers=6, seed=4603, cplx=True)]
+    dt, seed, qr = 0.01, 17, 3
+
+    def build():
+        systems, walkers = [], []
+        for c in cfg:
+            s = synth.make_system(c["M"], c["n_up"], c["n_dn"], c["n_chol"], seed=c["seed"])
+            if c["cplx"]:
+                rng = np.random.default_rng(c["seed"])
+                s.phi_t = np.diag(np.exp(1j * rng.uniform(0, 2 * np.pi, c["M"]))) @ s.phi_t
+            g = api.System.from_synth(s, precision="fp64")
+            W0 = synth.perturbed_walkers(s, c["n_walkers"], 0.05, seed=c["seed"] + 7)
+            systems.append(g)
+            walkers.append(api.Walkers(g, c["n_walkers"], W0, np.ones(c["n_walkers"])))
+        return systems, walkers
+
+    sysA, wkA = build()
+    sysB, wkB = build()
+    b = api.Batch(list(zip(sysA, wkA)))
+    got = b.step(7, dt, seed=seed, qr_every=qr)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cfg):
+        f = api.fields_generate(seed, 7, c["n_walkers"], c["n_chol"], step0=0, sys_id=i)
+        ref = wkB[i].step(7, dt, fields=f, qr_every=qr, outputs=("emix",))["emix"]
+        torch.cuda.synchronize()
+        assert rel_vec(to_np(got[i]), to_np(ref)) < 1e-12, i
+        assert rel_fro(to_np(wkA[i].get()["W"]), to_np(wkB[i].get()["W"])) < 1e-12, i
+    b.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("bf16x3", 1e-5)])
 def test_batch_uneven_systems_vs_oracle(api, prec, tol):
     """Five uneven systems (M in [8, 64], N = M/4 per spin, X = 4M), 8 steps,
