@@ -286,8 +286,15 @@ __global__ __launch_bounds__(256) void assemble_kernel(AssembleArgs a, CT* __res
   double2 v[5] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0),
                   make_double2(0, 0)};
   const bool given = a.parts_in != nullptr;
-  if (!given)
-    for (long e = t; e < per; e += 256) v[0] = cadd(v[0], cmul(a.ht[e], th[e]));
+  if (!given) {   // E1 partial sums: four independent chains keep four loads of each operand in flight
+    double2 e1[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    long e = t;
+    for (; e + 768 < per; e += 1024)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) e1[u] = cadd(e1[u], cmul(a.ht[e + 256 * u], th[e + 256 * u]));
+    for (; e < per; e += 256) e1[0] = cadd(e1[0], cmul(a.ht[e], th[e]));
+    v[0] = cadd(cadd(e1[0], e1[1]), cadd(e1[2], e1[3]));
+  }
   const double sdt = sqrt(a.dt);
   const double2* tro0 = a.tro + (long)w * 2 * a.X;
   const double2* tro1 = tro0 + a.X;
