@@ -376,12 +376,17 @@ int r32_autotune(afq_system s, afq_walkers w, int reps, int* tile_out);
 bool r32_taylor_used(afq_system s);
 // A_w = sum_n coef[w][n] L^n, written in packed real form to w->r32_x
 int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st);
-// w->u <- sum_{j <= order} A_w^j u / j! (Horner form, A_w from r32_abuild)
-int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st, bool terms_packed = false);
+// w->u <- sum_{j <= order} A_w^j u / j! (Horner form, A_w from r32_abuild);
+// with b1_rows, where the products can, the last one also writes u as the
+// walker rows of the B1 product (*b1_rows tells whether it did)
+int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st, bool terms_packed = false,
+               bool* b1_rows = nullptr);
 // (B1 - I) packed for the current B1 (no-op when up to date)
 int r32_prepare_b1(afq_system s);
-// out = B1 in = in + (B1 - I) in for every walker (M x n_tot complex FP64 each)
-int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStream_t st, bool pack_terms = false);
+// out = B1 in = in + (B1 - I) in for every walker (M x n_tot complex FP64 each);
+// in_rows_packed: the split-BF16 walker rows of `in` are already in place
+int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStream_t st, bool pack_terms = false,
+           bool in_rows_packed = false);
 // whether r32_b1(..., pack_terms = true) writes V in the packed term layouts of r32_taylor
 bool r32_b1_packs_terms(afq_system s);
 // tro[w][spin][n] = tr(Lt^{n,spin} Theta^spin) from the FP32 operands

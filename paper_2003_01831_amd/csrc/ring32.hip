@@ -365,6 +365,11 @@ struct HornerB3Args {
   long vp_rows, vp_wstride;
   unsigned char* vb;
   long vb_rows, vb_plane, vb_wstride;
+  // B3_HORNER_LAST, optional: the new U also as the walker rows of the B1
+  // product that follows (BF16 hi / lo planes, the layout of
+  // pack_walker_rows_bf3_kernel), so that it needs no packing pass
+  unsigned char* wr;
+  long wr_rows, wr_plane, wr_wstride;
 };
 
 enum { B3_HORNER = 0, B3_HORNER_LAST = 1, B3_B1 = 2, B3_XFORM = 3 };
@@ -552,10 +557,32 @@ __global__ __launch_bounds__(256, 1) void horner_bf3_kernel(HornerB3Args g) {
         const float re = odd ? o[2 + h] : acc[i][j][h], im = odd ? acc[i][j][2 + h] : o[h];
         bool ok;
         const long idx = at(i, j, h, ok);
-        if (!ok) continue;
         if constexpr (LAST) {
-          g.u[idx] = make_double2(cur[j][h].x + (double)(g.scale * re), cur[j][h].y + (double)(g.scale * im));
+          const double2 nv = make_double2(cur[j][h].x + (double)(g.scale * re), cur[j][h].y + (double)(g.scale * im));
+          if (ok) g.u[idx] = nv;
+          if (g.wr) {
+            // walker rows (n, Re|Im) over m: lane lr holds m = col / 2, lane
+            // lr ^ 2 (same quad, same rows n) holds m ^ 1. The pair (even m,
+            // m + 1) is split as the packing kernel splits it; the lane of the
+            // even m writes its real parts, the other lane its imaginary parts
+            // (k >= M and rows past n_tot read as zero there too)
+            const float fx = ok ? (float)nv.x : 0.f, fy = ok ? (float)nv.y : 0.f;
+            const bool em = !(lr & 2);
+            const float mine = em ? fx : fy, other = em ? fy : fx;   // this lane's part, the partner's
+            const float pv = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(other), 0x4E, 0xf, 0xf, false));
+            const long n = arow0 + arow + 16 * i + 4 * lq + (odd ? 2 + h : h);
+            const int m0 = (int)((brow0 + brow + 16 * j + lr) >> 1) & ~1;   // the even m of the pair
+            if (n < g.ntot && m0 < g.M) {
+              unsigned char* y = g.wr + (long)w * g.wr_wstride +
+                                 ((long)(m0 >> 5) * g.wr_rows + 2 * n + (em ? 0 : 1)) * ROWB + 2 * (m0 & 31);
+              unsigned hi, lo;
+              split_pair(em ? mine : pv, em ? pv : mine, hi, lo);
+              *reinterpret_cast<unsigned*>(y) = hi;
+              *reinterpret_cast<unsigned*>(y + g.wr_plane) = lo;
+            }
+          }
         } else {
+          if (!ok) continue;
           const long n = arow0 + arow + 16 * i + 4 * lq + (odd ? 2 + h : h);
           const int m = (int)((brow0 + brow + 16 * j + lr) >> 1);
           unsigned hi, lo;
@@ -1024,15 +1051,19 @@ int r32_prepare_b1(afq_system s) {
 
 bool r32_b1_packs_terms(afq_system s) { return taylor_b3(s); }
 
-int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStream_t st, bool pack_terms) {
+int r32_b1(afq_system s, afq_walkers w, const double2* in, double2* out, hipStream_t st, bool pack_terms,
+           bool in_rows_packed) {
   if (taylor_b3(s)) {
     const B1B3Shape b = b1_b3_shape(s);
     AFQ_CHECK(s->b1x3.p && s->b1x3_dt == s->B1_dt && s->b1x3_tile == b.tile && w->r32_layout == 2 + b.tile &&
                   w->r32_b1w.bytes >= (size_t)w->nw * b.a_wstride,
               AFQ_E_STATE, "B1 product (split BF16): operands not prepared");
-    hipLaunchKernelGGL(pack_walker_rows_bf3_kernel, dim3(ceil_div(s->ntot, 8), (unsigned)b.kchunk, w->nw), dim3(256),
-                       0, st, in, s->M, s->ntot, b.a_rows, b.a_plane, b.a_wstride, w->r32_b1w.as<unsigned char>());
-    AFQ_TRY_HIP(hipGetLastError());
+    if (!in_rows_packed) {   // else the last Horner product wrote them with U
+      hipLaunchKernelGGL(pack_walker_rows_bf3_kernel, dim3(ceil_div(s->ntot, 8), (unsigned)b.kchunk, w->nw),
+                         dim3(256), 0, st, in, s->M, s->ntot, b.a_rows, b.a_plane, b.a_wstride,
+                         w->r32_b1w.as<unsigned char>());
+      AFQ_TRY_HIP(hipGetLastError());
+    }
     HornerB3Args g{};
     g.a = w->r32_b1w.as<unsigned char>();
     g.b = s->b1x3.as<unsigned char>();
@@ -1287,7 +1318,8 @@ int r32_abuild(afq_system s, afq_walkers w, const float* coef, hipStream_t st) {
 }
 
 // U <- T_K(A) U in Horner form with split-BF16x3 products
-static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st, bool terms_packed) {
+static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st, bool terms_packed,
+                         bool* b1_rows) {
   const TaylorShape ts = taylor_shape(s);
   const TaylorB3Shape tb = taylor_b3_shape(s);
   AFQ_CHECK(w->r32_layout == 2 + tb.tile && w->r32_x.bytes >= (size_t)w->nw * tb.x_wstride &&
@@ -1336,15 +1368,29 @@ static int r32_taylor_b3(afq_system s, afq_walkers w, int order, hipStream_t st,
     g.a = in;
     g.yout = out;
     g.scale = 1.0f / (float)j;
-    if (j == 1) AFQ_RET(launch_b3<B3_HORNER_LAST>(tb.tile, g, st));
-    else AFQ_RET(launch_b3<B3_HORNER>(tb.tile, g, st));
+    if (j == 1) {
+      if (b1_rows) {   // U also as the walker rows of the B1 product that follows
+        const B1B3Shape b = b1_b3_shape(s);
+        AFQ_CHECK(w->r32_b1w.bytes >= (size_t)w->nw * b.a_wstride, AFQ_E_STATE,
+                  "Taylor propagator (split BF16): B1 walker rows not prepared");
+        g.wr = w->r32_b1w.as<unsigned char>();
+        g.wr_rows = b.a_rows;
+        g.wr_plane = b.a_plane;
+        g.wr_wstride = b.a_wstride;
+        *b1_rows = true;
+      }
+      AFQ_RET(launch_b3<B3_HORNER_LAST>(tb.tile, g, st));
+    } else {
+      AFQ_RET(launch_b3<B3_HORNER>(tb.tile, g, st));
+    }
     in = out;
   }
   return AFQ_OK;
 }
 
-int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st, bool terms_packed) {
-  if (taylor_b3(s)) return r32_taylor_b3(s, w, order, st, terms_packed);
+int r32_taylor(afq_system s, afq_walkers w, int order, hipStream_t st, bool terms_packed, bool* b1_rows) {
+  if (b1_rows) *b1_rows = false;
+  if (taylor_b3(s)) return r32_taylor_b3(s, w, order, st, terms_packed, b1_rows);
   const TaylorShape ts = taylor_shape(s);
   const size_t yb = (size_t)w->nw * ts.y_wstride * sizeof(float);
   AFQ_CHECK(w->r32_x.bytes >= (size_t)w->nw * ts.x_wstride * sizeof(float) && w->r32_y[0].bytes >= yb &&

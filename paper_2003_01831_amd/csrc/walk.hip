@@ -231,6 +231,7 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
   }
   TraceScope tr(AFQ_PH_TAYLOR, st);
   const bool ring = sizeof(T) == 4 && s->kp_nk == 0 && r32_taylor_used(s);
+  bool u_rows = false;   // the last Taylor product also wrote U as the B1 product's walker rows
   // U = B1 W  (FP64; the walkers' columns side by side as one n = nw ntot product)
   if (ring) {   // reduced modes: W + (B1 - I) W with the correction on the FP32 ring
     AFQ_RET(r32_b1(s, w, Win, w->u.as<double2>(), st, true));   // also packs V for the Taylor products where it can
@@ -244,7 +245,7 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
   }
   if (ring) {
     // reduced modes: U <- T_K(A) U in Horner form on the FP32 ring kernel
-    AFQ_RET(r32_taylor(s, w, order, st, r32_b1_packs_terms(s)));
+    AFQ_RET(r32_taylor(s, w, order, st, r32_b1_packs_terms(s), &u_rows));
   } else {
     // term_0 = U (in the contraction precision); term_j = A term_{j-1} / j; U += term_j
     T* cur = w->t1.as<T>();
@@ -265,7 +266,7 @@ static int propagate(afq_system s, afq_walkers w, int order, const T* coef, cons
   }
   // W' = B1 U
   if (ring) {
-    AFQ_RET(r32_b1(s, w, w->u.as<double2>(), Wout, st));
+    AFQ_RET(r32_b1(s, w, w->u.as<double2>(), Wout, st, false, u_rows));
   } else {
     GemmArgs<double> g = gemm_args<double>();
     g.m = M; g.n = nw * ntot; g.k = M; g.vn = ntot;
