@@ -172,6 +172,7 @@ int batch_create_impl(afq_batch* out, int n, const afq_system* systems, const af
     delete b;
     return rc;
   }
+  for (auto w : b->wk) ++w->in_batch;   // their steps keep W and S^-1 where the graph expects them
   *out = b;
   return AFQ_OK;
 }
@@ -262,6 +263,7 @@ int batch_step_impl(afq_batch b, int n_steps, double dt, uint64_t seed, int qr_e
 int batch_destroy_impl(afq_batch b) {
   if (!b) return AFQ_OK;
   (void)hipStreamSynchronize(b->origin);
+  for (auto w : b->wk) --w->in_batch;
   delete b;
   return AFQ_OK;
 }

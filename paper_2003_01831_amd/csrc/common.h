@@ -86,6 +86,10 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
+  void swap(DevBuf& o) noexcept {   // exchange the allocations (no device work)
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -221,6 +225,7 @@ struct afq_walkers_s {
   DevBuf Sinv_new;             // S^-1 of the propagated walkers (carried to the next step)
   bool s_carried = false;      // Sinv and logdet are those of the current W (set by a step's weight phase)
   bool theta_pre = false;      // Theta of the current W already formed (a batch's grouped launch)
+  int in_batch = 0;            // batches holding this walker set: their graphs bake its buffer addresses
   DevBuf logdet, logdet_new;   // nw x 2 complex
   DevBuf sing;                 // nw x 2 int
   DevBuf theta;                // nw x M x ntot complex

@@ -47,6 +47,10 @@ struct WeightArgs {
   const double2* sinv_new;
   double2* logdet_keep;
   long sinv_per;
+  // 1: the caller has exchanged the buffers (W now holds W', Wn the old W;
+  // sinv the new S^-1, sinv_new the old): only the walkers that died are
+  // restored from the old buffers, instead of the live ones copied
+  int swapped;
 };
 
 int pack_a(int prec, const double2* Lt, int X, int ntot, int M, int off, const PackShape& ps, bool real_trial,

@@ -437,11 +437,31 @@ __global__ __launch_bounds__(256) void commit_kernel(WeightArgs a) {
   if (a.sinv && blockIdx.x == 0 && threadIdx.x < 2) a.logdet_keep[2 * w + threadIdx.x] = a.logdet_new[2 * w + threadIdx.x];
 }
 
+// The same commit after the caller exchanged the walker (and S^-1) buffers:
+// the new values are already in place for every walker, and the walkers not
+// alive after the weight update get their old W (and S^-1, log det) back
+__global__ __launch_bounds__(256) void restore_kernel(WeightArgs a) {
+  const int w = blockIdx.y;
+  if (a.alive[w]) {
+    if (a.sinv && blockIdx.x == 0 && threadIdx.x < 2) a.logdet_keep[2 * w + threadIdx.x] = a.logdet_new[2 * w + threadIdx.x];
+    return;
+  }
+  const long per = a.per, sper = a.sinv ? a.sinv_per : 0;
+  const long base = (long)blockIdx.x * 1024 + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const long i = base + 256L * u;
+    if (i < per) a.W[w * per + i] = a.Wn[w * per + i];
+    else if (i - per < sper) a.sinv[w * sper + (i - per)] = a.sinv_new[w * sper + (i - per)];
+  }
+}
+
 int launch_weights(const WeightArgs& a, int nw, hipStream_t st) {
   hipLaunchKernelGGL(weight_kernel, dim3((nw + 255) / 256), dim3(256), 0, st, a, nw);
   AFQ_TRY_HIP(hipGetLastError());
   const long total = a.per + (a.sinv ? a.sinv_per : 0);
-  hipLaunchKernelGGL(commit_kernel, dim3((unsigned)((total + 1023) / 1024), nw), dim3(256), 0, st, a);
+  if (a.swapped) hipLaunchKernelGGL(restore_kernel, dim3((unsigned)((total + 1023) / 1024), nw), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(commit_kernel, dim3((unsigned)((total + 1023) / 1024), nw), dim3(256), 0, st, a);
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }

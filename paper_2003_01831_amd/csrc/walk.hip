@@ -394,6 +394,15 @@ int step_stage(int stage, afq_system s, afq_walkers w, double dt, const double* 
     wa.w_cap = w->w_cap;
     wa.ratio_out = reinterpret_cast<double2*>(ratio_out);
     wa.weights_out = weights_out;
+    // A walker set outside any batch takes W' (and the new S^-1) by exchanging
+    // the buffers, and only the walkers that died get their old values back;
+    // a batch's captured graph holds the buffer addresses, so there the live
+    // walkers are copied instead
+    if (w->in_batch == 0) {
+      w->W.swap(w->Wn);
+      if (carry) w->Sinv.swap(w->Sinv_new);
+      wa.swapped = 1;
+    }
     wa.W = w->W.as<double2>();
     wa.Wn = w->Wn.as<double2>();
     wa.per = (long)s->M * s->ntot;
