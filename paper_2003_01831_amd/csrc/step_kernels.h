@@ -65,7 +65,8 @@ int fill_d(double* y, double v, long n, hipStream_t st);
 int fill_i(int* y, int v, long n, hipStream_t st);
 int fill_eye(double* y, int M, hipStream_t st);
 int broadcast_trial(const double2* phi, double2* W, long per, int nw, hipStream_t st);
-int masked_copy(const double2* src, double2* dst, long per, int nw, const int* alive, hipStream_t st);
+int masked_copy(const double2* src, double2* dst, long per, int nw, const int* alive, hipStream_t st,
+                bool where_alive = true);
 int launch_assemble(const AssembleArgs& a, void* coef, bool coef_f32, hipStream_t st);
 int launch_emix(const double2* eloc, const double* wt, int nw, double* out, hipStream_t st);
 int launch_weights(const WeightArgs& a, int nw, hipStream_t st);

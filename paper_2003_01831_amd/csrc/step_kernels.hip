@@ -236,15 +236,16 @@ int broadcast_trial(const double2* phi, double2* W, long per, int nw, hipStream_
 
 // walker copy dst[w] = src[w] for live walkers
 __global__ void masked_copy_kernel(const double2* __restrict__ src, double2* __restrict__ dst, long per,
-                                   const int* __restrict__ alive) {
+                                   const int* __restrict__ alive, int where_alive) {
   const long w = blockIdx.y;
-  if (!alive[w]) return;
+  if ((alive[w] != 0) != (where_alive != 0)) return;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < per; i += (long)gridDim.x * blockDim.x)
     dst[w * per + i] = src[w * per + i];
 }
-int masked_copy(const double2* src, double2* dst, long per, int nw, const int* alive, hipStream_t st) {
+int masked_copy(const double2* src, double2* dst, long per, int nw, const int* alive, hipStream_t st,
+                bool where_alive) {
   const int bx = (int)std::min<long>(ceil_div(per, 256), 64);
-  hipLaunchKernelGGL(masked_copy_kernel, dim3(bx, nw), dim3(256), 0, st, src, dst, per, alive);
+  hipLaunchKernelGGL(masked_copy_kernel, dim3(bx, nw), dim3(256), 0, st, src, dst, per, alive, where_alive ? 1 : 0);
   AFQ_TRY_HIP(hipGetLastError());
   return AFQ_OK;
 }

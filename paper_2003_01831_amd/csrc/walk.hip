@@ -309,13 +309,19 @@ int qr_orbitals(afq_system s, afq_walkers w, const double2* src0, double2* mid, 
   return AFQ_OK;
 }
 
-// QR of the live walkers: W -> Wn -> u, then u back into W where alive
+// QR of the live walkers: W -> Wn -> u, then u back into W where alive (for
+// a walker set outside any batch: the buffers exchanged, the walkers not
+// alive given their old W back)
 static int qr_walkers(afq_system s, afq_walkers w) {
   w->s_carried = false;   // W changes
   TraceScope tr(AFQ_PH_QR, s->stream);
   AFQ_RET(qr_orbitals(s, w, w->W.as<double2>(), w->Wn.as<double2>(), w->u.as<double2>()));
-  return masked_copy(w->u.as<double2>(), w->W.as<double2>(), (long)s->M * s->ntot, w->nw, w->alive.as<int>(),
-                     s->stream);
+  const long per = (long)s->M * s->ntot;
+  if (w->in_batch == 0) {
+    w->W.swap(w->u);
+    return masked_copy(w->u.as<double2>(), w->W.as<double2>(), per, w->nw, w->alive.as<int>(), s->stream, false);
+  }
+  return masked_copy(w->u.as<double2>(), w->W.as<double2>(), per, w->nw, w->alive.as<int>(), s->stream);
 }
 
 // One step in three stages that end where an overlap inverse is needed: stage
