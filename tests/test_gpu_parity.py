@@ -213,6 +213,25 @@ def test_uneven_spins_and_dead_walkers(api):
     assert rel_fro(g["W"][live], o["W"][live]) < 1e-8
 
 
+def test_dead_walkers_between_qr_steps(api):
+    """Walkers that die on steps without QR (the new S^-1 carried to the next
+    step): the commit keeps their W, S^-1 and log det, so their local energies
+    on the following steps still follow the frozen walkers, as in the oracle."""
+    s = synth.make_system(8, 3, 2, 24, seed=2)
+    s.chol = s.chol * 2.0
+    nw = 16
+    fields = synth.make_fields(5, nw, 24, seed=7)
+    # dt 0.2: 1, 3, 4, 6 and 7 walkers dead after steps 1..5 (oracle), none QR
+    g, o = _run_both(api, s, synth.trial_walkers(s, nw), np.ones(nw), fields, 0.2, 0, 0.0)
+    assert np.array_equal(g["alive"].astype(bool), o["alive"])
+    assert not o["alive"].all() and o["alive"].any()
+    assert rel_vec(g["eloc"], o["eloc"]) < 1e-9   # every walker, every step, dead ones included
+    assert rel_vec(g["emix"], o["emix"]) < 1e-9
+    live = o["alive"]
+    assert rel_fro(g["W"][~live], o["W"][~live]) < 1e-8
+    assert rel_fro(g["W"][live], o["W"][live]) < 1e-8
+
+
 def test_device_philox_matches_cpu(api):
     x = to_np(api.fields_generate(987654321987, 3, 7, 257, step0=11, sys_id=2))
     ref = philox.normal_fields(987654321987, 3, 7, 257, step0=11, sys_id=2)
